@@ -1,0 +1,158 @@
+"""Lattice geometry, tensor layout and Hamiltonian of the oracle (test infrastructure only).
+
+Conventions (the paper leaves these open; readings are listed in the design notes):
+
+* Sites (y, x), y = 0 the top row, x = 0 the left column, k = y*Lx + x.
+* Physical index s in {0, 1}; s = 0 is S^z = +1/2.
+* Site tensor T_k[s][l, u, r, d]: the rank-5 tensor A_k(s, l, r, u, d) of
+  Sec. II.A Eq. (1) with the virtual legs stored in (l, u, r, d) order.  Legs on
+  the open boundary have dimension 1, bulk legs dimension D.
+* The parameter vector is the concatenation over k of T_k[s][l][u][r][d].
+  For 32x32, D=8 it holds 7,496,192 numbers, the "about 7.5 x 10^6 variables"
+  quoted in Sec. II.B.
+* H = J1 sum_NN S_i.S_j + J2 sum_diag S_i.S_j with S = sigma/2 and open
+  boundaries (Sec. III.A; the Hamiltonian elements of App. C Eq. (Elocal)).
+  Pinned by reproducing exact-diagonalisation energies printed in Table III.
+"""
+import numpy as np
+
+from . import philox
+
+
+class Lattice:
+    """An Ly x Lx open-boundary square lattice carrying a PEPS of bond dimension D."""
+
+    def __init__(self, Ly, Lx, D, Dc, J1=1.0, J2=0.0):
+        if Ly < 1 or Lx < 1 or D < 1 or Dc < 1:
+            raise ValueError("lattice sizes, D and Dc must be >= 1")
+        self.Ly, self.Lx, self.D, self.Dc = int(Ly), int(Lx), int(D), int(Dc)
+        self.J1, self.J2 = float(J1), float(J2)
+        self.N = self.Ly * self.Lx
+        self.offsets = []
+        off = 0
+        for y in range(self.Ly):
+            for x in range(self.Lx):
+                self.offsets.append(off)
+                off += 2 * int(np.prod(self.dims(y, x)))
+        self.Np = off
+
+    def dims(self, y, x):
+        """(l, u, r, d) leg dimensions of site (y, x); open-boundary legs have dimension 1."""
+        D = self.D
+        return (D if x > 0 else 1, D if y > 0 else 1,
+                D if x < self.Lx - 1 else 1, D if y < self.Ly - 1 else 1)
+
+    def site(self, y, x):
+        return y * self.Lx + x
+
+
+def site_tensor(T, lat, y, x, s):
+    """View of T_{y,x}[s] with shape (l, u, r, d)."""
+    dl, du, dr, dd = lat.dims(y, x)
+    n = dl * du * dr * dd
+    o = lat.offsets[lat.site(y, x)] + int(s) * n
+    return T[o:o + n].reshape(dl, du, dr, dd)
+
+
+def compact_size(lat):
+    """Length of one per-sample log-derivative vector: the occupied slot of every site."""
+    return lat.Np // 2
+
+
+def compact_offsets(lat):
+    offs, o = [], 0
+    for y in range(lat.Ly):
+        for x in range(lat.Lx):
+            offs.append(o)
+            o += int(np.prod(lat.dims(y, x)))
+    return offs
+
+
+# --------------------------------------------------------------------------
+# Hamiltonian (Sec. II.A Eq. (3); App. C Eq. (Elocal))
+# --------------------------------------------------------------------------
+
+def bonds(lat):
+    """All interacting pairs ((y1,x1), (y2,x2), J): NN horizontal, NN vertical, both diagonals."""
+    out = []
+    for y in range(lat.Ly):
+        for x in range(lat.Lx - 1):
+            out.append(((y, x), (y, x + 1), lat.J1))
+    for y in range(lat.Ly - 1):
+        for x in range(lat.Lx):
+            out.append(((y, x), (y + 1, x), lat.J1))
+    if lat.J2 != 0.0:
+        for y in range(lat.Ly - 1):
+            for x in range(lat.Lx - 1):
+                out.append(((y, x), (y + 1, x + 1), lat.J2))
+                out.append(((y, x + 1), (y + 1, x), lat.J2))
+    return out
+
+
+def bond_elements(si, sj, J):
+    """Matrix elements of J S_i.S_j (S = sigma/2) acting on the pair (si, sj).
+
+    Returns (diagonal, offdiagonal): <si sj|H_ij|si sj> = J/4 for parallel and
+    -J/4 for antiparallel spins; <sj si|H_ij|si sj> = J/2 connects an
+    antiparallel pair to its exchanged partner and is 0 otherwise.
+    """
+    if si == sj:
+        return 0.25 * J, 0.0
+    return -0.25 * J, 0.5 * J
+
+
+def local_energy(lat, spins, ratio_of_pair):
+    """E_loc(S) = sum over bonds of H_ij elements times Psi(S')/Psi(S) (App. C Eq. (Elocal)).
+
+    ``ratio_of_pair((y1,x1),(y2,x2))`` returns Psi(S')/Psi(S) for S' = S with the
+    two spins exchanged; it is called only for antiparallel pairs.
+    """
+    s = np.asarray(spins).reshape(lat.Ly, lat.Lx)
+    e = 0.0
+    for p, q, J in bonds(lat):
+        diag, off = bond_elements(s[p], s[q], J)
+        e += diag
+        if off != 0.0:
+            e += off * ratio_of_pair(p, q)
+    return e
+
+
+# --------------------------------------------------------------------------
+# Inputs drawn by the method (tensor initialisation, chain starts)
+# --------------------------------------------------------------------------
+
+def init_tensors(lat, seed, lattice_id=0, scale=None, perturb=0.0):
+    """T = scale * xi (+ perturb * xi'), xi, xi' ~ N(0,1) from Philox + Box-Muller.
+
+    Element p of the parameter vector uses counter (p, 0, 0, TAG_INIT) (and
+    TAG_PERTURB for xi') under key (seed, lattice_id).  The default scale is
+    1/sqrt(D^4) for every site, boundary sites included.
+    """
+    if scale is None:
+        scale = 1.0 / lat.D ** 2
+    key = (seed, lattice_id)
+    T = np.empty(lat.Np)
+    for p in range(lat.Np):
+        T[p] = scale * philox.gaussian((p, 0, 0, philox.TAG_INIT), key)
+        if perturb != 0.0:
+            T[p] += perturb * philox.gaussian((p, 0, 0, philox.TAG_PERTURB), key)
+    return T
+
+
+def neel(lat):
+    """Neel configuration s(y,x) = (x + y) mod 2 (S^z_tot = 0 when N is even)."""
+    return np.array([(x + y) % 2 for y in range(lat.Ly) for x in range(lat.Lx)], dtype=np.int8)
+
+
+def neel_shuffled(lat, seed, lattice_id, chain):
+    """Durstenfeld / Fisher-Yates shuffle of the Neel list with Philox indices.
+
+    For i = N-1 down to 1: j = floor(u_i (i+1)), swap entries i and j, where
+    u_i comes from counter (chain, 0, i, TAG_SHUFFLE) under key (seed, lattice_id).
+    """
+    s = neel(lat)
+    for i in range(lat.N - 1, 0, -1):
+        w = philox.philox4x64_10((chain, 0, i, philox.TAG_SHUFFLE), (seed, lattice_id))
+        j = philox.bounded_index(w[0], i + 1)
+        s[i], s[j] = s[j], s[i]
+    return s

@@ -1,0 +1,285 @@
+"""Variational Monte Carlo layer of the oracle (test infrastructure only).
+
+* ``eval_config``  -- Psi(S), E_loc(S), the log-derivatives G(S) and every pair
+                      ratio for one fixed configuration.
+* ``Chain`` / ``run_chain`` -- the sequential bond-visiting Metropolis sampler
+                      of Sec. II.A Eq. (9): one sweep = a top-down pass that
+                      visits every horizontal bond of row y (left to right),
+                      then every vertical bond between rows y and y+1, then
+                      forms U_y; followed by a bottom-up pass that measures and
+                      rebuilds the lower boundaries for the next sweep.
+* ``gradient``     -- Eq. (5): <G E_loc> - <G><E_loc> (Alg. 1, gradient step).
+* ``sr_step``      -- stochastic reconfiguration: (S + shift I) delta = g with
+                      S the covariance of G, solved by Cholesky.
+* ``sign_sgd``     -- Eq. (10): A <- A - r * delta * sgn(dE/dA), r ~ U[0,1)
+                      per element.
+
+Ratios Psi(S')/Psi(S) use the auxiliary tensors of App. C: every ratio is the
+value of the same row (or row-pair) network with the exchanged tensors, divided
+by that network with the current tensors.
+
+Parity: at Dc >= exact rank everything here is pinned by brute force in the
+tests; on truncated networks the pins are the invariants listed in ``peps``.
+"""
+import math
+
+import numpy as np
+
+from . import philox
+from .lattice import bonds, bond_elements, compact_offsets, compact_size, site_tensor
+from .peps import (ZeroAmplitude, absorb_down, compress, defect3, env3_left, env4_left,
+                   lower_boundary, row3_envs, row4_envs, row_tensors, trivial_mps,
+                   upper_boundaries, row3_value)
+
+
+def _dot(L, R):
+    return float(np.tensordot(L, R, axes=L.ndim))
+
+
+def _lower_boundaries(T, lat, spins):
+    """D_y for y = Ly..1 (D[Ly] trivial) for the configuration ``spins``."""
+    Dl = {lat.Ly: trivial_mps(lat.Lx)}
+    for y in range(lat.Ly - 1, 0, -1):
+        Dl[y], _ = lower_boundary(Dl[y + 1], T, lat, spins, y)
+    return Dl
+
+
+def _measure(T, lat, spins, U, collect_ratios=True):
+    """Bottom-up measurement pass (App. C): E_loc, compact G, ratios, new lower boundaries.
+
+    ``U[y+1]`` must hold U_y for the configuration ``spins``.
+    """
+    s = np.asarray(spins).reshape(lat.Ly, lat.Lx)
+    coffs = compact_offsets(lat)
+    G = np.zeros(compact_size(lat))
+    ratio = {}
+    Dl = {lat.Ly: trivial_mps(lat.Lx)}
+    for y in range(lat.Ly - 1, -1, -1):
+        Dn = Dl[y + 1]
+        row = row_tensors(T, lat, spins, y)
+        Lenv, Renv = row3_envs(U[y], row, Dn)
+        Ny = _dot(Lenv[1], Renv[1])
+        if Ny == 0.0:
+            raise ZeroAmplitude("row network value is zero")
+        # Log-derivatives of the sites of row y (Eqs. (6)-(7)), normalised by N_y.
+        for x in range(lat.Lx):
+            Delta = defect3(Lenv[x], U[y][x], Dn[x], Renv[x + 1])
+            k = lat.site(y, x)
+            G[coffs[k]:coffs[k] + Delta.size] = (Delta / Ny).ravel()
+        # Horizontal pairs of row y.
+        for x in range(lat.Lx - 1):
+            if s[y, x] != s[y, x + 1]:
+                fl = row_tensors(T, lat, spins, y, flips=((y, x), (y, x + 1)))
+                Lm = env3_left(Lenv[x], U[y][x], fl[x], Dn[x])
+                Lm = env3_left(Lm, U[y][x + 1], fl[x + 1], Dn[x + 1])
+                ratio[((y, x), (y, x + 1))] = _dot(Lm, Renv[x + 2]) / Ny
+        # Vertical and diagonal pairs between rows y and y+1.
+        if y < lat.Ly - 1:
+            D2 = Dl[y + 2]
+            row2 = row_tensors(T, lat, spins, y + 1)
+            L4, R4 = row4_envs(U[y], row, row2, D2)
+            N4 = _dot(L4[1], R4[1])
+            if N4 == 0.0:
+                raise ZeroAmplitude("row-pair network value is zero")
+            for x in range(lat.Lx):
+                if s[y, x] != s[y + 1, x]:
+                    f1 = row_tensors(T, lat, spins, y, flips=((y, x),))
+                    f2 = row_tensors(T, lat, spins, y + 1, flips=((y + 1, x),))
+                    Lm = env4_left(L4[x], U[y][x], f1[x], f2[x], D2[x])
+                    ratio[((y, x), (y + 1, x))] = _dot(Lm, R4[x + 1]) / N4
+            if lat.J2 != 0.0:
+                for x in range(lat.Lx - 1):
+                    for p, q in (((y, x), (y + 1, x + 1)), ((y, x + 1), (y + 1, x))):
+                        if s[p] != s[q]:
+                            f1 = row_tensors(T, lat, spins, y, flips=(p, q))
+                            f2 = row_tensors(T, lat, spins, y + 1, flips=(p, q))
+                            Lm = env4_left(L4[x], U[y][x], f1[x], f2[x], D2[x])
+                            Lm = env4_left(Lm, U[y][x + 1], f1[x + 1], f2[x + 1], D2[x + 1])
+                            ratio[(p, q)] = _dot(Lm, R4[x + 2]) / N4
+        if y >= 1:
+            Dl[y], _ = lower_boundary(Dn, T, lat, spins, y)
+    e_loc = 0.0
+    ratio_vec = np.zeros(len(bonds(lat)))
+    for i, (p, q, J) in enumerate(bonds(lat)):
+        diag, off = bond_elements(s[p], s[q], J)
+        e_loc += diag
+        if off != 0.0:
+            e_loc += off * ratio[(p, q)]
+            ratio_vec[i] = ratio[(p, q)]
+    return e_loc, G, ratio_vec, Dl
+
+
+def eval_config(T, lat, spins):
+    """Psi, E_loc, G and pair ratios for a fixed configuration.
+
+    Returns dict(sign, log_abs_psi, e_loc, dlnpsi (compact: occupied slot of
+    every site, in parameter-layout order), ratios (one per entry of
+    ``lattice.bonds``; 0 for parallel pairs)).
+    """
+    U, lam = upper_boundaries(T, lat, spins)
+    last = row3_value(U[lat.Ly - 1], row_tensors(T, lat, spins, lat.Ly - 1), trivial_mps(lat.Lx))
+    if last == 0.0:
+        raise ZeroAmplitude("Psi(S) = 0")
+    e_loc, G, ratios, _ = _measure(T, lat, spins, U)
+    return dict(sign=1 if last > 0 else -1, log_abs_psi=lam[lat.Ly - 1] + math.log(abs(last)),
+                e_loc=e_loc, dlnpsi=G, ratios=ratios)
+
+
+# --------------------------------------------------------------------------
+# Sequential bond-visiting Metropolis (Sec. II.A Eq. (9))
+# --------------------------------------------------------------------------
+
+class Chain:
+    """State of one Markov chain: spins, the sweep counter and its Philox stream ids."""
+
+    def __init__(self, lat, spins, seed, lattice_id, chain_id, sweep=0):
+        self.lat = lat
+        self.spins = np.array(spins, dtype=np.int8).copy()
+        self.seed, self.lattice_id, self.chain_id = seed, lattice_id, chain_id
+        self.sweep = sweep
+        self.accepted = 0
+        self.proposed = 0
+
+
+def _top_down_pass(T, lat, ch, Dl):
+    """Visit every bond once in the pinned order, accepting with r < |Psi(S_b)/Psi(S_a)|^2.
+
+    Returns the upper boundaries of the final configuration and (sign, log|Psi|).
+    """
+    s = ch.spins.reshape(lat.Ly, lat.Lx)
+    U = [trivial_mps(lat.Lx)]
+    lam = [0.0]
+    bond = 0
+    last = None
+    for y in range(lat.Ly):
+        Uy1, Dn = U[-1], Dl[y + 1]
+        # Horizontal bonds of row y.
+        row = row_tensors(T, lat, ch.spins, y)
+        _, Renv = row3_envs(Uy1, row, Dn)
+        L = np.ones((1, 1, 1))
+        for x in range(lat.Lx - 1):
+            if s[y, x] != s[y, x + 1]:
+                row = row_tensors(T, lat, ch.spins, y)
+                fl = row_tensors(T, lat, ch.spins, y, flips=((y, x), (y, x + 1)))
+                num = env3_left(env3_left(L, Uy1[x], fl[x], Dn[x]), Uy1[x + 1], fl[x + 1], Dn[x + 1])
+                den = env3_left(env3_left(L, Uy1[x], row[x], Dn[x]), Uy1[x + 1], row[x + 1], Dn[x + 1])
+                _accept(ch, _dot(num, Renv[x + 2]), _dot(den, Renv[x + 2]), bond,
+                        ((y, x), (y, x + 1)))
+            row = row_tensors(T, lat, ch.spins, y)
+            L = env3_left(L, Uy1[x], row[x], Dn[x])
+            bond += 1
+        if y == lat.Ly - 1:
+            row = row_tensors(T, lat, ch.spins, y)
+            last = row3_value(Uy1, row, Dn)
+            break
+        # Vertical bonds between rows y and y+1.
+        D2 = Dl[y + 2]
+        r1 = row_tensors(T, lat, ch.spins, y)
+        r2 = row_tensors(T, lat, ch.spins, y + 1)
+        _, R4 = row4_envs(Uy1, r1, r2, D2)
+        L4 = np.ones((1, 1, 1, 1))
+        for x in range(lat.Lx):
+            r1 = row_tensors(T, lat, ch.spins, y)
+            r2 = row_tensors(T, lat, ch.spins, y + 1)
+            if s[y, x] != s[y + 1, x]:
+                f1 = row_tensors(T, lat, ch.spins, y, flips=((y, x),))
+                f2 = row_tensors(T, lat, ch.spins, y + 1, flips=((y + 1, x),))
+                num = env4_left(L4, Uy1[x], f1[x], f2[x], D2[x])
+                den = env4_left(L4, Uy1[x], r1[x], r2[x], D2[x])
+                _accept(ch, _dot(num, R4[x + 1]), _dot(den, R4[x + 1]), bond,
+                        ((y, x), (y + 1, x)))
+                r1 = row_tensors(T, lat, ch.spins, y)
+                r2 = row_tensors(T, lat, ch.spins, y + 1)
+            L4 = env4_left(L4, Uy1[x], r1[x], r2[x], D2[x])
+            bond += 1
+        # Row y is final for this sweep: form U_y.
+        Uy, lognu = compress(absorb_down(Uy1, row_tensors(T, lat, ch.spins, y)), lat.Dc)
+        U.append(Uy)
+        lam.append(lam[-1] + lognu)
+    if last == 0.0:
+        raise ZeroAmplitude("Psi(S) = 0")
+    return U, (1 if last > 0 else -1, lam[lat.Ly - 1] + math.log(abs(last)))
+
+
+def _accept(ch, num, den, bond, pair):
+    if den == 0.0:
+        raise ZeroAmplitude("Metropolis denominator is zero")
+    if not (math.isfinite(num) and math.isfinite(den)):
+        raise FloatingPointError("non-finite amplitude ratio")
+    R = (num / den) ** 2
+    r = philox.metropolis_uniform(ch.seed, ch.lattice_id, ch.chain_id, ch.sweep, bond)
+    ch.proposed += 1
+    if r < R:
+        s = ch.spins.reshape(ch.lat.Ly, ch.lat.Lx)
+        (y1, x1), (y2, x2) = pair
+        s[y1, x1], s[y2, x2] = s[y2, x2], s[y1, x1]
+        ch.accepted += 1
+
+
+def run_chain(T, lat, ch, n_burn, n_meas):
+    """Run n_burn + n_meas sweeps; measure after each of the last n_meas (Sec. II.A).
+
+    Returns a list of per-sample dicts (sign, log_abs_psi, e_loc, dlnpsi,
+    spins) and leaves the final state in ``ch``.
+    """
+    Dl = _lower_boundaries(T, lat, ch.spins)
+    out = []
+    for i in range(n_burn + n_meas):
+        U, (sg, lp) = _top_down_pass(T, lat, ch, Dl)
+        e_loc, G, _, Dl = _measure(T, lat, ch.spins, U)
+        if i >= n_burn:
+            out.append(dict(sign=sg, log_abs_psi=lp, e_loc=e_loc, dlnpsi=G,
+                            spins=ch.spins.copy()))
+        ch.sweep += 1
+    return out
+
+
+# --------------------------------------------------------------------------
+# Estimators and updates (Eqs. (2), (5), (10); Alg. 1)
+# --------------------------------------------------------------------------
+
+def expand_dlnpsi(lat, compact, spins):
+    """Scatter a compact log-derivative vector into the full parameter layout (slot s of every site)."""
+    full = np.zeros(lat.Np)
+    coffs = compact_offsets(lat)
+    s = np.asarray(spins).reshape(-1)
+    for k in range(lat.N):
+        n = coffs[k + 1] - coffs[k] if k + 1 < lat.N else compact_size(lat) - coffs[k]
+        o = lat.offsets[k] + int(s[k]) * n
+        full[o:o + n] = compact[coffs[k]:coffs[k] + n]
+    return full
+
+
+def gradient(lat, e_loc, dlnpsi, spins):
+    """dE/dA = <G E_loc> - <G><E_loc> over all samples (Eq. (5)); returns (g, <E_loc>)."""
+    e = np.asarray(e_loc, dtype=np.float64)
+    O = np.stack([expand_dlnpsi(lat, dlnpsi[i], spins[i]) for i in range(len(e))])
+    E = e.mean()
+    g = (O * e[:, None]).mean(axis=0) - O.mean(axis=0) * E
+    return g, E
+
+
+def sr_step(lat, e_loc, dlnpsi, spins, shift):
+    """Solve (S + shift I) delta = g, S = Obar^T Obar / Ns, g = Obar^T Ebar / Ns, by Cholesky."""
+    import scipy.linalg
+    e = np.asarray(e_loc, dtype=np.float64)
+    O = np.stack([expand_dlnpsi(lat, dlnpsi[i], spins[i]) for i in range(len(e))])
+    Ob = O - O.mean(axis=0)
+    Eb = e - e.mean()
+    Ns = len(e)
+    S = Ob.T @ Ob / Ns
+    g = Ob.T @ Eb / Ns
+    S[np.diag_indices_from(S)] += shift
+    c = np.linalg.cholesky(S)
+    z = scipy.linalg.solve_triangular(c, g, lower=True)
+    return scipy.linalg.solve_triangular(c.T, z, lower=False), g
+
+
+def sign_sgd(T, g, step_len, seed, lattice_id, step):
+    """Eq. (10): A <- A - r delta sgn(g), r from counter (p, step, 0, TAG_SGD) per element."""
+    out = np.array(T, dtype=np.float64, copy=True)
+    for p in range(len(out)):
+        if g[p] != 0.0:
+            w = philox.philox4x64_10((p, step, 0, philox.TAG_SGD), (seed, lattice_id))
+            out[p] -= philox.uniform53(w[0]) * step_len * (1.0 if g[p] > 0 else -1.0)
+    return out

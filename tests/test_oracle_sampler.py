@@ -1,0 +1,95 @@
+"""Pins of the oracle's sequential bond-visiting Metropolis sampler (Sec. II.A Eq. (9)).
+
+* Stationary distribution: on a lattice small enough to enumerate, the chain's
+  histogram matches |Psi|^2 / Z from the dense contraction (chi-square test).
+* Replay: a chain is a deterministic function of (tensors, start, seed,
+  lattice id, chain id, sweep counter); splitting a run in two calls gives the
+  same samples.
+* Measured quantities equal a fixed-configuration evaluation of the sampled
+  configuration.
+* Only-horizontal sweeps conserve every row magnetisation, which is why the
+  paper insists on visiting both bond kinds (Sec. II.A).
+"""
+import numpy as np
+import scipy.stats
+
+import bruteforce as bf
+from oracle import vmc
+from oracle.lattice import Lattice, neel, neel_shuffled
+
+
+def _T(lat, seed):
+    return np.random.default_rng(seed).standard_normal(lat.Np) / lat.D ** 2
+
+
+def test_stationary_distribution_chi2():
+    lat = Lattice(2, 3, 2, 8)
+    T = _T(lat, 1)
+    configs = bf.sz0_configs(6)
+    psi = bf.amplitudes(T, 2, 3, 2, configs)
+    p = psi ** 2 / np.sum(psi ** 2)
+    counts = np.zeros(len(configs))
+    index = {c.tobytes(): i for i, c in enumerate(configs)}
+    for chain in range(4):
+        ch = vmc.Chain(lat, neel_shuffled(lat, 9359, 0, chain), 1234, 0, chain)
+        for smp in vmc.run_chain(T, lat, ch, 10, 700):
+            counts[index[smp['spins'].tobytes()]] += 1
+    n = counts.sum()
+    keep = p * n >= 5
+    obs = np.append(counts[keep], counts[~keep].sum())
+    exp = np.append(p[keep] * n, p[~keep].sum() * n)
+    if exp[-1] == 0:
+        obs, exp = obs[:-1], exp[:-1]
+    stat, pval = scipy.stats.chisquare(obs, exp)
+    # visiting vertical bonds moves magnetisation between the rows
+    top = {int(c[:3].sum()) for c, k in zip(configs, counts) if k > 0}
+    assert len(top) > 1
+    # consecutive sweeps are correlated; the p-value is only a coarse gate
+    assert pval > 1e-4, (stat, pval)
+
+
+def test_replay_and_split_runs():
+    lat = Lattice(2, 4, 2, 4)
+    T = _T(lat, 2)
+    s0 = neel_shuffled(lat, 9359, 0, 3)
+    a = vmc.Chain(lat, s0, 77, 0, 3)
+    ra = vmc.run_chain(T, lat, a, 2, 6)
+    b = vmc.Chain(lat, s0, 77, 0, 3)
+    rb = vmc.run_chain(T, lat, b, 2, 3) + vmc.run_chain(T, lat, b, 0, 3)
+    assert [x['spins'].tobytes() for x in ra] == [x['spins'].tobytes() for x in rb]
+    assert [x['e_loc'] for x in ra] == [x['e_loc'] for x in rb]
+    assert a.accepted == b.accepted and a.proposed == b.proposed
+    c = vmc.Chain(lat, s0, 78, 0, 3)
+    rc = vmc.run_chain(T, lat, c, 2, 6)
+    assert [x['spins'].tobytes() for x in ra] != [x['spins'].tobytes() for x in rc]
+
+
+def test_measurement_equals_fixed_config_eval():
+    lat = Lattice(3, 4, 2, 3, J2=0.5)
+    T = _T(lat, 3)
+    ch = vmc.Chain(lat, neel(lat), 5, 1, 0)
+    for smp in vmc.run_chain(T, lat, ch, 1, 3):
+        ref = vmc.eval_config(T, lat, smp['spins'])
+        assert smp['sign'] == ref['sign']
+        assert abs(smp['log_abs_psi'] - ref['log_abs_psi']) < 1e-12
+        assert abs(smp['e_loc'] - ref['e_loc']) < 1e-12
+        assert np.allclose(smp['dlnpsi'], ref['dlnpsi'], rtol=1e-12, atol=1e-14)
+
+
+def test_chain_moves_and_conserves_sz():
+    lat = Lattice(4, 4, 2, 4)
+    T = _T(lat, 4)
+    ch = vmc.Chain(lat, neel(lat), 6, 0, 0)
+    out = vmc.run_chain(T, lat, ch, 0, 4)
+    assert ch.accepted > 0 and ch.proposed >= ch.accepted
+    for smp in out:
+        assert smp['spins'].sum() == 8
+
+
+def test_horizontal_only_is_not_ergodic():
+    """Exchanges inside a row never change that row's magnetisation."""
+    lat = Lattice(1, 6, 2, 4)  # a single row has only horizontal bonds
+    T = _T(lat, 5)
+    ch = vmc.Chain(lat, np.array([0, 1, 0, 1, 0, 1], dtype=np.int8), 1, 0, 0)
+    out = vmc.run_chain(T, lat, ch, 0, 20)
+    assert all(x['spins'].sum() == 3 for x in out)
