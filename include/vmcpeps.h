@@ -1,0 +1,151 @@
+/*
+ * vmcpeps.h -- C ABI of the MI355X (gfx950) library for variational Monte Carlo
+ * on finite open-boundary PEPS (Liu, Huang, Gong, Gu, "Accurate simulation
+ * for finite projected entangled pair states in two dimensions").
+ *
+ * The calls follow the statement of the method in Sec. II.A-B and Alg. 1 of
+ * the paper: initialise tensors, generate configurations by sequential
+ * bond-visiting Metropolis sweeps (generateConfiguration), contract the
+ * single-layer network for Psi(S) (contractNetwork), evaluate E_loc from pair
+ * ratios Psi(S')/Psi(S) and the log-derivatives G = dlnPsi/dA from defect
+ * networks (contractDefectNetwork), then form the gradient and update.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Lattice: Ly x Lx open-boundary square lattice, sites (y, x), y = 0 top row,
+ *   k = y*Lx + x.  Spins are int8 0/1 (0 is S^z = +1/2), S^z_tot = 0 sector.
+ * Tensors (Sec. II.A Eq. (1)): site k holds T_k[s][l][u][r][d]; legs on the
+ *   open boundary have dimension 1, bulk legs dimension D.  The "canonical
+ *   flat" parameter vector is the concatenation over k of these blocks, length
+ *   Np = vp_num_params(); float64.
+ * Log-derivatives (Sec. II.A Eqs. (6)-(7)): per sample, the "compact" vector
+ *   of length Np/2 holds, for every site k in order, the l*u*r*d derivatives
+ *   of the occupied slot s_k (the other slot is zero by construction).
+ * Hamiltonian (Sec. II.A Eq. (3), App. C Eq. (Elocal)):
+ *   H = J1 sum_NN S_i.S_j + J2 sum_diag S_i.S_j, S = sigma/2.
+ * Pair order (the "ratios" outputs): horizontal bonds row by row, then
+ *   vertical bonds row by row, then for every plaquette (y, x) the two
+ *   diagonals (y,x)-(y+1,x+1) and (y,x+1)-(y+1,x) when J2 != 0.
+ * Contraction (App. B, App. C): boundary MPS truncated to Dc by the canonical
+ *   SVD compression (left-to-right orthogonalisation, right-to-left truncation
+ *   keeping the Dc largest singular values); 3-line row networks for
+ *   horizontal pairs and 2-row (4-line) networks for vertical and diagonal
+ *   pairs; every ratio divides by the same network with the current tensors.
+ * Randomness: Philox4x64-10 (Salmon et al., SC'11) under key (seed, lattice);
+ *   Metropolis uniforms use counter (chain, sweep, bond, 4), where bond counts
+ *   the visits of one sweep: row y's horizontal bonds, then the vertical bonds
+ *   between rows y and y+1, for y = 0, 1, ...
+ *
+ * Memory: every pointer argument named *_dev is a device pointer owned by the
+ *   caller (for example a torch tensor's data_ptr on the same device);
+ *   pointers named *_host are host pointers.  The library owns only its
+ *   internal workspace, allocated by vp_create and freed by vp_destroy.
+ * Streams: work is enqueued on the hipStream_t given to vp_create (NULL = the
+ *   null stream).  Calls return once the work is enqueued unless stated
+ *   otherwise; vp_sync waits and reports device-side error flags.
+ * Errors: every call returns a vp_status; vp_last_error(ctx) returns the
+ *   message of the last failure on that context.  No outputs are promised
+ *   after an error.  A context is not thread-safe; distinct contexts are
+ *   independent.
+ */
+#ifndef VMCPEPS_H
+#define VMCPEPS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  VP_OK = 0,
+  VP_ERR_ARG = 1,            /* null pointer, index out of range, bad enum */
+  VP_ERR_SHAPE = 2,          /* D < 1, Dc < 1, odd N, spins not in S^z = 0, sizes too large */
+  VP_ERR_OOM = 3,            /* device allocation failed */
+  VP_ERR_DEVICE = 4,         /* a HIP runtime call failed */
+  VP_ERR_ZERO_AMPLITUDE = 5, /* a network that must be non-zero was exactly zero */
+  VP_ERR_NONFINITE = 6,      /* a non-finite value appeared in a network */
+  VP_ERR_UNSUPPORTED = 7     /* the requested mode is not built */
+} vp_status;
+
+typedef enum { VP_FP64 = 0, VP_FP32 = 1, VP_BF16 = 2 } vp_prec;
+
+typedef struct {
+  int32_t Ly, Lx;      /* lattice extent */
+  int32_t D;           /* PEPS virtual bond dimension */
+  int32_t Dc;          /* boundary-MPS cutoff */
+  double J1, J2;       /* nearest-neighbour and diagonal couplings */
+  int32_t prec;        /* vp_prec of the contractions */
+  int32_t n_chains;    /* Markov chains kept on the device */
+} vp_lattice;
+
+typedef struct vp_ctx vp_ctx;
+
+/* Create a context for n_lats lattices; allocates every device buffer the
+ * sweeps need for n_chains chains of each lattice.  seed is the Philox key
+ * word 0; the lattice index is key word 1.  stream: a hipStream_t or NULL. */
+vp_status vp_create(const vp_lattice* lats, int32_t n_lats, uint64_t seed, void* stream, vp_ctx** out);
+vp_status vp_destroy(vp_ctx* ctx);
+const char* vp_last_error(const vp_ctx* ctx);
+
+/* Np = sum_k 2*dim(l)dim(u)dim(r)dim(d) (Sec. II.B counts 7,496,192 for 32x32, D=8). */
+int64_t vp_num_params(const vp_lattice* lat);
+/* Bytes of device workspace vp_create allocates for this lattice. */
+int64_t vp_workspace_bytes(const vp_lattice* lat);
+
+/* Canonical flat float64 tensors in or out (Np numbers).  T_dev is a device pointer. */
+vp_status vp_set_tensors(vp_ctx* ctx, int32_t lat, const double* T_dev);
+vp_status vp_get_tensors(vp_ctx* ctx, int32_t lat, double* T_dev);
+/* T = scale * xi + perturb * xi', xi, xi' ~ N(0,1) by Box-Muller on Philox
+ * words 0 and 1 of counters (p, 0, 0, 1) and (p, 0, 0, 2), key (seed, lat).
+ * scale <= 0 selects 1/D^2. */
+vp_status vp_init_tensors(vp_ctx* ctx, int32_t lat, uint64_t seed, double scale, double perturb);
+
+/* Set every chain's configuration: spins_dev [n_chains][N] int8, or NULL for
+ * a Fisher-Yates shuffle of the Neel list per chain (index j = floor(u (i+1))
+ * from counter (chain, 0, i, 3)).  Resets the sweep counters to 0. */
+vp_status vp_init_chains(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev);
+
+/* Run n_burn + n_meas sequential sweeps on every chain (Sec. II.A Eq. (9)),
+ * measuring after each of the last n_meas.  Outputs, indexed [chain][m]:
+ * log_abs_psi_dev, sign_dev (+1/-1), e_loc_dev (total energy, not per site),
+ * dlnpsi_dev ([chain][m][Np/2] in the working precision: float64 for VP_FP64,
+ * float32 otherwise; may be NULL), spins_out_dev ([chain][m][N], may be NULL).
+ * accept_dev ([chain][2] int64: accepted, proposed; accumulated; may be NULL). */
+vp_status vp_sample(vp_ctx* ctx, int32_t lat, int32_t n_burn, int32_t n_meas,
+                    double* log_abs_psi_dev, int8_t* sign_dev, double* e_loc_dev,
+                    void* dlnpsi_dev, int8_t* spins_out_dev, int64_t* accept_dev);
+
+/* Evaluate fixed configurations spins_dev [n_cfg][N] (n_cfg <= n_chains):
+ * the same outputs as one measured sweep without Metropolis moves, plus every
+ * pair ratio (ratios_dev [n_cfg][n_pairs], 0 for parallel pairs; may be NULL).
+ * n_pairs = Ly(Lx-1) + (Ly-1)Lx (+ 2(Ly-1)(Lx-1) when J2 != 0). */
+vp_status vp_eval(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev, int32_t n_cfg,
+                  double* log_abs_psi_dev, int8_t* sign_dev, double* e_loc_dev,
+                  void* dlnpsi_dev, double* ratios_dev);
+
+/* Eq. (5): grad = <G E_loc> - <G><E_loc> over n_samples samples (compact
+ * dlnpsi in the working precision, their spins [n][N]); grad_dev [Np] float64,
+ * e_mean_dev one float64. */
+vp_status vp_gradient(vp_ctx* ctx, int32_t lat, const double* e_loc_dev, const void* dlnpsi_dev,
+                      const int8_t* spins_dev, int64_t n_samples, double* grad_dev, double* e_mean_dev);
+
+/* Stochastic reconfiguration: (S + shift I) delta = g with S the covariance of
+ * the full-layout log-derivatives, solved in float64 by Cholesky; then
+ * T <- T - lr * delta.  delta_dev [Np] may be NULL.  Needs Np <= 32768. */
+vp_status vp_sr_update(vp_ctx* ctx, int32_t lat, const double* e_loc_dev, const void* dlnpsi_dev,
+                       const int8_t* spins_dev, int64_t n_samples, double shift, double lr,
+                       double* delta_dev);
+
+/* Eq. (10): T <- T - r * step_len * sgn(grad), r = uniform from counter
+ * (p, step, 0, 5) per element p. */
+vp_status vp_sign_sgd_update(vp_ctx* ctx, int32_t lat, const double* grad_dev, double step_len, uint64_t step);
+
+/* Wait for the context's stream; report device-side error flags. */
+vp_status vp_sync(vp_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VMCPEPS_H */

@@ -1,0 +1,152 @@
+"""Thin ctypes binding of ``libvmcpeps.so`` (the C ABI in ``include/vmcpeps.h``).
+
+Argument marshalling only: every step of the method runs in the HIP library.
+Device buffers are torch tensors on the current HIP device; the functions pass
+their ``data_ptr()`` and shapes.  Importing this module loads the library and
+raises if it is missing; there is no CPU fallback.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvmcpeps.so")
+
+VP_OK, VP_ERR_ARG, VP_ERR_SHAPE, VP_ERR_OOM, VP_ERR_DEVICE = 0, 1, 2, 3, 4
+VP_ERR_ZERO_AMPLITUDE, VP_ERR_NONFINITE, VP_ERR_UNSUPPORTED = 5, 6, 7
+VP_FP64, VP_FP32, VP_BF16 = 0, 1, 2
+
+STATUS_NAMES = {0: "VP_OK", 1: "VP_ERR_ARG", 2: "VP_ERR_SHAPE", 3: "VP_ERR_OOM", 4: "VP_ERR_DEVICE",
+                5: "VP_ERR_ZERO_AMPLITUDE", 6: "VP_ERR_NONFINITE", 7: "VP_ERR_UNSUPPORTED"}
+
+EXPORTED = ["vp_create", "vp_destroy", "vp_last_error", "vp_num_params", "vp_workspace_bytes",
+            "vp_set_tensors", "vp_get_tensors", "vp_init_tensors", "vp_init_chains", "vp_sample",
+            "vp_eval", "vp_gradient", "vp_sr_update", "vp_sign_sgd_update", "vp_sync"]
+
+
+class vp_lattice(ctypes.Structure):
+    _fields_ = [("Ly", ctypes.c_int32), ("Lx", ctypes.c_int32), ("D", ctypes.c_int32), ("Dc", ctypes.c_int32),
+                ("J1", ctypes.c_double), ("J2", ctypes.c_double), ("prec", ctypes.c_int32),
+                ("n_chains", ctypes.c_int32)]
+
+
+class VPError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1908_09359_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, U64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
+    sig = {
+        "vp_create": ([ctypes.POINTER(vp_lattice), I32, U64, P, ctypes.POINTER(P)], I32),
+        "vp_destroy": ([P], I32),
+        "vp_last_error": ([P], ctypes.c_char_p),
+        "vp_num_params": ([ctypes.POINTER(vp_lattice)], I64),
+        "vp_workspace_bytes": ([ctypes.POINTER(vp_lattice)], I64),
+        "vp_set_tensors": ([P, I32, P], I32),
+        "vp_get_tensors": ([P, I32, P], I32),
+        "vp_init_tensors": ([P, I32, U64, D, D], I32),
+        "vp_init_chains": ([P, I32, P], I32),
+        "vp_sample": ([P, I32, I32, I32, P, P, P, P, P, P], I32),
+        "vp_eval": ([P, I32, P, I32, P, P, P, P, P], I32),
+        "vp_gradient": ([P, I32, P, P, P, I64, P, P], I32),
+        "vp_sr_update": ([P, I32, P, P, P, I64, D, D, P], I32),
+        "vp_sign_sgd_update": ([P, I32, P, D, U64], I32),
+        "vp_sync": ([P], I32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+LIB = _load()
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def lattice(Ly, Lx, D, Dc, J1=1.0, J2=0.0, prec=VP_FP64, n_chains=1):
+    return vp_lattice(Ly, Lx, D, Dc, J1, J2, prec, n_chains)
+
+
+def vp_num_params(lat):
+    return int(LIB.vp_num_params(ctypes.byref(lat)))
+
+
+def vp_workspace_bytes(lat):
+    return int(LIB.vp_workspace_bytes(ctypes.byref(lat)))
+
+
+class Context:
+    """Owns a vp_ctx; methods mirror the C functions of the same names."""
+
+    def __init__(self, lats, seed=0, stream=None):
+        if isinstance(lats, vp_lattice):
+            lats = [lats]
+        self.lats = list(lats)
+        arr = (vp_lattice * len(self.lats))(*self.lats)
+        h = ctypes.c_void_p()
+        st = LIB.vp_create(arr, len(self.lats), ctypes.c_uint64(seed),
+                           ctypes.c_void_p(stream) if stream else None, ctypes.byref(h))
+        if st != VP_OK:
+            raise VPError(st, LIB.vp_last_error(None).decode())
+        self.h = h
+
+    def _check(self, st):
+        if st != VP_OK:
+            raise VPError(st, LIB.vp_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            LIB.vp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def num_params(self, lat=0):
+        return vp_num_params(self.lats[lat])
+
+    def vp_set_tensors(self, lat, T):
+        self._check(LIB.vp_set_tensors(self.h, lat, _ptr(T)))
+
+    def vp_get_tensors(self, lat, T):
+        self._check(LIB.vp_get_tensors(self.h, lat, _ptr(T)))
+
+    def vp_init_tensors(self, lat, seed, scale=0.0, perturb=0.0):
+        self._check(LIB.vp_init_tensors(self.h, lat, ctypes.c_uint64(seed), scale, perturb))
+
+    def vp_init_chains(self, lat, spins=None):
+        self._check(LIB.vp_init_chains(self.h, lat, _ptr(spins)))
+
+    def vp_sample(self, lat, n_burn, n_meas, log_abs_psi, sign, e_loc, dlnpsi=None, spins_out=None,
+                  accept=None):
+        self._check(LIB.vp_sample(self.h, lat, n_burn, n_meas, _ptr(log_abs_psi), _ptr(sign), _ptr(e_loc),
+                                  _ptr(dlnpsi), _ptr(spins_out), _ptr(accept)))
+
+    def vp_eval(self, lat, spins, n_cfg, log_abs_psi, sign, e_loc, dlnpsi=None, ratios=None):
+        self._check(LIB.vp_eval(self.h, lat, _ptr(spins), n_cfg, _ptr(log_abs_psi), _ptr(sign), _ptr(e_loc),
+                                _ptr(dlnpsi), _ptr(ratios)))
+
+    def vp_gradient(self, lat, e_loc, dlnpsi, spins, n_samples, grad, e_mean):
+        self._check(LIB.vp_gradient(self.h, lat, _ptr(e_loc), _ptr(dlnpsi), _ptr(spins), n_samples,
+                                    _ptr(grad), _ptr(e_mean)))
+
+    def vp_sr_update(self, lat, e_loc, dlnpsi, spins, n_samples, shift, lr, delta=None):
+        self._check(LIB.vp_sr_update(self.h, lat, _ptr(e_loc), _ptr(dlnpsi), _ptr(spins), n_samples, shift, lr,
+                                     _ptr(delta)))
+
+    def vp_sign_sgd_update(self, lat, grad, step_len, step):
+        self._check(LIB.vp_sign_sgd_update(self.h, lat, _ptr(grad), step_len, ctypes.c_uint64(step)))
+
+    def vp_sync(self):
+        self._check(LIB.vp_sync(self.h))

@@ -1,0 +1,547 @@
+// Host runtime and C ABI of the VMC-PEPS library: context and workspace
+// planning, tensor staging, and the sweep schedule that enqueues the phase
+// kernels row by row on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/vmcpeps.h"
+#include "vp_kernels.hpp"
+
+using namespace vp;
+
+namespace {
+
+struct Lattice {
+  vp_lattice p{};
+  int N = 0;
+  int64_t Np = 0;
+  std::vector<int64_t> offs;    // canonical offsets per site (N+1)
+  std::vector<int64_t> coff;    // compact offsets per site (N+1)
+  std::vector<int32_t> dims;    // [N][4]
+  std::vector<int32_t> sizes;   // l*u*r*d per site
+  std::vector<int32_t> kU, kD;  // boundary bond dims
+  size_t tsize = 8;             // bytes of the working type
+  // device buffers
+  double* T = nullptr;          // canonical float64 tensors
+  void* Tw = nullptr;           // padded working tensors
+  void* ws = nullptr;
+  int32_t* iws = nullptr;
+  double* dws = nullptr;
+  ChainMeta* meta = nullptr;
+  int8_t* spins = nullptr;
+  int32_t *d_kU = nullptr, *d_kD = nullptr, *d_dims = nullptr, *d_sizes = nullptr;
+  int64_t *d_offs = nullptr, *d_coff = nullptr;
+  double* d_scratch = nullptr;  // small scalar scratch
+  LatDev dev{};
+  bool tensors_ready = false;
+  bool chains_ready = false;
+  bool lower_valid = false;     // D boundaries match the current spins
+};
+
+}  // namespace
+
+struct vp_ctx {
+  std::vector<Lattice> lats;
+  uint64_t seed = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+vp_status fail(vp_ctx* ctx, vp_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (ctx) ctx->err = buf;
+  g_err = buf;
+  return st;
+}
+
+#define HIP_TRY(ctx, expr)                                                                  \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) return fail((ctx), VP_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+void site_dims(const vp_lattice& p, int y, int x, int32_t out[4]) {
+  out[0] = x > 0 ? p.D : 1;
+  out[1] = y > 0 ? p.D : 1;
+  out[2] = x < p.Lx - 1 ? p.D : 1;
+  out[3] = y < p.Ly - 1 ? p.D : 1;
+}
+
+// Bond dimensions of every boundary MPS produced by the canonical compression:
+// alpha'_0 = 1, alpha'_{j+1} = min(alpha'_j p_j, alpha_{j+1}); k_j = min(Dc, alpha'_j, p_j k_{j+1}).
+void plan_bonds(Lattice& L) {
+  const vp_lattice& p = L.p;
+  const int W = p.Lx + 1;
+  L.kU.assign((size_t)(p.Ly + 1) * W, 1);
+  L.kD.assign((size_t)(p.Ly + 1) * W, 1);
+  auto compress_dims = [&](const int32_t* kin, int y, bool upper, int32_t* kout) {
+    std::vector<int64_t> alpha(W), ap(W);
+    for (int j = 0; j <= p.Lx; ++j) {
+      int l = (j == 0 || j == p.Lx) ? 1 : p.D;
+      alpha[j] = (int64_t)kin[j] * l;
+    }
+    auto phys = [&](int j) {
+      int32_t dd[4];
+      site_dims(p, y, j, dd);
+      return upper ? dd[3] : dd[1];
+    };
+    ap[0] = 1;
+    for (int j = 0; j < p.Lx; ++j) ap[j + 1] = std::min<int64_t>(ap[j] * phys(j), alpha[j + 1]);
+    kout[p.Lx] = 1;
+    for (int j = p.Lx - 1; j >= 1; --j)
+      kout[j] = (int32_t)std::min<int64_t>(std::min<int64_t>(p.Dc, ap[j]), (int64_t)phys(j) * kout[j + 1]);
+    kout[0] = 1;
+  };
+  for (int y = 0; y <= p.Ly - 2; ++y) compress_dims(&L.kU[(size_t)y * W], y, true, &L.kU[(size_t)(y + 1) * W]);
+  for (int y = p.Ly - 1; y >= 1; --y) compress_dims(&L.kD[(size_t)(y + 1) * W], y, false, &L.kD[(size_t)y * W]);
+}
+
+struct Plan {
+  int64_t ws = 0, iws = 0, dws = 0;
+};
+
+Plan plan_workspace(const vp_lattice& p, LatDev* dev) {
+  const int64_t c = p.Dc, d = p.D, Lx = p.Lx, Ly = p.Ly;
+  const int64_t s3 = c * d * c, s4 = c * d * d * c, sx = c * c * d * d * d;
+  int64_t o = 0;
+  auto take = [&](int64_t n) {
+    int64_t r = o;
+    o += (n + 63) & ~int64_t(63);
+    return r;
+  };
+  LatDev L{};
+  L.oUb = take((Ly + 1) * Lx * s3);
+  L.oDb = take((Ly + 1) * Lx * s3);
+  L.oL3 = take((Lx + 1) * s3);
+  L.oR3 = take((Lx + 1) * s3);
+  L.oT3 = take(4 * s3);
+  L.oL4 = take((Lx + 1) * s4);
+  L.oR4 = take((Lx + 1) * s4);
+  L.oT4 = take(4 * s4);
+  L.oG = take(Lx * s4);
+  L.oX0 = take(sx);
+  L.oX1 = take(sx);
+  L.oY = take(s4);
+  L.oW = take(s4);
+  L.oH = take(s4);
+  L.oV = take(s4);
+  L.oTa = take(s3);
+  L.oTb = take(s3);
+  L.oDl = take(d * d * d * d);
+  Plan P;
+  P.ws = o;
+  int64_t io = 0;
+  L.ieL3 = io; io += Lx + 2;
+  L.ieR3 = io; io += Lx + 2;
+  L.ieT3 = io; io += 4;
+  L.ieL4 = io; io += Lx + 2;
+  L.ieR4 = io; io += Lx + 2;
+  L.ieT4 = io; io += 4;
+  P.iws = (io + 15) & ~int64_t(15);
+  L.dlamU = 0;
+  L.dlamD = Ly + 1;
+  P.dws = ((2 * (Ly + 1)) + 7) & ~int64_t(7);
+  if (dev) *dev = L;
+  return P;
+}
+
+size_t type_size(int prec) { return prec == VP_FP64 ? 8 : 4; }
+
+vp_status check_lattice(vp_ctx* ctx, const vp_lattice& p) {
+  if (p.Ly < 1 || p.Lx < 1 || p.D < 1 || p.Dc < 1 || p.n_chains < 1)
+    return fail(ctx, VP_ERR_SHAPE, "Ly, Lx, D, Dc and n_chains must be >= 1");
+  if ((p.Ly * p.Lx) % 2)
+    return fail(ctx, VP_ERR_SHAPE, "the S^z_tot = 0 sector needs an even number of sites");
+  if (p.Ly * p.Lx > 4096) return fail(ctx, VP_ERR_SHAPE, "at most 4096 sites");
+  if (p.D > 16 || p.Dc > 64 || p.D * p.Dc > 256)
+    return fail(ctx, VP_ERR_SHAPE, "sizes beyond the built kernels (D <= 16, Dc <= 64, D*Dc <= 256)");
+  if (p.prec != VP_FP64 && p.prec != VP_FP32)
+    return fail(ctx, VP_ERR_UNSUPPORTED, "precision %d is not built", p.prec);
+  return VP_OK;
+}
+
+Lattice* get_lat(vp_ctx* ctx, int32_t lat) {
+  if (!ctx || lat < 0 || lat >= (int32_t)ctx->lats.size()) return nullptr;
+  return &ctx->lats[lat];
+}
+
+template <typename T>
+void run_lower_pass(Lattice& L, hipStream_t s) {
+  for (int y = L.p.Ly - 1; y >= 1; --y) launch_compress<T>(L.dev, y, 0, s);
+}
+
+template <typename T>
+void run_sweep(Lattice& L, const SampleOut* o, hipStream_t s) {
+  const int Ly = L.p.Ly;
+  // top-down sampling pass
+  for (int y = 0; y < Ly; ++y) {
+    launch_row3_right<T>(L.dev, y, y, y + 1, s);
+    launch_hsweep<T>(L.dev, y, y == Ly - 1, s);
+    if (y < Ly - 1) {
+      launch_row4_right<T>(L.dev, y, s);
+      launch_vsweep<T>(L.dev, y, s);
+      launch_compress<T>(L.dev, y, 1, s);
+    }
+  }
+  // bottom-up measurement pass, rebuilding the lower boundaries
+  if (o) launch_begin_sample(L.dev, s);
+  for (int y = Ly - 1; y >= 0; --y) {
+    if (o) {
+      launch_measure3<T>(L.dev, y, *o, s);
+      if (y < Ly - 1) launch_measure4<T>(L.dev, y, *o, s);
+    }
+    if (y >= 1) launch_compress<T>(L.dev, y, 0, s);
+  }
+  if (o) launch_finish_sample(L.dev, *o, L.p.n_chains, s);
+  launch_next_sweep(L.dev, s);
+}
+
+template <typename T>
+void run_eval(const LatDev& D, const SampleOut& o, int n_cfg, hipStream_t s) {
+  const int Ly = D.Ly;
+  for (int y = 0; y < Ly - 1; ++y) launch_compress<T>(D, y, 1, s);
+  launch_psi_fixed<T>(D, s);
+  launch_begin_sample(D, s);
+  for (int y = Ly - 1; y >= 0; --y) {
+    launch_measure3<T>(D, y, o, s);
+    if (y < Ly - 1) launch_measure4<T>(D, y, o, s);
+    if (y >= 1) launch_compress<T>(D, y, 0, s);
+  }
+  launch_finish_sample(D, o, n_cfg, s);
+}
+
+vp_status check_flags(vp_ctx* ctx, Lattice& L) {
+  std::vector<ChainMeta> m(L.p.n_chains);
+  HIP_TRY(ctx, hipMemcpyAsync(m.data(), L.meta, sizeof(ChainMeta) * m.size(), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  int zero = 0, nonfin = 0;
+  for (auto& x : m) {
+    zero += (x.flags & FLAG_ZERO) != 0;
+    nonfin += (x.flags & FLAG_NONFINITE) != 0;
+  }
+  if (nonfin) return fail(ctx, VP_ERR_NONFINITE, "%d chain(s) produced a non-finite value", nonfin);
+  if (zero) return fail(ctx, VP_ERR_ZERO_AMPLITUDE, "%d chain(s) met a zero amplitude", zero);
+  return VP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t vp_num_params(const vp_lattice* p) {
+  if (!p || p->Ly < 1 || p->Lx < 1 || p->D < 1) return -1;
+  int64_t n = 0;
+  for (int y = 0; y < p->Ly; ++y)
+    for (int x = 0; x < p->Lx; ++x) {
+      int32_t d[4];
+      site_dims(*p, y, x, d);
+      n += 2LL * d[0] * d[1] * d[2] * d[3];
+    }
+  return n;
+}
+
+int64_t vp_workspace_bytes(const vp_lattice* p) {
+  if (!p) return -1;
+  Plan P = plan_workspace(*p, nullptr);
+  return (int64_t)p->n_chains * (P.ws * (int64_t)type_size(p->prec) + P.iws * 4 + P.dws * 8 + p->Ly * p->Lx +
+                                 (int64_t)sizeof(ChainMeta));
+}
+
+const char* vp_last_error(const vp_ctx* ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
+
+vp_status vp_create(const vp_lattice* lats, int32_t n_lats, uint64_t seed, void* stream, vp_ctx** out) {
+  if (!lats || n_lats < 1 || !out) return fail(nullptr, VP_ERR_ARG, "null argument or n_lats < 1");
+  *out = nullptr;
+  for (int i = 0; i < n_lats; ++i) {
+    vp_status st = check_lattice(nullptr, lats[i]);
+    if (st != VP_OK) return st;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+    return fail(nullptr, VP_ERR_DEVICE, "no HIP device available");
+  vp_ctx* ctx = new vp_ctx;
+  ctx->seed = seed;
+  ctx->stream = (hipStream_t)stream;
+  ctx->lats.resize(n_lats);
+  for (int i = 0; i < n_lats; ++i) {
+    Lattice& L = ctx->lats[i];
+    L.p = lats[i];
+    const vp_lattice& p = L.p;
+    L.N = p.Ly * p.Lx;
+    L.tsize = type_size(p.prec);
+    L.offs.assign(L.N + 1, 0);
+    L.coff.assign(L.N + 1, 0);
+    L.dims.assign(4 * L.N, 1);
+    L.sizes.assign(L.N, 0);
+    for (int k = 0; k < L.N; ++k) {
+      site_dims(p, k / p.Lx, k % p.Lx, &L.dims[4 * k]);
+      L.sizes[k] = L.dims[4 * k] * L.dims[4 * k + 1] * L.dims[4 * k + 2] * L.dims[4 * k + 3];
+      L.offs[k + 1] = L.offs[k] + 2LL * L.sizes[k];
+      L.coff[k + 1] = L.coff[k] + L.sizes[k];
+    }
+    L.Np = L.offs[L.N];
+    plan_bonds(L);
+    Plan P = plan_workspace(p, &L.dev);
+    const int64_t d4 = (int64_t)p.D * p.D * p.D * p.D;
+    auto alloc = [&](void** ptr, size_t bytes) -> bool { return hipMalloc(ptr, std::max<size_t>(bytes, 64)) == hipSuccess; };
+    bool ok = alloc((void**)&L.T, sizeof(double) * L.Np) && alloc(&L.Tw, L.tsize * L.N * 2 * d4) &&
+              alloc(&L.ws, L.tsize * P.ws * p.n_chains) && alloc((void**)&L.iws, 4 * P.iws * p.n_chains) &&
+              alloc((void**)&L.dws, 8 * P.dws * p.n_chains) &&
+              alloc((void**)&L.meta, sizeof(ChainMeta) * p.n_chains) &&
+              alloc((void**)&L.spins, (size_t)p.n_chains * L.N) &&
+              alloc((void**)&L.d_kU, 4 * L.kU.size()) && alloc((void**)&L.d_kD, 4 * L.kD.size()) &&
+              alloc((void**)&L.d_dims, 4 * L.dims.size()) && alloc((void**)&L.d_sizes, 4 * L.sizes.size()) &&
+              alloc((void**)&L.d_offs, 8 * L.offs.size()) && alloc((void**)&L.d_coff, 8 * L.coff.size()) &&
+              alloc((void**)&L.d_scratch, 64 * sizeof(double));
+    if (!ok) {
+      vp_destroy(ctx);
+      return fail(nullptr, VP_ERR_OOM, "device allocation failed for lattice %d", i);
+    }
+    hipMemcpy(L.d_kU, L.kU.data(), 4 * L.kU.size(), hipMemcpyHostToDevice);
+    hipMemcpy(L.d_kD, L.kD.data(), 4 * L.kD.size(), hipMemcpyHostToDevice);
+    hipMemcpy(L.d_dims, L.dims.data(), 4 * L.dims.size(), hipMemcpyHostToDevice);
+    hipMemcpy(L.d_sizes, L.sizes.data(), 4 * L.sizes.size(), hipMemcpyHostToDevice);
+    hipMemcpy(L.d_offs, L.offs.data(), 8 * L.offs.size(), hipMemcpyHostToDevice);
+    hipMemcpy(L.d_coff, L.coff.data(), 8 * L.coff.size(), hipMemcpyHostToDevice);
+    hipMemset(L.ws, 0, L.tsize * P.ws * p.n_chains);
+    hipMemset(L.iws, 0, 4 * P.iws * p.n_chains);
+    hipMemset(L.dws, 0, 8 * P.dws * p.n_chains);
+    hipMemset(L.meta, 0, sizeof(ChainMeta) * p.n_chains);
+    hipMemset(L.spins, 0, (size_t)p.n_chains * L.N);
+    LatDev& D = L.dev;
+    D.Ly = p.Ly; D.Lx = p.Lx; D.d = p.D; D.c = p.Dc; D.N = L.N;
+    D.J1 = p.J1; D.J2 = p.J2; D.n_chains = p.n_chains;
+    D.seed = seed; D.lat_id = i;
+    D.Tw = L.Tw; D.ws = L.ws; D.ws_stride = P.ws;
+    D.iws = L.iws; D.iws_stride = P.iws; D.dws = L.dws; D.dws_stride = P.dws;
+    D.meta = L.meta; D.spins = L.spins;
+    D.kU = L.d_kU; D.kD = L.d_kD; D.dims = L.d_dims; D.coff = L.d_coff;
+    if (p.prec == VP_FP64) launch_init_trivial<double>(D, ctx->stream);
+    else launch_init_trivial<float>(D, ctx->stream);
+    if (hipGetLastError() != hipSuccess) {
+      vp_destroy(ctx);
+      return fail(nullptr, VP_ERR_DEVICE, "kernel launch failed while creating the context");
+    }
+  }
+  *out = ctx;
+  return VP_OK;
+}
+
+vp_status vp_destroy(vp_ctx* ctx) {
+  if (!ctx) return VP_OK;
+  for (auto& L : ctx->lats) {
+    void* ptrs[] = {L.T, L.Tw, L.ws, L.iws, L.dws, L.meta, L.spins, L.d_kU, L.d_kD,
+                    L.d_dims, L.d_sizes, L.d_offs, L.d_coff, L.d_scratch};
+    for (void* q : ptrs)
+      if (q) hipFree(q);
+  }
+  delete ctx;
+  return VP_OK;
+}
+
+static vp_status stage_tensors(vp_ctx* ctx, Lattice& L) {
+  if (L.p.prec == VP_FP64)
+    launch_prepare_tensors<double>(L.dev, L.T, (double*)L.Tw, L.d_offs, ctx->stream);
+  else
+    launch_prepare_tensors<float>(L.dev, L.T, (float*)L.Tw, L.d_offs, ctx->stream);
+  HIP_TRY(ctx, hipGetLastError());
+  L.tensors_ready = true;
+  L.lower_valid = false;
+  return VP_OK;
+}
+
+vp_status vp_set_tensors(vp_ctx* ctx, int32_t lat, const double* T_dev) {
+  Lattice* L = get_lat(ctx, lat);
+  if (!L || !T_dev) return fail(ctx, VP_ERR_ARG, "bad lattice index or null tensor pointer");
+  HIP_TRY(ctx, hipMemcpyAsync(L->T, T_dev, sizeof(double) * L->Np, hipMemcpyDeviceToDevice, ctx->stream));
+  return stage_tensors(ctx, *L);
+}
+
+vp_status vp_get_tensors(vp_ctx* ctx, int32_t lat, double* T_dev) {
+  Lattice* L = get_lat(ctx, lat);
+  if (!L || !T_dev) return fail(ctx, VP_ERR_ARG, "bad lattice index or null tensor pointer");
+  HIP_TRY(ctx, hipMemcpyAsync(T_dev, L->T, sizeof(double) * L->Np, hipMemcpyDeviceToDevice, ctx->stream));
+  return VP_OK;
+}
+
+vp_status vp_init_tensors(vp_ctx* ctx, int32_t lat, uint64_t seed, double scale, double perturb) {
+  Lattice* L = get_lat(ctx, lat);
+  if (!L) return fail(ctx, VP_ERR_ARG, "bad lattice index");
+  if (!(scale > 0)) scale = 1.0 / ((double)L->p.D * L->p.D);
+  launch_init_tensors(L->T, L->Np, seed, lat, scale, perturb, ctx->stream);
+  HIP_TRY(ctx, hipGetLastError());
+  return stage_tensors(ctx, *L);
+}
+
+vp_status vp_init_chains(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev) {
+  Lattice* L = get_lat(ctx, lat);
+  if (!L) return fail(ctx, VP_ERR_ARG, "bad lattice index");
+  if (spins_dev) {
+    std::vector<int8_t> h((size_t)L->p.n_chains * L->N);
+    HIP_TRY(ctx, hipMemcpyAsync(h.data(), spins_dev, h.size(), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    for (int ch = 0; ch < L->p.n_chains; ++ch) {
+      int up = 0;
+      for (int i = 0; i < L->N; ++i) {
+        int8_t v = h[(size_t)ch * L->N + i];
+        if (v != 0 && v != 1) return fail(ctx, VP_ERR_SHAPE, "spins must be 0 or 1");
+        up += v;
+      }
+      if (2 * up != L->N) return fail(ctx, VP_ERR_SHAPE, "chain %d is not in the S^z_tot = 0 sector", ch);
+    }
+    HIP_TRY(ctx, hipMemcpyAsync(L->spins, spins_dev, h.size(), hipMemcpyDeviceToDevice, ctx->stream));
+    HIP_TRY(ctx, hipMemsetAsync(L->meta, 0, sizeof(ChainMeta) * L->p.n_chains, ctx->stream));
+  } else {
+    launch_init_chains(L->dev, ctx->stream);
+    HIP_TRY(ctx, hipGetLastError());
+  }
+  L->chains_ready = true;
+  L->lower_valid = false;
+  return VP_OK;
+}
+
+vp_status vp_sample(vp_ctx* ctx, int32_t lat, int32_t n_burn, int32_t n_meas, double* log_abs_psi_dev,
+                    int8_t* sign_dev, double* e_loc_dev, void* dlnpsi_dev, int8_t* spins_out_dev,
+                    int64_t* accept_dev) {
+  Lattice* L = get_lat(ctx, lat);
+  if (!L) return fail(ctx, VP_ERR_ARG, "bad lattice index");
+  if (n_burn < 0 || n_meas < 0) return fail(ctx, VP_ERR_ARG, "negative sweep count");
+  if (!L->tensors_ready || !L->chains_ready)
+    return fail(ctx, VP_ERR_ARG, "tensors and chains must be initialised first");
+  if (n_meas > 0 && (!log_abs_psi_dev || !sign_dev || !e_loc_dev))
+    return fail(ctx, VP_ERR_ARG, "log_abs_psi, sign and e_loc outputs are required");
+  hipStream_t s = ctx->stream;
+  const bool f64 = L->p.prec == VP_FP64;
+  if (!L->lower_valid) {
+    if (f64) run_lower_pass<double>(*L, s); else run_lower_pass<float>(*L, s);
+    L->lower_valid = true;
+  }
+  SampleOut o{};
+  o.log_abs_psi = log_abs_psi_dev;
+  o.sign = sign_dev;
+  o.e_loc = e_loc_dev;
+  o.dlnpsi = dlnpsi_dev;
+  o.spins = spins_out_dev;
+  o.ratios = nullptr;
+  o.n_meas = n_meas;
+  o.np_half = L->Np / 2;
+  for (int i = 0; i < n_burn + n_meas; ++i) {
+    o.m = i - n_burn;
+    const SampleOut* op = i >= n_burn ? &o : nullptr;
+    if (f64) run_sweep<double>(*L, op, s); else run_sweep<float>(*L, op, s);
+    HIP_TRY(ctx, hipGetLastError());
+  }
+  if (accept_dev) {
+    // accepted / proposed pairs are the 2nd and 3rd int64 of ChainMeta
+    HIP_TRY(ctx, hipMemcpy2DAsync(accept_dev, 2 * sizeof(int64_t), (const char*)L->meta + sizeof(int64_t),
+                                  sizeof(ChainMeta), 2 * sizeof(int64_t), L->p.n_chains, hipMemcpyDeviceToDevice, s));
+  }
+  return VP_OK;
+}
+
+vp_status vp_eval(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev, int32_t n_cfg, double* log_abs_psi_dev,
+                  int8_t* sign_dev, double* e_loc_dev, void* dlnpsi_dev, double* ratios_dev) {
+  Lattice* L = get_lat(ctx, lat);
+  if (!L || !spins_dev) return fail(ctx, VP_ERR_ARG, "bad lattice index or null spins");
+  if (n_cfg < 1 || n_cfg > L->p.n_chains) return fail(ctx, VP_ERR_ARG, "need 1 <= n_cfg <= n_chains");
+  if (!L->tensors_ready) return fail(ctx, VP_ERR_ARG, "tensors must be set first");
+  if (!log_abs_psi_dev || !sign_dev || !e_loc_dev) return fail(ctx, VP_ERR_ARG, "null output pointer");
+  std::vector<int8_t> h((size_t)n_cfg * L->N);
+  HIP_TRY(ctx, hipMemcpyAsync(h.data(), spins_dev, h.size(), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  for (int ch = 0; ch < n_cfg; ++ch) {
+    int up = 0;
+    for (int i = 0; i < L->N; ++i) {
+      int8_t v = h[(size_t)ch * L->N + i];
+      if (v != 0 && v != 1) return fail(ctx, VP_ERR_SHAPE, "spins must be 0 or 1");
+      up += v;
+    }
+    if (2 * up != L->N) return fail(ctx, VP_ERR_SHAPE, "configuration %d is not in the S^z_tot = 0 sector", ch);
+  }
+  hipStream_t s = ctx->stream;
+  // Evaluation reuses the chain slots; the sampler's state is invalidated.
+  launch_copy_spins(L->dev, spins_dev, n_cfg, s);
+  LatDev D = L->dev;
+  D.n_chains = n_cfg;
+  const vp_lattice& p = L->p;
+  SampleOut o{};
+  o.log_abs_psi = log_abs_psi_dev;
+  o.sign = sign_dev;
+  o.e_loc = e_loc_dev;
+  o.dlnpsi = dlnpsi_dev;
+  o.ratios = ratios_dev;
+  o.n_meas = 1;
+  o.m = 0;
+  o.np_half = L->Np / 2;
+  o.n_pairs = p.Ly * (p.Lx - 1) + (p.Ly - 1) * p.Lx + (p.J2 != 0.0 ? 2 * (p.Ly - 1) * (p.Lx - 1) : 0);
+  if (p.prec == VP_FP64) run_eval<double>(D, o, n_cfg, s); else run_eval<float>(D, o, n_cfg, s);
+  HIP_TRY(ctx, hipGetLastError());
+  L->chains_ready = false;
+  L->lower_valid = false;
+  // Errors in evaluated configurations are reported synchronously.
+  std::vector<ChainMeta> m(n_cfg);
+  HIP_TRY(ctx, hipMemcpyAsync(m.data(), L->meta, sizeof(ChainMeta) * n_cfg, hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  for (int i = 0; i < n_cfg; ++i) {
+    if (m[i].flags & FLAG_NONFINITE) return fail(ctx, VP_ERR_NONFINITE, "configuration %d: non-finite value", i);
+    if (m[i].flags & FLAG_ZERO) return fail(ctx, VP_ERR_ZERO_AMPLITUDE, "configuration %d: zero amplitude", i);
+  }
+  return VP_OK;
+}
+
+vp_status vp_gradient(vp_ctx* ctx, int32_t lat, const double* e_loc_dev, const void* dlnpsi_dev,
+                      const int8_t* spins_dev, int64_t n_samples, double* grad_dev, double* e_mean_dev) {
+  Lattice* L = get_lat(ctx, lat);
+  if (!L || !e_loc_dev || !dlnpsi_dev || !spins_dev || !grad_dev || !e_mean_dev)
+    return fail(ctx, VP_ERR_ARG, "bad lattice index or null pointer");
+  if (n_samples < 1) return fail(ctx, VP_ERR_ARG, "n_samples must be >= 1");
+  if (L->p.prec == VP_FP64)
+    launch_gradient<double>(L->d_offs, L->d_coff, L->d_sizes, L->N, L->Np, e_loc_dev, (const double*)dlnpsi_dev,
+                            spins_dev, n_samples, grad_dev, e_mean_dev, nullptr, ctx->stream);
+  else
+    launch_gradient<float>(L->d_offs, L->d_coff, L->d_sizes, L->N, L->Np, e_loc_dev, (const float*)dlnpsi_dev,
+                           spins_dev, n_samples, grad_dev, e_mean_dev, nullptr, ctx->stream);
+  HIP_TRY(ctx, hipGetLastError());
+  return VP_OK;
+}
+
+vp_status vp_sr_update(vp_ctx* ctx, int32_t lat, const double*, const void*, const int8_t*, int64_t, double,
+                       double, double*) {
+  if (!get_lat(ctx, lat)) return fail(ctx, VP_ERR_ARG, "bad lattice index");
+  return fail(ctx, VP_ERR_UNSUPPORTED, "vp_sr_update is not built yet");
+}
+
+vp_status vp_sign_sgd_update(vp_ctx* ctx, int32_t lat, const double* grad_dev, double step_len, uint64_t step) {
+  Lattice* L = get_lat(ctx, lat);
+  if (!L || !grad_dev) return fail(ctx, VP_ERR_ARG, "bad lattice index or null gradient");
+  launch_sign_sgd(L->T, grad_dev, L->Np, step_len, ctx->seed, lat, step, ctx->stream);
+  HIP_TRY(ctx, hipGetLastError());
+  return stage_tensors(ctx, *L);
+}
+
+vp_status vp_sync(vp_ctx* ctx) {
+  if (!ctx) return fail(nullptr, VP_ERR_ARG, "null context");
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  for (auto& L : ctx->lats) {
+    if (!L.chains_ready) continue;
+    vp_status st = check_flags(ctx, L);
+    if (st != VP_OK) return st;
+  }
+  return VP_OK;
+}
+
+}  // extern "C"

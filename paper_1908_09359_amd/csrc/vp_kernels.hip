@@ -1,0 +1,770 @@
+// Phase kernels of the VMC-PEPS hot path.  Each launch covers every chain of a
+// lattice (grid = chains, one 256-thread work-group per chain) and performs one
+// phase of a sweep for one row: right environments, the horizontal or vertical
+// Metropolis pass, the boundary compression, or the measurement of a row.
+#include "vp_device.hpp"
+#include "vp_kernels.hpp"
+
+#include <math.h>
+
+namespace vp {
+
+namespace {
+
+template <typename T>
+struct Chain {
+  T* ws;
+  int32_t* iw;
+  double* dw;
+  ChainMeta* meta;
+  int8_t* sp;
+};
+
+template <typename T>
+__device__ inline Chain<T> chain_of(const LatDev& L, int ch) {
+  Chain<T> C;
+  C.ws = (T*)L.ws + (int64_t)ch * L.ws_stride;
+  C.iw = L.iws + (int64_t)ch * L.iws_stride;
+  C.dw = L.dws + (int64_t)ch * L.dws_stride;
+  C.meta = L.meta + ch;
+  C.sp = L.spins + (int64_t)ch * L.N;
+  return C;
+}
+
+__device__ inline S4 st_std(int d) { return S4{d * d * d, d * d, d, 1}; }
+__device__ inline S4 st_mirror(S4 s) { return S4{s.r, s.u, s.l, s.d}; }
+__device__ inline S4 st_swapud(S4 s) { return S4{s.l, s.d, s.r, s.u}; }
+__device__ inline S3 sb_std(int c, int d) { return S3{d * c, c, 1}; }
+__device__ inline S3 sb_mirror(int c, int d) { return S3{1, c, d * c}; }
+
+template <typename T>
+__device__ inline const T* tw(const LatDev& L, int k, int s) {
+  const int d4 = L.d * L.d * L.d * L.d;
+  return (const T*)L.Tw + ((int64_t)k * 2 + s) * d4;
+}
+
+// Boundary site: slot holds U_{slot-1} (upper) or D_slot (lower).
+template <typename T>
+__device__ inline T* ub(const LatDev& L, const Chain<T>& C, int slot, int x) {
+  return C.ws + L.oUb + ((int64_t)slot * L.Lx + x) * (L.c * L.d * L.c);
+}
+template <typename T>
+__device__ inline T* db(const LatDev& L, const Chain<T>& C, int slot, int x) {
+  return C.ws + L.oDb + ((int64_t)slot * L.Lx + x) * (L.c * L.d * L.c);
+}
+
+__device__ inline int e3sz(const LatDev& L) { return L.c * L.d * L.c; }
+__device__ inline int e4sz(const LatDev& L) { return L.c * L.d * L.d * L.c; }
+
+template <typename T>
+__device__ inline void set_unit(T* x, int n) {
+  for (int i = threadIdx.x; i < n; i += WG) x[i] = (i == 0) ? T(1) : T(0);
+  __syncthreads();
+}
+
+__device__ inline void raise_flag(ChainMeta* m, int f) {
+  if (threadIdx.x == 0) m->flags |= f;
+}
+
+// 3-line column step with optional flipped site: t = T[s ^ flip].
+template <typename T>
+__device__ inline int step3(const LatDev& L, const Chain<T>& C, T* out, const T* in, int y, int x,
+                            int flip, const T* Ux, const T* Dx, bool right) {
+  int k = y * L.Lx + x;
+  const T* t = tw<T>(L, k, C.sp[k] ^ flip);
+  S4 st = st_std(L.d);
+  if (right)
+    env3_step<T>(out, in, Ux, sb_mirror(L.c, L.d), t, st_mirror(st), Dx, sb_mirror(L.c, L.d),
+                 C.ws + L.oX0, C.ws + L.oX1, L.c, L.d);
+  else
+    env3_step<T>(out, in, Ux, sb_std(L.c, L.d), t, st, Dx, sb_std(L.c, L.d), C.ws + L.oX0,
+                 C.ws + L.oX1, L.c, L.d);
+  return wg_renorm<T>(out, e3sz(L));
+}
+
+// 4-line column step over rows y and y+1; flip1/flip2 select the flipped slot.
+template <typename T>
+__device__ inline int step4(const LatDev& L, const Chain<T>& C, T* out, const T* in, int y, int x,
+                            int flip1, int flip2, const T* Ux, const T* Dx, bool right) {
+  int k1 = y * L.Lx + x, k2 = (y + 1) * L.Lx + x;
+  const T* t1 = tw<T>(L, k1, C.sp[k1] ^ flip1);
+  const T* t2 = tw<T>(L, k2, C.sp[k2] ^ flip2);
+  S4 st = st_std(L.d);
+  if (right)
+    env4_step<T>(out, in, Ux, sb_mirror(L.c, L.d), t1, st_mirror(st), t2, st_mirror(st), Dx,
+                 sb_mirror(L.c, L.d), C.ws + L.oX0, C.ws + L.oX1, L.c, L.d);
+  else
+    env4_step<T>(out, in, Ux, sb_std(L.c, L.d), t1, st, t2, st, Dx, sb_std(L.c, L.d),
+                 C.ws + L.oX0, C.ws + L.oX1, L.c, L.d);
+  return wg_renorm<T>(out, e4sz(L));
+}
+
+// value * 2^e as a double (exact scaling)
+__device__ inline double scaled(double v, int e) { return ldexp(v, e); }
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ void __launch_bounds__(WG) k_prepare_tensors(LatDev L, const double* __restrict__ Tflat,
+                                                        T* __restrict__ Tw, const int64_t* __restrict__ offs) {
+  const int d = L.d, d4 = d * d * d * d;
+  int64_t total = (int64_t)L.N * 2 * d4;
+  for (int64_t i = blockIdx.x * (int64_t)WG + threadIdx.x; i < total; i += (int64_t)gridDim.x * WG) {
+    int64_t k = i / (2 * d4);
+    int rem = (int)(i - k * 2 * d4);
+    int s = rem / d4, e = rem - s * d4;
+    int l = e / (d * d * d), u = (e / (d * d)) % d, r = (e / d) % d, dd = e % d;
+    int dl = L.dims[4 * k], du = L.dims[4 * k + 1], dr = L.dims[4 * k + 2], ddd = L.dims[4 * k + 3];
+    T v = T(0);
+    if (l < dl && u < du && r < dr && dd < ddd) {
+      int64_t n = (int64_t)dl * du * dr * ddd;
+      v = (T)Tflat[offs[k] + s * n + ((l * du + u) * dr + r) * ddd + dd];
+    }
+    Tw[i] = v;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(WG) k_init_trivial(LatDev L) {
+  Chain<T> C = chain_of<T>(L, blockIdx.x);
+  const int sz = L.c * L.d * L.c;
+  for (int x = 0; x < L.Lx; ++x) {
+    set_unit<T>(ub<T>(L, C, 0, x), sz);
+    set_unit<T>(db<T>(L, C, L.Ly, x), sz);
+  }
+  if (threadIdx.x == 0) {
+    C.dw[L.dlamU + 0] = 0.0;
+    C.dw[L.dlamD + L.Ly] = 0.0;
+  }
+}
+
+// R3[x] = R(x) for x = Lx-1 .. 1 of the network <D|row y|U>; R3[Lx] = ones.
+template <typename T>
+__global__ void __launch_bounds__(WG) k_row3_right(LatDev L, int y, int ub_slot, int db_slot) {
+  Chain<T> C = chain_of<T>(L, blockIdx.x);
+  const int sz = e3sz(L);
+  T* R = C.ws + L.oR3;
+  int* eR = C.iw + L.ieR3;
+  set_unit<T>(R + (int64_t)L.Lx * sz, sz);
+  if (threadIdx.x == 0) eR[L.Lx] = 0;
+  for (int x = L.Lx - 1; x >= 1; --x) {
+    int e = step3<T>(L, C, R + (int64_t)x * sz, R + (int64_t)(x + 1) * sz, y, x, 0,
+                     ub<T>(L, C, ub_slot, x), db<T>(L, C, db_slot, x), true);
+    if (threadIdx.x == 0) eR[x] = eR[x + 1] + e;
+    __syncthreads();
+  }
+}
+
+__device__ inline bool metropolis(const LatDev& L, ChainMeta* meta, double num, double den, int esum,
+                                  int bond) {
+  if (den == 0.0) {
+    raise_flag(meta, FLAG_ZERO);
+    return false;
+  }
+  double rho = scaled(num / den, esum);
+  double R = rho * rho;
+  if (!isfinite(R)) {
+    raise_flag(meta, FLAG_NONFINITE);
+    return false;
+  }
+  U64x4 w = philox4x64_10((uint64_t)blockIdx.x, (uint64_t)meta->sweep, (uint64_t)bond, TAG_METRO,
+                          L.seed, (uint64_t)L.lat_id);
+  double u = uniform53(w.v[0]);
+  return u < R;
+}
+
+// Horizontal bonds of row y, left to right (Sec. II.A Eq. (9)).  With moves = 0
+// no move is attempted.  For the last row the full amplitude is produced.
+template <typename T>
+__global__ void __launch_bounds__(WG) k_hsweep(LatDev L, int y, int last_row, int moves) {
+  Chain<T> C = chain_of<T>(L, blockIdx.x);
+  if (C.meta->flags) return;
+  const int sz = e3sz(L);
+  T* tmp = C.ws + L.oT3;
+  const T* R = C.ws + L.oR3;
+  const int* eR = C.iw + L.ieR3;
+  int slot[4] = {0, 1, 2, 3};  // cur, nxt, f1, f2
+  set_unit<T>(tmp + slot[0] * sz, sz);
+  int ecur = 0;
+  for (int x = 0; x < L.Lx - 1; ++x) {
+    const T* Ux = ub<T>(L, C, y, x);
+    const T* Dx = db<T>(L, C, y + 1, x);
+    T* cur = tmp + slot[0] * sz;
+    T* nxt = tmp + slot[1] * sz;
+    int enxt = ecur + step3<T>(L, C, nxt, cur, y, x, 0, Ux, Dx, false);
+    const int k = y * L.Lx + x;
+    bool acc = false;
+    if (moves && C.sp[k] != C.sp[k + 1]) {
+      T* f1 = tmp + slot[2] * sz;
+      T* f2 = tmp + slot[3] * sz;
+      int ef1 = ecur + step3<T>(L, C, f1, cur, y, x, 1, Ux, Dx, false);
+      int ef2 = ef1 + step3<T>(L, C, f2, f1, y, x + 1, 1, ub<T>(L, C, y, x + 1), db<T>(L, C, y + 1, x + 1), false);
+      double num = wg_dot<T>(f2, R + (int64_t)(x + 2) * sz, sz);
+      double den = wg_dot<T>(nxt, R + (int64_t)(x + 1) * sz, sz);
+      int bond = y * (2 * L.Lx - 1) + x;
+      acc = metropolis(L, C.meta, num, den, ef2 + eR[x + 2] - enxt - eR[x + 1], bond);
+      if (threadIdx.x == 0) {
+        C.meta->proposed += 1;
+        if (acc) {
+          int8_t a = C.sp[k];
+          C.sp[k] = C.sp[k + 1];
+          C.sp[k + 1] = a;
+          C.meta->accepted += 1;
+        }
+      }
+      __syncthreads();
+      if (acc) {  // column x now carries the exchanged tensor: f1 becomes current
+        int t = slot[1]; slot[1] = slot[2]; slot[2] = t;
+        enxt = ef1;
+      }
+    }
+    int t = slot[0]; slot[0] = slot[1]; slot[1] = t;
+    ecur = enxt;
+  }
+  if (last_row) {
+    const int x = L.Lx - 1;
+    T* cur = tmp + slot[0] * sz;
+    T* nxt = tmp + slot[1] * sz;
+    int e = ecur + step3<T>(L, C, nxt, cur, y, x, 0, ub<T>(L, C, y, x), db<T>(L, C, y + 1, x), false);
+    double v = (double)nxt[0];
+    if (threadIdx.x == 0) {
+      if (v == 0.0) {
+        C.meta->flags |= FLAG_ZERO;
+      } else if (!isfinite(v)) {
+        C.meta->flags |= FLAG_NONFINITE;
+      } else {
+        C.meta->logpsi = C.dw[L.dlamU + y] + log(fabs(v)) + e * 0.69314718055994530942;
+        C.meta->sign = v > 0 ? 1 : -1;
+      }
+    }
+  }
+}
+
+// R4[x] for x = Lx-1 .. 1 of <D_{y+2}|M_{y+1} M_y|U_{y-1}>.
+template <typename T>
+__global__ void __launch_bounds__(WG) k_row4_right(LatDev L, int y) {
+  Chain<T> C = chain_of<T>(L, blockIdx.x);
+  if (C.meta->flags) return;
+  const int sz = e4sz(L);
+  T* R = C.ws + L.oR4;
+  int* eR = C.iw + L.ieR4;
+  set_unit<T>(R + (int64_t)L.Lx * sz, sz);
+  if (threadIdx.x == 0) eR[L.Lx] = 0;
+  for (int x = L.Lx - 1; x >= 1; --x) {
+    int e = step4<T>(L, C, R + (int64_t)x * sz, R + (int64_t)(x + 1) * sz, y, x, 0, 0,
+                     ub<T>(L, C, y, x), db<T>(L, C, y + 2, x), true);
+    if (threadIdx.x == 0) eR[x] = eR[x + 1] + e;
+    __syncthreads();
+  }
+}
+
+// Vertical bonds between rows y and y+1, left to right.
+template <typename T>
+__global__ void __launch_bounds__(WG) k_vsweep(LatDev L, int y) {
+  Chain<T> C = chain_of<T>(L, blockIdx.x);
+  if (C.meta->flags) return;
+  const int sz = e4sz(L);
+  T* tmp = C.ws + L.oT4;
+  const T* R = C.ws + L.oR4;
+  const int* eR = C.iw + L.ieR4;
+  int slot[3] = {0, 1, 2};  // cur, nxt, f
+  set_unit<T>(tmp + slot[0] * sz, sz);
+  int ecur = 0;
+  for (int x = 0; x < L.Lx; ++x) {
+    const T* Ux = ub<T>(L, C, y, x);
+    const T* Dx = db<T>(L, C, y + 2, x);
+    T* cur = tmp + slot[0] * sz;
+    T* nxt = tmp + slot[1] * sz;
+    if (x == L.Lx - 1 && !(C.sp[y * L.Lx + x] != C.sp[(y + 1) * L.Lx + x])) break;
+    int enxt = ecur + step4<T>(L, C, nxt, cur, y, x, 0, 0, Ux, Dx, false);
+    const int k1 = y * L.Lx + x, k2 = (y + 1) * L.Lx + x;
+    if (C.sp[k1] != C.sp[k2]) {
+      T* f = tmp + slot[2] * sz;
+      int ef = ecur + step4<T>(L, C, f, cur, y, x, 1, 1, Ux, Dx, false);
+      double num = wg_dot<T>(f, R + (int64_t)(x + 1) * sz, sz);
+      double den = wg_dot<T>(nxt, R + (int64_t)(x + 1) * sz, sz);
+      int bond = y * (2 * L.Lx - 1) + (L.Lx - 1) + x;
+      bool acc = metropolis(L, C.meta, num, den, ef - enxt, bond);
+      if (threadIdx.x == 0) {
+        C.meta->proposed += 1;
+        if (acc) {
+          int8_t a = C.sp[k1];
+          C.sp[k1] = C.sp[k2];
+          C.sp[k2] = a;
+          C.meta->accepted += 1;
+        }
+      }
+      __syncthreads();
+      if (acc) {
+        int t = slot[1]; slot[1] = slot[2]; slot[2] = t;
+        enxt = ef;
+      }
+    }
+    int t = slot[0]; slot[0] = slot[1]; slot[1] = t;
+    ecur = enxt;
+  }
+}
+
+// Boundary compression (App. B) of row y into U_y (upper = 1) or D_y.
+//
+// The canonical SVD compression is computed through Gram matrices: the
+// left-to-right QR sweep of the reference definition only enters through the
+// Gram matrices G_j of the left blocks (R_j^T R_j = G_j), which a 4-line-type
+// column step carries exactly; the right-to-left SVD at site j is the
+// eigendecomposition of Y^T G_{j-1} Y with Y = (site j) x (right carry), whose
+// leading k_j eigenvectors are the kept right singular vectors.  The output
+// state is the same; the sign and gauge of every site may differ.
+template <typename T>
+__global__ void __launch_bounds__(WG) k_compress(LatDev L, int y, int upper) {
+  Chain<T> C = chain_of<T>(L, blockIdx.x);
+  if (C.meta->flags) return;
+  const int c = L.c, d = L.d, Lx = L.Lx;
+  const int ssz = c * d * c, gsz = c * d * d * c;
+  const int in_slot = upper ? y : y + 1;
+  const int out_slot = upper ? y + 1 : y;
+  auto A_in = [&](int x) -> const T* { return upper ? ub<T>(L, C, in_slot, x) : db<T>(L, C, in_slot, x); };
+  auto A_out = [&](int x) -> T* { return upper ? ub<T>(L, C, out_slot, x) : db<T>(L, C, out_slot, x); };
+  const int32_t* kout = upper ? (L.kU + (y + 1) * (Lx + 1)) : (L.kD + y * (Lx + 1));
+  const S3 sA = sb_std(c, d);
+  const S4 st = upper ? st_std(d) : st_swapud(st_std(d));
+  const S4 st2 = st_swapud(st);
+  T* G = C.ws + L.oG;
+  // Gram matrices of the left blocks: G[0] = G_{-1} (unit), G[j+1] = G_j.
+  set_unit<T>(G, gsz);
+  for (int j = 0; j < Lx - 1; ++j) {
+    const int k = y * Lx + j;
+    const T* t = tw<T>(L, k, C.sp[k]);
+    env4_step<T>(G + (int64_t)(j + 1) * gsz, G + (int64_t)j * gsz, A_in(j), sA, t, st, t, st2, A_in(j), sA,
+                 C.ws + L.oX0, C.ws + L.oX1, c, d);
+    wg_renorm<T>(G + (int64_t)(j + 1) * gsz, gsz);
+  }
+  T* Ta = C.ws + L.oTa;
+  T* Tb = C.ws + L.oTb;
+  T* Y = C.ws + L.oY;
+  T* W = C.ws + L.oW;
+  T* H = C.ws + L.oH;
+  T* V = C.ws + L.oV;
+  set_unit<T>(Ta, ssz);
+  int eT = 0;
+  const int dc = d * c;
+  const double tol = sizeof(T) == 8 ? 1e-14 : 2e-7;
+  for (int j = Lx - 1; j >= 1; --j) {
+    const int k = y * Lx + j;
+    const T* t = tw<T>(L, k, C.sp[k]);
+    compress_y<T>(Y, A_in(j), sA, t, st, Ta, C.ws + L.oX0, c, d);
+    // W = G_{j-1} Y  with G stored [a][l][l'][a'] and viewed as ((a,l), (a',l'))
+    wg_gemm<T>(W, rowmajor(dc), G + (int64_t)j * gsz, view(d, d * d * c, d * c, d, 1, c), Y, rowmajor(dc),
+               dc, dc, dc);
+    // H = Y^T W
+    wg_gemm<T>(H, rowmajor(dc), Y, colmajor(dc), W, rowmajor(dc), dc, dc, dc);
+    const int p = upper ? L.dims[4 * k + 3] : L.dims[4 * k + 1];
+    const int kr = kout[j + 1], kl = kout[j];
+    const int n = p * kr;
+    // compact n x n problem over the valid (dd, kk) pairs; W is free now
+    for (int i = threadIdx.x; i < n * n; i += WG) {
+      int a = i / n, b = i - a * n;
+      int pa = (a / kr) * c + a % kr, pb = (b / kr) * c + b % kr;
+      W[i] = H[pa * dc + pb];
+    }
+    __syncthreads();
+    jacobi_eig<T>(W, V, n, tol, sizeof(T) == 8 ? 40 : 30);
+    // keep the kl largest eigenvalues (ties by index)
+    T* out = A_out(j);
+    for (int i = threadIdx.x; i < ssz; i += WG) out[i] = T(0);
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += WG) {
+      T li = W[i * n + i];
+      int rank = 0;
+      for (int q = 0; q < n; ++q) {
+        T lq = W[q * n + q];
+        rank += (lq > li) || (lq == li && q < i);
+      }
+      if (rank < kl) {
+        for (int q = 0; q < n; ++q) out[rank * dc + (q / kr) * c + q % kr] = V[q * n + i];
+      }
+    }
+    __syncthreads();
+    // carry: Tb[(a,l)][k'] = sum_{(dd,kk)} Y[(a,l)][(dd,kk)] out[k'][(dd,kk)]
+    wg_gemm<T>(Tb, rowmajor(c), Y, rowmajor(dc), out, colmajor(dc), dc, c, dc);
+    eT += wg_renorm<T>(Tb, ssz);
+    T* tt = Ta; Ta = Tb; Tb = tt;
+  }
+  {
+    const int k = y * Lx;
+    const T* t = tw<T>(L, k, C.sp[k]);
+    compress_y<T>(Y, A_in(0), sA, t, st, Ta, C.ws + L.oX0, c, d);
+    double nrm2 = 0.0;
+    for (int i = threadIdx.x; i < dc; i += WG) nrm2 += (double)Y[i] * (double)Y[i];
+    nrm2 = wg_sum(nrm2);
+    double nu = sqrt(nrm2);
+    T* out = A_out(0);
+    T inv = nu > 0 ? (T)(1.0 / nu) : T(0);
+    for (int i = threadIdx.x; i < ssz; i += WG) out[i] = (i < dc) ? Y[i] * inv : T(0);
+    if (threadIdx.x == 0) {
+      if (!(nu > 0.0)) C.meta->flags |= FLAG_ZERO;
+      else if (!isfinite(nu)) C.meta->flags |= FLAG_NONFINITE;
+      double lognu = log(nu) + eT * 0.69314718055994530942;
+      if (upper) C.dw[L.dlamU + y + 1] = C.dw[L.dlamU + y] + lognu;
+      else C.dw[L.dlamD + y] = C.dw[L.dlamD + y + 1] + lognu;
+    }
+    __syncthreads();
+  }
+}
+
+// Measurement of row y (App. C): log-derivatives of its sites and its
+// horizontal pair ratios, all from the cached left/right auxiliary tensors.
+template <typename T>
+__global__ void __launch_bounds__(WG) k_measure3(LatDev L, int y, SampleOut o) {
+  Chain<T> C = chain_of<T>(L, blockIdx.x);
+  if (C.meta->flags) return;
+  const int sz = e3sz(L), Lx = L.Lx, d = L.d;
+  T* R = C.ws + L.oR3;
+  T* Le = C.ws + L.oL3;
+  T* tmp = C.ws + L.oT3;
+  int* eR = C.iw + L.ieR3;
+  int* eL = C.iw + L.ieL3;
+  set_unit<T>(R + (int64_t)Lx * sz, sz);
+  set_unit<T>(Le, sz);
+  if (threadIdx.x == 0) { eR[Lx] = 0; eL[0] = 0; }
+  __syncthreads();
+  for (int x = Lx - 1; x >= 1; --x) {
+    int e = step3<T>(L, C, R + (int64_t)x * sz, R + (int64_t)(x + 1) * sz, y, x, 0, ub<T>(L, C, y, x),
+                     db<T>(L, C, y + 1, x), true);
+    if (threadIdx.x == 0) eR[x] = eR[x + 1] + e;
+    __syncthreads();
+  }
+  for (int x = 0; x < Lx; ++x) {
+    int e = step3<T>(L, C, Le + (int64_t)(x + 1) * sz, Le + (int64_t)x * sz, y, x, 0, ub<T>(L, C, y, x),
+                     db<T>(L, C, y + 1, x), false);
+    if (threadIdx.x == 0) eL[x + 1] = eL[x] + e;
+    __syncthreads();
+  }
+  const double Nm = wg_dot<T>(Le + sz, R + sz, sz);
+  const int eN = eL[1] + eR[1];
+  if (Nm == 0.0) { raise_flag(C.meta, FLAG_ZERO); return; }
+  if (o.dlnpsi) {
+    T* Dl = C.ws + L.oDl;
+    for (int x = 0; x < Lx; ++x) {
+      const int k = y * Lx + x;
+      defect3<T>(Dl, Le + (int64_t)x * sz, ub<T>(L, C, y, x), sb_std(L.c, d), R + (int64_t)(x + 1) * sz,
+                 db<T>(L, C, y + 1, x), sb_std(L.c, d), C.ws + L.oX0, C.ws + L.oX1, L.c, d);
+      const double f = ldexp(1.0 / Nm, eL[x] + eR[x + 1] - eN);
+      const int dl = L.dims[4 * k], du = L.dims[4 * k + 1], dr = L.dims[4 * k + 2], dd = L.dims[4 * k + 3];
+      const int n = dl * du * dr * dd;
+      T* outp = (T*)o.dlnpsi + ((int64_t)blockIdx.x * o.n_meas + o.m) * o.np_half + L.coff[k];
+      for (int i = threadIdx.x; i < n; i += WG) {
+        int l = i / (du * dr * dd), u = (i / (dr * dd)) % du, r = (i / dd) % dr, q = i % dd;
+        outp[i] = (T)((double)Dl[((l * d + u) * d + r) * d + q] * f);
+      }
+      __syncthreads();
+    }
+  }
+  double eacc = 0.0;
+  for (int x = 0; x < Lx - 1; ++x) {
+    const int k = y * Lx + x;
+    const int pair = y * (Lx - 1) + x;
+    double rho = 0.0;
+    if (C.sp[k] == C.sp[k + 1]) {
+      eacc += 0.25 * L.J1;
+    } else {
+      int e1 = eL[x] + step3<T>(L, C, tmp, Le + (int64_t)x * sz, y, x, 1, ub<T>(L, C, y, x), db<T>(L, C, y + 1, x), false);
+      int e2 = e1 + step3<T>(L, C, tmp + sz, tmp, y, x + 1, 1, ub<T>(L, C, y, x + 1), db<T>(L, C, y + 1, x + 1), false);
+      double num = wg_dot<T>(tmp + sz, R + (int64_t)(x + 2) * sz, sz);
+      rho = ldexp(num / Nm, e2 + eR[x + 2] - eN);
+      eacc += -0.25 * L.J1 + 0.5 * L.J1 * rho;
+    }
+    if (o.ratios && threadIdx.x == 0) o.ratios[(int64_t)blockIdx.x * o.n_pairs + pair] = rho;
+  }
+  if (threadIdx.x == 0) {
+    if (!isfinite(eacc)) C.meta->flags |= FLAG_NONFINITE;
+    C.meta->e_acc += eacc;
+  }
+}
+
+// Vertical and diagonal pairs between rows y and y+1 (two-row network).
+template <typename T>
+__global__ void __launch_bounds__(WG) k_measure4(LatDev L, int y, SampleOut o) {
+  Chain<T> C = chain_of<T>(L, blockIdx.x);
+  if (C.meta->flags) return;
+  const int sz = e4sz(L), Lx = L.Lx;
+  T* R = C.ws + L.oR4;
+  T* Le = C.ws + L.oL4;
+  T* tmp = C.ws + L.oT4;
+  int* eR = C.iw + L.ieR4;
+  int* eL = C.iw + L.ieL4;
+  set_unit<T>(R + (int64_t)Lx * sz, sz);
+  set_unit<T>(Le, sz);
+  if (threadIdx.x == 0) { eR[Lx] = 0; eL[0] = 0; }
+  __syncthreads();
+  for (int x = Lx - 1; x >= 1; --x) {
+    int e = step4<T>(L, C, R + (int64_t)x * sz, R + (int64_t)(x + 1) * sz, y, x, 0, 0, ub<T>(L, C, y, x),
+                     db<T>(L, C, y + 2, x), true);
+    if (threadIdx.x == 0) eR[x] = eR[x + 1] + e;
+    __syncthreads();
+  }
+  for (int x = 0; x < Lx; ++x) {
+    int e = step4<T>(L, C, Le + (int64_t)(x + 1) * sz, Le + (int64_t)x * sz, y, x, 0, 0, ub<T>(L, C, y, x),
+                     db<T>(L, C, y + 2, x), false);
+    if (threadIdx.x == 0) eL[x + 1] = eL[x] + e;
+    __syncthreads();
+  }
+  const double Nm = wg_dot<T>(Le + sz, R + sz, sz);
+  const int eN = eL[1] + eR[1];
+  if (Nm == 0.0) { raise_flag(C.meta, FLAG_ZERO); return; }
+  double eacc = 0.0;
+  const int base_v = L.Ly * (Lx - 1);
+  for (int x = 0; x < Lx; ++x) {
+    const int k1 = y * Lx + x, k2 = (y + 1) * Lx + x;
+    double rho = 0.0;
+    if (C.sp[k1] == C.sp[k2]) {
+      eacc += 0.25 * L.J1;
+    } else {
+      int e1 = eL[x] + step4<T>(L, C, tmp, Le + (int64_t)x * sz, y, x, 1, 1, ub<T>(L, C, y, x), db<T>(L, C, y + 2, x), false);
+      double num = wg_dot<T>(tmp, R + (int64_t)(x + 1) * sz, sz);
+      rho = ldexp(num / Nm, e1 + eR[x + 1] - eN);
+      eacc += -0.25 * L.J1 + 0.5 * L.J1 * rho;
+    }
+    if (o.ratios && threadIdx.x == 0) o.ratios[(int64_t)blockIdx.x * o.n_pairs + base_v + y * Lx + x] = rho;
+  }
+  if (L.J2 != 0.0) {
+    const int base_d = base_v + (L.Ly - 1) * Lx;
+    for (int x = 0; x < Lx - 1; ++x) {
+      for (int which = 0; which < 2; ++which) {
+        // which 0: (y,x)-(y+1,x+1); which 1: (y,x+1)-(y+1,x)
+        const int kp = which == 0 ? y * Lx + x : y * Lx + x + 1;
+        const int kq = which == 0 ? (y + 1) * Lx + x + 1 : (y + 1) * Lx + x;
+        double rho = 0.0;
+        if (C.sp[kp] == C.sp[kq]) {
+          eacc += 0.25 * L.J2;
+        } else {
+          // column x: flips (y,x) for which 0 and (y+1,x) for which 1; column x+1 the other site
+          int f1a = which == 0 ? 1 : 0, f1b = which == 0 ? 0 : 1;
+          int e1 = eL[x] + step4<T>(L, C, tmp, Le + (int64_t)x * sz, y, x, f1a, f1b, ub<T>(L, C, y, x),
+                                    db<T>(L, C, y + 2, x), false);
+          int e2 = e1 + step4<T>(L, C, tmp + sz, tmp, y, x + 1, 1 - f1a, 1 - f1b, ub<T>(L, C, y, x + 1),
+                                 db<T>(L, C, y + 2, x + 1), false);
+          double num = wg_dot<T>(tmp + sz, R + (int64_t)(x + 2) * sz, sz);
+          rho = ldexp(num / Nm, e2 + eR[x + 2] - eN);
+          eacc += -0.25 * L.J2 + 0.5 * L.J2 * rho;
+        }
+        if (o.ratios && threadIdx.x == 0)
+          o.ratios[(int64_t)blockIdx.x * o.n_pairs + base_d + 2 * (y * (Lx - 1) + x) + which] = rho;
+      }
+    }
+  }
+  if (threadIdx.x == 0) {
+    if (!isfinite(eacc)) C.meta->flags |= FLAG_NONFINITE;
+    C.meta->e_acc += eacc;
+  }
+}
+
+__global__ void k_begin_sample(LatDev L) {
+  int ch = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ch < L.n_chains) L.meta[ch].e_acc = 0.0;
+}
+
+__global__ void k_finish_sample(LatDev L, SampleOut o, int n_active) {
+  int ch = blockIdx.x;
+  if (ch >= n_active) return;
+  const ChainMeta* m = L.meta + ch;
+  int64_t idx = (int64_t)ch * o.n_meas + o.m;
+  if (threadIdx.x == 0) {
+    if (o.log_abs_psi) o.log_abs_psi[idx] = m->logpsi;
+    if (o.sign) o.sign[idx] = (int8_t)m->sign;
+    if (o.e_loc) o.e_loc[idx] = m->e_acc;
+  }
+  if (o.spins)
+    for (int i = threadIdx.x; i < L.N; i += blockDim.x) o.spins[idx * L.N + i] = L.spins[(int64_t)ch * L.N + i];
+}
+
+__global__ void k_next_sweep(LatDev L) {
+  int ch = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ch < L.n_chains) L.meta[ch].sweep += 1;
+}
+
+__global__ void k_init_tensors(double* T, int64_t Np, uint64_t seed, int lat_id, double scale, double perturb) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < Np; p += (int64_t)gridDim.x * blockDim.x) {
+    const double two_pi = 6.283185307179586476925286766559;
+    U64x4 w = philox4x64_10((uint64_t)p, 0, 0, TAG_INIT, seed, (uint64_t)lat_id);
+    double z = sqrt(-2.0 * log(1.0 - uniform53(w.v[0]))) * cos(two_pi * uniform53(w.v[1]));
+    double v = scale * z;
+    if (perturb != 0.0) {
+      U64x4 q = philox4x64_10((uint64_t)p, 0, 0, TAG_PERTURB, seed, (uint64_t)lat_id);
+      v += perturb * sqrt(-2.0 * log(1.0 - uniform53(q.v[0]))) * cos(two_pi * uniform53(q.v[1]));
+    }
+    T[p] = v;
+  }
+}
+
+// Neel list shuffled by Fisher-Yates (Durstenfeld) with Philox indices.
+__global__ void k_init_chains(LatDev L) {
+  int ch = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ch >= L.n_chains) return;
+  int8_t* s = L.spins + (int64_t)ch * L.N;
+  for (int i = 0; i < L.N; ++i) s[i] = (int8_t)(((i / L.Lx) + (i % L.Lx)) & 1);
+  for (int i = L.N - 1; i >= 1; --i) {
+    U64x4 w = philox4x64_10((uint64_t)ch, 0, (uint64_t)i, TAG_SHUFFLE, L.seed, (uint64_t)L.lat_id);
+    uint64_t j = ((w.v[0] >> 11) * (uint64_t)(i + 1)) >> 53;
+    int8_t a = s[i]; s[i] = s[j]; s[j] = a;
+  }
+  ChainMeta* m = L.meta + ch;
+  m->sweep = 0; m->accepted = 0; m->proposed = 0; m->flags = 0; m->e_acc = 0.0;
+}
+
+__global__ void k_copy_spins(LatDev L, const int8_t* src, int n_cfg) {
+  int ch = blockIdx.x;
+  if (ch >= n_cfg) return;
+  for (int i = threadIdx.x; i < L.N; i += blockDim.x) L.spins[(int64_t)ch * L.N + i] = src[(int64_t)ch * L.N + i];
+  if (threadIdx.x == 0) {
+    ChainMeta* m = L.meta + ch;
+    m->flags = 0; m->e_acc = 0.0;
+  }
+}
+
+__global__ void k_mean(const double* e, int64_t ns, double* out) {
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < ns; i += WG) s += e[i];
+  s = wg_sum(s);
+  if (threadIdx.x == 0) *out = s / (double)ns;
+}
+
+// Eq. (5) in the full parameter layout; thread q owns compact entry q of every sample.
+template <typename T>
+__global__ void k_gradient(const int64_t* offs, const int64_t* coff, const int32_t* sz, int N, const double* e,
+                           const T* dl, const int8_t* spins, int64_t ns, int64_t nh, const double* emean,
+                           double* grad) {
+  int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= nh) return;
+  int lo = 0, hi = N - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (coff[mid] <= q) lo = mid; else hi = mid - 1;
+  }
+  const int k = lo;
+  const int64_t local = q - coff[k];
+  double a0 = 0, a1 = 0, b0 = 0, b1 = 0;
+  for (int64_t i = 0; i < ns; ++i) {
+    double g = (double)dl[i * nh + q];
+    double ei = e[i];
+    if (spins[i * N + k]) { a1 += g * ei; b1 += g; } else { a0 += g * ei; b0 += g; }
+  }
+  const double E = *emean, inv = 1.0 / (double)ns;
+  grad[offs[k] + local] = a0 * inv - b0 * inv * E;
+  grad[offs[k] + sz[k] + local] = a1 * inv - b1 * inv * E;
+}
+
+__global__ void k_sign_sgd(double* T, const double* g, int64_t Np, double step_len, uint64_t seed, int lat_id,
+                           uint64_t step) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < Np; p += (int64_t)gridDim.x * blockDim.x) {
+    double gv = g[p];
+    if (gv == 0.0) continue;
+    U64x4 w = philox4x64_10((uint64_t)p, step, 0, TAG_SGD, seed, (uint64_t)lat_id);
+    T[p] -= uniform53(w.v[0]) * step_len * (gv > 0 ? 1.0 : -1.0);
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+template <typename T>
+void launch_prepare_tensors(const LatDev& L, const double* Tflat, T* Tw, const int64_t* offs, hipStream_t s) {
+  int64_t total = (int64_t)L.N * 2 * L.d * L.d * L.d * L.d;
+  int blocks = (int)std::min<int64_t>((total + WG - 1) / WG, 65536);
+  hipLaunchKernelGGL(k_prepare_tensors<T>, dim3(blocks), dim3(WG), 0, s, L, Tflat, Tw, offs);
+}
+template <typename T>
+void launch_init_trivial(const LatDev& L, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_trivial<T>, dim3(L.n_chains), dim3(WG), 0, s, L);
+}
+template <typename T>
+void launch_row3_right(const LatDev& L, int y, int ub_slot, int db_slot, hipStream_t s) {
+  hipLaunchKernelGGL(k_row3_right<T>, dim3(L.n_chains), dim3(WG), 0, s, L, y, ub_slot, db_slot);
+}
+template <typename T>
+void launch_hsweep(const LatDev& L, int y, int last_row, hipStream_t s) {
+  hipLaunchKernelGGL(k_hsweep<T>, dim3(L.n_chains), dim3(WG), 0, s, L, y, last_row, 1);
+}
+template <typename T>
+void launch_psi_fixed(const LatDev& L, hipStream_t s) {
+  hipLaunchKernelGGL(k_hsweep<T>, dim3(L.n_chains), dim3(WG), 0, s, L, L.Ly - 1, 1, 0);
+}
+template <typename T>
+void launch_row4_right(const LatDev& L, int y, hipStream_t s) {
+  hipLaunchKernelGGL(k_row4_right<T>, dim3(L.n_chains), dim3(WG), 0, s, L, y);
+}
+template <typename T>
+void launch_vsweep(const LatDev& L, int y, hipStream_t s) {
+  hipLaunchKernelGGL(k_vsweep<T>, dim3(L.n_chains), dim3(WG), 0, s, L, y);
+}
+template <typename T>
+void launch_compress(const LatDev& L, int y, int upper, hipStream_t s) {
+  hipLaunchKernelGGL(k_compress<T>, dim3(L.n_chains), dim3(WG), 0, s, L, y, upper);
+}
+template <typename T>
+void launch_measure3(const LatDev& L, int y, const SampleOut& o, hipStream_t s) {
+  hipLaunchKernelGGL(k_measure3<T>, dim3(L.n_chains), dim3(WG), 0, s, L, y, o);
+}
+template <typename T>
+void launch_measure4(const LatDev& L, int y, const SampleOut& o, hipStream_t s) {
+  hipLaunchKernelGGL(k_measure4<T>, dim3(L.n_chains), dim3(WG), 0, s, L, y, o);
+}
+void launch_begin_sample(const LatDev& L, hipStream_t s) {
+  hipLaunchKernelGGL(k_begin_sample, dim3((L.n_chains + WG - 1) / WG), dim3(WG), 0, s, L);
+}
+void launch_finish_sample(const LatDev& L, const SampleOut& o, int n_active, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish_sample, dim3(n_active), dim3(64), 0, s, L, o, n_active);
+}
+void launch_next_sweep(const LatDev& L, hipStream_t s) {
+  hipLaunchKernelGGL(k_next_sweep, dim3((L.n_chains + WG - 1) / WG), dim3(WG), 0, s, L);
+}
+void launch_init_tensors(double* T, int64_t Np, uint64_t seed, int lat_id, double scale, double perturb,
+                         hipStream_t s) {
+  int blocks = (int)std::min<int64_t>((Np + WG - 1) / WG, 65536);
+  hipLaunchKernelGGL(k_init_tensors, dim3(blocks), dim3(WG), 0, s, T, Np, seed, lat_id, scale, perturb);
+}
+void launch_init_chains(const LatDev& L, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_chains, dim3((L.n_chains + 63) / 64), dim3(64), 0, s, L);
+}
+void launch_copy_spins(const LatDev& L, const int8_t* src, int n_cfg, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_spins, dim3(n_cfg), dim3(64), 0, s, L, src, n_cfg);
+}
+template <typename T>
+void launch_gradient(const int64_t* offs, const int64_t* coff, const int32_t* sz, int N, int64_t Np,
+                     const double* e, const T* dl, const int8_t* spins, int64_t ns, double* grad, double* emean,
+                     double* work, hipStream_t s) {
+  (void)work;
+  hipLaunchKernelGGL(k_mean, dim3(1), dim3(WG), 0, s, e, ns, emean);
+  int64_t nh = Np / 2;
+  hipLaunchKernelGGL(k_gradient<T>, dim3((unsigned)((nh + WG - 1) / WG)), dim3(WG), 0, s, offs, coff, sz, N, e, dl,
+                     spins, ns, nh, (const double*)emean, grad);
+}
+void launch_sign_sgd(double* T, const double* g, int64_t Np, double step_len, uint64_t seed, int lat_id,
+                     uint64_t step, hipStream_t s) {
+  int blocks = (int)std::min<int64_t>((Np + WG - 1) / WG, 65536);
+  hipLaunchKernelGGL(k_sign_sgd, dim3(blocks), dim3(WG), 0, s, T, g, Np, step_len, seed, lat_id, step);
+}
+
+#define VP_INSTANTIATE(T)                                                                            \
+  template void launch_prepare_tensors<T>(const LatDev&, const double*, T*, const int64_t*, hipStream_t); \
+  template void launch_init_trivial<T>(const LatDev&, hipStream_t);                                  \
+  template void launch_row3_right<T>(const LatDev&, int, int, int, hipStream_t);                    \
+  template void launch_hsweep<T>(const LatDev&, int, int, hipStream_t);                             \
+  template void launch_psi_fixed<T>(const LatDev&, hipStream_t);                                    \
+  template void launch_row4_right<T>(const LatDev&, int, hipStream_t);                              \
+  template void launch_vsweep<T>(const LatDev&, int, hipStream_t);                                  \
+  template void launch_compress<T>(const LatDev&, int, int, hipStream_t);                           \
+  template void launch_measure3<T>(const LatDev&, int, const SampleOut&, hipStream_t);              \
+  template void launch_measure4<T>(const LatDev&, int, const SampleOut&, hipStream_t);              \
+  template void launch_gradient<T>(const int64_t*, const int64_t*, const int32_t*, int, int64_t,    \
+                                   const double*, const T*, const int8_t*, int64_t, double*, double*, \
+                                   double*, hipStream_t);
+
+VP_INSTANTIATE(double)
+VP_INSTANTIATE(float)
+
+}  // namespace vp

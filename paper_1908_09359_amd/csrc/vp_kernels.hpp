@@ -1,0 +1,100 @@
+// Host-visible description of one lattice's device state and the phase-kernel
+// launchers (implemented in vp_kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vp {
+
+// Per-chain scalar state kept on the device.
+struct ChainMeta {
+  int64_t sweep;        // Philox counter word 1 of the next sweep
+  int64_t accepted;
+  int64_t proposed;
+  double e_acc;         // E_loc accumulator of the current measurement
+  double logpsi;        // log|Psi| of the last top-down pass
+  int32_t sign;         // sign of Psi
+  int32_t flags;        // bit 0: zero amplitude, bit 1: non-finite value
+};
+
+enum : int32_t { FLAG_ZERO = 1, FLAG_NONFINITE = 2 };
+
+// Everything a kernel needs to locate one chain's data.  Sizes are padded:
+// every virtual leg has dimension d = D and every boundary bond c = Dc; true
+// (smaller) dimensions are realised by zero entries.
+struct LatDev {
+  int Ly, Lx, d, c, N;
+  double J1, J2;
+  int n_chains;
+  uint64_t seed;
+  int lat_id;
+  // padded working tensors [N][2][d^4] (float or double), element type by kernel
+  const void* Tw;
+  // per-chain workspace (element type T), ints, doubles
+  void* ws;
+  int64_t ws_stride;
+  int32_t* iws;
+  int64_t iws_stride;
+  double* dws;
+  int64_t dws_stride;
+  ChainMeta* meta;
+  int8_t* spins;            // [n_chains][N]
+  const int32_t* kU;        // bond dims of U_y: kU[(y+1)*(Lx+1) + j], y = -1..Ly-1
+  const int32_t* kD;        // bond dims of D_y: kD[y*(Lx+1) + j], y = 0..Ly
+  const int32_t* dims;      // true leg dims per site [N][4] (l,u,r,d)
+  const int64_t* coff;      // compact log-derivative offset per site [N+1]
+  // workspace offsets (elements of T)
+  int64_t oUb, oDb;         // boundaries: [(Ly+1)][Lx][c*d*c]
+  int64_t oL3, oR3, oT3;    // 3-line envs: [(Lx+1)] slots each, 4 temps
+  int64_t oL4, oR4, oT4;    // 4-line envs: [(Lx+1)] slots each, 4 temps
+  int64_t oG;               // Gram matrices [Lx][c*d*d*c]
+  int64_t oX0, oX1;         // GEMM intermediates [c*c*d*d*d]
+  int64_t oY, oW, oH, oV;   // compression scratch [c*c*d*d]
+  int64_t oTa, oTb;         // compression carry [c*d*c]
+  int64_t oDl;              // defect tensor scratch [d^4]
+  // int offsets: exponents of env slots
+  int64_t ieL3, ieR3, ieT3, ieL4, ieR4, ieT4;
+  // double offsets
+  int64_t dlamU, dlamD;     // [(Ly+1)] cumulative log-scales
+};
+
+// Outputs of one measured sweep (all may be null except where stated).
+struct SampleOut {
+  double* log_abs_psi;  // [chain][n_meas]
+  int8_t* sign;
+  double* e_loc;
+  void* dlnpsi;         // [chain][n_meas][Np/2]
+  int8_t* spins;        // [chain][n_meas][N]
+  double* ratios;       // [chain][n_pairs] (vp_eval only)
+  int n_meas;
+  int m;                // index of this measurement
+  int64_t np_half;
+  int n_pairs;
+};
+
+template <typename T> void launch_prepare_tensors(const LatDev& L, const double* Tflat, T* Tw,
+                                                  const int64_t* offs, hipStream_t s);
+template <typename T> void launch_init_trivial(const LatDev& L, hipStream_t s);
+template <typename T> void launch_row3_right(const LatDev& L, int y, int ub_slot, int db_slot, hipStream_t s);
+template <typename T> void launch_hsweep(const LatDev& L, int y, int last_row, hipStream_t s);
+template <typename T> void launch_row4_right(const LatDev& L, int y, hipStream_t s);
+template <typename T> void launch_vsweep(const LatDev& L, int y, hipStream_t s);
+template <typename T> void launch_compress(const LatDev& L, int y, int upper, hipStream_t s);
+template <typename T> void launch_measure3(const LatDev& L, int y, const SampleOut& o, hipStream_t s);
+template <typename T> void launch_measure4(const LatDev& L, int y, const SampleOut& o, hipStream_t s);
+template <typename T> void launch_psi_fixed(const LatDev& L, hipStream_t s);
+void launch_begin_sample(const LatDev& L, hipStream_t s);
+void launch_finish_sample(const LatDev& L, const SampleOut& o, int n_active, hipStream_t s);
+void launch_next_sweep(const LatDev& L, hipStream_t s);
+void launch_init_tensors(double* T, int64_t Np, uint64_t seed, int lat_id, double scale, double perturb,
+                         hipStream_t s);
+void launch_init_chains(const LatDev& L, hipStream_t s);
+void launch_copy_spins(const LatDev& L, const int8_t* src, int n_cfg, hipStream_t s);
+template <typename T> void launch_gradient(const int64_t* offs, const int64_t* coff, const int32_t* sz,
+                                           int N, int64_t Np, const double* e, const T* dl,
+                                           const int8_t* spins, int64_t ns, double* grad, double* emean,
+                                           double* work, hipStream_t s);
+void launch_sign_sgd(double* T, const double* g, int64_t Np, double step_len, uint64_t seed, int lat_id,
+                     uint64_t step, hipStream_t s);
+
+}  // namespace vp

@@ -1,0 +1,44 @@
+"""Seeded synthetic inputs shared by tests, the benchmark and the smoke check.
+
+Nothing here computes any part of the method: only random tensors of the
+PEPS's shape and random spin configurations in the S^z_tot = 0 sector.
+
+Stand-in for the paper's workloads (its optimised PEPS tensors are not
+available): i.i.d. real Gaussian site tensors of standard deviation 1/D^2 on
+an open-boundary square lattice, with boundary legs of dimension 1, and
+configurations drawn uniformly from the S^z_tot = 0 sector.
+"""
+import numpy as np
+
+# Named workloads: (Ly, Lx, D, Dc, J2, precision, chains)
+WORKLOADS = {
+    "4x4_D2_Dc4_fp64": dict(Ly=4, Lx=4, D=2, Dc=4, J2=0.0, prec="fp64", chains=1),
+    "8x8_D4_Dc8_fp32": dict(Ly=8, Lx=8, D=4, Dc=8, J2=0.0, prec="fp32", chains=1024),
+    "16x16_D6_Dc12": dict(Ly=16, Lx=16, D=6, Dc=12, J2=0.0, prec="fp32", chains=4096),
+    "16x16_D8_Dc16": dict(Ly=16, Lx=16, D=8, Dc=16, J2=0.0, prec="fp32", chains=4096),
+}
+
+
+def num_params(Ly, Lx, D):
+    n = 0
+    for y in range(Ly):
+        for x in range(Lx):
+            n += 2 * (D if x > 0 else 1) * (D if y > 0 else 1) * (D if x < Lx - 1 else 1) * (D if y < Ly - 1 else 1)
+    return n
+
+
+def random_tensors(Ly, Lx, D, seed, scale=None):
+    """Flat float64 parameter vector, i.i.d. N(0, scale^2), scale = 1/D^2 by default."""
+    rng = np.random.default_rng(seed)
+    if scale is None:
+        scale = 1.0 / D ** 2
+    return rng.standard_normal(num_params(Ly, Lx, D)) * scale
+
+
+def random_configs(Ly, Lx, n, seed):
+    """n spin configurations (int8 0/1) with exactly half the spins 1."""
+    N = Ly * Lx
+    rng = np.random.default_rng(seed)
+    base = np.zeros(N, dtype=np.int8)
+    base[: N // 2] = 1
+    return np.stack([rng.permutation(base) for _ in range(n)]) if n else np.zeros((0, N), np.int8)

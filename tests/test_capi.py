@@ -1,0 +1,65 @@
+"""CPU-side checks of the C ABI: the library loads, exports every declared symbol,
+and its host-only functions agree with the parameter layout.  No compute call
+is made (no GPU here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vmcpeps.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(vp_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_header_declarations_listed_in_binding():
+    from paper_1908_09359_amd import binding
+    assert sorted(binding.EXPORTED) == _declared()
+
+
+def test_library_exports_every_symbol():
+    from paper_1908_09359_amd import binding
+    lib = ctypes.CDLL(binding.LIB_PATH)
+    for name in _declared():
+        assert hasattr(lib, name), name
+
+
+@pytest.mark.parametrize("shape", [(4, 4, 2), (8, 8, 4), (16, 16, 8), (32, 32, 8), (3, 5, 3), (1, 2, 2)])
+def test_num_params_matches_layout(shape):
+    from paper_1908_09359_amd import binding
+    from oracle.lattice import Lattice
+    Ly, Lx, D = shape
+    lat = binding.lattice(Ly, Lx, D, 4)
+    assert binding.vp_num_params(lat) == Lattice(Ly, Lx, D, 4).Np
+
+
+def test_workspace_bytes_positive_and_scales_with_chains():
+    from paper_1908_09359_amd import binding
+    a = binding.vp_workspace_bytes(binding.lattice(16, 16, 8, 16, prec=binding.VP_FP32, n_chains=1))
+    b = binding.vp_workspace_bytes(binding.lattice(16, 16, 8, 16, prec=binding.VP_FP32, n_chains=4096))
+    assert a > 0 and b == 4096 * a
+
+
+@pytest.mark.parametrize("bad", [dict(Ly=3, Lx=3), dict(D=0), dict(Dc=0), dict(n_chains=0), dict(prec=9)])
+def test_create_rejects_bad_shapes_before_touching_the_device(bad):
+    from paper_1908_09359_amd import binding
+    kw = dict(Ly=4, Lx=4, D=2, Dc=4, J1=1.0, J2=0.0, prec=binding.VP_FP64, n_chains=1)
+    kw.update(bad)
+    with pytest.raises(binding.VPError) as ei:
+        binding.Context(binding.vp_lattice(kw["Ly"], kw["Lx"], kw["D"], kw["Dc"], kw["J1"], kw["J2"],
+                                           kw["prec"], kw["n_chains"]))
+    assert ei.value.status in (binding.VP_ERR_SHAPE, binding.VP_ERR_UNSUPPORTED)
+
+
+def test_workload_inputs_are_seeded():
+    import numpy as np
+    from paper_1908_09359_amd import workloads
+    a = workloads.random_tensors(4, 4, 2, 1)
+    assert np.array_equal(a, workloads.random_tensors(4, 4, 2, 1))
+    c = workloads.random_configs(4, 4, 10, 3)
+    assert c.shape == (10, 16) and np.all(c.sum(1) == 8)
