@@ -36,6 +36,9 @@ class VPError(RuntimeError):
 
 
 def _load():
+    # torch's HIP runtime must be the one in the process: the library then
+    # binds to it by soname instead of loading a second copy.
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1908_09359_amd.build`")
     lib = ctypes.CDLL(LIB_PATH)

@@ -31,6 +31,7 @@ struct Lattice {
   double* T = nullptr;          // canonical float64 tensors
   void* Tw = nullptr;           // padded working tensors
   void* ws = nullptr;
+  double* cws = nullptr;
   int32_t* iws = nullptr;
   double* dws = nullptr;
   ChainMeta* meta = nullptr;
@@ -111,7 +112,7 @@ void plan_bonds(Lattice& L) {
 }
 
 struct Plan {
-  int64_t ws = 0, iws = 0, dws = 0;
+  int64_t ws = 0, iws = 0, dws = 0, cws = 0;
 };
 
 Plan plan_workspace(const vp_lattice& p, LatDev* dev) {
@@ -132,18 +133,26 @@ Plan plan_workspace(const vp_lattice& p, LatDev* dev) {
   L.oL4 = take((Lx + 1) * s4);
   L.oR4 = take((Lx + 1) * s4);
   L.oT4 = take(4 * s4);
-  L.oG = take(Lx * s4);
   L.oX0 = take(sx);
   L.oX1 = take(sx);
-  L.oY = take(s4);
-  L.oW = take(s4);
-  L.oH = take(s4);
-  L.oV = take(s4);
-  L.oTa = take(s3);
-  L.oTb = take(s3);
   L.oDl = take(d * d * d * d);
   Plan P;
   P.ws = o;
+  o = 0;
+  L.cG = take(Lx * s4);
+  L.cX0 = take(sx);
+  L.cX1 = take(sx);
+  L.cY = take(s4);
+  L.cW = take(s4);
+  L.cH = take(s4);
+  L.cHc = take(s4);
+  L.cVk = take(s4);
+  L.cVp = take(s3);
+  L.cTa = take(s3);
+  L.cTb = take(s3);
+  L.cRefl = take(128 * 129 / 2);
+  L.cLam = take(64);
+  P.cws = o;
   int64_t io = 0;
   L.ieL3 = io; io += Lx + 2;
   L.ieR3 = io; io += Lx + 2;
@@ -167,8 +176,8 @@ vp_status check_lattice(vp_ctx* ctx, const vp_lattice& p) {
   if ((p.Ly * p.Lx) % 2)
     return fail(ctx, VP_ERR_SHAPE, "the S^z_tot = 0 sector needs an even number of sites");
   if (p.Ly * p.Lx > 4096) return fail(ctx, VP_ERR_SHAPE, "at most 4096 sites");
-  if (p.D > 16 || p.Dc > 64 || p.D * p.Dc > 256)
-    return fail(ctx, VP_ERR_SHAPE, "sizes beyond the built kernels (D <= 16, Dc <= 64, D*Dc <= 256)");
+  if (p.D > 16 || p.Dc > 64 || p.D * p.Dc > 128)
+    return fail(ctx, VP_ERR_SHAPE, "sizes beyond the built kernels (D <= 16, Dc <= 64, D*Dc <= 128)");
   if (p.prec != VP_FP64 && p.prec != VP_FP32)
     return fail(ctx, VP_ERR_UNSUPPORTED, "precision %d is not built", p.prec);
   return VP_OK;
@@ -257,8 +266,8 @@ int64_t vp_num_params(const vp_lattice* p) {
 int64_t vp_workspace_bytes(const vp_lattice* p) {
   if (!p) return -1;
   Plan P = plan_workspace(*p, nullptr);
-  return (int64_t)p->n_chains * (P.ws * (int64_t)type_size(p->prec) + P.iws * 4 + P.dws * 8 + p->Ly * p->Lx +
-                                 (int64_t)sizeof(ChainMeta));
+  return (int64_t)p->n_chains * (P.ws * (int64_t)type_size(p->prec) + P.cws * 8 + P.iws * 4 + P.dws * 8 +
+                                 p->Ly * p->Lx + (int64_t)sizeof(ChainMeta));
 }
 
 const char* vp_last_error(const vp_ctx* ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
@@ -299,7 +308,8 @@ vp_status vp_create(const vp_lattice* lats, int32_t n_lats, uint64_t seed, void*
     const int64_t d4 = (int64_t)p.D * p.D * p.D * p.D;
     auto alloc = [&](void** ptr, size_t bytes) -> bool { return hipMalloc(ptr, std::max<size_t>(bytes, 64)) == hipSuccess; };
     bool ok = alloc((void**)&L.T, sizeof(double) * L.Np) && alloc(&L.Tw, L.tsize * L.N * 2 * d4) &&
-              alloc(&L.ws, L.tsize * P.ws * p.n_chains) && alloc((void**)&L.iws, 4 * P.iws * p.n_chains) &&
+              alloc(&L.ws, L.tsize * P.ws * p.n_chains) && alloc((void**)&L.cws, 8 * P.cws * p.n_chains) &&
+              alloc((void**)&L.iws, 4 * P.iws * p.n_chains) &&
               alloc((void**)&L.dws, 8 * P.dws * p.n_chains) &&
               alloc((void**)&L.meta, sizeof(ChainMeta) * p.n_chains) &&
               alloc((void**)&L.spins, (size_t)p.n_chains * L.N) &&
@@ -318,6 +328,7 @@ vp_status vp_create(const vp_lattice* lats, int32_t n_lats, uint64_t seed, void*
     hipMemcpy(L.d_offs, L.offs.data(), 8 * L.offs.size(), hipMemcpyHostToDevice);
     hipMemcpy(L.d_coff, L.coff.data(), 8 * L.coff.size(), hipMemcpyHostToDevice);
     hipMemset(L.ws, 0, L.tsize * P.ws * p.n_chains);
+    hipMemset(L.cws, 0, 8 * P.cws * p.n_chains);
     hipMemset(L.iws, 0, 4 * P.iws * p.n_chains);
     hipMemset(L.dws, 0, 8 * P.dws * p.n_chains);
     hipMemset(L.meta, 0, sizeof(ChainMeta) * p.n_chains);
@@ -327,6 +338,7 @@ vp_status vp_create(const vp_lattice* lats, int32_t n_lats, uint64_t seed, void*
     D.J1 = p.J1; D.J2 = p.J2; D.n_chains = p.n_chains;
     D.seed = seed; D.lat_id = i;
     D.Tw = L.Tw; D.ws = L.ws; D.ws_stride = P.ws;
+    D.cws = L.cws; D.cws_stride = P.cws;
     D.iws = L.iws; D.iws_stride = P.iws; D.dws = L.dws; D.dws_stride = P.dws;
     D.meta = L.meta; D.spins = L.spins;
     D.kU = L.d_kU; D.kD = L.d_kD; D.dims = L.d_dims; D.coff = L.d_coff;
@@ -344,7 +356,7 @@ vp_status vp_create(const vp_lattice* lats, int32_t n_lats, uint64_t seed, void*
 vp_status vp_destroy(vp_ctx* ctx) {
   if (!ctx) return VP_OK;
   for (auto& L : ctx->lats) {
-    void* ptrs[] = {L.T, L.Tw, L.ws, L.iws, L.dws, L.meta, L.spins, L.d_kU, L.d_kD,
+    void* ptrs[] = {L.T, L.Tw, L.ws, L.cws, L.iws, L.dws, L.meta, L.spins, L.d_kU, L.d_kD,
                     L.d_dims, L.d_sizes, L.d_offs, L.d_coff, L.d_scratch};
     for (void* q : ptrs)
       if (q) hipFree(q);

@@ -66,42 +66,49 @@ __device__ inline int vaddr(const View& v, int i, int j) {
   return i1 * v.si1 + i2 * v.si2 + j1 * v.sj1 + j2 * v.sj2;
 }
 
-// C(i,j) = sum_k A(i,k) B(k,j) for i < M, j < N.  All threads of the
-// work-group must call it; C is complete after the trailing barrier.
-template <typename T>
-__device__ void wg_gemm(T* __restrict__ C, View vc, const T* __restrict__ A, View va,
-                        const T* __restrict__ B, View vb, int M, int N, int K) {
+// One LDS tile buffer shared by every GEMM instantiation of a kernel.
+__device__ inline char* gemm_tiles() {
+  __shared__ __attribute__((aligned(16))) char buf[2 * 16 * 65 * sizeof(double)];
+  return buf;
+}
+
+// C(i,j) = sum_k A(i,k) B(k,j) for i < M, j < N, accumulated in TC.  All
+// threads of the work-group must call it; C is complete after the trailing
+// barrier.
+template <typename TC, typename TA, typename TB>
+__device__ void wg_gemm(TC* __restrict__ C, View vc, const TA* __restrict__ A, View va,
+                        const TB* __restrict__ B, View vb, int M, int N, int K) {
   constexpr int BM = 64, BN = 64, BK = 16;
-  __shared__ T As[BK][BM + 1];
-  __shared__ T Bs[BK][BN + 1];
+  TC (*As)[BM + 1] = reinterpret_cast<TC (*)[BM + 1]>(gemm_tiles());
+  TC (*Bs)[BN + 1] = reinterpret_cast<TC (*)[BN + 1]>(gemm_tiles() + BK * (BM + 1) * sizeof(TC));
   const int tid = threadIdx.x;
   const int tr = tid >> 4, tc = tid & 15;
   for (int m0 = 0; m0 < M; m0 += BM) {
     for (int n0 = 0; n0 < N; n0 += BN) {
-      T acc[4][4];
+      TC acc[4][4];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = T(0);
+        for (int j = 0; j < 4; ++j) acc[i][j] = TC(0);
       for (int k0 = 0; k0 < K; k0 += BK) {
 #pragma unroll
         for (int e = 0; e < (BM * BK) / WG; ++e) {
           int idx = tid + e * WG;
           int mi = idx % BM, ki = idx / BM;
           int m = m0 + mi, k = k0 + ki;
-          As[ki][mi] = (m < M && k < K) ? A[vaddr(va, m, k)] : T(0);
+          As[ki][mi] = (m < M && k < K) ? (TC)A[vaddr(va, m, k)] : TC(0);
         }
 #pragma unroll
         for (int e = 0; e < (BN * BK) / WG; ++e) {
           int idx = tid + e * WG;
           int ni = idx % BN, ki = idx / BN;
           int n = n0 + ni, k = k0 + ki;
-          Bs[ki][ni] = (n < N && k < K) ? B[vaddr(vb, k, n)] : T(0);
+          Bs[ki][ni] = (n < N && k < K) ? (TC)B[vaddr(vb, k, n)] : TC(0);
         }
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < BK; ++kk) {
-          T a[4], b[4];
+          TC a[4], b[4];
 #pragma unroll
           for (int i = 0; i < 4; ++i) a[i] = As[kk][tr * 4 + i];
 #pragma unroll
@@ -203,34 +210,35 @@ struct S4 { int l, u, r, d; };        // PEPS site
 template <typename T>
 __device__ void env3_step(T* Lout, const T* Lin, const T* A, S3 sA, const T* t, S4 st,
                           const T* B, S3 sB, T* X0, T* X1, int c, int d) {
+  using TC = T;
   // X0[c'][b][l][u] = sum_a Lin[a][(l,c')] A[a][(u,b)]
-  wg_gemm<T>(X0, view(c, d, c * d * d, c, 1, d * d), Lin, view(c, c, 1, 1, d * c, 0),
+  wg_gemm<TC>(X0, view(c, d, c * d * d, c, 1, d * d), Lin, view(c, c, 1, 1, d * c, 0),
              A, view(1, sA.s0, 0, c, sA.s1, sA.s2), d * c, d * c, c);
   // X1[b][r][c'][dd] = sum_{l,u} X0[(c',b)][(l,u)] t[(l,u)][(r,dd)]
-  wg_gemm<T>(X1, view(c, d, d * c * d, d, c * d, 1), X0, rowmajor(d * d),
+  wg_gemm<TC>(X1, view(c, d, d * c * d, d, c * d, 1), X0, rowmajor(d * d),
              t, view(d, st.l, st.u, d, st.r, st.d), c * c, d * d, d * d);
   // Lout[(b,r)][e] = sum_{c',dd} X1[(b,r)][(c',dd)] B[(c',dd)][e]
-  wg_gemm<T>(Lout, rowmajor(c), X1, rowmajor(c * d), B, view(d, sB.s0, sB.s1, 1, sB.s2, 0),
+  wg_gemm<TC>(Lout, rowmajor(c), X1, rowmajor(c * d), B, view(d, sB.s0, sB.s1, 1, sB.s2, 0),
              c * d, c, c * d);
 }
 
 // 4-line left step: Lout[b][r1][r2][e] = sum Lin[a][l1][l2][c] A[a][u][b]
 //   t1[l1][u][r1][m] t2[l2][m][r2][dd] B[c][dd][e].
 // X0/X1 scratch of d*d*d*c*c elements each.
-template <typename T>
-__device__ void env4_step(T* Lout, const T* Lin, const T* A, S3 sA, const T* t1, S4 s1,
-                          const T* t2, S4 s2, const T* B, S3 sB, T* X0, T* X1, int c, int d) {
+template <typename TC, typename T>
+__device__ void env4_step(TC* Lout, const TC* Lin, const T* A, S3 sA, const T* t1, S4 s1,
+                          const T* t2, S4 s2, const T* B, S3 sB, TC* X0, TC* X1, int c, int d) {
   // X0[(l2,c')][b][l1][u] = sum_a Lin[a][(l1,(l2,c'))] A[a][(u,b)]
-  wg_gemm<T>(X0, view(d * c, d, c * d * d, c, 1, d * d), Lin, view(d * c, d * c, 1, 1, d * d * c, 0),
+  wg_gemm<TC>(X0, view(d * c, d, c * d * d, c, 1, d * d), Lin, view(d * c, d * c, 1, 1, d * d * c, 0),
              A, view(1, sA.s0, 0, c, sA.s1, sA.s2), d * d * c, d * c, c);
   // X1[(c',b)][r1][l2][m] = sum_{l1,u} X0[(l2,c',b)][(l1,u)] t1[(l1,u)][(r1,m)]
-  wg_gemm<T>(X1, view(c * c, d, d * d * d, d, d * d, 1), X0, rowmajor(d * d),
+  wg_gemm<TC>(X1, view(c * c, d, d * d * d, d, d * d, 1), X0, rowmajor(d * d),
              t1, view(d, s1.l, s1.u, d, s1.r, s1.d), d * c * c, d * d, d * d);
   // X0[(b,r1)][r2][c'][dd] = sum_{l2,m} X1[(c',b,r1)][(l2,m)] t2[(l2,m)][(r2,dd)]
-  wg_gemm<T>(X0, view(c * d, d, d * d * c, d, c * d, 1), X1, rowmajor(d * d),
+  wg_gemm<TC>(X0, view(c * d, d, d * d * c, d, c * d, 1), X1, rowmajor(d * d),
              t2, view(d, s2.l, s2.u, d, s2.r, s2.d), c * c * d, d * d, d * d);
   // Lout[(b,r1,r2)][e] = sum_{c',dd} X0[(b,r1,r2)][(c',dd)] B[(c',dd)][e]
-  wg_gemm<T>(Lout, rowmajor(c), X0, rowmajor(c * d), B, view(d, sB.s0, sB.s1, 1, sB.s2, 0),
+  wg_gemm<TC>(Lout, rowmajor(c), X0, rowmajor(c * d), B, view(d, sB.s0, sB.s1, 1, sB.s2, 0),
              c * d * d, c, c * d);
 }
 
@@ -239,108 +247,28 @@ __device__ void env4_step(T* Lout, const T* Lin, const T* A, S3 sA, const T* t1,
 template <typename T>
 __device__ void defect3(T* Out, const T* Lp, const T* A, S3 sA, const T* Rn, const T* B, S3 sB,
                         T* X0, T* X1, int c, int d) {
+  using TC = T;
   // X0[l][u][c'][b] = sum_a Lp[a][(l,c')] A[a][(u,b)]
-  wg_gemm<T>(X0, view(c, d * c * c, c, c, c * c, 1), Lp, view(c, c, 1, 1, d * c, 0),
+  wg_gemm<TC>(X0, view(c, d * c * c, c, c, c * c, 1), Lp, view(c, c, 1, 1, d * c, 0),
              A, view(1, sA.s0, 0, c, sA.s1, sA.s2), d * c, d * c, c);
   // X1[(l,u)][r][c'][e] = sum_b X0[(l,u,c')][b] Rn[b][(r,e)]
-  wg_gemm<T>(X1, view(c, d * c * c, c, c, c * c, 1), X0, rowmajor(c), Rn, rowmajor(d * c),
+  wg_gemm<TC>(X1, view(c, d * c * c, c, c, c * c, 1), X0, rowmajor(c), Rn, rowmajor(d * c),
              d * d * c, d * c, c);
   // Out[(l,u,r)][dd] = sum_{c',e} X1[(l,u,r)][(c',e)] B[(c',e)][dd]
-  wg_gemm<T>(Out, rowmajor(d), X1, rowmajor(c * c), B, view(c, sB.s0, sB.s2, 1, sB.s1, 0),
+  wg_gemm<TC>(Out, rowmajor(d), X1, rowmajor(c * c), B, view(c, sB.s0, sB.s2, 1, sB.s1, 0),
              d * d * d, d, c * c);
 }
 
 // Compression helper: Y[a][l][dd][k] = sum_{u,b,r} A[a][u][b] t[l][u][r][dd] Tin[b][r][k].
-template <typename T>
-__device__ void compress_y(T* Y, const T* A, S3 sA, const T* t, S4 st, const T* Tin, T* X0,
+template <typename TC, typename T>
+__device__ void compress_y(TC* Y, const T* A, S3 sA, const T* t, S4 st, const TC* Tin, TC* X0,
                            int c, int d) {
   // X0[a][k][u][r] = sum_b A[(a,u)][b] Tin[b][(r,k)]
-  wg_gemm<T>(X0, view(d, c * d * d, d, c, 1, d * d), A, view(d, sA.s0, sA.s1, 1, sA.s2, 0),
+  wg_gemm<TC>(X0, view(d, c * d * d, d, c, 1, d * d), A, view(d, sA.s0, sA.s1, 1, sA.s2, 0),
              Tin, view(1, d * c, 0, c, c, 1), c * d, d * c, c);
   // Y[(a,k)][(l,dd)] = sum_{u,r} X0[(a,k)][(u,r)] t[(u,r)][(l,dd)]
-  wg_gemm<T>(Y, view(c, d * d * c, 1, d, d * c, c), X0, rowmajor(d * d),
+  wg_gemm<TC>(Y, view(c, d * d * c, 1, d, d * c, c), X0, rowmajor(d * d),
              t, view(d, st.u, st.r, d, st.l, st.d), c * c, d * d, d * d);
-}
-
-// ---------------------------------------------------------------------------
-// Symmetric eigensolver: cyclic Jacobi with the Brent-Luk parallel ordering
-// (round-robin pairs; all rotations of a round are disjoint).  H (n x n, row
-// major, ld n) is overwritten by its eigenvalues on the diagonal; V (ld n)
-// receives the eigenvectors as columns.  Rotation formulas: Golub & Van Loan,
-// symmetric Schur decomposition.
-// ---------------------------------------------------------------------------
-template <typename T>
-__device__ void jacobi_eig(T* H, T* V, int n, double tol, int max_sweeps) {
-  __shared__ T cs_c[WG / 2];
-  __shared__ T cs_s[WG / 2];
-  __shared__ int pp[WG / 2];
-  __shared__ int qq[WG / 2];
-  for (int i = threadIdx.x; i < n * n; i += WG) V[i] = (i / n == i % n) ? T(1) : T(0);
-  __syncthreads();
-  if (n < 2) return;
-  const int m = (n + 1) & ~1;  // even number of players (index n is a dummy when n is odd)
-  const int npair = m / 2;
-  double fro = 0.0;
-  for (int i = threadIdx.x; i < n * n; i += WG) fro += (double)H[i] * (double)H[i];
-  fro = wg_sum(fro);
-  const double thresh = tol * tol * fro;
-  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    double off = 0.0;
-    for (int i = threadIdx.x; i < n * n; i += WG)
-      if (i / n != i % n) off += (double)H[i] * (double)H[i];
-    off = wg_sum(off);
-    if (off <= thresh) break;
-    for (int rnd = 0; rnd < m - 1; ++rnd) {
-      if ((int)threadIdx.x < npair) {
-        int i = threadIdx.x;
-        // round-robin: player 0 fixed, players 1..m-1 rotate
-        auto player = [&](int pos) { return pos == 0 ? 0 : 1 + (pos - 1 + rnd) % (m - 1); };
-        int p = player(i), q = player(m - 1 - i);
-        if (p > q) { int t = p; p = q; q = t; }
-        T c = T(1), s = T(0);
-        if (q < n) {
-          double apq = (double)H[p * n + q];
-          double app = (double)H[p * n + p], aqq = (double)H[q * n + q];
-          if (apq != 0.0 && fabs(apq) > 1e-300) {
-            double tau = (aqq - app) / (2.0 * apq);
-            double tt = (tau >= 0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            double cc = 1.0 / sqrt(1.0 + tt * tt);
-            c = (T)cc;
-            s = (T)(tt * cc);
-          }
-        } else {
-          q = p;  // pair with the dummy: identity
-        }
-        pp[i] = p; qq[i] = q; cs_c[i] = c; cs_s[i] = s;
-      }
-      __syncthreads();
-      // H <- H J and V <- V J (columns p, q of every row)
-      for (int w = threadIdx.x; w < npair * n; w += WG) {
-        int i = w / n, r = w - i * n;
-        int p = pp[i], q = qq[i];
-        if (p == q) continue;
-        T c = cs_c[i], s = cs_s[i];
-        T hp = H[r * n + p], hq = H[r * n + q];
-        H[r * n + p] = c * hp - s * hq;
-        H[r * n + q] = s * hp + c * hq;
-        T vp = V[r * n + p], vq = V[r * n + q];
-        V[r * n + p] = c * vp - s * vq;
-        V[r * n + q] = s * vp + c * vq;
-      }
-      __syncthreads();
-      // H <- J^T H (rows p, q)
-      for (int w = threadIdx.x; w < npair * n; w += WG) {
-        int i = w / n, col = w - i * n;
-        int p = pp[i], q = qq[i];
-        if (p == q) continue;
-        T c = cs_c[i], s = cs_s[i];
-        T hp = H[p * n + col], hq = H[q * n + col];
-        H[p * n + col] = c * hp - s * hq;
-        H[q * n + col] = s * hp + c * hq;
-      }
-      __syncthreads();
-    }
-  }
 }
 
 }  // namespace vp

@@ -1,0 +1,275 @@
+// Leading eigenpairs of a small symmetric matrix, one work-group per matrix.
+//
+// Householder tridiagonalisation (the unblocked symmetric reduction of Golub &
+// Van Loan, Sec. 8.3.1) on the packed lower triangle held in LDS, eigenvalues
+// of the tridiagonal matrix by Sturm-count multisection (16 probes per
+// eigenvalue and step), eigenvectors of the tridiagonal matrix by inverse
+// iteration with partial-pivoting LU (Wilkinson), modified Gram-Schmidt among
+// the kept vectors, and back-transformation by the stored reflectors.
+#pragma once
+#include "vp_device.hpp"
+
+namespace vp {
+
+constexpr int EIG_NMAX = 128;
+constexpr int EIG_KMAX = 16;   // eigenvectors per inverse-iteration batch (one thread each)
+constexpr int EIG_PACK = EIG_NMAX * (EIG_NMAX + 1) / 2;
+
+__device__ inline int tri(int i) { return i * (i + 1) / 2; }
+
+// Number of eigenvalues of tridiag(d, e) strictly below x (Sturm sequence).
+__device__ inline int sturm_count(const double* d, const double* e2, int n, double x, double pivmin) {
+  int cnt = 0;
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  cnt += q < 0.0;
+  for (int j = 1; j < n; ++j) {
+    q = d[j] - x - e2[j - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += q < 0.0;
+  }
+  return cnt;
+}
+
+// H: n x n symmetric, row-major (ld n), any address space; n <= EIG_NMAX.
+// Writes the eigenvectors of the k largest eigenvalues, in descending order,
+// as columns 0..k-1 of V (ld k) and the eigenvalues to lam[0..k-1].
+// refl: global scratch of at least EIG_PACK doubles (Householder vectors).
+__device__ void sym_topk_eig(const double* H, int n, int k, double* V, double* lam, double* refl) {
+  __shared__ double Ap[EIG_PACK];
+  __shared__ double dg[EIG_NMAX], eg[EIG_NMAX], e2[EIG_NMAX], tau[EIG_NMAX];
+  __shared__ double pv[EIG_NMAX], wv[EIG_NMAX], vv[EIG_NMAX];
+  __shared__ double probe_x[WG];
+  __shared__ int probe_c[WG];
+  __shared__ double lamb[EIG_KMAX];
+  __shared__ double Xs[EIG_NMAX * EIG_KMAX];
+  __shared__ unsigned char pivf[EIG_NMAX * EIG_KMAX];
+  const int tid = threadIdx.x;
+
+  for (int e = tid; e < n * n; e += WG) {
+    int i = e / n, j = e - i * n;
+    if (j <= i) Ap[tri(i) + j] = H[e];
+  }
+  __syncthreads();
+
+  // ---- tridiagonalisation: Q^T A Q = T, Q = H_0 H_1 ... H_{n-3}
+  for (int i = 0; i < n - 2; ++i) {
+    const double alpha = Ap[tri(i + 1) + i];
+    double xn2 = 0.0;
+    for (int r = i + 2 + tid; r < n; r += WG) xn2 += Ap[tri(r) + i] * Ap[tri(r) + i];
+    xn2 = wg_sum(xn2);
+    double beta = alpha, t = 0.0;
+    if (xn2 > 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+      t = (beta - alpha) / beta;
+      const double scal = 1.0 / (alpha - beta);
+      for (int r = i + 2 + tid; r < n; r += WG) Ap[tri(r) + i] *= scal;
+    }
+    // reflector i: v[i+1] = 1, v[r] = Ap[r][i] (r > i+1); also kept in global memory
+    for (int r = i + 1 + tid; r < n; r += WG) {
+      double v = (r == i + 1) ? 1.0 : Ap[tri(r) + i];
+      vv[r] = v;
+      refl[tri(r) + i] = v;
+    }
+    if (tid == 0) { dg[i] = Ap[tri(i) + i]; eg[i] = beta; tau[i] = t; }
+    __syncthreads();
+    if (t != 0.0) {
+      // p = t * A22 v over rows/cols i+1..n-1
+      for (int r = i + 1 + tid; r < n; r += WG) {
+        double acc = 0.0;
+        for (int s = i + 1; s <= r; ++s) acc += Ap[tri(r) + s] * vv[s];
+        for (int s = r + 1; s < n; ++s) acc += Ap[tri(s) + r] * vv[s];
+        pv[r] = t * acc;
+      }
+      __syncthreads();
+      double pw = 0.0;
+      for (int r = i + 1 + tid; r < n; r += WG) pw += pv[r] * vv[r];
+      const double K = -0.5 * t * wg_sum(pw);
+      for (int r = i + 1 + tid; r < n; r += WG) wv[r] = pv[r] + K * vv[r];
+      __syncthreads();
+      const int m = n - i - 1;
+      for (int e = tid; e < m * m; e += WG) {
+        int rr = e / m, ss = e - rr * m;
+        if (ss > rr) continue;
+        int r = i + 1 + rr, s = i + 1 + ss;
+        Ap[tri(r) + s] -= vv[r] * wv[s] + wv[r] * vv[s];
+      }
+      __syncthreads();
+    }
+  }
+  if (tid == 0) {
+    if (n >= 2) {
+      dg[n - 2] = Ap[tri(n - 2) + n - 2];
+      eg[n - 2] = Ap[tri(n - 1) + n - 2];
+      tau[n - 2] = 0.0;
+    }
+    dg[n - 1] = Ap[tri(n - 1) + n - 1];
+    eg[n - 1] = 0.0;
+    tau[n - 1] = 0.0;
+  }
+  __syncthreads();
+  for (int j = tid; j < n; j += WG) e2[j] = eg[j] * eg[j];
+
+  // ---- Gershgorin interval and pivot floor
+  double lo = 1e300, hi = -1e300, amax = 0.0;
+  for (int j = tid; j < n; j += WG) {
+    double r = (j > 0 ? fabs(eg[j - 1]) : 0.0) + (j < n - 1 ? fabs(eg[j]) : 0.0);
+    lo = fmin(lo, dg[j] - r);
+    hi = fmax(hi, dg[j] + r);
+    amax = fmax(amax, fmax(fabs(dg[j]), fabs(eg[j])));
+  }
+  lo = -wg_max(-lo);
+  hi = wg_max(hi);
+  amax = wg_max(amax);
+  const double span = fmax(hi - lo, 1e-300);
+  lo -= 2.2e-16 * span + 1e-300;
+  hi += 2.2e-16 * span + 1e-300;
+  const double pivmin = fmax(1e-300, 2.2e-16 * 2.2e-16 * amax * amax);
+  const double tiny = fmax(1e-300, 2.2e-16 * amax);
+
+  for (int b0 = 0; b0 < k; b0 += EIG_KMAX) {
+    const int kb = min(EIG_KMAX, k - b0);
+    // ---- eigenvalues b0 .. b0+kb-1 (descending): 16 probes per eigenvalue
+    const int g = tid >> 4, lane = tid & 15;
+    const int t = b0 + g;
+    const int q = n - 1 - t;            // ascending index
+    double a = lo, c = hi;
+    for (int it = 0; it < 16; ++it) {
+      double x = a + (c - a) * (double)(lane + 1) / 17.0;
+      int cnt = (g < kb) ? sturm_count(dg, e2, n, x, pivmin) : 0;
+      probe_x[tid] = x;
+      probe_c[tid] = cnt;
+      __syncthreads();
+      if (g < kb) {
+        double na = a, nc = c;
+        for (int s = 0; s < 16; ++s) {
+          int cs = probe_c[(g << 4) + s];
+          double xs = probe_x[(g << 4) + s];
+          if (cs <= q) na = xs;
+          else { nc = xs; break; }
+        }
+        a = na;
+        c = nc;
+      }
+      __syncthreads();
+    }
+    if (g < kb && lane == 0) lamb[g] = 0.5 * (a + c);
+    __syncthreads();
+
+    // ---- inverse iteration, one thread per eigenvector; LU factors in LDS (Ap is free now)
+    double* U0 = Ap;
+    double* U1 = Ap + 1 * EIG_NMAX * EIG_KMAX;
+    double* U2 = Ap + 2 * EIG_NMAX * EIG_KMAX;
+    double* ML = Ap + 3 * EIG_NMAX * EIG_KMAX;
+    if (tid < kb) {
+      const int col = b0 + tid;
+      const double lm = lamb[tid];
+#define IX(j) ((j) * EIG_KMAX + tid)
+      // Gaussian elimination with partial pivoting of T - lm I; rows j and j+1 may swap,
+      // which fills a second superdiagonal (U2).
+      double aa = dg[0] - lm, cc = n > 1 ? eg[0] : 0.0;
+      for (int j = 0; j < n - 1; ++j) {
+        const double bb = eg[j];
+        const double a1 = dg[j + 1] - lm;
+        const double c1 = (j + 1 < n - 1) ? eg[j + 1] : 0.0;
+        if (fabs(aa) >= fabs(bb)) {
+          const double piv = fabs(aa) < tiny ? (aa < 0.0 ? -tiny : tiny) : aa;
+          const double m = bb / piv;
+          U0[IX(j)] = piv; U1[IX(j)] = cc; U2[IX(j)] = 0.0; ML[IX(j)] = m;
+          pivf[IX(j)] = 0;
+          aa = a1 - m * cc;
+          cc = c1;
+        } else {
+          const double m = aa / bb;
+          U0[IX(j)] = bb; U1[IX(j)] = a1; U2[IX(j)] = c1; ML[IX(j)] = m;
+          pivf[IX(j)] = 1;
+          const double naa = cc - m * a1;
+          cc = -m * c1;
+          aa = naa;
+        }
+      }
+      U0[IX(n - 1)] = fabs(aa) < tiny ? (aa < 0.0 ? -tiny : tiny) : aa;
+      // deterministic, eigenvector-dependent start vector
+      for (int j = 0; j < n; ++j) {
+        uint64_t h = (uint64_t)(j + 1) * 0x9E3779B97F4A7C15ull ^ (uint64_t)(col + 1) * 0xD2E7470EE14C6C93ull;
+        h ^= h >> 29;
+        Xs[IX(j)] = 0.5 + (double)(h & 0xFFFF) / 65536.0;
+      }
+      for (int it = 0; it < 3; ++it) {
+        for (int j = 0; j < n - 1; ++j) {
+          double rj = Xs[IX(j)], rj1 = Xs[IX(j + 1)];
+          if (pivf[IX(j)]) { double tt = rj; rj = rj1; rj1 = tt; }
+          Xs[IX(j)] = rj;
+          Xs[IX(j + 1)] = rj1 - ML[IX(j)] * rj;
+        }
+        double x1 = 0.0, x2 = 0.0, nrm = 0.0;
+        for (int j = n - 1; j >= 0; --j) {
+          const double xj = (Xs[IX(j)] - U1[IX(j)] * x1 - U2[IX(j)] * x2) / U0[IX(j)];
+          Xs[IX(j)] = xj;
+          x2 = x1;
+          x1 = xj;
+          nrm = fmax(nrm, fabs(xj));
+        }
+        const double inv = nrm > 0.0 ? 1.0 / nrm : 1.0;
+        for (int j = 0; j < n; ++j) Xs[IX(j)] *= inv;
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < n * kb; e += WG) {
+      int j = e / kb, tt = e - j * kb;
+      V[(int64_t)j * k + b0 + tt] = Xs[j * EIG_KMAX + tt];
+    }
+#undef IX
+    __syncthreads();
+    if (tid < kb) lam[b0 + tid] = lamb[tid];
+    __syncthreads();
+  }
+
+  // ---- modified Gram-Schmidt over the kept vectors (descending order)
+  for (int col = 0; col < k; ++col) {
+    for (int s = 0; s < col; ++s) {
+      double dp = 0.0;
+      for (int j = tid; j < n; j += WG) dp += V[(int64_t)j * k + s] * V[(int64_t)j * k + col];
+      dp = wg_sum(dp);
+      for (int j = tid; j < n; j += WG) V[(int64_t)j * k + col] -= dp * V[(int64_t)j * k + s];
+      __syncthreads();
+    }
+    double nn = 0.0;
+    for (int j = tid; j < n; j += WG) nn += V[(int64_t)j * k + col] * V[(int64_t)j * k + col];
+    nn = wg_sum(nn);
+    double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+    for (int j = tid; j < n; j += WG) V[(int64_t)j * k + col] *= inv;
+    __syncthreads();
+  }
+
+  // ---- back-transformation: x <- H_0 H_1 ... H_{n-3} x
+  for (int i = n - 3; i >= 0; --i) {
+    const double t = tau[i];
+    if (t == 0.0) continue;
+    for (int r = i + 1 + tid; r < n; r += WG) vv[r] = refl[tri(r) + i];
+    __syncthreads();
+    // dots for every kept vector: 16 threads per vector
+    for (int c0 = 0; c0 < k; c0 += WG / 16) {
+      const int col = c0 + (tid >> 4), lane = tid & 15;
+      double dp = 0.0;
+      if (col < k)
+        for (int r = i + 1 + lane; r < n; r += 16) dp += vv[r] * V[(int64_t)r * k + col];
+      probe_x[tid] = dp;
+      __syncthreads();
+      if (col < k && lane == 0) {
+        double s = 0.0;
+        for (int q2 = 0; q2 < 16; ++q2) s += probe_x[tid + q2];
+        pv[col - c0] = s;
+      }
+      __syncthreads();
+      for (int e = tid; e < (n - i - 1) * (WG / 16); e += WG) {
+        int cc = e / (n - i - 1), r = i + 1 + (e - cc * (n - i - 1));
+        int col2 = c0 + cc;
+        if (col2 < k) V[(int64_t)r * k + col2] -= t * pv[cc] * vv[r];
+      }
+      __syncthreads();
+    }
+  }
+}
+
+}  // namespace vp

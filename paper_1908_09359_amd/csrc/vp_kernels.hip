@@ -3,6 +3,7 @@
 // phase of a sweep for one row: right environments, the horizontal or vertical
 // Metropolis pass, the boundary compression, or the measurement of a row.
 #include "vp_device.hpp"
+#include "vp_eig.hpp"
 #include "vp_kernels.hpp"
 
 #include <math.h>
@@ -91,10 +92,10 @@ __device__ inline int step4(const LatDev& L, const Chain<T>& C, T* out, const T*
   const T* t2 = tw<T>(L, k2, C.sp[k2] ^ flip2);
   S4 st = st_std(L.d);
   if (right)
-    env4_step<T>(out, in, Ux, sb_mirror(L.c, L.d), t1, st_mirror(st), t2, st_mirror(st), Dx,
+    env4_step<T, T>(out, in, Ux, sb_mirror(L.c, L.d), t1, st_mirror(st), t2, st_mirror(st), Dx,
                  sb_mirror(L.c, L.d), C.ws + L.oX0, C.ws + L.oX1, L.c, L.d);
   else
-    env4_step<T>(out, in, Ux, sb_std(L.c, L.d), t1, st, t2, st, Dx, sb_std(L.c, L.d),
+    env4_step<T, T>(out, in, Ux, sb_std(L.c, L.d), t1, st, t2, st, Dx, sb_std(L.c, L.d),
                  C.ws + L.oX0, C.ws + L.oX1, L.c, L.d);
   return wg_renorm<T>(out, e4sz(L));
 }
@@ -310,16 +311,18 @@ __global__ void __launch_bounds__(WG) k_vsweep(LatDev L, int y) {
 // Boundary compression (App. B) of row y into U_y (upper = 1) or D_y.
 //
 // The canonical SVD compression is computed through Gram matrices: the
-// left-to-right QR sweep of the reference definition only enters through the
-// Gram matrices G_j of the left blocks (R_j^T R_j = G_j), which a 4-line-type
-// column step carries exactly; the right-to-left SVD at site j is the
-// eigendecomposition of Y^T G_{j-1} Y with Y = (site j) x (right carry), whose
-// leading k_j eigenvectors are the kept right singular vectors.  The output
-// state is the same; the sign and gauge of every site may differ.
+// left-to-right QR sweep of its definition only enters through the Gram
+// matrices G_j of the left blocks (R_j^T R_j = G_j), which a 2-row column step
+// carries exactly; the right-to-left SVD at site j is the eigendecomposition
+// of Y^T G_{j-1} Y with Y = (site j) x (right carry), whose leading k_j
+// eigenvectors are the kept right singular vectors.  The output state is the
+// same; the sign and gauge of every site may differ.  All of it runs in float64
+// (the Gram matrices square the condition number of the left blocks).
 template <typename T>
 __global__ void __launch_bounds__(WG) k_compress(LatDev L, int y, int upper) {
   Chain<T> C = chain_of<T>(L, blockIdx.x);
   if (C.meta->flags) return;
+  double* cw = L.cws + (int64_t)blockIdx.x * L.cws_stride;
   const int c = L.c, d = L.d, Lx = L.Lx;
   const int ssz = c * d * c, gsz = c * d * d * c;
   const int in_slot = upper ? y : y + 1;
@@ -330,78 +333,74 @@ __global__ void __launch_bounds__(WG) k_compress(LatDev L, int y, int upper) {
   const S3 sA = sb_std(c, d);
   const S4 st = upper ? st_std(d) : st_swapud(st_std(d));
   const S4 st2 = st_swapud(st);
-  T* G = C.ws + L.oG;
+  double* G = cw + L.cG;
+  double* X0 = cw + L.cX0;
+  double* X1 = cw + L.cX1;
   // Gram matrices of the left blocks: G[0] = G_{-1} (unit), G[j+1] = G_j.
-  set_unit<T>(G, gsz);
+  set_unit<double>(G, gsz);
   for (int j = 0; j < Lx - 1; ++j) {
     const int k = y * Lx + j;
     const T* t = tw<T>(L, k, C.sp[k]);
-    env4_step<T>(G + (int64_t)(j + 1) * gsz, G + (int64_t)j * gsz, A_in(j), sA, t, st, t, st2, A_in(j), sA,
-                 C.ws + L.oX0, C.ws + L.oX1, c, d);
-    wg_renorm<T>(G + (int64_t)(j + 1) * gsz, gsz);
+    env4_step<double, T>(G + (int64_t)(j + 1) * gsz, G + (int64_t)j * gsz, A_in(j), sA, t, st, t, st2, A_in(j),
+                         sA, X0, X1, c, d);
+    wg_renorm<double>(G + (int64_t)(j + 1) * gsz, gsz);
   }
-  T* Ta = C.ws + L.oTa;
-  T* Tb = C.ws + L.oTb;
-  T* Y = C.ws + L.oY;
-  T* W = C.ws + L.oW;
-  T* H = C.ws + L.oH;
-  T* V = C.ws + L.oV;
-  set_unit<T>(Ta, ssz);
+  double* Ta = cw + L.cTa;
+  double* Tb = cw + L.cTb;
+  double* Y = cw + L.cY;
+  double* W = cw + L.cW;
+  double* H = cw + L.cH;
+  double* Hc = cw + L.cHc;
+  double* Vk = cw + L.cVk;
+  double* Vp = cw + L.cVp;
+  set_unit<double>(Ta, ssz);
   int eT = 0;
   const int dc = d * c;
-  const double tol = sizeof(T) == 8 ? 1e-14 : 2e-7;
   for (int j = Lx - 1; j >= 1; --j) {
     const int k = y * Lx + j;
     const T* t = tw<T>(L, k, C.sp[k]);
-    compress_y<T>(Y, A_in(j), sA, t, st, Ta, C.ws + L.oX0, c, d);
-    // W = G_{j-1} Y  with G stored [a][l][l'][a'] and viewed as ((a,l), (a',l'))
-    wg_gemm<T>(W, rowmajor(dc), G + (int64_t)j * gsz, view(d, d * d * c, d * c, d, 1, c), Y, rowmajor(dc),
-               dc, dc, dc);
+    compress_y<double, T>(Y, A_in(j), sA, t, st, Ta, X0, c, d);
+    // W = G_{j-1} Y with G stored [a][l][l'][a'] and viewed as ((a,l), (a',l'))
+    wg_gemm<double>(W, rowmajor(dc), G + (int64_t)j * gsz, view(d, d * d * c, d * c, d, 1, c), Y, rowmajor(dc),
+                    dc, dc, dc);
     // H = Y^T W
-    wg_gemm<T>(H, rowmajor(dc), Y, colmajor(dc), W, rowmajor(dc), dc, dc, dc);
+    wg_gemm<double>(H, rowmajor(dc), Y, colmajor(dc), W, rowmajor(dc), dc, dc, dc);
     const int p = upper ? L.dims[4 * k + 3] : L.dims[4 * k + 1];
     const int kr = kout[j + 1], kl = kout[j];
     const int n = p * kr;
-    // compact n x n problem over the valid (dd, kk) pairs; W is free now
+    // compact n x n problem over the valid (dd, kk) pairs
     for (int i = threadIdx.x; i < n * n; i += WG) {
       int a = i / n, b = i - a * n;
-      int pa = (a / kr) * c + a % kr, pb = (b / kr) * c + b % kr;
-      W[i] = H[pa * dc + pb];
+      Hc[i] = H[((a / kr) * c + a % kr) * dc + (b / kr) * c + b % kr];
     }
     __syncthreads();
-    jacobi_eig<T>(W, V, n, tol, sizeof(T) == 8 ? 40 : 30);
-    // keep the kl largest eigenvalues (ties by index)
+    sym_topk_eig(Hc, n, kl, Vk, cw + L.cLam, cw + L.cRefl);
+    // new site j: rows k' < kl are the kept eigenvectors, in descending order
+    for (int i = threadIdx.x; i < ssz; i += WG) Vp[i] = 0.0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n * kl; i += WG) {
+      int q = i / kl, r = i - q * kl;
+      Vp[r * dc + (q / kr) * c + q % kr] = Vk[i];
+    }
+    __syncthreads();
     T* out = A_out(j);
-    for (int i = threadIdx.x; i < ssz; i += WG) out[i] = T(0);
-    __syncthreads();
-    for (int i = threadIdx.x; i < n; i += WG) {
-      T li = W[i * n + i];
-      int rank = 0;
-      for (int q = 0; q < n; ++q) {
-        T lq = W[q * n + q];
-        rank += (lq > li) || (lq == li && q < i);
-      }
-      if (rank < kl) {
-        for (int q = 0; q < n; ++q) out[rank * dc + (q / kr) * c + q % kr] = V[q * n + i];
-      }
-    }
-    __syncthreads();
-    // carry: Tb[(a,l)][k'] = sum_{(dd,kk)} Y[(a,l)][(dd,kk)] out[k'][(dd,kk)]
-    wg_gemm<T>(Tb, rowmajor(c), Y, rowmajor(dc), out, colmajor(dc), dc, c, dc);
-    eT += wg_renorm<T>(Tb, ssz);
-    T* tt = Ta; Ta = Tb; Tb = tt;
+    for (int i = threadIdx.x; i < ssz; i += WG) out[i] = (T)Vp[i];
+    // carry: Tb[(a,l)][k'] = sum_{(dd,kk)} Y[(a,l)][(dd,kk)] Vp[k'][(dd,kk)]
+    wg_gemm<double>(Tb, rowmajor(c), Y, rowmajor(dc), Vp, colmajor(dc), dc, c, dc);
+    eT += wg_renorm<double>(Tb, ssz);
+    double* tt = Ta; Ta = Tb; Tb = tt;
   }
   {
     const int k = y * Lx;
     const T* t = tw<T>(L, k, C.sp[k]);
-    compress_y<T>(Y, A_in(0), sA, t, st, Ta, C.ws + L.oX0, c, d);
+    compress_y<double, T>(Y, A_in(0), sA, t, st, Ta, X0, c, d);
     double nrm2 = 0.0;
-    for (int i = threadIdx.x; i < dc; i += WG) nrm2 += (double)Y[i] * (double)Y[i];
+    for (int i = threadIdx.x; i < dc; i += WG) nrm2 += Y[i] * Y[i];
     nrm2 = wg_sum(nrm2);
     double nu = sqrt(nrm2);
     T* out = A_out(0);
-    T inv = nu > 0 ? (T)(1.0 / nu) : T(0);
-    for (int i = threadIdx.x; i < ssz; i += WG) out[i] = (i < dc) ? Y[i] * inv : T(0);
+    double inv = nu > 0 ? 1.0 / nu : 0.0;
+    for (int i = threadIdx.x; i < ssz; i += WG) out[i] = (i < dc) ? (T)(Y[i] * inv) : T(0);
     if (threadIdx.x == 0) {
       if (!(nu > 0.0)) C.meta->flags |= FLAG_ZERO;
       else if (!isfinite(nu)) C.meta->flags |= FLAG_NONFINITE;

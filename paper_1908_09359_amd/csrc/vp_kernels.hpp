@@ -47,11 +47,17 @@ struct LatDev {
   int64_t oUb, oDb;         // boundaries: [(Ly+1)][Lx][c*d*c]
   int64_t oL3, oR3, oT3;    // 3-line envs: [(Lx+1)] slots each, 4 temps
   int64_t oL4, oR4, oT4;    // 4-line envs: [(Lx+1)] slots each, 4 temps
-  int64_t oG;               // Gram matrices [Lx][c*d*d*c]
   int64_t oX0, oX1;         // GEMM intermediates [c*c*d*d*d]
-  int64_t oY, oW, oH, oV;   // compression scratch [c*c*d*d]
-  int64_t oTa, oTb;         // compression carry [c*d*c]
   int64_t oDl;              // defect tensor scratch [d^4]
+  // float64 compression workspace (per chain)
+  double* cws;
+  int64_t cws_stride;
+  int64_t cG;               // Gram matrices [Lx][c*d*d*c]
+  int64_t cX0, cX1;         // intermediates [c*c*d*d*d]
+  int64_t cY, cW, cH, cHc, cVk;   // [c*c*d*d]
+  int64_t cVp, cTa, cTb;    // [c*d*c]
+  int64_t cRefl;            // Householder vectors [128*129/2]
+  int64_t cLam;             // eigenvalues [64]
   // int offsets: exponents of env slots
   int64_t ieL3, ieR3, ieT3, ieL4, ieR4, ieT4;
   // double offsets
