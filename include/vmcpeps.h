@@ -144,6 +144,26 @@ vp_status vp_sign_sgd_update(vp_ctx* ctx, int32_t lat, const double* grad_dev, d
 /* Wait for the context's stream; report device-side error flags. */
 vp_status vp_sync(vp_ctx* ctx);
 
+/* Device timing of the sweep phases, for benchmarks and profiling: while
+ * enabled, every phase launch is bracketed by a pair of HIP events on the
+ * context's stream.  vp_timing_enable clears the accumulated figures;
+ * vp_timing_read waits for the stream and writes, per phase, the summed
+ * kernel milliseconds and the number of launches (host arrays of VP_NPHASE). */
+typedef enum {
+  VP_PH_ROW3_ENVS = 0,   /* right 3-line environments of a row (sampling pass) */
+  VP_PH_HSWEEP = 1,      /* horizontal Metropolis pass of a row */
+  VP_PH_ROW4_ENVS = 2,   /* right 2-row environments (sampling pass) */
+  VP_PH_VSWEEP = 3,      /* vertical Metropolis pass between two rows */
+  VP_PH_COMPRESS_UP = 4, /* upper boundary U_y */
+  VP_PH_COMPRESS_DOWN = 5, /* lower boundary D_y */
+  VP_PH_MEASURE3 = 6,    /* log-derivatives and horizontal ratios of a row */
+  VP_PH_MEASURE4 = 7,    /* vertical and diagonal ratios of a row pair */
+  VP_PH_OTHER = 8,
+  VP_NPHASE = 9
+} vp_phase;
+vp_status vp_timing_enable(vp_ctx* ctx, int32_t enable);
+vp_status vp_timing_read(vp_ctx* ctx, double* ms_host, int64_t* launches_host);
+
 #ifdef __cplusplus
 }
 #endif

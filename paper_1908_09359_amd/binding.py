@@ -20,7 +20,11 @@ STATUS_NAMES = {0: "VP_OK", 1: "VP_ERR_ARG", 2: "VP_ERR_SHAPE", 3: "VP_ERR_OOM",
 
 EXPORTED = ["vp_create", "vp_destroy", "vp_last_error", "vp_num_params", "vp_workspace_bytes",
             "vp_set_tensors", "vp_get_tensors", "vp_init_tensors", "vp_init_chains", "vp_sample",
-            "vp_eval", "vp_gradient", "vp_sr_update", "vp_sign_sgd_update", "vp_sync"]
+            "vp_eval", "vp_gradient", "vp_sr_update", "vp_sign_sgd_update", "vp_sync",
+            "vp_timing_enable", "vp_timing_read"]
+
+PHASES = ["row3_envs", "hsweep", "row4_envs", "vsweep", "compress_up", "compress_down", "measure3",
+          "measure4", "other"]
 
 
 class vp_lattice(ctypes.Structure):
@@ -59,6 +63,8 @@ def _load():
         "vp_sr_update": ([P, I32, P, P, P, I64, D, D, P], I32),
         "vp_sign_sgd_update": ([P, I32, P, D, U64], I32),
         "vp_sync": ([P], I32),
+        "vp_timing_enable": ([P, I32], I32),
+        "vp_timing_read": ([P, P, P], I32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -153,3 +159,13 @@ class Context:
 
     def vp_sync(self):
         self._check(LIB.vp_sync(self.h))
+
+    def vp_timing_enable(self, enable=True):
+        self._check(LIB.vp_timing_enable(self.h, 1 if enable else 0))
+
+    def vp_timing_read(self):
+        """Per-phase (milliseconds, launches) since the last vp_timing_enable, as dicts."""
+        ms = (ctypes.c_double * len(PHASES))()
+        n = (ctypes.c_int64 * len(PHASES))()
+        self._check(LIB.vp_timing_read(self.h, ms, n))
+        return dict(zip(PHASES, list(ms))), dict(zip(PHASES, list(n)))

@@ -52,6 +52,13 @@ struct vp_ctx {
   uint64_t seed = 0;
   hipStream_t stream = nullptr;
   std::string err;
+  // phase timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev;        // pairs: start, stop
+  std::vector<int> ev_phase;
+  size_t ev_used = 0;
+  double ph_ms[VP_NPHASE] = {0};
+  int64_t ph_n[VP_NPHASE] = {0};
 };
 
 namespace {
@@ -188,35 +195,85 @@ Lattice* get_lat(vp_ctx* ctx, int32_t lat) {
   return &ctx->lats[lat];
 }
 
+// Brackets phase launches with HIP events while timing is enabled.
+struct Rec {
+  vp_ctx* ctx;
+  int phase = -1;
+  explicit Rec(vp_ctx* c) : ctx(c) {}
+  void begin(int ph) {
+    if (!ctx->timing) return;
+    if (ctx->ev_used + 2 > ctx->ev.size()) {
+      for (int i = 0; i < 64; ++i) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) { ctx->timing = false; return; }
+        ctx->ev.push_back(e);
+      }
+      ctx->ev_phase.resize(ctx->ev.size() / 2);
+    }
+    phase = ph;
+    hipEventRecord(ctx->ev[ctx->ev_used], ctx->stream);
+  }
+  void end() {
+    if (!ctx->timing || phase < 0) return;
+    hipEventRecord(ctx->ev[ctx->ev_used + 1], ctx->stream);
+    ctx->ev_phase[ctx->ev_used / 2] = phase;
+    ctx->ev_used += 2;
+    phase = -1;
+  }
+};
+
+void fold_timing(vp_ctx* ctx) {
+  if (ctx->ev_used == 0) return;
+  hipStreamSynchronize(ctx->stream);
+  for (size_t i = 0; i + 1 < ctx->ev_used; i += 2) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ctx->ev[i], ctx->ev[i + 1]) == hipSuccess) {
+      ctx->ph_ms[ctx->ev_phase[i / 2]] += ms;
+      ctx->ph_n[ctx->ev_phase[i / 2]] += 1;
+    }
+  }
+  ctx->ev_used = 0;
+}
+
+#define TIMED(rec, ph, call) \
+  do {                       \
+    (rec).begin(ph);         \
+    call;                    \
+    (rec).end();             \
+  } while (0)
+
 template <typename T>
-void run_lower_pass(Lattice& L, hipStream_t s) {
-  for (int y = L.p.Ly - 1; y >= 1; --y) launch_compress<T>(L.dev, y, 0, s);
+void run_lower_pass(vp_ctx* ctx, Lattice& L, hipStream_t s) {
+  Rec r(ctx);
+  for (int y = L.p.Ly - 1; y >= 1; --y) TIMED(r, VP_PH_COMPRESS_DOWN, launch_compress<T>(L.dev, y, 0, s));
 }
 
 template <typename T>
-void run_sweep(Lattice& L, const SampleOut* o, hipStream_t s) {
+void run_sweep(vp_ctx* ctx, Lattice& L, const SampleOut* o, hipStream_t s) {
   const int Ly = L.p.Ly;
+  Rec r(ctx);
   // top-down sampling pass
   for (int y = 0; y < Ly; ++y) {
-    launch_row3_right<T>(L.dev, y, y, y + 1, s);
-    launch_hsweep<T>(L.dev, y, y == Ly - 1, s);
+    TIMED(r, VP_PH_ROW3_ENVS, launch_row3_right<T>(L.dev, y, y, y + 1, s));
+    TIMED(r, VP_PH_HSWEEP, launch_hsweep<T>(L.dev, y, y == Ly - 1, s));
     if (y < Ly - 1) {
-      launch_row4_right<T>(L.dev, y, s);
-      launch_vsweep<T>(L.dev, y, s);
-      launch_compress<T>(L.dev, y, 1, s);
+      TIMED(r, VP_PH_ROW4_ENVS, launch_row4_right<T>(L.dev, y, s));
+      TIMED(r, VP_PH_VSWEEP, launch_vsweep<T>(L.dev, y, s));
+      TIMED(r, VP_PH_COMPRESS_UP, launch_compress<T>(L.dev, y, 1, s));
     }
   }
   // bottom-up measurement pass, rebuilding the lower boundaries
-  if (o) launch_begin_sample(L.dev, s);
+  if (o) TIMED(r, VP_PH_OTHER, launch_begin_sample(L.dev, s));
   for (int y = Ly - 1; y >= 0; --y) {
     if (o) {
-      launch_measure3<T>(L.dev, y, *o, s);
-      if (y < Ly - 1) launch_measure4<T>(L.dev, y, *o, s);
+      TIMED(r, VP_PH_MEASURE3, launch_measure3<T>(L.dev, y, *o, s));
+      if (y < Ly - 1) TIMED(r, VP_PH_MEASURE4, launch_measure4<T>(L.dev, y, *o, s));
     }
-    if (y >= 1) launch_compress<T>(L.dev, y, 0, s);
+    if (y >= 1) TIMED(r, VP_PH_COMPRESS_DOWN, launch_compress<T>(L.dev, y, 0, s));
   }
-  if (o) launch_finish_sample(L.dev, *o, L.p.n_chains, s);
-  launch_next_sweep(L.dev, s);
+  if (o) TIMED(r, VP_PH_OTHER, launch_finish_sample(L.dev, *o, L.p.n_chains, s));
+  TIMED(r, VP_PH_OTHER, launch_next_sweep(L.dev, s));
+  if (ctx->ev_used >= 8192) fold_timing(ctx);
 }
 
 template <typename T>
@@ -355,6 +412,8 @@ vp_status vp_create(const vp_lattice* lats, int32_t n_lats, uint64_t seed, void*
 
 vp_status vp_destroy(vp_ctx* ctx) {
   if (!ctx) return VP_OK;
+  if (ctx->stream) hipStreamSynchronize(ctx->stream); else hipDeviceSynchronize();
+  for (hipEvent_t e : ctx->ev) hipEventDestroy(e);
   for (auto& L : ctx->lats) {
     void* ptrs[] = {L.T, L.Tw, L.ws, L.cws, L.iws, L.dws, L.meta, L.spins, L.d_kU, L.d_kD,
                     L.d_dims, L.d_sizes, L.d_offs, L.d_coff, L.d_scratch};
@@ -439,7 +498,7 @@ vp_status vp_sample(vp_ctx* ctx, int32_t lat, int32_t n_burn, int32_t n_meas, do
   hipStream_t s = ctx->stream;
   const bool f64 = L->p.prec == VP_FP64;
   if (!L->lower_valid) {
-    if (f64) run_lower_pass<double>(*L, s); else run_lower_pass<float>(*L, s);
+    if (f64) run_lower_pass<double>(ctx, *L, s); else run_lower_pass<float>(ctx, *L, s);
     L->lower_valid = true;
   }
   SampleOut o{};
@@ -454,7 +513,7 @@ vp_status vp_sample(vp_ctx* ctx, int32_t lat, int32_t n_burn, int32_t n_meas, do
   for (int i = 0; i < n_burn + n_meas; ++i) {
     o.m = i - n_burn;
     const SampleOut* op = i >= n_burn ? &o : nullptr;
-    if (f64) run_sweep<double>(*L, op, s); else run_sweep<float>(*L, op, s);
+    if (f64) run_sweep<double>(ctx, *L, op, s); else run_sweep<float>(ctx, *L, op, s);
     HIP_TRY(ctx, hipGetLastError());
   }
   if (accept_dev) {
@@ -543,6 +602,21 @@ vp_status vp_sign_sgd_update(vp_ctx* ctx, int32_t lat, const double* grad_dev, d
   launch_sign_sgd(L->T, grad_dev, L->Np, step_len, ctx->seed, lat, step, ctx->stream);
   HIP_TRY(ctx, hipGetLastError());
   return stage_tensors(ctx, *L);
+}
+
+vp_status vp_timing_enable(vp_ctx* ctx, int32_t enable) {
+  if (!ctx) return fail(nullptr, VP_ERR_ARG, "null context");
+  fold_timing(ctx);
+  for (int i = 0; i < VP_NPHASE; ++i) { ctx->ph_ms[i] = 0.0; ctx->ph_n[i] = 0; }
+  ctx->timing = enable != 0;
+  return VP_OK;
+}
+
+vp_status vp_timing_read(vp_ctx* ctx, double* ms_host, int64_t* launches_host) {
+  if (!ctx || !ms_host || !launches_host) return fail(ctx, VP_ERR_ARG, "null argument");
+  fold_timing(ctx);
+  for (int i = 0; i < VP_NPHASE; ++i) { ms_host[i] = ctx->ph_ms[i]; launches_host[i] = ctx->ph_n[i]; }
+  return VP_OK;
 }
 
 vp_status vp_sync(vp_ctx* ctx) {
