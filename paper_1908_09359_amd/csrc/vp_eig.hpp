@@ -14,6 +14,8 @@ namespace vp {
 constexpr int EIG_NMAX = 128;
 constexpr int EIG_KMAX = 16;   // eigenvectors per inverse-iteration batch (one thread each)
 constexpr int EIG_PACK = EIG_NMAX * (EIG_NMAX + 1) / 2;
+// LDS the caller provides: packed matrix, inverse-iteration iterates, pivot flags
+constexpr size_t EIG_LDS_BYTES = sizeof(double) * (EIG_PACK + EIG_NMAX * EIG_KMAX) + EIG_NMAX * EIG_KMAX;
 
 __device__ inline int tri(int i) { return i * (i + 1) / 2; }
 
@@ -34,16 +36,17 @@ __device__ inline int sturm_count(const double* d, const double* e2, int n, doub
 // H: n x n symmetric, row-major (ld n), any address space; n <= EIG_NMAX.
 // Writes the eigenvectors of the k largest eigenvalues, in descending order,
 // as columns 0..k-1 of V (ld k) and the eigenvalues to lam[0..k-1].
-// refl: global scratch of at least EIG_PACK doubles (Householder vectors).
-__device__ void sym_topk_eig(const double* H, int n, int k, double* V, double* lam, double* refl) {
-  __shared__ double Ap[EIG_PACK];
+// refl: global scratch of at least EIG_PACK doubles (Householder vectors);
+// lds: EIG_LDS_BYTES of LDS owned by the caller.
+__device__ void sym_topk_eig(const double* H, int n, int k, double* V, double* lam, double* refl, char* lds) {
+  double* Ap = reinterpret_cast<double*>(lds);
+  double* Xs = Ap + EIG_PACK;
+  unsigned char* pivf = reinterpret_cast<unsigned char*>(Xs + EIG_NMAX * EIG_KMAX);
   __shared__ double dg[EIG_NMAX], eg[EIG_NMAX], e2[EIG_NMAX], tau[EIG_NMAX];
   __shared__ double pv[EIG_NMAX], wv[EIG_NMAX], vv[EIG_NMAX];
   __shared__ double probe_x[WG];
   __shared__ int probe_c[WG];
   __shared__ double lamb[EIG_KMAX];
-  __shared__ double Xs[EIG_NMAX * EIG_KMAX];
-  __shared__ unsigned char pivf[EIG_NMAX * EIG_KMAX];
   const int tid = threadIdx.x;
 
   for (int e = tid; e < n * n; e += WG) {
@@ -65,6 +68,7 @@ __device__ void sym_topk_eig(const double* H, int n, int k, double* V, double* l
       const double scal = 1.0 / (alpha - beta);
       for (int r = i + 2 + tid; r < n; r += WG) Ap[tri(r) + i] *= scal;
     }
+    __syncthreads();  // the loop below reads entries scaled by other threads
     // reflector i: v[i+1] = 1, v[r] = Ap[r][i] (r > i+1); also kept in global memory
     for (int r = i + 1 + tid; r < n; r += WG) {
       double v = (r == i + 1) ? 1.0 : Ap[tri(r) + i];

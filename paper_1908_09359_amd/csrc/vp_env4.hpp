@@ -1,0 +1,193 @@
+// Fused 2-row ("4-line") column step on MFMA, compile-time dimensions.
+//
+//   Lout[e][b][r1][r2] = sum Lin[c][a][l1][l2] A[a][u][b] t1[l1][u][r1][m]
+//                             t2[l2][m][r2][dd] B[c][dd][e]
+//
+// (environment layout: lower-boundary bond first).  The four pairwise
+// contractions run slice by slice -- one lower-boundary index c and a block
+// of BB upper-boundary indices b at a time -- so every intermediate stays in
+// LDS; the output accumulates in MFMA registers across the c slices.  Inputs
+// of arbitrary leg strides (mirrored or transposed views) are staged into LDS
+// in canonical order once per step.  TC is the MFMA type (float: 16x16x4 f32,
+// double: 16x16x4 f64), TB the storage type of the column tensors.
+#pragma once
+#include "vp_device.hpp"
+
+namespace vp {
+
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+typedef double v4d_t __attribute__((ext_vector_type(4)));
+
+template <typename TC> struct Mfma;
+template <> struct Mfma<float> {
+  typedef v4f_t acc_t;
+  __device__ static inline acc_t op(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // lane l holds D[4 (l/16) + r][l % 16]
+  __device__ static inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+template <> struct Mfma<double> {
+  typedef v4d_t acc_t;
+  __device__ static inline acc_t op(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // lane l holds D[(l/16) + 4 r][l % 16]
+  __device__ static inline int row(int lane, int r) { return (lane >> 4) + 4 * r; }
+};
+
+template <int D, int C>
+struct Env4Shape {
+  static constexpr int BB = (C % 4 == 0) ? C / 4 : ((C % 2 == 0) ? C / 2 : C);  // b-block
+  static constexpr int NBLK = C / BB;
+  static constexpr int SA = C * D * C, ST = D * D * D * D;
+  static constexpr int SL = C * D * D;            // one lower-bond slice of Lin
+  static constexpr int SX = D * D * D * BB;       // X1 / X2 / X3
+  static constexpr int N4 = BB * D * D;           // S4 columns per block
+  static constexpr int NT4 = (N4 + 15) / 16;      // S4 column tiles per block
+  static constexpr int T4W = (NT4 + 3) / 4;       // S4 tiles per wave per block
+  template <typename TC, typename TB, bool GRAM = false>
+  static constexpr size_t lds_bytes() {
+    return sizeof(TB) * (GRAM ? SA + ST : 2 * SA + 2 * ST) + sizeof(TC) * (SL + 2 * SX);
+  }
+};
+
+// One 16x16 output tile of a stage: acc += A(m0.., k) B(k, n0..) over K, with
+// the operand fetchers given as lambdas (i, k) -> value and (k, j) -> value.
+template <typename TC, int M, int N, int K, typename FA, typename FB>
+__device__ inline typename Mfma<TC>::acc_t mfma_tile(int m0, int n0, FA fa, FB fb) {
+  typename Mfma<TC>::acc_t acc = {0, 0, 0, 0};
+  const int lane = threadIdx.x & 63;
+  const int i = m0 + (lane & 15), j = n0 + (lane & 15), kq = lane >> 4;
+#pragma unroll
+  for (int k0 = 0; k0 < K; k0 += 4) {
+    const int k = k0 + kq;
+    TC a = (i < M && k < K) ? fa(i, k) : TC(0);
+    TC b = (j < N && k < K) ? fb(k, j) : TC(0);
+    acc = Mfma<TC>::op(a, b, acc);
+  }
+  return acc;
+}
+
+// Stage out[i][j] = sum_k A(i,k) B(k,j) into LDS (row-major, ld N), all waves.
+template <typename TC, int M, int N, int K, typename FA, typename FB>
+__device__ inline void mfma_stage(TC* out, FA fa, FB fb) {
+  constexpr int MT = (M + 15) / 16, NT = (N + 15) / 16;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int t = wave; t < MT * NT; t += 4) {
+    const int m0 = (t / NT) * 16, n0 = (t % NT) * 16;
+    auto acc = mfma_tile<TC, M, N, K>(m0, n0, fa, fb);
+    const int j = n0 + (lane & 15);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = m0 + Mfma<TC>::row(lane, r);
+      if (i < M && j < N) out[i * N + j] = acc[r];
+    }
+  }
+}
+
+// GRAM: t2 is the u<->d view of t1 and B is A (the Gram step of the boundary
+// compression); each is then staged once.
+template <typename TC, typename TB, int D, int C, bool GRAM = false>
+__device__ void env4_fused(TC* __restrict__ Lout, const TC* __restrict__ Lin, const TB* __restrict__ A, S3 sA,
+                           const TB* __restrict__ t1, S4 s1, const TB* __restrict__ t2, S4 s2,
+                           const TB* __restrict__ B, S3 sB, char* lds) {
+  using Sh = Env4Shape<D, C>;
+  constexpr int BB = Sh::BB, NBLK = Sh::NBLK, N4 = Sh::N4, NT4 = Sh::NT4, T4W = Sh::T4W;
+  TB* As = reinterpret_cast<TB*>(lds);
+  TB* Bs = GRAM ? As : As + Sh::SA;
+  TB* T1s = Bs + (GRAM ? 0 : Sh::SA) + (GRAM ? Sh::SA : 0);
+  TB* T2s = GRAM ? T1s : T1s + Sh::ST;
+  TC* Ls = reinterpret_cast<TC*>(T2s + Sh::ST);
+  TC* X1 = Ls + Sh::SL;  // X1 and X3
+  TC* X2 = X1 + Sh::SX;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+
+  // stage the column tensors in canonical leg order
+  for (int e = tid; e < Sh::SA; e += WG) {
+    const int p = e / (D * C), q = (e / C) % D, r = e % C;
+    As[e] = A[p * sA.s0 + q * sA.s1 + r * sA.s2];
+    if (!GRAM) Bs[e] = B[p * sB.s0 + q * sB.s1 + r * sB.s2];
+  }
+  for (int e = tid; e < Sh::ST; e += WG) {
+    const int l = e / (D * D * D), u = (e / (D * D)) % D, r = (e / D) % D, d = e % D;
+    T1s[e] = t1[l * s1.l + u * s1.u + r * s1.r + d * s1.d];
+    if (!GRAM) T2s[e] = t2[l * s2.l + u * s2.u + r * s2.r + d * s2.d];
+  }
+
+  typename Mfma<TC>::acc_t acc[NBLK][T4W];
+#pragma unroll
+  for (int q = 0; q < NBLK; ++q)
+#pragma unroll
+    for (int w = 0; w < T4W; ++w) acc[q][w] = {0, 0, 0, 0};
+
+  for (int cs = 0; cs < C; ++cs) {
+    __syncthreads();  // previous slice done with Ls / X buffers
+    for (int e = tid; e < Sh::SL; e += WG) Ls[e] = Lin[cs * Sh::SL + e];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NBLK; ++q) {
+      const int b0 = q * BB;
+      // S1: X1[(l1,l2)][(u,bb)] = sum_a Ls[a][(l1,l2)] As[a][u][b0+bb]
+      mfma_stage<TC, D * D, D * BB, C>(
+          X1, [&](int i, int k) { return Ls[k * D * D + i]; },
+          [&](int k, int j) { return (TC)As[k * D * C + (j / BB) * C + b0 + j % BB]; });
+      __syncthreads();
+      // S2: X2[(l2,bb)][(r1,m)] = sum_{l1,u} X1[l1][l2][u][bb] T1s[(l1,u)][(r1,m)]
+      mfma_stage<TC, D * BB, D * D, D * D>(
+          X2,
+          [&](int i, int k) {
+            return X1[(k / D) * D * D * BB + (i / BB) * D * BB + (k % D) * BB + i % BB];
+          },
+          [&](int k, int j) { return (TC)T1s[k * D * D + j]; });
+      __syncthreads();
+      // S3: X3[(bb,r1)][(r2,dd)] = sum_{l2,m} X2[l2][bb][r1][m] T2s[(l2,m)][(r2,dd)]
+      mfma_stage<TC, BB * D, D * D, D * D>(
+          X1,
+          [&](int i, int k) {
+            return X2[(((k / D) * BB + i / D) * D + i % D) * D + k % D];
+          },
+          [&](int k, int j) {
+            // GRAM: t2[l2][m][r2][dd] = t1[l2][dd][r2][m]
+            return GRAM ? (TC)T1s[(k / D) * D * D * D + (j % D) * D * D + (j / D) * D + k % D]
+                        : (TC)T2s[k * D * D + j];
+          });
+      __syncthreads();
+      // S4: acc[e][(bb,r1,r2)] += sum_dd Bs[cs][dd][e] X3[(bb,r1,r2)][dd]
+#pragma unroll
+      for (int w = 0; w < T4W; ++w) {
+        const int t = wave + 4 * w;
+        if (t < NT4) {
+          const int n0 = t * 16;
+          const int i = lane & 15, j = n0 + (lane & 15), kq = lane >> 4;
+#pragma unroll
+          for (int k0 = 0; k0 < D; k0 += 4) {
+            const int k = k0 + kq;
+            TC a = (i < C && k < D) ? (TC)Bs[cs * D * C + k * C + i] : TC(0);
+            TC b = (j < N4 && k < D) ? X1[j * D + k] : TC(0);
+            acc[q][w] = Mfma<TC>::op(a, b, acc[q][w]);
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // write Lout[e][b0 + (bb,r1,r2)]
+#pragma unroll
+  for (int q = 0; q < NBLK; ++q)
+#pragma unroll
+    for (int w = 0; w < T4W; ++w) {
+      const int t = wave + 4 * w;
+      if (t < NT4) {
+        const int j = t * 16 + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int e = Mfma<TC>::row(lane, r);
+          if (e < C && j < N4) Lout[e * (C * D * D) + q * N4 + j] = acc[q][w][r];
+        }
+      }
+    }
+  __syncthreads();
+}
+
+}  // namespace vp

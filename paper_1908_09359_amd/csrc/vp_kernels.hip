@@ -4,6 +4,7 @@
 // Metropolis pass, the boundary compression, or the measurement of a row.
 #include "vp_device.hpp"
 #include "vp_eig.hpp"
+#include "vp_env4.hpp"
 #include "vp_kernels.hpp"
 
 #include <math.h>
@@ -83,20 +84,30 @@ __device__ inline int step3(const LatDev& L, const Chain<T>& C, T* out, const T*
   return wg_renorm<T>(out, e3sz(L));
 }
 
+// LDS bytes a kernel provides for its 2-row column steps.
+template <typename TC, typename TB, int DD, int CC, bool GRAM = false>
+constexpr size_t env4_lds() {
+  if constexpr (DD > 0) return Env4Shape<DD, CC>::template lds_bytes<TC, TB, GRAM>();
+  else return 16;
+}
+
 // 4-line column step over rows y and y+1; flip1/flip2 select the flipped slot.
-template <typename T>
+// DD > 0 selects the fused MFMA step (environment layout [c][a][l1][l2]);
+// DD == 0 the generic strided-GEMM step (layout [a][l1][l2][c]).
+template <typename T, int DD, int CC>
 __device__ inline int step4(const LatDev& L, const Chain<T>& C, T* out, const T* in, int y, int x,
-                            int flip1, int flip2, const T* Ux, const T* Dx, bool right) {
+                            int flip1, int flip2, const T* Ux, const T* Dx, bool right, char* lds) {
   int k1 = y * L.Lx + x, k2 = (y + 1) * L.Lx + x;
   const T* t1 = tw<T>(L, k1, C.sp[k1] ^ flip1);
   const T* t2 = tw<T>(L, k2, C.sp[k2] ^ flip2);
   S4 st = st_std(L.d);
-  if (right)
-    env4_step<T, T>(out, in, Ux, sb_mirror(L.c, L.d), t1, st_mirror(st), t2, st_mirror(st), Dx,
-                 sb_mirror(L.c, L.d), C.ws + L.oX0, C.ws + L.oX1, L.c, L.d);
-  else
-    env4_step<T, T>(out, in, Ux, sb_std(L.c, L.d), t1, st, t2, st, Dx, sb_std(L.c, L.d),
-                 C.ws + L.oX0, C.ws + L.oX1, L.c, L.d);
+  const S3 sb = right ? sb_mirror(L.c, L.d) : sb_std(L.c, L.d);
+  const S4 s = right ? st_mirror(st) : st;
+  if constexpr (DD > 0) {
+    env4_fused<T, T, DD, CC>(out, in, Ux, sb, t1, s, t2, s, Dx, sb, lds);
+  } else {
+    env4_step<T, T>(out, in, Ux, sb, t1, s, t2, s, Dx, sb, C.ws + L.oX0, C.ws + L.oX1, L.c, L.d);
+  }
   return wg_renorm<T>(out, e4sz(L));
 }
 
@@ -244,8 +255,9 @@ __global__ void __launch_bounds__(WG) k_hsweep(LatDev L, int y, int last_row, in
 }
 
 // R4[x] for x = Lx-1 .. 1 of <D_{y+2}|M_{y+1} M_y|U_{y-1}>.
-template <typename T>
+template <typename T, int DD, int CC>
 __global__ void __launch_bounds__(WG) k_row4_right(LatDev L, int y) {
+  __shared__ __attribute__((aligned(16))) char lds[env4_lds<T, T, DD, CC>()];
   Chain<T> C = chain_of<T>(L, blockIdx.x);
   if (C.meta->flags) return;
   const int sz = e4sz(L);
@@ -254,16 +266,17 @@ __global__ void __launch_bounds__(WG) k_row4_right(LatDev L, int y) {
   set_unit<T>(R + (int64_t)L.Lx * sz, sz);
   if (threadIdx.x == 0) eR[L.Lx] = 0;
   for (int x = L.Lx - 1; x >= 1; --x) {
-    int e = step4<T>(L, C, R + (int64_t)x * sz, R + (int64_t)(x + 1) * sz, y, x, 0, 0,
-                     ub<T>(L, C, y, x), db<T>(L, C, y + 2, x), true);
+    int e = step4<T, DD, CC>(L, C, R + (int64_t)x * sz, R + (int64_t)(x + 1) * sz, y, x, 0, 0,
+                     ub<T>(L, C, y, x), db<T>(L, C, y + 2, x), true, lds);
     if (threadIdx.x == 0) eR[x] = eR[x + 1] + e;
     __syncthreads();
   }
 }
 
 // Vertical bonds between rows y and y+1, left to right.
-template <typename T>
+template <typename T, int DD, int CC>
 __global__ void __launch_bounds__(WG) k_vsweep(LatDev L, int y) {
+  __shared__ __attribute__((aligned(16))) char lds[env4_lds<T, T, DD, CC>()];
   Chain<T> C = chain_of<T>(L, blockIdx.x);
   if (C.meta->flags) return;
   const int sz = e4sz(L);
@@ -279,11 +292,11 @@ __global__ void __launch_bounds__(WG) k_vsweep(LatDev L, int y) {
     T* cur = tmp + slot[0] * sz;
     T* nxt = tmp + slot[1] * sz;
     if (x == L.Lx - 1 && !(C.sp[y * L.Lx + x] != C.sp[(y + 1) * L.Lx + x])) break;
-    int enxt = ecur + step4<T>(L, C, nxt, cur, y, x, 0, 0, Ux, Dx, false);
+    int enxt = ecur + step4<T, DD, CC>(L, C, nxt, cur, y, x, 0, 0, Ux, Dx, false, lds);
     const int k1 = y * L.Lx + x, k2 = (y + 1) * L.Lx + x;
     if (C.sp[k1] != C.sp[k2]) {
       T* f = tmp + slot[2] * sz;
-      int ef = ecur + step4<T>(L, C, f, cur, y, x, 1, 1, Ux, Dx, false);
+      int ef = ecur + step4<T, DD, CC>(L, C, f, cur, y, x, 1, 1, Ux, Dx, false, lds);
       double num = wg_dot<T>(f, R + (int64_t)(x + 1) * sz, sz);
       double den = wg_dot<T>(nxt, R + (int64_t)(x + 1) * sz, sz);
       int bond = y * (2 * L.Lx - 1) + (L.Lx - 1) + x;
@@ -318,8 +331,11 @@ __global__ void __launch_bounds__(WG) k_vsweep(LatDev L, int y) {
 // eigenvectors are the kept right singular vectors.  The output state is the
 // same; the sign and gauge of every site may differ.  All of it runs in float64
 // (the Gram matrices square the condition number of the left blocks).
-template <typename T>
+template <typename T, int DD, int CC>
 __global__ void __launch_bounds__(WG) k_compress(LatDev L, int y, int upper) {
+  constexpr size_t kGram = env4_lds<double, T, DD, CC, true>();
+  constexpr size_t kLds = kGram > EIG_LDS_BYTES ? kGram : EIG_LDS_BYTES;
+  __shared__ __attribute__((aligned(16))) char lds[kLds];
   Chain<T> C = chain_of<T>(L, blockIdx.x);
   if (C.meta->flags) return;
   double* cw = L.cws + (int64_t)blockIdx.x * L.cws_stride;
@@ -341,8 +357,12 @@ __global__ void __launch_bounds__(WG) k_compress(LatDev L, int y, int upper) {
   for (int j = 0; j < Lx - 1; ++j) {
     const int k = y * Lx + j;
     const T* t = tw<T>(L, k, C.sp[k]);
-    env4_step<double, T>(G + (int64_t)(j + 1) * gsz, G + (int64_t)j * gsz, A_in(j), sA, t, st, t, st2, A_in(j),
-                         sA, X0, X1, c, d);
+    if constexpr (DD > 0)
+      env4_fused<double, T, DD, CC, true>(G + (int64_t)(j + 1) * gsz, G + (int64_t)j * gsz, A_in(j), sA, t, st,
+                                          t, st2, A_in(j), sA, lds);
+    else
+      env4_step<double, T>(G + (int64_t)(j + 1) * gsz, G + (int64_t)j * gsz, A_in(j), sA, t, st, t, st2, A_in(j),
+                           sA, X0, X1, c, d);
     wg_renorm<double>(G + (int64_t)(j + 1) * gsz, gsz);
   }
   double* Ta = cw + L.cTa;
@@ -360,9 +380,9 @@ __global__ void __launch_bounds__(WG) k_compress(LatDev L, int y, int upper) {
     const int k = y * Lx + j;
     const T* t = tw<T>(L, k, C.sp[k]);
     compress_y<double, T>(Y, A_in(j), sA, t, st, Ta, X0, c, d);
-    // W = G_{j-1} Y with G stored [a][l][l'][a'] and viewed as ((a,l), (a',l'))
-    wg_gemm<double>(W, rowmajor(dc), G + (int64_t)j * gsz, view(d, d * d * c, d * c, d, 1, c), Y, rowmajor(dc),
-                    dc, dc, dc);
+    // W = G_{j-1} Y, G viewed as ((a,l), (a',l')); stored [a'][a][l][l'] (fused) or [a][l][l'][a']
+    const View gv = DD > 0 ? view(d, d * d, d, d, c * d * d, 1) : view(d, d * d * c, d * c, d, 1, c);
+    wg_gemm<double>(W, rowmajor(dc), G + (int64_t)j * gsz, gv, Y, rowmajor(dc), dc, dc, dc);
     // H = Y^T W
     wg_gemm<double>(H, rowmajor(dc), Y, colmajor(dc), W, rowmajor(dc), dc, dc, dc);
     const int p = upper ? L.dims[4 * k + 3] : L.dims[4 * k + 1];
@@ -374,7 +394,7 @@ __global__ void __launch_bounds__(WG) k_compress(LatDev L, int y, int upper) {
       Hc[i] = H[((a / kr) * c + a % kr) * dc + (b / kr) * c + b % kr];
     }
     __syncthreads();
-    sym_topk_eig(Hc, n, kl, Vk, cw + L.cLam, cw + L.cRefl);
+    sym_topk_eig(Hc, n, kl, Vk, cw + L.cLam, cw + L.cRefl, lds);
     // new site j: rows k' < kl are the kept eigenvectors, in descending order
     for (int i = threadIdx.x; i < ssz; i += WG) Vp[i] = 0.0;
     __syncthreads();
@@ -483,8 +503,9 @@ __global__ void __launch_bounds__(WG) k_measure3(LatDev L, int y, SampleOut o) {
 }
 
 // Vertical and diagonal pairs between rows y and y+1 (two-row network).
-template <typename T>
+template <typename T, int DD, int CC>
 __global__ void __launch_bounds__(WG) k_measure4(LatDev L, int y, SampleOut o) {
+  __shared__ __attribute__((aligned(16))) char lds[env4_lds<T, T, DD, CC>()];
   Chain<T> C = chain_of<T>(L, blockIdx.x);
   if (C.meta->flags) return;
   const int sz = e4sz(L), Lx = L.Lx;
@@ -498,14 +519,14 @@ __global__ void __launch_bounds__(WG) k_measure4(LatDev L, int y, SampleOut o) {
   if (threadIdx.x == 0) { eR[Lx] = 0; eL[0] = 0; }
   __syncthreads();
   for (int x = Lx - 1; x >= 1; --x) {
-    int e = step4<T>(L, C, R + (int64_t)x * sz, R + (int64_t)(x + 1) * sz, y, x, 0, 0, ub<T>(L, C, y, x),
-                     db<T>(L, C, y + 2, x), true);
+    int e = step4<T, DD, CC>(L, C, R + (int64_t)x * sz, R + (int64_t)(x + 1) * sz, y, x, 0, 0, ub<T>(L, C, y, x),
+                     db<T>(L, C, y + 2, x), true, lds);
     if (threadIdx.x == 0) eR[x] = eR[x + 1] + e;
     __syncthreads();
   }
   for (int x = 0; x < Lx; ++x) {
-    int e = step4<T>(L, C, Le + (int64_t)(x + 1) * sz, Le + (int64_t)x * sz, y, x, 0, 0, ub<T>(L, C, y, x),
-                     db<T>(L, C, y + 2, x), false);
+    int e = step4<T, DD, CC>(L, C, Le + (int64_t)(x + 1) * sz, Le + (int64_t)x * sz, y, x, 0, 0, ub<T>(L, C, y, x),
+                     db<T>(L, C, y + 2, x), false, lds);
     if (threadIdx.x == 0) eL[x + 1] = eL[x] + e;
     __syncthreads();
   }
@@ -520,7 +541,7 @@ __global__ void __launch_bounds__(WG) k_measure4(LatDev L, int y, SampleOut o) {
     if (C.sp[k1] == C.sp[k2]) {
       eacc += 0.25 * L.J1;
     } else {
-      int e1 = eL[x] + step4<T>(L, C, tmp, Le + (int64_t)x * sz, y, x, 1, 1, ub<T>(L, C, y, x), db<T>(L, C, y + 2, x), false);
+      int e1 = eL[x] + step4<T, DD, CC>(L, C, tmp, Le + (int64_t)x * sz, y, x, 1, 1, ub<T>(L, C, y, x), db<T>(L, C, y + 2, x), false, lds);
       double num = wg_dot<T>(tmp, R + (int64_t)(x + 1) * sz, sz);
       rho = ldexp(num / Nm, e1 + eR[x + 1] - eN);
       eacc += -0.25 * L.J1 + 0.5 * L.J1 * rho;
@@ -540,10 +561,10 @@ __global__ void __launch_bounds__(WG) k_measure4(LatDev L, int y, SampleOut o) {
         } else {
           // column x: flips (y,x) for which 0 and (y+1,x) for which 1; column x+1 the other site
           int f1a = which == 0 ? 1 : 0, f1b = which == 0 ? 0 : 1;
-          int e1 = eL[x] + step4<T>(L, C, tmp, Le + (int64_t)x * sz, y, x, f1a, f1b, ub<T>(L, C, y, x),
-                                    db<T>(L, C, y + 2, x), false);
-          int e2 = e1 + step4<T>(L, C, tmp + sz, tmp, y, x + 1, 1 - f1a, 1 - f1b, ub<T>(L, C, y, x + 1),
-                                 db<T>(L, C, y + 2, x + 1), false);
+          int e1 = eL[x] + step4<T, DD, CC>(L, C, tmp, Le + (int64_t)x * sz, y, x, f1a, f1b, ub<T>(L, C, y, x),
+                                    db<T>(L, C, y + 2, x), false, lds);
+          int e2 = e1 + step4<T, DD, CC>(L, C, tmp + sz, tmp, y, x + 1, 1 - f1a, 1 - f1b, ub<T>(L, C, y, x + 1),
+                                 db<T>(L, C, y + 2, x + 1), false, lds);
           double num = wg_dot<T>(tmp + sz, R + (int64_t)(x + 2) * sz, sz);
           rho = ldexp(num / Nm, e2 + eR[x + 2] - eN);
           eacc += -0.25 * L.J2 + 0.5 * L.J2 * rho;
@@ -692,17 +713,30 @@ template <typename T>
 void launch_psi_fixed(const LatDev& L, hipStream_t s) {
   hipLaunchKernelGGL(k_hsweep<T>, dim3(L.n_chains), dim3(WG), 0, s, L, L.Ly - 1, 1, 0);
 }
+// Compile-time (D, Dc) instantiations of the fused 2-row step; other shapes run the generic path.
+#define VP_DISPATCH_DC(KERNEL, T, ...)                                                                 \
+  do {                                                                                                 \
+    if (L.d == 8 && L.c == 16)                                                                         \
+      hipLaunchKernelGGL((KERNEL<T, 8, 16>), dim3(L.n_chains), dim3(WG), 0, s, __VA_ARGS__);           \
+    else if (L.d == 6 && L.c == 12)                                                                    \
+      hipLaunchKernelGGL((KERNEL<T, 6, 12>), dim3(L.n_chains), dim3(WG), 0, s, __VA_ARGS__);           \
+    else if (L.d == 4 && L.c == 8)                                                                     \
+      hipLaunchKernelGGL((KERNEL<T, 4, 8>), dim3(L.n_chains), dim3(WG), 0, s, __VA_ARGS__);            \
+    else                                                                                               \
+      hipLaunchKernelGGL((KERNEL<T, 0, 0>), dim3(L.n_chains), dim3(WG), 0, s, __VA_ARGS__);            \
+  } while (0)
+
 template <typename T>
 void launch_row4_right(const LatDev& L, int y, hipStream_t s) {
-  hipLaunchKernelGGL(k_row4_right<T>, dim3(L.n_chains), dim3(WG), 0, s, L, y);
+  VP_DISPATCH_DC(k_row4_right, T, L, y);
 }
 template <typename T>
 void launch_vsweep(const LatDev& L, int y, hipStream_t s) {
-  hipLaunchKernelGGL(k_vsweep<T>, dim3(L.n_chains), dim3(WG), 0, s, L, y);
+  VP_DISPATCH_DC(k_vsweep, T, L, y);
 }
 template <typename T>
 void launch_compress(const LatDev& L, int y, int upper, hipStream_t s) {
-  hipLaunchKernelGGL(k_compress<T>, dim3(L.n_chains), dim3(WG), 0, s, L, y, upper);
+  VP_DISPATCH_DC(k_compress, T, L, y, upper);
 }
 template <typename T>
 void launch_measure3(const LatDev& L, int y, const SampleOut& o, hipStream_t s) {
@@ -710,7 +744,7 @@ void launch_measure3(const LatDev& L, int y, const SampleOut& o, hipStream_t s) 
 }
 template <typename T>
 void launch_measure4(const LatDev& L, int y, const SampleOut& o, hipStream_t s) {
-  hipLaunchKernelGGL(k_measure4<T>, dim3(L.n_chains), dim3(WG), 0, s, L, y, o);
+  VP_DISPATCH_DC(k_measure4, T, L, y, o);
 }
 void launch_begin_sample(const LatDev& L, hipStream_t s) {
   hipLaunchKernelGGL(k_begin_sample, dim3((L.n_chains + WG - 1) / WG), dim3(WG), 0, s, L);

@@ -38,6 +38,10 @@ def _compare(g, o, N, tol_e, tol_lp, tol_rel):
     (6, 6, 3, 7, 0.5, 3),     # ragged GEMM tiles (D*Dc = 21, Dc^2*D = 147)
     (2, 6, 2, 3, 0.0, 3),     # two rows: no bulk row
     (1, 4, 3, 2, 0.0, 2),     # a single row: no vertical pairs
+    (6, 6, 4, 8, 0.5, 2),     # fused MFMA 2-row step, D=4 Dc=8
+    (4, 4, 6, 12, 0.0, 2),    # fused MFMA 2-row step, D=6 Dc=12 (padded 16x16 tiles)
+    (4, 4, 8, 16, 0.5, 2),    # fused MFMA 2-row step, D=8 Dc=16
+    (2, 4, 8, 16, 0.0, 2),
 ])
 def test_eval_fp64_parity(Ly, Lx, D, Dc, J2, ncfg):
     B = _B()
@@ -59,6 +63,34 @@ def test_eval_fp32_parity_8x8():
     assert np.array_equal(g["sign"], o["sign"])
     assert np.max(np.abs(g["e_loc"] - o["e_loc"])) / 64 <= 1e-4
     assert np.max(np.abs(g["log_abs_psi"] - o["log_abs_psi"])) <= 1e-3
+
+
+@pytest.mark.parametrize("Ly,Lx,D,Dc,J2", [(4, 4, 8, 16, 0.5), (6, 6, 4, 8, 0.0), (4, 6, 6, 12, 0.5)])
+def test_eval_fp32_parity_fused_shapes(Ly, Lx, D, Dc, J2):
+    B = _B()
+    print(f"eval fp32 {Ly}x{Lx} D={D} Dc={Dc} J2={J2}", flush=True)
+    T = W.random_tensors(Ly, Lx, D, seed=21)
+    cfgs = W.random_configs(Ly, Lx, 3, seed=22)
+    g = H.gpu_eval(Ly, Lx, D, Dc, J2, B.VP_FP32, T, cfgs)
+    o = H.oracle_eval(Ly, Lx, D, Dc, J2, T, cfgs)
+    assert np.array_equal(g["sign"], o["sign"])
+    assert np.max(np.abs(g["e_loc"] - o["e_loc"])) / (Ly * Lx) <= 1e-4
+    assert np.max(np.abs(g["log_abs_psi"] - o["log_abs_psi"])) <= 1e-3
+
+
+def test_sampler_fp64_bit_exact_fused_shape():
+    """Chains on the fused 2-row path (D=4, Dc=8): decisions bit-exact against the oracle."""
+    B = _B()
+    print("sample fp64 6x6 D=4 Dc=8 3 chains 1+2", flush=True)
+    T = W.random_tensors(6, 6, 4, seed=88)
+    lat = olat.Lattice(6, 6, 4, 8)
+    g = _gpu_sample(6, 6, 4, 8, 0.0, B.VP_FP64, T, 3, 1, 2, seed=41)
+    for c in range(3):
+        ch = vmc.Chain(lat, olat.neel_shuffled(lat, 41, 0, c), 41, 0, c)
+        o = vmc.run_chain(T, lat, ch, 1, 2)
+        assert np.array_equal(g["spins"][c], np.stack([x["spins"] for x in o])), c
+        assert np.max(np.abs(g["e_loc"][c] - np.array([x["e_loc"] for x in o]))) / 36 <= 1e-10
+        assert tuple(g["accept"][c]) == (ch.accepted, ch.proposed)
 
 
 def test_eval_more_chains_than_configs():
