@@ -72,24 +72,38 @@ __device__ inline char* gemm_tiles() {
   return buf;
 }
 
-// C(i,j) = sum_k A(i,k) B(k,j) for i < M, j < N, accumulated in TC.  All
-// threads of the work-group must call it; C is complete after the trailing
-// barrier.
+typedef float v4f_g __attribute__((ext_vector_type(4)));
+typedef double v4d_g __attribute__((ext_vector_type(4)));
+
+// 16x16x4 MFMA in the accumulation type; lane l holds output rows
+// 4 (l/16) + r (f32) or (l/16) + 4 r (f64) of column l % 16.
+__device__ inline v4f_g mfma4(float a, float b, v4f_g c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+__device__ inline v4d_g mfma4(double a, double b, v4d_g c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+__device__ inline int mfma4_row(float, int lane, int r) { return 4 * (lane >> 4) + r; }
+__device__ inline int mfma4_row(double, int lane, int r) { return (lane >> 4) + 4 * r; }
+template <typename T> struct Acc4;
+template <> struct Acc4<float> { typedef v4f_g type; };
+template <> struct Acc4<double> { typedef v4d_g type; };
+
+// C(i,j) = sum_k A(i,k) B(k,j) for i < M, j < N, accumulated in TC on MFMA.
+// 64x64 output blocks, K staged through LDS 16 at a time; each wave owns a
+// 2x2 set of 16x16 tiles.  All threads of the work-group must call it; C is
+// complete after the trailing barrier.
 template <typename TC, typename TA, typename TB>
 __device__ void wg_gemm(TC* __restrict__ C, View vc, const TA* __restrict__ A, View va,
                         const TB* __restrict__ B, View vb, int M, int N, int K) {
   constexpr int BM = 64, BN = 64, BK = 16;
   TC (*As)[BM + 1] = reinterpret_cast<TC (*)[BM + 1]>(gemm_tiles());
   TC (*Bs)[BN + 1] = reinterpret_cast<TC (*)[BN + 1]>(gemm_tiles() + BK * (BM + 1) * sizeof(TC));
-  const int tid = threadIdx.x;
-  const int tr = tid >> 4, tc = tid & 15;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tr0 = (wave >> 1) * 32, tc0 = (wave & 1) * 32;  // this wave's 32x32 corner
   for (int m0 = 0; m0 < M; m0 += BM) {
     for (int n0 = 0; n0 < N; n0 += BN) {
-      TC acc[4][4];
+      typename Acc4<TC>::type acc[2][2];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = TC(0);
+        for (int b = 0; b < 2; ++b) acc[a][b] = {0, 0, 0, 0};
       for (int k0 = 0; k0 < K; k0 += BK) {
 #pragma unroll
         for (int e = 0; e < (BM * BK) / WG; ++e) {
@@ -107,29 +121,29 @@ __device__ void wg_gemm(TC* __restrict__ C, View vc, const TA* __restrict__ A, V
         }
         __syncthreads();
 #pragma unroll
-        for (int kk = 0; kk < BK; ++kk) {
-          TC a[4], b[4];
-#pragma unroll
-          for (int i = 0; i < 4; ++i) a[i] = As[kk][tr * 4 + i];
-#pragma unroll
-          for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tc * 4 + j];
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+        for (int kk = 0; kk < BK; kk += 4) {
+          const int k = kk + (lane >> 4);
+          TC a0 = As[k][tr0 + (lane & 15)], a1 = As[k][tr0 + 16 + (lane & 15)];
+          TC b0 = Bs[k][tc0 + (lane & 15)], b1 = Bs[k][tc0 + 16 + (lane & 15)];
+          acc[0][0] = mfma4(a0, b0, acc[0][0]);
+          acc[0][1] = mfma4(a0, b1, acc[0][1]);
+          acc[1][0] = mfma4(a1, b0, acc[1][0]);
+          acc[1][1] = mfma4(a1, b1, acc[1][1]);
         }
         __syncthreads();
       }
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        int m = m0 + tr * 4 + i;
-        if (m >= M) continue;
+      for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          int n = n0 + tc * 4 + j;
-          if (n < N) C[vaddr(vc, m, n)] = acc[i][j];
+        for (int b = 0; b < 2; ++b) {
+          const int n = n0 + tc0 + 16 * b + (lane & 15);
+          if (n >= N) continue;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int m = m0 + tr0 + 16 * a + mfma4_row(TC(0), lane, r);
+            if (m < M) C[vaddr(vc, m, n)] = acc[a][b][r];
+          }
         }
-      }
     }
   }
   __syncthreads();
@@ -138,28 +152,26 @@ __device__ void wg_gemm(TC* __restrict__ C, View vc, const TA* __restrict__ A, V
 // ---------------------------------------------------------------------------
 // Work-group reductions (fixed order: per-thread partials, then a tree).
 // ---------------------------------------------------------------------------
+// Wavefront shuffle reduction, then the four wave partials through LDS in a
+// fixed order (two barriers).
 __device__ inline double wg_sum(double v) {
-  __shared__ double red[WG];
-  red[threadIdx.x] = v;
+  __shared__ double red[WG / 64];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int s = WG / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
-    __syncthreads();
-  }
-  double r = red[0];
+  double r = (red[0] + red[1]) + (red[2] + red[3]);
   __syncthreads();
   return r;
 }
 
 __device__ inline double wg_max(double v) {
-  __shared__ double red[WG];
-  red[threadIdx.x] = v;
+  __shared__ double red[WG / 64];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int s = WG / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
-    __syncthreads();
-  }
-  double r = red[0];
+  double r = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
   __syncthreads();
   return r;
 }

@@ -44,6 +44,7 @@ __device__ void sym_topk_eig(const double* H, int n, int k, double* V, double* l
   unsigned char* pivf = reinterpret_cast<unsigned char*>(Xs + EIG_NMAX * EIG_KMAX);
   __shared__ double dg[EIG_NMAX], eg[EIG_NMAX], e2[EIG_NMAX], tau[EIG_NMAX];
   __shared__ double pv[EIG_NMAX], wv[EIG_NMAX], vv[EIG_NMAX];
+  __shared__ double pv2[2][EIG_NMAX];
   __shared__ double probe_x[WG];
   __shared__ int probe_c[WG];
   __shared__ double lamb[EIG_KMAX];
@@ -78,25 +79,36 @@ __device__ void sym_topk_eig(const double* H, int n, int k, double* V, double* l
     if (tid == 0) { dg[i] = Ap[tri(i) + i]; eg[i] = beta; tau[i] = t; }
     __syncthreads();
     if (t != 0.0) {
-      // p = t * A22 v over rows/cols i+1..n-1
-      for (int r = i + 1 + tid; r < n; r += WG) {
+      // p = t * A22 v over rows/cols i+1..n-1: two threads per row (interleaved columns)
+      {
+        const int r = i + 1 + (tid >> 1), h = tid & 1;
         double acc = 0.0;
-        for (int s = i + 1; s <= r; ++s) acc += Ap[tri(r) + s] * vv[s];
-        for (int s = r + 1; s < n; ++s) acc += Ap[tri(s) + r] * vv[s];
-        pv[r] = t * acc;
+        if (r < n) {
+          const int trr = tri(r);
+#pragma unroll 8
+          for (int s = i + 1 + h; s < n; s += 2) acc += (s <= r ? Ap[trr + s] : Ap[tri(s) + r]) * vv[s];
+          pv2[h][r] = acc;
+        }
       }
       __syncthreads();
       double pw = 0.0;
-      for (int r = i + 1 + tid; r < n; r += WG) pw += pv[r] * vv[r];
+      for (int r = i + 1 + tid; r < n; r += WG) {
+        const double p = t * (pv2[0][r] + pv2[1][r]);
+        pv[r] = p;
+        pw += p * vv[r];
+      }
       const double K = -0.5 * t * wg_sum(pw);
       for (int r = i + 1 + tid; r < n; r += WG) wv[r] = pv[r] + K * vv[r];
       __syncthreads();
-      const int m = n - i - 1;
-      for (int e = tid; e < m * m; e += WG) {
-        int rr = e / m, ss = e - rr * m;
-        if (ss > rr) continue;
-        int r = i + 1 + rr, s = i + 1 + ss;
-        Ap[tri(r) + s] -= vv[r] * wv[s] + wv[r] * vv[s];
+      // A22 -= v w^T + w v^T on the lower triangle, two threads per row
+      {
+        const int r = i + 1 + (tid >> 1), h = tid & 1;
+        if (r < n) {
+          const int trr = tri(r);
+          const double vr = vv[r], wr = wv[r];
+#pragma unroll 8
+          for (int s = i + 1 + h; s <= r; s += 2) Ap[trr + s] -= vr * wv[s] + wr * vv[s];
+        }
       }
       __syncthreads();
     }
@@ -138,7 +150,7 @@ __device__ void sym_topk_eig(const double* H, int n, int k, double* V, double* l
     const int t = b0 + g;
     const int q = n - 1 - t;            // ascending index
     double a = lo, c = hi;
-    for (int it = 0; it < 16; ++it) {
+    for (int it = 0; it < 13; ++it) {  // 17^13 > 2^52
       double x = a + (c - a) * (double)(lane + 1) / 17.0;
       int cnt = (g < kb) ? sturm_count(dg, e2, n, x, pivmin) : 0;
       probe_x[tid] = x;
@@ -179,20 +191,20 @@ __device__ void sym_topk_eig(const double* H, int n, int k, double* V, double* l
         if (fabs(aa) >= fabs(bb)) {
           const double piv = fabs(aa) < tiny ? (aa < 0.0 ? -tiny : tiny) : aa;
           const double m = bb / piv;
-          U0[IX(j)] = piv; U1[IX(j)] = cc; U2[IX(j)] = 0.0; ML[IX(j)] = m;
+          U0[IX(j)] = 1.0 / piv; U1[IX(j)] = cc; U2[IX(j)] = 0.0; ML[IX(j)] = m;
           pivf[IX(j)] = 0;
           aa = a1 - m * cc;
           cc = c1;
         } else {
           const double m = aa / bb;
-          U0[IX(j)] = bb; U1[IX(j)] = a1; U2[IX(j)] = c1; ML[IX(j)] = m;
+          U0[IX(j)] = 1.0 / bb; U1[IX(j)] = a1; U2[IX(j)] = c1; ML[IX(j)] = m;
           pivf[IX(j)] = 1;
           const double naa = cc - m * a1;
           cc = -m * c1;
           aa = naa;
         }
       }
-      U0[IX(n - 1)] = fabs(aa) < tiny ? (aa < 0.0 ? -tiny : tiny) : aa;
+      U0[IX(n - 1)] = 1.0 / (fabs(aa) < tiny ? (aa < 0.0 ? -tiny : tiny) : aa);
       // deterministic, eigenvector-dependent start vector
       for (int j = 0; j < n; ++j) {
         uint64_t h = (uint64_t)(j + 1) * 0x9E3779B97F4A7C15ull ^ (uint64_t)(col + 1) * 0xD2E7470EE14C6C93ull;
@@ -208,7 +220,7 @@ __device__ void sym_topk_eig(const double* H, int n, int k, double* V, double* l
         }
         double x1 = 0.0, x2 = 0.0, nrm = 0.0;
         for (int j = n - 1; j >= 0; --j) {
-          const double xj = (Xs[IX(j)] - U1[IX(j)] * x1 - U2[IX(j)] * x2) / U0[IX(j)];
+          const double xj = (Xs[IX(j)] - U1[IX(j)] * x1 - U2[IX(j)] * x2) * U0[IX(j)];  // U0 holds 1/pivot
           Xs[IX(j)] = xj;
           x2 = x1;
           x1 = xj;
@@ -217,62 +229,94 @@ __device__ void sym_topk_eig(const double* H, int n, int k, double* V, double* l
         const double inv = nrm > 0.0 ? 1.0 / nrm : 1.0;
         for (int j = 0; j < n; ++j) Xs[IX(j)] *= inv;
       }
-    }
-    __syncthreads();
-    for (int e = tid; e < n * kb; e += WG) {
-      int j = e / kb, tt = e - j * kb;
-      V[(int64_t)j * k + b0 + tt] = Xs[j * EIG_KMAX + tt];
-    }
 #undef IX
+    }
     __syncthreads();
     if (tid < kb) lam[b0 + tid] = lamb[tid];
+    if (k > EIG_KMAX) {
+      // more than one batch: park this batch in V (global) and finish there
+      for (int e = tid; e < n * kb; e += WG) {
+        int j = e / kb, tt = e - j * kb;
+        V[(int64_t)j * k + b0 + tt] = Xs[j * EIG_KMAX + tt];
+      }
+    }
     __syncthreads();
   }
 
-  // ---- modified Gram-Schmidt over the kept vectors (descending order)
-  for (int col = 0; col < k; ++col) {
-    for (int s = 0; s < col; ++s) {
-      double dp = 0.0;
-      for (int j = tid; j < n; j += WG) dp += V[(int64_t)j * k + s] * V[(int64_t)j * k + col];
-      dp = wg_sum(dp);
-      for (int j = tid; j < n; j += WG) V[(int64_t)j * k + col] -= dp * V[(int64_t)j * k + s];
+  // Vectors live in LDS (Xs, [j][t]) when k <= EIG_KMAX, else in V.
+  const bool in_lds = k <= EIG_KMAX;
+  const int ld = in_lds ? EIG_KMAX : k;
+  double* Vw = in_lds ? Xs : V;
+
+  // ---- classical Gram-Schmidt, twice, over the kept vectors in descending order
+  for (int col = 1; col < k; ++col) {
+    for (int pass = 0; pass < 2; ++pass) {
+      // dots with every earlier vector: 16 lanes per earlier vector
+      for (int s0 = 0; s0 < col; s0 += WG / 16) {
+        const int sv = s0 + (tid >> 4);
+        double dp = 0.0;
+        if (sv < col)
+          for (int j = tid & 15; j < n; j += 16) dp += Vw[j * ld + sv] * Vw[j * ld + col];
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) dp += __shfl_xor(dp, o, 16);
+        if ((tid & 15) == 0 && sv < col) pv[sv] = dp;
+      }
+      __syncthreads();
+      for (int j = tid; j < n; j += WG) {
+        double x = Vw[j * ld + col];
+        for (int sv = 0; sv < col; ++sv) x -= pv[sv] * Vw[j * ld + sv];
+        Vw[j * ld + col] = x;
+      }
       __syncthreads();
     }
-    double nn = 0.0;
-    for (int j = tid; j < n; j += WG) nn += V[(int64_t)j * k + col] * V[(int64_t)j * k + col];
-    nn = wg_sum(nn);
-    double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
-    for (int j = tid; j < n; j += WG) V[(int64_t)j * k + col] *= inv;
-    __syncthreads();
   }
+  for (int c0 = 0; c0 < k; c0 += WG / 16) {
+    const int col = c0 + (tid >> 4);
+    double nn = 0.0;
+    if (col < k)
+      for (int j = tid & 15; j < n; j += 16) nn += Vw[j * ld + col] * Vw[j * ld + col];
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) nn += __shfl_xor(nn, o, 16);
+    if ((tid & 15) == 0 && col < k) pv[col] = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < n * k; e += WG) {
+    const int j = e / k, col = e - j * k;
+    Vw[j * ld + col] *= pv[col];
+  }
+  __syncthreads();
 
-  // ---- back-transformation: x <- H_0 H_1 ... H_{n-3} x
+  // ---- back-transformation: x <- H_0 H_1 ... H_{n-3} x, reflectors reloaded into LDS (Ap is free)
+  for (int e = tid; e < tri(n); e += WG) Ap[e] = refl[e];
+  __syncthreads();
   for (int i = n - 3; i >= 0; --i) {
     const double t = tau[i];
     if (t == 0.0) continue;
-    for (int r = i + 1 + tid; r < n; r += WG) vv[r] = refl[tri(r) + i];
+    for (int r = i + 1 + tid; r < n; r += WG) vv[r] = Ap[tri(r) + i];
     __syncthreads();
-    // dots for every kept vector: 16 threads per vector
     for (int c0 = 0; c0 < k; c0 += WG / 16) {
-      const int col = c0 + (tid >> 4), lane = tid & 15;
+      const int col = c0 + (tid >> 4);
       double dp = 0.0;
       if (col < k)
-        for (int r = i + 1 + lane; r < n; r += 16) dp += vv[r] * V[(int64_t)r * k + col];
-      probe_x[tid] = dp;
-      __syncthreads();
-      if (col < k && lane == 0) {
-        double s = 0.0;
-        for (int q2 = 0; q2 < 16; ++q2) s += probe_x[tid + q2];
-        pv[col - c0] = s;
-      }
-      __syncthreads();
-      for (int e = tid; e < (n - i - 1) * (WG / 16); e += WG) {
-        int cc = e / (n - i - 1), r = i + 1 + (e - cc * (n - i - 1));
-        int col2 = c0 + cc;
-        if (col2 < k) V[(int64_t)r * k + col2] -= t * pv[cc] * vv[r];
-      }
-      __syncthreads();
+        for (int r = i + 1 + (tid & 15); r < n; r += 16) dp += vv[r] * Vw[r * ld + col];
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) dp += __shfl_xor(dp, o, 16);
+      if ((tid & 15) == 0 && col < k) pv[col] = t * dp;
     }
+    __syncthreads();
+    for (int e = tid; e < (n - i - 1) * k; e += WG) {
+      const int rr = e / k, col = e - rr * k;
+      const int r = i + 1 + rr;
+      Vw[r * ld + col] -= pv[col] * vv[r];
+    }
+    __syncthreads();
+  }
+  if (in_lds) {
+    for (int e = tid; e < n * k; e += WG) {
+      const int j = e / k, col = e - j * k;
+      V[(int64_t)j * k + col] = Xs[j * EIG_KMAX + col];
+    }
+    __syncthreads();
   }
 }
 
