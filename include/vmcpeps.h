@@ -131,8 +131,12 @@ vp_status vp_gradient(vp_ctx* ctx, int32_t lat, const double* e_loc_dev, const v
                       const int8_t* spins_dev, int64_t n_samples, double* grad_dev, double* e_mean_dev);
 
 /* Stochastic reconfiguration: (S + shift I) delta = g with S the covariance of
- * the full-layout log-derivatives, solved in float64 by Cholesky; then
- * T <- T - lr * delta.  delta_dev [Np] may be NULL.  Needs Np <= 32768. */
+ * the full-layout log-derivatives and g the Eq. (5) gradient, solved in float64
+ * by a blocked Cholesky factorisation on the device; then T <- T - lr * delta.
+ * delta_dev [Np] may be NULL.  Needs Np <= 32768 and n_samples * Np < 2^31;
+ * allocates (8 Np^2 + 8 n_samples Np) bytes of workspace for the call and
+ * waits for completion.  VP_ERR_NONFINITE if S + shift I is not numerically
+ * positive definite. */
 vp_status vp_sr_update(vp_ctx* ctx, int32_t lat, const double* e_loc_dev, const void* dlnpsi_dev,
                        const int8_t* spins_dev, int64_t n_samples, double shift, double lr,
                        double* delta_dev);
@@ -140,6 +144,17 @@ vp_status vp_sr_update(vp_ctx* ctx, int32_t lat, const double* e_loc_dev, const 
 /* Eq. (10): T <- T - r * step_len * sgn(grad), r = uniform from counter
  * (p, step, 0, 5) per element p. */
 vp_status vp_sign_sgd_update(vp_ctx* ctx, int32_t lat, const double* grad_dev, double step_len, uint64_t step);
+
+/* Integrated autocorrelation time of each chain's measurement series with
+ * Sokal's automatic window (Madras & Sokal, J. Stat. Phys. 50, 1988): rho(t)
+ * is the normalised autocovariance of the chain, tau(M) = 1/2 + sum_{t=1..M}
+ * rho(t), and M is the smallest window with M >= c tau(M).  series_host is
+ * [n_chains][len] (host memory); tau_host receives [n_chains].  mean_out is
+ * the mean over all samples; stderr_out the standard error of that mean,
+ * sqrt(sum_chains var_c 2 tau_c / len) / n_chains.  Host-only, synchronous.
+ * Returns VP_ERR_ARG for len < 2 or c <= 0. */
+vp_status vp_stats_tau(const double* series_host, int32_t n_chains, int32_t len, double c, double* tau_host,
+                       double* mean_out, double* stderr_out);
 
 /* Wait for the context's stream; report device-side error flags. */
 vp_status vp_sync(vp_ctx* ctx);

@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "VP_OK", 1: "VP_ERR_ARG", 2: "VP_ERR_SHAPE", 3: "VP_ERR_OOM",
 EXPORTED = ["vp_create", "vp_destroy", "vp_last_error", "vp_num_params", "vp_workspace_bytes",
             "vp_set_tensors", "vp_get_tensors", "vp_init_tensors", "vp_init_chains", "vp_sample",
             "vp_eval", "vp_gradient", "vp_sr_update", "vp_sign_sgd_update", "vp_sync",
-            "vp_timing_enable", "vp_timing_read"]
+            "vp_timing_enable", "vp_timing_read", "vp_stats_tau"]
 
 PHASES = ["row3_envs", "hsweep", "row4_envs", "vsweep", "compress_up", "compress_down", "measure3",
           "measure4", "other"]
@@ -65,6 +65,7 @@ def _load():
         "vp_sync": ([P], I32),
         "vp_timing_enable": ([P, I32], I32),
         "vp_timing_read": ([P, P, P], I32),
+        "vp_stats_tau": ([P, I32, I32, D, P, P, P], I32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -90,6 +91,21 @@ def vp_num_params(lat):
 
 def vp_workspace_bytes(lat):
     return int(LIB.vp_workspace_bytes(ctypes.byref(lat)))
+
+
+def vp_stats_tau(series, c=5.0):
+    """Per-chain tau_int, mean and tau-corrected standard error of a [n_chains][len] float64 array."""
+    import numpy as np
+    x = np.ascontiguousarray(series, dtype=np.float64)
+    if x.ndim != 2:
+        raise ValueError("series must be [n_chains][len]")
+    tau = np.empty(x.shape[0])
+    mean, err = ctypes.c_double(), ctypes.c_double()
+    st = LIB.vp_stats_tau(x.ctypes.data_as(ctypes.c_void_p), x.shape[0], x.shape[1], c,
+                          tau.ctypes.data_as(ctypes.c_void_p), ctypes.byref(mean), ctypes.byref(err))
+    if st != VP_OK:
+        raise VPError(st, LIB.vp_last_error(None).decode())
+    return tau, mean.value, err.value
 
 
 class Context:

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -590,10 +591,34 @@ vp_status vp_gradient(vp_ctx* ctx, int32_t lat, const double* e_loc_dev, const v
   return VP_OK;
 }
 
-vp_status vp_sr_update(vp_ctx* ctx, int32_t lat, const double*, const void*, const int8_t*, int64_t, double,
-                       double, double*) {
-  if (!get_lat(ctx, lat)) return fail(ctx, VP_ERR_ARG, "bad lattice index");
-  return fail(ctx, VP_ERR_UNSUPPORTED, "vp_sr_update is not built yet");
+vp_status vp_sr_update(vp_ctx* ctx, int32_t lat, const double* e_loc_dev, const void* dlnpsi_dev,
+                       const int8_t* spins_dev, int64_t n_samples, double shift, double lr, double* delta_dev) {
+  Lattice* L = get_lat(ctx, lat);
+  if (!L || !e_loc_dev || !dlnpsi_dev || !spins_dev) return fail(ctx, VP_ERR_ARG, "bad lattice index or null pointer");
+  if (n_samples < 2) return fail(ctx, VP_ERR_ARG, "n_samples must be >= 2");
+  if (!(shift >= 0.0)) return fail(ctx, VP_ERR_ARG, "shift must be >= 0");
+  if (L->Np > 32768) return fail(ctx, VP_ERR_SHAPE, "the dense S matrix needs Np <= 32768 (Np = %lld)", (long long)L->Np);
+  if (n_samples * L->Np >= (int64_t)1 << 31) return fail(ctx, VP_ERR_SHAPE, "n_samples * Np must stay below 2^31");
+  // the factorisation workspace is allocated for the call and released afterwards
+  double* work = nullptr;
+  int* flag = nullptr;
+  const int64_t nd = sr_work_doubles(L->Np, n_samples);
+  if (hipMalloc((void**)&work, sizeof(double) * nd) != hipSuccess) return fail(ctx, VP_ERR_OOM, "SR workspace");
+  if (hipMalloc((void**)&flag, sizeof(int)) != hipSuccess) { hipFree(work); return fail(ctx, VP_ERR_OOM, "SR flag"); }
+  hipMemsetAsync(flag, 0, sizeof(int), ctx->stream);
+  int rc = L->p.prec == VP_FP64
+               ? launch_sr<double>(L->d_offs, L->d_coff, L->d_sizes, L->N, L->Np, e_loc_dev, (const double*)dlnpsi_dev,
+                                   spins_dev, n_samples, shift, lr, L->T, delta_dev, work, flag, ctx->stream)
+               : launch_sr<float>(L->d_offs, L->d_coff, L->d_sizes, L->N, L->Np, e_loc_dev, (const float*)dlnpsi_dev,
+                                  spins_dev, n_samples, shift, lr, L->T, delta_dev, work, flag, ctx->stream);
+  int hflag = 0;
+  hipError_t e1 = hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream);
+  hipError_t e2 = hipStreamSynchronize(ctx->stream);
+  hipFree(work);
+  hipFree(flag);
+  if (rc != 0 || e1 != hipSuccess || e2 != hipSuccess) return fail(ctx, VP_ERR_DEVICE, "SR kernels failed");
+  if (hflag) return fail(ctx, VP_ERR_NONFINITE, "S + shift I is not numerically positive definite");
+  return stage_tensors(ctx, *L);
 }
 
 vp_status vp_sign_sgd_update(vp_ctx* ctx, int32_t lat, const double* grad_dev, double step_len, uint64_t step) {
@@ -602,6 +627,39 @@ vp_status vp_sign_sgd_update(vp_ctx* ctx, int32_t lat, const double* grad_dev, d
   launch_sign_sgd(L->T, grad_dev, L->Np, step_len, ctx->seed, lat, step, ctx->stream);
   HIP_TRY(ctx, hipGetLastError());
   return stage_tensors(ctx, *L);
+}
+
+vp_status vp_stats_tau(const double* x, int32_t n_chains, int32_t len, double c, double* tau, double* mean_out,
+                       double* stderr_out) {
+  if (!x || !tau || !mean_out || !stderr_out || n_chains < 1 || len < 2 || !(c > 0))
+    return fail(nullptr, VP_ERR_ARG, "bad arguments to vp_stats_tau");
+  double total = 0.0, var_mean = 0.0;
+  std::vector<double> d(len);
+  for (int ch = 0; ch < n_chains; ++ch) {
+    const double* s = x + (int64_t)ch * len;
+    double m = 0.0;
+    for (int t = 0; t < len; ++t) m += s[t];
+    m /= len;
+    total += m;
+    for (int t = 0; t < len; ++t) d[t] = s[t] - m;
+    double c0 = 0.0;
+    for (int t = 0; t < len; ++t) c0 += d[t] * d[t];
+    c0 /= len;
+    double tau_c = 0.5;
+    if (c0 > 0.0) {
+      for (int M = 1; M < len; ++M) {
+        double cm = 0.0;
+        for (int t = 0; t + M < len; ++t) cm += d[t] * d[t + M];
+        tau_c += cm / len / c0;
+        if (M >= c * tau_c) break;
+      }
+    }
+    tau[ch] = tau_c;
+    var_mean += c0 * 2.0 * tau_c / len;
+  }
+  *mean_out = total / n_chains;
+  *stderr_out = std::sqrt(std::max(var_mean, 0.0)) / n_chains;
+  return VP_OK;
 }
 
 vp_status vp_timing_enable(vp_ctx* ctx, int32_t enable) {

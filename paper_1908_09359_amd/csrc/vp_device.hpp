@@ -85,13 +85,15 @@ template <typename T> struct Acc4;
 template <> struct Acc4<float> { typedef v4f_g type; };
 template <> struct Acc4<double> { typedef v4d_g type; };
 
-// C(i,j) = sum_k A(i,k) B(k,j) for i < M, j < N, accumulated in TC on MFMA.
+// C(i,j) = alpha sum_k A(i,k) B(k,j) (+ C(i,j) when accumulate) for i < M,
+// j < N, accumulated in TC on MFMA.
 // 64x64 output blocks, K staged through LDS 16 at a time; each wave owns a
 // 2x2 set of 16x16 tiles.  All threads of the work-group must call it; C is
 // complete after the trailing barrier.
 template <typename TC, typename TA, typename TB>
 __device__ void wg_gemm(TC* __restrict__ C, View vc, const TA* __restrict__ A, View va,
-                        const TB* __restrict__ B, View vb, int M, int N, int K) {
+                        const TB* __restrict__ B, View vb, int M, int N, int K, TC alpha = TC(1),
+                        bool accumulate = false) {
   constexpr int BM = 64, BN = 64, BK = 16;
   TC (*As)[BM + 1] = reinterpret_cast<TC (*)[BM + 1]>(gemm_tiles());
   TC (*Bs)[BN + 1] = reinterpret_cast<TC (*)[BN + 1]>(gemm_tiles() + BK * (BM + 1) * sizeof(TC));
@@ -141,7 +143,10 @@ __device__ void wg_gemm(TC* __restrict__ C, View vc, const TA* __restrict__ A, V
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int m = m0 + tr0 + 16 * a + mfma4_row(TC(0), lane, r);
-            if (m < M) C[vaddr(vc, m, n)] = acc[a][b][r];
+            if (m < M) {
+              TC* cp = C + vaddr(vc, m, n);
+              *cp = accumulate ? *cp + alpha * acc[a][b][r] : alpha * acc[a][b][r];
+            }
           }
         }
     }

@@ -100,6 +100,11 @@ template <typename T> void launch_gradient(const int64_t* offs, const int64_t* c
                                            int N, int64_t Np, const double* e, const T* dl,
                                            const int8_t* spins, int64_t ns, double* grad, double* emean,
                                            double* work, hipStream_t s);
+template <typename T>
+int launch_sr(const int64_t* offs, const int64_t* coff, const int32_t* sz, int N, int64_t np, const double* e,
+              const T* dl, const int8_t* spins, int64_t ns, double shift, double lr, double* Tm,
+              double* delta_out, double* work, int* flag, hipStream_t s);
+int64_t sr_work_doubles(int64_t np, int64_t ns);
 void launch_sign_sgd(double* T, const double* g, int64_t Np, double step_len, uint64_t seed, int lat_id,
                      uint64_t step, hipStream_t s);
 
