@@ -90,13 +90,15 @@ template <> struct Acc4<double> { typedef v4d_g type; };
 // 64x64 output blocks, K staged through LDS 16 at a time; each wave owns a
 // 2x2 set of 16x16 tiles.  All threads of the work-group must call it; C is
 // complete after the trailing barrier.
+// tiles: LDS of GEMM_TILE_BYTES owned by the caller.
+constexpr size_t GEMM_TILE_BYTES = 2 * 16 * 65 * sizeof(double);
 template <typename TC, typename TA, typename TB>
-__device__ void wg_gemm(TC* __restrict__ C, View vc, const TA* __restrict__ A, View va,
-                        const TB* __restrict__ B, View vb, int M, int N, int K, TC alpha = TC(1),
-                        bool accumulate = false) {
+__device__ void wg_gemm_t(char* tiles, TC* __restrict__ C, View vc, const TA* __restrict__ A, View va,
+                          const TB* __restrict__ B, View vb, int M, int N, int K, TC alpha = TC(1),
+                          bool accumulate = false) {
   constexpr int BM = 64, BN = 64, BK = 16;
-  TC (*As)[BM + 1] = reinterpret_cast<TC (*)[BM + 1]>(gemm_tiles());
-  TC (*Bs)[BN + 1] = reinterpret_cast<TC (*)[BN + 1]>(gemm_tiles() + BK * (BM + 1) * sizeof(TC));
+  TC (*As)[BM + 1] = reinterpret_cast<TC (*)[BM + 1]>(tiles);
+  TC (*Bs)[BN + 1] = reinterpret_cast<TC (*)[BN + 1]>(tiles + BK * (BM + 1) * sizeof(TC));
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int tr0 = (wave >> 1) * 32, tc0 = (wave & 1) * 32;  // this wave's 32x32 corner
   for (int m0 = 0; m0 < M; m0 += BM) {
@@ -152,6 +154,13 @@ __device__ void wg_gemm(TC* __restrict__ C, View vc, const TA* __restrict__ A, V
     }
   }
   __syncthreads();
+}
+
+// The same with the kernel-wide static tile buffer.
+template <typename TC, typename TA, typename TB>
+__device__ void wg_gemm(TC* __restrict__ C, View vc, const TA* __restrict__ A, View va, const TB* __restrict__ B,
+                        View vb, int M, int N, int K, TC alpha = TC(1), bool accumulate = false) {
+  wg_gemm_t<TC>(gemm_tiles(), C, vc, A, va, B, vb, M, N, K, alpha, accumulate);
 }
 
 // ---------------------------------------------------------------------------
@@ -279,12 +288,12 @@ __device__ void defect3(T* Out, const T* Lp, const T* A, S3 sA, const T* Rn, con
 // Compression helper: Y[a][l][dd][k] = sum_{u,b,r} A[a][u][b] t[l][u][r][dd] Tin[b][r][k].
 template <typename TC, typename T>
 __device__ void compress_y(TC* Y, const T* A, S3 sA, const T* t, S4 st, const TC* Tin, TC* X0,
-                           int c, int d) {
+                           int c, int d, char* tiles) {
   // X0[a][k][u][r] = sum_b A[(a,u)][b] Tin[b][(r,k)]
-  wg_gemm<TC>(X0, view(d, c * d * d, d, c, 1, d * d), A, view(d, sA.s0, sA.s1, 1, sA.s2, 0),
+  wg_gemm_t<TC>(tiles, X0, view(d, c * d * d, d, c, 1, d * d), A, view(d, sA.s0, sA.s1, 1, sA.s2, 0),
              Tin, view(1, d * c, 0, c, c, 1), c * d, d * c, c);
   // Y[(a,k)][(l,dd)] = sum_{u,r} X0[(a,k)][(u,r)] t[(u,r)][(l,dd)]
-  wg_gemm<TC>(Y, view(c, d * d * c, 1, d, d * c, c), X0, rowmajor(d * d),
+  wg_gemm_t<TC>(tiles, Y, view(c, d * d * c, 1, d, d * c, c), X0, rowmajor(d * d),
              t, view(d, st.u, st.r, d, st.l, st.d), c * c, d * d, d * d);
 }
 

@@ -14,8 +14,11 @@ namespace vp {
 constexpr int EIG_NMAX = 128;
 constexpr int EIG_KMAX = 16;   // eigenvectors per inverse-iteration batch (one thread each)
 constexpr int EIG_PACK = EIG_NMAX * (EIG_NMAX + 1) / 2;
-// LDS the caller provides: packed matrix, inverse-iteration iterates, pivot flags
-constexpr size_t EIG_LDS_BYTES = sizeof(double) * (EIG_PACK + EIG_NMAX * EIG_KMAX) + EIG_NMAX * EIG_KMAX;
+// LDS the caller provides: the packed matrix; afterwards the same space holds
+// the LU factors (3 x n x EIG_KMAX), the kept vectors (n x EIG_KMAX) and the
+// pivot-swap bit words (n).
+constexpr size_t EIG_LDS_BYTES = sizeof(double) * EIG_PACK;
+static_assert(3 * EIG_NMAX * EIG_KMAX * 8 + EIG_NMAX * EIG_KMAX * 8 + EIG_NMAX * 4 <= EIG_LDS_BYTES, "eig LDS");
 
 __device__ inline int tri(int i) { return i * (i + 1) / 2; }
 
@@ -40,8 +43,8 @@ __device__ inline int sturm_count(const double* d, const double* e2, int n, doub
 // lds: EIG_LDS_BYTES of LDS owned by the caller.
 __device__ void sym_topk_eig(const double* H, int n, int k, double* V, double* lam, double* refl, char* lds) {
   double* Ap = reinterpret_cast<double*>(lds);
-  double* Xs = Ap + EIG_PACK;
-  unsigned char* pivf = reinterpret_cast<unsigned char*>(Xs + EIG_NMAX * EIG_KMAX);
+  double* Xs = Ap + 3 * EIG_NMAX * EIG_KMAX;                            // after the tridiagonalisation
+  unsigned* pivw = reinterpret_cast<unsigned*>(Xs + EIG_NMAX * EIG_KMAX);  // bit t: row swap of vector t
   __shared__ double dg[EIG_NMAX], eg[EIG_NMAX], e2[EIG_NMAX], tau[EIG_NMAX];
   __shared__ double pv[EIG_NMAX], wv[EIG_NMAX], vv[EIG_NMAX];
   __shared__ double pv2[2][EIG_NMAX];
@@ -173,16 +176,17 @@ __device__ void sym_topk_eig(const double* H, int n, int k, double* V, double* l
     __syncthreads();
 
     // ---- inverse iteration, one thread per eigenvector; LU factors in LDS (Ap is free now)
-    double* U0 = Ap;
-    double* U1 = Ap + 1 * EIG_NMAX * EIG_KMAX;
-    double* U2 = Ap + 2 * EIG_NMAX * EIG_KMAX;
-    double* ML = Ap + 3 * EIG_NMAX * EIG_KMAX;
+    double* U0 = Ap;                               // reciprocal pivots
+    double* U1 = Ap + 1 * EIG_NMAX * EIG_KMAX;     // first superdiagonal of U
+    double* ML = Ap + 2 * EIG_NMAX * EIG_KMAX;     // multipliers
+    for (int j = tid; j < n; j += WG) pivw[j] = 0u;
+    __syncthreads();
     if (tid < kb) {
       const int col = b0 + tid;
       const double lm = lamb[tid];
 #define IX(j) ((j) * EIG_KMAX + tid)
-      // Gaussian elimination with partial pivoting of T - lm I; rows j and j+1 may swap,
-      // which fills a second superdiagonal (U2).
+      // Gaussian elimination with partial pivoting of T - lm I; a swap of rows j
+      // and j+1 puts the known entry e[j+1] on the second superdiagonal.
       double aa = dg[0] - lm, cc = n > 1 ? eg[0] : 0.0;
       for (int j = 0; j < n - 1; ++j) {
         const double bb = eg[j];
@@ -191,14 +195,13 @@ __device__ void sym_topk_eig(const double* H, int n, int k, double* V, double* l
         if (fabs(aa) >= fabs(bb)) {
           const double piv = fabs(aa) < tiny ? (aa < 0.0 ? -tiny : tiny) : aa;
           const double m = bb / piv;
-          U0[IX(j)] = 1.0 / piv; U1[IX(j)] = cc; U2[IX(j)] = 0.0; ML[IX(j)] = m;
-          pivf[IX(j)] = 0;
+          U0[IX(j)] = 1.0 / piv; U1[IX(j)] = cc; ML[IX(j)] = m;
           aa = a1 - m * cc;
           cc = c1;
         } else {
           const double m = aa / bb;
-          U0[IX(j)] = 1.0 / bb; U1[IX(j)] = a1; U2[IX(j)] = c1; ML[IX(j)] = m;
-          pivf[IX(j)] = 1;
+          U0[IX(j)] = 1.0 / bb; U1[IX(j)] = a1; ML[IX(j)] = m;
+          atomicOr(&pivw[j], 1u << tid);
           const double naa = cc - m * a1;
           cc = -m * c1;
           aa = naa;
@@ -214,13 +217,14 @@ __device__ void sym_topk_eig(const double* H, int n, int k, double* V, double* l
       for (int it = 0; it < 3; ++it) {
         for (int j = 0; j < n - 1; ++j) {
           double rj = Xs[IX(j)], rj1 = Xs[IX(j + 1)];
-          if (pivf[IX(j)]) { double tt = rj; rj = rj1; rj1 = tt; }
+          if ((pivw[j] >> tid) & 1u) { double tt = rj; rj = rj1; rj1 = tt; }
           Xs[IX(j)] = rj;
           Xs[IX(j + 1)] = rj1 - ML[IX(j)] * rj;
         }
         double x1 = 0.0, x2 = 0.0, nrm = 0.0;
         for (int j = n - 1; j >= 0; --j) {
-          const double xj = (Xs[IX(j)] - U1[IX(j)] * x1 - U2[IX(j)] * x2) * U0[IX(j)];  // U0 holds 1/pivot
+          const double u2 = ((pivw[j] >> tid) & 1u) && j + 1 < n - 1 ? eg[j + 1] : 0.0;
+          const double xj = (Xs[IX(j)] - U1[IX(j)] * x1 - u2 * x2) * U0[IX(j)];  // U0 holds 1/pivot
           Xs[IX(j)] = xj;
           x2 = x1;
           x1 = xj;
@@ -286,28 +290,30 @@ __device__ void sym_topk_eig(const double* H, int n, int k, double* V, double* l
   }
   __syncthreads();
 
-  // ---- back-transformation: x <- H_0 H_1 ... H_{n-3} x, reflectors reloaded into LDS (Ap is free)
-  for (int e = tid; e < tri(n); e += WG) Ap[e] = refl[e];
-  __syncthreads();
+  // ---- back-transformation: x <- H_0 H_1 ... H_{n-3} x; reflector i streamed from global
+  // memory, the next one prefetched into a register while the current one is applied
+  double vreg = (n >= 3 && tid > n - 3 && tid < n) ? refl[tri(tid) + n - 3] : 0.0;
   for (int i = n - 3; i >= 0; --i) {
+    if (tid < n) vv[tid] = tid > i ? vreg : 0.0;
+    if (i >= 1 && tid > i - 1 && tid < n) vreg = refl[tri(tid) + i - 1];
+    __syncthreads();
     const double t = tau[i];
-    if (t == 0.0) continue;
-    for (int r = i + 1 + tid; r < n; r += WG) vv[r] = Ap[tri(r) + i];
-    __syncthreads();
-    for (int c0 = 0; c0 < k; c0 += WG / 16) {
-      const int col = c0 + (tid >> 4);
-      double dp = 0.0;
-      if (col < k)
-        for (int r = i + 1 + (tid & 15); r < n; r += 16) dp += vv[r] * Vw[r * ld + col];
+    if (t != 0.0) {
+      for (int c0 = 0; c0 < k; c0 += WG / 16) {
+        const int col = c0 + (tid >> 4);
+        double dp = 0.0;
+        if (col < k)
+          for (int r = i + 1 + (tid & 15); r < n; r += 16) dp += vv[r] * Vw[r * ld + col];
 #pragma unroll
-      for (int o = 8; o > 0; o >>= 1) dp += __shfl_xor(dp, o, 16);
-      if ((tid & 15) == 0 && col < k) pv[col] = t * dp;
-    }
-    __syncthreads();
-    for (int e = tid; e < (n - i - 1) * k; e += WG) {
-      const int rr = e / k, col = e - rr * k;
-      const int r = i + 1 + rr;
-      Vw[r * ld + col] -= pv[col] * vv[r];
+        for (int o = 8; o > 0; o >>= 1) dp += __shfl_xor(dp, o, 16);
+        if ((tid & 15) == 0 && col < k) pv[col] = t * dp;
+      }
+      __syncthreads();
+      for (int e = tid; e < (n - i - 1) * k; e += WG) {
+        const int rr = e / k, col = e - rr * k;
+        const int r = i + 1 + rr;
+        Vw[r * ld + col] -= pv[col] * vv[r];
+      }
     }
     __syncthreads();
   }

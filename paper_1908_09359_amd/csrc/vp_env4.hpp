@@ -4,9 +4,9 @@
 //                             t2[l2][m][r2][dd] B[c][dd][e]
 //
 // (environment layout: lower-boundary bond first).  The four pairwise
-// contractions run slice by slice -- one lower-boundary index c and a block
-// of BB upper-boundary indices b at a time -- so every intermediate stays in
-// LDS; the output accumulates in MFMA registers across the c slices.  Inputs
+// contractions run slice by slice -- one block of BB upper-boundary indices b
+// and one lower-boundary index c at a time -- so every intermediate stays in
+// LDS; a block's output accumulates in MFMA registers across the c slices.  Inputs
 // of arbitrary leg strides (mirrored or transposed views) are staged into LDS
 // in canonical order once per step.  TC is the MFMA type (float: 16x16x4 f32,
 // double: 16x16x4 f64), TB the storage type of the column tensors.
@@ -69,14 +69,40 @@ __device__ inline typename Mfma<TC>::acc_t mfma_tile(int m0, int n0, FA fa, FB f
   return acc;
 }
 
+typedef __bf16 v8bf_t __attribute__((ext_vector_type(8)));
+
+// bf16 operands, f32 accumulation (16x16x32): lane l supplies A[l%16][8(l/16)..+7]
+// and B[8(l/16)..+7][l%16]; the output layout is that of the f32 16x16x4.
+template <int M, int N, int K, typename FA, typename FB>
+__device__ inline v4f_t mfma_tile_bf16(int m0, int n0, FA fa, FB fb) {
+  v4f_t acc = {0, 0, 0, 0};
+  const int lane = threadIdx.x & 63;
+  const int i = m0 + (lane & 15), j = n0 + (lane & 15), kq = (lane >> 4) * 8;
+#pragma unroll
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    v8bf_t a, b;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int k = k0 + kq + q;
+      a[q] = (__bf16)((i < M && k < K) ? (float)fa(i, k) : 0.0f);
+      b[q] = (__bf16)((j < N && k < K) ? (float)fb(k, j) : 0.0f);
+    }
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
 // Stage out[i][j] = sum_k A(i,k) B(k,j) into LDS (row-major, ld N), all waves.
-template <typename TC, int M, int N, int K, typename FA, typename FB>
+// BF16: operands rounded to bf16, products accumulated in f32 (TC = float).
+template <typename TC, int M, int N, int K, bool BF16 = false, typename FA, typename FB>
 __device__ inline void mfma_stage(TC* out, FA fa, FB fb) {
   constexpr int MT = (M + 15) / 16, NT = (N + 15) / 16;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int t = wave; t < MT * NT; t += 4) {
     const int m0 = (t / NT) * 16, n0 = (t % NT) * 16;
-    auto acc = mfma_tile<TC, M, N, K>(m0, n0, fa, fb);
+    typename Mfma<TC>::acc_t acc;
+    if constexpr (BF16) acc = mfma_tile_bf16<M, N, K>(m0, n0, fa, fb);
+    else acc = mfma_tile<TC, M, N, K>(m0, n0, fa, fb);
     const int j = n0 + (lane & 15);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -88,7 +114,7 @@ __device__ inline void mfma_stage(TC* out, FA fa, FB fb) {
 
 // GRAM: t2 is the u<->d view of t1 and B is A (the Gram step of the boundary
 // compression); each is then staged once.
-template <typename TC, typename TB, int D, int C, bool GRAM = false>
+template <typename TC, typename TB, int D, int C, bool GRAM = false, bool BF16 = false>
 __device__ void env4_fused(TC* __restrict__ Lout, const TC* __restrict__ Lin, const TB* __restrict__ A, S3 sA,
                            const TB* __restrict__ t1, S4 s1, const TB* __restrict__ t2, S4 s2,
                            const TB* __restrict__ B, S3 sB, char* lds) {
@@ -115,26 +141,23 @@ __device__ void env4_fused(TC* __restrict__ Lout, const TC* __restrict__ Lin, co
     if (!GRAM) T2s[e] = t2[l * s2.l + u * s2.u + r * s2.r + d * s2.d];
   }
 
-  typename Mfma<TC>::acc_t acc[NBLK][T4W];
+  // b-blocks outer, lower-bond slices inner: only one block's accumulators are live
+  for (int q = 0; q < NBLK; ++q) {
+    const int b0 = q * BB;
+    typename Mfma<TC>::acc_t acc[T4W];
 #pragma unroll
-  for (int q = 0; q < NBLK; ++q)
-#pragma unroll
-    for (int w = 0; w < T4W; ++w) acc[q][w] = {0, 0, 0, 0};
-
-  for (int cs = 0; cs < C; ++cs) {
-    __syncthreads();  // previous slice done with Ls / X buffers
-    for (int e = tid; e < Sh::SL; e += WG) Ls[e] = Lin[cs * Sh::SL + e];
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < NBLK; ++q) {
-      const int b0 = q * BB;
+    for (int w = 0; w < T4W; ++w) acc[w] = {0, 0, 0, 0};
+    for (int cs = 0; cs < C; ++cs) {
+      __syncthreads();  // previous slice done with Ls / X buffers
+      for (int e = tid; e < Sh::SL; e += WG) Ls[e] = Lin[cs * Sh::SL + e];
+      __syncthreads();
       // S1: X1[(l1,l2)][(u,bb)] = sum_a Ls[a][(l1,l2)] As[a][u][b0+bb]
-      mfma_stage<TC, D * D, D * BB, C>(
+      mfma_stage<TC, D * D, D * BB, C, BF16>(
           X1, [&](int i, int k) { return Ls[k * D * D + i]; },
           [&](int k, int j) { return (TC)As[k * D * C + (j / BB) * C + b0 + j % BB]; });
       __syncthreads();
       // S2: X2[(l2,bb)][(r1,m)] = sum_{l1,u} X1[l1][l2][u][bb] T1s[(l1,u)][(r1,m)]
-      mfma_stage<TC, D * BB, D * D, D * D>(
+      mfma_stage<TC, D * BB, D * D, D * D, BF16>(
           X2,
           [&](int i, int k) {
             return X1[(k / D) * D * D * BB + (i / BB) * D * BB + (k % D) * BB + i % BB];
@@ -142,7 +165,7 @@ __device__ void env4_fused(TC* __restrict__ Lout, const TC* __restrict__ Lin, co
           [&](int k, int j) { return (TC)T1s[k * D * D + j]; });
       __syncthreads();
       // S3: X3[(bb,r1)][(r2,dd)] = sum_{l2,m} X2[l2][bb][r1][m] T2s[(l2,m)][(r2,dd)]
-      mfma_stage<TC, BB * D, D * D, D * D>(
+      mfma_stage<TC, BB * D, D * D, D * D, BF16>(
           X1,
           [&](int i, int k) {
             return X2[(((k / D) * BB + i / D) * D + i % D) * D + k % D];
@@ -159,22 +182,30 @@ __device__ void env4_fused(TC* __restrict__ Lout, const TC* __restrict__ Lin, co
         const int t = wave + 4 * w;
         if (t < NT4) {
           const int n0 = t * 16;
-          const int i = lane & 15, j = n0 + (lane & 15), kq = lane >> 4;
+          if constexpr (BF16) {
+            const int i = lane & 15, j = n0 + (lane & 15), kq = (lane >> 4) * 8;
+            v8bf_t a, b;
 #pragma unroll
-          for (int k0 = 0; k0 < D; k0 += 4) {
-            const int k = k0 + kq;
-            TC a = (i < C && k < D) ? (TC)Bs[cs * D * C + k * C + i] : TC(0);
-            TC b = (j < N4 && k < D) ? X1[j * D + k] : TC(0);
-            acc[q][w] = Mfma<TC>::op(a, b, acc[q][w]);
+            for (int q = 0; q < 8; ++q) {
+              const int k = kq + q;
+              a[q] = (__bf16)((i < C && k < D) ? (float)Bs[cs * D * C + k * C + i] : 0.0f);
+              b[q] = (__bf16)((j < N4 && k < D) ? (float)X1[j * D + k] : 0.0f);
+            }
+            acc[w] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[w], 0, 0, 0);
+          } else {
+            const int i = lane & 15, j = n0 + (lane & 15), kq = lane >> 4;
+#pragma unroll
+            for (int k0 = 0; k0 < D; k0 += 4) {
+              const int k = k0 + kq;
+              TC a = (i < C && k < D) ? (TC)Bs[cs * D * C + k * C + i] : TC(0);
+              TC b = (j < N4 && k < D) ? X1[j * D + k] : TC(0);
+              acc[w] = Mfma<TC>::op(a, b, acc[w]);
+            }
           }
         }
       }
-      __syncthreads();
     }
-  }
-  // write Lout[e][b0 + (bb,r1,r2)]
-#pragma unroll
-  for (int q = 0; q < NBLK; ++q)
+    // write Lout[e][b0 + (bb,r1,r2)]
 #pragma unroll
     for (int w = 0; w < T4W; ++w) {
       const int t = wave + 4 * w;
@@ -183,10 +214,11 @@ __device__ void env4_fused(TC* __restrict__ Lout, const TC* __restrict__ Lin, co
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int e = Mfma<TC>::row(lane, r);
-          if (e < C && j < N4) Lout[e * (C * D * D) + q * N4 + j] = acc[q][w][r];
+          if (e < C && j < N4) Lout[e * (C * D * D) + q * N4 + j] = acc[w][r];
         }
       }
     }
+  }
   __syncthreads();
 }
 

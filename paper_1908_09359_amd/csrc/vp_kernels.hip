@@ -332,9 +332,10 @@ __global__ void __launch_bounds__(WG) k_vsweep(LatDev L, int y) {
 // same; the sign and gauge of every site may differ.  All of it runs in float64
 // (the Gram matrices square the condition number of the left blocks).
 template <typename T, int DD, int CC>
-__global__ void __launch_bounds__(WG) k_compress(LatDev L, int y, int upper) {
+__global__ void __launch_bounds__(WG, 2) k_compress(LatDev L, int y, int upper) {
   constexpr size_t kGram = env4_lds<double, T, DD, CC, true>();
-  constexpr size_t kLds = kGram > EIG_LDS_BYTES ? kGram : EIG_LDS_BYTES;
+  constexpr size_t kEig = EIG_LDS_BYTES > GEMM_TILE_BYTES ? EIG_LDS_BYTES : GEMM_TILE_BYTES;
+  constexpr size_t kLds = kGram > kEig ? kGram : kEig;  // Gram step, GEMM tiles and eigensolver share it
   __shared__ __attribute__((aligned(16))) char lds[kLds];
   Chain<T> C = chain_of<T>(L, blockIdx.x);
   if (C.meta->flags) return;
@@ -379,12 +380,12 @@ __global__ void __launch_bounds__(WG) k_compress(LatDev L, int y, int upper) {
   for (int j = Lx - 1; j >= 1; --j) {
     const int k = y * Lx + j;
     const T* t = tw<T>(L, k, C.sp[k]);
-    compress_y<double, T>(Y, A_in(j), sA, t, st, Ta, X0, c, d);
+    compress_y<double, T>(Y, A_in(j), sA, t, st, Ta, X0, c, d, lds);
     // W = G_{j-1} Y, G viewed as ((a,l), (a',l')); stored [a'][a][l][l'] (fused) or [a][l][l'][a']
     const View gv = DD > 0 ? view(d, d * d, d, d, c * d * d, 1) : view(d, d * d * c, d * c, d, 1, c);
-    wg_gemm<double>(W, rowmajor(dc), G + (int64_t)j * gsz, gv, Y, rowmajor(dc), dc, dc, dc);
+    wg_gemm_t<double>(lds, W, rowmajor(dc), G + (int64_t)j * gsz, gv, Y, rowmajor(dc), dc, dc, dc);
     // H = Y^T W
-    wg_gemm<double>(H, rowmajor(dc), Y, colmajor(dc), W, rowmajor(dc), dc, dc, dc);
+    wg_gemm_t<double>(lds, H, rowmajor(dc), Y, colmajor(dc), W, rowmajor(dc), dc, dc, dc);
     const int p = upper ? L.dims[4 * k + 3] : L.dims[4 * k + 1];
     const int kr = kout[j + 1], kl = kout[j];
     const int n = p * kr;
@@ -406,14 +407,14 @@ __global__ void __launch_bounds__(WG) k_compress(LatDev L, int y, int upper) {
     T* out = A_out(j);
     for (int i = threadIdx.x; i < ssz; i += WG) out[i] = (T)Vp[i];
     // carry: Tb[(a,l)][k'] = sum_{(dd,kk)} Y[(a,l)][(dd,kk)] Vp[k'][(dd,kk)]
-    wg_gemm<double>(Tb, rowmajor(c), Y, rowmajor(dc), Vp, colmajor(dc), dc, c, dc);
+    wg_gemm_t<double>(lds, Tb, rowmajor(c), Y, rowmajor(dc), Vp, colmajor(dc), dc, c, dc);
     eT += wg_renorm<double>(Tb, ssz);
     double* tt = Ta; Ta = Tb; Tb = tt;
   }
   {
     const int k = y * Lx;
     const T* t = tw<T>(L, k, C.sp[k]);
-    compress_y<double, T>(Y, A_in(0), sA, t, st, Ta, X0, c, d);
+    compress_y<double, T>(Y, A_in(0), sA, t, st, Ta, X0, c, d, lds);
     double nrm2 = 0.0;
     for (int i = threadIdx.x; i < dc; i += WG) nrm2 += Y[i] * Y[i];
     nrm2 = wg_sum(nrm2);
