@@ -75,6 +75,8 @@ def main():
     ap.add_argument("--L", type=int, default=16)
     ap.add_argument("--D", type=int, default=8)
     ap.add_argument("--Dc", type=int, default=16)
+    ap.add_argument("--prec", choices=["fp32", "bf16"], default="fp32",
+                    help="fp32: float32 contractions; bf16: sampling pass with bf16 operands")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -88,7 +90,8 @@ def main():
     Ly = Lx = args.L
     D, Dc, nch = args.D, args.Dc, args.chains
     dev = torch.device("cuda:0")
-    lat = B.lattice(Ly, Lx, D, Dc, 1.0, 0.0, B.VP_FP32, nch)
+    prec = B.VP_BF16 if args.prec == "bf16" else B.VP_FP32
+    lat = B.lattice(Ly, Lx, D, Dc, 1.0, 0.0, prec, nch)
     ctx = B.Context(lat, seed=9359)
     ctx.vp_init_tensors(0, seed=1908, scale=0.0, perturb=0.0)
     ctx.vp_init_chains(0, None)
@@ -126,9 +129,12 @@ def main():
     out = {
         "metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if args.prec == "fp32" else "bf16/f32",
+        "data": "synthetic",
         "config": {"workload": f"{Ly}x{Lx} Heisenberg D={D} Dc={Dc}, {nch} chains, plain pair sweeps, "
-                               "fp32 contractions / fp64 compression",
+                               + ("fp32 contractions" if args.prec == "fp32" else
+                                  "bf16-operand sampling pass, fp32 measurement")
+                               + " / fp64 compression",
                    "Ly": Ly, "Lx": Lx, "D": D, "Dc": Dc, "chains": nch, "J2": 0.0,
                    "parallelism": "chains (1 GPU)"},
         "roofline": roofline,

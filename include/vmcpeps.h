@@ -31,6 +31,14 @@
  *   keeping the Dc largest singular values); 3-line row networks for
  *   horizontal pairs and 2-row (4-line) networks for vertical and diagonal
  *   pairs; every ratio divides by the same network with the current tensors.
+ * Precision (vp_lattice.prec): VP_FP64 contracts in float64; VP_FP32 in
+ *   float32 on MFMA; VP_BF16 takes the sampling pass (the ratios that decide
+ *   Metropolis moves) with bf16 operands and float32 accumulation, and measures
+ *   Psi, E_loc and G like VP_FP32 (App. D: a ratio error of a few bf16 ulps
+ *   changes acceptance probabilities by as much, which the chain tolerates;
+ *   the estimators need the full working precision).  Every mode keeps an
+ *   exact power-of-two scale per network column, accumulates log|Psi| and
+ *   normalises ratios in float64, and compresses boundaries in float64.
  * Randomness: Philox4x64-10 (Salmon et al., SC'11) under key (seed, lattice);
  *   Metropolis uniforms use counter (chain, sweep, bond, 4), where bond counts
  *   the visits of one sweep: row y's horizontal bonds, then the vertical bonds
@@ -115,6 +123,17 @@ vp_status vp_init_chains(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev);
 vp_status vp_sample(vp_ctx* ctx, int32_t lat, int32_t n_burn, int32_t n_meas,
                     double* log_abs_psi_dev, int8_t* sign_dev, double* e_loc_dev,
                     void* dlnpsi_dev, int8_t* spins_out_dev, int64_t* accept_dev);
+
+/* Record the sampler's decisions: while trace_dev is set (NULL clears it),
+ * every sweep of vp_sample overwrites trace_dev[chain][b][0..1] with the ratio
+ * rho = Psi(S')/Psi(S) that bond b's Metropolis test used (float64, after the
+ * exact power-of-two rescaling) and 1.0 if the exchange was accepted, 0.0
+ * otherwise; b = y(2Lx-1)+x for the horizontal bond (y,x)-(y,x+1) and
+ * y(2Lx-1)+(Lx-1)+x for the vertical bond (y,x)-(y+1,x); pairs that are
+ * parallel when visited get (0, 0).  trace_dev holds n_chains * n_bonds * 2
+ * float64 with n_bonds = Ly(Lx-1) + (Ly-1)Lx, stays owned by the caller and
+ * must outlive its use. */
+vp_status vp_trace_ratios(vp_ctx* ctx, int32_t lat, double* trace_dev);
 
 /* Evaluate fixed configurations spins_dev [n_cfg][N] (n_cfg <= n_chains):
  * the same outputs as one measured sweep without Metropolis moves, plus every

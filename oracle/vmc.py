@@ -109,6 +109,37 @@ def _measure(T, lat, spins, U, collect_ratios=True):
     return e_loc, G, ratio_vec, Dl
 
 
+def plaquette_ratios(T, lat, spins):
+    """Psi(S')/Psi(S) for the flip of every movable plaquette, [Ly-1][Lx-1] (0 elsewhere).
+
+    Each is the two-row network of rows y, y+1 (between U_{y-1} and D_{y+2})
+    with both columns x, x+1 exchanged, divided by the same network with the
+    current tensors -- the vertical-pair construction of App. C with two
+    columns modified.
+    """
+    from . import proposal as P
+    s = np.asarray(spins)
+    U, _ = upper_boundaries(T, lat, s)
+    Dl = _lower_boundaries(T, lat, s)
+    mov = P.movable(s, lat.Ly, lat.Lx)
+    out = np.zeros((lat.Ly - 1, lat.Lx - 1))
+    for y in range(lat.Ly - 1):
+        r1, r2, D2 = row_tensors(T, lat, s, y), row_tensors(T, lat, s, y + 1), Dl[y + 2]
+        L4, R4 = row4_envs(U[y], r1, r2, D2)
+        N4 = _dot(L4[1], R4[1])
+        if N4 == 0.0:
+            raise ZeroAmplitude("row-pair network value is zero")
+        for x in range(lat.Lx - 1):
+            if mov[y, x]:
+                sites = ((y, x), (y, x + 1), (y + 1, x), (y + 1, x + 1))
+                f1 = row_tensors(T, lat, s, y, flips=sites)
+                f2 = row_tensors(T, lat, s, y + 1, flips=sites)
+                Lm = env4_left(env4_left(L4[x], U[y][x], f1[x], f2[x], D2[x]), U[y][x + 1], f1[x + 1], f2[x + 1],
+                               D2[x + 1])
+                out[y, x] = _dot(Lm, R4[x + 2]) / N4
+    return out
+
+
 def eval_config(T, lat, spins):
     """Psi, E_loc, G and pair ratios for a fixed configuration.
 
@@ -130,7 +161,14 @@ def eval_config(T, lat, spins):
 # --------------------------------------------------------------------------
 
 class Chain:
-    """State of one Markov chain: spins, the sweep counter and its Philox stream ids."""
+    """State of one Markov chain: spins, the sweep counter and its Philox stream ids.
+
+    Test hooks, neither of which changes the arithmetic: ``trace`` (a dict, or
+    None) receives bond -> Psi(S')/Psi(S) for every proposal; ``forced`` (a
+    dict bond -> bool, or None) replaces the Metropolis test by a given
+    decision, so that another sampler's sweep can be replayed and its ratios
+    recomputed here.
+    """
 
     def __init__(self, lat, spins, seed, lattice_id, chain_id, sweep=0):
         self.lat = lat
@@ -139,10 +177,18 @@ class Chain:
         self.sweep = sweep
         self.accepted = 0
         self.proposed = 0
+        self.trace = None
+        self.forced = None
+        self.plaq_accepted = 0
+        self.plaq_proposed = 0
 
 
-def _top_down_pass(T, lat, ch, Dl):
+def _top_down_pass(T, lat, ch, Dl, proposal=None):
     """Visit every bond once in the pinned order, accepting with r < |Psi(S_b)/Psi(S_a)|^2.
+
+    With ``proposal`` (flat network parameters, see ``oracle.proposal``) the
+    row-pair step also visits plaquette (y, x) right after the vertical bond
+    (y, x)-(y+1, x), for x = 0..Lx-2 (``_plaquette_step``).
 
     Returns the upper boundaries of the final configuration and (sign, log|Psi|).
     """
@@ -190,6 +236,10 @@ def _top_down_pass(T, lat, ch, Dl):
                         ((y, x), (y + 1, x)))
                 r1 = row_tensors(T, lat, ch.spins, y)
                 r2 = row_tensors(T, lat, ch.spins, y + 1)
+            if proposal is not None and x < lat.Lx - 1:
+                _plaquette_step(T, lat, ch, proposal, y, x, L4, Uy1, D2, R4)
+                r1 = row_tensors(T, lat, ch.spins, y)
+                r2 = row_tensors(T, lat, ch.spins, y + 1)
             L4 = env4_left(L4, Uy1[x], r1[x], r2[x], D2[x])
             bond += 1
         # Row y is final for this sweep: form U_y.
@@ -201,31 +251,82 @@ def _top_down_pass(T, lat, ch, Dl):
     return U, (1 if last > 0 else -1, lam[lat.Ly - 1] + math.log(abs(last)))
 
 
+def _plaquette_step(T, lat, ch, theta, y, x, L4, Uy1, D2, R4):
+    """Propose-or-stay Metropolis-Hastings move of plaquette (y, x) (learned sampler).
+
+    Propose the flip of its four spins with probability pi(S) = sigmoid(f_x(S))
+    when it holds two up and two down spins; accept with
+    min[1, R pi(S')/pi(S)], R = (Psi(S')/Psi(S))^2 from the two-row network
+    with both columns exchanged, divided by the same network with the current
+    tensors.  Uniforms: words 0 (propose) and 1 (accept) of Philox counter
+    (chain, sweep, y(Lx-1)+x, TAG_PLAQ).
+    """
+    from . import proposal as P
+    s = ch.spins.reshape(lat.Ly, lat.Lx)
+    if not P.movable(ch.spins, lat.Ly, lat.Lx)[y, x]:
+        return
+    q = y * (lat.Lx - 1) + x
+    u_prop, u_acc = philox.plaquette_uniforms(ch.seed, ch.lattice_id, ch.chain_id, ch.sweep, q)
+    pi = P.propensity(theta, ch.spins, lat.Ly, lat.Lx, y, x)
+    if not u_prop < pi:
+        return
+    sites = ((y, x), (y, x + 1), (y + 1, x), (y + 1, x + 1))
+    r1 = row_tensors(T, lat, ch.spins, y)
+    r2 = row_tensors(T, lat, ch.spins, y + 1)
+    f1 = row_tensors(T, lat, ch.spins, y, flips=sites)
+    f2 = row_tensors(T, lat, ch.spins, y + 1, flips=sites)
+    num = env4_left(env4_left(L4, Uy1[x], f1[x], f2[x], D2[x]), Uy1[x + 1], f1[x + 1], f2[x + 1], D2[x + 1])
+    den = env4_left(env4_left(L4, Uy1[x], r1[x], r2[x], D2[x]), Uy1[x + 1], r1[x + 1], r2[x + 1], D2[x + 1])
+    num, den = _dot(num, R4[x + 2]), _dot(den, R4[x + 2])
+    if den == 0.0:
+        raise ZeroAmplitude("Metropolis denominator is zero")
+    if not (math.isfinite(num) and math.isfinite(den)):
+        raise FloatingPointError("non-finite amplitude ratio")
+    flipped = ch.spins.copy().reshape(lat.Ly, lat.Lx)
+    for p in sites:
+        flipped[p] = 1 - flipped[p]
+    pi_back = P.propensity(theta, flipped.ravel(), lat.Ly, lat.Lx, y, x)
+    if ch.trace is not None:
+        ch.trace[("p", q)] = num / den
+    ch.plaq_proposed += 1
+    take = ch.forced[("p", q)] if ch.forced is not None else u_acc < (num / den) ** 2 * pi_back / pi
+    if take:
+        for p in sites:
+            s[p] = 1 - s[p]
+        ch.plaq_accepted += 1
+
+
 def _accept(ch, num, den, bond, pair):
     if den == 0.0:
         raise ZeroAmplitude("Metropolis denominator is zero")
     if not (math.isfinite(num) and math.isfinite(den)):
         raise FloatingPointError("non-finite amplitude ratio")
     R = (num / den) ** 2
-    r = philox.metropolis_uniform(ch.seed, ch.lattice_id, ch.chain_id, ch.sweep, bond)
+    if ch.trace is not None:
+        ch.trace[bond] = num / den
+    if ch.forced is not None:
+        take = ch.forced[bond]
+    else:
+        take = philox.metropolis_uniform(ch.seed, ch.lattice_id, ch.chain_id, ch.sweep, bond) < R
     ch.proposed += 1
-    if r < R:
+    if take:
         s = ch.spins.reshape(ch.lat.Ly, ch.lat.Lx)
         (y1, x1), (y2, x2) = pair
         s[y1, x1], s[y2, x2] = s[y2, x2], s[y1, x1]
         ch.accepted += 1
 
 
-def run_chain(T, lat, ch, n_burn, n_meas):
+def run_chain(T, lat, ch, n_burn, n_meas, proposal=None):
     """Run n_burn + n_meas sweeps; measure after each of the last n_meas (Sec. II.A).
 
-    Returns a list of per-sample dicts (sign, log_abs_psi, e_loc, dlnpsi,
-    spins) and leaves the final state in ``ch``.
+    ``proposal``: network parameters of the learned plaquette moves, or None
+    for the plain sequential sweep.  Returns a list of per-sample dicts (sign,
+    log_abs_psi, e_loc, dlnpsi, spins) and leaves the final state in ``ch``.
     """
     Dl = _lower_boundaries(T, lat, ch.spins)
     out = []
     for i in range(n_burn + n_meas):
-        U, (sg, lp) = _top_down_pass(T, lat, ch, Dl)
+        U, (sg, lp) = _top_down_pass(T, lat, ch, Dl, proposal)
         e_loc, G, _, Dl = _measure(T, lat, ch.spins, U)
         if i >= n_burn:
             out.append(dict(sign=sg, log_abs_psi=lp, e_loc=e_loc, dlnpsi=G,

@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "VP_OK", 1: "VP_ERR_ARG", 2: "VP_ERR_SHAPE", 3: "VP_ERR_OOM",
 EXPORTED = ["vp_create", "vp_destroy", "vp_last_error", "vp_num_params", "vp_workspace_bytes",
             "vp_set_tensors", "vp_get_tensors", "vp_init_tensors", "vp_init_chains", "vp_sample",
             "vp_eval", "vp_gradient", "vp_sr_update", "vp_sign_sgd_update", "vp_sync",
-            "vp_timing_enable", "vp_timing_read", "vp_stats_tau"]
+            "vp_timing_enable", "vp_timing_read", "vp_stats_tau", "vp_trace_ratios"]
 
 PHASES = ["row3_envs", "hsweep", "row4_envs", "vsweep", "compress_up", "compress_down", "measure3",
           "measure4", "other"]
@@ -66,6 +66,7 @@ def _load():
         "vp_timing_enable": ([P, I32], I32),
         "vp_timing_read": ([P, P, P], I32),
         "vp_stats_tau": ([P, I32, I32, D, P, P, P], I32),
+        "vp_trace_ratios": ([P, I32, P], I32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -157,6 +158,11 @@ class Context:
                   accept=None):
         self._check(LIB.vp_sample(self.h, lat, n_burn, n_meas, _ptr(log_abs_psi), _ptr(sign), _ptr(e_loc),
                                   _ptr(dlnpsi), _ptr(spins_out), _ptr(accept)))
+
+    def vp_trace_ratios(self, lat, trace):
+        """trace: float64 [n_chains, n_bonds, 2] device tensor (kept alive by the caller) or None."""
+        self._trace = trace
+        self._check(LIB.vp_trace_ratios(self.h, lat, _ptr(trace)))
 
     def vp_eval(self, lat, spins, n_cfg, log_abs_psi, sign, e_loc, dlnpsi=None, ratios=None):
         self._check(LIB.vp_eval(self.h, lat, _ptr(spins), n_cfg, _ptr(log_abs_psi), _ptr(sign), _ptr(e_loc),

@@ -186,8 +186,8 @@ vp_status check_lattice(vp_ctx* ctx, const vp_lattice& p) {
   if (p.Ly * p.Lx > 4096) return fail(ctx, VP_ERR_SHAPE, "at most 4096 sites");
   if (p.D > 16 || p.Dc > 64 || p.D * p.Dc > 128)
     return fail(ctx, VP_ERR_SHAPE, "sizes beyond the built kernels (D <= 16, Dc <= 64, D*Dc <= 128)");
-  if (p.prec != VP_FP64 && p.prec != VP_FP32)
-    return fail(ctx, VP_ERR_UNSUPPORTED, "precision %d is not built", p.prec);
+  if (p.prec != VP_FP64 && p.prec != VP_FP32 && p.prec != VP_BF16)
+    return fail(ctx, VP_ERR_ARG, "unknown precision %d", p.prec);
   return VP_OK;
 }
 
@@ -252,14 +252,17 @@ void run_lower_pass(vp_ctx* ctx, Lattice& L, hipStream_t s) {
 template <typename T>
 void run_sweep(vp_ctx* ctx, Lattice& L, const SampleOut* o, hipStream_t s) {
   const int Ly = L.p.Ly;
+  // VP_BF16: the sampling pass contracts with bf16 operands; measurement and
+  // compression keep their precision.
+  const bool bf = L.p.prec == VP_BF16;
   Rec r(ctx);
   // top-down sampling pass
   for (int y = 0; y < Ly; ++y) {
-    TIMED(r, VP_PH_ROW3_ENVS, launch_row3_right<T>(L.dev, y, y, y + 1, s));
-    TIMED(r, VP_PH_HSWEEP, launch_hsweep<T>(L.dev, y, y == Ly - 1, s));
+    TIMED(r, VP_PH_ROW3_ENVS, launch_row3_right<T>(L.dev, y, y, y + 1, bf, s));
+    TIMED(r, VP_PH_HSWEEP, launch_hsweep<T>(L.dev, y, y == Ly - 1, bf, s));
     if (y < Ly - 1) {
-      TIMED(r, VP_PH_ROW4_ENVS, launch_row4_right<T>(L.dev, y, s));
-      TIMED(r, VP_PH_VSWEEP, launch_vsweep<T>(L.dev, y, s));
+      TIMED(r, VP_PH_ROW4_ENVS, launch_row4_right<T>(L.dev, y, bf, s));
+      TIMED(r, VP_PH_VSWEEP, launch_vsweep<T>(L.dev, y, bf, s));
       TIMED(r, VP_PH_COMPRESS_UP, launch_compress<T>(L.dev, y, 1, s));
     }
   }
@@ -399,6 +402,8 @@ vp_status vp_create(const vp_lattice* lats, int32_t n_lats, uint64_t seed, void*
     D.cws = L.cws; D.cws_stride = P.cws;
     D.iws = L.iws; D.iws_stride = P.iws; D.dws = L.dws; D.dws_stride = P.dws;
     D.meta = L.meta; D.spins = L.spins;
+    D.trace = nullptr;
+    D.n_bonds = p.Ly * (p.Lx - 1) + (p.Ly - 1) * p.Lx;
     D.kU = L.d_kU; D.kD = L.d_kD; D.dims = L.d_dims; D.coff = L.d_coff;
     if (p.prec == VP_FP64) launch_init_trivial<double>(D, ctx->stream);
     else launch_init_trivial<float>(D, ctx->stream);
@@ -511,6 +516,7 @@ vp_status vp_sample(vp_ctx* ctx, int32_t lat, int32_t n_burn, int32_t n_meas, do
   o.ratios = nullptr;
   o.n_meas = n_meas;
   o.np_half = L->Np / 2;
+  o.psi_meas = L->p.prec == VP_BF16;
   for (int i = 0; i < n_burn + n_meas; ++i) {
     o.m = i - n_burn;
     const SampleOut* op = i >= n_burn ? &o : nullptr;
@@ -522,6 +528,13 @@ vp_status vp_sample(vp_ctx* ctx, int32_t lat, int32_t n_burn, int32_t n_meas, do
     HIP_TRY(ctx, hipMemcpy2DAsync(accept_dev, 2 * sizeof(int64_t), (const char*)L->meta + sizeof(int64_t),
                                   sizeof(ChainMeta), 2 * sizeof(int64_t), L->p.n_chains, hipMemcpyDeviceToDevice, s));
   }
+  return VP_OK;
+}
+
+vp_status vp_trace_ratios(vp_ctx* ctx, int32_t lat, double* trace_dev) {
+  Lattice* L = get_lat(ctx, lat);
+  if (!L) return fail(ctx, VP_ERR_ARG, "bad lattice index");
+  L->dev.trace = trace_dev;
   return VP_OK;
 }
 

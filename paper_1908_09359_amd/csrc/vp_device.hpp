@@ -92,6 +92,75 @@ template <> struct Acc4<double> { typedef v4d_g type; };
 // complete after the trailing barrier.
 // tiles: LDS of GEMM_TILE_BYTES owned by the caller.
 constexpr size_t GEMM_TILE_BYTES = 2 * 16 * 65 * sizeof(double);
+typedef __bf16 v8bf_g __attribute__((ext_vector_type(8)));
+
+// bf16 operands, f32 accumulation (C(i,j) as above, TC = float): A and B are
+// rounded to bf16 (round to nearest even) when staged, 32 k-values at a time,
+// k-contiguous in LDS so that each lane fetches its 8 k-values of the
+// 16x16x32 MFMA in one read; the output layout is that of the f32 16x16x4.
+template <typename TA, typename TB>
+__device__ void wg_gemm_bf16(char* tiles, float* __restrict__ C, View vc, const TA* __restrict__ A, View va,
+                             const TB* __restrict__ B, View vb, int M, int N, int K, float alpha,
+                             bool accumulate) {
+  constexpr int BM = 64, BN = 64, BK = 32, LD = BK + 8;
+  __bf16 (*As)[LD] = reinterpret_cast<__bf16 (*)[LD]>(tiles);
+  __bf16 (*Bs)[LD] = reinterpret_cast<__bf16 (*)[LD]>(tiles + BM * LD * sizeof(__bf16));
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int tr0 = (wave >> 1) * 32, tc0 = (wave & 1) * 32;
+  const int kq = (lane >> 4) * 8, li = lane & 15;
+  for (int m0 = 0; m0 < M; m0 += BM) {
+    for (int n0 = 0; n0 < N; n0 += BN) {
+      v4f_g acc[2][2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = {0, 0, 0, 0};
+      for (int k0 = 0; k0 < K; k0 += BK) {
+#pragma unroll
+        for (int e = 0; e < (BM * BK) / WG; ++e) {
+          int idx = tid + e * WG;
+          int mi = idx % BM, ki = idx / BM;
+          int m = m0 + mi, k = k0 + ki;
+          As[mi][ki] = (__bf16)((m < M && k < K) ? (float)A[vaddr(va, m, k)] : 0.0f);
+        }
+#pragma unroll
+        for (int e = 0; e < (BN * BK) / WG; ++e) {
+          int idx = tid + e * WG;
+          int ni = idx % BN, ki = idx / BN;
+          int n = n0 + ni, k = k0 + ki;
+          Bs[ni][ki] = (__bf16)((n < N && k < K) ? (float)B[vaddr(vb, k, n)] : 0.0f);
+        }
+        __syncthreads();
+        const v8bf_g a0 = *reinterpret_cast<const v8bf_g*>(&As[tr0 + li][kq]);
+        const v8bf_g a1 = *reinterpret_cast<const v8bf_g*>(&As[tr0 + 16 + li][kq]);
+        const v8bf_g b0 = *reinterpret_cast<const v8bf_g*>(&Bs[tc0 + li][kq]);
+        const v8bf_g b1 = *reinterpret_cast<const v8bf_g*>(&Bs[tc0 + 16 + li][kq]);
+        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[1][1], 0, 0, 0);
+        __syncthreads();
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          const int n = n0 + tc0 + 16 * b + li;
+          if (n >= N) continue;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int m = m0 + tr0 + 16 * a + 4 * (lane >> 4) + r;
+            if (m < M) {
+              float* cp = C + vaddr(vc, m, n);
+              *cp = accumulate ? *cp + alpha * acc[a][b][r] : alpha * acc[a][b][r];
+            }
+          }
+        }
+    }
+  }
+  __syncthreads();
+}
+
 template <typename TC, typename TA, typename TB>
 __device__ void wg_gemm_t(char* tiles, TC* __restrict__ C, View vc, const TA* __restrict__ A, View va,
                           const TB* __restrict__ B, View vb, int M, int N, int K, TC alpha = TC(1),
@@ -161,6 +230,19 @@ template <typename TC, typename TA, typename TB>
 __device__ void wg_gemm(TC* __restrict__ C, View vc, const TA* __restrict__ A, View va, const TB* __restrict__ B,
                         View vb, int M, int N, int K, TC alpha = TC(1), bool accumulate = false) {
   wg_gemm_t<TC>(gemm_tiles(), C, vc, A, va, B, vb, M, N, K, alpha, accumulate);
+}
+
+// Operand precision chosen at compile time: BF16 rounds both operands to bf16
+// (f32 accumulation); otherwise the products are formed in TC.
+template <bool BF16, typename TC, typename TA, typename TB>
+__device__ inline void wg_gemm_p(TC* __restrict__ C, View vc, const TA* __restrict__ A, View va,
+                                 const TB* __restrict__ B, View vb, int M, int N, int K) {
+  if constexpr (BF16) {
+    static_assert(sizeof(TC) == 4, "bf16 operands accumulate in float");
+    wg_gemm_bf16(gemm_tiles(), C, vc, A, va, B, vb, M, N, K, 1.0f, false);
+  } else {
+    wg_gemm_t<TC>(gemm_tiles(), C, vc, A, va, B, vb, M, N, K);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -233,38 +315,38 @@ struct S4 { int l, u, r, d; };        // PEPS site
 // 3-line left step (App. C): Lout[b][r][e] =
 //   sum Lin[a][l][c] A[a][u][b] t[l][u][r][dd] B[c][dd][e].
 // Lin/Lout are dense c x d x c; X0/X1 scratch of c*c*d*d elements.
-template <typename T>
+template <typename T, bool BF16 = false>
 __device__ void env3_step(T* Lout, const T* Lin, const T* A, S3 sA, const T* t, S4 st,
                           const T* B, S3 sB, T* X0, T* X1, int c, int d) {
   using TC = T;
   // X0[c'][b][l][u] = sum_a Lin[a][(l,c')] A[a][(u,b)]
-  wg_gemm<TC>(X0, view(c, d, c * d * d, c, 1, d * d), Lin, view(c, c, 1, 1, d * c, 0),
+  wg_gemm_p<BF16, TC>(X0, view(c, d, c * d * d, c, 1, d * d), Lin, view(c, c, 1, 1, d * c, 0),
              A, view(1, sA.s0, 0, c, sA.s1, sA.s2), d * c, d * c, c);
   // X1[b][r][c'][dd] = sum_{l,u} X0[(c',b)][(l,u)] t[(l,u)][(r,dd)]
-  wg_gemm<TC>(X1, view(c, d, d * c * d, d, c * d, 1), X0, rowmajor(d * d),
+  wg_gemm_p<BF16, TC>(X1, view(c, d, d * c * d, d, c * d, 1), X0, rowmajor(d * d),
              t, view(d, st.l, st.u, d, st.r, st.d), c * c, d * d, d * d);
   // Lout[(b,r)][e] = sum_{c',dd} X1[(b,r)][(c',dd)] B[(c',dd)][e]
-  wg_gemm<TC>(Lout, rowmajor(c), X1, rowmajor(c * d), B, view(d, sB.s0, sB.s1, 1, sB.s2, 0),
+  wg_gemm_p<BF16, TC>(Lout, rowmajor(c), X1, rowmajor(c * d), B, view(d, sB.s0, sB.s1, 1, sB.s2, 0),
              c * d, c, c * d);
 }
 
 // 4-line left step: Lout[b][r1][r2][e] = sum Lin[a][l1][l2][c] A[a][u][b]
 //   t1[l1][u][r1][m] t2[l2][m][r2][dd] B[c][dd][e].
 // X0/X1 scratch of d*d*d*c*c elements each.
-template <typename TC, typename T>
+template <typename TC, typename T, bool BF16 = false>
 __device__ void env4_step(TC* Lout, const TC* Lin, const T* A, S3 sA, const T* t1, S4 s1,
                           const T* t2, S4 s2, const T* B, S3 sB, TC* X0, TC* X1, int c, int d) {
   // X0[(l2,c')][b][l1][u] = sum_a Lin[a][(l1,(l2,c'))] A[a][(u,b)]
-  wg_gemm<TC>(X0, view(d * c, d, c * d * d, c, 1, d * d), Lin, view(d * c, d * c, 1, 1, d * d * c, 0),
+  wg_gemm_p<BF16, TC>(X0, view(d * c, d, c * d * d, c, 1, d * d), Lin, view(d * c, d * c, 1, 1, d * d * c, 0),
              A, view(1, sA.s0, 0, c, sA.s1, sA.s2), d * d * c, d * c, c);
   // X1[(c',b)][r1][l2][m] = sum_{l1,u} X0[(l2,c',b)][(l1,u)] t1[(l1,u)][(r1,m)]
-  wg_gemm<TC>(X1, view(c * c, d, d * d * d, d, d * d, 1), X0, rowmajor(d * d),
+  wg_gemm_p<BF16, TC>(X1, view(c * c, d, d * d * d, d, d * d, 1), X0, rowmajor(d * d),
              t1, view(d, s1.l, s1.u, d, s1.r, s1.d), d * c * c, d * d, d * d);
   // X0[(b,r1)][r2][c'][dd] = sum_{l2,m} X1[(c',b,r1)][(l2,m)] t2[(l2,m)][(r2,dd)]
-  wg_gemm<TC>(X0, view(c * d, d, d * d * c, d, c * d, 1), X1, rowmajor(d * d),
+  wg_gemm_p<BF16, TC>(X0, view(c * d, d, d * d * c, d, c * d, 1), X1, rowmajor(d * d),
              t2, view(d, s2.l, s2.u, d, s2.r, s2.d), c * c * d, d * d, d * d);
   // Lout[(b,r1,r2)][e] = sum_{c',dd} X0[(b,r1,r2)][(c',dd)] B[(c',dd)][e]
-  wg_gemm<TC>(Lout, rowmajor(c), X0, rowmajor(c * d), B, view(d, sB.s0, sB.s1, 1, sB.s2, 0),
+  wg_gemm_p<BF16, TC>(Lout, rowmajor(c), X0, rowmajor(c * d), B, view(d, sB.s0, sB.s1, 1, sB.s2, 0),
              c * d * d, c, c * d);
 }
 

@@ -69,17 +69,17 @@ __device__ inline void raise_flag(ChainMeta* m, int f) {
 }
 
 // 3-line column step with optional flipped site: t = T[s ^ flip].
-template <typename T>
+template <typename T, bool BF16 = false>
 __device__ inline int step3(const LatDev& L, const Chain<T>& C, T* out, const T* in, int y, int x,
                             int flip, const T* Ux, const T* Dx, bool right) {
   int k = y * L.Lx + x;
   const T* t = tw<T>(L, k, C.sp[k] ^ flip);
   S4 st = st_std(L.d);
   if (right)
-    env3_step<T>(out, in, Ux, sb_mirror(L.c, L.d), t, st_mirror(st), Dx, sb_mirror(L.c, L.d),
+    env3_step<T, BF16>(out, in, Ux, sb_mirror(L.c, L.d), t, st_mirror(st), Dx, sb_mirror(L.c, L.d),
                  C.ws + L.oX0, C.ws + L.oX1, L.c, L.d);
   else
-    env3_step<T>(out, in, Ux, sb_std(L.c, L.d), t, st, Dx, sb_std(L.c, L.d), C.ws + L.oX0,
+    env3_step<T, BF16>(out, in, Ux, sb_std(L.c, L.d), t, st, Dx, sb_std(L.c, L.d), C.ws + L.oX0,
                  C.ws + L.oX1, L.c, L.d);
   return wg_renorm<T>(out, e3sz(L));
 }
@@ -93,8 +93,9 @@ constexpr size_t env4_lds() {
 
 // 4-line column step over rows y and y+1; flip1/flip2 select the flipped slot.
 // DD > 0 selects the fused MFMA step (environment layout [c][a][l1][l2]);
-// DD == 0 the generic strided-GEMM step (layout [a][l1][l2][c]).
-template <typename T, int DD, int CC>
+// DD == 0 the generic strided-GEMM step (layout [a][l1][l2][c]).  BF16: bf16
+// operands with f32 accumulation.
+template <typename T, int DD, int CC, bool BF16 = false>
 __device__ inline int step4(const LatDev& L, const Chain<T>& C, T* out, const T* in, int y, int x,
                             int flip1, int flip2, const T* Ux, const T* Dx, bool right, char* lds) {
   int k1 = y * L.Lx + x, k2 = (y + 1) * L.Lx + x;
@@ -104,9 +105,9 @@ __device__ inline int step4(const LatDev& L, const Chain<T>& C, T* out, const T*
   const S3 sb = right ? sb_mirror(L.c, L.d) : sb_std(L.c, L.d);
   const S4 s = right ? st_mirror(st) : st;
   if constexpr (DD > 0) {
-    env4_fused<T, T, DD, CC>(out, in, Ux, sb, t1, s, t2, s, Dx, sb, lds);
+    env4_fused<T, T, DD, CC, false, BF16>(out, in, Ux, sb, t1, s, t2, s, Dx, sb, lds);
   } else {
-    env4_step<T, T>(out, in, Ux, sb, t1, s, t2, s, Dx, sb, C.ws + L.oX0, C.ws + L.oX1, L.c, L.d);
+    env4_step<T, T, BF16>(out, in, Ux, sb, t1, s, t2, s, Dx, sb, C.ws + L.oX0, C.ws + L.oX1, L.c, L.d);
   }
   return wg_renorm<T>(out, e4sz(L));
 }
@@ -153,7 +154,7 @@ __global__ void __launch_bounds__(WG) k_init_trivial(LatDev L) {
 }
 
 // R3[x] = R(x) for x = Lx-1 .. 1 of the network <D|row y|U>; R3[Lx] = ones.
-template <typename T>
+template <typename T, bool BF16>
 __global__ void __launch_bounds__(WG) k_row3_right(LatDev L, int y, int ub_slot, int db_slot) {
   Chain<T> C = chain_of<T>(L, blockIdx.x);
   const int sz = e3sz(L);
@@ -162,8 +163,8 @@ __global__ void __launch_bounds__(WG) k_row3_right(LatDev L, int y, int ub_slot,
   set_unit<T>(R + (int64_t)L.Lx * sz, sz);
   if (threadIdx.x == 0) eR[L.Lx] = 0;
   for (int x = L.Lx - 1; x >= 1; --x) {
-    int e = step3<T>(L, C, R + (int64_t)x * sz, R + (int64_t)(x + 1) * sz, y, x, 0,
-                     ub<T>(L, C, ub_slot, x), db<T>(L, C, db_slot, x), true);
+    int e = step3<T, BF16>(L, C, R + (int64_t)x * sz, R + (int64_t)(x + 1) * sz, y, x, 0,
+                           ub<T>(L, C, ub_slot, x), db<T>(L, C, db_slot, x), true);
     if (threadIdx.x == 0) eR[x] = eR[x + 1] + e;
     __syncthreads();
   }
@@ -184,12 +185,27 @@ __device__ inline bool metropolis(const LatDev& L, ChainMeta* meta, double num, 
   U64x4 w = philox4x64_10((uint64_t)blockIdx.x, (uint64_t)meta->sweep, (uint64_t)bond, TAG_METRO,
                           L.seed, (uint64_t)L.lat_id);
   double u = uniform53(w.v[0]);
-  return u < R;
+  const bool acc = u < R;
+  if (L.trace && threadIdx.x == 0) {
+    double* t = L.trace + 2 * ((int64_t)blockIdx.x * L.n_bonds + bond);
+    t[0] = rho;
+    t[1] = acc ? 1.0 : 0.0;
+  }
+  return acc;
+}
+
+// Trace entry of a bond whose pair is parallel (no move proposed).
+__device__ inline void trace_skip(const LatDev& L, int bond) {
+  if (L.trace && threadIdx.x == 0) {
+    double* t = L.trace + 2 * ((int64_t)blockIdx.x * L.n_bonds + bond);
+    t[0] = 0.0;
+    t[1] = 0.0;
+  }
 }
 
 // Horizontal bonds of row y, left to right (Sec. II.A Eq. (9)).  With moves = 0
 // no move is attempted.  For the last row the full amplitude is produced.
-template <typename T>
+template <typename T, bool BF16>
 __global__ void __launch_bounds__(WG) k_hsweep(LatDev L, int y, int last_row, int moves) {
   Chain<T> C = chain_of<T>(L, blockIdx.x);
   if (C.meta->flags) return;
@@ -205,14 +221,16 @@ __global__ void __launch_bounds__(WG) k_hsweep(LatDev L, int y, int last_row, in
     const T* Dx = db<T>(L, C, y + 1, x);
     T* cur = tmp + slot[0] * sz;
     T* nxt = tmp + slot[1] * sz;
-    int enxt = ecur + step3<T>(L, C, nxt, cur, y, x, 0, Ux, Dx, false);
+    int enxt = ecur + step3<T, BF16>(L, C, nxt, cur, y, x, 0, Ux, Dx, false);
     const int k = y * L.Lx + x;
     bool acc = false;
+    if (moves && C.sp[k] == C.sp[k + 1]) trace_skip(L, y * (2 * L.Lx - 1) + x);
     if (moves && C.sp[k] != C.sp[k + 1]) {
       T* f1 = tmp + slot[2] * sz;
       T* f2 = tmp + slot[3] * sz;
-      int ef1 = ecur + step3<T>(L, C, f1, cur, y, x, 1, Ux, Dx, false);
-      int ef2 = ef1 + step3<T>(L, C, f2, f1, y, x + 1, 1, ub<T>(L, C, y, x + 1), db<T>(L, C, y + 1, x + 1), false);
+      int ef1 = ecur + step3<T, BF16>(L, C, f1, cur, y, x, 1, Ux, Dx, false);
+      int ef2 = ef1 + step3<T, BF16>(L, C, f2, f1, y, x + 1, 1, ub<T>(L, C, y, x + 1),
+                                     db<T>(L, C, y + 1, x + 1), false);
       double num = wg_dot<T>(f2, R + (int64_t)(x + 2) * sz, sz);
       double den = wg_dot<T>(nxt, R + (int64_t)(x + 1) * sz, sz);
       int bond = y * (2 * L.Lx - 1) + x;
@@ -239,7 +257,7 @@ __global__ void __launch_bounds__(WG) k_hsweep(LatDev L, int y, int last_row, in
     const int x = L.Lx - 1;
     T* cur = tmp + slot[0] * sz;
     T* nxt = tmp + slot[1] * sz;
-    int e = ecur + step3<T>(L, C, nxt, cur, y, x, 0, ub<T>(L, C, y, x), db<T>(L, C, y + 1, x), false);
+    int e = ecur + step3<T, BF16>(L, C, nxt, cur, y, x, 0, ub<T>(L, C, y, x), db<T>(L, C, y + 1, x), false);
     double v = (double)nxt[0];
     if (threadIdx.x == 0) {
       if (v == 0.0) {
@@ -255,7 +273,7 @@ __global__ void __launch_bounds__(WG) k_hsweep(LatDev L, int y, int last_row, in
 }
 
 // R4[x] for x = Lx-1 .. 1 of <D_{y+2}|M_{y+1} M_y|U_{y-1}>.
-template <typename T, int DD, int CC>
+template <typename T, int DD, int CC, bool BF16>
 __global__ void __launch_bounds__(WG) k_row4_right(LatDev L, int y) {
   __shared__ __attribute__((aligned(16))) char lds[env4_lds<T, T, DD, CC>()];
   Chain<T> C = chain_of<T>(L, blockIdx.x);
@@ -266,15 +284,15 @@ __global__ void __launch_bounds__(WG) k_row4_right(LatDev L, int y) {
   set_unit<T>(R + (int64_t)L.Lx * sz, sz);
   if (threadIdx.x == 0) eR[L.Lx] = 0;
   for (int x = L.Lx - 1; x >= 1; --x) {
-    int e = step4<T, DD, CC>(L, C, R + (int64_t)x * sz, R + (int64_t)(x + 1) * sz, y, x, 0, 0,
-                     ub<T>(L, C, y, x), db<T>(L, C, y + 2, x), true, lds);
+    int e = step4<T, DD, CC, BF16>(L, C, R + (int64_t)x * sz, R + (int64_t)(x + 1) * sz, y, x, 0, 0,
+                                   ub<T>(L, C, y, x), db<T>(L, C, y + 2, x), true, lds);
     if (threadIdx.x == 0) eR[x] = eR[x + 1] + e;
     __syncthreads();
   }
 }
 
 // Vertical bonds between rows y and y+1, left to right.
-template <typename T, int DD, int CC>
+template <typename T, int DD, int CC, bool BF16>
 __global__ void __launch_bounds__(WG) k_vsweep(LatDev L, int y) {
   __shared__ __attribute__((aligned(16))) char lds[env4_lds<T, T, DD, CC>()];
   Chain<T> C = chain_of<T>(L, blockIdx.x);
@@ -291,16 +309,17 @@ __global__ void __launch_bounds__(WG) k_vsweep(LatDev L, int y) {
     const T* Dx = db<T>(L, C, y + 2, x);
     T* cur = tmp + slot[0] * sz;
     T* nxt = tmp + slot[1] * sz;
+    const int vb = y * (2 * L.Lx - 1) + (L.Lx - 1) + x;
+    if (C.sp[y * L.Lx + x] == C.sp[(y + 1) * L.Lx + x]) trace_skip(L, vb);
     if (x == L.Lx - 1 && !(C.sp[y * L.Lx + x] != C.sp[(y + 1) * L.Lx + x])) break;
-    int enxt = ecur + step4<T, DD, CC>(L, C, nxt, cur, y, x, 0, 0, Ux, Dx, false, lds);
+    int enxt = ecur + step4<T, DD, CC, BF16>(L, C, nxt, cur, y, x, 0, 0, Ux, Dx, false, lds);
     const int k1 = y * L.Lx + x, k2 = (y + 1) * L.Lx + x;
     if (C.sp[k1] != C.sp[k2]) {
       T* f = tmp + slot[2] * sz;
-      int ef = ecur + step4<T, DD, CC>(L, C, f, cur, y, x, 1, 1, Ux, Dx, false, lds);
+      int ef = ecur + step4<T, DD, CC, BF16>(L, C, f, cur, y, x, 1, 1, Ux, Dx, false, lds);
       double num = wg_dot<T>(f, R + (int64_t)(x + 1) * sz, sz);
       double den = wg_dot<T>(nxt, R + (int64_t)(x + 1) * sz, sz);
-      int bond = y * (2 * L.Lx - 1) + (L.Lx - 1) + x;
-      bool acc = metropolis(L, C.meta, num, den, ef - enxt, bond);
+      bool acc = metropolis(L, C.meta, num, den, ef - enxt, vb);
       if (threadIdx.x == 0) {
         C.meta->proposed += 1;
         if (acc) {
@@ -464,6 +483,11 @@ __global__ void __launch_bounds__(WG) k_measure3(LatDev L, int y, SampleOut o) {
   const double Nm = wg_dot<T>(Le + sz, R + sz, sz);
   const int eN = eL[1] + eR[1];
   if (Nm == 0.0) { raise_flag(C.meta, FLAG_ZERO); return; }
+  if (o.psi_meas && y == L.Ly - 1 && threadIdx.x == 0) {
+    // the bottom row's network is Psi itself (D_{Ly} trivial)
+    C.meta->logpsi = C.dw[L.dlamU + y] + log(fabs(Nm)) + eN * 0.69314718055994530942;
+    C.meta->sign = Nm > 0 ? 1 : -1;
+  }
   if (o.dlnpsi) {
     T* Dl = C.ws + L.oDl;
     for (int x = 0; x < Lx; ++x) {
@@ -703,16 +727,28 @@ void launch_init_trivial(const LatDev& L, hipStream_t s) {
   hipLaunchKernelGGL(k_init_trivial<T>, dim3(L.n_chains), dim3(WG), 0, s, L);
 }
 template <typename T>
-void launch_row3_right(const LatDev& L, int y, int ub_slot, int db_slot, hipStream_t s) {
-  hipLaunchKernelGGL(k_row3_right<T>, dim3(L.n_chains), dim3(WG), 0, s, L, y, ub_slot, db_slot);
+void launch_row3_right(const LatDev& L, int y, int ub_slot, int db_slot, bool bf16, hipStream_t s) {
+  if constexpr (sizeof(T) == 4) {
+    if (bf16) {
+      hipLaunchKernelGGL((k_row3_right<T, true>), dim3(L.n_chains), dim3(WG), 0, s, L, y, ub_slot, db_slot);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_row3_right<T, false>), dim3(L.n_chains), dim3(WG), 0, s, L, y, ub_slot, db_slot);
 }
 template <typename T>
-void launch_hsweep(const LatDev& L, int y, int last_row, hipStream_t s) {
-  hipLaunchKernelGGL(k_hsweep<T>, dim3(L.n_chains), dim3(WG), 0, s, L, y, last_row, 1);
+void launch_hsweep(const LatDev& L, int y, int last_row, bool bf16, hipStream_t s) {
+  if constexpr (sizeof(T) == 4) {
+    if (bf16) {
+      hipLaunchKernelGGL((k_hsweep<T, true>), dim3(L.n_chains), dim3(WG), 0, s, L, y, last_row, 1);
+      return;
+    }
+  }
+  hipLaunchKernelGGL((k_hsweep<T, false>), dim3(L.n_chains), dim3(WG), 0, s, L, y, last_row, 1);
 }
 template <typename T>
 void launch_psi_fixed(const LatDev& L, hipStream_t s) {
-  hipLaunchKernelGGL(k_hsweep<T>, dim3(L.n_chains), dim3(WG), 0, s, L, L.Ly - 1, 1, 0);
+  hipLaunchKernelGGL((k_hsweep<T, false>), dim3(L.n_chains), dim3(WG), 0, s, L, L.Ly - 1, 1, 0);
 }
 // Compile-time (D, Dc) instantiations of the fused 2-row step; other shapes run the generic path.
 #define VP_DISPATCH_DC(KERNEL, T, ...)                                                                 \
@@ -727,13 +763,33 @@ void launch_psi_fixed(const LatDev& L, hipStream_t s) {
       hipLaunchKernelGGL((KERNEL<T, 0, 0>), dim3(L.n_chains), dim3(WG), 0, s, __VA_ARGS__);            \
   } while (0)
 
+// The same with a compile-time operand-precision flag BF (bf16 operands when true).
+#define VP_DISPATCH_DC_BF(KERNEL, T, BF, ...)                                                          \
+  do {                                                                                                 \
+    if (L.d == 8 && L.c == 16)                                                                         \
+      hipLaunchKernelGGL((KERNEL<T, 8, 16, BF>), dim3(L.n_chains), dim3(WG), 0, s, __VA_ARGS__);       \
+    else if (L.d == 6 && L.c == 12)                                                                    \
+      hipLaunchKernelGGL((KERNEL<T, 6, 12, BF>), dim3(L.n_chains), dim3(WG), 0, s, __VA_ARGS__);       \
+    else if (L.d == 4 && L.c == 8)                                                                     \
+      hipLaunchKernelGGL((KERNEL<T, 4, 8, BF>), dim3(L.n_chains), dim3(WG), 0, s, __VA_ARGS__);        \
+    else                                                                                               \
+      hipLaunchKernelGGL((KERNEL<T, 0, 0, BF>), dim3(L.n_chains), dim3(WG), 0, s, __VA_ARGS__);        \
+  } while (0)
+
+// bf16 operands exist only for float accumulation.
 template <typename T>
-void launch_row4_right(const LatDev& L, int y, hipStream_t s) {
-  VP_DISPATCH_DC(k_row4_right, T, L, y);
+void launch_row4_right(const LatDev& L, int y, bool bf16, hipStream_t s) {
+  if constexpr (sizeof(T) == 4) {
+    if (bf16) { VP_DISPATCH_DC_BF(k_row4_right, T, true, L, y); return; }
+  }
+  VP_DISPATCH_DC_BF(k_row4_right, T, false, L, y);
 }
 template <typename T>
-void launch_vsweep(const LatDev& L, int y, hipStream_t s) {
-  VP_DISPATCH_DC(k_vsweep, T, L, y);
+void launch_vsweep(const LatDev& L, int y, bool bf16, hipStream_t s) {
+  if constexpr (sizeof(T) == 4) {
+    if (bf16) { VP_DISPATCH_DC_BF(k_vsweep, T, true, L, y); return; }
+  }
+  VP_DISPATCH_DC_BF(k_vsweep, T, false, L, y);
 }
 template <typename T>
 void launch_compress(const LatDev& L, int y, int upper, hipStream_t s) {
@@ -786,11 +842,11 @@ void launch_sign_sgd(double* T, const double* g, int64_t Np, double step_len, ui
 #define VP_INSTANTIATE(T)                                                                            \
   template void launch_prepare_tensors<T>(const LatDev&, const double*, T*, const int64_t*, hipStream_t); \
   template void launch_init_trivial<T>(const LatDev&, hipStream_t);                                  \
-  template void launch_row3_right<T>(const LatDev&, int, int, int, hipStream_t);                    \
-  template void launch_hsweep<T>(const LatDev&, int, int, hipStream_t);                             \
+  template void launch_row3_right<T>(const LatDev&, int, int, int, bool, hipStream_t);                    \
+  template void launch_hsweep<T>(const LatDev&, int, int, bool, hipStream_t);                             \
   template void launch_psi_fixed<T>(const LatDev&, hipStream_t);                                    \
-  template void launch_row4_right<T>(const LatDev&, int, hipStream_t);                              \
-  template void launch_vsweep<T>(const LatDev&, int, hipStream_t);                                  \
+  template void launch_row4_right<T>(const LatDev&, int, bool, hipStream_t);                              \
+  template void launch_vsweep<T>(const LatDev&, int, bool, hipStream_t);                                  \
   template void launch_compress<T>(const LatDev&, int, int, hipStream_t);                           \
   template void launch_measure3<T>(const LatDev&, int, const SampleOut&, hipStream_t);              \
   template void launch_measure4<T>(const LatDev&, int, const SampleOut&, hipStream_t);              \

@@ -39,6 +39,8 @@ struct LatDev {
   int64_t dws_stride;
   ChainMeta* meta;
   int8_t* spins;            // [n_chains][N]
+  double* trace;            // [n_chains][n_bonds][2] (rho, accepted) of the last sweep, or null
+  int n_bonds;              // Ly(Lx-1) + (Ly-1)Lx
   const int32_t* kU;        // bond dims of U_y: kU[(y+1)*(Lx+1) + j], y = -1..Ly-1
   const int32_t* kD;        // bond dims of D_y: kD[y*(Lx+1) + j], y = 0..Ly
   const int32_t* dims;      // true leg dims per site [N][4] (l,u,r,d)
@@ -76,15 +78,16 @@ struct SampleOut {
   int m;                // index of this measurement
   int64_t np_half;
   int n_pairs;
+  int psi_meas;         // Psi from the measurement pass (bottom row) instead of the sampling pass
 };
 
 template <typename T> void launch_prepare_tensors(const LatDev& L, const double* Tflat, T* Tw,
                                                   const int64_t* offs, hipStream_t s);
 template <typename T> void launch_init_trivial(const LatDev& L, hipStream_t s);
-template <typename T> void launch_row3_right(const LatDev& L, int y, int ub_slot, int db_slot, hipStream_t s);
-template <typename T> void launch_hsweep(const LatDev& L, int y, int last_row, hipStream_t s);
-template <typename T> void launch_row4_right(const LatDev& L, int y, hipStream_t s);
-template <typename T> void launch_vsweep(const LatDev& L, int y, hipStream_t s);
+template <typename T> void launch_row3_right(const LatDev& L, int y, int ub_slot, int db_slot, bool bf16, hipStream_t s);
+template <typename T> void launch_hsweep(const LatDev& L, int y, int last_row, bool bf16, hipStream_t s);
+template <typename T> void launch_row4_right(const LatDev& L, int y, bool bf16, hipStream_t s);
+template <typename T> void launch_vsweep(const LatDev& L, int y, bool bf16, hipStream_t s);
 template <typename T> void launch_compress(const LatDev& L, int y, int upper, hipStream_t s);
 template <typename T> void launch_measure3(const LatDev& L, int y, const SampleOut& o, hipStream_t s);
 template <typename T> void launch_measure4(const LatDev& L, int y, const SampleOut& o, hipStream_t s);

@@ -27,12 +27,17 @@ def num_params(Ly, Lx, D):
     return n
 
 
-def random_tensors(Ly, Lx, D, seed, scale=None):
-    """Flat float64 parameter vector, i.i.d. N(0, scale^2), scale = 1/D^2 by default."""
+def random_tensors(Ly, Lx, D, seed, scale=None, perturb=0.0):
+    """Flat float64 parameter vector, i.i.d. N(0, scale^2), scale = 1/D^2 by default,
+    plus perturb * xi' with xi' ~ N(0, 1) from a second seeded stream."""
     rng = np.random.default_rng(seed)
     if scale is None:
         scale = 1.0 / D ** 2
-    return rng.standard_normal(num_params(Ly, Lx, D)) * scale
+    n = num_params(Ly, Lx, D)
+    T = rng.standard_normal(n) * scale
+    if perturb:
+        T = T + perturb * np.random.default_rng([seed, 1]).standard_normal(n)
+    return T
 
 
 def random_configs(Ly, Lx, n, seed):

@@ -53,7 +53,8 @@ def test_create_rejects_bad_shapes_before_touching_the_device(bad):
     with pytest.raises(binding.VPError) as ei:
         binding.Context(binding.vp_lattice(kw["Ly"], kw["Lx"], kw["D"], kw["Dc"], kw["J1"], kw["J2"],
                                            kw["prec"], kw["n_chains"]))
-    assert ei.value.status in (binding.VP_ERR_SHAPE, binding.VP_ERR_UNSUPPORTED)
+    # an unknown precision is a bad enum (VP_ERR_ARG); the rest are shapes
+    assert ei.value.status == (binding.VP_ERR_ARG if "prec" in bad else binding.VP_ERR_SHAPE)
 
 
 def test_workload_inputs_are_seeded():

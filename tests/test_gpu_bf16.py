@@ -1,0 +1,209 @@
+"""Reduced-precision sampling (bf16 operands, f32 accumulation) against the oracle.
+
+The bf16 mode changes only the ratios that decide Metropolis moves; Psi, E_loc
+and the log-derivatives are measured in float32.  So:
+
+* the sampler's own ratios are traced (vp_trace_ratios) and the oracle replays
+  the same sweep with the same decisions, recomputing every ratio in float64;
+  every decision must also agree with the sampler's own ratio and the shared
+  Philox uniform (bit-exact decision logic);
+* the fixed-configuration gate (64 configurations of the 16x16, D=6, Dc=12
+  workload, stored by tests/golden/make_c3_gate.py from the oracle) holds
+  |dE_loc|/N <= 1e-4;
+* chains sampled with bf16 ratios and with float32 ratios give the same energy
+  within their statistical error.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import lattice as olat
+from oracle import philox
+from oracle import vmc
+from paper_1908_09359_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_gate_16x16_D6_Dc12.json")
+
+
+def _B():
+    from paper_1908_09359_amd import binding as B
+    return B
+
+
+def n_bonds(Ly, Lx):
+    return Ly * (Lx - 1) + (Ly - 1) * Lx
+
+
+def _traced_sweep(Ly, Lx, D, Dc, prec, T, starts, seed):
+    """One measured sweep of len(starts) chains with the ratio trace on."""
+    import torch
+    B = _B()
+    n = len(starts)
+    ctx = B.Context(B.lattice(Ly, Lx, D, Dc, 1.0, 0.0, prec, n), seed=seed)
+    dev = torch.device("cuda")
+    ctx.vp_set_tensors(0, torch.tensor(T, dtype=torch.float64, device=dev))
+    ctx.vp_init_chains(0, torch.tensor(np.asarray(starts), dtype=torch.int8, device=dev))
+    tr = torch.full((n, n_bonds(Ly, Lx), 2), -7.0, dtype=torch.float64, device=dev)
+    ctx.vp_trace_ratios(0, tr)
+    lp = torch.empty(n, dtype=torch.float64, device=dev)
+    sg = torch.empty(n, dtype=torch.int8, device=dev)
+    el = torch.empty(n, dtype=torch.float64, device=dev)
+    so = torch.empty((n, Ly * Lx), dtype=torch.int8, device=dev)
+    ctx.vp_sample(0, 0, 1, lp, sg, el, None, so, None)
+    ctx.vp_sync()
+    out = dict(trace=tr.cpu().numpy(), spins=so.cpu().numpy(), e_loc=el.cpu().numpy(),
+               log_abs_psi=lp.cpu().numpy())
+    ctx.vp_trace_ratios(0, None)
+    ctx.close()
+    return out
+
+
+def _replay(T, lat, start, seed, chain, trace):
+    """The oracle's float64 ratios along the sampler's own decisions."""
+    ch = vmc.Chain(lat, start, seed, 0, chain)
+    ch.trace = {}
+    ch.forced = {b: bool(trace[b, 1] == 1.0) for b in range(trace.shape[0])}
+    vmc.run_chain(T, lat, ch, 1, 0)
+    return ch.trace, ch.spins
+
+
+def _check_sweep(Ly, Lx, D, Dc, prec, n, seed):
+    T = W.random_tensors(Ly, Lx, D, seed=seed)
+    lat = olat.Lattice(Ly, Lx, D, Dc)
+    starts = [olat.neel_shuffled(lat, seed, 0, c) for c in range(n)]
+    g = _traced_sweep(Ly, Lx, D, Dc, prec, T, starts, seed)
+    rel = []
+    for c in range(n):
+        tr = g["trace"][c]
+        assert np.all(tr[:, 1] >= 0.0), "every bond must be written"
+        ref, spins = _replay(T, lat, starts[c], seed, c, tr)
+        # the sampler's final state is the oracle's under the same decisions
+        assert np.array_equal(g["spins"][c], spins), c
+        for b in range(tr.shape[0]):
+            if b not in ref:
+                assert tr[b, 0] == 0.0 and tr[b, 1] == 0.0, (c, b)
+                continue
+            # decision logic: bit-exact from the sampler's own ratio and the shared uniform
+            u = philox.metropolis_uniform(seed, 0, c, 0, b)
+            assert (u < tr[b, 0] ** 2) == (tr[b, 1] == 1.0), (c, b)
+            rel.append(abs(tr[b, 0] - ref[b]) / max(abs(ref[b]), 1e-300))
+    return np.array(rel)
+
+
+def test_trace_fp64_matches_oracle():
+    """The trace itself: float64 ratios equal the oracle's to rounding."""
+    print("trace fp64 4x4 D=2 Dc=4 4 chains", flush=True)
+    rel = _check_sweep(4, 4, 2, 4, _B().VP_FP64, 4, seed=12)
+    assert len(rel) > 0 and rel.max() <= 1e-10
+
+
+@pytest.mark.parametrize("Ly,Lx,D,Dc", [(6, 6, 4, 8), (6, 6, 3, 6), (8, 8, 6, 12)])
+def test_sampling_ratios_bf16(Ly, Lx, D, Dc):
+    """bf16-operand ratios against the float64 oracle along the same sweep.
+
+    bf16 keeps 8 significant bits: each operand rounding is a relative
+    perturbation of at most u = 2^-9, and a ratio is a quotient of two networks
+    of ~Lx column steps, each step rounding its three operands once.  A
+    network value then carries about sqrt(3 Lx) independent u-sized relative
+    errors, amplified by its cancellation (sum |terms| / |sum|, O(1)-O(10) for
+    these Gaussian tensors).  Bounds: median relative error <= 8 u sqrt(3 Lx),
+    and 95% of ratios within 64 u sqrt(3 Lx); App. D's estimate for the
+    sampler's tolerance (|dR/R| of a few per cent changes acceptance rates by
+    as much) is the scale these protect.
+    """
+    print(f"trace bf16 {Ly}x{Lx} D={D} Dc={Dc}", flush=True)
+    rel = _check_sweep(Ly, Lx, D, Dc, _B().VP_BF16, 3, seed=20 + D)
+    u = 2.0 ** -9
+    scale = u * np.sqrt(3 * Lx)
+    print(f"bf16 ratio rel err: median {np.median(rel):.3e} p95 {np.quantile(rel, 0.95):.3e} "
+          f"max {rel.max():.3e} (n={len(rel)}, u sqrt(3Lx) = {scale:.3e})", flush=True)
+    assert np.median(rel) <= 8 * scale
+    assert np.quantile(rel, 0.95) <= 64 * scale
+
+
+def test_sampling_ratios_fp32():
+    """The same replay in float32: ratios to float32 rounding (u = 2^-24, same growth model)."""
+    print("trace fp32 6x6 D=4 Dc=8", flush=True)
+    rel = _check_sweep(6, 6, 4, 8, _B().VP_FP32, 3, seed=31)
+    scale = 2.0 ** -24 * np.sqrt(3 * 6)
+    print(f"fp32 ratio rel err: median {np.median(rel):.3e} max {rel.max():.3e}", flush=True)
+    assert np.median(rel) <= 64 * scale
+    assert np.quantile(rel, 0.95) <= 1024 * scale
+
+
+def test_bf16_fixed_config_gate_16x16_D6_Dc12():
+    """64 fixed configurations of the 16x16, D=6, Dc=12 workload: |dE_loc|/N <= 1e-4."""
+    import torch
+    B = _B()
+    with open(GOLDEN) as f:
+        doc = json.load(f)
+    w = doc["workload"]
+    Ly, Lx, D, Dc = w["Ly"], w["Lx"], w["D"], w["Dc"]
+    N = Ly * Lx
+    T = W.random_tensors(Ly, Lx, D, seed=w["tensor_seed"], perturb=w["perturb"])
+    cfgs = np.array([[int(ch) for ch in r["spins"]] for r in doc["configs"]], dtype=np.int8)
+    n = len(cfgs)
+    print(f"bf16 gate {Ly}x{Lx} D={D} Dc={Dc} {n} configs", flush=True)
+    ctx = B.Context(B.lattice(Ly, Lx, D, Dc, w["J1"], w["J2"], B.VP_BF16, n), seed=1)
+    dev = torch.device("cuda")
+    ctx.vp_set_tensors(0, torch.tensor(T, dtype=torch.float64, device=dev))
+    lp = torch.empty(n, dtype=torch.float64, device=dev)
+    sg = torch.empty(n, dtype=torch.int8, device=dev)
+    el = torch.empty(n, dtype=torch.float64, device=dev)
+    dl = torch.empty((n, ctx.num_params() // 2), dtype=torch.float32, device=dev)
+    ctx.vp_eval(0, torch.tensor(cfgs, device=dev), n, lp, sg, el, dl, None)
+    ctx.vp_sync()
+    e_ref = np.array([r["e_loc"] for r in doc["configs"]])
+    lp_ref = np.array([r["log_abs_psi"] for r in doc["configs"]])
+    sg_ref = np.array([r["sign"] for r in doc["configs"]])
+    idx = np.array(doc["dlnpsi_index"])
+    dl_ref = np.array([r["dlnpsi_sample"] for r in doc["configs"]])
+    dl_norm = np.array([r["dlnpsi_norm"] for r in doc["configs"]])
+    e_err = np.abs(el.cpu().numpy() - e_ref) / N
+    lp_err = np.abs(lp.cpu().numpy() - lp_ref)
+    g = dl.double().cpu().numpy()
+    dl_err = np.linalg.norm(g[:, idx] - dl_ref, axis=1) / (dl_norm * np.sqrt(len(idx) / g.shape[1]))
+    ctx.close()
+    print(f"max |dE|/N {e_err.max():.3e}  max |dlog|psi|| {lp_err.max():.3e}  "
+          f"dlnpsi rel (sampled, rms-normalised) max {dl_err.max():.3e}", flush=True)
+    assert e_err.max() <= 1e-4
+    assert np.array_equal(sg.cpu().numpy(), sg_ref)
+    assert lp_err.max() <= 1e-3
+    assert dl_err.max() <= 1e-2
+
+
+def test_bf16_chains_energy_matches_fp32():
+    """Chains driven by bf16 ratios sample the same distribution as float32 chains.
+
+    6x6, D=4, Dc=8, 256 chains, 4 burn-in + 12 measured sweeps each; the chain
+    means are independent, so the standard error of the mean is their spread
+    over sqrt(chains); the two estimates must agree within 4 combined standard
+    errors.
+    """
+    import torch
+    B = _B()
+    Ly = Lx = 6
+    T = W.random_tensors(Ly, Lx, 4, seed=606)
+    means = {}
+    for prec in (B.VP_FP32, B.VP_BF16):
+        print(f"chains prec={prec} 6x6 D=4 Dc=8 256 x (4+12)", flush=True)
+        n, nm = 256, 12
+        ctx = B.Context(B.lattice(Ly, Lx, 4, 8, 1.0, 0.0, prec, n), seed=4242)
+        dev = torch.device("cuda")
+        ctx.vp_set_tensors(0, torch.tensor(T, dtype=torch.float64, device=dev))
+        ctx.vp_init_chains(0, None)
+        lp = torch.empty(n * nm, dtype=torch.float64, device=dev)
+        sg = torch.empty(n * nm, dtype=torch.int8, device=dev)
+        el = torch.empty(n * nm, dtype=torch.float64, device=dev)
+        ctx.vp_sample(0, 4, nm, lp, sg, el)
+        ctx.vp_sync()
+        cm = el.cpu().numpy().reshape(n, nm).mean(axis=1) / (Ly * Lx)
+        means[prec] = (cm.mean(), cm.std(ddof=1) / np.sqrt(n))
+        ctx.close()
+    (m1, s1), (m2, s2) = means[B.VP_FP32], means[B.VP_BF16]
+    print(f"E/N fp32 {m1:.5f} +- {s1:.5f}   bf16 {m2:.5f} +- {s2:.5f}", flush=True)
+    assert abs(m1 - m2) <= 4 * np.hypot(s1, s2)

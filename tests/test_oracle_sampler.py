@@ -93,3 +93,26 @@ def test_horizontal_only_is_not_ergodic():
     ch = vmc.Chain(lat, np.array([0, 1, 0, 1, 0, 1], dtype=np.int8), 1, 0, 0)
     out = vmc.run_chain(T, lat, ch, 0, 20)
     assert all(x['spins'].sum() == 3 for x in out)
+
+
+def test_replay_hooks_reproduce_the_chain():
+    """Forcing the decisions a chain took reproduces it; the trace holds the ratios it used."""
+    from oracle import philox
+    from paper_1908_09359_amd import workloads as W
+    lat = Lattice(4, 4, 2, 4)
+    T = W.random_tensors(4, 4, 2, seed=3)
+    start = neel_shuffled(lat, 5, 0, 1)
+    ch = vmc.Chain(lat, start, 5, 0, 1)
+    ch.trace = {}
+    vmc.run_chain(T, lat, ch, 1, 0)
+    taken = {b: philox.metropolis_uniform(5, 0, 1, 0, b) < r * r for b, r in ch.trace.items()}
+    assert ch.trace and any(taken.values())
+    rep = vmc.Chain(lat, start, 5, 0, 1)
+    rep.trace, rep.forced = {}, taken
+    vmc.run_chain(T, lat, rep, 1, 0)
+    assert np.array_equal(rep.spins, ch.spins) and rep.trace == ch.trace
+    # rejecting everything leaves the start untouched
+    none = vmc.Chain(lat, start, 5, 0, 1)
+    none.forced = {b: False for b in range(4 * 3 + 3 * 4)}
+    vmc.run_chain(T, lat, none, 1, 0)
+    assert np.array_equal(none.spins, start)
