@@ -32,6 +32,8 @@ TAG_PERTURB = 2    # extra Gaussian perturbation:    counter (param, 0, 0, TAG)
 TAG_SHUFFLE = 3    # Fisher-Yates start shuffle:     counter (chain, 0, i, TAG)
 TAG_METRO = 4      # Metropolis uniform:             counter (chain, sweep, bond, TAG)
 TAG_SGD = 5        # sign-gradient random step:      counter (param, step, 0, TAG)
+TAG_PLAQ = 6       # plaquette proposal (word 0: propose, word 1: accept):
+                   #                                 counter (chain, sweep, plaquette, TAG)
 
 
 def philox4x64_10(counter, key):
@@ -73,3 +75,9 @@ def metropolis_uniform(seed, lattice_id, chain, sweep, bond):
     """The uniform r compared with the acceptance ratio at one visited bond."""
     w = philox4x64_10((chain, sweep, bond, TAG_METRO), (seed, lattice_id))
     return uniform53(w[0])
+
+
+def plaquette_uniforms(seed, lattice_id, chain, sweep, plaquette):
+    """(u_propose, u_accept) of the plaquette move q = y*(Lx-1) + x."""
+    w = philox4x64_10((chain, sweep, plaquette, TAG_PLAQ), (seed, lattice_id))
+    return uniform53(w[0]), uniform53(w[1])
