@@ -78,6 +78,12 @@ typedef enum {
 
 typedef enum { VP_FP64 = 0, VP_FP32 = 1, VP_BF16 = 2 } vp_prec;
 
+/* Samplers (vp_set_sampler).  VP_SAMPLER_PAIR_SEQ: the sequential
+ * nearest-neighbour exchange sweep of Sec. II.A Eq. (9).
+ * VP_SAMPLER_LEARNED_PLAQ: the same sweep with a learned plaquette move after
+ * each vertical bond (see vp_set_sampler). */
+typedef enum { VP_SAMPLER_PAIR_SEQ = 0, VP_SAMPLER_LEARNED_PLAQ = 1 } vp_sampler;
+
 typedef struct {
   int32_t Ly, Lx;      /* lattice extent */
   int32_t D;           /* PEPS virtual bond dimension */
@@ -142,6 +148,60 @@ vp_status vp_trace_ratios(vp_ctx* ctx, int32_t lat, double* trace_dev);
 vp_status vp_eval(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev, int32_t n_cfg,
                   double* log_abs_psi_dev, int8_t* sign_dev, double* e_loc_dev,
                   void* dlnpsi_dev, double* ratios_dev);
+
+/* Psi(S')/Psi(S) for the flip of all four spins of every plaquette (y, x)
+ * (sites (y,x), (y,x+1), (y+1,x), (y+1,x+1)) that holds two up and two down
+ * spins; ratios_dev [n_cfg][(Ly-1)(Lx-1)] float64, 0 for the other plaquettes.
+ * Each ratio is the two-row network of rows y, y+1 with columns x and x+1
+ * exchanged, divided by the same network with the current tensors (the
+ * construction App. C uses for vertical pairs).  Same preconditions and
+ * synchronous error reporting as vp_eval; invalidates the sampler's state. */
+vp_status vp_plaquette_ratios(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev, int32_t n_cfg,
+                              double* ratios_dev);
+
+/* ---- learned plaquette proposal (not in the paper) ------------------------
+ * Network f(S): spins as +1 (s = 0) / -1 (s = 1) in one channel;
+ * conv3x3(1->32), ReLU, conv3x3(32->32), ReLU, conv3x3(32->32), ReLU,
+ * conv3x3(32->1), zero padding at the open boundary,
+ * out[co][y][x] = b[co] + sum W[co][ci][ky][kx] in[ci][y+ky-1][x+kx-1].
+ * The logit of plaquette (y, x) is the output at (y, x); its propensity is
+ * pi = sigmoid(logit).  Parameters: float32, flat, in the order
+ * W1[32][1][3][3] b1[32] W2[32][32][3][3] b2[32] W3[32][32][3][3] b3[32]
+ * W4[1][32][3][3] b4[1] (vp_proposal_num_params() = 19105 numbers). */
+int64_t vp_proposal_num_params(void);
+/* Copy the parameters in (device pointer); resets the optimiser state. */
+vp_status vp_proposal_set_weights(vp_ctx* ctx, int32_t lat, const float* w_dev);
+vp_status vp_proposal_get_weights(vp_ctx* ctx, int32_t lat, float* w_dev);
+/* Logit maps of n configurations: logits_dev [n][Ly][Lx] float32.  Waits. */
+vp_status vp_proposal_forward(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev, int32_t n, float* logits_dev);
+/* Training loss and its gradient on n configurations: the mean over all
+ * movable plaquettes of the binary cross-entropy of pi against the acceptance
+ * probability a = min(1, rho^2), rho from ratios_dev (as written by
+ * vp_plaquette_ratios).  grad_dev [vp_proposal_num_params()] float32,
+ * loss_dev one float64.  Waits. */
+vp_status vp_proposal_loss_grad(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev, const double* ratios_dev,
+                                int32_t n, float* grad_dev, double* loss_dev);
+/* Adam (beta1 0.9, beta2 0.999, eps 1e-8, step size lr) on that loss over
+ * epochs passes of shuffled minibatches of `batch` configurations (whole
+ * batches only; the shuffle is seeded by seed).  loss_dev [epochs] float64
+ * (mean minibatch loss per epoch) may be NULL.  Allocates its workspace for
+ * the call and waits. */
+vp_status vp_proposal_train(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev, const double* ratios_dev,
+                            int64_t n, int32_t epochs, int32_t batch, double lr, uint64_t seed,
+                            double* loss_dev);
+/* Select the sampler of the following vp_sample calls.
+ * VP_SAMPLER_LEARNED_PLAQ (needs weights): within the row-pair step of every
+ * row y < Ly-1, right after the vertical bond (y,x)-(y+1,x), x < Lx-1, a
+ * plaquette (y, x) holding two up and two down spins is proposed with
+ * probability pi(S) (Philox word 0 of counter (chain, sweep, y(Lx-1)+x, 6))
+ * and its flip accepted iff u < rho^2 pi(S')/pi(S), u = word 1 of the same
+ * counter: Metropolis-Hastings for a propose-or-stay move, so |Psi|^2 stays
+ * the stationary distribution whatever the weights.  The network runs in the
+ * working precision (float64 for VP_FP64, float32 otherwise). */
+vp_status vp_set_sampler(vp_ctx* ctx, int32_t lat, int32_t sampler);
+/* Move counters since vp_init_chains: counts_dev [n_chains][4] int64 =
+ * (pair accepted, pair proposed, plaquette accepted, plaquette proposed). */
+vp_status vp_move_counts(vp_ctx* ctx, int32_t lat, int64_t* counts_dev);
 
 /* Eq. (5): grad = <G E_loc> - <G><E_loc> over n_samples samples (compact
  * dlnpsi in the working precision, their spins [n][N]); grad_dev [Np] float64,

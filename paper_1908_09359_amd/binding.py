@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libvmcpeps.so")
 VP_OK, VP_ERR_ARG, VP_ERR_SHAPE, VP_ERR_OOM, VP_ERR_DEVICE = 0, 1, 2, 3, 4
 VP_ERR_ZERO_AMPLITUDE, VP_ERR_NONFINITE, VP_ERR_UNSUPPORTED = 5, 6, 7
 VP_FP64, VP_FP32, VP_BF16 = 0, 1, 2
+VP_SAMPLER_PAIR_SEQ, VP_SAMPLER_LEARNED_PLAQ = 0, 1
 
 STATUS_NAMES = {0: "VP_OK", 1: "VP_ERR_ARG", 2: "VP_ERR_SHAPE", 3: "VP_ERR_OOM", 4: "VP_ERR_DEVICE",
                 5: "VP_ERR_ZERO_AMPLITUDE", 6: "VP_ERR_NONFINITE", 7: "VP_ERR_UNSUPPORTED"}
@@ -21,7 +22,9 @@ STATUS_NAMES = {0: "VP_OK", 1: "VP_ERR_ARG", 2: "VP_ERR_SHAPE", 3: "VP_ERR_OOM",
 EXPORTED = ["vp_create", "vp_destroy", "vp_last_error", "vp_num_params", "vp_workspace_bytes",
             "vp_set_tensors", "vp_get_tensors", "vp_init_tensors", "vp_init_chains", "vp_sample",
             "vp_eval", "vp_gradient", "vp_sr_update", "vp_sign_sgd_update", "vp_sync",
-            "vp_timing_enable", "vp_timing_read", "vp_stats_tau", "vp_trace_ratios"]
+            "vp_timing_enable", "vp_timing_read", "vp_stats_tau", "vp_trace_ratios", "vp_plaquette_ratios",
+            "vp_proposal_num_params", "vp_proposal_set_weights", "vp_proposal_get_weights", "vp_proposal_forward",
+            "vp_proposal_loss_grad", "vp_proposal_train", "vp_set_sampler", "vp_move_counts"]
 
 PHASES = ["row3_envs", "hsweep", "row4_envs", "vsweep", "compress_up", "compress_down", "measure3",
           "measure4", "other"]
@@ -67,6 +70,15 @@ def _load():
         "vp_timing_read": ([P, P, P], I32),
         "vp_stats_tau": ([P, I32, I32, D, P, P, P], I32),
         "vp_trace_ratios": ([P, I32, P], I32),
+        "vp_plaquette_ratios": ([P, I32, P, I32, P], I32),
+        "vp_proposal_num_params": ([], I64),
+        "vp_proposal_set_weights": ([P, I32, P], I32),
+        "vp_proposal_get_weights": ([P, I32, P], I32),
+        "vp_proposal_forward": ([P, I32, P, I32, P], I32),
+        "vp_proposal_loss_grad": ([P, I32, P, P, I32, P, P], I32),
+        "vp_proposal_train": ([P, I32, P, P, I64, I32, I32, D, U64, P], I32),
+        "vp_set_sampler": ([P, I32, I32], I32),
+        "vp_move_counts": ([P, I32, P], I32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -76,6 +88,10 @@ def _load():
 
 
 LIB = _load()
+
+
+def vp_proposal_num_params():
+    return int(LIB.vp_proposal_num_params())
 
 
 def _ptr(t):
@@ -163,6 +179,31 @@ class Context:
         """trace: float64 [n_chains, n_bonds, 2] device tensor (kept alive by the caller) or None."""
         self._trace = trace
         self._check(LIB.vp_trace_ratios(self.h, lat, _ptr(trace)))
+
+    def vp_plaquette_ratios(self, lat, spins, n_cfg, ratios):
+        self._check(LIB.vp_plaquette_ratios(self.h, lat, _ptr(spins), n_cfg, _ptr(ratios)))
+
+    def vp_proposal_set_weights(self, lat, w):
+        self._check(LIB.vp_proposal_set_weights(self.h, lat, _ptr(w)))
+
+    def vp_proposal_get_weights(self, lat, w):
+        self._check(LIB.vp_proposal_get_weights(self.h, lat, _ptr(w)))
+
+    def vp_proposal_forward(self, lat, spins, n, logits):
+        self._check(LIB.vp_proposal_forward(self.h, lat, _ptr(spins), n, _ptr(logits)))
+
+    def vp_proposal_loss_grad(self, lat, spins, ratios, n, grad, loss):
+        self._check(LIB.vp_proposal_loss_grad(self.h, lat, _ptr(spins), _ptr(ratios), n, _ptr(grad), _ptr(loss)))
+
+    def vp_proposal_train(self, lat, spins, ratios, n, epochs, batch, lr, seed, loss=None):
+        self._check(LIB.vp_proposal_train(self.h, lat, _ptr(spins), _ptr(ratios), n, epochs, batch, lr,
+                                          ctypes.c_uint64(seed), _ptr(loss)))
+
+    def vp_set_sampler(self, lat, sampler):
+        self._check(LIB.vp_set_sampler(self.h, lat, sampler))
+
+    def vp_move_counts(self, lat, counts):
+        self._check(LIB.vp_move_counts(self.h, lat, _ptr(counts)))
 
     def vp_eval(self, lat, spins, n_cfg, log_abs_psi, sign, e_loc, dlnpsi=None, ratios=None):
         self._check(LIB.vp_eval(self.h, lat, _ptr(spins), n_cfg, _ptr(log_abs_psi), _ptr(sign), _ptr(e_loc),

@@ -13,6 +13,7 @@
 
 #include "../../include/vmcpeps.h"
 #include "vp_kernels.hpp"
+#include "vp_net.hpp"
 
 using namespace vp;
 
@@ -40,6 +41,13 @@ struct Lattice {
   int32_t *d_kU = nullptr, *d_kD = nullptr, *d_dims = nullptr, *d_sizes = nullptr;
   int64_t *d_offs = nullptr, *d_coff = nullptr;
   double* d_scratch = nullptr;  // small scalar scratch
+  // proposal network: float32 master, working-precision copy, Adam moments
+  float* d_net = nullptr;
+  double* d_net64 = nullptr;
+  float* d_adam = nullptr;      // [2][NET_NPARAM]: m, v
+  int64_t adam_t = 0;
+  bool net_ready = false;
+  int32_t sampler = VP_SAMPLER_PAIR_SEQ;
   LatDev dev{};
   bool tensors_ready = false;
   bool chains_ready = false;
@@ -262,7 +270,7 @@ void run_sweep(vp_ctx* ctx, Lattice& L, const SampleOut* o, hipStream_t s) {
     TIMED(r, VP_PH_HSWEEP, launch_hsweep<T>(L.dev, y, y == Ly - 1, bf, s));
     if (y < Ly - 1) {
       TIMED(r, VP_PH_ROW4_ENVS, launch_row4_right<T>(L.dev, y, bf, s));
-      TIMED(r, VP_PH_VSWEEP, launch_vsweep<T>(L.dev, y, bf, s));
+      TIMED(r, VP_PH_VSWEEP, launch_vsweep<T>(L.dev, y, bf, L.sampler == VP_SAMPLER_LEARNED_PLAQ, s));
       TIMED(r, VP_PH_COMPRESS_UP, launch_compress<T>(L.dev, y, 1, s));
     }
   }
@@ -307,6 +315,83 @@ vp_status check_flags(vp_ctx* ctx, Lattice& L) {
   if (zero) return fail(ctx, VP_ERR_ZERO_AMPLITUDE, "%d chain(s) met a zero amplitude", zero);
   return VP_OK;
 }
+
+// Checks that every configuration is 0/1 and in the S^z_tot = 0 sector.
+vp_status check_configs(vp_ctx* ctx, const Lattice& L, const int8_t* spins_dev, int64_t n_cfg) {
+  std::vector<int8_t> h((size_t)n_cfg * L.N);
+  HIP_TRY(ctx, hipMemcpyAsync(h.data(), spins_dev, h.size(), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  for (int64_t ch = 0; ch < n_cfg; ++ch) {
+    int up = 0;
+    for (int i = 0; i < L.N; ++i) {
+      int8_t v = h[(size_t)ch * L.N + i];
+      if (v != 0 && v != 1) return fail(ctx, VP_ERR_SHAPE, "spins must be 0 or 1");
+      up += v;
+    }
+    if (2 * up != L.N)
+      return fail(ctx, VP_ERR_SHAPE, "configuration %lld is not in the S^z_tot = 0 sector", (long long)ch);
+  }
+  return VP_OK;
+}
+
+// The evaluation pass on fixed configurations with the outputs of o; reports
+// device-side errors synchronously.
+vp_status eval_configs(vp_ctx* ctx, Lattice* L, const int8_t* spins_dev, int32_t n_cfg, SampleOut o) {
+  if (!L->tensors_ready) return fail(ctx, VP_ERR_ARG, "tensors must be set first");
+  if (n_cfg < 1 || n_cfg > L->p.n_chains) return fail(ctx, VP_ERR_ARG, "need 1 <= n_cfg <= n_chains");
+  vp_status st = check_configs(ctx, *L, spins_dev, n_cfg);
+  if (st != VP_OK) return st;
+  hipStream_t s = ctx->stream;
+  // Evaluation reuses the chain slots; the sampler's state is invalidated.
+  launch_copy_spins(L->dev, spins_dev, n_cfg, s);
+  LatDev D = L->dev;
+  D.n_chains = n_cfg;
+  const vp_lattice& p = L->p;
+  o.n_meas = 1;
+  o.m = 0;
+  o.np_half = L->Np / 2;
+  o.n_pairs = p.Ly * (p.Lx - 1) + (p.Ly - 1) * p.Lx + (p.J2 != 0.0 ? 2 * (p.Ly - 1) * (p.Lx - 1) : 0);
+  if (p.prec == VP_FP64) run_eval<double>(D, o, n_cfg, s); else run_eval<float>(D, o, n_cfg, s);
+  HIP_TRY(ctx, hipGetLastError());
+  L->chains_ready = false;
+  L->lower_valid = false;
+  std::vector<ChainMeta> m(n_cfg);
+  HIP_TRY(ctx, hipMemcpyAsync(m.data(), L->meta, sizeof(ChainMeta) * n_cfg, hipMemcpyDeviceToHost, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  for (int i = 0; i < n_cfg; ++i) {
+    if (m[i].flags & FLAG_NONFINITE) return fail(ctx, VP_ERR_NONFINITE, "configuration %d: non-finite value", i);
+    if (m[i].flags & FLAG_ZERO) return fail(ctx, VP_ERR_ZERO_AMPLITUDE, "configuration %d: zero amplitude", i);
+  }
+  return VP_OK;
+}
+
+// Workspace of one batched network call of n configurations.
+struct NetWork {
+  float* work = nullptr;
+  double* part = nullptr;
+  int* cnt = nullptr;
+  double* scal = nullptr;
+  float* grad = nullptr;
+  int8_t* sb = nullptr;
+  double* rb = nullptr;
+  int32_t* idx = nullptr;
+  bool alloc(const Lattice& L, int n) {
+    const int H = L.p.Ly, W = L.p.Lx;
+    return hipMalloc((void**)&work, sizeof(float) * net_work_floats(n, H, W)) == hipSuccess &&
+           hipMalloc((void**)&part, sizeof(double) * n) == hipSuccess &&
+           hipMalloc((void**)&cnt, sizeof(int) * n) == hipSuccess &&
+           hipMalloc((void**)&scal, sizeof(double) * 4) == hipSuccess &&
+           hipMalloc((void**)&grad, sizeof(float) * NET_NPARAM) == hipSuccess &&
+           hipMalloc((void**)&sb, (size_t)n * H * W) == hipSuccess &&
+           hipMalloc((void**)&rb, sizeof(double) * n * (H - 1) * (W - 1)) == hipSuccess &&
+           hipMalloc((void**)&idx, sizeof(int32_t) * n) == hipSuccess;
+  }
+  ~NetWork() {
+    void* p[] = {work, part, cnt, scal, grad, sb, rb, idx};
+    for (void* q : p)
+      if (q) hipFree(q);
+  }
+};
 
 }  // namespace
 
@@ -377,7 +462,10 @@ vp_status vp_create(const vp_lattice* lats, int32_t n_lats, uint64_t seed, void*
               alloc((void**)&L.d_kU, 4 * L.kU.size()) && alloc((void**)&L.d_kD, 4 * L.kD.size()) &&
               alloc((void**)&L.d_dims, 4 * L.dims.size()) && alloc((void**)&L.d_sizes, 4 * L.sizes.size()) &&
               alloc((void**)&L.d_offs, 8 * L.offs.size()) && alloc((void**)&L.d_coff, 8 * L.coff.size()) &&
-              alloc((void**)&L.d_scratch, 64 * sizeof(double));
+              alloc((void**)&L.d_scratch, 64 * sizeof(double)) &&
+              alloc((void**)&L.d_net, sizeof(float) * NET_NPARAM) &&
+              alloc((void**)&L.d_net64, sizeof(double) * NET_NPARAM) &&
+              alloc((void**)&L.d_adam, 2 * sizeof(float) * NET_NPARAM);
     if (!ok) {
       vp_destroy(ctx);
       return fail(nullptr, VP_ERR_OOM, "device allocation failed for lattice %d", i);
@@ -403,6 +491,7 @@ vp_status vp_create(const vp_lattice* lats, int32_t n_lats, uint64_t seed, void*
     D.iws = L.iws; D.iws_stride = P.iws; D.dws = L.dws; D.dws_stride = P.dws;
     D.meta = L.meta; D.spins = L.spins;
     D.trace = nullptr;
+    D.net = p.prec == VP_FP64 ? (const void*)L.d_net64 : (const void*)L.d_net;
     D.n_bonds = p.Ly * (p.Lx - 1) + (p.Ly - 1) * p.Lx;
     D.kU = L.d_kU; D.kD = L.d_kD; D.dims = L.d_dims; D.coff = L.d_coff;
     if (p.prec == VP_FP64) launch_init_trivial<double>(D, ctx->stream);
@@ -422,7 +511,7 @@ vp_status vp_destroy(vp_ctx* ctx) {
   for (hipEvent_t e : ctx->ev) hipEventDestroy(e);
   for (auto& L : ctx->lats) {
     void* ptrs[] = {L.T, L.Tw, L.ws, L.cws, L.iws, L.dws, L.meta, L.spins, L.d_kU, L.d_kD,
-                    L.d_dims, L.d_sizes, L.d_offs, L.d_coff, L.d_scratch};
+                    L.d_dims, L.d_sizes, L.d_offs, L.d_coff, L.d_scratch, L.d_net, L.d_net64, L.d_adam};
     for (void* q : ptrs)
       if (q) hipFree(q);
   }
@@ -542,49 +631,153 @@ vp_status vp_eval(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev, int32_t n_c
                   int8_t* sign_dev, double* e_loc_dev, void* dlnpsi_dev, double* ratios_dev) {
   Lattice* L = get_lat(ctx, lat);
   if (!L || !spins_dev) return fail(ctx, VP_ERR_ARG, "bad lattice index or null spins");
-  if (n_cfg < 1 || n_cfg > L->p.n_chains) return fail(ctx, VP_ERR_ARG, "need 1 <= n_cfg <= n_chains");
-  if (!L->tensors_ready) return fail(ctx, VP_ERR_ARG, "tensors must be set first");
   if (!log_abs_psi_dev || !sign_dev || !e_loc_dev) return fail(ctx, VP_ERR_ARG, "null output pointer");
-  std::vector<int8_t> h((size_t)n_cfg * L->N);
-  HIP_TRY(ctx, hipMemcpyAsync(h.data(), spins_dev, h.size(), hipMemcpyDeviceToHost, ctx->stream));
-  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-  for (int ch = 0; ch < n_cfg; ++ch) {
-    int up = 0;
-    for (int i = 0; i < L->N; ++i) {
-      int8_t v = h[(size_t)ch * L->N + i];
-      if (v != 0 && v != 1) return fail(ctx, VP_ERR_SHAPE, "spins must be 0 or 1");
-      up += v;
-    }
-    if (2 * up != L->N) return fail(ctx, VP_ERR_SHAPE, "configuration %d is not in the S^z_tot = 0 sector", ch);
-  }
-  hipStream_t s = ctx->stream;
-  // Evaluation reuses the chain slots; the sampler's state is invalidated.
-  launch_copy_spins(L->dev, spins_dev, n_cfg, s);
-  LatDev D = L->dev;
-  D.n_chains = n_cfg;
-  const vp_lattice& p = L->p;
   SampleOut o{};
   o.log_abs_psi = log_abs_psi_dev;
   o.sign = sign_dev;
   o.e_loc = e_loc_dev;
   o.dlnpsi = dlnpsi_dev;
   o.ratios = ratios_dev;
-  o.n_meas = 1;
-  o.m = 0;
-  o.np_half = L->Np / 2;
-  o.n_pairs = p.Ly * (p.Lx - 1) + (p.Ly - 1) * p.Lx + (p.J2 != 0.0 ? 2 * (p.Ly - 1) * (p.Lx - 1) : 0);
-  if (p.prec == VP_FP64) run_eval<double>(D, o, n_cfg, s); else run_eval<float>(D, o, n_cfg, s);
+  return eval_configs(ctx, L, spins_dev, n_cfg, o);
+}
+
+vp_status vp_plaquette_ratios(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev, int32_t n_cfg,
+                              double* ratios_dev) {
+  Lattice* L = get_lat(ctx, lat);
+  if (!L || !spins_dev || !ratios_dev) return fail(ctx, VP_ERR_ARG, "bad lattice index or null pointer");
+  if (L->p.Ly < 2 || L->p.Lx < 2) return fail(ctx, VP_ERR_SHAPE, "plaquettes need Ly, Lx >= 2");
+  SampleOut o{};
+  o.plaq = ratios_dev;
+  return eval_configs(ctx, L, spins_dev, n_cfg, o);
+}
+
+int64_t vp_proposal_num_params(void) { return NET_NPARAM; }
+
+vp_status vp_proposal_set_weights(vp_ctx* ctx, int32_t lat, const float* w_dev) {
+  Lattice* L = get_lat(ctx, lat);
+  if (!L || !w_dev) return fail(ctx, VP_ERR_ARG, "bad lattice index or null pointer");
+  hipStream_t s = ctx->stream;
+  HIP_TRY(ctx, hipMemcpyAsync(L->d_net, w_dev, sizeof(float) * NET_NPARAM, hipMemcpyDeviceToDevice, s));
+  net_cast_f64(L->d_net, L->d_net64, s);
+  HIP_TRY(ctx, hipMemsetAsync(L->d_adam, 0, 2 * sizeof(float) * NET_NPARAM, s));
   HIP_TRY(ctx, hipGetLastError());
-  L->chains_ready = false;
-  L->lower_valid = false;
-  // Errors in evaluated configurations are reported synchronously.
-  std::vector<ChainMeta> m(n_cfg);
-  HIP_TRY(ctx, hipMemcpyAsync(m.data(), L->meta, sizeof(ChainMeta) * n_cfg, hipMemcpyDeviceToHost, s));
+  L->adam_t = 0;
+  L->net_ready = true;
+  return VP_OK;
+}
+
+vp_status vp_proposal_get_weights(vp_ctx* ctx, int32_t lat, float* w_dev) {
+  Lattice* L = get_lat(ctx, lat);
+  if (!L || !w_dev) return fail(ctx, VP_ERR_ARG, "bad lattice index or null pointer");
+  if (!L->net_ready) return fail(ctx, VP_ERR_ARG, "the proposal network has no weights yet");
+  HIP_TRY(ctx, hipMemcpyAsync(w_dev, L->d_net, sizeof(float) * NET_NPARAM, hipMemcpyDeviceToDevice, ctx->stream));
+  return VP_OK;
+}
+
+vp_status vp_set_sampler(vp_ctx* ctx, int32_t lat, int32_t sampler) {
+  Lattice* L = get_lat(ctx, lat);
+  if (!L) return fail(ctx, VP_ERR_ARG, "bad lattice index");
+  if (sampler != VP_SAMPLER_PAIR_SEQ && sampler != VP_SAMPLER_LEARNED_PLAQ)
+    return fail(ctx, VP_ERR_ARG, "unknown sampler %d", sampler);
+  if (sampler == VP_SAMPLER_LEARNED_PLAQ && !L->net_ready)
+    return fail(ctx, VP_ERR_ARG, "the learned sampler needs proposal weights (vp_proposal_set_weights)");
+  if (sampler == VP_SAMPLER_LEARNED_PLAQ && (L->p.Ly < 2 || L->p.Lx < 2))
+    return fail(ctx, VP_ERR_SHAPE, "plaquettes need Ly, Lx >= 2");
+  L->sampler = sampler;
+  return VP_OK;
+}
+
+vp_status vp_move_counts(vp_ctx* ctx, int32_t lat, int64_t* counts_dev) {
+  Lattice* L = get_lat(ctx, lat);
+  if (!L || !counts_dev) return fail(ctx, VP_ERR_ARG, "bad lattice index or null pointer");
+  const int n = L->p.n_chains;
+  hipStream_t s = ctx->stream;
+  HIP_TRY(ctx, hipMemcpy2DAsync(counts_dev, 4 * sizeof(int64_t), (const char*)L->meta + offsetof(ChainMeta, accepted),
+                                sizeof(ChainMeta), 2 * sizeof(int64_t), n, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(ctx, hipMemcpy2DAsync(counts_dev + 2, 4 * sizeof(int64_t),
+                                (const char*)L->meta + offsetof(ChainMeta, p_accepted), sizeof(ChainMeta),
+                                2 * sizeof(int64_t), n, hipMemcpyDeviceToDevice, s));
+  return VP_OK;
+}
+
+vp_status vp_proposal_forward(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev, int32_t n, float* logits_dev) {
+  Lattice* L = get_lat(ctx, lat);
+  if (!L || !spins_dev || !logits_dev) return fail(ctx, VP_ERR_ARG, "bad lattice index or null pointer");
+  if (!L->net_ready) return fail(ctx, VP_ERR_ARG, "the proposal network has no weights yet");
+  if (n < 1) return fail(ctx, VP_ERR_ARG, "n must be >= 1");
+  NetWork w;
+  if (!w.alloc(*L, n)) return fail(ctx, VP_ERR_OOM, "proposal workspace allocation failed");
+  net_forward(L->d_net, spins_dev, n, L->p.Ly, L->p.Lx, w.work, logits_dev, ctx->stream);
+  HIP_TRY(ctx, hipGetLastError());
+  HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return VP_OK;
+}
+
+vp_status vp_proposal_loss_grad(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev, const double* ratios_dev,
+                                int32_t n, float* grad_dev, double* loss_dev) {
+  Lattice* L = get_lat(ctx, lat);
+  if (!L || !spins_dev || !ratios_dev || !grad_dev || !loss_dev)
+    return fail(ctx, VP_ERR_ARG, "bad lattice index or null pointer");
+  if (!L->net_ready) return fail(ctx, VP_ERR_ARG, "the proposal network has no weights yet");
+  if (n < 1) return fail(ctx, VP_ERR_ARG, "n must be >= 1");
+  if (L->p.Ly < 2 || L->p.Lx < 2) return fail(ctx, VP_ERR_SHAPE, "plaquettes need Ly, Lx >= 2");
+  NetWork w;
+  if (!w.alloc(*L, n)) return fail(ctx, VP_ERR_OOM, "proposal workspace allocation failed");
+  hipStream_t s = ctx->stream;
+  net_loss_grad(L->d_net, spins_dev, ratios_dev, n, L->p.Ly, L->p.Lx, w.work, w.part, w.cnt, w.scal, grad_dev, s);
+  HIP_TRY(ctx, hipMemcpyAsync(loss_dev, w.scal, sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIP_TRY(ctx, hipGetLastError());
   HIP_TRY(ctx, hipStreamSynchronize(s));
-  for (int i = 0; i < n_cfg; ++i) {
-    if (m[i].flags & FLAG_NONFINITE) return fail(ctx, VP_ERR_NONFINITE, "configuration %d: non-finite value", i);
-    if (m[i].flags & FLAG_ZERO) return fail(ctx, VP_ERR_ZERO_AMPLITUDE, "configuration %d: zero amplitude", i);
+  return VP_OK;
+}
+
+vp_status vp_proposal_train(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev, const double* ratios_dev,
+                            int64_t n, int32_t epochs, int32_t batch, double lr, uint64_t seed,
+                            double* loss_dev) {
+  Lattice* L = get_lat(ctx, lat);
+  if (!L || !spins_dev || !ratios_dev) return fail(ctx, VP_ERR_ARG, "bad lattice index or null pointer");
+  if (!L->net_ready) return fail(ctx, VP_ERR_ARG, "the proposal network has no weights yet");
+  if (n < 1 || epochs < 1 || batch < 1 || !(lr > 0.0)) return fail(ctx, VP_ERR_ARG, "need n, epochs, batch >= 1, lr > 0");
+  if (n > INT32_MAX) return fail(ctx, VP_ERR_ARG, "at most 2^31 - 1 training configurations");
+  if (L->p.Ly < 2 || L->p.Lx < 2) return fail(ctx, VP_ERR_SHAPE, "plaquettes need Ly, Lx >= 2");
+  const int nb = (int)std::min<int64_t>(batch, n);
+  NetWork w;
+  if (!w.alloc(*L, nb)) return fail(ctx, VP_ERR_OOM, "proposal workspace allocation failed");
+  hipStream_t s = ctx->stream;
+  const int H = L->p.Ly, W = L->p.Lx;
+  std::vector<int32_t> perm(n);
+  std::vector<double> eloss(epochs, 0.0);
+  std::vector<double> bl;
+  uint64_t state = seed ^ 0x9E3779B97F4A7C15ull;
+  auto next = [&]() {  // splitmix64 (Steele, Lea, Flood 2014) for the host-side shuffle
+    uint64_t z = (state += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  };
+  for (int ep = 0; ep < epochs; ++ep) {
+    for (int64_t i = 0; i < n; ++i) perm[i] = (int32_t)i;
+    for (int64_t i = n - 1; i >= 1; --i) std::swap(perm[i], perm[next() % (uint64_t)(i + 1)]);
+    const int64_t nbatch = n / nb;  // whole batches only; the remainder rotates with the shuffle
+    bl.assign(nbatch, 0.0);
+    for (int64_t bi = 0; bi < nbatch; ++bi) {
+      HIP_TRY(ctx, hipMemcpyAsync(w.idx, perm.data() + bi * nb, sizeof(int32_t) * nb, hipMemcpyHostToDevice, s));
+      net_gather(spins_dev, ratios_dev, w.idx, nb, H, W, w.sb, w.rb, s);
+      net_loss_grad(L->d_net, w.sb, w.rb, nb, H, W, w.work, w.part, w.cnt, w.scal, w.grad, s);
+      net_adam(L->d_net, w.grad, L->d_adam, L->d_adam + NET_NPARAM, (float)lr, (int)++L->adam_t, s);
+      HIP_TRY(ctx, hipMemcpyAsync(&bl[bi], w.scal, sizeof(double), hipMemcpyDeviceToHost, s));
+      // the host index buffer is reused by the next batch
+      HIP_TRY(ctx, hipStreamSynchronize(s));
+    }
+    double m = 0.0;
+    for (double v : bl) m += v;
+    eloss[ep] = nbatch ? m / nbatch : 0.0;
   }
+  net_cast_f64(L->d_net, L->d_net64, s);
+  HIP_TRY(ctx, hipGetLastError());
+  if (loss_dev)
+    HIP_TRY(ctx, hipMemcpyAsync(loss_dev, eloss.data(), sizeof(double) * epochs, hipMemcpyHostToDevice, s));
+  HIP_TRY(ctx, hipStreamSynchronize(s));
   return VP_OK;
 }
 

@@ -43,7 +43,7 @@ __device__ __host__ inline double uniform53(uint64_t w) {
   return (double)(w >> 11) * (1.0 / 9007199254740992.0);
 }
 
-enum : uint64_t { TAG_INIT = 1, TAG_PERTURB = 2, TAG_SHUFFLE = 3, TAG_METRO = 4, TAG_SGD = 5 };
+enum : uint64_t { TAG_INIT = 1, TAG_PERTURB = 2, TAG_SHUFFLE = 3, TAG_METRO = 4, TAG_SGD = 5, TAG_PLAQ = 6 };
 
 // ---------------------------------------------------------------------------
 // Strided 2-level views: element (i, j) of a matrix lives at

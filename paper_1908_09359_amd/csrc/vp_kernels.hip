@@ -6,6 +6,7 @@
 #include "vp_eig.hpp"
 #include "vp_env4.hpp"
 #include "vp_kernels.hpp"
+#include "vp_net.hpp"
 
 #include <math.h>
 
@@ -292,16 +293,41 @@ __global__ void __launch_bounds__(WG) k_row4_right(LatDev L, int y) {
 }
 
 // Vertical bonds between rows y and y+1, left to right.
-template <typename T, int DD, int CC, bool BF16>
+// Propose-or-stay Metropolis-Hastings decision of a learned plaquette move:
+// accept iff u < R pi(S')/pi(S), R = rho^2.
+__device__ inline bool plaquette_accept(ChainMeta* meta, double num, double den, int esum, double pi_fwd,
+                                        double pi_back, double u) {
+  if (den == 0.0) {
+    raise_flag(meta, FLAG_ZERO);
+    return false;
+  }
+  const double rho = scaled(num / den, esum);
+  const double R = rho * rho;
+  if (!isfinite(R)) {
+    raise_flag(meta, FLAG_NONFINITE);
+    return false;
+  }
+  return u < R * pi_back / pi_fwd;
+}
+
+constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
+
+// Vertical bonds between rows y and y+1, left to right.  LEARN: after the
+// vertical bond at x < Lx-1, the learned move of plaquette (y, x): proposed
+// with probability pi = sigmoid(f_x(S)) (word 0 of Philox counter (chain,
+// sweep, y(Lx-1)+x, 6)), accepted with min[1, R pi(S')/pi(S)] (word 1); R from
+// the two-row network with columns x and x+1 exchanged in both rows.
+template <typename T, int DD, int CC, bool BF16, bool LEARN>
 __global__ void __launch_bounds__(WG) k_vsweep(LatDev L, int y) {
-  __shared__ __attribute__((aligned(16))) char lds[env4_lds<T, T, DD, CC>()];
+  __shared__ __attribute__((aligned(16)))
+  char lds[cmax(env4_lds<T, T, DD, CC>(), LEARN ? net_lds_bytes<T>() : 0)];
   Chain<T> C = chain_of<T>(L, blockIdx.x);
   if (C.meta->flags) return;
   const int sz = e4sz(L);
   T* tmp = C.ws + L.oT4;
   const T* R = C.ws + L.oR4;
   const int* eR = C.iw + L.ieR4;
-  int slot[3] = {0, 1, 2};  // cur, nxt, f
+  int slot[4] = {0, 1, 2, 3};  // cur, nxt, f (and a fourth temp for plaquette moves)
   set_unit<T>(tmp + slot[0] * sz, sz);
   int ecur = 0;
   for (int x = 0; x < L.Lx; ++x) {
@@ -333,6 +359,44 @@ __global__ void __launch_bounds__(WG) k_vsweep(LatDev L, int y) {
       if (acc) {
         int t = slot[1]; slot[1] = slot[2]; slot[2] = t;
         enxt = ef;
+      }
+    }
+    if constexpr (LEARN) {
+      const int k1 = y * L.Lx + x, k2 = k1 + L.Lx;
+      if (x < L.Lx - 1 && C.sp[k1] + C.sp[k1 + 1] + C.sp[k2] + C.sp[k2 + 1] == 2) {
+        const int q = y * (L.Lx - 1) + x;
+        U64x4 w = philox4x64_10((uint64_t)blockIdx.x, (uint64_t)C.meta->sweep, (uint64_t)q, TAG_PLAQ, L.seed,
+                                (uint64_t)L.lat_id);
+        const T* Wn = static_cast<const T*>(L.net);
+        const double pi_fwd = net_sigmoid(net_logit<T>(Wn, C.sp, L.Ly, L.Lx, y, x, 0, lds));
+        if (uniform53(w.v[0]) < pi_fwd) {
+          const T* Ux1 = ub<T>(L, C, y, x + 1);
+          const T* Dx1 = db<T>(L, C, y + 2, x + 1);
+          T* cur = tmp + slot[0] * sz;
+          T* nxt = tmp + slot[1] * sz;
+          T* f1 = tmp + slot[2] * sz;
+          T* f2 = tmp + slot[3] * sz;
+          const int ef1 = ecur + step4<T, DD, CC, BF16>(L, C, f1, cur, y, x, 1, 1, Ux, Dx, false, lds);
+          const int ef2 = ef1 + step4<T, DD, CC, BF16>(L, C, f2, f1, y, x + 1, 1, 1, Ux1, Dx1, false, lds);
+          // the current network through column x+1, into the slot of cur (no longer needed)
+          const int eden = enxt + step4<T, DD, CC, BF16>(L, C, cur, nxt, y, x + 1, 0, 0, Ux1, Dx1, false, lds);
+          const double num = wg_dot<T>(f2, R + (int64_t)(x + 2) * sz, sz);
+          const double den = wg_dot<T>(cur, R + (int64_t)(x + 2) * sz, sz);
+          const double pi_back = net_sigmoid(net_logit<T>(Wn, C.sp, L.Ly, L.Lx, y, x, 1, lds));
+          const bool acc = plaquette_accept(C.meta, num, den, ef2 - eden, pi_fwd, pi_back, uniform53(w.v[1]));
+          if (threadIdx.x == 0) {
+            C.meta->p_proposed += 1;
+            if (acc) {
+              C.sp[k1] ^= 1; C.sp[k1 + 1] ^= 1; C.sp[k2] ^= 1; C.sp[k2 + 1] ^= 1;
+              C.meta->p_accepted += 1;
+            }
+          }
+          __syncthreads();
+          if (acc) {  // column x now carries the flipped tensors: f1 is the environment through x
+            int t = slot[1]; slot[1] = slot[2]; slot[2] = t;
+            enxt = ef1;
+          }
+        }
       }
     }
     int t = slot[0]; slot[0] = slot[1]; slot[1] = t;
@@ -599,6 +663,22 @@ __global__ void __launch_bounds__(WG) k_measure4(LatDev L, int y, SampleOut o) {
       }
     }
   }
+  if (o.plaq) {
+    // flips of the movable plaquettes (y, x): both columns exchanged in both rows
+    for (int x = 0; x < Lx - 1; ++x) {
+      const int k1 = y * Lx + x, k2 = k1 + Lx;
+      double rho = 0.0;
+      if (C.sp[k1] + C.sp[k1 + 1] + C.sp[k2] + C.sp[k2 + 1] == 2) {
+        int e1 = eL[x] + step4<T, DD, CC>(L, C, tmp, Le + (int64_t)x * sz, y, x, 1, 1, ub<T>(L, C, y, x),
+                                          db<T>(L, C, y + 2, x), false, lds);
+        int e2 = e1 + step4<T, DD, CC>(L, C, tmp + sz, tmp, y, x + 1, 1, 1, ub<T>(L, C, y, x + 1),
+                                       db<T>(L, C, y + 2, x + 1), false, lds);
+        double num = wg_dot<T>(tmp + sz, R + (int64_t)(x + 2) * sz, sz);
+        rho = ldexp(num / Nm, e2 + eR[x + 2] - eN);
+      }
+      if (threadIdx.x == 0) o.plaq[(int64_t)blockIdx.x * (L.Ly - 1) * (Lx - 1) + y * (Lx - 1) + x] = rho;
+    }
+  }
   if (threadIdx.x == 0) {
     if (!isfinite(eacc)) C.meta->flags |= FLAG_NONFINITE;
     C.meta->e_acc += eacc;
@@ -656,6 +736,7 @@ __global__ void k_init_chains(LatDev L) {
   }
   ChainMeta* m = L.meta + ch;
   m->sweep = 0; m->accepted = 0; m->proposed = 0; m->flags = 0; m->e_acc = 0.0;
+  m->p_accepted = 0; m->p_proposed = 0;
 }
 
 __global__ void k_copy_spins(LatDev L, const int8_t* src, int n_cfg) {
@@ -784,12 +865,28 @@ void launch_row4_right(const LatDev& L, int y, bool bf16, hipStream_t s) {
   }
   VP_DISPATCH_DC_BF(k_row4_right, T, false, L, y);
 }
+#define VP_DISPATCH_DC_VS(T, BF, LR)                                                                   \
+  do {                                                                                                 \
+    if (L.d == 8 && L.c == 16)                                                                         \
+      hipLaunchKernelGGL((k_vsweep<T, 8, 16, BF, LR>), dim3(L.n_chains), dim3(WG), 0, s, L, y);        \
+    else if (L.d == 6 && L.c == 12)                                                                    \
+      hipLaunchKernelGGL((k_vsweep<T, 6, 12, BF, LR>), dim3(L.n_chains), dim3(WG), 0, s, L, y);        \
+    else if (L.d == 4 && L.c == 8)                                                                     \
+      hipLaunchKernelGGL((k_vsweep<T, 4, 8, BF, LR>), dim3(L.n_chains), dim3(WG), 0, s, L, y);         \
+    else                                                                                               \
+      hipLaunchKernelGGL((k_vsweep<T, 0, 0, BF, LR>), dim3(L.n_chains), dim3(WG), 0, s, L, y);         \
+  } while (0)
 template <typename T>
-void launch_vsweep(const LatDev& L, int y, bool bf16, hipStream_t s) {
+void launch_vsweep(const LatDev& L, int y, bool bf16, bool learned, hipStream_t s) {
   if constexpr (sizeof(T) == 4) {
-    if (bf16) { VP_DISPATCH_DC_BF(k_vsweep, T, true, L, y); return; }
+    if (bf16) {
+      if (learned) VP_DISPATCH_DC_VS(T, true, true);
+      else VP_DISPATCH_DC_VS(T, true, false);
+      return;
+    }
   }
-  VP_DISPATCH_DC_BF(k_vsweep, T, false, L, y);
+  if (learned) VP_DISPATCH_DC_VS(T, false, true);
+  else VP_DISPATCH_DC_VS(T, false, false);
 }
 template <typename T>
 void launch_compress(const LatDev& L, int y, int upper, hipStream_t s) {
@@ -846,7 +943,7 @@ void launch_sign_sgd(double* T, const double* g, int64_t Np, double step_len, ui
   template void launch_hsweep<T>(const LatDev&, int, int, bool, hipStream_t);                             \
   template void launch_psi_fixed<T>(const LatDev&, hipStream_t);                                    \
   template void launch_row4_right<T>(const LatDev&, int, bool, hipStream_t);                              \
-  template void launch_vsweep<T>(const LatDev&, int, bool, hipStream_t);                                  \
+  template void launch_vsweep<T>(const LatDev&, int, bool, bool, hipStream_t);                                \
   template void launch_compress<T>(const LatDev&, int, int, hipStream_t);                           \
   template void launch_measure3<T>(const LatDev&, int, const SampleOut&, hipStream_t);              \
   template void launch_measure4<T>(const LatDev&, int, const SampleOut&, hipStream_t);              \

@@ -15,6 +15,8 @@ struct ChainMeta {
   double logpsi;        // log|Psi| of the last top-down pass
   int32_t sign;         // sign of Psi
   int32_t flags;        // bit 0: zero amplitude, bit 1: non-finite value
+  int64_t p_accepted;   // learned plaquette moves
+  int64_t p_proposed;
 };
 
 enum : int32_t { FLAG_ZERO = 1, FLAG_NONFINITE = 2 };
@@ -41,6 +43,7 @@ struct LatDev {
   int8_t* spins;            // [n_chains][N]
   double* trace;            // [n_chains][n_bonds][2] (rho, accepted) of the last sweep, or null
   int n_bonds;              // Ly(Lx-1) + (Ly-1)Lx
+  const void* net;          // proposal network parameters in the working precision, or null
   const int32_t* kU;        // bond dims of U_y: kU[(y+1)*(Lx+1) + j], y = -1..Ly-1
   const int32_t* kD;        // bond dims of D_y: kD[y*(Lx+1) + j], y = 0..Ly
   const int32_t* dims;      // true leg dims per site [N][4] (l,u,r,d)
@@ -79,6 +82,7 @@ struct SampleOut {
   int64_t np_half;
   int n_pairs;
   int psi_meas;         // Psi from the measurement pass (bottom row) instead of the sampling pass
+  double* plaq;         // [chain][(Ly-1)(Lx-1)] plaquette-flip ratios, or null
 };
 
 template <typename T> void launch_prepare_tensors(const LatDev& L, const double* Tflat, T* Tw,
@@ -87,7 +91,7 @@ template <typename T> void launch_init_trivial(const LatDev& L, hipStream_t s);
 template <typename T> void launch_row3_right(const LatDev& L, int y, int ub_slot, int db_slot, bool bf16, hipStream_t s);
 template <typename T> void launch_hsweep(const LatDev& L, int y, int last_row, bool bf16, hipStream_t s);
 template <typename T> void launch_row4_right(const LatDev& L, int y, bool bf16, hipStream_t s);
-template <typename T> void launch_vsweep(const LatDev& L, int y, bool bf16, hipStream_t s);
+template <typename T> void launch_vsweep(const LatDev& L, int y, bool bf16, bool learned, hipStream_t s);
 template <typename T> void launch_compress(const LatDev& L, int y, int upper, hipStream_t s);
 template <typename T> void launch_measure3(const LatDev& L, int y, const SampleOut& o, hipStream_t s);
 template <typename T> void launch_measure4(const LatDev& L, int y, const SampleOut& o, hipStream_t s);
@@ -110,5 +114,17 @@ int launch_sr(const int64_t* offs, const int64_t* coff, const int32_t* sz, int N
 int64_t sr_work_doubles(int64_t np, int64_t ns);
 void launch_sign_sgd(double* T, const double* g, int64_t Np, double step_len, uint64_t seed, int lat_id,
                      uint64_t step, hipStream_t s);
+
+// Proposal network (batched, float32): work holds net_work_floats(n, H, W)
+// floats; part [n] doubles, cnt [n] ints, scal [2] doubles.
+size_t net_work_floats(int n, int H, int W);
+void net_forward(const float* th, const int8_t* spins, int n, int H, int W, float* work, float* logits,
+                 hipStream_t s);
+void net_loss_grad(const float* th, const int8_t* spins, const double* ratios, int n, int H, int W, float* work,
+                   double* part, int* cnt, double* scal, float* grad, hipStream_t s);
+void net_adam(float* th, const float* g, float* m, float* v, float lr, int t, hipStream_t s);
+void net_gather(const int8_t* spins, const double* ratios, const int32_t* idx, int nb, int H, int W, int8_t* sb,
+                double* rb, hipStream_t s);
+void net_cast_f64(const float* src, double* dst, hipStream_t s);
 
 }  // namespace vp
