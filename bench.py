@@ -99,7 +99,7 @@ def main():
     lp = torch.empty(nch, dtype=torch.float64, device=dev)
     sg = torch.empty(nch, dtype=torch.int8, device=dev)
     el = torch.empty(nch, dtype=torch.float64, device=dev)
-    dl = torch.empty((nch, nh), dtype=torch.float32, device=dev)
+    dl = torch.empty((nch, nh), dtype=torch.float32 if args.prec == "fp32" else torch.float64, device=dev)
     for _ in range(args.warmup):
         ctx.vp_sample(0, 0, 1, lp, sg, el, dl)
     ctx.vp_sync()
@@ -129,11 +129,11 @@ def main():
     out = {
         "metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if args.prec == "fp32" else "bf16/f32",
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if args.prec == "fp32" else "bf16/f64",
         "data": "synthetic",
         "config": {"workload": f"{Ly}x{Lx} Heisenberg D={D} Dc={Dc}, {nch} chains, plain pair sweeps, "
                                + ("fp32 contractions" if args.prec == "fp32" else
-                                  "bf16-operand sampling pass, fp32 measurement")
+                                  "bf16-operand sampling pass, fp64 measurement")
                                + " / fp64 compression",
                    "Ly": Ly, "Lx": Lx, "D": D, "Dc": Dc, "chains": nch, "J2": 0.0,
                    "parallelism": "chains (1 GPU)"},

@@ -32,13 +32,17 @@
  *   horizontal pairs and 2-row (4-line) networks for vertical and diagonal
  *   pairs; every ratio divides by the same network with the current tensors.
  * Precision (vp_lattice.prec): VP_FP64 contracts in float64; VP_FP32 in
- *   float32 on MFMA; VP_BF16 takes the sampling pass (the ratios that decide
- *   Metropolis moves) with bf16 operands and float32 accumulation, and measures
- *   Psi, E_loc and G like VP_FP32 (App. D: a ratio error of a few bf16 ulps
- *   changes acceptance probabilities by as much, which the chain tolerates;
- *   the estimators need the full working precision).  Every mode keeps an
- *   exact power-of-two scale per network column, accumulates log|Psi| and
- *   normalises ratios in float64, and compresses boundaries in float64.
+ *   float32 on MFMA; VP_BF16 stores tensors, boundaries and environments in
+ *   float64, takes the sampling pass (the ratios that decide Metropolis moves)
+ *   with bf16 operands and float32 accumulation, and measures Psi, E_loc and G
+ *   in float64 (App. D: a ratio error of a few bf16 ulps changes acceptance
+ *   probabilities by as much, which the chain tolerates; the estimators are
+ *   not protected by that argument, and float32 measurements of strongly
+ *   cancelling networks miss the 1e-4 per-site energy tolerance).  Every mode
+ *   keeps an exact power-of-two scale per network column, accumulates
+ *   log|Psi| and normalises ratios in float64, and compresses boundaries in
+ *   float64.  The "working precision" below is float32 for VP_FP32 and
+ *   float64 otherwise.
  * Randomness: Philox4x64-10 (Salmon et al., SC'11) under key (seed, lattice);
  *   Metropolis uniforms use counter (chain, sweep, bond, 4), where bond counts
  *   the visits of one sweep: row y's horizontal bonds, then the vertical bonds
@@ -123,8 +127,8 @@ vp_status vp_init_chains(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev);
 /* Run n_burn + n_meas sequential sweeps on every chain (Sec. II.A Eq. (9)),
  * measuring after each of the last n_meas.  Outputs, indexed [chain][m]:
  * log_abs_psi_dev, sign_dev (+1/-1), e_loc_dev (total energy, not per site),
- * dlnpsi_dev ([chain][m][Np/2] in the working precision: float64 for VP_FP64,
- * float32 otherwise; may be NULL), spins_out_dev ([chain][m][N], may be NULL).
+ * dlnpsi_dev ([chain][m][Np/2] in the working precision: float32 for VP_FP32,
+ * float64 otherwise; may be NULL), spins_out_dev ([chain][m][N], may be NULL).
  * accept_dev ([chain][2] int64: accepted, proposed; accumulated; may be NULL). */
 vp_status vp_sample(vp_ctx* ctx, int32_t lat, int32_t n_burn, int32_t n_meas,
                     double* log_abs_psi_dev, int8_t* sign_dev, double* e_loc_dev,
@@ -197,7 +201,7 @@ vp_status vp_proposal_train(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev, c
  * and its flip accepted iff u < rho^2 pi(S')/pi(S), u = word 1 of the same
  * counter: Metropolis-Hastings for a propose-or-stay move, so |Psi|^2 stays
  * the stationary distribution whatever the weights.  The network runs in the
- * working precision (float64 for VP_FP64, float32 otherwise). */
+ * working precision. */
 vp_status vp_set_sampler(vp_ctx* ctx, int32_t lat, int32_t sampler);
 /* Move counters since vp_init_chains: counts_dev [n_chains][4] int64 =
  * (pair accepted, pair proposed, plaquette accepted, plaquette proposed). */

@@ -184,7 +184,10 @@ Plan plan_workspace(const vp_lattice& p, LatDev* dev) {
   return P;
 }
 
-size_t type_size(int prec) { return prec == VP_FP64 ? 8 : 4; }
+// Working precision: float32 for VP_FP32; float64 for VP_FP64 and VP_BF16 (whose
+// bf16 operands are rounded from float64 storage inside the sampling kernels).
+bool works_f64(int prec) { return prec != VP_FP32; }
+size_t type_size(int prec) { return works_f64(prec) ? 8 : 4; }
 
 vp_status check_lattice(vp_ctx* ctx, const vp_lattice& p) {
   if (p.Ly < 1 || p.Lx < 1 || p.D < 1 || p.Dc < 1 || p.n_chains < 1)
@@ -260,8 +263,8 @@ void run_lower_pass(vp_ctx* ctx, Lattice& L, hipStream_t s) {
 template <typename T>
 void run_sweep(vp_ctx* ctx, Lattice& L, const SampleOut* o, hipStream_t s) {
   const int Ly = L.p.Ly;
-  // VP_BF16: the sampling pass contracts with bf16 operands; measurement and
-  // compression keep their precision.
+  // VP_BF16: the sampling pass contracts with bf16 operands (f32 accumulation);
+  // measurement and compression run in float64.
   const bool bf = L.p.prec == VP_BF16;
   Rec r(ctx);
   // top-down sampling pass
@@ -351,7 +354,7 @@ vp_status eval_configs(vp_ctx* ctx, Lattice* L, const int8_t* spins_dev, int32_t
   o.m = 0;
   o.np_half = L->Np / 2;
   o.n_pairs = p.Ly * (p.Lx - 1) + (p.Ly - 1) * p.Lx + (p.J2 != 0.0 ? 2 * (p.Ly - 1) * (p.Lx - 1) : 0);
-  if (p.prec == VP_FP64) run_eval<double>(D, o, n_cfg, s); else run_eval<float>(D, o, n_cfg, s);
+  if (works_f64(p.prec)) run_eval<double>(D, o, n_cfg, s); else run_eval<float>(D, o, n_cfg, s);
   HIP_TRY(ctx, hipGetLastError());
   L->chains_ready = false;
   L->lower_valid = false;
@@ -491,10 +494,10 @@ vp_status vp_create(const vp_lattice* lats, int32_t n_lats, uint64_t seed, void*
     D.iws = L.iws; D.iws_stride = P.iws; D.dws = L.dws; D.dws_stride = P.dws;
     D.meta = L.meta; D.spins = L.spins;
     D.trace = nullptr;
-    D.net = p.prec == VP_FP64 ? (const void*)L.d_net64 : (const void*)L.d_net;
+    D.net = works_f64(p.prec) ? (const void*)L.d_net64 : (const void*)L.d_net;
     D.n_bonds = p.Ly * (p.Lx - 1) + (p.Ly - 1) * p.Lx;
     D.kU = L.d_kU; D.kD = L.d_kD; D.dims = L.d_dims; D.coff = L.d_coff;
-    if (p.prec == VP_FP64) launch_init_trivial<double>(D, ctx->stream);
+    if (works_f64(p.prec)) launch_init_trivial<double>(D, ctx->stream);
     else launch_init_trivial<float>(D, ctx->stream);
     if (hipGetLastError() != hipSuccess) {
       vp_destroy(ctx);
@@ -520,7 +523,7 @@ vp_status vp_destroy(vp_ctx* ctx) {
 }
 
 static vp_status stage_tensors(vp_ctx* ctx, Lattice& L) {
-  if (L.p.prec == VP_FP64)
+  if (works_f64(L.p.prec))
     launch_prepare_tensors<double>(L.dev, L.T, (double*)L.Tw, L.d_offs, ctx->stream);
   else
     launch_prepare_tensors<float>(L.dev, L.T, (float*)L.Tw, L.d_offs, ctx->stream);
@@ -591,7 +594,7 @@ vp_status vp_sample(vp_ctx* ctx, int32_t lat, int32_t n_burn, int32_t n_meas, do
   if (n_meas > 0 && (!log_abs_psi_dev || !sign_dev || !e_loc_dev))
     return fail(ctx, VP_ERR_ARG, "log_abs_psi, sign and e_loc outputs are required");
   hipStream_t s = ctx->stream;
-  const bool f64 = L->p.prec == VP_FP64;
+  const bool f64 = works_f64(L->p.prec);
   if (!L->lower_valid) {
     if (f64) run_lower_pass<double>(ctx, *L, s); else run_lower_pass<float>(ctx, *L, s);
     L->lower_valid = true;
@@ -787,7 +790,7 @@ vp_status vp_gradient(vp_ctx* ctx, int32_t lat, const double* e_loc_dev, const v
   if (!L || !e_loc_dev || !dlnpsi_dev || !spins_dev || !grad_dev || !e_mean_dev)
     return fail(ctx, VP_ERR_ARG, "bad lattice index or null pointer");
   if (n_samples < 1) return fail(ctx, VP_ERR_ARG, "n_samples must be >= 1");
-  if (L->p.prec == VP_FP64)
+  if (works_f64(L->p.prec))
     launch_gradient<double>(L->d_offs, L->d_coff, L->d_sizes, L->N, L->Np, e_loc_dev, (const double*)dlnpsi_dev,
                             spins_dev, n_samples, grad_dev, e_mean_dev, nullptr, ctx->stream);
   else
@@ -812,7 +815,7 @@ vp_status vp_sr_update(vp_ctx* ctx, int32_t lat, const double* e_loc_dev, const 
   if (hipMalloc((void**)&work, sizeof(double) * nd) != hipSuccess) return fail(ctx, VP_ERR_OOM, "SR workspace");
   if (hipMalloc((void**)&flag, sizeof(int)) != hipSuccess) { hipFree(work); return fail(ctx, VP_ERR_OOM, "SR flag"); }
   hipMemsetAsync(flag, 0, sizeof(int), ctx->stream);
-  int rc = L->p.prec == VP_FP64
+  int rc = works_f64(L->p.prec)
                ? launch_sr<double>(L->d_offs, L->d_coff, L->d_sizes, L->N, L->Np, e_loc_dev, (const double*)dlnpsi_dev,
                                    spins_dev, n_samples, shift, lr, L->T, delta_dev, work, flag, ctx->stream)
                : launch_sr<float>(L->d_offs, L->d_coff, L->d_sizes, L->N, L->Np, e_loc_dev, (const float*)dlnpsi_dev,

@@ -94,13 +94,13 @@ template <> struct Acc4<double> { typedef v4d_g type; };
 constexpr size_t GEMM_TILE_BYTES = 2 * 16 * 65 * sizeof(double);
 typedef __bf16 v8bf_g __attribute__((ext_vector_type(8)));
 
-// bf16 operands, f32 accumulation (C(i,j) as above, TC = float): A and B are
+// bf16 operands, f32 accumulation (C(i,j) as above, stored as TC): A and B are
 // rounded to bf16 (round to nearest even) when staged, 32 k-values at a time,
 // k-contiguous in LDS so that each lane fetches its 8 k-values of the
 // 16x16x32 MFMA in one read; the output layout is that of the f32 16x16x4.
-template <typename TA, typename TB>
-__device__ void wg_gemm_bf16(char* tiles, float* __restrict__ C, View vc, const TA* __restrict__ A, View va,
-                             const TB* __restrict__ B, View vb, int M, int N, int K, float alpha,
+template <typename TC, typename TA, typename TB>
+__device__ void wg_gemm_bf16(char* tiles, TC* __restrict__ C, View vc, const TA* __restrict__ A, View va,
+                             const TB* __restrict__ B, View vb, int M, int N, int K, TC alpha,
                              bool accumulate) {
   constexpr int BM = 64, BN = 64, BK = 32, LD = BK + 8;
   __bf16 (*As)[LD] = reinterpret_cast<__bf16 (*)[LD]>(tiles);
@@ -151,8 +151,8 @@ __device__ void wg_gemm_bf16(char* tiles, float* __restrict__ C, View vc, const 
           for (int r = 0; r < 4; ++r) {
             const int m = m0 + tr0 + 16 * a + 4 * (lane >> 4) + r;
             if (m < M) {
-              float* cp = C + vaddr(vc, m, n);
-              *cp = accumulate ? *cp + alpha * acc[a][b][r] : alpha * acc[a][b][r];
+              TC* cp = C + vaddr(vc, m, n);
+              *cp = accumulate ? *cp + alpha * (TC)acc[a][b][r] : alpha * (TC)acc[a][b][r];
             }
           }
         }
@@ -238,8 +238,7 @@ template <bool BF16, typename TC, typename TA, typename TB>
 __device__ inline void wg_gemm_p(TC* __restrict__ C, View vc, const TA* __restrict__ A, View va,
                                  const TB* __restrict__ B, View vb, int M, int N, int K) {
   if constexpr (BF16) {
-    static_assert(sizeof(TC) == 4, "bf16 operands accumulate in float");
-    wg_gemm_bf16(gemm_tiles(), C, vc, A, va, B, vb, M, N, K, 1.0f, false);
+    wg_gemm_bf16<TC>(gemm_tiles(), C, vc, A, va, B, vb, M, N, K, TC(1), false);
   } else {
     wg_gemm_t<TC>(gemm_tiles(), C, vc, A, va, B, vb, M, N, K);
   }

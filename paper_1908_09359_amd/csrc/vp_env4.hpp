@@ -92,22 +92,32 @@ __device__ inline v4f_t mfma_tile_bf16(int m0, int n0, FA fa, FB fb) {
   return acc;
 }
 
+// Accumulators of a stage: those of TC, or f32 (f32 output layout) with bf16 operands.
+template <typename TC, bool BF16> struct Acc {
+  typedef typename Mfma<TC>::acc_t type;
+  __device__ static inline int row(int lane, int r) { return Mfma<TC>::row(lane, r); }
+};
+template <typename TC> struct Acc<TC, true> {
+  typedef v4f_t type;
+  __device__ static inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
 // Stage out[i][j] = sum_k A(i,k) B(k,j) into LDS (row-major, ld N), all waves.
-// BF16: operands rounded to bf16, products accumulated in f32 (TC = float).
+// BF16: operands rounded to bf16, products accumulated in f32, stored as TC.
 template <typename TC, int M, int N, int K, bool BF16 = false, typename FA, typename FB>
 __device__ inline void mfma_stage(TC* out, FA fa, FB fb) {
   constexpr int MT = (M + 15) / 16, NT = (N + 15) / 16;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int t = wave; t < MT * NT; t += 4) {
     const int m0 = (t / NT) * 16, n0 = (t % NT) * 16;
-    typename Mfma<TC>::acc_t acc;
+    typename Acc<TC, BF16>::type acc;
     if constexpr (BF16) acc = mfma_tile_bf16<M, N, K>(m0, n0, fa, fb);
     else acc = mfma_tile<TC, M, N, K>(m0, n0, fa, fb);
     const int j = n0 + (lane & 15);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int i = m0 + Mfma<TC>::row(lane, r);
-      if (i < M && j < N) out[i * N + j] = acc[r];
+      const int i = m0 + Acc<TC, BF16>::row(lane, r);
+      if (i < M && j < N) out[i * N + j] = (TC)acc[r];
     }
   }
 }
@@ -144,7 +154,7 @@ __device__ void env4_fused(TC* __restrict__ Lout, const TC* __restrict__ Lin, co
   // b-blocks outer, lower-bond slices inner: only one block's accumulators are live
   for (int q = 0; q < NBLK; ++q) {
     const int b0 = q * BB;
-    typename Mfma<TC>::acc_t acc[T4W];
+    typename Acc<TC, BF16>::type acc[T4W];
 #pragma unroll
     for (int w = 0; w < T4W; ++w) acc[w] = {0, 0, 0, 0};
     for (int cs = 0; cs < C; ++cs) {
@@ -213,8 +223,8 @@ __device__ void env4_fused(TC* __restrict__ Lout, const TC* __restrict__ Lin, co
         const int j = t * 16 + (lane & 15);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int e = Mfma<TC>::row(lane, r);
-          if (e < C && j < N4) Lout[e * (C * D * D) + q * N4 + j] = acc[w][r];
+          const int e = Acc<TC, BF16>::row(lane, r);
+          if (e < C && j < N4) Lout[e * (C * D * D) + q * N4 + j] = (TC)acc[w][r];
         }
       }
     }

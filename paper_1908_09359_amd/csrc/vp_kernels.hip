@@ -809,7 +809,7 @@ void launch_init_trivial(const LatDev& L, hipStream_t s) {
 }
 template <typename T>
 void launch_row3_right(const LatDev& L, int y, int ub_slot, int db_slot, bool bf16, hipStream_t s) {
-  if constexpr (sizeof(T) == 4) {
+  if constexpr (sizeof(T) == 8) {
     if (bf16) {
       hipLaunchKernelGGL((k_row3_right<T, true>), dim3(L.n_chains), dim3(WG), 0, s, L, y, ub_slot, db_slot);
       return;
@@ -819,7 +819,7 @@ void launch_row3_right(const LatDev& L, int y, int ub_slot, int db_slot, bool bf
 }
 template <typename T>
 void launch_hsweep(const LatDev& L, int y, int last_row, bool bf16, hipStream_t s) {
-  if constexpr (sizeof(T) == 4) {
+  if constexpr (sizeof(T) == 8) {
     if (bf16) {
       hipLaunchKernelGGL((k_hsweep<T, true>), dim3(L.n_chains), dim3(WG), 0, s, L, y, last_row, 1);
       return;
@@ -857,10 +857,10 @@ void launch_psi_fixed(const LatDev& L, hipStream_t s) {
       hipLaunchKernelGGL((KERNEL<T, 0, 0, BF>), dim3(L.n_chains), dim3(WG), 0, s, __VA_ARGS__);        \
   } while (0)
 
-// bf16 operands exist only for float accumulation.
+// bf16 operands are taken from float64 storage (VP_BF16 works in float64).
 template <typename T>
 void launch_row4_right(const LatDev& L, int y, bool bf16, hipStream_t s) {
-  if constexpr (sizeof(T) == 4) {
+  if constexpr (sizeof(T) == 8) {
     if (bf16) { VP_DISPATCH_DC_BF(k_row4_right, T, true, L, y); return; }
   }
   VP_DISPATCH_DC_BF(k_row4_right, T, false, L, y);
@@ -878,7 +878,7 @@ void launch_row4_right(const LatDev& L, int y, bool bf16, hipStream_t s) {
   } while (0)
 template <typename T>
 void launch_vsweep(const LatDev& L, int y, bool bf16, bool learned, hipStream_t s) {
-  if constexpr (sizeof(T) == 4) {
+  if constexpr (sizeof(T) == 8) {
     if (bf16) {
       if (learned) VP_DISPATCH_DC_VS(T, true, true);
       else VP_DISPATCH_DC_VS(T, true, false);

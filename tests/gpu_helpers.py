@@ -22,7 +22,7 @@ def gpu_eval(Ly, Lx, D, Dc, J2, prec, T, cfgs, n_chains=None):
     lp = torch.empty(n, dtype=torch.float64, device=dev)
     sg = torch.empty(n, dtype=torch.int8, device=dev)
     el = torch.empty(n, dtype=torch.float64, device=dev)
-    dt = torch.float64 if prec == B.VP_FP64 else torch.float32
+    dt = torch.float32 if prec == B.VP_FP32 else torch.float64
     dl = torch.empty((n, ctx.num_params() // 2), dtype=dt, device=dev)
     ra = torch.empty((n, n_pairs(Ly, Lx, J2)), dtype=torch.float64, device=dev)
     ctx.vp_eval(0, sp, n, lp, sg, el, dl, ra)

@@ -1,7 +1,8 @@
 """Reduced-precision sampling (bf16 operands, f32 accumulation) against the oracle.
 
 The bf16 mode changes only the ratios that decide Metropolis moves; Psi, E_loc
-and the log-derivatives are measured in float32.  So:
+and the log-derivatives are measured in float64 (tensors and boundaries are
+stored in float64; the sampling kernels round their operands to bf16).  So:
 
 * the sampler's own ratios are traced (vp_trace_ratios) and the oracle replays
   the same sweep with the same decisions, recomputing every ratio in float64;
@@ -154,7 +155,7 @@ def test_bf16_fixed_config_gate_16x16_D6_Dc12():
     lp = torch.empty(n, dtype=torch.float64, device=dev)
     sg = torch.empty(n, dtype=torch.int8, device=dev)
     el = torch.empty(n, dtype=torch.float64, device=dev)
-    dl = torch.empty((n, ctx.num_params() // 2), dtype=torch.float32, device=dev)
+    dl = torch.empty((n, ctx.num_params() // 2), dtype=torch.float64, device=dev)
     ctx.vp_eval(0, torch.tensor(cfgs, device=dev), n, lp, sg, el, dl, None)
     ctx.vp_sync()
     e_ref = np.array([r["e_loc"] for r in doc["configs"]])
@@ -172,8 +173,8 @@ def test_bf16_fixed_config_gate_16x16_D6_Dc12():
           f"dlnpsi rel (sampled, rms-normalised) max {dl_err.max():.3e}", flush=True)
     assert e_err.max() <= 1e-4
     assert np.array_equal(sg.cpu().numpy(), sg_ref)
-    assert lp_err.max() <= 1e-3
-    assert dl_err.max() <= 1e-2
+    assert lp_err.max() <= 1e-4
+    assert dl_err.max() <= 1e-4
 
 
 def test_bf16_chains_energy_matches_fp32():

@@ -116,7 +116,7 @@ def _gpu_sample(Ly, Lx, D, Dc, J2, prec, T, n_chains, n_burn, n_meas, seed, spin
     lp = torch.empty(n, dtype=torch.float64, device=dev)
     sg = torch.empty(n, dtype=torch.int8, device=dev)
     el = torch.empty(n, dtype=torch.float64, device=dev)
-    dt = torch.float64 if prec == B.VP_FP64 else torch.float32
+    dt = torch.float32 if prec == B.VP_FP32 else torch.float64
     dl = torch.empty((n, ctx.num_params() // 2), dtype=dt, device=dev)
     so = torch.empty((n, N), dtype=torch.int8, device=dev)
     acc = torch.zeros((n_chains, 2), dtype=torch.int64, device=dev)

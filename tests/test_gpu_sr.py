@@ -20,7 +20,7 @@ def _run_sr(Ly, Lx, D, prec, e, dl, spins, shift, lr, T):
     dev = torch.device("cuda")
     ctx = B.Context(B.lattice(Ly, Lx, D, 4, 1.0, 0.0, prec, 1), seed=1)
     ctx.vp_set_tensors(0, torch.tensor(T, device=dev))
-    dt = torch.float64 if prec == B.VP_FP64 else torch.float32
+    dt = torch.float32 if prec == B.VP_FP32 else torch.float64
     delta = torch.empty(ctx.num_params(), dtype=torch.float64, device=dev)
     ctx.vp_sr_update(0, torch.tensor(e, device=dev), torch.tensor(dl, dtype=dt, device=dev),
                      torch.tensor(spins, dtype=torch.int8, device=dev), len(e), shift, lr, delta)
