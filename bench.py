@@ -1,18 +1,28 @@
 """Throughput benchmark of the VMC-PEPS hot path on one MI355X.
 
 One step = one sequential Metropolis sweep of every chain (top-down sampling
-pass over all horizontal and vertical bonds, then the bottom-up measurement
-pass), producing Psi, E_loc and the log-derivatives dlnPsi/dT of every chain.
+pass over all horizontal and vertical bonds -- plus, on the learned path, the
+plaquette moves of every row pair -- then the bottom-up measurement pass),
+producing Psi, E_loc and the log-derivatives dlnPsi/dT of every chain.
 
-    python bench.py [--steps K] [--warmup W] [--chains C]
+Two paths on the 16x16, D=8, Dc=16 Heisenberg workload:
 
-Prints one JSON line.  Inputs are synthetic (seeded Gaussian tensors of
-standard deviation 1/D^2, Philox-shuffled Neel starts) and resident in HBM
+* plain:   float32 contractions, nearest-neighbour pair sweeps;
+* learned: bf16 sampling pass over float64 storage, float64 measurement, pair
+           sweeps plus learned plaquette moves; the proposal network is first
+           trained (untimed) on configurations of the same chains.
+
+    python bench.py [--steps K] [--warmup W] [--chains C] [--tau-sweeps S]
+
+Prints one JSON line whose value is the learned path's samples/s; the plain
+path is reported beside it.  With --tau-sweeps S > 0 both paths also run S
+measured sweeps to estimate tau_int of E_loc and the time each needs for the
+same standard error of E/site.  Inputs are synthetic (seeded Gaussian tensors
+of standard deviation 1/D^2, Philox-shuffled Neel starts) and resident in HBM
 before the timed region.
 """
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -27,7 +37,7 @@ PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15, "hbm": 8.0e12}
 
 
 def phase_flops(Ly, Lx, D, Dc):
-    """Algorithmic float64/float32 flops per chain of one launch of each deterministic phase.
+    """Algorithmic flops per chain of one launch of each deterministic phase.
 
     Column-step costs (multiply-adds, bulk dimensions):
       3-line step   D^4 Dc^2 + 2 D^2 Dc^3
@@ -49,7 +59,6 @@ def phase_flops(Ly, Lx, D, Dc):
 def cpu_baseline(Ly, Lx, D, Dc, seed):
     """The oracle, one chain, one sweep (sampling + measurement) of the same workload, one thread."""
     from threadpoolctl import threadpool_limits
-    import numpy as np
     from oracle import lattice as olat
     from oracle import vmc
     from paper_1908_09359_amd import workloads as W
@@ -63,7 +72,120 @@ def cpu_baseline(Ly, Lx, D, Dc, seed):
         vmc._measure(T, lat, ch.spins, U)
         dt = time.perf_counter() - t0
     return {"value": 1.0 / dt, "unit": "samples/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 chain x 1 sweep of {Ly}x{Lx} D={D} Dc={Dc} (float64 numpy, 1 thread, {dt:.1f} s)"}
+            "sample": f"1 chain x 1 sweep (pair moves, sampling + measurement) of {Ly}x{Lx} D={D} Dc={Dc}, "
+                      f"float64 numpy on 1 thread, {dt:.1f} s"}
+
+
+class Path:
+    """One lattice context, its output buffers and the sweep loop of one path."""
+
+    def __init__(self, B, torch, Ly, Lx, D, Dc, prec, nch, seed=9359):
+        self.B, self.torch = B, torch
+        self.Ly, self.Lx, self.N = Ly, Lx, Ly * Lx
+        self.prec, self.nch = prec, nch
+        self.dev = torch.device("cuda:0")
+        self.ctx = B.Context(B.lattice(Ly, Lx, D, Dc, 1.0, 0.0, prec, nch), seed=seed)
+        self.ctx.vp_init_tensors(0, seed=1908, scale=0.0, perturb=0.0)
+        self.ctx.vp_init_chains(0, None)
+        dt = torch.float32 if prec == B.VP_FP32 else torch.float64
+        self.lp = torch.empty(nch, dtype=torch.float64, device=self.dev)
+        self.sg = torch.empty(nch, dtype=torch.int8, device=self.dev)
+        self.el = torch.empty(nch, dtype=torch.float64, device=self.dev)
+        self.dl = torch.empty((nch, self.ctx.num_params() // 2), dtype=dt, device=self.dev)
+        self.so = torch.empty((nch, self.N), dtype=torch.int8, device=self.dev)
+
+    def sweep(self, spins=False):
+        self.ctx.vp_sample(0, 0, 1, self.lp, self.sg, self.el, self.dl, self.so if spins else None)
+
+    def train_proposal(self, sweeps, epochs, batch, lr):
+        """Configurations of `sweeps` pair sweeps -> plaquette ratios -> Adam; chains resume after."""
+        B, torch = self.B, self.torch
+        from paper_1908_09359_amd.workloads import random_proposal_weights
+        t0 = time.perf_counter()
+        npl = (self.Ly - 1) * (self.Lx - 1)
+        cfgs = torch.empty((sweeps * self.nch, self.N), dtype=torch.int8, device=self.dev)
+        for s in range(sweeps):
+            self.sweep(spins=True)
+            cfgs[s * self.nch:(s + 1) * self.nch].copy_(self.so)
+        last = self.so.clone()
+        rho = torch.empty((sweeps * self.nch, npl), dtype=torch.float64, device=self.dev)
+        for s in range(sweeps):
+            self.ctx.vp_plaquette_ratios(0, cfgs[s * self.nch:(s + 1) * self.nch], self.nch,
+                                         rho[s * self.nch:(s + 1) * self.nch])
+        w = torch.tensor(random_proposal_weights(seed=4), device=self.dev)
+        self.ctx.vp_proposal_set_weights(0, w)
+        loss = torch.empty(epochs, dtype=torch.float64, device=self.dev)
+        self.ctx.vp_proposal_train(0, cfgs, rho, cfgs.shape[0], epochs, batch, lr, 11, loss)
+        # evaluation reused the chain slots: the chains continue from their last states
+        self.ctx.vp_init_chains(0, last)
+        self.ctx.vp_set_sampler(0, B.VP_SAMPLER_LEARNED_PLAQ)
+        self.ctx.vp_sync()
+        return {"configs": int(cfgs.shape[0]), "epochs": epochs, "batch": batch, "lr": lr,
+                "loss_first_epoch": float(loss[0].item()), "loss_last_epoch": float(loss[-1].item()),
+                "seconds": time.perf_counter() - t0}
+
+    def timed(self, warmup, steps):
+        torch = self.torch
+        for _ in range(warmup):
+            self.sweep()
+        self.ctx.vp_sync()
+        torch.cuda.synchronize()
+        cnt0 = self.counts()
+        self.ctx.vp_timing_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            self.sweep()
+        self.ctx.vp_sync()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ms, launches = self.ctx.vp_timing_read()
+        self.ctx.vp_timing_enable(False)
+        cnt = self.counts() - cnt0
+        return {"samples_per_s": self.nch * steps / dt, "ms_per_step": dt / steps * 1e3, "ms": ms,
+                "launches": launches, "seconds": dt,
+                "pair_accept": float(cnt[0] / max(cnt[1], 1)),
+                "plaquette_accept": float(cnt[2] / cnt[3]) if cnt[3] else None,
+                "plaquette_proposed_per_sweep": float(cnt[3] / self.nch / steps),
+                "e_site_last_sweep": float(self.el.mean().item()) / self.N}
+
+    def tau_run(self, sweeps):
+        """`sweeps` measured sweeps: tau_int of E_loc/N per chain and the tau-corrected error of E/N."""
+        import numpy as np
+        torch = self.torch
+        series = torch.empty((sweeps, self.nch), dtype=torch.float64, device=self.dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(sweeps):
+            self.sweep()
+            series[s].copy_(self.el)
+            print(f"tau sweep {s + 1}/{sweeps}", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        x = series.t().contiguous().cpu().numpy() / self.N
+        tau, mean, err = self.B.vp_stats_tau(x, 5.0)
+        var = float(np.mean(np.var(x, axis=1, ddof=1)))
+        return {"sweeps": sweeps, "seconds": dt, "samples_per_s": self.nch * sweeps / dt,
+                "tau_int_mean": float(np.mean(tau)), "e_site": mean, "e_site_stderr": err,
+                "var_e_site_per_sample": var}
+
+    def counts(self):
+        c = self.torch.empty((self.nch, 4), dtype=self.torch.int64, device=self.dev)
+        self.ctx.vp_move_counts(0, c)
+        return c.sum(dim=0).cpu().numpy()
+
+    def close(self):
+        self.ctx.close()
+
+
+def roofline(ms, launches, flops, nch, fp64_contractions):
+    """Dominant deterministic phase: algorithmic flops per launch / live average launch time."""
+    timed = {k: v for k, v in ms.items() if k in flops and launches[k] > 0}
+    dom = max(timed, key=lambda k: timed[k])
+    avg_s = ms[dom] / launches[dom] / 1e3
+    achieved = flops[dom] * nch / avg_s
+    peak = PEAK["fp64"] if (dom.startswith("compress") or fp64_contractions) else PEAK["fp32"]
+    return {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+            "frac": achieved / peak, "traffic": None, "avg_launch_ms": ms[dom] / launches[dom]}
 
 
 def main():
@@ -75,8 +197,10 @@ def main():
     ap.add_argument("--L", type=int, default=16)
     ap.add_argument("--D", type=int, default=8)
     ap.add_argument("--Dc", type=int, default=16)
-    ap.add_argument("--prec", choices=["fp32", "bf16"], default="fp32",
-                    help="fp32: float32 contractions; bf16: sampling pass with bf16 operands")
+    ap.add_argument("--train-sweeps", type=int, default=2)
+    ap.add_argument("--train-epochs", type=int, default=4)
+    ap.add_argument("--tau-sweeps", type=int, default=0)
+    ap.add_argument("--only", choices=["both", "plain", "learned"], default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -89,61 +213,60 @@ def main():
 
     Ly = Lx = args.L
     D, Dc, nch = args.D, args.Dc, args.chains
-    dev = torch.device("cuda:0")
-    prec = B.VP_BF16 if args.prec == "bf16" else B.VP_FP32
-    lat = B.lattice(Ly, Lx, D, Dc, 1.0, 0.0, prec, nch)
-    ctx = B.Context(lat, seed=9359)
-    ctx.vp_init_tensors(0, seed=1908, scale=0.0, perturb=0.0)
-    ctx.vp_init_chains(0, None)
-    nh = ctx.num_params() // 2
-    lp = torch.empty(nch, dtype=torch.float64, device=dev)
-    sg = torch.empty(nch, dtype=torch.int8, device=dev)
-    el = torch.empty(nch, dtype=torch.float64, device=dev)
-    dl = torch.empty((nch, nh), dtype=torch.float32 if args.prec == "fp32" else torch.float64, device=dev)
-    for _ in range(args.warmup):
-        ctx.vp_sample(0, 0, 1, lp, sg, el, dl)
-    ctx.vp_sync()
-    torch.cuda.synchronize()
-    ctx.vp_timing_enable(True)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ctx.vp_sample(0, 0, 1, lp, sg, el, dl)
-    ctx.vp_sync()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms, launches = ctx.vp_timing_read()
-    ctx.vp_timing_enable(False)
-    e_site = float(el.mean().item()) / (Ly * Lx)
-    dt = t1 - t0
-    value = nch * args.steps / dt
-
     flops = phase_flops(Ly, Lx, D, Dc)
-    timed = {k: v for k, v in ms.items() if k in flops and launches[k] > 0}
-    dom = max(timed, key=lambda k: timed[k])
-    avg_s = ms[dom] / launches[dom] / 1e3
-    achieved = flops[dom] * nch / avg_s
-    peak = PEAK["fp64"] if dom.startswith("compress") else PEAK["fp32"]
-    roofline = {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": peak / 1e12,
-                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
-                "avg_launch_ms": ms[dom] / launches[dom]}
+    res = {}
+    if args.only in ("both", "plain"):
+        p = Path(B, torch, Ly, Lx, D, Dc, B.VP_FP32, nch)
+        r = p.timed(args.warmup, args.steps)
+        print(f"plain: {r['samples_per_s']:.1f} samples/s", file=sys.stderr, flush=True)
+        r["roofline"] = roofline(r["ms"], r["launches"], flops, nch, False)
+        if args.tau_sweeps:
+            r["tau"] = p.tau_run(args.tau_sweeps)
+        p.close()
+        del p
+        torch.cuda.empty_cache()
+        res["plain"] = r
+    if args.only in ("both", "learned"):
+        p = Path(B, torch, Ly, Lx, D, Dc, B.VP_BF16, nch)
+        tr = p.train_proposal(args.train_sweeps, args.train_epochs, 256, 3e-3)
+        print(f"learned: trained in {tr['seconds']:.1f} s", file=sys.stderr, flush=True)
+        r = p.timed(args.warmup, args.steps)
+        print(f"learned: {r['samples_per_s']:.1f} samples/s", file=sys.stderr, flush=True)
+        r["training"] = tr
+        r["roofline"] = roofline(r["ms"], r["launches"], flops, nch, True)
+        if args.tau_sweeps:
+            r["tau"] = p.tau_run(args.tau_sweeps)
+        p.close()
+        res["learned"] = r
+
+    head = res.get("learned") or res["plain"]
+    is_learned = "learned" in res
     out = {
-        "metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if args.prec == "fp32" else "bf16/f64",
-        "data": "synthetic",
-        "config": {"workload": f"{Ly}x{Lx} Heisenberg D={D} Dc={Dc}, {nch} chains, plain pair sweeps, "
-                               + ("fp32 contractions" if args.prec == "fp32" else
-                                  "bf16-operand sampling pass, fp64 measurement")
+        "metric": METRIC, "value": head["samples_per_s"], "unit": "samples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16/f64" if is_learned else "f32", "data": "synthetic",
+        "config": {"workload": f"{Ly}x{Lx} Heisenberg D={D} Dc={Dc}, {nch} chains, "
+                               + ("learned plaquette moves + pair sweeps, bf16-operand sampling pass, "
+                                  "fp64 measurement" if is_learned else "plain pair sweeps, fp32 contractions")
                                + " / fp64 compression",
                    "Ly": Ly, "Lx": Lx, "D": D, "Dc": Dc, "chains": nch, "J2": 0.0,
                    "parallelism": "chains (1 GPU)"},
-        "roofline": roofline,
-        "phase_ms_per_step": {k: v / args.steps for k, v in ms.items()},
-        "e_site_last_sweep": e_site,
+        "roofline": head["roofline"],
+        "phase_ms_per_step": {k: v / args.steps for k, v in head["ms"].items()},
     }
+    for name, r in res.items():
+        out[name] = {k: v for k, v in r.items() if k not in ("ms", "launches", "roofline")}
+        out[name]["phase_ms_per_step"] = {k: v / args.steps for k, v in r["ms"].items()}
+        out[name]["dominant_kernel"] = r["roofline"]
+    if "plain" in res and "learned" in res:
+        out["learned_over_plain_raw"] = res["learned"]["samples_per_s"] / res["plain"]["samples_per_s"]
+        if args.tau_sweeps:
+            # time to a fixed standard error dE of E/site ~ var * 2 tau / (dE^2 * rate)
+            def cost(t):
+                return t["var_e_site_per_sample"] * 2.0 * t["tau_int_mean"] / t["samples_per_s"]
+            out["learned_over_plain_at_fixed_dE"] = cost(res["plain"]["tau"]) / cost(res["learned"]["tau"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(Ly, Lx, D, Dc, seed=1908)
-    ctx.close()
     print(json.dumps(out), flush=True)
 
 

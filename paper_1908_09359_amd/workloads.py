@@ -47,3 +47,11 @@ def random_configs(Ly, Lx, n, seed):
     base = np.zeros(N, dtype=np.int8)
     base[: N // 2] = 1
     return np.stack([rng.permutation(base) for _ in range(n)]) if n else np.zeros((0, N), np.int8)
+
+
+def random_proposal_weights(seed, n=19105, scale=0.05, bias=-1.0):
+    """float32 start of the plaquette proposal network: i.i.d. N(0, scale^2)
+    parameters and output bias `bias` (a propensity near sigmoid(bias))."""
+    w = (np.random.default_rng(seed).standard_normal(n) * scale).astype(np.float32)
+    w[-1] = bias
+    return w
