@@ -134,6 +134,43 @@ vp_status vp_sample(vp_ctx* ctx, int32_t lat, int32_t n_burn, int32_t n_meas,
                     double* log_abs_psi_dev, int8_t* sign_dev, double* e_loc_dev,
                     void* dlnpsi_dev, int8_t* spins_out_dev, int64_t* accept_dev);
 
+/* Launch schedules of a lattice's sweeps (vp_set_schedule).
+ * VP_SCHED_PHASES: one launch per phase and row, every chain in each.
+ * VP_SCHED_PERSISTENT: one launch per sweep; its work-groups take chains from
+ *   a queue and run each chain's whole sweep (all rows, both passes).
+ * VP_SCHED_GRAPH: the per-phase launches of one sweep are captured once per
+ *   vp_sample call into a HIP graph and replayed every sweep.
+ * All three produce the same results (float64: bit-identical chains); phase
+ * timing (vp_timing_*) then books whole sweeps under VP_PH_OTHER. */
+typedef enum { VP_SCHED_PHASES = 0, VP_SCHED_PERSISTENT = 1, VP_SCHED_GRAPH = 2 } vp_schedule;
+vp_status vp_set_schedule(vp_ctx* ctx, int32_t lat, int32_t schedule);
+
+/* Outputs of one lattice in vp_sample_batch (device pointers, same layout as
+ * vp_sample's; dlnpsi_dev and spins_out_dev may be NULL). */
+typedef struct {
+  double* log_abs_psi_dev;
+  int8_t* sign_dev;
+  double* e_loc_dev;
+  void* dlnpsi_dev;
+  int8_t* spins_out_dev;
+} vp_outputs;
+
+/* vp_sample for several lattices of one context at once (uneven sizes and
+ * couplings allowed; D, Dc and precision must be equal): each sweep is one
+ * persistent launch whose queue holds every chain of every listed lattice,
+ * largest lattices first.  lats_host [n_lats] lattice indices (distinct);
+ * outs_host [n_lats] (may be NULL when n_meas = 0).  Each lattice keeps its
+ * own sampler. */
+vp_status vp_sample_batch(vp_ctx* ctx, int32_t n_lats, const int32_t* lats_host, int32_t n_burn, int32_t n_meas,
+                          const vp_outputs* outs_host);
+
+/* Times `sweeps` unmeasured sweeps of the lattice under each schedule (after
+ * one warm-up sweep each; the chains advance by 3 (sweeps + 1) sweeps, which
+ * count as burn-in), keeps the fastest and returns it in *schedule_out;
+ * ms_host [3] (may be NULL) receives the milliseconds per sweep of
+ * VP_SCHED_PHASES, VP_SCHED_PERSISTENT and VP_SCHED_GRAPH.  Waits. */
+vp_status vp_autotune(vp_ctx* ctx, int32_t lat, int32_t sweeps, double* ms_host, int32_t* schedule_out);
+
 /* Record the sampler's decisions: while trace_dev is set (NULL clears it),
  * every sweep of vp_sample overwrites trace_dev[chain][b][0..1] with the ratio
  * rho = Psi(S')/Psi(S) that bond b's Metropolis test used (float64, after the

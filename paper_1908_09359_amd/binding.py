@@ -15,6 +15,7 @@ VP_OK, VP_ERR_ARG, VP_ERR_SHAPE, VP_ERR_OOM, VP_ERR_DEVICE = 0, 1, 2, 3, 4
 VP_ERR_ZERO_AMPLITUDE, VP_ERR_NONFINITE, VP_ERR_UNSUPPORTED = 5, 6, 7
 VP_FP64, VP_FP32, VP_BF16 = 0, 1, 2
 VP_SAMPLER_PAIR_SEQ, VP_SAMPLER_LEARNED_PLAQ = 0, 1
+VP_SCHED_PHASES, VP_SCHED_PERSISTENT, VP_SCHED_GRAPH = 0, 1, 2
 
 STATUS_NAMES = {0: "VP_OK", 1: "VP_ERR_ARG", 2: "VP_ERR_SHAPE", 3: "VP_ERR_OOM", 4: "VP_ERR_DEVICE",
                 5: "VP_ERR_ZERO_AMPLITUDE", 6: "VP_ERR_NONFINITE", 7: "VP_ERR_UNSUPPORTED"}
@@ -24,10 +25,16 @@ EXPORTED = ["vp_create", "vp_destroy", "vp_last_error", "vp_num_params", "vp_wor
             "vp_eval", "vp_gradient", "vp_sr_update", "vp_sign_sgd_update", "vp_sync",
             "vp_timing_enable", "vp_timing_read", "vp_stats_tau", "vp_trace_ratios", "vp_plaquette_ratios",
             "vp_proposal_num_params", "vp_proposal_set_weights", "vp_proposal_get_weights", "vp_proposal_forward",
-            "vp_proposal_loss_grad", "vp_proposal_train", "vp_set_sampler", "vp_move_counts"]
+            "vp_proposal_loss_grad", "vp_proposal_train", "vp_set_sampler", "vp_move_counts", "vp_set_schedule",
+            "vp_sample_batch", "vp_autotune"]
 
 PHASES = ["row3_envs", "hsweep", "row4_envs", "vsweep", "compress_up", "compress_down", "measure3",
           "measure4", "other"]
+
+
+class vp_outputs(ctypes.Structure):
+    _fields_ = [("log_abs_psi_dev", ctypes.c_void_p), ("sign_dev", ctypes.c_void_p), ("e_loc_dev", ctypes.c_void_p),
+                ("dlnpsi_dev", ctypes.c_void_p), ("spins_out_dev", ctypes.c_void_p)]
 
 
 class vp_lattice(ctypes.Structure):
@@ -79,6 +86,9 @@ def _load():
         "vp_proposal_train": ([P, I32, P, P, I64, I32, I32, D, U64, P], I32),
         "vp_set_sampler": ([P, I32, I32], I32),
         "vp_move_counts": ([P, I32, P], I32),
+        "vp_set_schedule": ([P, I32, I32], I32),
+        "vp_sample_batch": ([P, I32, P, I32, I32, P], I32),
+        "vp_autotune": ([P, I32, I32, P, P], I32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -201,6 +211,28 @@ class Context:
 
     def vp_set_sampler(self, lat, sampler):
         self._check(LIB.vp_set_sampler(self.h, lat, sampler))
+
+    def vp_set_schedule(self, lat, schedule):
+        self._check(LIB.vp_set_schedule(self.h, lat, schedule))
+
+    def vp_sample_batch(self, lats, n_burn, n_meas, outputs=None):
+        """lats: lattice indices; outputs: one dict per lattice with log_abs_psi, sign, e_loc
+        (and optionally dlnpsi, spins_out) device tensors, or None for unmeasured sweeps."""
+        n = len(lats)
+        idx = (ctypes.c_int32 * n)(*lats)
+        outs = None
+        if outputs is not None:
+            outs = (vp_outputs * n)(*[vp_outputs(_ptr(o["log_abs_psi"]), _ptr(o["sign"]), _ptr(o["e_loc"]),
+                                                 _ptr(o.get("dlnpsi")), _ptr(o.get("spins_out")))
+                                      for o in outputs])
+        self._check(LIB.vp_sample_batch(self.h, n, idx, n_burn, n_meas, outs))
+
+    def vp_autotune(self, lat, sweeps):
+        """Returns (chosen schedule, [ms per sweep of phases, persistent, graph])."""
+        ms = (ctypes.c_double * 3)()
+        pick = ctypes.c_int32()
+        self._check(LIB.vp_autotune(self.h, lat, sweeps, ms, ctypes.byref(pick)))
+        return pick.value, list(ms)
 
     def vp_move_counts(self, lat, counts):
         self._check(LIB.vp_move_counts(self.h, lat, _ptr(counts)))

@@ -48,6 +48,8 @@ struct Lattice {
   int64_t adam_t = 0;
   bool net_ready = false;
   int32_t sampler = VP_SAMPLER_PAIR_SEQ;
+  int32_t schedule = VP_SCHED_PHASES;
+  int64_t sweeps = 0;           // sweeps since vp_init_chains (every chain's counter)
   LatDev dev{};
   bool tensors_ready = false;
   bool chains_ready = false;
@@ -68,6 +70,17 @@ struct vp_ctx {
   size_t ev_used = 0;
   double ph_ms[VP_NPHASE] = {0};
   int64_t ph_n[VP_NPHASE] = {0};
+  // persistent-launch tables (device) and their host images
+  LatDev* q_lats = nullptr;
+  SampleOut* q_outs = nullptr;
+  int2* q_items = nullptr;
+  int* q_next = nullptr;
+  size_t q_lat_cap = 0, q_item_cap = 0;
+  std::vector<LatDev> h_lats;
+  std::vector<SampleOut> h_outs;
+  std::vector<int2> h_items;
+  hipStream_t cap_stream = nullptr;  // private stream for graph capture
+  hipEvent_t cap_event = nullptr;
 };
 
 namespace {
@@ -289,6 +302,105 @@ void run_sweep(vp_ctx* ctx, Lattice& L, const SampleOut* o, hipStream_t s) {
   if (o) TIMED(r, VP_PH_OTHER, launch_finish_sample(L.dev, *o, L.p.n_chains, s));
   TIMED(r, VP_PH_OTHER, launch_next_sweep(L.dev, s));
   if (ctx->ev_used >= 8192) fold_timing(ctx);
+}
+
+// Persistent schedule: every chain of every lattice in one launch per sweep.
+// All lattices share d, c and the working precision.
+template <typename T>
+vp_status run_queue(vp_ctx* ctx, const std::vector<Lattice*>& lats, int n_burn, int n_meas,
+                    const std::vector<SampleOut>& outs, hipStream_t s) {
+  const int n = (int)lats.size();
+  // the tables are rewritten: the previous call's launches must be done
+  HIP_TRY(ctx, hipStreamSynchronize(s));
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return lats[a]->N > lats[b]->N; });
+  ctx->h_lats.resize(n);
+  ctx->h_outs.assign(outs.begin(), outs.end());
+  ctx->h_items.clear();
+  for (int i = 0; i < n; ++i) {
+    ctx->h_lats[i] = lats[i]->dev;
+    ctx->h_lats[i].learned = lats[i]->sampler == VP_SAMPLER_LEARNED_PLAQ;
+  }
+  // largest lattices first: their sweeps start early and the short ones fill the tail
+  for (int i : order)
+    for (int ch = 0; ch < lats[i]->p.n_chains; ++ch) ctx->h_items.push_back(int2{i, ch});
+  const size_t ni = ctx->h_items.size();
+  if (ctx->q_lat_cap < (size_t)n) {
+    if (ctx->q_lats) hipFree(ctx->q_lats);
+    if (ctx->q_outs) hipFree(ctx->q_outs);
+    ctx->q_lats = nullptr; ctx->q_outs = nullptr;
+    if (hipMalloc((void**)&ctx->q_lats, sizeof(LatDev) * n) != hipSuccess ||
+        hipMalloc((void**)&ctx->q_outs, sizeof(SampleOut) * n) != hipSuccess)
+      return fail(ctx, VP_ERR_OOM, "persistent-launch tables");
+    ctx->q_lat_cap = n;
+  }
+  if (ctx->q_item_cap < ni) {
+    if (ctx->q_items) hipFree(ctx->q_items);
+    ctx->q_items = nullptr;
+    if (hipMalloc((void**)&ctx->q_items, sizeof(int2) * ni) != hipSuccess)
+      return fail(ctx, VP_ERR_OOM, "persistent-launch work list");
+    ctx->q_item_cap = ni;
+  }
+  if (!ctx->q_next && hipMalloc((void**)&ctx->q_next, sizeof(int)) != hipSuccess)
+    return fail(ctx, VP_ERR_OOM, "persistent-launch counter");
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->q_lats, ctx->h_lats.data(), sizeof(LatDev) * n, hipMemcpyHostToDevice, s));
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->q_outs, ctx->h_outs.data(), sizeof(SampleOut) * n, hipMemcpyHostToDevice, s));
+  HIP_TRY(ctx, hipMemcpyAsync(ctx->q_items, ctx->h_items.data(), sizeof(int2) * ni, hipMemcpyHostToDevice, s));
+  const bool bf = lats[0]->p.prec == VP_BF16;
+  int dev = 0, cus = 0;
+  HIP_TRY(ctx, hipGetDevice(&dev));
+  HIP_TRY(ctx, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int occ = std::max(1, sweep_queue_occupancy<T>(lats[0]->dev, bf));
+  const int grid = (int)std::min<size_t>(ni, (size_t)cus * occ);
+  Rec r(ctx);
+  for (int i = 0; i < n_burn + n_meas; ++i) {
+    TIMED(r, VP_PH_OTHER, launch_sweep_queue<T>(lats[0]->dev, ctx->q_lats, ctx->q_outs, i >= n_burn ? 1 : 0,
+                                                 ctx->q_items, (int)ni, ctx->q_next, bf, grid, s));
+    HIP_TRY(ctx, hipGetLastError());
+  }
+  if (ctx->ev_used >= 8192) fold_timing(ctx);
+  return VP_OK;
+}
+
+// Graph schedule: the per-phase launches of one sweep captured once per call
+// (one graph without and one with measurement) and replayed every sweep.
+template <typename T>
+vp_status run_graph(vp_ctx* ctx, Lattice& L, int n_burn, int n_meas, const SampleOut& o, hipStream_t s) {
+  if (!ctx->cap_stream) {
+    HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->cap_event, hipEventDisableTiming));
+  }
+  if (ctx->ev_used) fold_timing(ctx);  // no event synchronisation may happen while capturing
+  const bool timing = ctx->timing;
+  ctx->timing = false;  // no event records inside the graphs
+  hipGraph_t g[2] = {nullptr, nullptr};
+  hipGraphExec_t x[2] = {nullptr, nullptr};
+  vp_status st = VP_OK;
+  for (int k = 0; k < 2 && st == VP_OK; ++k) {
+    if ((k == 0 && n_burn == 0) || (k == 1 && n_meas == 0)) continue;
+    if (hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      st = fail(ctx, VP_ERR_DEVICE, "graph capture could not begin");
+      break;
+    }
+    run_sweep<T>(ctx, L, k == 1 ? &o : nullptr, ctx->cap_stream);
+    if (hipStreamEndCapture(ctx->cap_stream, &g[k]) != hipSuccess ||
+        hipGraphInstantiate(&x[k], g[k], nullptr, nullptr, 0) != hipSuccess)
+      st = fail(ctx, VP_ERR_DEVICE, "graph capture of the sweep failed");
+  }
+  ctx->timing = timing;
+  Rec r(ctx);
+  for (int i = 0; i < n_burn + n_meas && st == VP_OK; ++i) {
+    TIMED(r, VP_PH_OTHER, hipGraphLaunch(x[i >= n_burn ? 1 : 0], s));
+    if (hipGetLastError() != hipSuccess) st = fail(ctx, VP_ERR_DEVICE, "graph launch failed");
+  }
+  // the executable graphs are released once their launches are done
+  hipStreamSynchronize(s);
+  for (int k = 0; k < 2; ++k) {
+    if (x[k]) hipGraphExecDestroy(x[k]);
+    if (g[k]) hipGraphDestroy(g[k]);
+  }
+  return st;
 }
 
 template <typename T>
@@ -518,6 +630,11 @@ vp_status vp_destroy(vp_ctx* ctx) {
     for (void* q : ptrs)
       if (q) hipFree(q);
   }
+  void* qp[] = {ctx->q_lats, ctx->q_outs, ctx->q_items, ctx->q_next};
+  for (void* q : qp)
+    if (q) hipFree(q);
+  if (ctx->cap_event) hipEventDestroy(ctx->cap_event);
+  if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
   delete ctx;
   return VP_OK;
 }
@@ -579,6 +696,7 @@ vp_status vp_init_chains(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev) {
     HIP_TRY(ctx, hipGetLastError());
   }
   L->chains_ready = true;
+  L->sweeps = 0;
   L->lower_valid = false;
   return VP_OK;
 }
@@ -609,17 +727,127 @@ vp_status vp_sample(vp_ctx* ctx, int32_t lat, int32_t n_burn, int32_t n_meas, do
   o.n_meas = n_meas;
   o.np_half = L->Np / 2;
   o.psi_meas = L->p.prec == VP_BF16;
-  for (int i = 0; i < n_burn + n_meas; ++i) {
-    o.m = i - n_burn;
-    const SampleOut* op = i >= n_burn ? &o : nullptr;
-    if (f64) run_sweep<double>(ctx, *L, op, s); else run_sweep<float>(ctx, *L, op, s);
-    HIP_TRY(ctx, hipGetLastError());
+  // measurement row = sweep counter - (counter at the first measured sweep)
+  o.dyn_m = 1;
+  o.sweep0 = L->sweeps + n_burn;
+  vp_status st = VP_OK;
+  if (L->schedule == VP_SCHED_PERSISTENT) {
+    std::vector<Lattice*> one{L};
+    std::vector<SampleOut> oo{o};
+    st = f64 ? run_queue<double>(ctx, one, n_burn, n_meas, oo, s) : run_queue<float>(ctx, one, n_burn, n_meas, oo, s);
+  } else if (L->schedule == VP_SCHED_GRAPH) {
+    st = f64 ? run_graph<double>(ctx, *L, n_burn, n_meas, o, s) : run_graph<float>(ctx, *L, n_burn, n_meas, o, s);
+  } else {
+    for (int i = 0; i < n_burn + n_meas; ++i) {
+      const SampleOut* op = i >= n_burn ? &o : nullptr;
+      if (f64) run_sweep<double>(ctx, *L, op, s); else run_sweep<float>(ctx, *L, op, s);
+      HIP_TRY(ctx, hipGetLastError());
+    }
   }
+  if (st != VP_OK) return st;
+  L->sweeps += n_burn + n_meas;
   if (accept_dev) {
     // accepted / proposed pairs are the 2nd and 3rd int64 of ChainMeta
     HIP_TRY(ctx, hipMemcpy2DAsync(accept_dev, 2 * sizeof(int64_t), (const char*)L->meta + sizeof(int64_t),
                                   sizeof(ChainMeta), 2 * sizeof(int64_t), L->p.n_chains, hipMemcpyDeviceToDevice, s));
   }
+  return VP_OK;
+}
+
+vp_status vp_set_schedule(vp_ctx* ctx, int32_t lat, int32_t schedule) {
+  Lattice* L = get_lat(ctx, lat);
+  if (!L) return fail(ctx, VP_ERR_ARG, "bad lattice index");
+  if (schedule != VP_SCHED_PHASES && schedule != VP_SCHED_PERSISTENT && schedule != VP_SCHED_GRAPH)
+    return fail(ctx, VP_ERR_ARG, "unknown schedule %d", schedule);
+  L->schedule = schedule;
+  return VP_OK;
+}
+
+vp_status vp_sample_batch(vp_ctx* ctx, int32_t n_lats, const int32_t* lats_host, int32_t n_burn, int32_t n_meas,
+                          const vp_outputs* outs_host) {
+  if (!ctx || n_lats < 1 || !lats_host) return fail(ctx, VP_ERR_ARG, "need at least one lattice");
+  if (n_burn < 0 || n_meas < 0) return fail(ctx, VP_ERR_ARG, "negative sweep count");
+  if (n_meas > 0 && !outs_host) return fail(ctx, VP_ERR_ARG, "outputs are required for measured sweeps");
+  std::vector<Lattice*> ls;
+  std::vector<SampleOut> os;
+  for (int i = 0; i < n_lats; ++i) {
+    Lattice* L = get_lat(ctx, lats_host[i]);
+    if (!L) return fail(ctx, VP_ERR_ARG, "bad lattice index %d", lats_host[i]);
+    for (Lattice* q : ls)
+      if (q == L) return fail(ctx, VP_ERR_ARG, "lattice %d listed twice", lats_host[i]);
+    if (!L->tensors_ready || !L->chains_ready)
+      return fail(ctx, VP_ERR_ARG, "lattice %d: tensors and chains must be initialised first", lats_host[i]);
+    if (!ls.empty() && (L->p.D != ls[0]->p.D || L->p.Dc != ls[0]->p.Dc || L->p.prec != ls[0]->p.prec))
+      return fail(ctx, VP_ERR_SHAPE, "one batch needs equal D, Dc and precision");
+    SampleOut o{};
+    if (n_meas > 0) {
+      const vp_outputs& u = outs_host[i];
+      if (!u.log_abs_psi_dev || !u.sign_dev || !u.e_loc_dev)
+        return fail(ctx, VP_ERR_ARG, "lattice %d: log_abs_psi, sign and e_loc outputs are required", lats_host[i]);
+      o.log_abs_psi = u.log_abs_psi_dev;
+      o.sign = u.sign_dev;
+      o.e_loc = u.e_loc_dev;
+      o.dlnpsi = u.dlnpsi_dev;
+      o.spins = u.spins_out_dev;
+    }
+    o.n_meas = n_meas;
+    o.np_half = L->Np / 2;
+    o.psi_meas = L->p.prec == VP_BF16;
+    o.dyn_m = 1;
+    o.sweep0 = L->sweeps + n_burn;
+    ls.push_back(L);
+    os.push_back(o);
+  }
+  hipStream_t s = ctx->stream;
+  const bool f64 = works_f64(ls[0]->p.prec);
+  for (Lattice* L : ls)
+    if (!L->lower_valid) {
+      if (f64) run_lower_pass<double>(ctx, *L, s); else run_lower_pass<float>(ctx, *L, s);
+      L->lower_valid = true;
+    }
+  vp_status st = f64 ? run_queue<double>(ctx, ls, n_burn, n_meas, os, s) : run_queue<float>(ctx, ls, n_burn, n_meas, os, s);
+  if (st != VP_OK) return st;
+  for (Lattice* L : ls) L->sweeps += n_burn + n_meas;
+  return VP_OK;
+}
+
+vp_status vp_autotune(vp_ctx* ctx, int32_t lat, int32_t sweeps, double* ms_host, int32_t* schedule_out) {
+  Lattice* L = get_lat(ctx, lat);
+  if (!L) return fail(ctx, VP_ERR_ARG, "bad lattice index");
+  if (sweeps < 1) return fail(ctx, VP_ERR_ARG, "sweeps must be >= 1");
+  if (!L->tensors_ready || !L->chains_ready)
+    return fail(ctx, VP_ERR_ARG, "tensors and chains must be initialised first");
+  hipStream_t s = ctx->stream;
+  hipEvent_t e0, e1;
+  HIP_TRY(ctx, hipEventCreate(&e0));
+  HIP_TRY(ctx, hipEventCreate(&e1));
+  const int32_t cand[3] = {VP_SCHED_PHASES, VP_SCHED_PERSISTENT, VP_SCHED_GRAPH};
+  double best = 1e300;
+  int32_t pick = VP_SCHED_PHASES;
+  const bool timing = ctx->timing;
+  ctx->timing = false;
+  vp_status st = VP_OK;
+  for (int k = 0; k < 3 && st == VP_OK; ++k) {
+    L->schedule = cand[k];
+    // one untimed sweep first (initial boundaries, graph and code warm-up)
+    st = vp_sample(ctx, lat, 1, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+    if (st != VP_OK) break;
+    hipEventRecord(e0, s);
+    st = vp_sample(ctx, lat, sweeps, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+    hipEventRecord(e1, s);
+    if (st != VP_OK) break;
+    if (hipEventSynchronize(e1) != hipSuccess) { st = fail(ctx, VP_ERR_DEVICE, "autotune timing failed"); break; }
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    if (ms_host) ms_host[k] = ms / sweeps;
+    if (ms < best) { best = ms; pick = cand[k]; }
+  }
+  ctx->timing = timing;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (st != VP_OK) return st;
+  L->schedule = pick;
+  if (schedule_out) *schedule_out = pick;
   return VP_OK;
 }
 

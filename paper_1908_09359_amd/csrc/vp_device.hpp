@@ -233,14 +233,15 @@ __device__ void wg_gemm(TC* __restrict__ C, View vc, const TA* __restrict__ A, V
 }
 
 // Operand precision chosen at compile time: BF16 rounds both operands to bf16
-// (f32 accumulation); otherwise the products are formed in TC.
+// (f32 accumulation); otherwise the products are formed in TC.  tiles: LDS of
+// GEMM_TILE_BYTES owned by the caller.
 template <bool BF16, typename TC, typename TA, typename TB>
-__device__ inline void wg_gemm_p(TC* __restrict__ C, View vc, const TA* __restrict__ A, View va,
+__device__ inline void wg_gemm_p(char* tiles, TC* __restrict__ C, View vc, const TA* __restrict__ A, View va,
                                  const TB* __restrict__ B, View vb, int M, int N, int K) {
   if constexpr (BF16) {
-    wg_gemm_bf16<TC>(gemm_tiles(), C, vc, A, va, B, vb, M, N, K, TC(1), false);
+    wg_gemm_bf16<TC>(tiles, C, vc, A, va, B, vb, M, N, K, TC(1), false);
   } else {
-    wg_gemm_t<TC>(gemm_tiles(), C, vc, A, va, B, vb, M, N, K);
+    wg_gemm_t<TC>(tiles, C, vc, A, va, B, vb, M, N, K);
   }
 }
 
@@ -316,16 +317,16 @@ struct S4 { int l, u, r, d; };        // PEPS site
 // Lin/Lout are dense c x d x c; X0/X1 scratch of c*c*d*d elements.
 template <typename T, bool BF16 = false>
 __device__ void env3_step(T* Lout, const T* Lin, const T* A, S3 sA, const T* t, S4 st,
-                          const T* B, S3 sB, T* X0, T* X1, int c, int d) {
+                          const T* B, S3 sB, T* X0, T* X1, int c, int d, char* tiles) {
   using TC = T;
   // X0[c'][b][l][u] = sum_a Lin[a][(l,c')] A[a][(u,b)]
-  wg_gemm_p<BF16, TC>(X0, view(c, d, c * d * d, c, 1, d * d), Lin, view(c, c, 1, 1, d * c, 0),
+  wg_gemm_p<BF16, TC>(tiles, X0, view(c, d, c * d * d, c, 1, d * d), Lin, view(c, c, 1, 1, d * c, 0),
              A, view(1, sA.s0, 0, c, sA.s1, sA.s2), d * c, d * c, c);
   // X1[b][r][c'][dd] = sum_{l,u} X0[(c',b)][(l,u)] t[(l,u)][(r,dd)]
-  wg_gemm_p<BF16, TC>(X1, view(c, d, d * c * d, d, c * d, 1), X0, rowmajor(d * d),
+  wg_gemm_p<BF16, TC>(tiles, X1, view(c, d, d * c * d, d, c * d, 1), X0, rowmajor(d * d),
              t, view(d, st.l, st.u, d, st.r, st.d), c * c, d * d, d * d);
   // Lout[(b,r)][e] = sum_{c',dd} X1[(b,r)][(c',dd)] B[(c',dd)][e]
-  wg_gemm_p<BF16, TC>(Lout, rowmajor(c), X1, rowmajor(c * d), B, view(d, sB.s0, sB.s1, 1, sB.s2, 0),
+  wg_gemm_p<BF16, TC>(tiles, Lout, rowmajor(c), X1, rowmajor(c * d), B, view(d, sB.s0, sB.s1, 1, sB.s2, 0),
              c * d, c, c * d);
 }
 
@@ -334,18 +335,18 @@ __device__ void env3_step(T* Lout, const T* Lin, const T* A, S3 sA, const T* t, 
 // X0/X1 scratch of d*d*d*c*c elements each.
 template <typename TC, typename T, bool BF16 = false>
 __device__ void env4_step(TC* Lout, const TC* Lin, const T* A, S3 sA, const T* t1, S4 s1,
-                          const T* t2, S4 s2, const T* B, S3 sB, TC* X0, TC* X1, int c, int d) {
+                          const T* t2, S4 s2, const T* B, S3 sB, TC* X0, TC* X1, int c, int d, char* tiles) {
   // X0[(l2,c')][b][l1][u] = sum_a Lin[a][(l1,(l2,c'))] A[a][(u,b)]
-  wg_gemm_p<BF16, TC>(X0, view(d * c, d, c * d * d, c, 1, d * d), Lin, view(d * c, d * c, 1, 1, d * d * c, 0),
+  wg_gemm_p<BF16, TC>(tiles, X0, view(d * c, d, c * d * d, c, 1, d * d), Lin, view(d * c, d * c, 1, 1, d * d * c, 0),
              A, view(1, sA.s0, 0, c, sA.s1, sA.s2), d * d * c, d * c, c);
   // X1[(c',b)][r1][l2][m] = sum_{l1,u} X0[(l2,c',b)][(l1,u)] t1[(l1,u)][(r1,m)]
-  wg_gemm_p<BF16, TC>(X1, view(c * c, d, d * d * d, d, d * d, 1), X0, rowmajor(d * d),
+  wg_gemm_p<BF16, TC>(tiles, X1, view(c * c, d, d * d * d, d, d * d, 1), X0, rowmajor(d * d),
              t1, view(d, s1.l, s1.u, d, s1.r, s1.d), d * c * c, d * d, d * d);
   // X0[(b,r1)][r2][c'][dd] = sum_{l2,m} X1[(c',b,r1)][(l2,m)] t2[(l2,m)][(r2,dd)]
-  wg_gemm_p<BF16, TC>(X0, view(c * d, d, d * d * c, d, c * d, 1), X1, rowmajor(d * d),
+  wg_gemm_p<BF16, TC>(tiles, X0, view(c * d, d, d * d * c, d, c * d, 1), X1, rowmajor(d * d),
              t2, view(d, s2.l, s2.u, d, s2.r, s2.d), c * c * d, d * d, d * d);
   // Lout[(b,r1,r2)][e] = sum_{c',dd} X0[(b,r1,r2)][(c',dd)] B[(c',dd)][e]
-  wg_gemm_p<BF16, TC>(Lout, rowmajor(c), X0, rowmajor(c * d), B, view(d, sB.s0, sB.s1, 1, sB.s2, 0),
+  wg_gemm_p<BF16, TC>(tiles, Lout, rowmajor(c), X0, rowmajor(c * d), B, view(d, sB.s0, sB.s1, 1, sB.s2, 0),
              c * d * d, c, c * d);
 }
 
@@ -353,16 +354,16 @@ __device__ void env4_step(TC* Lout, const TC* Lin, const T* A, S3 sA, const T* t
 //   Out[l][u][r][dd] = sum Lp[a][l][c] A[a][u][b] Rn[b][r][e] B[c][dd][e].
 template <typename T>
 __device__ void defect3(T* Out, const T* Lp, const T* A, S3 sA, const T* Rn, const T* B, S3 sB,
-                        T* X0, T* X1, int c, int d) {
+                        T* X0, T* X1, int c, int d, char* tiles) {
   using TC = T;
   // X0[l][u][c'][b] = sum_a Lp[a][(l,c')] A[a][(u,b)]
-  wg_gemm<TC>(X0, view(c, d * c * c, c, c, c * c, 1), Lp, view(c, c, 1, 1, d * c, 0),
+  wg_gemm_t<TC>(tiles, X0, view(c, d * c * c, c, c, c * c, 1), Lp, view(c, c, 1, 1, d * c, 0),
              A, view(1, sA.s0, 0, c, sA.s1, sA.s2), d * c, d * c, c);
   // X1[(l,u)][r][c'][e] = sum_b X0[(l,u,c')][b] Rn[b][(r,e)]
-  wg_gemm<TC>(X1, view(c, d * c * c, c, c, c * c, 1), X0, rowmajor(c), Rn, rowmajor(d * c),
+  wg_gemm_t<TC>(tiles, X1, view(c, d * c * c, c, c, c * c, 1), X0, rowmajor(c), Rn, rowmajor(d * c),
              d * d * c, d * c, c);
   // Out[(l,u,r)][dd] = sum_{c',e} X1[(l,u,r)][(c',e)] B[(c',e)][dd]
-  wg_gemm<TC>(Out, rowmajor(d), X1, rowmajor(c * c), B, view(c, sB.s0, sB.s2, 1, sB.s1, 0),
+  wg_gemm_t<TC>(tiles, Out, rowmajor(d), X1, rowmajor(c * c), B, view(c, sB.s0, sB.s2, 1, sB.s1, 0),
              d * d * d, d, c * c);
 }
 

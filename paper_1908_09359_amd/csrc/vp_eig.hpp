@@ -17,8 +17,13 @@ constexpr int EIG_PACK = EIG_NMAX * (EIG_NMAX + 1) / 2;
 // LDS the caller provides: the packed matrix; afterwards the same space holds
 // the LU factors (3 x n x EIG_KMAX), the kept vectors (n x EIG_KMAX) and the
 // pivot-swap bit words (n).
-constexpr size_t EIG_LDS_BYTES = sizeof(double) * EIG_PACK;
-static_assert(3 * EIG_NMAX * EIG_KMAX * 8 + EIG_NMAX * EIG_KMAX * 8 + EIG_NMAX * 4 <= EIG_LDS_BYTES, "eig LDS");
+// Small work arrays follow the packed matrix: d, e, e^2, tau, p, w, v (7 n),
+// two half-row partials (2 n), the multisection probes and counts (2 WG) and
+// the batch eigenvalues (EIG_KMAX).
+constexpr size_t EIG_PACK_BYTES = sizeof(double) * EIG_PACK;
+constexpr size_t EIG_SMALL_BYTES = sizeof(double) * (9 * EIG_NMAX + WG + EIG_KMAX) + sizeof(int) * WG;
+constexpr size_t EIG_LDS_BYTES = EIG_PACK_BYTES + EIG_SMALL_BYTES;
+static_assert(3 * EIG_NMAX * EIG_KMAX * 8 + EIG_NMAX * EIG_KMAX * 8 + EIG_NMAX * 4 <= EIG_PACK_BYTES, "eig LDS");
 
 __device__ inline int tri(int i) { return i * (i + 1) / 2; }
 
@@ -45,12 +50,17 @@ __device__ void sym_topk_eig(const double* H, int n, int k, double* V, double* l
   double* Ap = reinterpret_cast<double*>(lds);
   double* Xs = Ap + 3 * EIG_NMAX * EIG_KMAX;                            // after the tridiagonalisation
   unsigned* pivw = reinterpret_cast<unsigned*>(Xs + EIG_NMAX * EIG_KMAX);  // bit t: row swap of vector t
-  __shared__ double dg[EIG_NMAX], eg[EIG_NMAX], e2[EIG_NMAX], tau[EIG_NMAX];
-  __shared__ double pv[EIG_NMAX], wv[EIG_NMAX], vv[EIG_NMAX];
-  __shared__ double pv2[2][EIG_NMAX];
-  __shared__ double probe_x[WG];
-  __shared__ int probe_c[WG];
-  __shared__ double lamb[EIG_KMAX];
+  double* dg = reinterpret_cast<double*>(lds + EIG_PACK_BYTES);
+  double* eg = dg + EIG_NMAX;
+  double* e2 = eg + EIG_NMAX;
+  double* tau = e2 + EIG_NMAX;
+  double* pv = tau + EIG_NMAX;
+  double* wv = pv + EIG_NMAX;
+  double* vv = wv + EIG_NMAX;
+  double (*pv2)[EIG_NMAX] = reinterpret_cast<double (*)[EIG_NMAX]>(vv + EIG_NMAX);
+  double* probe_x = vv + 3 * EIG_NMAX;
+  double* lamb = probe_x + WG;
+  int* probe_c = reinterpret_cast<int*>(lamb + EIG_KMAX);
   const int tid = threadIdx.x;
 
   for (int e = tid; e < n * n; e += WG) {

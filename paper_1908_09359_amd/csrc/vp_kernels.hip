@@ -10,6 +10,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 namespace vp {
 
 namespace {
@@ -21,6 +23,7 @@ struct Chain {
   double* dw;
   ChainMeta* meta;
   int8_t* sp;
+  int id;  // chain index within its lattice (Philox counter word 0, output row)
 };
 
 template <typename T>
@@ -31,6 +34,7 @@ __device__ inline Chain<T> chain_of(const LatDev& L, int ch) {
   C.dw = L.dws + (int64_t)ch * L.dws_stride;
   C.meta = L.meta + ch;
   C.sp = L.spins + (int64_t)ch * L.N;
+  C.id = ch;
   return C;
 }
 
@@ -69,19 +73,25 @@ __device__ inline void raise_flag(ChainMeta* m, int f) {
   if (threadIdx.x == 0) m->flags |= f;
 }
 
+// Row of this measurement in the outputs: fixed, or from the sweep counter
+// (so that one captured sweep serves every measured sweep of a call).
+__device__ inline int64_t meas_index(const SampleOut& o, const ChainMeta* m) {
+  return o.dyn_m ? m->sweep - o.sweep0 : (int64_t)o.m;
+}
+
 // 3-line column step with optional flipped site: t = T[s ^ flip].
 template <typename T, bool BF16 = false>
 __device__ inline int step3(const LatDev& L, const Chain<T>& C, T* out, const T* in, int y, int x,
-                            int flip, const T* Ux, const T* Dx, bool right) {
+                            int flip, const T* Ux, const T* Dx, bool right, char* tiles) {
   int k = y * L.Lx + x;
   const T* t = tw<T>(L, k, C.sp[k] ^ flip);
   S4 st = st_std(L.d);
   if (right)
     env3_step<T, BF16>(out, in, Ux, sb_mirror(L.c, L.d), t, st_mirror(st), Dx, sb_mirror(L.c, L.d),
-                 C.ws + L.oX0, C.ws + L.oX1, L.c, L.d);
+                       C.ws + L.oX0, C.ws + L.oX1, L.c, L.d, tiles);
   else
     env3_step<T, BF16>(out, in, Ux, sb_std(L.c, L.d), t, st, Dx, sb_std(L.c, L.d), C.ws + L.oX0,
-                 C.ws + L.oX1, L.c, L.d);
+                       C.ws + L.oX1, L.c, L.d, tiles);
   return wg_renorm<T>(out, e3sz(L));
 }
 
@@ -89,7 +99,7 @@ __device__ inline int step3(const LatDev& L, const Chain<T>& C, T* out, const T*
 template <typename TC, typename TB, int DD, int CC, bool GRAM = false>
 constexpr size_t env4_lds() {
   if constexpr (DD > 0) return Env4Shape<DD, CC>::template lds_bytes<TC, TB, GRAM>();
-  else return 16;
+  else return GEMM_TILE_BYTES;  // the generic step's GEMM tiles
 }
 
 // 4-line column step over rows y and y+1; flip1/flip2 select the flipped slot.
@@ -108,7 +118,7 @@ __device__ inline int step4(const LatDev& L, const Chain<T>& C, T* out, const T*
   if constexpr (DD > 0) {
     env4_fused<T, T, DD, CC, false, BF16>(out, in, Ux, sb, t1, s, t2, s, Dx, sb, lds);
   } else {
-    env4_step<T, T, BF16>(out, in, Ux, sb, t1, s, t2, s, Dx, sb, C.ws + L.oX0, C.ws + L.oX1, L.c, L.d);
+    env4_step<T, T, BF16>(out, in, Ux, sb, t1, s, t2, s, Dx, sb, C.ws + L.oX0, C.ws + L.oX1, L.c, L.d, lds);
   }
   return wg_renorm<T>(out, e4sz(L));
 }
@@ -156,8 +166,8 @@ __global__ void __launch_bounds__(WG) k_init_trivial(LatDev L) {
 
 // R3[x] = R(x) for x = Lx-1 .. 1 of the network <D|row y|U>; R3[Lx] = ones.
 template <typename T, bool BF16>
-__global__ void __launch_bounds__(WG) k_row3_right(LatDev L, int y, int ub_slot, int db_slot) {
-  Chain<T> C = chain_of<T>(L, blockIdx.x);
+__device__ void ph_row3_right(const LatDev& L, int ch, int y, int ub_slot, int db_slot, char* tiles) {
+  Chain<T> C = chain_of<T>(L, ch);
   const int sz = e3sz(L);
   T* R = C.ws + L.oR3;
   int* eR = C.iw + L.ieR3;
@@ -165,13 +175,13 @@ __global__ void __launch_bounds__(WG) k_row3_right(LatDev L, int y, int ub_slot,
   if (threadIdx.x == 0) eR[L.Lx] = 0;
   for (int x = L.Lx - 1; x >= 1; --x) {
     int e = step3<T, BF16>(L, C, R + (int64_t)x * sz, R + (int64_t)(x + 1) * sz, y, x, 0,
-                           ub<T>(L, C, ub_slot, x), db<T>(L, C, db_slot, x), true);
+                           ub<T>(L, C, ub_slot, x), db<T>(L, C, db_slot, x), true, tiles);
     if (threadIdx.x == 0) eR[x] = eR[x + 1] + e;
     __syncthreads();
   }
 }
 
-__device__ inline bool metropolis(const LatDev& L, ChainMeta* meta, double num, double den, int esum,
+__device__ inline bool metropolis(const LatDev& L, int ch, ChainMeta* meta, double num, double den, int esum,
                                   int bond) {
   if (den == 0.0) {
     raise_flag(meta, FLAG_ZERO);
@@ -183,12 +193,12 @@ __device__ inline bool metropolis(const LatDev& L, ChainMeta* meta, double num, 
     raise_flag(meta, FLAG_NONFINITE);
     return false;
   }
-  U64x4 w = philox4x64_10((uint64_t)blockIdx.x, (uint64_t)meta->sweep, (uint64_t)bond, TAG_METRO,
+  U64x4 w = philox4x64_10((uint64_t)ch, (uint64_t)meta->sweep, (uint64_t)bond, TAG_METRO,
                           L.seed, (uint64_t)L.lat_id);
   double u = uniform53(w.v[0]);
   const bool acc = u < R;
   if (L.trace && threadIdx.x == 0) {
-    double* t = L.trace + 2 * ((int64_t)blockIdx.x * L.n_bonds + bond);
+    double* t = L.trace + 2 * ((int64_t)ch * L.n_bonds + bond);
     t[0] = rho;
     t[1] = acc ? 1.0 : 0.0;
   }
@@ -196,9 +206,9 @@ __device__ inline bool metropolis(const LatDev& L, ChainMeta* meta, double num, 
 }
 
 // Trace entry of a bond whose pair is parallel (no move proposed).
-__device__ inline void trace_skip(const LatDev& L, int bond) {
+__device__ inline void trace_skip(const LatDev& L, int ch, int bond) {
   if (L.trace && threadIdx.x == 0) {
-    double* t = L.trace + 2 * ((int64_t)blockIdx.x * L.n_bonds + bond);
+    double* t = L.trace + 2 * ((int64_t)ch * L.n_bonds + bond);
     t[0] = 0.0;
     t[1] = 0.0;
   }
@@ -207,8 +217,8 @@ __device__ inline void trace_skip(const LatDev& L, int bond) {
 // Horizontal bonds of row y, left to right (Sec. II.A Eq. (9)).  With moves = 0
 // no move is attempted.  For the last row the full amplitude is produced.
 template <typename T, bool BF16>
-__global__ void __launch_bounds__(WG) k_hsweep(LatDev L, int y, int last_row, int moves) {
-  Chain<T> C = chain_of<T>(L, blockIdx.x);
+__device__ void ph_hsweep(const LatDev& L, int ch, int y, int last_row, int moves, char* tiles) {
+  Chain<T> C = chain_of<T>(L, ch);
   if (C.meta->flags) return;
   const int sz = e3sz(L);
   T* tmp = C.ws + L.oT3;
@@ -222,20 +232,20 @@ __global__ void __launch_bounds__(WG) k_hsweep(LatDev L, int y, int last_row, in
     const T* Dx = db<T>(L, C, y + 1, x);
     T* cur = tmp + slot[0] * sz;
     T* nxt = tmp + slot[1] * sz;
-    int enxt = ecur + step3<T, BF16>(L, C, nxt, cur, y, x, 0, Ux, Dx, false);
+    int enxt = ecur + step3<T, BF16>(L, C, nxt, cur, y, x, 0, Ux, Dx, false, tiles);
     const int k = y * L.Lx + x;
     bool acc = false;
-    if (moves && C.sp[k] == C.sp[k + 1]) trace_skip(L, y * (2 * L.Lx - 1) + x);
+    if (moves && C.sp[k] == C.sp[k + 1]) trace_skip(L, C.id, y * (2 * L.Lx - 1) + x);
     if (moves && C.sp[k] != C.sp[k + 1]) {
       T* f1 = tmp + slot[2] * sz;
       T* f2 = tmp + slot[3] * sz;
-      int ef1 = ecur + step3<T, BF16>(L, C, f1, cur, y, x, 1, Ux, Dx, false);
+      int ef1 = ecur + step3<T, BF16>(L, C, f1, cur, y, x, 1, Ux, Dx, false, tiles);
       int ef2 = ef1 + step3<T, BF16>(L, C, f2, f1, y, x + 1, 1, ub<T>(L, C, y, x + 1),
-                                     db<T>(L, C, y + 1, x + 1), false);
+                                     db<T>(L, C, y + 1, x + 1), false, tiles);
       double num = wg_dot<T>(f2, R + (int64_t)(x + 2) * sz, sz);
       double den = wg_dot<T>(nxt, R + (int64_t)(x + 1) * sz, sz);
       int bond = y * (2 * L.Lx - 1) + x;
-      acc = metropolis(L, C.meta, num, den, ef2 + eR[x + 2] - enxt - eR[x + 1], bond);
+      acc = metropolis(L, C.id, C.meta, num, den, ef2 + eR[x + 2] - enxt - eR[x + 1], bond);
       if (threadIdx.x == 0) {
         C.meta->proposed += 1;
         if (acc) {
@@ -258,7 +268,8 @@ __global__ void __launch_bounds__(WG) k_hsweep(LatDev L, int y, int last_row, in
     const int x = L.Lx - 1;
     T* cur = tmp + slot[0] * sz;
     T* nxt = tmp + slot[1] * sz;
-    int e = ecur + step3<T, BF16>(L, C, nxt, cur, y, x, 0, ub<T>(L, C, y, x), db<T>(L, C, y + 1, x), false);
+    int e = ecur + step3<T, BF16>(L, C, nxt, cur, y, x, 0, ub<T>(L, C, y, x), db<T>(L, C, y + 1, x), false,
+                                  tiles);
     double v = (double)nxt[0];
     if (threadIdx.x == 0) {
       if (v == 0.0) {
@@ -275,9 +286,8 @@ __global__ void __launch_bounds__(WG) k_hsweep(LatDev L, int y, int last_row, in
 
 // R4[x] for x = Lx-1 .. 1 of <D_{y+2}|M_{y+1} M_y|U_{y-1}>.
 template <typename T, int DD, int CC, bool BF16>
-__global__ void __launch_bounds__(WG) k_row4_right(LatDev L, int y) {
-  __shared__ __attribute__((aligned(16))) char lds[env4_lds<T, T, DD, CC>()];
-  Chain<T> C = chain_of<T>(L, blockIdx.x);
+__device__ void ph_row4_right(const LatDev& L, int ch, int y, char* lds) {
+  Chain<T> C = chain_of<T>(L, ch);
   if (C.meta->flags) return;
   const int sz = e4sz(L);
   T* R = C.ws + L.oR4;
@@ -318,10 +328,8 @@ constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
 // sweep, y(Lx-1)+x, 6)), accepted with min[1, R pi(S')/pi(S)] (word 1); R from
 // the two-row network with columns x and x+1 exchanged in both rows.
 template <typename T, int DD, int CC, bool BF16, bool LEARN>
-__global__ void __launch_bounds__(WG) k_vsweep(LatDev L, int y) {
-  __shared__ __attribute__((aligned(16)))
-  char lds[cmax(env4_lds<T, T, DD, CC>(), LEARN ? net_lds_bytes<T>() : 0)];
-  Chain<T> C = chain_of<T>(L, blockIdx.x);
+__device__ void ph_vsweep(const LatDev& L, int ch, int y, char* lds) {
+  Chain<T> C = chain_of<T>(L, ch);
   if (C.meta->flags) return;
   const int sz = e4sz(L);
   T* tmp = C.ws + L.oT4;
@@ -336,7 +344,7 @@ __global__ void __launch_bounds__(WG) k_vsweep(LatDev L, int y) {
     T* cur = tmp + slot[0] * sz;
     T* nxt = tmp + slot[1] * sz;
     const int vb = y * (2 * L.Lx - 1) + (L.Lx - 1) + x;
-    if (C.sp[y * L.Lx + x] == C.sp[(y + 1) * L.Lx + x]) trace_skip(L, vb);
+    if (C.sp[y * L.Lx + x] == C.sp[(y + 1) * L.Lx + x]) trace_skip(L, C.id, vb);
     if (x == L.Lx - 1 && !(C.sp[y * L.Lx + x] != C.sp[(y + 1) * L.Lx + x])) break;
     int enxt = ecur + step4<T, DD, CC, BF16>(L, C, nxt, cur, y, x, 0, 0, Ux, Dx, false, lds);
     const int k1 = y * L.Lx + x, k2 = (y + 1) * L.Lx + x;
@@ -345,7 +353,7 @@ __global__ void __launch_bounds__(WG) k_vsweep(LatDev L, int y) {
       int ef = ecur + step4<T, DD, CC, BF16>(L, C, f, cur, y, x, 1, 1, Ux, Dx, false, lds);
       double num = wg_dot<T>(f, R + (int64_t)(x + 1) * sz, sz);
       double den = wg_dot<T>(nxt, R + (int64_t)(x + 1) * sz, sz);
-      bool acc = metropolis(L, C.meta, num, den, ef - enxt, vb);
+      bool acc = metropolis(L, C.id, C.meta, num, den, ef - enxt, vb);
       if (threadIdx.x == 0) {
         C.meta->proposed += 1;
         if (acc) {
@@ -365,7 +373,7 @@ __global__ void __launch_bounds__(WG) k_vsweep(LatDev L, int y) {
       const int k1 = y * L.Lx + x, k2 = k1 + L.Lx;
       if (x < L.Lx - 1 && C.sp[k1] + C.sp[k1 + 1] + C.sp[k2] + C.sp[k2 + 1] == 2) {
         const int q = y * (L.Lx - 1) + x;
-        U64x4 w = philox4x64_10((uint64_t)blockIdx.x, (uint64_t)C.meta->sweep, (uint64_t)q, TAG_PLAQ, L.seed,
+        U64x4 w = philox4x64_10((uint64_t)C.id, (uint64_t)C.meta->sweep, (uint64_t)q, TAG_PLAQ, L.seed,
                                 (uint64_t)L.lat_id);
         const T* Wn = static_cast<const T*>(L.net);
         const double pi_fwd = net_sigmoid(net_logit<T>(Wn, C.sp, L.Ly, L.Lx, y, x, 0, lds));
@@ -414,15 +422,19 @@ __global__ void __launch_bounds__(WG) k_vsweep(LatDev L, int y) {
 // eigenvectors are the kept right singular vectors.  The output state is the
 // same; the sign and gauge of every site may differ.  All of it runs in float64
 // (the Gram matrices square the condition number of the left blocks).
+// LDS of a compression: the Gram step, the GEMM tiles and the eigensolver share it.
 template <typename T, int DD, int CC>
-__global__ void __launch_bounds__(WG, 2) k_compress(LatDev L, int y, int upper) {
+constexpr size_t compress_lds() {
   constexpr size_t kGram = env4_lds<double, T, DD, CC, true>();
   constexpr size_t kEig = EIG_LDS_BYTES > GEMM_TILE_BYTES ? EIG_LDS_BYTES : GEMM_TILE_BYTES;
-  constexpr size_t kLds = kGram > kEig ? kGram : kEig;  // Gram step, GEMM tiles and eigensolver share it
-  __shared__ __attribute__((aligned(16))) char lds[kLds];
-  Chain<T> C = chain_of<T>(L, blockIdx.x);
+  return kGram > kEig ? kGram : kEig;
+}
+
+template <typename T, int DD, int CC>
+__device__ void ph_compress(const LatDev& L, int ch, int y, int upper, char* lds) {
+  Chain<T> C = chain_of<T>(L, ch);
   if (C.meta->flags) return;
-  double* cw = L.cws + (int64_t)blockIdx.x * L.cws_stride;
+  double* cw = L.cws + (int64_t)ch * L.cws_stride;
   const int c = L.c, d = L.d, Lx = L.Lx;
   const int ssz = c * d * c, gsz = c * d * d * c;
   const int in_slot = upper ? y : y + 1;
@@ -446,7 +458,7 @@ __global__ void __launch_bounds__(WG, 2) k_compress(LatDev L, int y, int upper) 
                                           t, st2, A_in(j), sA, lds);
     else
       env4_step<double, T>(G + (int64_t)(j + 1) * gsz, G + (int64_t)j * gsz, A_in(j), sA, t, st, t, st2, A_in(j),
-                           sA, X0, X1, c, d);
+                           sA, X0, X1, c, d, lds);
     wg_renorm<double>(G + (int64_t)(j + 1) * gsz, gsz);
   }
   double* Ta = cw + L.cTa;
@@ -519,8 +531,8 @@ __global__ void __launch_bounds__(WG, 2) k_compress(LatDev L, int y, int upper) 
 // Measurement of row y (App. C): log-derivatives of its sites and its
 // horizontal pair ratios, all from the cached left/right auxiliary tensors.
 template <typename T>
-__global__ void __launch_bounds__(WG) k_measure3(LatDev L, int y, SampleOut o) {
-  Chain<T> C = chain_of<T>(L, blockIdx.x);
+__device__ void ph_measure3(const LatDev& L, int ch, int y, const SampleOut& o, char* tiles) {
+  Chain<T> C = chain_of<T>(L, ch);
   if (C.meta->flags) return;
   const int sz = e3sz(L), Lx = L.Lx, d = L.d;
   T* R = C.ws + L.oR3;
@@ -534,13 +546,13 @@ __global__ void __launch_bounds__(WG) k_measure3(LatDev L, int y, SampleOut o) {
   __syncthreads();
   for (int x = Lx - 1; x >= 1; --x) {
     int e = step3<T>(L, C, R + (int64_t)x * sz, R + (int64_t)(x + 1) * sz, y, x, 0, ub<T>(L, C, y, x),
-                     db<T>(L, C, y + 1, x), true);
+                     db<T>(L, C, y + 1, x), true, tiles);
     if (threadIdx.x == 0) eR[x] = eR[x + 1] + e;
     __syncthreads();
   }
   for (int x = 0; x < Lx; ++x) {
     int e = step3<T>(L, C, Le + (int64_t)(x + 1) * sz, Le + (int64_t)x * sz, y, x, 0, ub<T>(L, C, y, x),
-                     db<T>(L, C, y + 1, x), false);
+                     db<T>(L, C, y + 1, x), false, tiles);
     if (threadIdx.x == 0) eL[x + 1] = eL[x] + e;
     __syncthreads();
   }
@@ -557,11 +569,11 @@ __global__ void __launch_bounds__(WG) k_measure3(LatDev L, int y, SampleOut o) {
     for (int x = 0; x < Lx; ++x) {
       const int k = y * Lx + x;
       defect3<T>(Dl, Le + (int64_t)x * sz, ub<T>(L, C, y, x), sb_std(L.c, d), R + (int64_t)(x + 1) * sz,
-                 db<T>(L, C, y + 1, x), sb_std(L.c, d), C.ws + L.oX0, C.ws + L.oX1, L.c, d);
+                 db<T>(L, C, y + 1, x), sb_std(L.c, d), C.ws + L.oX0, C.ws + L.oX1, L.c, d, tiles);
       const double f = ldexp(1.0 / Nm, eL[x] + eR[x + 1] - eN);
       const int dl = L.dims[4 * k], du = L.dims[4 * k + 1], dr = L.dims[4 * k + 2], dd = L.dims[4 * k + 3];
       const int n = dl * du * dr * dd;
-      T* outp = (T*)o.dlnpsi + ((int64_t)blockIdx.x * o.n_meas + o.m) * o.np_half + L.coff[k];
+      T* outp = (T*)o.dlnpsi + ((int64_t)ch * o.n_meas + meas_index(o, C.meta)) * o.np_half + L.coff[k];
       for (int i = threadIdx.x; i < n; i += WG) {
         int l = i / (du * dr * dd), u = (i / (dr * dd)) % du, r = (i / dd) % dr, q = i % dd;
         outp[i] = (T)((double)Dl[((l * d + u) * d + r) * d + q] * f);
@@ -577,13 +589,15 @@ __global__ void __launch_bounds__(WG) k_measure3(LatDev L, int y, SampleOut o) {
     if (C.sp[k] == C.sp[k + 1]) {
       eacc += 0.25 * L.J1;
     } else {
-      int e1 = eL[x] + step3<T>(L, C, tmp, Le + (int64_t)x * sz, y, x, 1, ub<T>(L, C, y, x), db<T>(L, C, y + 1, x), false);
-      int e2 = e1 + step3<T>(L, C, tmp + sz, tmp, y, x + 1, 1, ub<T>(L, C, y, x + 1), db<T>(L, C, y + 1, x + 1), false);
+      int e1 = eL[x] + step3<T>(L, C, tmp, Le + (int64_t)x * sz, y, x, 1, ub<T>(L, C, y, x), db<T>(L, C, y + 1, x),
+                                false, tiles);
+      int e2 = e1 + step3<T>(L, C, tmp + sz, tmp, y, x + 1, 1, ub<T>(L, C, y, x + 1), db<T>(L, C, y + 1, x + 1),
+                             false, tiles);
       double num = wg_dot<T>(tmp + sz, R + (int64_t)(x + 2) * sz, sz);
       rho = ldexp(num / Nm, e2 + eR[x + 2] - eN);
       eacc += -0.25 * L.J1 + 0.5 * L.J1 * rho;
     }
-    if (o.ratios && threadIdx.x == 0) o.ratios[(int64_t)blockIdx.x * o.n_pairs + pair] = rho;
+    if (o.ratios && threadIdx.x == 0) o.ratios[(int64_t)ch * o.n_pairs + pair] = rho;
   }
   if (threadIdx.x == 0) {
     if (!isfinite(eacc)) C.meta->flags |= FLAG_NONFINITE;
@@ -593,9 +607,8 @@ __global__ void __launch_bounds__(WG) k_measure3(LatDev L, int y, SampleOut o) {
 
 // Vertical and diagonal pairs between rows y and y+1 (two-row network).
 template <typename T, int DD, int CC>
-__global__ void __launch_bounds__(WG) k_measure4(LatDev L, int y, SampleOut o) {
-  __shared__ __attribute__((aligned(16))) char lds[env4_lds<T, T, DD, CC>()];
-  Chain<T> C = chain_of<T>(L, blockIdx.x);
+__device__ void ph_measure4(const LatDev& L, int ch, int y, const SampleOut& o, char* lds) {
+  Chain<T> C = chain_of<T>(L, ch);
   if (C.meta->flags) return;
   const int sz = e4sz(L), Lx = L.Lx;
   T* R = C.ws + L.oR4;
@@ -635,7 +648,7 @@ __global__ void __launch_bounds__(WG) k_measure4(LatDev L, int y, SampleOut o) {
       rho = ldexp(num / Nm, e1 + eR[x + 1] - eN);
       eacc += -0.25 * L.J1 + 0.5 * L.J1 * rho;
     }
-    if (o.ratios && threadIdx.x == 0) o.ratios[(int64_t)blockIdx.x * o.n_pairs + base_v + y * Lx + x] = rho;
+    if (o.ratios && threadIdx.x == 0) o.ratios[(int64_t)ch * o.n_pairs + base_v + y * Lx + x] = rho;
   }
   if (L.J2 != 0.0) {
     const int base_d = base_v + (L.Ly - 1) * Lx;
@@ -659,7 +672,7 @@ __global__ void __launch_bounds__(WG) k_measure4(LatDev L, int y, SampleOut o) {
           eacc += -0.25 * L.J2 + 0.5 * L.J2 * rho;
         }
         if (o.ratios && threadIdx.x == 0)
-          o.ratios[(int64_t)blockIdx.x * o.n_pairs + base_d + 2 * (y * (Lx - 1) + x) + which] = rho;
+          o.ratios[(int64_t)ch * o.n_pairs + base_d + 2 * (y * (Lx - 1) + x) + which] = rho;
       }
     }
   }
@@ -676,13 +689,48 @@ __global__ void __launch_bounds__(WG) k_measure4(LatDev L, int y, SampleOut o) {
         double num = wg_dot<T>(tmp + sz, R + (int64_t)(x + 2) * sz, sz);
         rho = ldexp(num / Nm, e2 + eR[x + 2] - eN);
       }
-      if (threadIdx.x == 0) o.plaq[(int64_t)blockIdx.x * (L.Ly - 1) * (Lx - 1) + y * (Lx - 1) + x] = rho;
+      if (threadIdx.x == 0) o.plaq[(int64_t)ch * (L.Ly - 1) * (Lx - 1) + y * (Lx - 1) + x] = rho;
     }
   }
   if (threadIdx.x == 0) {
     if (!isfinite(eacc)) C.meta->flags |= FLAG_NONFINITE;
     C.meta->e_acc += eacc;
   }
+}
+
+// Wrappers: one work-group per chain, one phase of one row.
+template <typename T, bool BF16>
+__global__ void __launch_bounds__(WG) k_row3_right(LatDev L, int y, int ub_slot, int db_slot) {
+  ph_row3_right<T, BF16>(L, blockIdx.x, y, ub_slot, db_slot, gemm_tiles());
+}
+template <typename T, bool BF16>
+__global__ void __launch_bounds__(WG) k_hsweep(LatDev L, int y, int last_row, int moves) {
+  ph_hsweep<T, BF16>(L, blockIdx.x, y, last_row, moves, gemm_tiles());
+}
+template <typename T, int DD, int CC, bool BF16>
+__global__ void __launch_bounds__(WG) k_row4_right(LatDev L, int y) {
+  __shared__ __attribute__((aligned(16))) char lds[env4_lds<T, T, DD, CC>()];
+  ph_row4_right<T, DD, CC, BF16>(L, blockIdx.x, y, lds);
+}
+template <typename T, int DD, int CC, bool BF16, bool LEARN>
+__global__ void __launch_bounds__(WG) k_vsweep(LatDev L, int y) {
+  __shared__ __attribute__((aligned(16)))
+  char lds[cmax(env4_lds<T, T, DD, CC>(), LEARN ? net_lds_bytes<T>() : 0)];
+  ph_vsweep<T, DD, CC, BF16, LEARN>(L, blockIdx.x, y, lds);
+}
+template <typename T, int DD, int CC>
+__global__ void __launch_bounds__(WG, 2) k_compress(LatDev L, int y, int upper) {
+  __shared__ __attribute__((aligned(16))) char lds[compress_lds<T, DD, CC>()];
+  ph_compress<T, DD, CC>(L, blockIdx.x, y, upper, lds);
+}
+template <typename T>
+__global__ void __launch_bounds__(WG) k_measure3(LatDev L, int y, SampleOut o) {
+  ph_measure3<T>(L, blockIdx.x, y, o, gemm_tiles());
+}
+template <typename T, int DD, int CC>
+__global__ void __launch_bounds__(WG) k_measure4(LatDev L, int y, SampleOut o) {
+  __shared__ __attribute__((aligned(16))) char lds[env4_lds<T, T, DD, CC>()];
+  ph_measure4<T, DD, CC>(L, blockIdx.x, y, o, lds);
 }
 
 __global__ void k_begin_sample(LatDev L) {
@@ -694,7 +742,7 @@ __global__ void k_finish_sample(LatDev L, SampleOut o, int n_active) {
   int ch = blockIdx.x;
   if (ch >= n_active) return;
   const ChainMeta* m = L.meta + ch;
-  int64_t idx = (int64_t)ch * o.n_meas + o.m;
+  int64_t idx = (int64_t)ch * o.n_meas + meas_index(o, m);
   if (threadIdx.x == 0) {
     if (o.log_abs_psi) o.log_abs_psi[idx] = m->logpsi;
     if (o.sign) o.sign[idx] = (int8_t)m->sign;
@@ -707,6 +755,123 @@ __global__ void k_finish_sample(LatDev L, SampleOut o, int n_active) {
 __global__ void k_next_sweep(LatDev L) {
   int ch = blockIdx.x * blockDim.x + threadIdx.x;
   if (ch < L.n_chains) L.meta[ch].sweep += 1;
+}
+
+// ---------------------------------------------------------------------------
+// Persistent whole-sweep kernel: a work-group takes (lattice, chain) items from
+// a queue and runs one complete sweep of that chain -- every phase of the
+// top-down sampling pass and (if requested) the bottom-up measurement pass --
+// before taking the next.  Chains of lattices of different sizes share one
+// launch; items are queued largest lattice first, so the short sweeps fill the
+// tail.  The queue counter must be zero at launch; every work-group leaves
+// when the queue is exhausted.
+// ---------------------------------------------------------------------------
+template <typename T, int DD, int CC>
+constexpr size_t sweep_lds() {
+  return cmax(cmax(env4_lds<T, T, DD, CC>(), compress_lds<T, DD, CC>()), net_lds_bytes<T>());
+}
+
+// Out-of-line phases of the persistent kernel: each keeps its own register
+// allocation instead of the union of all phases.
+template <typename T, bool BF16>
+__device__ __noinline__ void nl_row3_right(const LatDev& L, int ch, int y, char* lds) {
+  ph_row3_right<T, BF16>(L, ch, y, y, y + 1, lds);
+}
+template <typename T, bool BF16>
+__device__ __noinline__ void nl_hsweep(const LatDev& L, int ch, int y, char* lds) {
+  ph_hsweep<T, BF16>(L, ch, y, y == L.Ly - 1, 1, lds);
+}
+template <typename T, int DD, int CC, bool BF16>
+__device__ __noinline__ void nl_row4_right(const LatDev& L, int ch, int y, char* lds) {
+  ph_row4_right<T, DD, CC, BF16>(L, ch, y, lds);
+}
+template <typename T, int DD, int CC, bool BF16, bool LEARN>
+__device__ __noinline__ void nl_vsweep(const LatDev& L, int ch, int y, char* lds) {
+  ph_vsweep<T, DD, CC, BF16, LEARN>(L, ch, y, lds);
+}
+template <typename T, int DD, int CC>
+__device__ __noinline__ void nl_compress(const LatDev& L, int ch, int y, int upper, char* lds) {
+  ph_compress<T, DD, CC>(L, ch, y, upper, lds);
+}
+template <typename T>
+__device__ __noinline__ void nl_measure3(const LatDev& L, int ch, int y, const SampleOut& o, char* lds) {
+  ph_measure3<T>(L, ch, y, o, lds);
+}
+template <typename T, int DD, int CC>
+__device__ __noinline__ void nl_measure4(const LatDev& L, int ch, int y, const SampleOut& o, char* lds) {
+  ph_measure4<T, DD, CC>(L, ch, y, o, lds);
+}
+
+template <typename T, int DD, int CC, bool BF16>
+__device__ void chain_sweep(const LatDev& L, int ch, const SampleOut* o, char* lds) {
+  const int Ly = L.Ly;
+  for (int y = 0; y < Ly; ++y) {
+    nl_row3_right<T, BF16>(L, ch, y, lds);
+    __syncthreads();
+    nl_hsweep<T, BF16>(L, ch, y, lds);
+    __syncthreads();
+    if (y < Ly - 1) {
+      nl_row4_right<T, DD, CC, BF16>(L, ch, y, lds);
+      __syncthreads();
+      if (L.learned) nl_vsweep<T, DD, CC, BF16, true>(L, ch, y, lds);
+      else nl_vsweep<T, DD, CC, BF16, false>(L, ch, y, lds);
+      __syncthreads();
+      nl_compress<T, DD, CC>(L, ch, y, 1, lds);
+      __syncthreads();
+    }
+  }
+  ChainMeta* m = L.meta + ch;
+  if (o && threadIdx.x == 0) m->e_acc = 0.0;
+  __syncthreads();
+  for (int y = Ly - 1; y >= 0; --y) {
+    if (o) {
+      nl_measure3<T>(L, ch, y, *o, lds);
+      __syncthreads();
+      if (y < Ly - 1) {
+        nl_measure4<T, DD, CC>(L, ch, y, *o, lds);
+        __syncthreads();
+      }
+    }
+    if (y >= 1) {
+      nl_compress<T, DD, CC>(L, ch, y, 0, lds);
+      __syncthreads();
+    }
+  }
+  if (o) {
+    const int64_t idx = (int64_t)ch * o->n_meas + meas_index(*o, m);
+    if (threadIdx.x == 0) {
+      if (o->log_abs_psi) o->log_abs_psi[idx] = m->logpsi;
+      if (o->sign) o->sign[idx] = (int8_t)m->sign;
+      if (o->e_loc) o->e_loc[idx] = m->e_acc;
+    }
+    if (o->spins)
+      for (int i = threadIdx.x; i < L.N; i += WG) o->spins[idx * L.N + i] = L.spins[(int64_t)ch * L.N + i];
+  }
+  if (threadIdx.x == 0) m->sweep += 1;
+  __syncthreads();
+}
+
+template <typename T, int DD, int CC, bool BF16>
+__global__ void __launch_bounds__(WG, 2) k_sweep_queue(const LatDev* __restrict__ lats,
+                                                       const SampleOut* __restrict__ outs, int measure,
+                                                       const int2* __restrict__ items, int n_items,
+                                                       int* __restrict__ next) {
+  __shared__ __attribute__((aligned(16))) char lds[sweep_lds<T, DD, CC>()];
+  __shared__ int item;
+  for (;;) {
+    if (threadIdx.x == 0) item = atomicAdd(next, 1);
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(item);
+    __syncthreads();
+    if (it >= n_items) break;
+    const int2 w = items[it];
+    const int li = __builtin_amdgcn_readfirstlane(w.x), ch = __builtin_amdgcn_readfirstlane(w.y);
+    chain_sweep<T, DD, CC, BF16>(lats[li], ch, measure ? outs + li : nullptr, lds);
+  }
+}
+
+__global__ void k_zero_int(int* p) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
 }
 
 __global__ void k_init_tensors(double* T, int64_t Np, uint64_t seed, int lat_id, double scale, double perturb) {
@@ -900,6 +1065,55 @@ template <typename T>
 void launch_measure4(const LatDev& L, int y, const SampleOut& o, hipStream_t s) {
   VP_DISPATCH_DC(k_measure4, T, L, y, o);
 }
+// One persistent launch: `grid` work-groups drain the item queue.
+template <typename T>
+void launch_sweep_queue(const LatDev& L0, const LatDev* lats, const SampleOut* outs, int measure, const int2* items,
+                        int n_items, int* next, bool bf16, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, next);
+  const LatDev& L = L0;
+#define VP_SQ(DD, CC, BF)                                                                              \
+  hipLaunchKernelGGL((k_sweep_queue<T, DD, CC, BF>), dim3(grid), dim3(WG), 0, s, lats, outs, measure, items, \
+                     n_items, next)
+#define VP_SQ_SHAPE(BF)                                                                                \
+  do {                                                                                                 \
+    if (L.d == 8 && L.c == 16) VP_SQ(8, 16, BF);                                                       \
+    else if (L.d == 6 && L.c == 12) VP_SQ(6, 12, BF);                                                  \
+    else if (L.d == 4 && L.c == 8) VP_SQ(4, 8, BF);                                                    \
+    else VP_SQ(0, 0, BF);                                                                              \
+  } while (0)
+  if constexpr (sizeof(T) == 8) {
+    if (bf16) {
+      VP_SQ_SHAPE(true);
+      return;
+    }
+  }
+  VP_SQ_SHAPE(false);
+#undef VP_SQ_SHAPE
+#undef VP_SQ
+}
+
+// Work-groups of the persistent kernel that fit on one CU at once.
+template <typename T>
+int sweep_queue_occupancy(const LatDev& L, bool bf16) {
+  int n = 0;
+#define VP_OCC(DD, CC, BF) hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_sweep_queue<T, DD, CC, BF>, WG, 0)
+  auto shape = [&](auto bf) {
+    constexpr bool BF = decltype(bf)::value;
+    if (L.d == 8 && L.c == 16) VP_OCC(8, 16, BF);
+    else if (L.d == 6 && L.c == 12) VP_OCC(6, 12, BF);
+    else if (L.d == 4 && L.c == 8) VP_OCC(4, 8, BF);
+    else VP_OCC(0, 0, BF);
+  };
+  if constexpr (sizeof(T) == 8) {
+    if (bf16) shape(std::true_type{});
+    else shape(std::false_type{});
+  } else {
+    shape(std::false_type{});
+  }
+#undef VP_OCC
+  return n;
+}
+
 void launch_begin_sample(const LatDev& L, hipStream_t s) {
   hipLaunchKernelGGL(k_begin_sample, dim3((L.n_chains + WG - 1) / WG), dim3(WG), 0, s, L);
 }
@@ -944,6 +1158,9 @@ void launch_sign_sgd(double* T, const double* g, int64_t Np, double step_len, ui
   template void launch_psi_fixed<T>(const LatDev&, hipStream_t);                                    \
   template void launch_row4_right<T>(const LatDev&, int, bool, hipStream_t);                              \
   template void launch_vsweep<T>(const LatDev&, int, bool, bool, hipStream_t);                                \
+  template void launch_sweep_queue<T>(const LatDev&, const LatDev*, const SampleOut*, int, const int2*, int, int*, \
+                                      bool, int, hipStream_t);                                              \
+  template int sweep_queue_occupancy<T>(const LatDev&, bool);                                \
   template void launch_compress<T>(const LatDev&, int, int, hipStream_t);                           \
   template void launch_measure3<T>(const LatDev&, int, const SampleOut&, hipStream_t);              \
   template void launch_measure4<T>(const LatDev&, int, const SampleOut&, hipStream_t);              \

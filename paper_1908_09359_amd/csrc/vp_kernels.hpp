@@ -44,6 +44,7 @@ struct LatDev {
   double* trace;            // [n_chains][n_bonds][2] (rho, accepted) of the last sweep, or null
   int n_bonds;              // Ly(Lx-1) + (Ly-1)Lx
   const void* net;          // proposal network parameters in the working precision, or null
+  int learned;              // learned plaquette moves in the persistent sweep kernel
   const int32_t* kU;        // bond dims of U_y: kU[(y+1)*(Lx+1) + j], y = -1..Ly-1
   const int32_t* kD;        // bond dims of D_y: kD[y*(Lx+1) + j], y = 0..Ly
   const int32_t* dims;      // true leg dims per site [N][4] (l,u,r,d)
@@ -78,7 +79,9 @@ struct SampleOut {
   int8_t* spins;        // [chain][n_meas][N]
   double* ratios;       // [chain][n_pairs] (vp_eval only)
   int n_meas;
-  int m;                // index of this measurement
+  int m;                // index of this measurement (dyn_m == 0)
+  int dyn_m;            // 1: the index is the chain's sweep counter minus sweep0
+  int64_t sweep0;
   int64_t np_half;
   int n_pairs;
   int psi_meas;         // Psi from the measurement pass (bottom row) instead of the sampling pass
@@ -92,6 +95,12 @@ template <typename T> void launch_row3_right(const LatDev& L, int y, int ub_slot
 template <typename T> void launch_hsweep(const LatDev& L, int y, int last_row, bool bf16, hipStream_t s);
 template <typename T> void launch_row4_right(const LatDev& L, int y, bool bf16, hipStream_t s);
 template <typename T> void launch_vsweep(const LatDev& L, int y, bool bf16, bool learned, hipStream_t s);
+// Persistent whole-sweep launch over (lattice, chain) items; lats/outs/items/next are device arrays,
+// L0 a host copy of any of the lattices (they share d, c and the working type).
+template <typename T> void launch_sweep_queue(const LatDev& L0, const LatDev* lats, const SampleOut* outs,
+                                              int measure, const int2* items, int n_items, int* next, bool bf16,
+                                              int grid, hipStream_t s);
+template <typename T> int sweep_queue_occupancy(const LatDev& L0, bool bf16);
 template <typename T> void launch_compress(const LatDev& L, int y, int upper, hipStream_t s);
 template <typename T> void launch_measure3(const LatDev& L, int y, const SampleOut& o, hipStream_t s);
 template <typename T> void launch_measure4(const LatDev& L, int y, const SampleOut& o, hipStream_t s);
