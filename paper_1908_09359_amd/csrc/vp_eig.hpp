@@ -18,8 +18,8 @@ constexpr int EIG_PACK = EIG_NMAX * (EIG_NMAX + 1) / 2;
 // the LU factors (3 x n x EIG_KMAX), the kept vectors (n x EIG_KMAX) and the
 // pivot-swap bit words (n).
 // Small work arrays follow the packed matrix: d, e, e^2, tau, p, w, v (7 n),
-// two half-row partials (2 n), the multisection probes and counts (2 WG) and
-// the batch eigenvalues (EIG_KMAX).
+// two spare rows (2 n), the multisection probes and counts (2 WG) and the batch
+// eigenvalues (EIG_KMAX).
 constexpr size_t EIG_PACK_BYTES = sizeof(double) * EIG_PACK;
 constexpr size_t EIG_SMALL_BYTES = sizeof(double) * (9 * EIG_NMAX + WG + EIG_KMAX) + sizeof(int) * WG;
 constexpr size_t EIG_LDS_BYTES = EIG_PACK_BYTES + EIG_SMALL_BYTES;
@@ -41,12 +41,179 @@ __device__ inline int sturm_count(const double* d, const double* e2, int n, doub
   return cnt;
 }
 
+typedef __attribute__((address_space(3))) double lds_f64;
+
+// x from the lane given by the DPP control `ctrl` within its row of 16 lanes.
+template <int CTRL>
+__device__ inline double dpp_f64(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+// Sum over the 16 lanes of a row, returned to all of them: quad_perm [1,0,3,2]
+// and [2,3,0,1] sum each quad, row_half_mirror pairs the quads of each half,
+// row_mirror the halves.
+__device__ inline double row16_sum(double x) {
+  x += dpp_f64<0xB1>(x);
+  x += dpp_f64<0x4E>(x);
+  x += dpp_f64<0x141>(x);
+  x += dpp_f64<0x140>(x);
+  return x;
+}
+
+// Householder tridiagonalisation Q^T A Q = T, Q = H_0 H_1 ... H_{n-3}.
+// The full symmetric matrix lives in registers: thread t owns the 8x8 tile
+// (t / 16, t % 16) of the 128 x 128 zero-padded matrix, so the 16 tiles of a
+// block row sit in one row of 16 lanes of a wavefront.  Step i applies
+// H_i A H_i = A - v w^T - w v^T to the whole matrix (v vanishes on rows <= i,
+// which leaves the finished rows and columns as they are up to rounding).
+// Per step: the owners of column i publish it with partial norms; every
+// thread forms the reflector; p = t A v by tile products summed over the row
+// of lanes; v^T p over the block rows through LDS; then the rank-2 update.
+// H: n x n row-major (ld n); outputs d (dg), e (eg), tau and the reflectors
+// refl[tri(r) + i] = v_r (r > i, v_{i+1} = 1); xc0, xc1, pv: LDS rows of
+// EIG_NMAX doubles, red: 36 doubles of LDS.  Column i and its norms alternate
+// between two buffers, so a step needs two barriers.  All threads of the
+// work-group call it.
+__device__ __noinline__ void eig_tridiag(const double* H, int n, lds_f64* dg, lds_f64* eg, lds_f64* tau,
+                                         lds_f64* xc0, lds_f64* xc1, lds_f64* pv, lds_f64* red, double* refl) {
+  const int tid = threadIdx.x;
+  const int br = tid >> 4, bc = tid & 15, lane = tid & 63, wave = tid >> 6;
+  double a[8][8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q)
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int r = 8 * br + q, s2 = 8 * bc + c;
+      a[q][c] = (r < n && s2 < n) ? H[r * n + s2] : 0.0;
+    }
+  lds_f64* kpart = red + 32;  // [4] partial v^T p, per wavefront
+  // column i of the current matrix, as held by its owners (bc == i / 8); taken
+  // inside a statically unrolled column loop under a uniform condition
+  double xo[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+    if (c == 0) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) xo[q] = a[q][c];
+    }
+  for (int i = 0; i < n - 2; ++i) {
+    lds_f64* xcol = (i & 1) ? xc1 : xc0;        // column i
+    lds_f64* nrm = red + 16 * (i & 1);          // [16] its partial norms, per block row
+    const bool owner = bc == (i >> 3);
+    if (owner) {
+      double s2 = 0.0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        xcol[8 * br + q] = xo[q];
+        if (8 * br + q >= i + 2) s2 += xo[q] * xo[q];
+      }
+      nrm[br] = s2;
+    }
+    __syncthreads();
+    // every thread forms the reflector (dlarfg): beta = -sign(alpha) |(alpha, x)|
+    const double alpha = xcol[i + 1];
+    double xn2 = 0.0;
+#pragma unroll
+    for (int b = 0; b < 16; ++b) xn2 += nrm[b];
+    double beta = alpha, t = 0.0, scal = 0.0;
+    if (xn2 > 0.0) {
+      beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+      t = (beta - alpha) / beta;
+      scal = 1.0 / (alpha - beta);
+    }
+    if (tid == 0) { dg[i] = xcol[i]; eg[i] = beta; tau[i] = t; }
+    if (owner) {  // the owners hold column i: store the reflector's entries of their rows
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int r = 8 * br + q;
+        if (r > i && r < n) refl[tri(r) + i] = (r == i + 1) ? 1.0 : xo[q] * scal;
+      }
+    }
+    if (t != 0.0) {  // uniform
+      double vc[8], vr[8], pr[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int rc = 8 * bc + q, rr = 8 * br + q;
+        vc[q] = rc == i + 1 ? 1.0 : ((rc > i + 1 && rc < n) ? (double)xcol[rc] * scal : 0.0);
+        vr[q] = rr == i + 1 ? 1.0 : ((rr > i + 1 && rr < n) ? (double)xcol[rr] * scal : 0.0);
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc += a[q][c] * vc[c];
+        pr[q] = row16_sum(acc) * t;
+      }
+      double part = 0.0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) part += pr[q] * vr[q];
+      // v^T p: four block rows per wavefront, then across wavefronts
+      part += __shfl_xor(part, 16, 64);
+      part += __shfl_xor(part, 32, 64);
+      if (bc == 0) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) pv[8 * br + q] = pr[q];
+      }
+      if (lane == 0) kpart[wave] = part;
+      __syncthreads();
+      const double K = -0.5 * t * (((double)kpart[0] + (double)kpart[1]) + ((double)kpart[2] + (double)kpart[3]));
+#pragma unroll
+      for (int q = 0; q < 8; ++q) pr[q] += K * vr[q];  // w on the tile's rows
+      const int cn = (i + 1) & 7;  // column of the next step within its tile
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const double wc = (double)pv[8 * bc + c] + K * vc[c];  // w on the tile's columns
+#pragma unroll
+        for (int q = 0; q < 8; ++q) a[q][c] -= vr[q] * wc + pr[q] * vc[c];
+        if (c == cn) {
+#pragma unroll
+          for (int q = 0; q < 8; ++q) xo[q] = a[q][c];
+        }
+      }
+    } else {
+      const int cn = (i + 1) & 7;
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (c == cn) {
+#pragma unroll
+          for (int q = 0; q < 8; ++q) xo[q] = a[q][c];
+        }
+    }
+    // next step: its column goes to the other buffer; pv and kpart are written
+    // only after its first barrier, which every thread reaches after its reads above
+  }
+  // the last 2 x 2 block
+  if (n >= 2) {
+    const int i0 = n - 2, i1 = n - 1;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int r = 8 * br + q, s2 = 8 * bc + c;
+        if (r == i0 && s2 == i0) dg[i0] = a[q][c];
+        if (r == i1 && s2 == i0) eg[i0] = a[q][c];
+        if (r == i1 && s2 == i1) dg[i1] = a[q][c];
+      }
+    if (tid == 0) { tau[i0] = 0.0; eg[i1] = 0.0; tau[i1] = 0.0; }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (8 * br + q == 0 && 8 * bc + c == 0) dg[0] = a[q][c];
+    if (tid == 0) { eg[0] = 0.0; tau[0] = 0.0; }
+  }
+  __syncthreads();
+}
+
 // H: n x n symmetric, row-major (ld n), any address space; n <= EIG_NMAX.
 // Writes the eigenvectors of the k largest eigenvalues, in descending order,
 // as columns 0..k-1 of V (ld k) and the eigenvalues to lam[0..k-1].
 // refl: global scratch of at least EIG_PACK doubles (Householder vectors);
 // lds: EIG_LDS_BYTES of LDS owned by the caller.
-__device__ void sym_topk_eig(const double* H, int n, int k, double* V, double* lam, double* refl, char* lds) {
+__device__ __forceinline__ void sym_topk_eig(const double* H, int n, int k, double* V, double* lam, double* refl, char* lds) {
   double* Ap = reinterpret_cast<double*>(lds);
   double* Xs = Ap + 3 * EIG_NMAX * EIG_KMAX;                            // after the tridiagonalisation
   unsigned* pivw = reinterpret_cast<unsigned*>(Xs + EIG_NMAX * EIG_KMAX);  // bit t: row swap of vector t
@@ -57,86 +224,14 @@ __device__ void sym_topk_eig(const double* H, int n, int k, double* V, double* l
   double* pv = tau + EIG_NMAX;
   double* wv = pv + EIG_NMAX;
   double* vv = wv + EIG_NMAX;
-  double (*pv2)[EIG_NMAX] = reinterpret_cast<double (*)[EIG_NMAX]>(vv + EIG_NMAX);
   double* probe_x = vv + 3 * EIG_NMAX;
   double* lamb = probe_x + WG;
   int* probe_c = reinterpret_cast<int*>(lamb + EIG_KMAX);
   const int tid = threadIdx.x;
 
-  for (int e = tid; e < n * n; e += WG) {
-    int i = e / n, j = e - i * n;
-    if (j <= i) Ap[tri(i) + j] = H[e];
-  }
-  __syncthreads();
-
-  // ---- tridiagonalisation: Q^T A Q = T, Q = H_0 H_1 ... H_{n-3}
-  for (int i = 0; i < n - 2; ++i) {
-    const double alpha = Ap[tri(i + 1) + i];
-    double xn2 = 0.0;
-    for (int r = i + 2 + tid; r < n; r += WG) xn2 += Ap[tri(r) + i] * Ap[tri(r) + i];
-    xn2 = wg_sum(xn2);
-    double beta = alpha, t = 0.0;
-    if (xn2 > 0.0) {
-      beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-      t = (beta - alpha) / beta;
-      const double scal = 1.0 / (alpha - beta);
-      for (int r = i + 2 + tid; r < n; r += WG) Ap[tri(r) + i] *= scal;
-    }
-    __syncthreads();  // the loop below reads entries scaled by other threads
-    // reflector i: v[i+1] = 1, v[r] = Ap[r][i] (r > i+1); also kept in global memory
-    for (int r = i + 1 + tid; r < n; r += WG) {
-      double v = (r == i + 1) ? 1.0 : Ap[tri(r) + i];
-      vv[r] = v;
-      refl[tri(r) + i] = v;
-    }
-    if (tid == 0) { dg[i] = Ap[tri(i) + i]; eg[i] = beta; tau[i] = t; }
-    __syncthreads();
-    if (t != 0.0) {
-      // p = t * A22 v over rows/cols i+1..n-1: two threads per row (interleaved columns)
-      {
-        const int r = i + 1 + (tid >> 1), h = tid & 1;
-        double acc = 0.0;
-        if (r < n) {
-          const int trr = tri(r);
-#pragma unroll 8
-          for (int s = i + 1 + h; s < n; s += 2) acc += (s <= r ? Ap[trr + s] : Ap[tri(s) + r]) * vv[s];
-          pv2[h][r] = acc;
-        }
-      }
-      __syncthreads();
-      double pw = 0.0;
-      for (int r = i + 1 + tid; r < n; r += WG) {
-        const double p = t * (pv2[0][r] + pv2[1][r]);
-        pv[r] = p;
-        pw += p * vv[r];
-      }
-      const double K = -0.5 * t * wg_sum(pw);
-      for (int r = i + 1 + tid; r < n; r += WG) wv[r] = pv[r] + K * vv[r];
-      __syncthreads();
-      // A22 -= v w^T + w v^T on the lower triangle, two threads per row
-      {
-        const int r = i + 1 + (tid >> 1), h = tid & 1;
-        if (r < n) {
-          const int trr = tri(r);
-          const double vr = vv[r], wr = wv[r];
-#pragma unroll 8
-          for (int s = i + 1 + h; s <= r; s += 2) Ap[trr + s] -= vr * wv[s] + wr * vv[s];
-        }
-      }
-      __syncthreads();
-    }
-  }
-  if (tid == 0) {
-    if (n >= 2) {
-      dg[n - 2] = Ap[tri(n - 2) + n - 2];
-      eg[n - 2] = Ap[tri(n - 1) + n - 2];
-      tau[n - 2] = 0.0;
-    }
-    dg[n - 1] = Ap[tri(n - 1) + n - 1];
-    eg[n - 1] = 0.0;
-    tau[n - 1] = 0.0;
-  }
-  __syncthreads();
+  // ---- tridiagonalisation (out of line: its register tile needs the whole register budget)
+  eig_tridiag(H, n, (lds_f64*)(dg), (lds_f64*)(eg), (lds_f64*)(tau), (lds_f64*)(wv), (lds_f64*)(vv),
+              (lds_f64*)(pv), (lds_f64*)(probe_x), refl);
   for (int j = tid; j < n; j += WG) e2[j] = eg[j] * eg[j];
 
   // ---- Gershgorin interval and pivot floor

@@ -166,7 +166,7 @@ __global__ void __launch_bounds__(WG) k_init_trivial(LatDev L) {
 
 // R3[x] = R(x) for x = Lx-1 .. 1 of the network <D|row y|U>; R3[Lx] = ones.
 template <typename T, bool BF16>
-__device__ void ph_row3_right(const LatDev& L, int ch, int y, int ub_slot, int db_slot, char* tiles) {
+__device__ __forceinline__ void ph_row3_right(const LatDev& L, int ch, int y, int ub_slot, int db_slot, char* tiles) {
   Chain<T> C = chain_of<T>(L, ch);
   const int sz = e3sz(L);
   T* R = C.ws + L.oR3;
@@ -217,7 +217,7 @@ __device__ inline void trace_skip(const LatDev& L, int ch, int bond) {
 // Horizontal bonds of row y, left to right (Sec. II.A Eq. (9)).  With moves = 0
 // no move is attempted.  For the last row the full amplitude is produced.
 template <typename T, bool BF16>
-__device__ void ph_hsweep(const LatDev& L, int ch, int y, int last_row, int moves, char* tiles) {
+__device__ __forceinline__ void ph_hsweep(const LatDev& L, int ch, int y, int last_row, int moves, char* tiles) {
   Chain<T> C = chain_of<T>(L, ch);
   if (C.meta->flags) return;
   const int sz = e3sz(L);
@@ -286,7 +286,7 @@ __device__ void ph_hsweep(const LatDev& L, int ch, int y, int last_row, int move
 
 // R4[x] for x = Lx-1 .. 1 of <D_{y+2}|M_{y+1} M_y|U_{y-1}>.
 template <typename T, int DD, int CC, bool BF16>
-__device__ void ph_row4_right(const LatDev& L, int ch, int y, char* lds) {
+__device__ __forceinline__ void ph_row4_right(const LatDev& L, int ch, int y, char* lds) {
   Chain<T> C = chain_of<T>(L, ch);
   if (C.meta->flags) return;
   const int sz = e4sz(L);
@@ -328,7 +328,7 @@ constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
 // sweep, y(Lx-1)+x, 6)), accepted with min[1, R pi(S')/pi(S)] (word 1); R from
 // the two-row network with columns x and x+1 exchanged in both rows.
 template <typename T, int DD, int CC, bool BF16, bool LEARN>
-__device__ void ph_vsweep(const LatDev& L, int ch, int y, char* lds) {
+__device__ __forceinline__ void ph_vsweep(const LatDev& L, int ch, int y, char* lds) {
   Chain<T> C = chain_of<T>(L, ch);
   if (C.meta->flags) return;
   const int sz = e4sz(L);
@@ -431,7 +431,7 @@ constexpr size_t compress_lds() {
 }
 
 template <typename T, int DD, int CC>
-__device__ void ph_compress(const LatDev& L, int ch, int y, int upper, char* lds) {
+__device__ __forceinline__ void ph_compress(const LatDev& L, int ch, int y, int upper, char* lds) {
   Chain<T> C = chain_of<T>(L, ch);
   if (C.meta->flags) return;
   double* cw = L.cws + (int64_t)ch * L.cws_stride;
@@ -531,7 +531,7 @@ __device__ void ph_compress(const LatDev& L, int ch, int y, int upper, char* lds
 // Measurement of row y (App. C): log-derivatives of its sites and its
 // horizontal pair ratios, all from the cached left/right auxiliary tensors.
 template <typename T>
-__device__ void ph_measure3(const LatDev& L, int ch, int y, const SampleOut& o, char* tiles) {
+__device__ __forceinline__ void ph_measure3(const LatDev& L, int ch, int y, const SampleOut& o, char* tiles) {
   Chain<T> C = chain_of<T>(L, ch);
   if (C.meta->flags) return;
   const int sz = e3sz(L), Lx = L.Lx, d = L.d;
@@ -607,7 +607,7 @@ __device__ void ph_measure3(const LatDev& L, int ch, int y, const SampleOut& o, 
 
 // Vertical and diagonal pairs between rows y and y+1 (two-row network).
 template <typename T, int DD, int CC>
-__device__ void ph_measure4(const LatDev& L, int ch, int y, const SampleOut& o, char* lds) {
+__device__ __forceinline__ void ph_measure4(const LatDev& L, int ch, int y, const SampleOut& o, char* lds) {
   Chain<T> C = chain_of<T>(L, ch);
   if (C.meta->flags) return;
   const int sz = e4sz(L), Lx = L.Lx;
