@@ -36,9 +36,10 @@ template <> struct Mfma<double> {
   __device__ static inline int row(int lane, int r) { return (lane >> 4) + 4 * r; }
 };
 
-template <int D, int C>
+// BBX > 0 overrides the b-block size (it must divide C).
+template <int D, int C, int BBX = 0>
 struct Env4Shape {
-  static constexpr int BB = (C % 4 == 0) ? C / 4 : ((C % 2 == 0) ? C / 2 : C);  // b-block
+  static constexpr int BB = BBX > 0 ? BBX : ((C % 4 == 0) ? C / 4 : ((C % 2 == 0) ? C / 2 : C));  // b-block
   static constexpr int NBLK = C / BB;
   static constexpr int SA = C * D * C, ST = D * D * D * D;
   static constexpr int SL = C * D * D;            // one lower-bond slice of Lin
@@ -124,11 +125,16 @@ __device__ inline void mfma_stage(TC* out, FA fa, FB fb) {
 
 // GRAM: t2 is the u<->d view of t1 and B is A (the Gram step of the boundary
 // compression); each is then staged once.
+// b-block of a fused step: the Gram step of the compression over float64
+// tensors takes C/8 so that its LDS stays within two work-groups per CU.
+template <typename TC, typename TB, int D, int C, bool GRAM>
+constexpr int env4_bb() { return (GRAM && sizeof(TB) == 8 && C % 8 == 0) ? C / 8 : 0; }
+
 template <typename TC, typename TB, int D, int C, bool GRAM = false, bool BF16 = false>
 __device__ void env4_fused(TC* __restrict__ Lout, const TC* __restrict__ Lin, const TB* __restrict__ A, S3 sA,
                            const TB* __restrict__ t1, S4 s1, const TB* __restrict__ t2, S4 s2,
                            const TB* __restrict__ B, S3 sB, char* lds) {
-  using Sh = Env4Shape<D, C>;
+  using Sh = Env4Shape<D, C, env4_bb<TC, TB, D, C, GRAM>()>;
   constexpr int BB = Sh::BB, NBLK = Sh::NBLK, N4 = Sh::N4, NT4 = Sh::NT4, T4W = Sh::T4W;
   TB* As = reinterpret_cast<TB*>(lds);
   TB* Bs = GRAM ? As : As + Sh::SA;

@@ -98,7 +98,7 @@ __device__ inline int step3(const LatDev& L, const Chain<T>& C, T* out, const T*
 // LDS bytes a kernel provides for its 2-row column steps.
 template <typename TC, typename TB, int DD, int CC, bool GRAM = false>
 constexpr size_t env4_lds() {
-  if constexpr (DD > 0) return Env4Shape<DD, CC>::template lds_bytes<TC, TB, GRAM>();
+  if constexpr (DD > 0) return Env4Shape<DD, CC, env4_bb<TC, TB, DD, CC, GRAM>()>::template lds_bytes<TC, TB, GRAM>();
   else return GEMM_TILE_BYTES;  // the generic step's GEMM tiles
 }
 
