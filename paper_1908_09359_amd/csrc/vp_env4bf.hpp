@@ -1,0 +1,222 @@
+// Fused 2-row ("4-line") column step with bf16 operands, compile-time dimensions.
+//
+//   Lout[e][b][r1][r2] = sum Lin[c][a][l1][l2] A[a][u][b] t1[l1][u][r1][m]
+//                             t2[l2][m][r2][dd] B[c][dd][e]
+//
+// Same contraction order as env4_fused (four pairwise products per block of BB
+// upper-boundary indices and per lower-boundary index c, the last one
+// accumulated across c in MFMA registers), but every operand lives in LDS as
+// bf16 in the layout its MFMA consumes: k contiguous, rows of the contraction
+// length rounded up to 8 (zero padded) plus 8 elements of bank spread, so that
+// each lane fetches its 8 k-values of a 16x16x32 MFMA in one 16-byte read;
+// k-groups past the contraction length are zero without a read.
+// Products accumulate in f32; stage outputs are rounded to bf16 when stored
+// for the next stage.  Lin/Lout and the column tensors are in TS (float64 or
+// float32) storage.
+#pragma once
+#include "vp_device.hpp"
+
+namespace vp {
+
+typedef __bf16 v8bf_e __attribute__((ext_vector_type(8)));
+typedef float v4f_e __attribute__((ext_vector_type(4)));
+
+template <int D, int C>
+struct Env4Bf {
+  static constexpr int BB = (C % 4 == 0) ? C / 4 : ((C % 2 == 0) ? C / 2 : C);
+  static constexpr int NBLK = C / BB;
+  static constexpr int rup8(int x) { return (x + 7) / 8 * 8; }
+  static constexpr int K1 = C, K2 = D * D, K3 = D * D, K4 = D;      // contraction lengths
+  static constexpr int P1 = rup8(K1) + 8, P2 = rup8(K2) + 8, P3 = rup8(K3) + 8, P4 = rup8(K4) + 8;  // row strides
+  // operand arrays (bf16 elements)
+  static constexpr int nAT = D * C * P1;          // [(u, b)][a]
+  static constexpr int nLs = D * D * P1;          // [(l1, l2)][a]     (one lower-bond slice)
+  static constexpr int nT1 = D * D * P2;          // [(r1, m)][(l1, u)]
+  static constexpr int nT2 = D * D * P3;          // [(r2, dd)][(l2, m)]
+  static constexpr int nBT = C * C * P4;          // [(c, e)][dd]
+  static constexpr int nX1 = D * BB * P2;         // [(l2, bb)][(l1, u)]
+  static constexpr int nX2 = BB * D * P3;         // [(bb, r1)][(l2, m)]
+  static constexpr int nX3 = BB * D * D * P4;     // [(bb, r1, r2)][dd]
+  static constexpr int N4 = BB * D * D;           // output columns per block
+  static constexpr int NT4 = (N4 + 15) / 16;
+  static constexpr int T4W = (NT4 + 3) / 4;
+  static constexpr size_t lds_bytes() {
+    return 2 * (size_t)(nAT + nLs + nT1 + nT2 + nBT + nX1 + nX2 + nX3);
+  }
+};
+
+// 8 bf16 of a row from k0 on; zero past the contraction length K (rows are
+// zero padded to a multiple of 8).
+__device__ inline v8bf_e ld8(const __bf16* row, int k0, int K) {
+  const v8bf_e z = {};
+  return k0 < K ? *reinterpret_cast<const v8bf_e*>(row + k0) : z;
+}
+
+// 16x16 output tile of A (M x K, row stride PA) times B^T (N x K, row stride
+// PB), both bf16 in LDS.
+template <int K>
+__device__ inline v4f_e bf_tile(const __bf16* A, int PA, const __bf16* B, int PB, int m0, int n0, int M, int N) {
+  v4f_e acc = {0, 0, 0, 0};
+  const int lane = threadIdx.x & 63;
+  const int i = min(m0 + (lane & 15), M - 1), j = min(n0 + (lane & 15), N - 1), kq = (lane >> 4) * 8;
+#pragma unroll
+  for (int s = 0; s < (K + 31) / 32; ++s) {
+    const v8bf_e a = ld8(A + i * PA, 32 * s + kq, K);
+    const v8bf_e b = ld8(B + j * PB, 32 * s + kq, K);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+template <int D, int C, typename TS>
+__device__ void env4_bf16(TS* __restrict__ Lout, const TS* __restrict__ Lin, const TS* __restrict__ A, S3 sA,
+                          const TS* __restrict__ t1, S4 s1, const TS* __restrict__ t2, S4 s2,
+                          const TS* __restrict__ B, S3 sB, char* lds) {
+  using S = Env4Bf<D, C>;
+  constexpr int BB = S::BB;
+  __bf16* AT = reinterpret_cast<__bf16*>(lds);
+  __bf16* Ls = AT + S::nAT;
+  __bf16* T1 = Ls + S::nLs;
+  __bf16* T2 = T1 + S::nT1;
+  __bf16* BT = T2 + S::nT2;
+  __bf16* X1 = BT + S::nBT;
+  __bf16* X2 = X1 + S::nX1;
+  __bf16* X3 = X2 + S::nX2;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const __bf16 zero = (__bf16)0.0f;
+
+  // stage the column tensors once, transposed to k-contiguous rows; zero the
+  // padding of every array (the intermediates' padding is never written later)
+  for (int e = tid; e < S::nAT; e += WG) {
+    const int row = e / S::P1, a = e - row * S::P1, u = row / C, b = row - u * C;
+    AT[e] = a < C ? (__bf16)(float)A[a * sA.s0 + u * sA.s1 + b * sA.s2] : zero;
+  }
+  for (int e = tid; e < S::nT1; e += WG) {
+    const int row = e / S::P2, k = e - row * S::P2;  // row = (r1, m), k = (l1, u)
+    const int r = row / D, m = row - r * D, l = k / D, u = k - l * D;
+    T1[e] = k < D * D ? (__bf16)(float)t1[l * s1.l + u * s1.u + r * s1.r + m * s1.d] : zero;
+  }
+  for (int e = tid; e < S::nT2; e += WG) {
+    const int row = e / S::P3, k = e - row * S::P3;  // row = (r2, dd), k = (l2, m)
+    const int r = row / D, dd = row - r * D, l = k / D, m = k - l * D;
+    T2[e] = k < D * D ? (__bf16)(float)t2[l * s2.l + m * s2.u + r * s2.r + dd * s2.d] : zero;
+  }
+  for (int e = tid; e < S::nBT; e += WG) {
+    const int row = e / S::P4, dd = e - row * S::P4, c = row / C, ee = row - c * C;
+    BT[e] = dd < D ? (__bf16)(float)B[c * sB.s0 + dd * sB.s1 + ee * sB.s2] : zero;
+  }
+  for (int e = tid; e < S::nX1 + S::nX2 + S::nX3; e += WG) X1[e] = zero;
+
+  for (int q = 0; q < S::NBLK; ++q) {
+    const int b0 = q * BB;
+    v4f_e acc[S::T4W];
+#pragma unroll
+    for (int w = 0; w < S::T4W; ++w) acc[w] = {0, 0, 0, 0};
+    for (int cs = 0; cs < C; ++cs) {
+      __syncthreads();  // previous slice done with Ls / X buffers (and the staging above)
+      for (int e = tid; e < S::nLs; e += WG) {
+        const int row = e / S::P1, a = e - row * S::P1;  // row = (l1, l2)
+        Ls[e] = a < C ? (__bf16)(float)Lin[(cs * C + a) * (D * D) + row] : zero;
+      }
+      __syncthreads();
+      // S1: X1[(l2,bb)][(l1,u)] = sum_a Ls[(l1,l2)][a] AT[(u, b0+bb)][a]; M = D^2, N = D BB
+      {
+        constexpr int MT = (D * D + 15) / 16, NT = (D * BB + 15) / 16;
+        for (int t = wave; t < MT * NT; t += 4) {
+          const int m0 = (t / NT) * 16, n0 = (t % NT) * 16;
+          // B rows j = (u, bb) -> AT row u C + b0 + bb: a strided row set, fetched row by row
+          v4f_e c4 = {0, 0, 0, 0};
+          {
+            // rows past M or N are clamped to the last one: their products land in
+            // output rows and columns that are never stored
+            const int i = min(m0 + (lane & 15), D * D - 1), j = min(n0 + (lane & 15), D * BB - 1);
+            const int kq = (lane >> 4) * 8, u = j / BB, bb = j - u * BB;
+#pragma unroll
+            for (int s = 0; s < (S::K1 + 31) / 32; ++s) {
+              const v8bf_e a = ld8(Ls + i * S::P1, 32 * s + kq, S::K1);
+              const v8bf_e b = ld8(AT + (u * C + b0 + bb) * S::P1, 32 * s + kq, S::K1);
+              c4 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c4, 0, 0, 0);
+            }
+          }
+          const int j = n0 + (lane & 15);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = m0 + 4 * (lane >> 4) + r;  // (l1, l2)
+            if (i < D * D && j < D * BB) {
+              const int l1 = i / D, l2 = i - l1 * D, u = j / BB, bb = j - u * BB;
+              X1[(l2 * BB + bb) * S::P2 + l1 * D + u] = (__bf16)c4[r];
+            }
+          }
+        }
+      }
+      __syncthreads();
+      // S2: X2[(bb,r1)][(l2,m)] = sum_{(l1,u)} X1[(l2,bb)][(l1,u)] T1[(r1,m)][(l1,u)]; M = D BB, N = D^2
+      {
+        constexpr int MT = (D * BB + 15) / 16, NT = (D * D + 15) / 16;
+        for (int t = wave; t < MT * NT; t += 4) {
+          const int m0 = (t / NT) * 16, n0 = (t % NT) * 16;
+          const v4f_e c4 = bf_tile<S::K2>(X1, S::P2, T1, S::P2, m0, n0, D * BB, D * D);
+          const int j = n0 + (lane & 15);  // (r1, m)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = m0 + 4 * (lane >> 4) + r;  // (l2, bb)
+            if (i < D * BB && j < D * D) {
+              const int l2 = i / BB, bb = i - l2 * BB, r1 = j / D, m = j - r1 * D;
+              X2[(bb * D + r1) * S::P3 + l2 * D + m] = (__bf16)c4[r];
+            }
+          }
+        }
+      }
+      __syncthreads();
+      // S3: X3[(bb,r1,r2)][dd] = sum_{(l2,m)} X2[(bb,r1)][(l2,m)] T2[(r2,dd)][(l2,m)]; M = BB D, N = D^2
+      {
+        constexpr int MT = (BB * D + 15) / 16, NT = (D * D + 15) / 16;
+        for (int t = wave; t < MT * NT; t += 4) {
+          const int m0 = (t / NT) * 16, n0 = (t % NT) * 16;
+          const v4f_e c4 = bf_tile<S::K3>(X2, S::P3, T2, S::P3, m0, n0, BB * D, D * D);
+          const int j = n0 + (lane & 15);  // (r2, dd)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = m0 + 4 * (lane >> 4) + r;  // (bb, r1)
+            if (i < BB * D && j < D * D) {
+              const int r2 = j / D, dd = j - r2 * D;
+              X3[(i * D + r2) * S::P4 + dd] = (__bf16)c4[r];
+            }
+          }
+        }
+      }
+      __syncthreads();
+      // S4: acc[e][(bb,r1,r2)] += sum_dd BT[(cs, e)][dd] X3[(bb,r1,r2)][dd]; M = C, N = BB D^2
+#pragma unroll
+      for (int w = 0; w < S::T4W; ++w) {
+        const int t = wave + 4 * w;
+        if (t < S::NT4) {
+          const int i = min(lane & 15, C - 1), j = min(t * 16 + (lane & 15), S::N4 - 1);
+          const int kq = (lane >> 4) * 8;
+#pragma unroll
+          for (int s = 0; s < (S::K4 + 31) / 32; ++s) {
+            const v8bf_e a = ld8(BT + (cs * C + i) * S::P4, 32 * s + kq, S::K4);
+            const v8bf_e b = ld8(X3 + j * S::P4, 32 * s + kq, S::K4);
+            acc[w] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[w], 0, 0, 0);
+          }
+        }
+      }
+    }
+    // write Lout[e][b0 + (bb, r1, r2)]
+#pragma unroll
+    for (int w = 0; w < S::T4W; ++w) {
+      const int t = wave + 4 * w;
+      if (t < S::NT4) {
+        const int j = t * 16 + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int e = 4 * (lane >> 4) + r;
+          if (e < C && j < S::N4) Lout[e * (C * D * D) + q * S::N4 + j] = (TS)acc[w][r];
+        }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+}  // namespace vp

@@ -5,6 +5,7 @@
 #include "vp_device.hpp"
 #include "vp_eig.hpp"
 #include "vp_env4.hpp"
+#include "vp_env4bf.hpp"
 #include "vp_kernels.hpp"
 #include "vp_net.hpp"
 
@@ -115,8 +116,10 @@ __device__ inline int step4(const LatDev& L, const Chain<T>& C, T* out, const T*
   S4 st = st_std(L.d);
   const S3 sb = right ? sb_mirror(L.c, L.d) : sb_std(L.c, L.d);
   const S4 s = right ? st_mirror(st) : st;
-  if constexpr (DD > 0) {
-    env4_fused<T, T, DD, CC, false, BF16>(out, in, Ux, sb, t1, s, t2, s, Dx, sb, lds);
+  if constexpr (DD > 0 && BF16) {
+    env4_bf16<DD, CC, T>(out, in, Ux, sb, t1, s, t2, s, Dx, sb, lds);
+  } else if constexpr (DD > 0) {
+    env4_fused<T, T, DD, CC>(out, in, Ux, sb, t1, s, t2, s, Dx, sb, lds);
   } else {
     env4_step<T, T, BF16>(out, in, Ux, sb, t1, s, t2, s, Dx, sb, C.ws + L.oX0, C.ws + L.oX1, L.c, L.d, lds);
   }
@@ -707,15 +710,22 @@ template <typename T, bool BF16>
 __global__ void __launch_bounds__(WG) k_hsweep(LatDev L, int y, int last_row, int moves) {
   ph_hsweep<T, BF16>(L, blockIdx.x, y, last_row, moves, gemm_tiles());
 }
+// LDS of a 2-row step: the bf16 step stages compact bf16 operands.
+template <typename T, int DD, int CC, bool BF16>
+constexpr size_t step4_lds() {
+  if constexpr (BF16 && DD > 0) return Env4Bf<DD, CC>::lds_bytes();
+  else return env4_lds<T, T, DD, CC>();
+}
+
 template <typename T, int DD, int CC, bool BF16>
 __global__ void __launch_bounds__(WG) k_row4_right(LatDev L, int y) {
-  __shared__ __attribute__((aligned(16))) char lds[env4_lds<T, T, DD, CC>()];
+  __shared__ __attribute__((aligned(16))) char lds[step4_lds<T, DD, CC, BF16>()];
   ph_row4_right<T, DD, CC, BF16>(L, blockIdx.x, y, lds);
 }
 template <typename T, int DD, int CC, bool BF16, bool LEARN>
 __global__ void __launch_bounds__(WG) k_vsweep(LatDev L, int y) {
   __shared__ __attribute__((aligned(16)))
-  char lds[cmax(env4_lds<T, T, DD, CC>(), LEARN ? net_lds_bytes<T>() : 0)];
+  char lds[cmax(step4_lds<T, DD, CC, BF16>(), LEARN ? net_lds_bytes<T>() : 0)];
   ph_vsweep<T, DD, CC, BF16, LEARN>(L, blockIdx.x, y, lds);
 }
 template <typename T, int DD, int CC>
