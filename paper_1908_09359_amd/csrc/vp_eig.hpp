@@ -28,13 +28,21 @@ static_assert(3 * EIG_NMAX * EIG_KMAX * 8 + EIG_NMAX * EIG_KMAX * 8 + EIG_NMAX *
 __device__ inline int tri(int i) { return i * (i + 1) / 2; }
 
 // Number of eigenvalues of tridiag(d, e) strictly below x (Sturm sequence).
+// 1/q: the hardware reciprocal refined by one Newton step (relative error at
+// the level of the last bits; the counts and pivots below need no more).
+__device__ inline double recip(double q) {
+  const double r = __builtin_amdgcn_rcp(q);
+  return fma(r, fma(-q, r, 1.0), r);
+}
+
 __device__ inline int sturm_count(const double* d, const double* e2, int n, double x, double pivmin) {
   int cnt = 0;
   double q = d[0] - x;
   if (fabs(q) < pivmin) q = -pivmin;
   cnt += q < 0.0;
+#pragma unroll 8
   for (int j = 1; j < n; ++j) {
-    q = d[j] - x - e2[j - 1] / q;
+    q = d[j] - x - e2[j - 1] * recip(q);
     if (fabs(q) < pivmin) q = -pivmin;
     cnt += q < 0.0;
   }
@@ -293,26 +301,29 @@ __device__ __forceinline__ void sym_topk_eig(const double* H, int n, int k, doub
       // Gaussian elimination with partial pivoting of T - lm I; a swap of rows j
       // and j+1 puts the known entry e[j+1] on the second superdiagonal.
       double aa = dg[0] - lm, cc = n > 1 ? eg[0] : 0.0;
+      #pragma unroll 4
       for (int j = 0; j < n - 1; ++j) {
         const double bb = eg[j];
         const double a1 = dg[j + 1] - lm;
         const double c1 = (j + 1 < n - 1) ? eg[j + 1] : 0.0;
         if (fabs(aa) >= fabs(bb)) {
           const double piv = fabs(aa) < tiny ? (aa < 0.0 ? -tiny : tiny) : aa;
-          const double m = bb / piv;
-          U0[IX(j)] = 1.0 / piv; U1[IX(j)] = cc; ML[IX(j)] = m;
+          const double ip = recip(piv);
+          const double m = bb * ip;
+          U0[IX(j)] = ip; U1[IX(j)] = cc; ML[IX(j)] = m;
           aa = a1 - m * cc;
           cc = c1;
         } else {
-          const double m = aa / bb;
-          U0[IX(j)] = 1.0 / bb; U1[IX(j)] = a1; ML[IX(j)] = m;
+          const double ib = recip(bb);
+          const double m = aa * ib;
+          U0[IX(j)] = ib; U1[IX(j)] = a1; ML[IX(j)] = m;
           atomicOr(&pivw[j], 1u << tid);
           const double naa = cc - m * a1;
           cc = -m * c1;
           aa = naa;
         }
       }
-      U0[IX(n - 1)] = 1.0 / (fabs(aa) < tiny ? (aa < 0.0 ? -tiny : tiny) : aa);
+      U0[IX(n - 1)] = recip(fabs(aa) < tiny ? (aa < 0.0 ? -tiny : tiny) : aa);
       // deterministic, eigenvector-dependent start vector
       for (int j = 0; j < n; ++j) {
         uint64_t h = (uint64_t)(j + 1) * 0x9E3779B97F4A7C15ull ^ (uint64_t)(col + 1) * 0xD2E7470EE14C6C93ull;
@@ -320,6 +331,7 @@ __device__ __forceinline__ void sym_topk_eig(const double* H, int n, int k, doub
         Xs[IX(j)] = 0.5 + (double)(h & 0xFFFF) / 65536.0;
       }
       for (int it = 0; it < 3; ++it) {
+        #pragma unroll 4
         for (int j = 0; j < n - 1; ++j) {
           double rj = Xs[IX(j)], rj1 = Xs[IX(j + 1)];
           if ((pivw[j] >> tid) & 1u) { double tt = rj; rj = rj1; rj1 = tt; }
@@ -327,6 +339,7 @@ __device__ __forceinline__ void sym_topk_eig(const double* H, int n, int k, doub
           Xs[IX(j + 1)] = rj1 - ML[IX(j)] * rj;
         }
         double x1 = 0.0, x2 = 0.0, nrm = 0.0;
+        #pragma unroll 4
         for (int j = n - 1; j >= 0; --j) {
           const double u2 = ((pivw[j] >> tid) & 1u) && j + 1 < n - 1 ? eg[j + 1] : 0.0;
           const double xj = (Xs[IX(j)] - U1[IX(j)] * x1 - u2 * x2) * U0[IX(j)];  // U0 holds 1/pivot
@@ -395,8 +408,53 @@ __device__ __forceinline__ void sym_topk_eig(const double* H, int n, int k, doub
   }
   __syncthreads();
 
-  // ---- back-transformation: x <- H_0 H_1 ... H_{n-3} x; reflector i streamed from global
-  // memory, the next one prefetched into a register while the current one is applied
+  // ---- back-transformation: x <- H_0 H_1 ... H_{n-3} x
+  if (in_lds) {
+    // the k <= 16 vectors in registers: thread t holds rows 8 (t / 16) .. +7 of
+    // column t % 16; reflector i is staged in one of two LDS rows while the
+    // previous one is applied, and the column sums of v^T x alternate between
+    // two LDS rows, so one barrier per reflector suffices.
+    const int col = tid & 15, rb = tid >> 4, wave = tid >> 6;
+    double* vb[2] = {vv, wv};
+    double* rs[2] = {pv, probe_x};  // [4 waves][16 columns] each
+    double x[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int r = 8 * rb + q;
+      x[q] = (r < n && col < k) ? Xs[r * EIG_KMAX + col] : 0.0;
+    }
+    if (n >= 3 && tid < EIG_NMAX) vb[(n - 3) & 1][tid] = (tid > n - 3 && tid < n) ? refl[tri(tid) + n - 3] : 0.0;
+    __syncthreads();
+    for (int i = n - 3; i >= 0; --i) {
+      const double* v = vb[i & 1];
+      double vr[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) vr[q] = v[8 * rb + q];
+      const double t = tau[i];
+      double part = 0.0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) part += vr[q] * x[q];
+      part += __shfl_xor(part, 16, 64);
+      part += __shfl_xor(part, 32, 64);
+      double* red = rs[i & 1];
+      if ((tid & 63) < 16) red[wave * 16 + col] = part;
+      // stage reflector i - 1 (every reader of that row has passed the previous barrier)
+      if (i >= 1 && tid < EIG_NMAX) vb[(i - 1) & 1][tid] = (tid > i - 1 && tid < n) ? refl[tri(tid) + i - 1] : 0.0;
+      __syncthreads();
+      const double f = t * ((red[col] + red[16 + col]) + (red[32 + col] + red[48 + col]));
+#pragma unroll
+      for (int q = 0; q < 8; ++q) x[q] -= f * vr[q];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int r = 8 * rb + q;
+      if (r < n && col < k) V[(int64_t)r * k + col] = x[q];
+    }
+    __syncthreads();
+    return;
+  }
+  // more than 16 vectors: reflector i streamed from global memory into LDS, the
+  // next one prefetched into a register while the current one is applied
   double vreg = (n >= 3 && tid > n - 3 && tid < n) ? refl[tri(tid) + n - 3] : 0.0;
   for (int i = n - 3; i >= 0; --i) {
     if (tid < n) vv[tid] = tid > i ? vreg : 0.0;
