@@ -49,20 +49,25 @@ enum : uint64_t { TAG_INIT = 1, TAG_PERTURB = 2, TAG_SHUFFLE = 3, TAG_METRO = 4,
 // Strided 2-level views: element (i, j) of a matrix lives at
 //   (i / n2i) * si1 + (i % n2i) * si2 + (j / n2j) * sj1 + (j % n2j) * sj2.
 // ---------------------------------------------------------------------------
+// The divisions use multiply-high by m = floor(2^32 / n2) + 1, exact for
+// indices and divisors below 2^16 (the error term n (m n2 - 2^32) / 2^32 stays
+// below 1/n2).
 struct View {
   int n2i, n2j;
   int si1, si2, sj1, sj2;
+  uint64_t mi, mj;
 };
 
-__host__ __device__ inline View rowmajor(int ld) { return View{1, 1, ld, 0, 1, 0}; }
-__host__ __device__ inline View colmajor(int ld) { return View{1, 1, 1, 0, ld, 0}; }
+__host__ __device__ inline uint64_t div_magic(int d) { return (1ull << 32) / (uint64_t)d + 1; }
 __host__ __device__ inline View view(int n2i, int si1, int si2, int n2j, int sj1, int sj2) {
-  return View{n2i, n2j, si1, si2, sj1, sj2};
+  return View{n2i, n2j, si1, si2, sj1, sj2, div_magic(n2i), div_magic(n2j)};
 }
+__host__ __device__ inline View rowmajor(int ld) { return view(1, ld, 0, 1, 1, 0); }
+__host__ __device__ inline View colmajor(int ld) { return view(1, 1, 0, 1, ld, 0); }
 
 __device__ inline int vaddr(const View& v, int i, int j) {
-  int i1 = i / v.n2i, i2 = i - i1 * v.n2i;
-  int j1 = j / v.n2j, j2 = j - j1 * v.n2j;
+  const int i1 = (int)(((uint64_t)(unsigned)i * v.mi) >> 32), i2 = i - i1 * v.n2i;
+  const int j1 = (int)(((uint64_t)(unsigned)j * v.mj) >> 32), j2 = j - j1 * v.n2j;
   return i1 * v.si1 + i2 * v.si2 + j1 * v.sj1 + j2 * v.sj2;
 }
 
