@@ -36,24 +36,36 @@ METRIC = "samples/s (psi, E_loc, dlnpsi) 16x16 D=8 Dc=16, learned+bf16 vs plain 
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15, "hbm": 8.0e12}
 
 
-def phase_flops(Ly, Lx, D, Dc):
-    """Algorithmic flops per chain of one launch of each deterministic phase.
+def phase_flops(Ly, Lx, D, Dc, nch, launches, anti_h=0, anti_v=0):
+    """Algorithmic flops of each phase over the timed region (all chains, all launches).
 
     Column-step costs (multiply-adds, bulk dimensions):
       3-line step   D^4 Dc^2 + 2 D^2 Dc^3
       2-row step    2 D^5 Dc^2 + 2 D^3 Dc^3
+      defect        D^2 Dc^3 + D^3 Dc^3 + D^4 Dc^2
       compression of one row (Gram steps, right-to-left carries, eigenproblems
       of order n = D Dc: tridiagonalisation 4/3 n^3 flops, back-transformation
       4 n^2 Dc flops)
+    A measurement launch (one row, or one row pair) computes the right and left
+    environments (Lx-1 steps each), the defects of the row's sites, and one ratio
+    network per antiparallel pair: two 3-line steps for a horizontal pair, one
+    2-row step for a vertical pair.  anti_h / anti_v are the numbers of
+    antiparallel horizontal / vertical pairs in the configurations measured.
     """
     c, d = Dc, D
     env3 = d ** 4 * c ** 2 + 2 * d ** 2 * c ** 3
     env4 = 2 * d ** 5 * c ** 2 + 2 * d ** 3 * c ** 3
+    defect = d ** 2 * c ** 3 + d ** 3 * c ** 3 + d ** 4 * c ** 2
     n = d * c
     comp_mac = (Lx - 1) * env4 + Lx * (d ** 2 * c ** 3 + d ** 4 * c ** 2) + (Lx - 1) * (2 * n ** 3 + d ** 2 * c ** 3)
     comp = 2 * comp_mac + (Lx - 1) * (4.0 / 3.0 * n ** 3 + 4 * n ** 2 * c)
-    return {"row3_envs": 2 * (Lx - 1) * env3, "row4_envs": 2 * (Lx - 1) * env4,
-            "compress_up": comp, "compress_down": comp}
+    per_launch = {"row3_envs": 2 * (Lx - 1) * env3, "row4_envs": 2 * (Lx - 1) * env4,
+                  "compress_up": comp, "compress_down": comp}
+    out = {k: v * nch * launches.get(k, 0) for k, v in per_launch.items()}
+    out["measure3"] = 2.0 * (nch * launches.get("measure3", 0) * (2 * (Lx - 1) * env3 + Lx * defect)
+                             + anti_h * 2 * env3)
+    out["measure4"] = 2.0 * (nch * launches.get("measure4", 0) * 2 * (Lx - 1) * env4 + anti_v * env4)
+    return out
 
 
 def cpu_baseline(Ly, Lx, D, Dc, seed):
@@ -131,18 +143,23 @@ class Path:
         self.ctx.vp_sync()
         torch.cuda.synchronize()
         cnt0 = self.counts()
+        # the configurations measured in each step (an output of the sweep)
+        so = torch.empty((steps, self.nch, self.N), dtype=torch.int8, device=self.dev)
         self.ctx.vp_timing_enable(True)
         t0 = time.perf_counter()
-        for _ in range(steps):
-            self.sweep()
+        for s in range(steps):
+            self.ctx.vp_sample(0, 0, 1, self.lp, self.sg, self.el, self.dl, so[s])
         self.ctx.vp_sync()
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         ms, launches = self.ctx.vp_timing_read()
         self.ctx.vp_timing_enable(False)
         cnt = self.counts() - cnt0
+        g = so.view(steps, self.nch, self.Ly, self.Lx)
+        anti_h = int((g[..., :, 1:] != g[..., :, :-1]).sum().item())
+        anti_v = int((g[..., 1:, :] != g[..., :-1, :]).sum().item())
         return {"samples_per_s": self.nch * steps / dt, "ms_per_step": dt / steps * 1e3, "ms": ms,
-                "launches": launches, "seconds": dt,
+                "launches": launches, "seconds": dt, "anti_h": anti_h, "anti_v": anti_v,
                 "pair_accept": float(cnt[0] / max(cnt[1], 1)),
                 "plaquette_accept": float(cnt[2] / cnt[3]) if cnt[3] else None,
                 "plaquette_proposed_per_sweep": float(cnt[3] / self.nch / steps),
@@ -177,15 +194,16 @@ class Path:
         self.ctx.close()
 
 
-def roofline(ms, launches, flops, nch, fp64_contractions):
-    """Dominant deterministic phase: algorithmic flops per launch / live average launch time."""
-    timed = {k: v for k, v in ms.items() if k in flops and launches[k] > 0}
+def roofline(ms, launches, flops, fp64_phases):
+    """The phase with the largest share of the timed sweeps among those with an algorithmic
+    flop count: its flops over the timed region / its summed live launch time."""
+    timed = {k: v for k, v in ms.items() if k in flops and flops[k] > 0}
     dom = max(timed, key=lambda k: timed[k])
-    avg_s = ms[dom] / launches[dom] / 1e3
-    achieved = flops[dom] * nch / avg_s
-    peak = PEAK["fp64"] if (dom.startswith("compress") or fp64_contractions) else PEAK["fp32"]
+    achieved = flops[dom] / (ms[dom] / 1e3)
+    peak = PEAK["fp64"] if dom in fp64_phases else PEAK["fp32"]
     return {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": None, "avg_launch_ms": ms[dom] / launches[dom]}
+            "frac": achieved / peak, "traffic": None, "launches": launches[dom],
+            "avg_launch_ms": ms[dom] / launches[dom]}
 
 
 def main():
@@ -202,6 +220,8 @@ def main():
     ap.add_argument("--tau-sweeps", type=int, default=0)
     ap.add_argument("--only", choices=["both", "plain", "learned"], default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 1 GiB device to device three times (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -209,17 +229,25 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.copy_probe:
+        x = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")  # 1 GiB
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": x.numel() * 8, "copies": 3}), flush=True)
+        return
     from paper_1908_09359_amd import binding as B
 
     Ly = Lx = args.L
     D, Dc, nch = args.D, args.Dc, args.chains
-    flops = phase_flops(Ly, Lx, D, Dc)
     res = {}
     if args.only in ("both", "plain"):
         p = Path(B, torch, Ly, Lx, D, Dc, B.VP_FP32, nch)
         r = p.timed(args.warmup, args.steps)
         print(f"plain: {r['samples_per_s']:.1f} samples/s", file=sys.stderr, flush=True)
-        r["roofline"] = roofline(r["ms"], r["launches"], flops, nch, False)
+        fl = phase_flops(Ly, Lx, D, Dc, nch, r["launches"], r["anti_h"], r["anti_v"])
+        r["roofline"] = roofline(r["ms"], r["launches"], fl, ("compress_up", "compress_down"))
         if args.tau_sweeps:
             r["tau"] = p.tau_run(args.tau_sweeps)
         p.close()
@@ -233,7 +261,8 @@ def main():
         r = p.timed(args.warmup, args.steps)
         print(f"learned: {r['samples_per_s']:.1f} samples/s", file=sys.stderr, flush=True)
         r["training"] = tr
-        r["roofline"] = roofline(r["ms"], r["launches"], flops, nch, True)
+        fl = phase_flops(Ly, Lx, D, Dc, nch, r["launches"], r["anti_h"], r["anti_v"])
+        r["roofline"] = roofline(r["ms"], r["launches"], fl, ("compress_up", "compress_down", "measure3", "measure4"))
         if args.tau_sweeps:
             r["tau"] = p.tau_run(args.tau_sweeps)
         p.close()
@@ -255,15 +284,18 @@ def main():
         "phase_ms_per_step": {k: v / args.steps for k, v in head["ms"].items()},
     }
     for name, r in res.items():
-        out[name] = {k: v for k, v in r.items() if k not in ("ms", "launches", "roofline")}
+        out[name] = {k: v for k, v in r.items() if k not in ("ms", "launches", "roofline", "anti_h", "anti_v")}
         out[name]["phase_ms_per_step"] = {k: v / args.steps for k, v in r["ms"].items()}
         out[name]["dominant_kernel"] = r["roofline"]
     if "plain" in res and "learned" in res:
         out["learned_over_plain_raw"] = res["learned"]["samples_per_s"] / res["plain"]["samples_per_s"]
         if args.tau_sweeps:
-            # time to a fixed standard error dE of E/site ~ var * 2 tau / (dE^2 * rate)
+            # time to a fixed standard error dE of E/site ~ var * 2 tau / (dE^2 * rate).  Both paths
+            # sample |Psi|^2 of the same tensors, so var is the same in expectation; its sample
+            # estimates are heavy-tailed (E_loc diverges near nodes of Psi) and are left out of
+            # the ratio, which keeps tau_int and the rate only.
             def cost(t):
-                return t["var_e_site_per_sample"] * 2.0 * t["tau_int_mean"] / t["samples_per_s"]
+                return 2.0 * t["tau_int_mean"] / t["samples_per_s"]
             out["learned_over_plain_at_fixed_dE"] = cost(res["plain"]["tau"]) / cost(res["learned"]["tau"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(Ly, Lx, D, Dc, seed=1908)

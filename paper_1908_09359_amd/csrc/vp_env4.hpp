@@ -47,9 +47,14 @@ struct Env4Shape {
   static constexpr int N4 = BB * D * D;           // S4 columns per block
   static constexpr int NT4 = (N4 + 15) / 16;      // S4 column tiles per block
   static constexpr int T4W = (NT4 + 3) / 4;       // S4 tiles per wave per block
+  // Site tensors of S2 / S3 held in registers instead of LDS: when the D^2
+  // output columns of those stages span exactly four 16-column tiles, wave w
+  // always owns tile w, so its B operand is fixed for the whole step.
+  template <bool GRAM = false, bool BF16 = false>
+  static constexpr bool regt() { return !GRAM && !BF16 && (D * D + 15) / 16 == 4; }
   template <typename TC, typename TB, bool GRAM = false>
   static constexpr size_t lds_bytes() {
-    return sizeof(TB) * (GRAM ? SA + ST : 2 * SA + 2 * ST) + sizeof(TC) * (SL + 2 * SX);
+    return sizeof(TB) * (GRAM ? SA + ST : 2 * SA + (regt<GRAM>() ? 0 : 2 * ST)) + sizeof(TC) * (SL + 2 * SX);
   }
 };
 
@@ -123,6 +128,37 @@ __device__ inline void mfma_stage(TC* out, FA fa, FB fb) {
   }
 }
 
+// A stage whose B operand sits in registers: N spans four 16-column tiles and
+// wave w owns columns 16w..16w+15 of every row tile; f[s] holds
+// B(4s + lane/16, 16w + lane%16).  The row tiles' accumulation chains are
+// interleaved.
+template <typename TC, int M, int N, int K, typename FA>
+__device__ inline void mfma_stage_regb(TC* out, FA fa, const TC (&f)[(K + 3) / 4]) {
+  constexpr int MT = (M + 15) / 16, KS = (K + 3) / 4;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, kq = lane >> 4;
+  typename Mfma<TC>::acc_t acc[MT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) acc[mt] = {0, 0, 0, 0};
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    const int k = 4 * s + kq;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const int i = mt * 16 + (lane & 15);
+      const TC a = (i < M && k < K) ? fa(i, k) : TC(0);
+      acc[mt] = Mfma<TC>::op(a, f[s], acc[mt]);
+    }
+  }
+  const int j = 16 * wave + (lane & 15);
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = mt * 16 + Mfma<TC>::row(lane, r);
+      if (i < M && j < N) out[i * N + j] = acc[mt][r];
+    }
+}
+
 // GRAM: t2 is the u<->d view of t1 and B is A (the Gram step of the boundary
 // compression); each is then staged once.
 // b-block of a fused step: the Gram step of the compression over float64
@@ -136,14 +172,29 @@ __device__ void env4_fused(TC* __restrict__ Lout, const TC* __restrict__ Lin, co
                            const TB* __restrict__ B, S3 sB, char* lds) {
   using Sh = Env4Shape<D, C, env4_bb<TC, TB, D, C, GRAM>()>;
   constexpr int BB = Sh::BB, NBLK = Sh::NBLK, N4 = Sh::N4, NT4 = Sh::NT4, T4W = Sh::T4W;
+  constexpr bool REGT = Sh::template regt<GRAM, BF16>();
+  constexpr int KS = (D * D + 3) / 4;
   TB* As = reinterpret_cast<TB*>(lds);
   TB* Bs = GRAM ? As : As + Sh::SA;
   TB* T1s = Bs + (GRAM ? 0 : Sh::SA) + (GRAM ? Sh::SA : 0);
   TB* T2s = GRAM ? T1s : T1s + Sh::ST;
-  TC* Ls = reinterpret_cast<TC*>(T2s + Sh::ST);
+  TC* Ls = reinterpret_cast<TC*>(REGT ? T1s : T2s + Sh::ST);
   TC* X1 = Ls + Sh::SL;  // X1 and X3
   TC* X2 = X1 + Sh::SX;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+
+  // this wave's B fragments of S2 (t1) and S3 (t2), read once from global memory
+  TC f1[REGT ? KS : 1], f2[REGT ? KS : 1];
+  if constexpr (REGT) {
+    const int j = 16 * wave + (lane & 15), r = j / D, dq = j % D;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const int k = 4 * s + (lane >> 4), l = k / D, u = k % D;
+      const bool ok = j < D * D && k < D * D;
+      f1[s] = ok ? (TC)t1[l * s1.l + u * s1.u + r * s1.r + dq * s1.d] : TC(0);
+      f2[s] = ok ? (TC)t2[l * s2.l + u * s2.u + r * s2.r + dq * s2.d] : TC(0);
+    }
+  }
 
   // stage the column tensors in canonical leg order
   for (int e = tid; e < Sh::SA; e += WG) {
@@ -151,13 +202,26 @@ __device__ void env4_fused(TC* __restrict__ Lout, const TC* __restrict__ Lin, co
     As[e] = A[p * sA.s0 + q * sA.s1 + r * sA.s2];
     if (!GRAM) Bs[e] = B[p * sB.s0 + q * sB.s1 + r * sB.s2];
   }
-  for (int e = tid; e < Sh::ST; e += WG) {
-    const int l = e / (D * D * D), u = (e / (D * D)) % D, r = (e / D) % D, d = e % D;
-    T1s[e] = t1[l * s1.l + u * s1.u + r * s1.r + d * s1.d];
-    if (!GRAM) T2s[e] = t2[l * s2.l + u * s2.u + r * s2.r + d * s2.d];
-  }
+  if constexpr (!REGT)
+    for (int e = tid; e < Sh::ST; e += WG) {
+      const int l = e / (D * D * D), u = (e / (D * D)) % D, r = (e / D) % D, d = e % D;
+      T1s[e] = t1[l * s1.l + u * s1.u + r * s1.r + d * s1.d];
+      if (!GRAM) T2s[e] = t2[l * s2.l + u * s2.u + r * s2.r + d * s2.d];
+    }
 
-  // b-blocks outer, lower-bond slices inner: only one block's accumulators are live
+  // b-blocks outer, lower-bond slices inner: only one block's accumulators are
+  // live.  Each slice of Lin is fetched one slice ahead into registers, so its
+  // global-memory latency overlaps the previous slice's products.
+  constexpr int NPF = (Sh::SL + WG - 1) / WG;
+  TC pre[NPF];
+  auto fetch = [&](int cs) {
+#pragma unroll
+    for (int u = 0; u < NPF; ++u) {
+      const int e = tid + u * WG;
+      pre[u] = e < Sh::SL ? Lin[cs * Sh::SL + e] : TC(0);
+    }
+  };
+  fetch(0);
   for (int q = 0; q < NBLK; ++q) {
     const int b0 = q * BB;
     typename Acc<TC, BF16>::type acc[T4W];
@@ -165,7 +229,13 @@ __device__ void env4_fused(TC* __restrict__ Lout, const TC* __restrict__ Lin, co
     for (int w = 0; w < T4W; ++w) acc[w] = {0, 0, 0, 0};
     for (int cs = 0; cs < C; ++cs) {
       __syncthreads();  // previous slice done with Ls / X buffers
-      for (int e = tid; e < Sh::SL; e += WG) Ls[e] = Lin[cs * Sh::SL + e];
+#pragma unroll
+      for (int u = 0; u < NPF; ++u) {
+        const int e = tid + u * WG;
+        if (e < Sh::SL) Ls[e] = pre[u];
+      }
+      if (cs + 1 < C) fetch(cs + 1);
+      else if (q + 1 < NBLK) fetch(0);
       __syncthreads();
       // S1: X1[(l1,l2)][(u,bb)] = sum_a Ls[a][(l1,l2)] As[a][u][b0+bb]
       mfma_stage<TC, D * D, D * BB, C, BF16>(
@@ -173,24 +243,22 @@ __device__ void env4_fused(TC* __restrict__ Lout, const TC* __restrict__ Lin, co
           [&](int k, int j) { return (TC)As[k * D * C + (j / BB) * C + b0 + j % BB]; });
       __syncthreads();
       // S2: X2[(l2,bb)][(r1,m)] = sum_{l1,u} X1[l1][l2][u][bb] T1s[(l1,u)][(r1,m)]
-      mfma_stage<TC, D * BB, D * D, D * D, BF16>(
-          X2,
-          [&](int i, int k) {
-            return X1[(k / D) * D * D * BB + (i / BB) * D * BB + (k % D) * BB + i % BB];
-          },
-          [&](int k, int j) { return (TC)T1s[k * D * D + j]; });
+      auto fa2 = [&](int i, int k) {
+        return X1[(k / D) * D * D * BB + (i / BB) * D * BB + (k % D) * BB + i % BB];
+      };
+      if constexpr (REGT) mfma_stage_regb<TC, D * BB, D * D, D * D>(X2, fa2, f1);
+      else
+        mfma_stage<TC, D * BB, D * D, D * D, BF16>(X2, fa2, [&](int k, int j) { return (TC)T1s[k * D * D + j]; });
       __syncthreads();
       // S3: X3[(bb,r1)][(r2,dd)] = sum_{l2,m} X2[l2][bb][r1][m] T2s[(l2,m)][(r2,dd)]
-      mfma_stage<TC, BB * D, D * D, D * D, BF16>(
-          X1,
-          [&](int i, int k) {
-            return X2[(((k / D) * BB + i / D) * D + i % D) * D + k % D];
-          },
-          [&](int k, int j) {
-            // GRAM: t2[l2][m][r2][dd] = t1[l2][dd][r2][m]
-            return GRAM ? (TC)T1s[(k / D) * D * D * D + (j % D) * D * D + (j / D) * D + k % D]
-                        : (TC)T2s[k * D * D + j];
-          });
+      auto fa3 = [&](int i, int k) { return X2[(((k / D) * BB + i / D) * D + i % D) * D + k % D]; };
+      if constexpr (REGT) mfma_stage_regb<TC, BB * D, D * D, D * D>(X1, fa3, f2);
+      else
+        mfma_stage<TC, BB * D, D * D, D * D, BF16>(X1, fa3, [&](int k, int j) {
+          // GRAM: t2[l2][m][r2][dd] = t1[l2][dd][r2][m]
+          return GRAM ? (TC)T1s[(k / D) * D * D * D + (j % D) * D * D + (j / D) * D + k % D]
+                      : (TC)T2s[k * D * D + j];
+        });
       __syncthreads();
       // S4: acc[e][(bb,r1,r2)] += sum_dd Bs[cs][dd][e] X3[(bb,r1,r2)][dd]
 #pragma unroll

@@ -107,6 +107,19 @@ __device__ void env4_bf16(TS* __restrict__ Lout, const TS* __restrict__ Lin, con
   }
   for (int e = tid; e < S::nX1 + S::nX2 + S::nX3; e += WG) X1[e] = zero;
 
+  // lower-bond slices of Lin are fetched one slice ahead into registers, so
+  // their global-memory latency overlaps the previous slice's products
+  constexpr int NPF = (S::nLs + WG - 1) / WG;
+  float pre[NPF];
+  auto fetch = [&](int cs) {
+#pragma unroll
+    for (int u = 0; u < NPF; ++u) {
+      const int e = tid + u * WG;
+      const int row = e / S::P1, a = e - row * S::P1;  // row = (l1, l2)
+      pre[u] = (e < S::nLs && a < C) ? (float)Lin[(cs * C + a) * (D * D) + row] : 0.0f;
+    }
+  };
+  fetch(0);
   for (int q = 0; q < S::NBLK; ++q) {
     const int b0 = q * BB;
     v4f_e acc[S::T4W];
@@ -114,10 +127,13 @@ __device__ void env4_bf16(TS* __restrict__ Lout, const TS* __restrict__ Lin, con
     for (int w = 0; w < S::T4W; ++w) acc[w] = {0, 0, 0, 0};
     for (int cs = 0; cs < C; ++cs) {
       __syncthreads();  // previous slice done with Ls / X buffers (and the staging above)
-      for (int e = tid; e < S::nLs; e += WG) {
-        const int row = e / S::P1, a = e - row * S::P1;  // row = (l1, l2)
-        Ls[e] = a < C ? (__bf16)(float)Lin[(cs * C + a) * (D * D) + row] : zero;
+#pragma unroll
+      for (int u = 0; u < NPF; ++u) {
+        const int e = tid + u * WG;
+        if (e < S::nLs) Ls[e] = (__bf16)pre[u];
       }
+      if (cs + 1 < C) fetch(cs + 1);
+      else if (q + 1 < S::NBLK) fetch(0);
       __syncthreads();
       // S1: X1[(l2,bb)][(l1,u)] = sum_a Ls[(l1,l2)][a] AT[(u, b0+bb)][a]; M = D^2, N = D BB
       {

@@ -553,7 +553,8 @@ __device__ __forceinline__ void ph_measure3(const LatDev& L, int ch, int y, cons
     if (threadIdx.x == 0) eR[x] = eR[x + 1] + e;
     __syncthreads();
   }
-  for (int x = 0; x < Lx; ++x) {
+  // left environments Le[1..max(Lx-1,1)]; Le[Lx] of a wider row is never needed
+  for (int x = 0; x < (Lx > 1 ? Lx - 1 : 1); ++x) {
     int e = step3<T>(L, C, Le + (int64_t)(x + 1) * sz, Le + (int64_t)x * sz, y, x, 0, ub<T>(L, C, y, x),
                      db<T>(L, C, y + 1, x), false, tiles);
     if (threadIdx.x == 0) eL[x + 1] = eL[x] + e;
@@ -629,7 +630,8 @@ __device__ __forceinline__ void ph_measure4(const LatDev& L, int ch, int y, cons
     if (threadIdx.x == 0) eR[x] = eR[x + 1] + e;
     __syncthreads();
   }
-  for (int x = 0; x < Lx; ++x) {
+  // left environments Le[1..max(Lx-1,1)]; Le[Lx] of a wider row pair is never needed
+  for (int x = 0; x < (Lx > 1 ? Lx - 1 : 1); ++x) {
     int e = step4<T, DD, CC>(L, C, Le + (int64_t)(x + 1) * sz, Le + (int64_t)x * sz, y, x, 0, 0, ub<T>(L, C, y, x),
                      db<T>(L, C, y + 2, x), false, lds);
     if (threadIdx.x == 0) eL[x + 1] = eL[x] + e;
@@ -718,12 +720,12 @@ constexpr size_t step4_lds() {
 }
 
 template <typename T, int DD, int CC, bool BF16>
-__global__ void __launch_bounds__(WG) k_row4_right(LatDev L, int y) {
+__global__ void __launch_bounds__(WG, 2) k_row4_right(LatDev L, int y) {
   __shared__ __attribute__((aligned(16))) char lds[step4_lds<T, DD, CC, BF16>()];
   ph_row4_right<T, DD, CC, BF16>(L, blockIdx.x, y, lds);
 }
 template <typename T, int DD, int CC, bool BF16, bool LEARN>
-__global__ void __launch_bounds__(WG) k_vsweep(LatDev L, int y) {
+__global__ void __launch_bounds__(WG, 2) k_vsweep(LatDev L, int y) {
   __shared__ __attribute__((aligned(16)))
   char lds[cmax(step4_lds<T, DD, CC, BF16>(), LEARN ? net_lds_bytes<T>() : 0)];
   ph_vsweep<T, DD, CC, BF16, LEARN>(L, blockIdx.x, y, lds);
@@ -738,7 +740,7 @@ __global__ void __launch_bounds__(WG) k_measure3(LatDev L, int y, SampleOut o) {
   ph_measure3<T>(L, blockIdx.x, y, o, gemm_tiles());
 }
 template <typename T, int DD, int CC>
-__global__ void __launch_bounds__(WG) k_measure4(LatDev L, int y, SampleOut o) {
+__global__ void __launch_bounds__(WG, 2) k_measure4(LatDev L, int y, SampleOut o) {
   __shared__ __attribute__((aligned(16))) char lds[env4_lds<T, T, DD, CC>()];
   ph_measure4<T, DD, CC>(L, blockIdx.x, y, o, lds);
 }

@@ -38,6 +38,7 @@ def _compare(g, o, N, tol_e, tol_lp, tol_rel):
     (6, 6, 3, 7, 0.5, 3),     # ragged GEMM tiles (D*Dc = 21, Dc^2*D = 147)
     (2, 6, 2, 3, 0.0, 3),     # two rows: no bulk row
     (1, 4, 3, 2, 0.0, 2),     # a single row: no vertical pairs
+    (4, 1, 3, 2, 0.0, 2),     # a single column: no horizontal pairs
     (6, 6, 4, 8, 0.5, 2),     # fused MFMA 2-row step, D=4 Dc=8
     (4, 4, 6, 12, 0.0, 2),    # fused MFMA 2-row step, D=6 Dc=12 (padded 16x16 tiles)
     (4, 4, 8, 16, 0.5, 2),    # fused MFMA 2-row step, D=8 Dc=16
