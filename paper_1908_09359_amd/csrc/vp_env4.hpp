@@ -51,10 +51,11 @@ struct Env4Shape {
   // output columns of those stages span exactly four 16-column tiles, wave w
   // always owns tile w, so its B operand is fixed for the whole step.
   template <bool GRAM = false, bool BF16 = false>
-  static constexpr bool regt() { return !GRAM && !BF16 && (D * D + 15) / 16 == 4; }
+  static constexpr bool regt() { return !BF16 && (D * D + 15) / 16 == 4; }
   template <typename TC, typename TB, bool GRAM = false>
   static constexpr size_t lds_bytes() {
-    return sizeof(TB) * (GRAM ? SA + ST : 2 * SA + (regt<GRAM>() ? 0 : 2 * ST)) + sizeof(TC) * (SL + 2 * SX);
+    return sizeof(TB) * (GRAM ? SA : 2 * SA) + (regt<GRAM>() ? 0 : sizeof(TB) * (GRAM ? ST : 2 * ST)) +
+           sizeof(TC) * (SL + 2 * SX);
   }
 };
 
@@ -162,9 +163,12 @@ __device__ inline void mfma_stage_regb(TC* out, FA fa, const TC (&f)[(K + 3) / 4
 // GRAM: t2 is the u<->d view of t1 and B is A (the Gram step of the boundary
 // compression); each is then staged once.
 // b-block of a fused step: the Gram step of the compression over float64
-// tensors takes C/8 so that its LDS stays within two work-groups per CU.
+// tensors staged in LDS takes C/8 so that its LDS stays within two work-groups
+// per CU.
 template <typename TC, typename TB, int D, int C, bool GRAM>
-constexpr int env4_bb() { return (GRAM && sizeof(TB) == 8 && C % 8 == 0) ? C / 8 : 0; }
+constexpr int env4_bb() {
+  return (GRAM && sizeof(TB) == 8 && C % 8 == 0 && (D * D + 15) / 16 != 4) ? C / 8 : 0;
+}
 
 template <typename TC, typename TB, int D, int C, bool GRAM = false, bool BF16 = false>
 __device__ void env4_fused(TC* __restrict__ Lout, const TC* __restrict__ Lin, const TB* __restrict__ A, S3 sA,
@@ -183,7 +187,8 @@ __device__ void env4_fused(TC* __restrict__ Lout, const TC* __restrict__ Lin, co
   TC* X2 = X1 + Sh::SX;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
 
-  // this wave's B fragments of S2 (t1) and S3 (t2), read once from global memory
+  // this wave's B fragments of S2 (t1) and S3 (t2; for GRAM the u<->d view of
+  // t1), read once from global memory
   TC f1[REGT ? KS : 1], f2[REGT ? KS : 1];
   if constexpr (REGT) {
     const int j = 16 * wave + (lane & 15), r = j / D, dq = j % D;
