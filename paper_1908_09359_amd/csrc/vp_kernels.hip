@@ -6,6 +6,7 @@
 #include "vp_eig.hpp"
 #include "vp_env4.hpp"
 #include "vp_env4bf.hpp"
+#include "vp_env3.hpp"
 #include "vp_kernels.hpp"
 #include "vp_net.hpp"
 
@@ -80,13 +81,27 @@ __device__ inline int64_t meas_index(const SampleOut& o, const ChainMeta* m) {
   return o.dyn_m ? m->sweep - o.sweep0 : (int64_t)o.m;
 }
 
-// 3-line column step with optional flipped site: t = T[s ^ flip].
-template <typename T, bool BF16 = false>
+// 3-line column step with optional flipped site: t = T[s ^ flip].  (DD, CC)
+// with DD*DD = 64 and DD*CC = 128 select the fused MFMA step (working
+// precision); otherwise the generic strided-GEMM step runs.
+template <typename T, int DD, int CC>
+constexpr bool fused3() {
+  if constexpr (DD > 0) return Env3Shape<DD, CC>::ok;
+  else return false;
+}
+template <typename T, int DD, int CC, bool BF16 = false>
 __device__ inline int step3(const LatDev& L, const Chain<T>& C, T* out, const T* in, int y, int x,
                             int flip, const T* Ux, const T* Dx, bool right, char* tiles) {
   int k = y * L.Lx + x;
   const T* t = tw<T>(L, k, C.sp[k] ^ flip);
   S4 st = st_std(L.d);
+  if constexpr (fused3<T, DD, CC>() && !BF16) {
+    if (right)
+      env3_fused<T, DD, CC>(out, in, Ux, sb_mirror(CC, DD), t, st_mirror(st), Dx, sb_mirror(CC, DD), tiles);
+    else
+      env3_fused<T, DD, CC>(out, in, Ux, sb_std(CC, DD), t, st, Dx, sb_std(CC, DD), tiles);
+    return wg_renorm<T>(out, CC * DD * CC);
+  }
   if (right)
     env3_step<T, BF16>(out, in, Ux, sb_mirror(L.c, L.d), t, st_mirror(st), Dx, sb_mirror(L.c, L.d),
                        C.ws + L.oX0, C.ws + L.oX1, L.c, L.d, tiles);
@@ -94,6 +109,19 @@ __device__ inline int step3(const LatDev& L, const Chain<T>& C, T* out, const T*
     env3_step<T, BF16>(out, in, Ux, sb_std(L.c, L.d), t, st, Dx, sb_std(L.c, L.d), C.ws + L.oX0,
                        C.ws + L.oX1, L.c, L.d, tiles);
   return wg_renorm<T>(out, e3sz(L));
+}
+
+// LDS bytes of a kernel's 3-line column steps (and, with defects, its defect tensors).
+template <typename T, int DD, int CC, bool BF16, bool DEFECT = false>
+constexpr size_t step3_lds() {
+  if constexpr (DD > 0 && !BF16) {
+    if constexpr (Env3Shape<DD, CC>::ok) {
+      constexpr size_t a = Env3Shape<DD, CC>::template lds_bytes<T>();
+      constexpr size_t b = DEFECT ? Env3Shape<DD, CC>::template defect_lds_bytes<T>() : 0;
+      return a > b ? a : b;
+    }
+  }
+  return GEMM_TILE_BYTES;
 }
 
 // LDS bytes a kernel provides for its 2-row column steps.
@@ -168,7 +196,7 @@ __global__ void __launch_bounds__(WG) k_init_trivial(LatDev L) {
 }
 
 // R3[x] = R(x) for x = Lx-1 .. 1 of the network <D|row y|U>; R3[Lx] = ones.
-template <typename T, bool BF16>
+template <typename T, int DD, int CC, bool BF16>
 __device__ __forceinline__ void ph_row3_right(const LatDev& L, int ch, int y, int ub_slot, int db_slot, char* tiles) {
   Chain<T> C = chain_of<T>(L, ch);
   const int sz = e3sz(L);
@@ -177,7 +205,7 @@ __device__ __forceinline__ void ph_row3_right(const LatDev& L, int ch, int y, in
   set_unit<T>(R + (int64_t)L.Lx * sz, sz);
   if (threadIdx.x == 0) eR[L.Lx] = 0;
   for (int x = L.Lx - 1; x >= 1; --x) {
-    int e = step3<T, BF16>(L, C, R + (int64_t)x * sz, R + (int64_t)(x + 1) * sz, y, x, 0,
+    int e = step3<T, DD, CC, BF16>(L, C, R + (int64_t)x * sz, R + (int64_t)(x + 1) * sz, y, x, 0,
                            ub<T>(L, C, ub_slot, x), db<T>(L, C, db_slot, x), true, tiles);
     if (threadIdx.x == 0) eR[x] = eR[x + 1] + e;
     __syncthreads();
@@ -219,7 +247,7 @@ __device__ inline void trace_skip(const LatDev& L, int ch, int bond) {
 
 // Horizontal bonds of row y, left to right (Sec. II.A Eq. (9)).  With moves = 0
 // no move is attempted.  For the last row the full amplitude is produced.
-template <typename T, bool BF16>
+template <typename T, int DD, int CC, bool BF16>
 __device__ __forceinline__ void ph_hsweep(const LatDev& L, int ch, int y, int last_row, int moves, char* tiles) {
   Chain<T> C = chain_of<T>(L, ch);
   if (C.meta->flags) return;
@@ -235,15 +263,15 @@ __device__ __forceinline__ void ph_hsweep(const LatDev& L, int ch, int y, int la
     const T* Dx = db<T>(L, C, y + 1, x);
     T* cur = tmp + slot[0] * sz;
     T* nxt = tmp + slot[1] * sz;
-    int enxt = ecur + step3<T, BF16>(L, C, nxt, cur, y, x, 0, Ux, Dx, false, tiles);
+    int enxt = ecur + step3<T, DD, CC, BF16>(L, C, nxt, cur, y, x, 0, Ux, Dx, false, tiles);
     const int k = y * L.Lx + x;
     bool acc = false;
     if (moves && C.sp[k] == C.sp[k + 1]) trace_skip(L, C.id, y * (2 * L.Lx - 1) + x);
     if (moves && C.sp[k] != C.sp[k + 1]) {
       T* f1 = tmp + slot[2] * sz;
       T* f2 = tmp + slot[3] * sz;
-      int ef1 = ecur + step3<T, BF16>(L, C, f1, cur, y, x, 1, Ux, Dx, false, tiles);
-      int ef2 = ef1 + step3<T, BF16>(L, C, f2, f1, y, x + 1, 1, ub<T>(L, C, y, x + 1),
+      int ef1 = ecur + step3<T, DD, CC, BF16>(L, C, f1, cur, y, x, 1, Ux, Dx, false, tiles);
+      int ef2 = ef1 + step3<T, DD, CC, BF16>(L, C, f2, f1, y, x + 1, 1, ub<T>(L, C, y, x + 1),
                                      db<T>(L, C, y + 1, x + 1), false, tiles);
       double num = wg_dot<T>(f2, R + (int64_t)(x + 2) * sz, sz);
       double den = wg_dot<T>(nxt, R + (int64_t)(x + 1) * sz, sz);
@@ -271,7 +299,7 @@ __device__ __forceinline__ void ph_hsweep(const LatDev& L, int ch, int y, int la
     const int x = L.Lx - 1;
     T* cur = tmp + slot[0] * sz;
     T* nxt = tmp + slot[1] * sz;
-    int e = ecur + step3<T, BF16>(L, C, nxt, cur, y, x, 0, ub<T>(L, C, y, x), db<T>(L, C, y + 1, x), false,
+    int e = ecur + step3<T, DD, CC, BF16>(L, C, nxt, cur, y, x, 0, ub<T>(L, C, y, x), db<T>(L, C, y + 1, x), false,
                                   tiles);
     double v = (double)nxt[0];
     if (threadIdx.x == 0) {
@@ -533,7 +561,7 @@ __device__ __forceinline__ void ph_compress(const LatDev& L, int ch, int y, int 
 
 // Measurement of row y (App. C): log-derivatives of its sites and its
 // horizontal pair ratios, all from the cached left/right auxiliary tensors.
-template <typename T>
+template <typename T, int DD, int CC>
 __device__ __forceinline__ void ph_measure3(const LatDev& L, int ch, int y, const SampleOut& o, char* tiles) {
   Chain<T> C = chain_of<T>(L, ch);
   if (C.meta->flags) return;
@@ -548,14 +576,14 @@ __device__ __forceinline__ void ph_measure3(const LatDev& L, int ch, int y, cons
   if (threadIdx.x == 0) { eR[Lx] = 0; eL[0] = 0; }
   __syncthreads();
   for (int x = Lx - 1; x >= 1; --x) {
-    int e = step3<T>(L, C, R + (int64_t)x * sz, R + (int64_t)(x + 1) * sz, y, x, 0, ub<T>(L, C, y, x),
+    int e = step3<T, DD, CC>(L, C, R + (int64_t)x * sz, R + (int64_t)(x + 1) * sz, y, x, 0, ub<T>(L, C, y, x),
                      db<T>(L, C, y + 1, x), true, tiles);
     if (threadIdx.x == 0) eR[x] = eR[x + 1] + e;
     __syncthreads();
   }
   // left environments Le[1..max(Lx-1,1)]; Le[Lx] of a wider row is never needed
   for (int x = 0; x < (Lx > 1 ? Lx - 1 : 1); ++x) {
-    int e = step3<T>(L, C, Le + (int64_t)(x + 1) * sz, Le + (int64_t)x * sz, y, x, 0, ub<T>(L, C, y, x),
+    int e = step3<T, DD, CC>(L, C, Le + (int64_t)(x + 1) * sz, Le + (int64_t)x * sz, y, x, 0, ub<T>(L, C, y, x),
                      db<T>(L, C, y + 1, x), false, tiles);
     if (threadIdx.x == 0) eL[x + 1] = eL[x] + e;
     __syncthreads();
@@ -572,8 +600,12 @@ __device__ __forceinline__ void ph_measure3(const LatDev& L, int ch, int y, cons
     T* Dl = C.ws + L.oDl;
     for (int x = 0; x < Lx; ++x) {
       const int k = y * Lx + x;
-      defect3<T>(Dl, Le + (int64_t)x * sz, ub<T>(L, C, y, x), sb_std(L.c, d), R + (int64_t)(x + 1) * sz,
-                 db<T>(L, C, y + 1, x), sb_std(L.c, d), C.ws + L.oX0, C.ws + L.oX1, L.c, d, tiles);
+      if constexpr (fused3<T, DD, CC>())
+        defect3_fused<T, DD, CC>(Dl, Le + (int64_t)x * sz, ub<T>(L, C, y, x), sb_std(CC, DD),
+                                 R + (int64_t)(x + 1) * sz, db<T>(L, C, y + 1, x), sb_std(CC, DD), tiles);
+      else
+        defect3<T>(Dl, Le + (int64_t)x * sz, ub<T>(L, C, y, x), sb_std(L.c, d), R + (int64_t)(x + 1) * sz,
+                   db<T>(L, C, y + 1, x), sb_std(L.c, d), C.ws + L.oX0, C.ws + L.oX1, L.c, d, tiles);
       const double f = ldexp(1.0 / Nm, eL[x] + eR[x + 1] - eN);
       const int dl = L.dims[4 * k], du = L.dims[4 * k + 1], dr = L.dims[4 * k + 2], dd = L.dims[4 * k + 3];
       const int n = dl * du * dr * dd;
@@ -593,9 +625,9 @@ __device__ __forceinline__ void ph_measure3(const LatDev& L, int ch, int y, cons
     if (C.sp[k] == C.sp[k + 1]) {
       eacc += 0.25 * L.J1;
     } else {
-      int e1 = eL[x] + step3<T>(L, C, tmp, Le + (int64_t)x * sz, y, x, 1, ub<T>(L, C, y, x), db<T>(L, C, y + 1, x),
+      int e1 = eL[x] + step3<T, DD, CC>(L, C, tmp, Le + (int64_t)x * sz, y, x, 1, ub<T>(L, C, y, x), db<T>(L, C, y + 1, x),
                                 false, tiles);
-      int e2 = e1 + step3<T>(L, C, tmp + sz, tmp, y, x + 1, 1, ub<T>(L, C, y, x + 1), db<T>(L, C, y + 1, x + 1),
+      int e2 = e1 + step3<T, DD, CC>(L, C, tmp + sz, tmp, y, x + 1, 1, ub<T>(L, C, y, x + 1), db<T>(L, C, y + 1, x + 1),
                              false, tiles);
       double num = wg_dot<T>(tmp + sz, R + (int64_t)(x + 2) * sz, sz);
       rho = ldexp(num / Nm, e2 + eR[x + 2] - eN);
@@ -704,13 +736,15 @@ __device__ __forceinline__ void ph_measure4(const LatDev& L, int ch, int y, cons
 }
 
 // Wrappers: one work-group per chain, one phase of one row.
-template <typename T, bool BF16>
-__global__ void __launch_bounds__(WG) k_row3_right(LatDev L, int y, int ub_slot, int db_slot) {
-  ph_row3_right<T, BF16>(L, blockIdx.x, y, ub_slot, db_slot, gemm_tiles());
+template <typename T, int DD, int CC, bool BF16>
+__global__ void __launch_bounds__(WG, 2) k_row3_right(LatDev L, int y, int ub_slot, int db_slot) {
+  __shared__ __attribute__((aligned(16))) char lds[step3_lds<T, DD, CC, BF16>()];
+  ph_row3_right<T, DD, CC, BF16>(L, blockIdx.x, y, ub_slot, db_slot, lds);
 }
-template <typename T, bool BF16>
-__global__ void __launch_bounds__(WG) k_hsweep(LatDev L, int y, int last_row, int moves) {
-  ph_hsweep<T, BF16>(L, blockIdx.x, y, last_row, moves, gemm_tiles());
+template <typename T, int DD, int CC, bool BF16>
+__global__ void __launch_bounds__(WG, 2) k_hsweep(LatDev L, int y, int last_row, int moves) {
+  __shared__ __attribute__((aligned(16))) char lds[step3_lds<T, DD, CC, BF16>()];
+  ph_hsweep<T, DD, CC, BF16>(L, blockIdx.x, y, last_row, moves, lds);
 }
 // LDS of a 2-row step: the bf16 step stages compact bf16 operands.
 template <typename T, int DD, int CC, bool BF16>
@@ -735,9 +769,10 @@ __global__ void __launch_bounds__(WG, 2) k_compress(LatDev L, int y, int upper) 
   __shared__ __attribute__((aligned(16))) char lds[compress_lds<T, DD, CC>()];
   ph_compress<T, DD, CC>(L, blockIdx.x, y, upper, lds);
 }
-template <typename T>
-__global__ void __launch_bounds__(WG) k_measure3(LatDev L, int y, SampleOut o) {
-  ph_measure3<T>(L, blockIdx.x, y, o, gemm_tiles());
+template <typename T, int DD, int CC>
+__global__ void __launch_bounds__(WG, 2) k_measure3(LatDev L, int y, SampleOut o) {
+  __shared__ __attribute__((aligned(16))) char lds[step3_lds<T, DD, CC, false, true>()];
+  ph_measure3<T, DD, CC>(L, blockIdx.x, y, o, lds);
 }
 template <typename T, int DD, int CC>
 __global__ void __launch_bounds__(WG, 2) k_measure4(LatDev L, int y, SampleOut o) {
@@ -780,18 +815,19 @@ __global__ void k_next_sweep(LatDev L) {
 // ---------------------------------------------------------------------------
 template <typename T, int DD, int CC>
 constexpr size_t sweep_lds() {
-  return cmax(cmax(env4_lds<T, T, DD, CC>(), compress_lds<T, DD, CC>()), net_lds_bytes<T>());
+  return cmax(cmax(cmax(env4_lds<T, T, DD, CC>(), compress_lds<T, DD, CC>()), net_lds_bytes<T>()),
+              step3_lds<T, DD, CC, false, true>());
 }
 
 // Out-of-line phases of the persistent kernel: each keeps its own register
 // allocation instead of the union of all phases.
-template <typename T, bool BF16>
+template <typename T, int DD, int CC, bool BF16>
 __device__ __noinline__ void nl_row3_right(const LatDev& L, int ch, int y, char* lds) {
-  ph_row3_right<T, BF16>(L, ch, y, y, y + 1, lds);
+  ph_row3_right<T, DD, CC, BF16>(L, ch, y, y, y + 1, lds);
 }
-template <typename T, bool BF16>
+template <typename T, int DD, int CC, bool BF16>
 __device__ __noinline__ void nl_hsweep(const LatDev& L, int ch, int y, char* lds) {
-  ph_hsweep<T, BF16>(L, ch, y, y == L.Ly - 1, 1, lds);
+  ph_hsweep<T, DD, CC, BF16>(L, ch, y, y == L.Ly - 1, 1, lds);
 }
 template <typename T, int DD, int CC, bool BF16>
 __device__ __noinline__ void nl_row4_right(const LatDev& L, int ch, int y, char* lds) {
@@ -805,9 +841,9 @@ template <typename T, int DD, int CC>
 __device__ __noinline__ void nl_compress(const LatDev& L, int ch, int y, int upper, char* lds) {
   ph_compress<T, DD, CC>(L, ch, y, upper, lds);
 }
-template <typename T>
+template <typename T, int DD, int CC>
 __device__ __noinline__ void nl_measure3(const LatDev& L, int ch, int y, const SampleOut& o, char* lds) {
-  ph_measure3<T>(L, ch, y, o, lds);
+  ph_measure3<T, DD, CC>(L, ch, y, o, lds);
 }
 template <typename T, int DD, int CC>
 __device__ __noinline__ void nl_measure4(const LatDev& L, int ch, int y, const SampleOut& o, char* lds) {
@@ -818,9 +854,9 @@ template <typename T, int DD, int CC, bool BF16>
 __device__ void chain_sweep(const LatDev& L, int ch, const SampleOut* o, char* lds) {
   const int Ly = L.Ly;
   for (int y = 0; y < Ly; ++y) {
-    nl_row3_right<T, BF16>(L, ch, y, lds);
+    nl_row3_right<T, DD, CC, BF16>(L, ch, y, lds);
     __syncthreads();
-    nl_hsweep<T, BF16>(L, ch, y, lds);
+    nl_hsweep<T, DD, CC, BF16>(L, ch, y, lds);
     __syncthreads();
     if (y < Ly - 1) {
       nl_row4_right<T, DD, CC, BF16>(L, ch, y, lds);
@@ -837,7 +873,7 @@ __device__ void chain_sweep(const LatDev& L, int ch, const SampleOut* o, char* l
   __syncthreads();
   for (int y = Ly - 1; y >= 0; --y) {
     if (o) {
-      nl_measure3<T>(L, ch, y, *o, lds);
+      nl_measure3<T, DD, CC>(L, ch, y, *o, lds);
       __syncthreads();
       if (y < Ly - 1) {
         nl_measure4<T, DD, CC>(L, ch, y, *o, lds);
@@ -984,30 +1020,6 @@ template <typename T>
 void launch_init_trivial(const LatDev& L, hipStream_t s) {
   hipLaunchKernelGGL(k_init_trivial<T>, dim3(L.n_chains), dim3(WG), 0, s, L);
 }
-template <typename T>
-void launch_row3_right(const LatDev& L, int y, int ub_slot, int db_slot, bool bf16, hipStream_t s) {
-  if constexpr (sizeof(T) == 8) {
-    if (bf16) {
-      hipLaunchKernelGGL((k_row3_right<T, true>), dim3(L.n_chains), dim3(WG), 0, s, L, y, ub_slot, db_slot);
-      return;
-    }
-  }
-  hipLaunchKernelGGL((k_row3_right<T, false>), dim3(L.n_chains), dim3(WG), 0, s, L, y, ub_slot, db_slot);
-}
-template <typename T>
-void launch_hsweep(const LatDev& L, int y, int last_row, bool bf16, hipStream_t s) {
-  if constexpr (sizeof(T) == 8) {
-    if (bf16) {
-      hipLaunchKernelGGL((k_hsweep<T, true>), dim3(L.n_chains), dim3(WG), 0, s, L, y, last_row, 1);
-      return;
-    }
-  }
-  hipLaunchKernelGGL((k_hsweep<T, false>), dim3(L.n_chains), dim3(WG), 0, s, L, y, last_row, 1);
-}
-template <typename T>
-void launch_psi_fixed(const LatDev& L, hipStream_t s) {
-  hipLaunchKernelGGL((k_hsweep<T, false>), dim3(L.n_chains), dim3(WG), 0, s, L, L.Ly - 1, 1, 0);
-}
 // Compile-time (D, Dc) instantiations of the fused 2-row step; other shapes run the generic path.
 #define VP_DISPATCH_DC(KERNEL, T, ...)                                                                 \
   do {                                                                                                 \
@@ -1034,6 +1046,25 @@ void launch_psi_fixed(const LatDev& L, hipStream_t s) {
       hipLaunchKernelGGL((KERNEL<T, 0, 0, BF>), dim3(L.n_chains), dim3(WG), 0, s, __VA_ARGS__);        \
   } while (0)
 
+template <typename T>
+void launch_row3_right(const LatDev& L, int y, int ub_slot, int db_slot, bool bf16, hipStream_t s) {
+  if constexpr (sizeof(T) == 8) {
+    if (bf16) { VP_DISPATCH_DC_BF(k_row3_right, T, true, L, y, ub_slot, db_slot); return; }
+  }
+  VP_DISPATCH_DC_BF(k_row3_right, T, false, L, y, ub_slot, db_slot);
+}
+template <typename T>
+void launch_hsweep(const LatDev& L, int y, int last_row, bool bf16, hipStream_t s) {
+  if constexpr (sizeof(T) == 8) {
+    if (bf16) { VP_DISPATCH_DC_BF(k_hsweep, T, true, L, y, last_row, 1); return; }
+  }
+  VP_DISPATCH_DC_BF(k_hsweep, T, false, L, y, last_row, 1);
+}
+template <typename T>
+void launch_psi_fixed(const LatDev& L, hipStream_t s) {
+  const int y = L.Ly - 1;
+  VP_DISPATCH_DC_BF(k_hsweep, T, false, L, y, 1, 0);
+}
 // bf16 operands are taken from float64 storage (VP_BF16 works in float64).
 template <typename T>
 void launch_row4_right(const LatDev& L, int y, bool bf16, hipStream_t s) {
@@ -1071,7 +1102,7 @@ void launch_compress(const LatDev& L, int y, int upper, hipStream_t s) {
 }
 template <typename T>
 void launch_measure3(const LatDev& L, int y, const SampleOut& o, hipStream_t s) {
-  hipLaunchKernelGGL(k_measure3<T>, dim3(L.n_chains), dim3(WG), 0, s, L, y, o);
+  VP_DISPATCH_DC(k_measure3, T, L, y, o);
 }
 template <typename T>
 void launch_measure4(const LatDev& L, int y, const SampleOut& o, hipStream_t s) {

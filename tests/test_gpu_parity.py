@@ -94,6 +94,34 @@ def test_sampler_fp64_bit_exact_fused_shape():
         assert tuple(g["accept"][c]) == (ch.accepted, ch.proposed)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_sampler_bit_exact_d8_dc16(prec):
+    """The benchmark's bond dimensions (fused 3-line and 2-row steps, defects) on a 4x6 lattice:
+    float64 decisions bit-exact against the oracle; float32 measurements of the visited states."""
+    B = _B()
+    print(f"sample {prec} 4x6 D=8 Dc=16 3 chains 1+2", flush=True)
+    T = W.random_tensors(4, 6, 8, seed=89)
+    lat = olat.Lattice(4, 6, 8, 16)
+    if prec == "fp64":
+        g = _gpu_sample(4, 6, 8, 16, 0.0, B.VP_FP64, T, 3, 1, 2, seed=43)
+        for c in range(3):
+            ch = vmc.Chain(lat, olat.neel_shuffled(lat, 43, 0, c), 43, 0, c)
+            o = vmc.run_chain(T, lat, ch, 1, 2)
+            assert np.array_equal(g["spins"][c], np.stack([x["spins"] for x in o])), c
+            assert np.max(np.abs(g["e_loc"][c] - np.array([x["e_loc"] for x in o]))) / 24 <= 1e-10
+            assert np.max(np.abs(g["log_abs_psi"][c] - np.array([x["log_abs_psi"] for x in o]))) <= 1e-10
+            for m in range(2):
+                od = np.asarray(o[m]["dlnpsi"]).ravel()
+                assert np.max(np.abs(g["dlnpsi"][c, m] - od)) <= 1e-9 * max(1.0, np.max(np.abs(od)))
+            assert tuple(g["accept"][c]) == (ch.accepted, ch.proposed)
+    else:
+        g = _gpu_sample(4, 6, 8, 16, 0.0, B.VP_FP32, T, 3, 1, 2, seed=43)
+        cfgs = g["spins"].reshape(6, 24)
+        o = H.oracle_eval(4, 6, 8, 16, 0.0, T, cfgs)
+        assert np.max(np.abs(g["e_loc"].ravel() - o["e_loc"])) / 24 <= 1e-4
+        assert np.max(np.abs(g["log_abs_psi"].ravel() - o["log_abs_psi"])) <= 1e-3
+
+
 def test_eval_more_chains_than_configs():
     """n_cfg below the context's chain count (a ragged last batch)."""
     B = _B()
