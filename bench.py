@@ -42,7 +42,7 @@ def phase_flops(Ly, Lx, D, Dc, nch, launches, anti_h=0, anti_v=0):
     Column-step costs (multiply-adds, bulk dimensions):
       3-line step   D^4 Dc^2 + 2 D^2 Dc^3
       2-row step    2 D^5 Dc^2 + 2 D^3 Dc^3
-      defect        D^2 Dc^3 + D^3 Dc^3 + D^4 Dc^2
+      defect        D^4 Dc^2 + 2 D^2 Dc^3  ((Lp.A)(B.Rn), contracted over two bonds at a time)
       compression of one row (Gram steps, right-to-left carries, eigenproblems
       of order n = D Dc: tridiagonalisation 4/3 n^3 flops, back-transformation
       4 n^2 Dc flops)
@@ -55,7 +55,7 @@ def phase_flops(Ly, Lx, D, Dc, nch, launches, anti_h=0, anti_v=0):
     c, d = Dc, D
     env3 = d ** 4 * c ** 2 + 2 * d ** 2 * c ** 3
     env4 = 2 * d ** 5 * c ** 2 + 2 * d ** 3 * c ** 3
-    defect = d ** 2 * c ** 3 + d ** 3 * c ** 3 + d ** 4 * c ** 2
+    defect = d ** 4 * c ** 2 + 2 * d ** 2 * c ** 3
     n = d * c
     comp_mac = (Lx - 1) * env4 + Lx * (d ** 2 * c ** 3 + d ** 4 * c ** 2) + (Lx - 1) * (2 * n ** 3 + d ** 2 * c ** 3)
     comp = 2 * comp_mac + (Lx - 1) * (4.0 / 3.0 * n ** 3 + 4 * n ** 2 * c)

@@ -82,8 +82,9 @@ __device__ inline int64_t meas_index(const SampleOut& o, const ChainMeta* m) {
 }
 
 // 3-line column step with optional flipped site: t = T[s ^ flip].  (DD, CC)
-// with DD*DD = 64 and DD*CC = 128 select the fused MFMA step (working
-// precision); otherwise the generic strided-GEMM step runs.
+// with DD*DD = 64 and DD*CC = 128 select the fused MFMA step in the working
+// precision, also for a bf16 sampling pass (it is faster there than the
+// generic bf16-operand step); otherwise the generic strided-GEMM step runs.
 template <typename T, int DD, int CC>
 constexpr bool fused3() {
   if constexpr (DD > 0) return Env3Shape<DD, CC>::ok;
@@ -95,7 +96,7 @@ __device__ inline int step3(const LatDev& L, const Chain<T>& C, T* out, const T*
   int k = y * L.Lx + x;
   const T* t = tw<T>(L, k, C.sp[k] ^ flip);
   S4 st = st_std(L.d);
-  if constexpr (fused3<T, DD, CC>() && !BF16) {
+  if constexpr (fused3<T, DD, CC>()) {
     if (right)
       env3_fused<T, DD, CC>(out, in, Ux, sb_mirror(CC, DD), t, st_mirror(st), Dx, sb_mirror(CC, DD), tiles);
     else
@@ -114,7 +115,7 @@ __device__ inline int step3(const LatDev& L, const Chain<T>& C, T* out, const T*
 // LDS bytes of a kernel's 3-line column steps (and, with defects, its defect tensors).
 template <typename T, int DD, int CC, bool BF16, bool DEFECT = false>
 constexpr size_t step3_lds() {
-  if constexpr (DD > 0 && !BF16) {
+  if constexpr (DD > 0) {
     if constexpr (Env3Shape<DD, CC>::ok) {
       constexpr size_t a = Env3Shape<DD, CC>::template lds_bytes<T>();
       constexpr size_t b = DEFECT ? Env3Shape<DD, CC>::template defect_lds_bytes<T>() : 0;
