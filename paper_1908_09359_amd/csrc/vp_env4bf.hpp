@@ -106,17 +106,19 @@ __device__ void env4_bf16(TS* __restrict__ Lout, const TS* __restrict__ Lin, con
     BT[e] = dd < D ? (__bf16)(float)B[c * sB.s0 + dd * sB.s1 + ee * sB.s2] : zero;
   }
   for (int e = tid; e < S::nX1 + S::nX2 + S::nX3; e += WG) X1[e] = zero;
+  for (int e = tid; e < S::nLs; e += WG) Ls[e] = zero;
 
-  // lower-bond slices of Lin are fetched one slice ahead into registers, so
-  // their global-memory latency overlaps the previous slice's products
-  constexpr int NPF = (S::nLs + WG - 1) / WG;
+  // lower-bond slices of Lin ([a][(l1,l2)], contiguous) are read coalesced one
+  // slice ahead into registers, so their global-memory latency overlaps the
+  // previous slice's products, and transposed into Ls when stored
+  constexpr int SL = C * D * D;
+  constexpr int NPF = (SL + WG - 1) / WG;
   float pre[NPF];
   auto fetch = [&](int cs) {
 #pragma unroll
     for (int u = 0; u < NPF; ++u) {
       const int e = tid + u * WG;
-      const int row = e / S::P1, a = e - row * S::P1;  // row = (l1, l2)
-      pre[u] = (e < S::nLs && a < C) ? (float)Lin[(cs * C + a) * (D * D) + row] : 0.0f;
+      pre[u] = e < SL ? (float)Lin[cs * SL + e] : 0.0f;
     }
   };
   fetch(0);
@@ -129,8 +131,8 @@ __device__ void env4_bf16(TS* __restrict__ Lout, const TS* __restrict__ Lin, con
       __syncthreads();  // previous slice done with Ls / X buffers (and the staging above)
 #pragma unroll
       for (int u = 0; u < NPF; ++u) {
-        const int e = tid + u * WG;
-        if (e < S::nLs) Ls[e] = (__bf16)pre[u];
+        const int e = tid + u * WG, a = e / (D * D), row = e - a * (D * D);  // row = (l1, l2)
+        if (e < SL) Ls[row * S::P1 + a] = (__bf16)pre[u];
       }
       if (cs + 1 < C) fetch(cs + 1);
       else if (q + 1 < S::NBLK) fetch(0);
