@@ -170,11 +170,26 @@ template <typename TC, typename TA, typename TB>
 __device__ void wg_gemm_t(char* tiles, TC* __restrict__ C, View vc, const TA* __restrict__ A, View va,
                           const TB* __restrict__ B, View vb, int M, int N, int K, TC alpha = TC(1),
                           bool accumulate = false) {
-  constexpr int BM = 64, BN = 64, BK = 16;
+  constexpr int BM = 64, BN = 64, BK = 16, NA = (BM * BK) / WG, NB = (BN * BK) / WG;
   TC (*As)[BM + 1] = reinterpret_cast<TC (*)[BM + 1]>(tiles);
   TC (*Bs)[BN + 1] = reinterpret_cast<TC (*)[BN + 1]>(tiles + BK * (BM + 1) * sizeof(TC));
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int tr0 = (wave >> 1) * 32, tc0 = (wave & 1) * 32;  // this wave's 32x32 corner
+  // the next K-chunk of both operands is read into registers while the current
+  // one is multiplied
+  TC pa[NA], pb[NB];
+  auto fetch = [&](int m0, int n0, int k0) {
+#pragma unroll
+    for (int e = 0; e < NA; ++e) {
+      const int idx = tid + e * WG, mi = idx % BM, ki = idx / BM, m = m0 + mi, k = k0 + ki;
+      pa[e] = (m < M && k < K) ? (TC)A[vaddr(va, m, k)] : TC(0);
+    }
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+      const int idx = tid + e * WG, ni = idx % BN, ki = idx / BN, n = n0 + ni, k = k0 + ki;
+      pb[e] = (n < N && k < K) ? (TC)B[vaddr(vb, k, n)] : TC(0);
+    }
+  };
   for (int m0 = 0; m0 < M; m0 += BM) {
     for (int n0 = 0; n0 < N; n0 += BN) {
       typename Acc4<TC>::type acc[2][2];
@@ -182,22 +197,20 @@ __device__ void wg_gemm_t(char* tiles, TC* __restrict__ C, View vc, const TA* __
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = {0, 0, 0, 0};
+      fetch(m0, n0, 0);
       for (int k0 = 0; k0 < K; k0 += BK) {
 #pragma unroll
-        for (int e = 0; e < (BM * BK) / WG; ++e) {
-          int idx = tid + e * WG;
-          int mi = idx % BM, ki = idx / BM;
-          int m = m0 + mi, k = k0 + ki;
-          As[ki][mi] = (m < M && k < K) ? (TC)A[vaddr(va, m, k)] : TC(0);
+        for (int e = 0; e < NA; ++e) {
+          const int idx = tid + e * WG;
+          As[idx / BM][idx % BM] = pa[e];
         }
 #pragma unroll
-        for (int e = 0; e < (BN * BK) / WG; ++e) {
-          int idx = tid + e * WG;
-          int ni = idx % BN, ki = idx / BN;
-          int n = n0 + ni, k = k0 + ki;
-          Bs[ki][ni] = (n < N && k < K) ? (TC)B[vaddr(vb, k, n)] : TC(0);
+        for (int e = 0; e < NB; ++e) {
+          const int idx = tid + e * WG;
+          Bs[idx / BN][idx % BN] = pb[e];
         }
         __syncthreads();
+        if (k0 + BK < K) fetch(m0, n0, k0 + BK);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
           const int k = kk + (lane >> 4);
