@@ -331,13 +331,16 @@ __device__ __forceinline__ void sym_topk_eig(const double* H, int n, int k, doub
         Xs[IX(j)] = 0.5 + (double)(h & 0xFFFF) / 65536.0;
       }
       for (int it = 0; it < 3; ++it) {
+        // forward elimination; the running entry j + 1 stays in a register
+        double carry = Xs[IX(0)];
         #pragma unroll 4
         for (int j = 0; j < n - 1; ++j) {
-          double rj = Xs[IX(j)], rj1 = Xs[IX(j + 1)];
+          double rj = carry, rj1 = Xs[IX(j + 1)];
           if ((pivw[j] >> tid) & 1u) { double tt = rj; rj = rj1; rj1 = tt; }
           Xs[IX(j)] = rj;
-          Xs[IX(j + 1)] = rj1 - ML[IX(j)] * rj;
+          carry = rj1 - ML[IX(j)] * rj;
         }
+        Xs[IX(n - 1)] = carry;
         double x1 = 0.0, x2 = 0.0, nrm = 0.0;
         #pragma unroll 4
         for (int j = n - 1; j >= 0; --j) {
