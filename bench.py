@@ -35,6 +35,31 @@ METRIC = "samples/s (psi, E_loc, dlnpsi) 16x16 D=8 Dc=16, learned+bf16 vs plain 
 
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15, "hbm": 8.0e12}
 
+# HBM bytes per launch of the phases' kernels, from rocprofv3 --pmc FETCH_SIZE and
+# WRITE_SIZE runs (profiles/hbm_traffic_16x16_D8_Dc16_1024ch.md), each scaled by
+# what the same counter reads for a device-to-device copy of known size.  They
+# describe the kernel sources whose digest is `src`; for any other sources the
+# benchmark reports no traffic.
+TRAFFIC = {"src": "f53955df19009809",
+           "bytes_per_launch": {
+               # k_compress<double, 8, 16> (both directions): 1.733e7 KiB fetched x 2.0, 1.860e7 KiB written
+               "learned": {"compress_up": 5.4542e10, "compress_down": 5.4542e10, "measure4": 4.4696e10},
+               # k_compress<float, 8, 16>: 1.779e7 KiB fetched x 2.0, 1.850e7 KiB written
+               "plain": {"compress_up": 5.5369e10, "compress_down": 5.5369e10, "measure4": 1.8192e10}}}
+
+
+def kernel_source_digest():
+    """sha256 over the HIP/C++ sources of the library (names and contents)."""
+    import hashlib
+    import glob
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1908_09359_amd", "csrc", "*"))):
+        if f.endswith((".hip", ".hpp", ".cpp", ".h")):
+            h.update(os.path.basename(f).encode())
+            with open(f, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
 
 def phase_flops(Ly, Lx, D, Dc, nch, launches, anti_h=0, anti_v=0):
     """Algorithmic flops of each phase over the timed region (all chains, all launches).
@@ -194,16 +219,19 @@ class Path:
         self.ctx.close()
 
 
-def roofline(ms, launches, flops, fp64_phases):
+def roofline(ms, launches, flops, fp64_phases, path):
     """The phase with the largest share of the timed sweeps among those with an algorithmic
     flop count: its flops over the timed region / its summed live launch time."""
     timed = {k: v for k, v in ms.items() if k in flops and flops[k] > 0}
     dom = max(timed, key=lambda k: timed[k])
     achieved = flops[dom] / (ms[dom] / 1e3)
     peak = PEAK["fp64"] if dom in fp64_phases else PEAK["fp32"]
+    traffic = None
+    if TRAFFIC["src"] is not None and TRAFFIC["src"] == kernel_source_digest():
+        traffic = TRAFFIC["bytes_per_launch"].get(path, {}).get(dom)
     return {"bound": "alu", "kernel": dom, "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": None, "launches": launches[dom],
-            "avg_launch_ms": ms[dom] / launches[dom]}
+            "frac": achieved / peak, "traffic": traffic, "traffic_unit": "HBM bytes per launch",
+            "launches": launches[dom], "avg_launch_ms": ms[dom] / launches[dom]}
 
 
 def main():
@@ -247,7 +275,7 @@ def main():
         r = p.timed(args.warmup, args.steps)
         print(f"plain: {r['samples_per_s']:.1f} samples/s", file=sys.stderr, flush=True)
         fl = phase_flops(Ly, Lx, D, Dc, nch, r["launches"], r["anti_h"], r["anti_v"])
-        r["roofline"] = roofline(r["ms"], r["launches"], fl, ("compress_up", "compress_down"))
+        r["roofline"] = roofline(r["ms"], r["launches"], fl, ("compress_up", "compress_down"), "plain")
         if args.tau_sweeps:
             r["tau"] = p.tau_run(args.tau_sweeps)
         p.close()
@@ -262,7 +290,8 @@ def main():
         print(f"learned: {r['samples_per_s']:.1f} samples/s", file=sys.stderr, flush=True)
         r["training"] = tr
         fl = phase_flops(Ly, Lx, D, Dc, nch, r["launches"], r["anti_h"], r["anti_v"])
-        r["roofline"] = roofline(r["ms"], r["launches"], fl, ("compress_up", "compress_down", "measure3", "measure4"))
+        r["roofline"] = roofline(r["ms"], r["launches"], fl, ("compress_up", "compress_down", "measure3", "measure4"),
+                                 "learned")
         if args.tau_sweeps:
             r["tau"] = p.tau_run(args.tau_sweeps)
         p.close()
