@@ -43,7 +43,17 @@ struct Env4Shape {
   static constexpr int NBLK = C / BB;
   static constexpr int SA = C * D * C, ST = D * D * D * D;
   static constexpr int SL = C * D * D;            // one lower-bond slice of Lin
-  static constexpr int SX = D * D * D * BB;       // X1 / X2 / X3
+  // LDS rows are padded so that the 16 lanes of an MFMA operand read fall in
+  // distinct banks: Ls rows (one per a) by 4 words, X1 rows (l1,l2) of (u,bb) by
+  // 4 words, X2 / X3 rows of D by one word, and in the Gram step the rows (a,u)
+  // of the boundary tensor by 4 words.
+  static constexpr int LP = D * D + 4;            // Ls row stride
+  static constexpr int RS1 = D * BB + 4;          // X1 row stride
+  static constexpr int RS2 = D + 1;               // X2 / X3 row stride
+  static constexpr int AP = C + 4;                // Gram step: boundary tensor row stride
+  static constexpr int SLP = C * LP;
+  static constexpr int SX1 = D * D * RS1, SX2 = BB * D * D * RS2;
+  static constexpr int SX13 = SX1 > SX2 ? SX1 : SX2;  // X1 and X3 share a buffer
   static constexpr int N4 = BB * D * D;           // S4 columns per block
   static constexpr int NT4 = (N4 + 15) / 16;      // S4 column tiles per block
   static constexpr int T4W = (NT4 + 3) / 4;       // S4 tiles per wave per block
@@ -54,8 +64,8 @@ struct Env4Shape {
   static constexpr bool regt() { return !BF16 && (D * D + 15) / 16 == 4; }
   template <typename TC, typename TB, bool GRAM = false>
   static constexpr size_t lds_bytes() {
-    return sizeof(TB) * (GRAM ? SA : 2 * SA) + (regt<GRAM>() ? 0 : sizeof(TB) * (GRAM ? ST : 2 * ST)) +
-           sizeof(TC) * (SL + 2 * SX);
+    return sizeof(TB) * (GRAM ? C * D * AP : 2 * SA) + (regt<GRAM>() ? 0 : sizeof(TB) * (GRAM ? ST : 2 * ST)) +
+           sizeof(TC) * (SLP + SX13 + SX2);
   }
 };
 
@@ -111,8 +121,8 @@ template <typename TC> struct Acc<TC, true> {
 
 // Stage out[i][j] = sum_k A(i,k) B(k,j) into LDS (row-major, ld N), all waves.
 // BF16: operands rounded to bf16, products accumulated in f32, stored as TC.
-template <typename TC, int M, int N, int K, bool BF16 = false, typename FA, typename FB>
-__device__ inline void mfma_stage(TC* out, FA fa, FB fb) {
+template <typename TC, int M, int N, int K, bool BF16 = false, typename FO, typename FA, typename FB>
+__device__ inline void mfma_stage(TC* out, FO oidx, FA fa, FB fb) {
   constexpr int MT = (M + 15) / 16, NT = (N + 15) / 16;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int t = wave; t < MT * NT; t += 4) {
@@ -124,7 +134,7 @@ __device__ inline void mfma_stage(TC* out, FA fa, FB fb) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = m0 + Acc<TC, BF16>::row(lane, r);
-      if (i < M && j < N) out[i * N + j] = (TC)acc[r];
+      if (i < M && j < N) out[oidx(i, j)] = (TC)acc[r];
     }
   }
 }
@@ -133,8 +143,8 @@ __device__ inline void mfma_stage(TC* out, FA fa, FB fb) {
 // wave w owns columns 16w..16w+15 of every row tile; f[s] holds
 // B(4s + lane/16, 16w + lane%16).  The row tiles' accumulation chains are
 // interleaved.
-template <typename TC, int M, int N, int K, typename FA>
-__device__ inline void mfma_stage_regb(TC* out, FA fa, const TC (&f)[(K + 3) / 4]) {
+template <typename TC, int M, int N, int K, typename FO, typename FA>
+__device__ inline void mfma_stage_regb(TC* out, FO oidx, FA fa, const TC (&f)[(K + 3) / 4]) {
   constexpr int MT = (M + 15) / 16, KS = (K + 3) / 4;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, kq = lane >> 4;
   typename Mfma<TC>::acc_t acc[MT];
@@ -156,7 +166,7 @@ __device__ inline void mfma_stage_regb(TC* out, FA fa, const TC (&f)[(K + 3) / 4
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = mt * 16 + Mfma<TC>::row(lane, r);
-      if (i < M && j < N) out[i * N + j] = acc[mt][r];
+      if (i < M && j < N) out[oidx(i, j)] = acc[mt][r];
     }
 }
 
@@ -180,11 +190,12 @@ __device__ void env4_fused(TC* __restrict__ Lout, const TC* __restrict__ Lin, co
   constexpr int KS = (D * D + 3) / 4;
   TB* As = reinterpret_cast<TB*>(lds);
   TB* Bs = GRAM ? As : As + Sh::SA;
-  TB* T1s = Bs + (GRAM ? 0 : Sh::SA) + (GRAM ? Sh::SA : 0);
+  TB* T1s = GRAM ? As + C * D * Sh::AP : Bs + Sh::SA;
   TB* T2s = GRAM ? T1s : T1s + Sh::ST;
   TC* Ls = reinterpret_cast<TC*>(REGT ? T1s : T2s + Sh::ST);
-  TC* X1 = Ls + Sh::SL;  // X1 and X3
-  TC* X2 = X1 + Sh::SX;
+  TC* X1 = Ls + Sh::SLP;  // X1 and X3
+  TC* X2 = X1 + Sh::SX13;
+  constexpr int LP = Sh::LP, RS1 = Sh::RS1, RS2 = Sh::RS2, AP = Sh::AP;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
 
   // this wave's B fragments of S2 (t1) and S3 (t2; for GRAM the u<->d view of
@@ -201,11 +212,18 @@ __device__ void env4_fused(TC* __restrict__ Lout, const TC* __restrict__ Lin, co
     }
   }
 
-  // stage the column tensors in canonical leg order
+  // stage the column tensors: B as [c][dd][e]; A as [a][b-block][u][bb] (the
+  // columns of S1 contiguous), or in the Gram step, where A is also B, as
+  // [a][u][b] with rows padded to AP
   for (int e = tid; e < Sh::SA; e += WG) {
     const int p = e / (D * C), q = (e / C) % D, r = e % C;
-    As[e] = A[p * sA.s0 + q * sA.s1 + r * sA.s2];
-    if (!GRAM) Bs[e] = B[p * sB.s0 + q * sB.s1 + r * sB.s2];
+    if constexpr (GRAM) {
+      As[(p * D + q) * AP + r] = A[p * sA.s0 + q * sA.s1 + r * sA.s2];
+    } else {
+      Bs[e] = B[p * sB.s0 + q * sB.s1 + r * sB.s2];
+      const int rem = e % (D * C), blk = rem / (D * BB), u = (rem / BB) % D, b = blk * BB + rem % BB;
+      As[e] = A[p * sA.s0 + u * sA.s1 + b * sA.s2];
+    }
   }
   if constexpr (!REGT)
     for (int e = tid; e < Sh::ST; e += WG) {
@@ -236,30 +254,34 @@ __device__ void env4_fused(TC* __restrict__ Lout, const TC* __restrict__ Lin, co
       __syncthreads();  // previous slice done with Ls / X buffers
 #pragma unroll
       for (int u = 0; u < NPF; ++u) {
-        const int e = tid + u * WG;
-        if (e < Sh::SL) Ls[e] = pre[u];
+        const int e = tid + u * WG, a = e / (D * D);
+        if (e < Sh::SL) Ls[a * LP + e - a * (D * D)] = pre[u];
       }
       if (cs + 1 < C) fetch(cs + 1);
       else if (q + 1 < NBLK) fetch(0);
       __syncthreads();
       // S1: X1[(l1,l2)][(u,bb)] = sum_a Ls[a][(l1,l2)] As[a][u][b0+bb]
       mfma_stage<TC, D * D, D * BB, C, BF16>(
-          X1, [&](int i, int k) { return Ls[k * D * D + i]; },
-          [&](int k, int j) { return (TC)As[k * D * C + (j / BB) * C + b0 + j % BB]; });
+          X1, [&](int i, int j) { return i * RS1 + j; }, [&](int i, int k) { return Ls[k * LP + i]; },
+          [&](int k, int j) {
+            if constexpr (GRAM) return (TC)As[(k * D + j / BB) * AP + b0 + j % BB];
+            else return (TC)As[k * (D * C) + q * (D * BB) + j];
+          });
       __syncthreads();
+      // rows (i, j / D) of X2 and X3 padded to RS2
+      auto oidx23 = [&](int i, int j) { return (i * D + j / D) * RS2 + j % D; };
       // S2: X2[(l2,bb)][(r1,m)] = sum_{l1,u} X1[l1][l2][u][bb] T1s[(l1,u)][(r1,m)]
-      auto fa2 = [&](int i, int k) {
-        return X1[(k / D) * D * D * BB + (i / BB) * D * BB + (k % D) * BB + i % BB];
-      };
-      if constexpr (REGT) mfma_stage_regb<TC, D * BB, D * D, D * D>(X2, fa2, f1);
+      auto fa2 = [&](int i, int k) { return X1[((k / D) * D + i / BB) * RS1 + (k % D) * BB + i % BB]; };
+      if constexpr (REGT) mfma_stage_regb<TC, D * BB, D * D, D * D>(X2, oidx23, fa2, f1);
       else
-        mfma_stage<TC, D * BB, D * D, D * D, BF16>(X2, fa2, [&](int k, int j) { return (TC)T1s[k * D * D + j]; });
+        mfma_stage<TC, D * BB, D * D, D * D, BF16>(X2, oidx23, fa2,
+                                                    [&](int k, int j) { return (TC)T1s[k * D * D + j]; });
       __syncthreads();
       // S3: X3[(bb,r1)][(r2,dd)] = sum_{l2,m} X2[l2][bb][r1][m] T2s[(l2,m)][(r2,dd)]
-      auto fa3 = [&](int i, int k) { return X2[(((k / D) * BB + i / D) * D + i % D) * D + k % D]; };
-      if constexpr (REGT) mfma_stage_regb<TC, BB * D, D * D, D * D>(X1, fa3, f2);
+      auto fa3 = [&](int i, int k) { return X2[(((k / D) * BB + i / D) * D + i % D) * RS2 + k % D]; };
+      if constexpr (REGT) mfma_stage_regb<TC, BB * D, D * D, D * D>(X1, oidx23, fa3, f2);
       else
-        mfma_stage<TC, BB * D, D * D, D * D, BF16>(X1, fa3, [&](int k, int j) {
+        mfma_stage<TC, BB * D, D * D, D * D, BF16>(X1, oidx23, fa3, [&](int k, int j) {
           // GRAM: t2[l2][m][r2][dd] = t1[l2][dd][r2][m]
           return GRAM ? (TC)T1s[(k / D) * D * D * D + (j % D) * D * D + (j / D) * D + k % D]
                       : (TC)T2s[k * D * D + j];
@@ -277,8 +299,9 @@ __device__ void env4_fused(TC* __restrict__ Lout, const TC* __restrict__ Lin, co
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
               const int k = kq + q;
-              a[q] = (__bf16)((i < C && k < D) ? (float)Bs[cs * D * C + k * C + i] : 0.0f);
-              b[q] = (__bf16)((j < N4 && k < D) ? (float)X1[j * D + k] : 0.0f);
+              a[q] = (__bf16)((i < C && k < D) ? (float)(GRAM ? Bs[(cs * D + k) * AP + i] : Bs[cs * D * C + k * C + i])
+                                               : 0.0f);
+              b[q] = (__bf16)((j < N4 && k < D) ? (float)X1[j * RS2 + k] : 0.0f);
             }
             acc[w] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[w], 0, 0, 0);
           } else {
@@ -286,8 +309,8 @@ __device__ void env4_fused(TC* __restrict__ Lout, const TC* __restrict__ Lin, co
 #pragma unroll
             for (int k0 = 0; k0 < D; k0 += 4) {
               const int k = k0 + kq;
-              TC a = (i < C && k < D) ? (TC)Bs[cs * D * C + k * C + i] : TC(0);
-              TC b = (j < N4 && k < D) ? X1[j * D + k] : TC(0);
+              TC a = (i < C && k < D) ? (TC)(GRAM ? Bs[(cs * D + k) * AP + i] : Bs[cs * D * C + k * C + i]) : TC(0);
+              TC b = (j < N4 && k < D) ? X1[j * RS2 + k] : TC(0);
               acc[w] = Mfma<TC>::op(a, b, acc[w]);
             }
           }
