@@ -97,6 +97,9 @@ __device__ __noinline__ void eig_tridiag(const double* H, int n, lds_f64* dg, ld
       a[q][c] = (r < n && s2 < n) ? H[r * n + s2] : 0.0;
     }
   lds_f64* kpart = red + 32;  // [4] partial v^T p, per wavefront
+  // the column and p live in LDS with element 8 b + q in slot 16 q + b, so that
+  // the 16 lanes of a row (b = bc) read 16 consecutive words
+  auto slot = [](int r) { return (r & 7) * 16 + (r >> 3); };
   // column i of the current matrix, as held by its owners (bc == i / 8); taken
   // inside a statically unrolled column loop under a uniform condition
   double xo[8];
@@ -114,14 +117,14 @@ __device__ __noinline__ void eig_tridiag(const double* H, int n, lds_f64* dg, ld
       double s2 = 0.0;
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        xcol[8 * br + q] = xo[q];
+        xcol[16 * q + br] = xo[q];
         if (8 * br + q >= i + 2) s2 += xo[q] * xo[q];
       }
       nrm[br] = s2;
     }
     __syncthreads();
     // every thread forms the reflector (dlarfg): beta = -sign(alpha) |(alpha, x)|
-    const double alpha = xcol[i + 1];
+    const double alpha = xcol[slot(i + 1)];
     double xn2 = 0.0;
 #pragma unroll
     for (int b = 0; b < 16; ++b) xn2 += nrm[b];
@@ -131,7 +134,7 @@ __device__ __noinline__ void eig_tridiag(const double* H, int n, lds_f64* dg, ld
       t = (beta - alpha) / beta;
       scal = 1.0 / (alpha - beta);
     }
-    if (tid == 0) { dg[i] = xcol[i]; eg[i] = beta; tau[i] = t; }
+    if (tid == 0) { dg[i] = xcol[slot(i)]; eg[i] = beta; tau[i] = t; }
     if (owner) {  // the owners hold column i: store the reflector's entries of their rows
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
@@ -144,8 +147,8 @@ __device__ __noinline__ void eig_tridiag(const double* H, int n, lds_f64* dg, ld
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
         const int rc = 8 * bc + q, rr = 8 * br + q;
-        vc[q] = rc == i + 1 ? 1.0 : ((rc > i + 1 && rc < n) ? (double)xcol[rc] * scal : 0.0);
-        vr[q] = rr == i + 1 ? 1.0 : ((rr > i + 1 && rr < n) ? (double)xcol[rr] * scal : 0.0);
+        vc[q] = rc == i + 1 ? 1.0 : ((rc > i + 1 && rc < n) ? (double)xcol[16 * q + bc] * scal : 0.0);
+        vr[q] = rr == i + 1 ? 1.0 : ((rr > i + 1 && rr < n) ? (double)xcol[16 * q + br] * scal : 0.0);
       }
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
@@ -162,7 +165,7 @@ __device__ __noinline__ void eig_tridiag(const double* H, int n, lds_f64* dg, ld
       part += __shfl_xor(part, 32, 64);
       if (bc == 0) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q) pv[8 * br + q] = pr[q];
+        for (int q = 0; q < 8; ++q) pv[16 * q + br] = pr[q];
       }
       if (lane == 0) kpart[wave] = part;
       __syncthreads();
@@ -172,7 +175,7 @@ __device__ __noinline__ void eig_tridiag(const double* H, int n, lds_f64* dg, ld
       const int cn = (i + 1) & 7;  // column of the next step within its tile
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
-        const double wc = (double)pv[8 * bc + c] + K * vc[c];  // w on the tile's columns
+        const double wc = (double)pv[16 * c + bc] + K * vc[c];  // w on the tile's columns
 #pragma unroll
         for (int q = 0; q < 8; ++q) a[q][c] -= vr[q] * wc + pr[q] * vc[c];
         if (c == cn) {
