@@ -72,7 +72,18 @@ __device__ inline void set_unit(T* x, int n) {
 }
 
 __device__ inline void raise_flag(ChainMeta* m, int f) {
-  if (threadIdx.x == 0) m->flags |= f;
+  if (threadIdx.x == 0) atomicOr(&m->flags, f);
+}
+
+// Whether a chain has an error flag, decided once for the whole work-group
+// (a kernel on another stream may raise a flag of the same chain meanwhile).
+__device__ inline bool chain_flagged(const ChainMeta* m) {
+  __shared__ int f;
+  if (threadIdx.x == 0) f = m->flags;
+  __syncthreads();
+  const bool v = f != 0;
+  __syncthreads();
+  return v;
 }
 
 // Row of this measurement in the outputs: fixed, or from the sweep counter
@@ -251,7 +262,7 @@ __device__ inline void trace_skip(const LatDev& L, int ch, int bond) {
 template <typename T, int DD, int CC, bool BF16>
 __device__ __forceinline__ void ph_hsweep(const LatDev& L, int ch, int y, int last_row, int moves, char* tiles) {
   Chain<T> C = chain_of<T>(L, ch);
-  if (C.meta->flags) return;
+  if (chain_flagged(C.meta)) return;
   const int sz = e3sz(L);
   T* tmp = C.ws + L.oT3;
   const T* R = C.ws + L.oR3;
@@ -305,9 +316,9 @@ __device__ __forceinline__ void ph_hsweep(const LatDev& L, int ch, int y, int la
     double v = (double)nxt[0];
     if (threadIdx.x == 0) {
       if (v == 0.0) {
-        C.meta->flags |= FLAG_ZERO;
+        atomicOr(&C.meta->flags, FLAG_ZERO);
       } else if (!isfinite(v)) {
-        C.meta->flags |= FLAG_NONFINITE;
+        atomicOr(&C.meta->flags, FLAG_NONFINITE);
       } else {
         C.meta->logpsi = C.dw[L.dlamU + y] + log(fabs(v)) + e * 0.69314718055994530942;
         C.meta->sign = v > 0 ? 1 : -1;
@@ -320,7 +331,7 @@ __device__ __forceinline__ void ph_hsweep(const LatDev& L, int ch, int y, int la
 template <typename T, int DD, int CC, bool BF16>
 __device__ __forceinline__ void ph_row4_right(const LatDev& L, int ch, int y, char* lds) {
   Chain<T> C = chain_of<T>(L, ch);
-  if (C.meta->flags) return;
+  if (chain_flagged(C.meta)) return;
   const int sz = e4sz(L);
   T* R = C.ws + L.oR4;
   int* eR = C.iw + L.ieR4;
@@ -362,7 +373,7 @@ constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
 template <typename T, int DD, int CC, bool BF16, bool LEARN>
 __device__ __forceinline__ void ph_vsweep(const LatDev& L, int ch, int y, char* lds) {
   Chain<T> C = chain_of<T>(L, ch);
-  if (C.meta->flags) return;
+  if (chain_flagged(C.meta)) return;
   const int sz = e4sz(L);
   T* tmp = C.ws + L.oT4;
   const T* R = C.ws + L.oR4;
@@ -465,7 +476,7 @@ constexpr size_t compress_lds() {
 template <typename T, int DD, int CC>
 __device__ __forceinline__ void ph_compress(const LatDev& L, int ch, int y, int upper, char* lds) {
   Chain<T> C = chain_of<T>(L, ch);
-  if (C.meta->flags) return;
+  if (chain_flagged(C.meta)) return;
   double* cw = L.cws + (int64_t)ch * L.cws_stride;
   const int c = L.c, d = L.d, Lx = L.Lx;
   const int ssz = c * d * c, gsz = c * d * d * c;
@@ -550,8 +561,8 @@ __device__ __forceinline__ void ph_compress(const LatDev& L, int ch, int y, int 
     double inv = nu > 0 ? 1.0 / nu : 0.0;
     for (int i = threadIdx.x; i < ssz; i += WG) out[i] = (i < dc) ? (T)(Y[i] * inv) : T(0);
     if (threadIdx.x == 0) {
-      if (!(nu > 0.0)) C.meta->flags |= FLAG_ZERO;
-      else if (!isfinite(nu)) C.meta->flags |= FLAG_NONFINITE;
+      if (!(nu > 0.0)) atomicOr(&C.meta->flags, FLAG_ZERO);
+      else if (!isfinite(nu)) atomicOr(&C.meta->flags, FLAG_NONFINITE);
       double lognu = log(nu) + eT * 0.69314718055994530942;
       if (upper) C.dw[L.dlamU + y + 1] = C.dw[L.dlamU + y] + lognu;
       else C.dw[L.dlamD + y] = C.dw[L.dlamD + y + 1] + lognu;
@@ -565,7 +576,7 @@ __device__ __forceinline__ void ph_compress(const LatDev& L, int ch, int y, int 
 template <typename T, int DD, int CC>
 __device__ __forceinline__ void ph_measure3(const LatDev& L, int ch, int y, const SampleOut& o, char* tiles) {
   Chain<T> C = chain_of<T>(L, ch);
-  if (C.meta->flags) return;
+  if (chain_flagged(C.meta)) return;
   const int sz = e3sz(L), Lx = L.Lx, d = L.d;
   T* R = C.ws + L.oR3;
   T* Le = C.ws + L.oL3;
@@ -637,7 +648,7 @@ __device__ __forceinline__ void ph_measure3(const LatDev& L, int ch, int y, cons
     if (o.ratios && threadIdx.x == 0) o.ratios[(int64_t)ch * o.n_pairs + pair] = rho;
   }
   if (threadIdx.x == 0) {
-    if (!isfinite(eacc)) C.meta->flags |= FLAG_NONFINITE;
+    if (!isfinite(eacc)) atomicOr(&C.meta->flags, FLAG_NONFINITE);
     C.meta->e_acc += eacc;
   }
 }
@@ -646,7 +657,7 @@ __device__ __forceinline__ void ph_measure3(const LatDev& L, int ch, int y, cons
 template <typename T, int DD, int CC>
 __device__ __forceinline__ void ph_measure4(const LatDev& L, int ch, int y, const SampleOut& o, char* lds) {
   Chain<T> C = chain_of<T>(L, ch);
-  if (C.meta->flags) return;
+  if (chain_flagged(C.meta)) return;
   const int sz = e4sz(L), Lx = L.Lx;
   T* R = C.ws + L.oR4;
   T* Le = C.ws + L.oL4;
@@ -731,7 +742,7 @@ __device__ __forceinline__ void ph_measure4(const LatDev& L, int ch, int y, cons
     }
   }
   if (threadIdx.x == 0) {
-    if (!isfinite(eacc)) C.meta->flags |= FLAG_NONFINITE;
+    if (!isfinite(eacc)) atomicOr(&C.meta->flags, FLAG_NONFINITE);
     C.meta->e_acc += eacc;
   }
 }
