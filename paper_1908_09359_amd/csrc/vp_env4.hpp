@@ -43,17 +43,21 @@ struct Env4Shape {
   static constexpr int NBLK = C / BB;
   static constexpr int SA = C * D * C, ST = D * D * D * D;
   static constexpr int SL = C * D * D;            // one lower-bond slice of Lin
-  // LDS rows are padded so that the 16 lanes of an MFMA operand read fall in
-  // distinct banks: Ls rows (one per a) by 4 words, X1 rows (l1,l2) of (u,bb) by
-  // 4 words, X2 / X3 rows of D by one word, and in the Gram step the rows (a,u)
-  // of the boundary tensor by 4 words.
-  static constexpr int LP = D * D + 4;            // Ls row stride
-  static constexpr int RS1 = D * BB + 4;          // X1 row stride
-  static constexpr int RS2 = D + 1;               // X2 / X3 row stride
+  // LDS rows are padded so that an MFMA operand read hits distinct banks: the
+  // 16 lanes of one read pass for 8-byte words, the 32 lanes (two k-groups) of
+  // one pass for 4-byte words.  Ls rows (one per a), X1 rows (l1,l2) of (u,bb),
+  // X2 / X3 rows of D, the boundary tensor's rows (one per a) outside the Gram
+  // step and its rows (a,u) in it.  E is the size of a working word.
+  template <int E> static constexpr int lp() { return D * D + (E == 8 ? 4 : 16); }   // Ls
+  template <int E> static constexpr int rs1() { return D * BB + (E == 8 ? 4 : 8); }  // X1
+  template <int E> static constexpr int rs2() { return D + (E == 8 ? 1 : 2); }       // X2 / X3
+  template <int E> static constexpr int arow() { return D * C + (E == 8 ? 0 : 16); } // A, per a
   static constexpr int AP = C + 4;                // Gram step: boundary tensor row stride
-  static constexpr int SLP = C * LP;
-  static constexpr int SX1 = D * D * RS1, SX2 = BB * D * D * RS2;
-  static constexpr int SX13 = SX1 > SX2 ? SX1 : SX2;  // X1 and X3 share a buffer
+  template <int E> static constexpr int slp() { return C * lp<E>(); }
+  template <int E> static constexpr int sx2() { return BB * D * D * rs2<E>(); }
+  template <int E> static constexpr int sx13() {  // X1 and X3 share a buffer
+    return D * D * rs1<E>() > sx2<E>() ? D * D * rs1<E>() : sx2<E>();
+  }
   static constexpr int N4 = BB * D * D;           // S4 columns per block
   static constexpr int NT4 = (N4 + 15) / 16;      // S4 column tiles per block
   static constexpr int T4W = (NT4 + 3) / 4;       // S4 tiles per wave per block
@@ -64,8 +68,9 @@ struct Env4Shape {
   static constexpr bool regt() { return !BF16 && (D * D + 15) / 16 == 4; }
   template <typename TC, typename TB, bool GRAM = false>
   static constexpr size_t lds_bytes() {
-    return sizeof(TB) * (GRAM ? C * D * AP : 2 * SA) + (regt<GRAM>() ? 0 : sizeof(TB) * (GRAM ? ST : 2 * ST)) +
-           sizeof(TC) * (SLP + SX13 + SX2);
+    constexpr int E = sizeof(TC);
+    return sizeof(TB) * (GRAM ? C * D * AP : C * arow<sizeof(TB)>() + SA) +
+           (regt<GRAM>() ? 0 : sizeof(TB) * (GRAM ? ST : 2 * ST)) + sizeof(TC) * (slp<E>() + sx13<E>() + sx2<E>());
   }
 };
 
@@ -188,14 +193,16 @@ __device__ void env4_fused(TC* __restrict__ Lout, const TC* __restrict__ Lin, co
   constexpr int BB = Sh::BB, NBLK = Sh::NBLK, N4 = Sh::N4, NT4 = Sh::NT4, T4W = Sh::T4W;
   constexpr bool REGT = Sh::template regt<GRAM, BF16>();
   constexpr int KS = (D * D + 3) / 4;
+  constexpr int E = sizeof(TC);
+  constexpr int LP = Sh::template lp<E>(), RS1 = Sh::template rs1<E>(), RS2 = Sh::template rs2<E>();
+  constexpr int AP = Sh::AP, AR = Sh::template arow<sizeof(TB)>();
   TB* As = reinterpret_cast<TB*>(lds);
-  TB* Bs = GRAM ? As : As + Sh::SA;
-  TB* T1s = GRAM ? As + C * D * Sh::AP : Bs + Sh::SA;
+  TB* Bs = GRAM ? As : As + C * AR;
+  TB* T1s = GRAM ? As + C * D * AP : Bs + Sh::SA;
   TB* T2s = GRAM ? T1s : T1s + Sh::ST;
   TC* Ls = reinterpret_cast<TC*>(REGT ? T1s : T2s + Sh::ST);
-  TC* X1 = Ls + Sh::SLP;  // X1 and X3
-  TC* X2 = X1 + Sh::SX13;
-  constexpr int LP = Sh::LP, RS1 = Sh::RS1, RS2 = Sh::RS2, AP = Sh::AP;
+  TC* X1 = Ls + Sh::template slp<E>();  // X1 and X3
+  TC* X2 = X1 + Sh::template sx13<E>();
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
 
   // this wave's B fragments of S2 (t1) and S3 (t2; for GRAM the u<->d view of
@@ -222,7 +229,7 @@ __device__ void env4_fused(TC* __restrict__ Lout, const TC* __restrict__ Lin, co
     } else {
       Bs[e] = B[p * sB.s0 + q * sB.s1 + r * sB.s2];
       const int rem = e % (D * C), blk = rem / (D * BB), u = (rem / BB) % D, b = blk * BB + rem % BB;
-      As[e] = A[p * sA.s0 + u * sA.s1 + b * sA.s2];
+      As[p * AR + rem] = A[p * sA.s0 + u * sA.s1 + b * sA.s2];
     }
   }
   if constexpr (!REGT)
@@ -265,7 +272,7 @@ __device__ void env4_fused(TC* __restrict__ Lout, const TC* __restrict__ Lin, co
           X1, [&](int i, int j) { return i * RS1 + j; }, [&](int i, int k) { return Ls[k * LP + i]; },
           [&](int k, int j) {
             if constexpr (GRAM) return (TC)As[(k * D + j / BB) * AP + b0 + j % BB];
-            else return (TC)As[k * (D * C) + q * (D * BB) + j];
+            else return (TC)As[k * AR + q * (D * BB) + j];
           });
       __syncthreads();
       // rows (i, j / D) of X2 and X3 padded to RS2
