@@ -251,22 +251,29 @@ __device__ void env4_fused(TC* __restrict__ Lout, const TC* __restrict__ Lin, co
       pre[u] = e < Sh::SL ? Lin[cs * Sh::SL + e] : TC(0);
     }
   };
+  // slices are taken in the order (block, slice); the next one is stored into
+  // Ls as soon as S1 of the current one has read it, and the one after that is
+  // then fetched, so a slice costs four barriers
+  auto store = [&]() {
+#pragma unroll
+    for (int u = 0; u < NPF; ++u) {
+      const int e = tid + u * WG, a = e / (D * D);
+      if (e < Sh::SL) Ls[a * LP + e - a * (D * D)] = pre[u];
+    }
+  };
+  constexpr int NS = NBLK * C;
   fetch(0);
+  __syncthreads();  // staging above done
+  store();
+  if (NS > 1) fetch(1 % C);
+  __syncthreads();
   for (int q = 0; q < NBLK; ++q) {
     const int b0 = q * BB;
     typename Acc<TC, BF16>::type acc[T4W];
 #pragma unroll
     for (int w = 0; w < T4W; ++w) acc[w] = {0, 0, 0, 0};
     for (int cs = 0; cs < C; ++cs) {
-      __syncthreads();  // previous slice done with Ls / X buffers
-#pragma unroll
-      for (int u = 0; u < NPF; ++u) {
-        const int e = tid + u * WG, a = e / (D * D);
-        if (e < Sh::SL) Ls[a * LP + e - a * (D * D)] = pre[u];
-      }
-      if (cs + 1 < C) fetch(cs + 1);
-      else if (q + 1 < NBLK) fetch(0);
-      __syncthreads();
+      const int pos = q * C + cs;
       // S1: X1[(l1,l2)][(u,bb)] = sum_a Ls[a][(l1,l2)] As[a][u][b0+bb]
       mfma_stage<TC, D * D, D * BB, C, BF16>(
           X1, [&](int i, int j) { return i * RS1 + j; }, [&](int i, int k) { return Ls[k * LP + i]; },
@@ -275,6 +282,10 @@ __device__ void env4_fused(TC* __restrict__ Lout, const TC* __restrict__ Lin, co
             else return (TC)As[k * AR + q * (D * BB) + j];
           });
       __syncthreads();
+      if (pos + 1 < NS) {  // Ls is free: the next slice goes in
+        store();
+        if (pos + 2 < NS) fetch((pos + 2) % C);
+      }
       // rows (i, j / D) of X2 and X3 padded to RS2
       auto oidx23 = [&](int i, int j) { return (i * D + j / D) * RS2 + j % D; };
       // S2: X2[(l2,bb)][(r1,m)] = sum_{l1,u} X1[l1][l2][u][bb] T1s[(l1,u)][(r1,m)]
@@ -323,6 +334,7 @@ __device__ void env4_fused(TC* __restrict__ Lout, const TC* __restrict__ Lin, co
           }
         }
       }
+      __syncthreads();  // X3 read: the next S1 may write X1
     }
     // write Lout[e][b0 + (bb,r1,r2)]
 #pragma unroll
