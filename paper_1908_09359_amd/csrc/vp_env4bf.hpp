@@ -121,22 +121,28 @@ __device__ void env4_bf16(TS* __restrict__ Lout, const TS* __restrict__ Lin, con
       pre[u] = e < SL ? (float)Lin[cs * SL + e] : 0.0f;
     }
   };
+  // slices in the order (block, slice); the next one is stored into Ls as soon
+  // as S1 of the current one has read it, so a slice costs four barriers
+  auto store = [&]() {
+#pragma unroll
+    for (int u = 0; u < NPF; ++u) {
+      const int e = tid + u * WG, a = e / (D * D), row = e - a * (D * D);  // row = (l1, l2)
+      if (e < SL) Ls[row * S::P1 + a] = (__bf16)pre[u];
+    }
+  };
+  constexpr int NS = S::NBLK * C;
   fetch(0);
+  __syncthreads();  // staging (and the zeroing of Ls) done
+  store();
+  if (NS > 1) fetch(1 % C);
+  __syncthreads();
   for (int q = 0; q < S::NBLK; ++q) {
     const int b0 = q * BB;
     v4f_e acc[S::T4W];
 #pragma unroll
     for (int w = 0; w < S::T4W; ++w) acc[w] = {0, 0, 0, 0};
     for (int cs = 0; cs < C; ++cs) {
-      __syncthreads();  // previous slice done with Ls / X buffers (and the staging above)
-#pragma unroll
-      for (int u = 0; u < NPF; ++u) {
-        const int e = tid + u * WG, a = e / (D * D), row = e - a * (D * D);  // row = (l1, l2)
-        if (e < SL) Ls[row * S::P1 + a] = (__bf16)pre[u];
-      }
-      if (cs + 1 < C) fetch(cs + 1);
-      else if (q + 1 < S::NBLK) fetch(0);
-      __syncthreads();
+      const int pos = q * C + cs;
       // S1: X1[(l2,bb)][(l1,u)] = sum_a Ls[(l1,l2)][a] AT[(u, b0+bb)][a]; M = D^2, N = D BB
       {
         constexpr int MT = (D * D + 15) / 16, NT = (D * BB + 15) / 16;
@@ -168,6 +174,10 @@ __device__ void env4_bf16(TS* __restrict__ Lout, const TS* __restrict__ Lin, con
         }
       }
       __syncthreads();
+      if (pos + 1 < NS) {  // Ls is free: the next slice goes in
+        store();
+        if (pos + 2 < NS) fetch((pos + 2) % C);
+      }
       // S2: X2[(bb,r1)][(l2,m)] = sum_{(l1,u)} X1[(l2,bb)][(l1,u)] T1[(r1,m)][(l1,u)]; M = D BB, N = D^2
       {
         constexpr int MT = (D * BB + 15) / 16, NT = (D * D + 15) / 16;
@@ -219,6 +229,7 @@ __device__ void env4_bf16(TS* __restrict__ Lout, const TS* __restrict__ Lin, con
           }
         }
       }
+      __syncthreads();  // X3 read: the next S1 may write X1
     }
     // write Lout[e][b0 + (bb, r1, r2)]
 #pragma unroll
