@@ -102,7 +102,7 @@ def test_trace_fp64_matches_oracle():
     assert len(rel) > 0 and rel.max() <= 1e-10
 
 
-@pytest.mark.parametrize("Ly,Lx,D,Dc", [(6, 6, 4, 8), (6, 6, 3, 6), (8, 8, 6, 12)])
+@pytest.mark.parametrize("Ly,Lx,D,Dc", [(6, 6, 4, 8), (6, 6, 3, 6), (8, 8, 6, 12), (6, 6, 8, 16)])
 def test_sampling_ratios_bf16(Ly, Lx, D, Dc):
     """bf16-operand ratios against the float64 oracle along the same sweep.
 

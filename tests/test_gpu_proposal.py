@@ -43,7 +43,8 @@ def _ctx(Ly, Lx, D, Dc, prec, n, seed=1, T=None, theta=None):
 
 
 @pytest.mark.parametrize("Ly,Lx,D,Dc,prec,tol", [(4, 4, 2, 4, 0, 1e-10), (6, 6, 4, 8, 0, 1e-10),
-                                                  (4, 6, 3, 5, 0, 1e-10), (6, 6, 4, 8, 1, 1e-3)])
+                                                  (4, 6, 3, 5, 0, 1e-10), (6, 6, 4, 8, 1, 1e-3),
+                                                  (4, 6, 8, 16, 0, 1e-10)])
 def test_plaquette_ratios_match_oracle(Ly, Lx, D, Dc, prec, tol):
     import torch
     print(f"plaquette ratios {Ly}x{Lx} D={D} Dc={Dc} prec={prec}", flush=True)
@@ -108,7 +109,8 @@ def test_loss_gradient_matches_oracle():
         assert np.max(np.abs(g[a:b] - ref_g[a:b])) <= 1e-4 * max(1e-3, np.max(np.abs(ref_g[a:b]))), i
 
 
-@pytest.mark.parametrize("Ly,Lx,D,Dc,n,sweeps", [(4, 4, 2, 4, 3, 6), (6, 6, 4, 8, 2, 3), (4, 5, 3, 4, 2, 3)])
+@pytest.mark.parametrize("Ly,Lx,D,Dc,n,sweeps", [(4, 4, 2, 4, 3, 6), (6, 6, 4, 8, 2, 3), (4, 5, 3, 4, 2, 3),
+                                                 (4, 6, 8, 16, 2, 2)])
 def test_learned_sampler_bit_exact_fp64(Ly, Lx, D, Dc, n, sweeps):
     """Learned chains in float64: every configuration and move count equals the oracle's."""
     import torch

@@ -62,7 +62,7 @@ def _run(schedule, Ly, Lx, D, Dc, J2, n, T, seed, calls, learned=None):
 
 
 @pytest.mark.parametrize("Ly,Lx,D,Dc,J2,learn", [(4, 4, 2, 4, 0.0, False), (6, 6, 4, 8, 0.5, False),
-                                                 (4, 6, 3, 4, 0.0, True)])
+                                                 (4, 6, 3, 4, 0.0, True), (4, 6, 8, 16, 0.0, True)])
 def test_schedules_agree_bit_exactly(Ly, Lx, D, Dc, J2, learn):
     B = _B()
     print(f"schedules {Ly}x{Lx} D={D} Dc={Dc} J2={J2} learned={learn}", flush=True)
