@@ -8,7 +8,8 @@ producing Psi, E_loc and the log-derivatives dlnPsi/dT of every chain.
 Two paths on the 16x16, D=8, Dc=16 Heisenberg workload:
 
 * plain:   float32 contractions, nearest-neighbour pair sweeps;
-* learned: bf16 sampling pass over float64 storage, float64 measurement, pair
+* learned: bf16-operand 2-row steps and float64 3-line steps in the sampling
+           pass over float64 storage, float64 measurement, pair
            sweeps plus learned plaquette moves; the proposal network is first
            trained (untimed) on configurations of the same chains.
 
@@ -304,7 +305,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "bf16/f64" if is_learned else "f32", "data": "synthetic",
         "config": {"workload": f"{Ly}x{Lx} Heisenberg D={D} Dc={Dc}, {nch} chains, "
-                               + ("learned plaquette moves + pair sweeps, bf16-operand sampling pass, "
+                               + ("learned plaquette moves + pair sweeps, bf16-operand 2-row steps in the sampling pass, "
                                   "fp64 measurement" if is_learned else "plain pair sweeps, fp32 contractions")
                                + " / fp64 compression",
                    "Ly": Ly, "Lx": Lx, "D": D, "Dc": Dc, "chains": nch, "J2": 0.0,

@@ -33,9 +33,11 @@
  *   pairs; every ratio divides by the same network with the current tensors.
  * Precision (vp_lattice.prec): VP_FP64 contracts in float64; VP_FP32 in
  *   float32 on MFMA; VP_BF16 stores tensors, boundaries and environments in
- *   float64, takes the sampling pass (the ratios that decide Metropolis moves)
- *   with bf16 operands and float32 accumulation, and measures Psi, E_loc and G
- *   in float64 (App. D: a ratio error of a few bf16 ulps changes acceptance
+ *   float64, takes the 2-row steps of the sampling pass (the ratios that decide
+ *   Metropolis moves) with bf16 operands and float32 accumulation (its 3-line
+ *   steps run in float64 where a fused float64 step is built, D = 8 and
+ *   Dc = 16, which is faster there), and measures Psi, E_loc and G in float64
+ *   (App. D: a ratio error of a few bf16 ulps changes acceptance
  *   probabilities by as much, which the chain tolerates; the estimators are
  *   not protected by that argument, and float32 measurements of strongly
  *   cancelling networks miss the 1e-4 per-site energy tolerance).  Every mode
