@@ -305,7 +305,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "bf16/f64" if is_learned else "f32", "data": "synthetic",
         "config": {"workload": f"{Ly}x{Lx} Heisenberg D={D} Dc={Dc}, {nch} chains, "
-                               + ("learned plaquette moves + pair sweeps, bf16-operand 2-row steps in the sampling pass, "
+                               + ("learned plaquette moves + pair sweeps, bf16-operand 2-row steps in the "
+                                  "sampling pass, "
                                   "fp64 measurement" if is_learned else "plain pair sweeps, fp32 contractions")
                                + " / fp64 compression",
                    "Ly": Ly, "Lx": Lx, "D": D, "Dc": Dc, "chains": nch, "J2": 0.0,
