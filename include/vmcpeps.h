@@ -192,6 +192,20 @@ vp_status vp_eval(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev, int32_t n_c
                   double* log_abs_psi_dev, int8_t* sign_dev, double* e_loc_dev,
                   void* dlnpsi_dev, double* ratios_dev);
 
+/* Two truncation cutoffs (Sec. II.A, App. D): the chains of lattice
+ * lat_sample move with its cutoff Dc1 (a ratio only meets a uniform number,
+ * so a modest cutoff suffices), and after every sweep past the n_burn first
+ * their configurations are measured on lattice lat_measure with its cutoff
+ * Dc2, as vp_eval does.  The two lattices must agree in Ly, Lx, D, J1, J2 and
+ * precision; lat_measure needs at least as many chains and its tensors set
+ * (normally the same as lat_sample's); its chain slots are overwritten.
+ * Outputs as in vp_sample (row chain * n_meas + m; spins_out_dev and
+ * dlnpsi_dev may be NULL).  The sampling chains' state advances exactly as
+ * under vp_sample. */
+vp_status vp_sample_split(vp_ctx* ctx, int32_t lat_sample, int32_t lat_measure, int32_t n_burn, int32_t n_meas,
+                          double* log_abs_psi_dev, int8_t* sign_dev, double* e_loc_dev, void* dlnpsi_dev,
+                          int8_t* spins_out_dev);
+
 /* Psi(S')/Psi(S) for the flip of all four spins of every plaquette (y, x)
  * (sites (y,x), (y,x+1), (y+1,x), (y+1,x+1)) that holds two up and two down
  * spins; ratios_dev [n_cfg][(Ly-1)(Lx-1)] float64, 0 for the other plaquettes.

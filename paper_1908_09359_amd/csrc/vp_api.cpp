@@ -449,21 +449,25 @@ vp_status check_configs(vp_ctx* ctx, const Lattice& L, const int8_t* spins_dev, 
   return VP_OK;
 }
 
-// The evaluation pass on fixed configurations with the outputs of o; reports
-// device-side errors synchronously.
-vp_status eval_configs(vp_ctx* ctx, Lattice* L, const int8_t* spins_dev, int32_t n_cfg, SampleOut o) {
+// The evaluation pass on fixed configurations with the outputs of o (row
+// i * n_meas + row for configuration i); reports device-side errors
+// synchronously.  `validate` checks the configurations on the host first.
+vp_status eval_configs(vp_ctx* ctx, Lattice* L, const int8_t* spins_dev, int32_t n_cfg, SampleOut o,
+                       int32_t n_meas = 1, int32_t row = 0, bool validate = true) {
   if (!L->tensors_ready) return fail(ctx, VP_ERR_ARG, "tensors must be set first");
   if (n_cfg < 1 || n_cfg > L->p.n_chains) return fail(ctx, VP_ERR_ARG, "need 1 <= n_cfg <= n_chains");
-  vp_status st = check_configs(ctx, *L, spins_dev, n_cfg);
-  if (st != VP_OK) return st;
+  if (validate) {
+    vp_status st = check_configs(ctx, *L, spins_dev, n_cfg);
+    if (st != VP_OK) return st;
+  }
   hipStream_t s = ctx->stream;
   // Evaluation reuses the chain slots; the sampler's state is invalidated.
   launch_copy_spins(L->dev, spins_dev, n_cfg, s);
   LatDev D = L->dev;
   D.n_chains = n_cfg;
   const vp_lattice& p = L->p;
-  o.n_meas = 1;
-  o.m = 0;
+  o.n_meas = n_meas;
+  o.m = row;
   o.np_half = L->Np / 2;
   o.n_pairs = p.Ly * (p.Lx - 1) + (p.Ly - 1) * p.Lx + (p.J2 != 0.0 ? 2 * (p.Ly - 1) * (p.Lx - 1) : 0);
   if (works_f64(p.prec)) run_eval<double>(D, o, n_cfg, s); else run_eval<float>(D, o, n_cfg, s);
@@ -870,6 +874,50 @@ vp_status vp_eval(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev, int32_t n_c
   o.dlnpsi = dlnpsi_dev;
   o.ratios = ratios_dev;
   return eval_configs(ctx, L, spins_dev, n_cfg, o);
+}
+
+vp_status vp_sample_split(vp_ctx* ctx, int32_t lat_sample, int32_t lat_measure, int32_t n_burn, int32_t n_meas,
+                          double* log_abs_psi_dev, int8_t* sign_dev, double* e_loc_dev, void* dlnpsi_dev,
+                          int8_t* spins_out_dev) {
+  Lattice* A = get_lat(ctx, lat_sample);
+  Lattice* M = get_lat(ctx, lat_measure);
+  if (!A || !M || lat_sample == lat_measure) return fail(ctx, VP_ERR_ARG, "need two distinct lattice indices");
+  if (n_burn < 0 || n_meas < 0) return fail(ctx, VP_ERR_ARG, "negative sweep count");
+  const vp_lattice& pa = A->p;
+  const vp_lattice& pm = M->p;
+  if (pa.Ly != pm.Ly || pa.Lx != pm.Lx || pa.D != pm.D || pa.J1 != pm.J1 || pa.J2 != pm.J2 || pa.prec != pm.prec)
+    return fail(ctx, VP_ERR_SHAPE, "the sampling and measuring lattices may differ only in Dc and chain count");
+  if (pm.n_chains < pa.n_chains)
+    return fail(ctx, VP_ERR_SHAPE, "the measuring lattice needs at least as many chains as the sampling one");
+  if (!A->tensors_ready || !A->chains_ready || !M->tensors_ready)
+    return fail(ctx, VP_ERR_ARG, "tensors of both lattices and the sampling chains must be set first");
+  if (n_meas > 0 && (!log_abs_psi_dev || !sign_dev || !e_loc_dev))
+    return fail(ctx, VP_ERR_ARG, "log_abs_psi, sign and e_loc outputs are required");
+  hipStream_t s = ctx->stream;
+  const bool f64 = works_f64(pa.prec);
+  if (!A->lower_valid) {
+    if (f64) run_lower_pass<double>(ctx, *A, s); else run_lower_pass<float>(ctx, *A, s);
+    A->lower_valid = true;
+  }
+  for (int i = 0; i < n_burn + n_meas; ++i) {
+    // a sweep at the sampling cutoff (its bottom-up pass rebuilds the lower
+    // boundaries the next sweep needs), then the chains' states measured at
+    // the measuring cutoff
+    if (f64) run_sweep<double>(ctx, *A, nullptr, s); else run_sweep<float>(ctx, *A, nullptr, s);
+    HIP_TRY(ctx, hipGetLastError());
+    if (i >= n_burn) {
+      SampleOut o{};
+      o.log_abs_psi = log_abs_psi_dev;
+      o.sign = sign_dev;
+      o.e_loc = e_loc_dev;
+      o.dlnpsi = dlnpsi_dev;
+      o.spins = spins_out_dev;
+      vp_status st = eval_configs(ctx, M, A->spins, pa.n_chains, o, n_meas, i - n_burn, false);
+      if (st != VP_OK) return st;
+    }
+  }
+  A->sweeps += n_burn + n_meas;
+  return check_flags(ctx, *A);
 }
 
 vp_status vp_plaquette_ratios(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev, int32_t n_cfg,
