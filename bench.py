@@ -220,6 +220,35 @@ class Path:
         self.ctx.close()
 
 
+def split_run(B, torch, Ly, Lx, D, Dc1, Dc2, nch, warmup, steps, seed=9359):
+    """Two cutoffs: bf16-operand sampling at Dc1, float64 measurement at Dc2 (vp_sample_split)."""
+    dev = torch.device("cuda:0")
+    ctx = B.Context([B.lattice(Ly, Lx, D, Dc1, 1.0, 0.0, B.VP_BF16, nch),
+                     B.lattice(Ly, Lx, D, Dc2, 1.0, 0.0, B.VP_BF16, nch)], seed=seed)
+    ctx.vp_init_tensors(0, seed=1908, scale=0.0, perturb=0.0)
+    T = torch.empty(ctx.num_params(0), dtype=torch.float64, device=dev)
+    ctx.vp_get_tensors(0, T)
+    ctx.vp_set_tensors(1, T)
+    ctx.vp_init_chains(0, None)
+    lp = torch.empty(nch * steps, dtype=torch.float64, device=dev)
+    sg = torch.empty(nch * steps, dtype=torch.int8, device=dev)
+    el = torch.empty(nch * steps, dtype=torch.float64, device=dev)
+    dl = torch.empty((nch * steps, ctx.num_params(1) // 2), dtype=torch.float64, device=dev)
+    ctx.vp_sample_split(0, 1, warmup, 1, lp[:nch], sg[:nch], el[:nch], dl[:nch])
+    ctx.vp_sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.vp_sample_split(0, 1, 0, steps, lp, sg, el, dl)
+    ctx.vp_sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    e = float(el.mean().item()) / (Ly * Lx)
+    ctx.close()
+    return {"workload": f"{Ly}x{Lx} Heisenberg D={D}, sampling Dc1={Dc1} (bf16-operand 2-row steps), "
+                        f"measurement Dc2={Dc2} (float64), {nch} chains",
+            "samples_per_s": nch * steps / dt, "ms_per_step": dt / steps * 1e3, "e_site_mean": e}
+
+
 def roofline(ms, launches, flops, fp64_phases, path):
     """The phase with the largest share of the timed sweeps among those with an algorithmic
     flop count: its flops over the timed region / its summed live launch time."""
@@ -247,6 +276,8 @@ def main():
     ap.add_argument("--train-sweeps", type=int, default=2)
     ap.add_argument("--train-epochs", type=int, default=4)
     ap.add_argument("--tau-sweeps", type=int, default=0)
+    ap.add_argument("--split-dc2", type=int, default=0,
+                    help="also time two-cutoff sampling (Dc1 = --Dc, Dc2 = this) on the --L, --D lattice")
     ap.add_argument("--only", choices=["both", "plain", "learned"], default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
@@ -328,6 +359,8 @@ def main():
             def cost(t):
                 return 2.0 * t["tau_int_mean"] / t["samples_per_s"]
             out["learned_over_plain_at_fixed_dE"] = cost(res["plain"]["tau"]) / cost(res["learned"]["tau"])
+    if args.split_dc2:
+        out["split_cutoffs"] = split_run(B, torch, Ly, Lx, D, Dc, args.split_dc2, nch, args.warmup, args.steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(Ly, Lx, D, Dc, seed=1908)
     print(json.dumps(out), flush=True)

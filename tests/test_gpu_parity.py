@@ -43,6 +43,7 @@ def _compare(g, o, N, tol_e, tol_lp, tol_rel):
     (4, 4, 6, 12, 0.0, 2),    # fused MFMA 2-row step, D=6 Dc=12 (padded 16x16 tiles)
     (4, 4, 8, 16, 0.5, 2),    # fused MFMA 2-row step, D=8 Dc=16
     (2, 4, 8, 16, 0.0, 2),
+    (4, 4, 5, 18, 0.0, 2),    # more than 16 kept vectors in the eigensolver (Dc = 18 at bonds of dim 25)
 ])
 def test_eval_fp64_parity(Ly, Lx, D, Dc, J2, ncfg):
     B = _B()
