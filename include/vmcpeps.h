@@ -281,6 +281,17 @@ vp_status vp_sr_update(vp_ctx* ctx, int32_t lat, const double* e_loc_dev, const 
  * (p, step, 0, 5) per element p. */
 vp_status vp_sign_sgd_update(vp_ctx* ctx, int32_t lat, const double* grad_dev, double step_len, uint64_t step);
 
+/* Algorithm 1 for n_steps optimisation steps: each step runs vp_sample
+ * (n_burn sweeps, then n_meas measured sweeps of every chain), the Eq. (5)
+ * gradient over the n_chains * n_meas samples and the Eq. (10) update with
+ * step length delta_host[i] and random counter step0 + i (Sec. II.B uses
+ * 0.005, 0.002, 0.001 and 0.0005 in successive stages).  e_mean_host
+ * [n_steps] (may be NULL) receives each step's mean E_loc, measured before
+ * its update.  Allocates the samples of one step for the call and waits for
+ * completion. */
+vp_status vp_optimize(vp_ctx* ctx, int32_t lat, int32_t n_steps, int32_t n_burn, int32_t n_meas,
+                      const double* delta_host, uint64_t step0, double* e_mean_host);
+
 /* Integrated autocorrelation time of each chain's measurement series with
  * Sokal's automatic window (Madras & Sokal, J. Stat. Phys. 50, 1988): rho(t)
  * is the normalised autocovariance of the chain, tau(M) = 1/2 + sum_{t=1..M}

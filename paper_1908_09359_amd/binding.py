@@ -26,7 +26,7 @@ EXPORTED = ["vp_create", "vp_destroy", "vp_last_error", "vp_num_params", "vp_wor
             "vp_timing_enable", "vp_timing_read", "vp_stats_tau", "vp_trace_ratios", "vp_plaquette_ratios",
             "vp_proposal_num_params", "vp_proposal_set_weights", "vp_proposal_get_weights", "vp_proposal_forward",
             "vp_proposal_loss_grad", "vp_proposal_train", "vp_set_sampler", "vp_move_counts", "vp_set_schedule",
-            "vp_sample_batch", "vp_autotune", "vp_sample_split"]
+            "vp_sample_batch", "vp_autotune", "vp_sample_split", "vp_optimize"]
 
 PHASES = ["row3_envs", "hsweep", "row4_envs", "vsweep", "compress_up", "compress_down", "measure3",
           "measure4", "other"]
@@ -89,6 +89,7 @@ def _load():
         "vp_set_schedule": ([P, I32, I32], I32),
         "vp_sample_batch": ([P, I32, P, I32, I32, P], I32),
         "vp_sample_split": ([P, I32, I32, I32, I32, P, P, P, P, P], I32),
+        "vp_optimize": ([P, I32, I32, I32, I32, P, ctypes.c_uint64, P], I32),
         "vp_autotune": ([P, I32, I32, P, P], I32),
     }
     for name, (args, res) in sig.items():
@@ -242,6 +243,13 @@ class Context:
                         spins_out=None):
         self._check(LIB.vp_sample_split(self.h, lat_sample, lat_measure, n_burn, n_meas, _ptr(log_abs_psi),
                                         _ptr(sign), _ptr(e_loc), _ptr(dlnpsi), _ptr(spins_out)))
+
+    def vp_optimize(self, lat, deltas, n_burn, n_meas, step0=0):
+        """Algorithm 1 with step lengths `deltas` (one per step); returns the step energies (mean E_loc)."""
+        d = (ctypes.c_double * len(deltas))(*[float(x) for x in deltas])
+        e = (ctypes.c_double * len(deltas))()
+        self._check(LIB.vp_optimize(self.h, lat, len(deltas), n_burn, n_meas, d, ctypes.c_uint64(step0), e))
+        return list(e)
 
     def vp_eval(self, lat, spins, n_cfg, log_abs_psi, sign, e_loc, dlnpsi=None, ratios=None):
         self._check(LIB.vp_eval(self.h, lat, _ptr(spins), n_cfg, _ptr(log_abs_psi), _ptr(sign), _ptr(e_loc),

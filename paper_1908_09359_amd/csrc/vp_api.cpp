@@ -1114,6 +1114,48 @@ vp_status vp_sign_sgd_update(vp_ctx* ctx, int32_t lat, const double* grad_dev, d
   return stage_tensors(ctx, *L);
 }
 
+vp_status vp_optimize(vp_ctx* ctx, int32_t lat, int32_t n_steps, int32_t n_burn, int32_t n_meas,
+                      const double* delta_host, uint64_t step0, double* e_mean_host) {
+  Lattice* L = get_lat(ctx, lat);
+  if (!L || !delta_host) return fail(ctx, VP_ERR_ARG, "bad lattice index or null step lengths");
+  if (n_steps < 0 || n_burn < 0 || n_meas < 1)
+    return fail(ctx, VP_ERR_ARG, "need n_steps >= 0, n_burn >= 0, n_meas >= 1");
+  const int64_t n = (int64_t)L->p.n_chains * n_meas;
+  const size_t wsz = type_size(L->p.prec);
+  // the samples of one step, the gradient and the mean energy: allocated for the call
+  double *lp = nullptr, *el = nullptr, *grad = nullptr, *em = nullptr;
+  int8_t *sg = nullptr, *so = nullptr;
+  void* dl = nullptr;
+  auto release = [&]() {
+    void* ps[] = {lp, el, grad, em, sg, so, dl};
+    for (void* q : ps)
+      if (q) hipFree(q);
+  };
+  if (hipMalloc((void**)&lp, sizeof(double) * n) != hipSuccess ||
+      hipMalloc((void**)&el, sizeof(double) * n) != hipSuccess ||
+      hipMalloc((void**)&grad, sizeof(double) * L->Np) != hipSuccess ||
+      hipMalloc((void**)&em, sizeof(double)) != hipSuccess || hipMalloc((void**)&sg, n) != hipSuccess ||
+      hipMalloc((void**)&so, n * L->N) != hipSuccess || hipMalloc(&dl, wsz * n * (L->Np / 2)) != hipSuccess) {
+    release();
+    return fail(ctx, VP_ERR_OOM, "optimisation buffers");
+  }
+  vp_status st = VP_OK;
+  for (int i = 0; i < n_steps && st == VP_OK; ++i) {
+    // Algorithm 1: sample, Eq. (5) gradient, Eq. (10) update
+    st = vp_sample(ctx, lat, n_burn, n_meas, lp, sg, el, dl, so, nullptr);
+    if (st == VP_OK) st = vp_gradient(ctx, lat, el, dl, so, n, grad, em);
+    if (st == VP_OK && e_mean_host) {
+      if (hipMemcpyAsync(e_mean_host + i, em, sizeof(double), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+          hipStreamSynchronize(ctx->stream) != hipSuccess)
+        st = fail(ctx, VP_ERR_DEVICE, "reading the step energy failed");
+    }
+    if (st == VP_OK) st = vp_sign_sgd_update(ctx, lat, grad, delta_host[i], step0 + (uint64_t)i);
+  }
+  hipStreamSynchronize(ctx->stream);
+  release();
+  return st;
+}
+
 vp_status vp_stats_tau(const double* x, int32_t n_chains, int32_t len, double c, double* tau, double* mean_out,
                        double* stderr_out) {
   if (!x || !tau || !mean_out || !stderr_out || n_chains < 1 || len < 2 || !(c > 0))
