@@ -1,11 +1,16 @@
 // Leading eigenpairs of a small symmetric matrix, one work-group per matrix.
 //
 // Householder tridiagonalisation (the unblocked symmetric reduction of Golub &
-// Van Loan, Sec. 8.3.1) on the packed lower triangle held in LDS, eigenvalues
-// of the tridiagonal matrix by Sturm-count multisection (16 probes per
-// eigenvalue and step), eigenvectors of the tridiagonal matrix by inverse
-// iteration with partial-pivoting LU (Wilkinson), modified Gram-Schmidt among
-// the kept vectors, and back-transformation by the stored reflectors.
+// Van Loan, Sec. 8.3.1) with the matrix in registers, eigenvalues of the
+// tridiagonal matrix by Sturm-count multisection (16 probes per eigenvalue and
+// step), eigenvectors of the tridiagonal matrix by inverse iteration with
+// partial-pivoting LU (Wilkinson), classical Gram-Schmidt (twice) among the
+// kept vectors, and back-transformation by the stored reflectors.
+//
+// Global and LDS data are addressed through address-space-qualified pointers
+// wherever the compiler cannot infer the space: a generic (flat) access counts
+// on the LDS wait counter as well, so every later LDS wait would also wait for
+// outstanding global stores.
 #pragma once
 #include "vp_device.hpp"
 
@@ -14,16 +19,15 @@ namespace vp {
 constexpr int EIG_NMAX = 128;
 constexpr int EIG_KMAX = 16;   // eigenvectors per inverse-iteration batch (one thread each)
 constexpr int EIG_PACK = EIG_NMAX * (EIG_NMAX + 1) / 2;
-// LDS the caller provides: the packed matrix; afterwards the same space holds
-// the LU factors (3 x n x EIG_KMAX), the kept vectors (n x EIG_KMAX) and the
-// pivot-swap bit words (n).
+// LDS the caller provides: a first block (the size of a packed matrix) that
+// holds the LU factors (3 x n x EIG_KMAX) and the kept vectors (n x EIG_KMAX).
 // Small work arrays follow the packed matrix: d, e, e^2, tau, p, w, v (7 n),
 // two spare rows (2 n), the multisection probes and counts (2 WG) and the batch
 // eigenvalues (EIG_KMAX).
 constexpr size_t EIG_PACK_BYTES = sizeof(double) * EIG_PACK;
 constexpr size_t EIG_SMALL_BYTES = sizeof(double) * (9 * EIG_NMAX + WG + EIG_KMAX) + sizeof(int) * WG;
 constexpr size_t EIG_LDS_BYTES = EIG_PACK_BYTES + EIG_SMALL_BYTES;
-static_assert(3 * EIG_NMAX * EIG_KMAX * 8 + EIG_NMAX * EIG_KMAX * 8 + EIG_NMAX * 4 <= EIG_PACK_BYTES, "eig LDS");
+static_assert(3 * EIG_NMAX * EIG_KMAX * 8 + EIG_NMAX * EIG_KMAX * 8 <= EIG_PACK_BYTES, "eig LDS");
 
 __device__ inline int tri(int i) { return i * (i + 1) / 2; }
 
@@ -50,6 +54,7 @@ __device__ inline int sturm_count(const double* d, const double* e2, int n, doub
 }
 
 typedef __attribute__((address_space(3))) double lds_f64;
+typedef __attribute__((address_space(1))) double gbl_f64;
 
 // x from the lane given by the DPP control `ctrl` within its row of 16 lanes.
 template <int CTRL>
@@ -58,16 +63,6 @@ __device__ inline double dpp_f64(double x) {
   const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
   const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, false);
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-// Sum over the 16 lanes of a row, returned to all of them: quad_perm [1,0,3,2]
-// and [2,3,0,1] sum each quad, row_half_mirror pairs the quads of each half,
-// row_mirror the halves.
-__device__ inline double row16_sum(double x) {
-  x += dpp_f64<0xB1>(x);
-  x += dpp_f64<0x4E>(x);
-  x += dpp_f64<0x141>(x);
-  x += dpp_f64<0x140>(x);
-  return x;
 }
 
 // Householder tridiagonalisation Q^T A Q = T, Q = H_0 H_1 ... H_{n-3}.
@@ -84,8 +79,8 @@ __device__ inline double row16_sum(double x) {
 // EIG_NMAX doubles, red: 36 doubles of LDS.  Column i and its norms alternate
 // between two buffers, so a step needs two barriers.  All threads of the
 // work-group call it.
-__device__ __noinline__ void eig_tridiag(const double* H, int n, lds_f64* dg, lds_f64* eg, lds_f64* tau,
-                                         lds_f64* xc0, lds_f64* xc1, lds_f64* pv, lds_f64* red, double* refl) {
+__device__ __noinline__ void eig_tridiag(const gbl_f64* H, int n, lds_f64* dg, lds_f64* eg, lds_f64* tau,
+                                         lds_f64* xc0, lds_f64* xc1, lds_f64* pv, lds_f64* red, gbl_f64* refl) {
   const int tid = threadIdx.x;
   const int br = tid >> 4, bc = tid & 15, lane = tid & 63, wave = tid >> 6;
   double a[8][8];
@@ -100,6 +95,7 @@ __device__ __noinline__ void eig_tridiag(const double* H, int n, lds_f64* dg, ld
   // the column and p live in LDS with element 8 b + q in slot 16 q + b, so that
   // the 16 lanes of a row (b = bc) read 16 consecutive words
   auto slot = [](int r) { return (r & 7) * 16 + (r >> 3); };
+  const int tri_tid = tri(tid);
   // column i of the current matrix, as held by its owners (bc == i / 8); taken
   // inside a statically unrolled column loop under a uniform condition
   double xo[8];
@@ -135,28 +131,48 @@ __device__ __noinline__ void eig_tridiag(const double* H, int n, lds_f64* dg, ld
       scal = 1.0 / (alpha - beta);
     }
     if (tid == 0) { dg[i] = xcol[slot(i)]; eg[i] = beta; tau[i] = t; }
-    if (owner) {  // the owners hold column i: store the reflector's entries of their rows
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int r = 8 * br + q;
-        if (r > i && r < n) refl[tri(r) + i] = (r == i + 1) ? 1.0 : xo[q] * scal;
-      }
-    }
+    if (tid > i && tid < n)  // reflector entry of row tid, from the published column
+      refl[tri_tid + i] = (tid == i + 1) ? 1.0 : (double)xcol[slot(tid)] * scal;
     if (t != 0.0) {  // uniform
-      double vc[8], vr[8], pr[8];
+      // all 16 column entries are read before any is used (every slot holds a
+      // value: rows beyond n are zero), so the reads overlap
+      double xcv[8], xrv[8], vc[8], vr[8], pr[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        const int rc = 8 * bc + q, rr = 8 * br + q;
-        vc[q] = rc == i + 1 ? 1.0 : ((rc > i + 1 && rc < n) ? (double)xcol[16 * q + bc] * scal : 0.0);
-        vr[q] = rr == i + 1 ? 1.0 : ((rr > i + 1 && rr < n) ? (double)xcol[16 * q + br] * scal : 0.0);
+        xcv[q] = xcol[16 * q + bc];
+        xrv[q] = xcol[16 * q + br];
       }
+      // v on the tile's columns and rows: 1 at row i + 1, x scal beyond it up
+      // to n, 0 elsewhere (selects, no branches); indices relative to the tile
+      const int uc = i + 1 - 8 * bc, nc = n - 8 * bc, ur = i + 1 - 8 * br, nr = n - 8 * br;
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        double acc = 0.0;
-#pragma unroll
-        for (int c = 0; c < 8; ++c) acc += a[q][c] * vc[c];
-        pr[q] = row16_sum(acc) * t;
+        const double xc = xcv[q] * scal, xr = xrv[q] * scal;
+        vc[q] = ((q > uc) & (q < nc)) ? xc : 0.0;
+        vr[q] = ((q > ur) & (q < nr)) ? xr : 0.0;
+        vc[q] = q == uc ? 1.0 : vc[q];
+        vr[q] = q == ur ? 1.0 : vr[q];
       }
+      // the eight row products advance together, then their sums over the 16
+      // lanes of the row stage by stage (quad_perm [1,0,3,2] and [2,3,0,1] sum
+      // each quad, row_half_mirror pairs the quads of each half, row_mirror the
+      // halves), so that consecutive instructions are independent
+#pragma unroll
+      for (int q = 0; q < 8; ++q) pr[q] = 0.0;
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) pr[q] += a[q][c] * vc[c];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) pr[q] += dpp_f64<0xB1>(pr[q]);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) pr[q] += dpp_f64<0x4E>(pr[q]);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) pr[q] += dpp_f64<0x141>(pr[q]);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) pr[q] += dpp_f64<0x140>(pr[q]);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) pr[q] *= t;
       double part = 0.0;
 #pragma unroll
       for (int q = 0; q < 8; ++q) part += pr[q] * vr[q];
@@ -173,11 +189,14 @@ __device__ __noinline__ void eig_tridiag(const double* H, int n, lds_f64* dg, ld
 #pragma unroll
       for (int q = 0; q < 8; ++q) pr[q] += K * vr[q];  // w on the tile's rows
       const int cn = (i + 1) & 7;  // column of the next step within its tile
+      double pc[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) pc[c] = pv[16 * c + bc];
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
-        const double wc = (double)pv[16 * c + bc] + K * vc[c];  // w on the tile's columns
+        const double wc = pc[c] + K * vc[c];  // w on the tile's columns
 #pragma unroll
-        for (int q = 0; q < 8; ++q) a[q][c] -= vr[q] * wc + pr[q] * vc[c];
+        for (int q = 0; q < 8; ++q) a[q][c] = fma(-pr[q], vc[c], fma(-vr[q], wc, a[q][c]));
         if (c == cn) {
 #pragma unroll
           for (int q = 0; q < 8; ++q) xo[q] = a[q][c];
@@ -219,7 +238,7 @@ __device__ __noinline__ void eig_tridiag(const double* H, int n, lds_f64* dg, ld
   __syncthreads();
 }
 
-// H: n x n symmetric, row-major (ld n), any address space; n <= EIG_NMAX.
+// H: n x n symmetric, row-major (ld n), in global memory; n <= EIG_NMAX.
 // Writes the eigenvectors of the k largest eigenvalues, in descending order,
 // as columns 0..k-1 of V (ld k) and the eigenvalues to lam[0..k-1].
 // refl: global scratch of at least EIG_PACK doubles (Householder vectors);
@@ -227,7 +246,6 @@ __device__ __noinline__ void eig_tridiag(const double* H, int n, lds_f64* dg, ld
 __device__ __forceinline__ void sym_topk_eig(const double* H, int n, int k, double* V, double* lam, double* refl, char* lds) {
   double* Ap = reinterpret_cast<double*>(lds);
   double* Xs = Ap + 3 * EIG_NMAX * EIG_KMAX;                            // after the tridiagonalisation
-  unsigned* pivw = reinterpret_cast<unsigned*>(Xs + EIG_NMAX * EIG_KMAX);  // bit t: row swap of vector t
   double* dg = reinterpret_cast<double*>(lds + EIG_PACK_BYTES);
   double* eg = dg + EIG_NMAX;
   double* e2 = eg + EIG_NMAX;
@@ -241,8 +259,8 @@ __device__ __forceinline__ void sym_topk_eig(const double* H, int n, int k, doub
   const int tid = threadIdx.x;
 
   // ---- tridiagonalisation (out of line: its register tile needs the whole register budget)
-  eig_tridiag(H, n, (lds_f64*)(dg), (lds_f64*)(eg), (lds_f64*)(tau), (lds_f64*)(wv), (lds_f64*)(vv),
-              (lds_f64*)(pv), (lds_f64*)(probe_x), refl);
+  eig_tridiag((const gbl_f64*)H, n, (lds_f64*)(dg), (lds_f64*)(eg), (lds_f64*)(tau), (lds_f64*)(wv),
+              (lds_f64*)(vv), (lds_f64*)(pv), (lds_f64*)(probe_x), (gbl_f64*)refl);
   for (int j = tid; j < n; j += WG) e2[j] = eg[j] * eg[j];
 
   // ---- Gershgorin interval and pivot floor
@@ -295,36 +313,43 @@ __device__ __forceinline__ void sym_topk_eig(const double* H, int n, int k, doub
     double* U0 = Ap;                               // reciprocal pivots
     double* U1 = Ap + 1 * EIG_NMAX * EIG_KMAX;     // first superdiagonal of U
     double* ML = Ap + 2 * EIG_NMAX * EIG_KMAX;     // multipliers
-    for (int j = tid; j < n; j += WG) pivw[j] = 0u;
-    __syncthreads();
     if (tid < kb) {
       const int col = b0 + tid;
       const double lm = lamb[tid];
 #define IX(j) ((j) * EIG_KMAX + tid)
       // Gaussian elimination with partial pivoting of T - lm I; a swap of rows j
-      // and j+1 puts the known entry e[j+1] on the second superdiagonal.
+      // and j+1 puts the known entry e[j+1] on the second superdiagonal.  The
+      // swaps are kept as bits in registers (bit j % 32 of word j / 32), and
+      // the entries a step needs are read one step ahead.
+      unsigned pb[EIG_NMAX / 32];
       double aa = dg[0] - lm, cc = n > 1 ? eg[0] : 0.0;
-      #pragma unroll 4
-      for (int j = 0; j < n - 1; ++j) {
-        const double bb = eg[j];
-        const double a1 = dg[j + 1] - lm;
-        const double c1 = (j + 1 < n - 1) ? eg[j + 1] : 0.0;
-        if (fabs(aa) >= fabs(bb)) {
-          const double piv = fabs(aa) < tiny ? (aa < 0.0 ? -tiny : tiny) : aa;
-          const double ip = recip(piv);
-          const double m = bb * ip;
-          U0[IX(j)] = ip; U1[IX(j)] = cc; ML[IX(j)] = m;
-          aa = a1 - m * cc;
-          cc = c1;
-        } else {
-          const double ib = recip(bb);
-          const double m = aa * ib;
-          U0[IX(j)] = ib; U1[IX(j)] = a1; ML[IX(j)] = m;
-          atomicOr(&pivw[j], 1u << tid);
-          const double naa = cc - m * a1;
-          cc = -m * c1;
-          aa = naa;
+      double bb = cc, dn = dg[min(1, n - 1)], en = eg[min(1, n - 1)];  // e_j, d_{j+1}, e_{j+1}
+#pragma unroll
+      for (int w = 0; w < EIG_NMAX / 32; ++w) {
+        unsigned bits = 0u;
+#pragma unroll 4
+        for (int jj = 0; jj < 32; ++jj) {
+          const int j = 32 * w + jj;
+          if (j >= n - 1) break;
+          const double a1 = dn - lm;
+          const double c1 = (j + 1 < n - 1) ? en : 0.0;
+          dn = dg[min(j + 2, n - 1)];
+          en = eg[min(j + 2, n - 1)];
+          // no swap: pivot aa (kept away from zero), U row (aa, cc), next row
+          // (a1 - m cc, c1); swap: pivot bb, U row (bb, a1, e[j+1]), next row
+          // (cc - m a1, -m c1).  Both by selects, so the lanes do not diverge.
+          const bool sw = fabs(aa) < fabs(bb);
+          const double pa = fabs(aa) < tiny ? (aa < 0.0 ? -tiny : tiny) : aa;
+          const double ip = recip(sw ? bb : pa);
+          const double m = (sw ? aa : bb) * ip;
+          const double u1 = sw ? a1 : cc;
+          U0[IX(j)] = ip; U1[IX(j)] = u1; ML[IX(j)] = m;
+          bits |= (sw ? 1u : 0u) << jj;
+          aa = fma(-m, u1, sw ? cc : a1);
+          cc = sw ? -m * c1 : c1;
+          bb = c1;
         }
+        pb[w] = bits;
       }
       U0[IX(n - 1)] = recip(fabs(aa) < tiny ? (aa < 0.0 ? -tiny : tiny) : aa);
       // deterministic, eigenvector-dependent start vector
@@ -334,25 +359,47 @@ __device__ __forceinline__ void sym_topk_eig(const double* H, int n, int k, doub
         Xs[IX(j)] = 0.5 + (double)(h & 0xFFFF) / 65536.0;
       }
       for (int it = 0; it < 3; ++it) {
-        // forward elimination; the running entry j + 1 stays in a register
+        // forward elimination; the running entry j + 1 stays in a register and
+        // the next step's operands are read one step ahead
         double carry = Xs[IX(0)];
-        #pragma unroll 4
-        for (int j = 0; j < n - 1; ++j) {
-          double rj = carry, rj1 = Xs[IX(j + 1)];
-          if ((pivw[j] >> tid) & 1u) { double tt = rj; rj = rj1; rj1 = tt; }
-          Xs[IX(j)] = rj;
-          carry = rj1 - ML[IX(j)] * rj;
+        double nx = Xs[IX(min(1, n - 1))], nm = ML[IX(0)];
+#pragma unroll
+        for (int w = 0; w < EIG_NMAX / 32; ++w) {
+          const unsigned bits = pb[w];
+#pragma unroll 4
+          for (int jj = 0; jj < 32; ++jj) {
+            const int j = 32 * w + jj;
+            if (j >= n - 1) break;
+            double rj = carry, rj1 = nx;
+            const double m = nm;
+            nx = Xs[IX(min(j + 2, n - 1))];
+            nm = ML[IX(min(j + 1, n - 1))];
+            if ((bits >> jj) & 1u) { double tt = rj; rj = rj1; rj1 = tt; }
+            Xs[IX(j)] = rj;
+            carry = rj1 - m * rj;
+          }
         }
         Xs[IX(n - 1)] = carry;
+        // back substitution, operands of row j - 1 read while row j is solved
         double x1 = 0.0, x2 = 0.0, nrm = 0.0;
-        #pragma unroll 4
-        for (int j = n - 1; j >= 0; --j) {
-          const double u2 = ((pivw[j] >> tid) & 1u) && j + 1 < n - 1 ? eg[j + 1] : 0.0;
-          const double xj = (Xs[IX(j)] - U1[IX(j)] * x1 - u2 * x2) * U0[IX(j)];  // U0 holds 1/pivot
-          Xs[IX(j)] = xj;
-          x2 = x1;
-          x1 = xj;
-          nrm = fmax(nrm, fabs(xj));
+        double cx = Xs[IX(n - 1)], cu1 = U1[IX(n - 1)], cu0 = U0[IX(n - 1)], ce = eg[n - 1];
+#pragma unroll
+        for (int w = EIG_NMAX / 32 - 1; w >= 0; --w) {
+          const unsigned bits = pb[w];
+#pragma unroll 4
+          for (int jj = 31; jj >= 0; --jj) {
+            const int j = 32 * w + jj;
+            if (j > n - 1) continue;
+            const double xr = cx, u1 = cu1, u0 = cu0, e1 = ce;
+            const int jn = max(j - 1, 0);
+            cx = Xs[IX(jn)]; cu1 = U1[IX(jn)]; cu0 = U0[IX(jn)]; ce = eg[min(j, n - 1)];
+            const double u2 = (((bits >> jj) & 1u) && j + 1 < n - 1) ? e1 : 0.0;
+            const double xj = (xr - u1 * x1 - u2 * x2) * u0;  // U0 holds 1/pivot
+            Xs[IX(j)] = xj;
+            x2 = x1;
+            x1 = xj;
+            nrm = fmax(nrm, fabs(xj));
+          }
         }
         const double inv = nrm > 0.0 ? 1.0 / nrm : 1.0;
         for (int j = 0; j < n; ++j) Xs[IX(j)] *= inv;
@@ -373,66 +420,76 @@ __device__ __forceinline__ void sym_topk_eig(const double* H, int n, int k, doub
 
   // Vectors live in LDS (Xs, [j][t]) when k <= EIG_KMAX, else in V.
   const bool in_lds = k <= EIG_KMAX;
-  const int ld = in_lds ? EIG_KMAX : k;
-  double* Vw = in_lds ? Xs : V;
 
-  // ---- classical Gram-Schmidt, twice, over the kept vectors in descending order
-  for (int col = 1; col < k; ++col) {
-    for (int pass = 0; pass < 2; ++pass) {
-      // dots with every earlier vector: 16 lanes per earlier vector
-      for (int s0 = 0; s0 < col; s0 += WG / 16) {
-        const int sv = s0 + (tid >> 4);
-        double dp = 0.0;
-        if (sv < col)
-          for (int j = tid & 15; j < n; j += 16) dp += Vw[j * ld + sv] * Vw[j * ld + col];
+  // ---- classical Gram-Schmidt, twice, over the kept vectors in descending
+  // order, then unit norms; Vw is the LDS or the global copy of the vectors
+  auto orthonormalise = [&](auto* Vw, int ld) {
+    for (int col = 1; col < k; ++col) {
+      for (int pass = 0; pass < 2; ++pass) {
+        // dots with every earlier vector: 16 lanes per earlier vector
+        for (int s0 = 0; s0 < col; s0 += WG / 16) {
+          const int sv = s0 + (tid >> 4);
+          double dp = 0.0;
+          if (sv < col)
+            for (int j = tid & 15; j < n; j += 16) dp += Vw[j * ld + sv] * Vw[j * ld + col];
 #pragma unroll
-        for (int o = 8; o > 0; o >>= 1) dp += __shfl_xor(dp, o, 16);
-        if ((tid & 15) == 0 && sv < col) pv[sv] = dp;
+          for (int o = 8; o > 0; o >>= 1) dp += __shfl_xor(dp, o, 16);
+          if ((tid & 15) == 0 && sv < col) pv[sv] = dp;
+        }
+        __syncthreads();
+        for (int j = tid; j < n; j += WG) {
+          double x = Vw[j * ld + col];
+          for (int sv = 0; sv < col; ++sv) x -= pv[sv] * Vw[j * ld + sv];
+          Vw[j * ld + col] = x;
+        }
+        __syncthreads();
       }
-      __syncthreads();
-      for (int j = tid; j < n; j += WG) {
-        double x = Vw[j * ld + col];
-        for (int sv = 0; sv < col; ++sv) x -= pv[sv] * Vw[j * ld + sv];
-        Vw[j * ld + col] = x;
-      }
-      __syncthreads();
     }
-  }
-  for (int c0 = 0; c0 < k; c0 += WG / 16) {
-    const int col = c0 + (tid >> 4);
-    double nn = 0.0;
-    if (col < k)
-      for (int j = tid & 15; j < n; j += 16) nn += Vw[j * ld + col] * Vw[j * ld + col];
+    for (int c0 = 0; c0 < k; c0 += WG / 16) {
+      const int col = c0 + (tid >> 4);
+      double nn = 0.0;
+      if (col < k)
+        for (int j = tid & 15; j < n; j += 16) nn += Vw[j * ld + col] * Vw[j * ld + col];
 #pragma unroll
-    for (int o = 8; o > 0; o >>= 1) nn += __shfl_xor(nn, o, 16);
-    if ((tid & 15) == 0 && col < k) pv[col] = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
-  }
-  __syncthreads();
-  for (int e = tid; e < n * k; e += WG) {
-    const int j = e / k, col = e - j * k;
-    Vw[j * ld + col] *= pv[col];
-  }
-  __syncthreads();
+      for (int o = 8; o > 0; o >>= 1) nn += __shfl_xor(nn, o, 16);
+      if ((tid & 15) == 0 && col < k) pv[col] = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+    }
+    __syncthreads();
+    for (int e = tid; e < n * k; e += WG) {
+      const int j = e / k, col = e - j * k;
+      Vw[j * ld + col] *= pv[col];
+    }
+    __syncthreads();
+  };
+  const gbl_f64* rf = (const gbl_f64*)refl;
+  // entry tid of reflector i (zero outside rows i + 1 .. n - 1)
+  auto refl_entry = [&](int i) -> double { return (tid > i && tid < n) ? rf[tri(tid) + i] : 0.0; };
 
   // ---- back-transformation: x <- H_0 H_1 ... H_{n-3} x
   if (in_lds) {
+    orthonormalise((lds_f64*)Xs, EIG_KMAX);
     // the k <= 16 vectors in registers: thread t holds rows 8 (t / 16) .. +7 of
     // column t % 16; reflector i is staged in one of two LDS rows while the
-    // previous one is applied, and the column sums of v^T x alternate between
-    // two LDS rows, so one barrier per reflector suffices.
+    // previous one is applied (read from global memory one step before it is
+    // staged), and the column sums of v^T x alternate between two LDS rows, so
+    // one barrier per reflector suffices.
     const int col = tid & 15, rb = tid >> 4, wave = tid >> 6;
-    double* vb[2] = {vv, wv};
-    double* rs[2] = {pv, probe_x};  // [4 waves][16 columns] each
+    lds_f64* const vb0 = (lds_f64*)vv;
+    lds_f64* const vb1 = (lds_f64*)wv;
+    lds_f64* const rs0 = (lds_f64*)pv;       // [4 waves][16 columns] each
+    lds_f64* const rs1 = (lds_f64*)probe_x;
+    const lds_f64* xl = (const lds_f64*)Xs;
     double x[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int r = 8 * rb + q;
-      x[q] = (r < n && col < k) ? Xs[r * EIG_KMAX + col] : 0.0;
+      x[q] = (r < n && col < k) ? xl[r * EIG_KMAX + col] : 0.0;
     }
-    if (n >= 3 && tid < EIG_NMAX) vb[(n - 3) & 1][tid] = (tid > n - 3 && tid < n) ? refl[tri(tid) + n - 3] : 0.0;
+    if (n >= 3 && tid < EIG_NMAX) (((n - 3) & 1) ? vb1 : vb0)[tid] = refl_entry(n - 3);
+    double vnext = (n >= 4 && tid < EIG_NMAX) ? refl_entry(n - 4) : 0.0;
     __syncthreads();
     for (int i = n - 3; i >= 0; --i) {
-      const double* v = vb[i & 1];
+      const lds_f64* v = (i & 1) ? vb1 : vb0;
       double vr[8];
 #pragma unroll
       for (int q = 0; q < 8; ++q) vr[q] = v[8 * rb + q];
@@ -442,29 +499,34 @@ __device__ __forceinline__ void sym_topk_eig(const double* H, int n, int k, doub
       for (int q = 0; q < 8; ++q) part += vr[q] * x[q];
       part += __shfl_xor(part, 16, 64);
       part += __shfl_xor(part, 32, 64);
-      double* red = rs[i & 1];
+      lds_f64* red = (i & 1) ? rs1 : rs0;
       if ((tid & 63) < 16) red[wave * 16 + col] = part;
-      // stage reflector i - 1 (every reader of that row has passed the previous barrier)
-      if (i >= 1 && tid < EIG_NMAX) vb[(i - 1) & 1][tid] = (tid > i - 1 && tid < n) ? refl[tri(tid) + i - 1] : 0.0;
+      // stage reflector i - 1 (every reader of that row has passed the previous
+      // barrier) and read reflector i - 2
+      if (i >= 1 && tid < EIG_NMAX) (((i - 1) & 1) ? vb1 : vb0)[tid] = vnext;
+      if (i >= 2 && tid < EIG_NMAX) vnext = refl_entry(i - 2);
       __syncthreads();
       const double f = t * ((red[col] + red[16 + col]) + (red[32 + col] + red[48 + col]));
 #pragma unroll
       for (int q = 0; q < 8; ++q) x[q] -= f * vr[q];
     }
+    gbl_f64* Vg = (gbl_f64*)V;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
       const int r = 8 * rb + q;
-      if (r < n && col < k) V[(int64_t)r * k + col] = x[q];
+      if (r < n && col < k) Vg[(int64_t)r * k + col] = x[q];
     }
     __syncthreads();
     return;
   }
-  // more than 16 vectors: reflector i streamed from global memory into LDS, the
-  // next one prefetched into a register while the current one is applied
-  double vreg = (n >= 3 && tid > n - 3 && tid < n) ? refl[tri(tid) + n - 3] : 0.0;
+  // more than 16 vectors, in V: reflector i staged in LDS, the next one read
+  // into a register while the current one is applied
+  gbl_f64* Vg = (gbl_f64*)V;
+  orthonormalise(Vg, k);
+  double vreg = (n >= 3 && tid < EIG_NMAX) ? refl_entry(n - 3) : 0.0;
   for (int i = n - 3; i >= 0; --i) {
-    if (tid < n) vv[tid] = tid > i ? vreg : 0.0;
-    if (i >= 1 && tid > i - 1 && tid < n) vreg = refl[tri(tid) + i - 1];
+    if (tid < n) vv[tid] = vreg;
+    if (i >= 1 && tid < EIG_NMAX) vreg = refl_entry(i - 1);
     __syncthreads();
     const double t = tau[i];
     if (t != 0.0) {
@@ -472,7 +534,7 @@ __device__ __forceinline__ void sym_topk_eig(const double* H, int n, int k, doub
         const int col = c0 + (tid >> 4);
         double dp = 0.0;
         if (col < k)
-          for (int r = i + 1 + (tid & 15); r < n; r += 16) dp += vv[r] * Vw[r * ld + col];
+          for (int r = i + 1 + (tid & 15); r < n; r += 16) dp += vv[r] * Vg[r * k + col];
 #pragma unroll
         for (int o = 8; o > 0; o >>= 1) dp += __shfl_xor(dp, o, 16);
         if ((tid & 15) == 0 && col < k) pv[col] = t * dp;
@@ -481,15 +543,8 @@ __device__ __forceinline__ void sym_topk_eig(const double* H, int n, int k, doub
       for (int e = tid; e < (n - i - 1) * k; e += WG) {
         const int rr = e / k, col = e - rr * k;
         const int r = i + 1 + rr;
-        Vw[r * ld + col] -= pv[col] * vv[r];
+        Vg[r * k + col] -= pv[col] * vv[r];
       }
-    }
-    __syncthreads();
-  }
-  if (in_lds) {
-    for (int e = tid; e < n * k; e += WG) {
-      const int j = e / k, col = e - j * k;
-      V[(int64_t)j * k + col] = Xs[j * EIG_KMAX + col];
     }
     __syncthreads();
   }
