@@ -13,6 +13,16 @@ namespace vp {
 
 constexpr int WG = 256;
 
+// Global-memory view of a pointer that addresses global memory.  Functions the
+// compiler keeps out of line receive plain (generic) pointers; their accesses
+// become flat instructions, which count on the LDS wait counter as well, so
+// every LDS wait behind a flat load or store also waits for global memory.
+// Accesses through this view are global instructions.
+template <typename T>
+__device__ inline __attribute__((address_space(1))) T* gmem(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
 // ---------------------------------------------------------------------------
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11), written from its
 // definition: ten rounds of two 64x64->128 products, word permutation and key
@@ -104,9 +114,12 @@ typedef __bf16 v8bf_g __attribute__((ext_vector_type(8)));
 // k-contiguous in LDS so that each lane fetches its 8 k-values of the
 // 16x16x32 MFMA in one read; the output layout is that of the f32 16x16x4.
 template <typename TC, typename TA, typename TB>
-__device__ void wg_gemm_bf16(char* tiles, TC* __restrict__ C, View vc, const TA* __restrict__ A, View va,
-                             const TB* __restrict__ B, View vb, int M, int N, int K, TC alpha,
+__device__ void wg_gemm_bf16(char* tiles, TC* __restrict__ C_p, View vc, const TA* __restrict__ A_p, View va,
+                             const TB* __restrict__ B_p, View vb, int M, int N, int K, TC alpha,
                              bool accumulate) {
+  auto* C = gmem(C_p);
+  const auto* A = gmem(A_p);
+  const auto* B = gmem(B_p);
   constexpr int BM = 64, BN = 64, BK = 32, LD = BK + 8;
   __bf16 (*As)[LD] = reinterpret_cast<__bf16 (*)[LD]>(tiles);
   __bf16 (*Bs)[LD] = reinterpret_cast<__bf16 (*)[LD]>(tiles + BM * LD * sizeof(__bf16));
@@ -156,7 +169,7 @@ __device__ void wg_gemm_bf16(char* tiles, TC* __restrict__ C, View vc, const TA*
           for (int r = 0; r < 4; ++r) {
             const int m = m0 + tr0 + 16 * a + 4 * (lane >> 4) + r;
             if (m < M) {
-              TC* cp = C + vaddr(vc, m, n);
+              auto* cp = C + vaddr(vc, m, n);
               *cp = accumulate ? *cp + alpha * (TC)acc[a][b][r] : alpha * (TC)acc[a][b][r];
             }
           }
@@ -167,9 +180,12 @@ __device__ void wg_gemm_bf16(char* tiles, TC* __restrict__ C, View vc, const TA*
 }
 
 template <typename TC, typename TA, typename TB>
-__device__ void wg_gemm_t(char* tiles, TC* __restrict__ C, View vc, const TA* __restrict__ A, View va,
-                          const TB* __restrict__ B, View vb, int M, int N, int K, TC alpha = TC(1),
+__device__ void wg_gemm_t(char* tiles, TC* __restrict__ C_p, View vc, const TA* __restrict__ A_p, View va,
+                          const TB* __restrict__ B_p, View vb, int M, int N, int K, TC alpha = TC(1),
                           bool accumulate = false) {
+  auto* C = gmem(C_p);
+  const auto* A = gmem(A_p);
+  const auto* B = gmem(B_p);
   constexpr int BM = 64, BN = 64, BK = 16, NA = (BM * BK) / WG, NB = (BN * BK) / WG;
   TC (*As)[BM + 1] = reinterpret_cast<TC (*)[BM + 1]>(tiles);
   TC (*Bs)[BN + 1] = reinterpret_cast<TC (*)[BN + 1]>(tiles + BK * (BM + 1) * sizeof(TC));
@@ -233,7 +249,7 @@ __device__ void wg_gemm_t(char* tiles, TC* __restrict__ C, View vc, const TA* __
           for (int r = 0; r < 4; ++r) {
             const int m = m0 + tr0 + 16 * a + mfma4_row(TC(0), lane, r);
             if (m < M) {
-              TC* cp = C + vaddr(vc, m, n);
+              auto* cp = C + vaddr(vc, m, n);
               *cp = accumulate ? *cp + alpha * acc[a][b][r] : alpha * acc[a][b][r];
             }
           }
@@ -305,7 +321,8 @@ __device__ inline void wg_fill(T* dst, T v, int n) {
 // Scale x by an exact power of two so that max|x| lies in [1, 2); returns the
 // exponent removed (0 for an all-zero tensor).  Exact in every precision.
 template <typename T>
-__device__ inline int wg_renorm(T* x, int n) {
+__device__ inline int wg_renorm(T* x_p, int n) {
+  auto* x = gmem(x_p);
   double m = 0.0;
   for (int i = threadIdx.x; i < n; i += WG) m = fmax(m, fabs((double)x[i]));
   m = wg_max(m);
@@ -318,7 +335,9 @@ __device__ inline int wg_renorm(T* x, int n) {
 }
 
 template <typename T>
-__device__ inline double wg_dot(const T* a, const T* b, int n) {
+__device__ inline double wg_dot(const T* a_p, const T* b_p, int n) {
+  const auto* a = gmem(a_p);
+  const auto* b = gmem(b_p);
   double s = 0.0;
   for (int i = threadIdx.x; i < n; i += WG) s += (double)a[i] * (double)b[i];
   return wg_sum(s);

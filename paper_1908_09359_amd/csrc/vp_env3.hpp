@@ -41,8 +41,13 @@ struct Env3Shape {
 };
 
 template <typename T, int D, int C>
-__device__ void env3_fused(T* __restrict__ Lout, const T* __restrict__ Lin, const T* __restrict__ A, S3 sA,
-                           const T* __restrict__ t, S4 st, const T* __restrict__ B, S3 sB, char* lds) {
+__device__ void env3_fused(T* __restrict__ Lout_p, const T* __restrict__ Lin_p, const T* __restrict__ A_p, S3 sA,
+                           const T* __restrict__ t_p, S4 st, const T* __restrict__ B_p, S3 sB, char* lds) {
+  auto* Lout = gmem(Lout_p);
+  const auto* Lin = gmem(Lin_p);
+  const auto* A = gmem(A_p);
+  const auto* t = gmem(t_p);
+  const auto* B = gmem(B_p);
   using Sh = Env3Shape<D, C>;
   static_assert(Sh::ok, "env3_fused: D*D = 64 and D*Dc = 128 only");
   using M = Mfma<T>;
@@ -153,8 +158,13 @@ __device__ void env3_fused(T* __restrict__ Lout, const T* __restrict__ Lin, cons
 }
 
 template <typename T, int D, int C>
-__device__ void defect3_fused(T* __restrict__ Out, const T* __restrict__ Lp, const T* __restrict__ A, S3 sA,
-                              const T* __restrict__ Rn, const T* __restrict__ B, S3 sB, char* lds) {
+__device__ void defect3_fused(T* __restrict__ Out_p, const T* __restrict__ Lp_p, const T* __restrict__ A_p, S3 sA,
+                              const T* __restrict__ Rn_p, const T* __restrict__ B_p, S3 sB, char* lds) {
+  auto* Out = gmem(Out_p);
+  const auto* Lp = gmem(Lp_p);
+  const auto* A = gmem(A_p);
+  const auto* Rn = gmem(Rn_p);
+  const auto* B = gmem(B_p);
   using Sh = Env3Shape<D, C>;
   static_assert(Sh::ok, "defect3_fused: D*D = 64 and D*Dc = 128 only");
   using M = Mfma<T>;

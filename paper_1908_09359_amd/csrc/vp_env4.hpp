@@ -128,18 +128,30 @@ template <typename TC> struct Acc<TC, true> {
 // BF16: operands rounded to bf16, products accumulated in f32, stored as TC.
 template <typename TC, int M, int N, int K, bool BF16 = false, typename FO, typename FA, typename FB>
 __device__ inline void mfma_stage(TC* out, FO oidx, FA fa, FB fb) {
-  constexpr int MT = (M + 15) / 16, NT = (N + 15) / 16;
+  constexpr int MT = (M + 15) / 16, NT = (N + 15) / 16, NTW = (MT * NT + 3) / 4;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int t = wave; t < MT * NT; t += 4) {
-    const int m0 = (t / NT) * 16, n0 = (t % NT) * 16;
-    typename Acc<TC, BF16>::type acc;
-    if constexpr (BF16) acc = mfma_tile_bf16<M, N, K>(m0, n0, fa, fb);
-    else acc = mfma_tile<TC, M, N, K>(m0, n0, fa, fb);
-    const int j = n0 + (lane & 15);
+  // a wave's tiles t = wave + 4 w accumulate side by side and are stored only
+  // after all their operands are read (the stores could alias the operands in
+  // LDS, so a store would hold back every later read)
+  typename Acc<TC, BF16>::type acc[NTW];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = m0 + Acc<TC, BF16>::row(lane, r);
-      if (i < M && j < N) out[oidx(i, j)] = (TC)acc[r];
+  for (int w = 0; w < NTW; ++w) {
+    const int t = min(wave + 4 * w, MT * NT - 1);  // a wave without a last tile repeats one, unstored
+    const int m0 = (t / NT) * 16, n0 = (t % NT) * 16;
+    if constexpr (BF16) acc[w] = mfma_tile_bf16<M, N, K>(m0, n0, fa, fb);
+    else acc[w] = mfma_tile<TC, M, N, K>(m0, n0, fa, fb);
+  }
+#pragma unroll
+  for (int w = 0; w < NTW; ++w) {
+    const int t = wave + 4 * w;
+    if (t < MT * NT) {
+      const int m0 = (t / NT) * 16, n0 = (t % NT) * 16;
+      const int j = n0 + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = m0 + Acc<TC, BF16>::row(lane, r);
+        if (i < M && j < N) out[oidx(i, j)] = (TC)acc[w][r];
+      }
     }
   }
 }
@@ -186,9 +198,15 @@ constexpr int env4_bb() {
 }
 
 template <typename TC, typename TB, int D, int C, bool GRAM = false, bool BF16 = false>
-__device__ void env4_fused(TC* __restrict__ Lout, const TC* __restrict__ Lin, const TB* __restrict__ A, S3 sA,
-                           const TB* __restrict__ t1, S4 s1, const TB* __restrict__ t2, S4 s2,
-                           const TB* __restrict__ B, S3 sB, char* lds) {
+__device__ void env4_fused(TC* __restrict__ Lout_p, const TC* __restrict__ Lin_p, const TB* __restrict__ A_p, S3 sA,
+                           const TB* __restrict__ t1_p, S4 s1, const TB* __restrict__ t2_p, S4 s2,
+                           const TB* __restrict__ B_p, S3 sB, char* lds) {
+  auto* Lout = gmem(Lout_p);
+  const auto* Lin = gmem(Lin_p);
+  const auto* A = gmem(A_p);
+  const auto* t1 = gmem(t1_p);
+  const auto* t2 = gmem(t2_p);
+  const auto* B = gmem(B_p);
   using Sh = Env4Shape<D, C, env4_bb<TC, TB, D, C, GRAM>()>;
   constexpr int BB = Sh::BB, NBLK = Sh::NBLK, N4 = Sh::N4, NT4 = Sh::NT4, T4W = Sh::T4W;
   constexpr bool REGT = Sh::template regt<GRAM, BF16>();

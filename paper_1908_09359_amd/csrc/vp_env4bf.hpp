@@ -69,9 +69,15 @@ __device__ inline v4f_e bf_tile(const __bf16* A, int PA, const __bf16* B, int PB
 }
 
 template <int D, int C, typename TS>
-__device__ void env4_bf16(TS* __restrict__ Lout, const TS* __restrict__ Lin, const TS* __restrict__ A, S3 sA,
-                          const TS* __restrict__ t1, S4 s1, const TS* __restrict__ t2, S4 s2,
-                          const TS* __restrict__ B, S3 sB, char* lds) {
+__device__ void env4_bf16(TS* __restrict__ Lout_p, const TS* __restrict__ Lin_p, const TS* __restrict__ A_p, S3 sA,
+                          const TS* __restrict__ t1_p, S4 s1, const TS* __restrict__ t2_p, S4 s2,
+                          const TS* __restrict__ B_p, S3 sB, char* lds) {
+  auto* Lout = gmem(Lout_p);
+  const auto* Lin = gmem(Lin_p);
+  const auto* A = gmem(A_p);
+  const auto* t1 = gmem(t1_p);
+  const auto* t2 = gmem(t2_p);
+  const auto* B = gmem(B_p);
   using S = Env4Bf<D, C>;
   constexpr int BB = S::BB;
   __bf16* AT = reinterpret_cast<__bf16*>(lds);

@@ -66,7 +66,8 @@ __device__ inline int e3sz(const LatDev& L) { return L.c * L.d * L.c; }
 __device__ inline int e4sz(const LatDev& L) { return L.c * L.d * L.d * L.c; }
 
 template <typename T>
-__device__ inline void set_unit(T* x, int n) {
+__device__ inline void set_unit(T* x_p, int n) {
+  auto* x = gmem(x_p);
   for (int i = threadIdx.x; i < n; i += WG) x[i] = (i == 0) ? T(1) : T(0);
   __syncthreads();
 }
