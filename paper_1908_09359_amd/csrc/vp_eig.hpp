@@ -307,104 +307,144 @@ __device__ __forceinline__ void sym_topk_eig(const double* H, int n, int k, doub
       __syncthreads();
     }
     if (g < kb && lane == 0) lamb[g] = 0.5 * (a + c);
+    // deterministic, eigenvector-dependent start vectors: entry j of vector t
+    // at Xs[j * EIG_KMAX + t], written by the whole work-group
+    for (int e = tid; e < n * EIG_KMAX; e += WG) {
+      const int j = e / EIG_KMAX, t = e - j * EIG_KMAX;
+      if (t < kb) {
+        uint64_t h = (uint64_t)(j + 1) * 0x9E3779B97F4A7C15ull ^ (uint64_t)(b0 + t + 1) * 0xD2E7470EE14C6C93ull;
+        h ^= h >> 29;
+        Xs[e] = 0.5 + (double)(h & 0xFFFF) / 65536.0;
+      }
+    }
     __syncthreads();
 
     // ---- inverse iteration, one thread per eigenvector; LU factors in LDS (Ap is free now)
     double* U0 = Ap;                               // reciprocal pivots
     double* U1 = Ap + 1 * EIG_NMAX * EIG_KMAX;     // first superdiagonal of U
     double* ML = Ap + 2 * EIG_NMAX * EIG_KMAX;     // multipliers
+    double* inv_nrm = probe_x;                     // per vector: 1 / max |x| of the last iterate
     if (tid < kb) {
-      const int col = b0 + tid;
       const double lm = lamb[tid];
+      const int nm1 = n - 1;  // elimination steps
 #define IX(j) ((j) * EIG_KMAX + tid)
+      // Steps run in blocks of four whose operands are read one block ahead;
+      // the row swaps are kept as bits in registers (bit j % 32 of word j / 32).
+      unsigned pb[EIG_NMAX / 32] = {0u, 0u, 0u, 0u};
+      auto word = [&](int j) {
+        const int w = j >> 5;
+        return w == 0 ? pb[0] : (w == 1 ? pb[1] : (w == 2 ? pb[2] : pb[3]));
+      };
       // Gaussian elimination with partial pivoting of T - lm I; a swap of rows j
-      // and j+1 puts the known entry e[j+1] on the second superdiagonal.  The
-      // swaps are kept as bits in registers (bit j % 32 of word j / 32), and
-      // the entries a step needs are read one step ahead.
-      unsigned pb[EIG_NMAX / 32];
-      double aa = dg[0] - lm, cc = n > 1 ? eg[0] : 0.0;
-      double bb = cc, dn = dg[min(1, n - 1)], en = eg[min(1, n - 1)];  // e_j, d_{j+1}, e_{j+1}
+      // and j+1 puts the known entry e[j+1] on the second superdiagonal.
+      double aa = dg[0] - lm, cc = n > 1 ? eg[0] : 0.0, bb = cc;  // bb = e_j
+      double nd[4], ne[4];  // d_{j+1}, e_{j+1} of the next block
 #pragma unroll
-      for (int w = 0; w < EIG_NMAX / 32; ++w) {
+      for (int q = 0; q < 4; ++q) { nd[q] = dg[min(q + 1, n - 1)]; ne[q] = eg[min(q + 1, n - 1)]; }
+      for (int jb = 0; jb < nm1; jb += 4) {
+        double cd[4], ce[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          cd[q] = nd[q]; ce[q] = ne[q];
+          nd[q] = dg[min(jb + 5 + q, n - 1)];
+          ne[q] = eg[min(jb + 5 + q, n - 1)];
+        }
         unsigned bits = 0u;
-#pragma unroll 4
-        for (int jj = 0; jj < 32; ++jj) {
-          const int j = 32 * w + jj;
-          if (j >= n - 1) break;
-          const double a1 = dn - lm;
-          const double c1 = (j + 1 < n - 1) ? en : 0.0;
-          dn = dg[min(j + 2, n - 1)];
-          en = eg[min(j + 2, n - 1)];
-          // no swap: pivot aa (kept away from zero), U row (aa, cc), next row
-          // (a1 - m cc, c1); swap: pivot bb, U row (bb, a1, e[j+1]), next row
-          // (cc - m a1, -m c1).  Both by selects, so the lanes do not diverge.
-          const bool sw = fabs(aa) < fabs(bb);
-          const double pa = fabs(aa) < tiny ? (aa < 0.0 ? -tiny : tiny) : aa;
-          const double ip = recip(sw ? bb : pa);
-          const double m = (sw ? aa : bb) * ip;
-          const double u1 = sw ? a1 : cc;
-          U0[IX(j)] = ip; U1[IX(j)] = u1; ML[IX(j)] = m;
-          bits |= (sw ? 1u : 0u) << jj;
-          aa = fma(-m, u1, sw ? cc : a1);
-          cc = sw ? -m * c1 : c1;
-          bb = c1;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int j = jb + q;
+          if (j < nm1) {
+            const double a1 = cd[q] - lm;
+            const double c1 = (j + 1 < nm1) ? ce[q] : 0.0;
+            // no swap: pivot aa (kept away from zero), U row (aa, cc), next row
+            // (a1 - m cc, c1); swap: pivot bb, U row (bb, a1, e[j+1]), next row
+            // (cc - m a1, -m c1).  Both by selects, so the lanes do not diverge.
+            const bool sw = fabs(aa) < fabs(bb);
+            const double pa = fabs(aa) < tiny ? (aa < 0.0 ? -tiny : tiny) : aa;
+            const double ip = recip(sw ? bb : pa);
+            const double m = (sw ? aa : bb) * ip;
+            const double u1 = sw ? a1 : cc;
+            U0[IX(j)] = ip; U1[IX(j)] = u1; ML[IX(j)] = m;
+            bits |= (sw ? 1u : 0u) << q;
+            aa = fma(-m, u1, sw ? cc : a1);
+            cc = sw ? -m * c1 : c1;
+            bb = c1;
+          }
         }
-        pb[w] = bits;
+        const int w = jb >> 5;
+#pragma unroll
+        for (int i = 0; i < EIG_NMAX / 32; ++i) pb[i] |= (w == i) ? bits << (jb & 31) : 0u;
       }
-      U0[IX(n - 1)] = recip(fabs(aa) < tiny ? (aa < 0.0 ? -tiny : tiny) : aa);
-      // deterministic, eigenvector-dependent start vector
-      for (int j = 0; j < n; ++j) {
-        uint64_t h = (uint64_t)(j + 1) * 0x9E3779B97F4A7C15ull ^ (uint64_t)(col + 1) * 0xD2E7470EE14C6C93ull;
-        h ^= h >> 29;
-        Xs[IX(j)] = 0.5 + (double)(h & 0xFFFF) / 65536.0;
-      }
+      U0[IX(nm1)] = recip(fabs(aa) < tiny ? (aa < 0.0 ? -tiny : tiny) : aa);
+      U1[IX(nm1)] = 0.0;  // the last row has no superdiagonal
+      double s = 1.0;     // scale of the current iterate, applied as it is read
       for (int it = 0; it < 3; ++it) {
-        // forward elimination; the running entry j + 1 stays in a register and
-        // the next step's operands are read one step ahead
-        double carry = Xs[IX(0)];
-        double nx = Xs[IX(min(1, n - 1))], nm = ML[IX(0)];
+        // forward elimination; the running entry j + 1 stays in a register
+        double carry = Xs[IX(0)] * s;
+        double nx[4], nm[4];  // Xs[j+1], ML[j] of the next block
 #pragma unroll
-        for (int w = 0; w < EIG_NMAX / 32; ++w) {
-          const unsigned bits = pb[w];
-#pragma unroll 4
-          for (int jj = 0; jj < 32; ++jj) {
-            const int j = 32 * w + jj;
-            if (j >= n - 1) break;
-            double rj = carry, rj1 = nx;
-            const double m = nm;
-            nx = Xs[IX(min(j + 2, n - 1))];
-            nm = ML[IX(min(j + 1, n - 1))];
-            if ((bits >> jj) & 1u) { double tt = rj; rj = rj1; rj1 = tt; }
-            Xs[IX(j)] = rj;
-            carry = rj1 - m * rj;
+        for (int q = 0; q < 4; ++q) { nx[q] = Xs[IX(min(q + 1, nm1))]; nm[q] = ML[IX(min(q, nm1))]; }
+        for (int jb = 0; jb < nm1; jb += 4) {
+          double cx[4], cm[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            cx[q] = nx[q]; cm[q] = nm[q];
+            nx[q] = Xs[IX(min(jb + 5 + q, nm1))];
+            nm[q] = ML[IX(min(jb + 4 + q, nm1))];
+          }
+          const unsigned bits = word(jb) >> (jb & 31);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int j = jb + q;
+            if (j < nm1) {
+              double rj = carry, rj1 = cx[q] * s;
+              if ((bits >> q) & 1u) { const double tt = rj; rj = rj1; rj1 = tt; }
+              Xs[IX(j)] = rj;
+              carry = rj1 - cm[q] * rj;
+            }
           }
         }
-        Xs[IX(n - 1)] = carry;
-        // back substitution, operands of row j - 1 read while row j is solved
+        Xs[IX(nm1)] = carry;
+        // back substitution from row n - 1 down, in blocks of four rows
         double x1 = 0.0, x2 = 0.0, nrm = 0.0;
-        double cx = Xs[IX(n - 1)], cu1 = U1[IX(n - 1)], cu0 = U0[IX(n - 1)], ce = eg[n - 1];
+        double px[4], pu1[4], pu0[4], pe[4];  // rows jt - q of the next block
 #pragma unroll
-        for (int w = EIG_NMAX / 32 - 1; w >= 0; --w) {
-          const unsigned bits = pb[w];
-#pragma unroll 4
-          for (int jj = 31; jj >= 0; --jj) {
-            const int j = 32 * w + jj;
-            if (j > n - 1) continue;
-            const double xr = cx, u1 = cu1, u0 = cu0, e1 = ce;
-            const int jn = max(j - 1, 0);
-            cx = Xs[IX(jn)]; cu1 = U1[IX(jn)]; cu0 = U0[IX(jn)]; ce = eg[min(j, n - 1)];
-            const double u2 = (((bits >> jj) & 1u) && j + 1 < n - 1) ? e1 : 0.0;
-            const double xj = (xr - u1 * x1 - u2 * x2) * u0;  // U0 holds 1/pivot
-            Xs[IX(j)] = xj;
-            x2 = x1;
-            x1 = xj;
-            nrm = fmax(nrm, fabs(xj));
+        for (int q = 0; q < 4; ++q) {
+          const int j = max(nm1 - q, 0);
+          px[q] = Xs[IX(j)]; pu1[q] = U1[IX(j)]; pu0[q] = U0[IX(j)]; pe[q] = eg[min(j + 1, nm1)];
+        }
+        for (int jt = nm1; jt >= 0; jt -= 4) {
+          double cx[4], cu1[4], cu0[4], ce[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            cx[q] = px[q]; cu1[q] = pu1[q]; cu0[q] = pu0[q]; ce[q] = pe[q];
+            const int j = max(jt - 4 - q, 0);
+            px[q] = Xs[IX(j)]; pu1[q] = U1[IX(j)]; pu0[q] = U0[IX(j)]; pe[q] = eg[min(j + 1, nm1)];
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int j = jt - q;
+            if (j >= 0) {
+              const bool swp = (word(j) >> (j & 31)) & 1u;
+              const double u2 = (swp && j + 1 < nm1) ? ce[q] : 0.0;
+              const double xj = (cx[q] - cu1[q] * x1 - u2 * x2) * cu0[q];  // U0 holds 1/pivot
+              Xs[IX(j)] = xj;
+              x2 = x1;
+              x1 = xj;
+              nrm = fmax(nrm, fabs(xj));
+            }
           }
         }
-        const double inv = nrm > 0.0 ? 1.0 / nrm : 1.0;
-        for (int j = 0; j < n; ++j) Xs[IX(j)] *= inv;
+        s = nrm > 0.0 ? 1.0 / nrm : 1.0;
       }
+      inv_nrm[tid] = s;
 #undef IX
+    }
+    __syncthreads();
+    // the last iterate's scale, applied by the whole work-group
+    for (int e = tid; e < n * EIG_KMAX; e += WG) {
+      const int t = e % EIG_KMAX;
+      if (t < kb) Xs[e] *= inv_nrm[t];
     }
     __syncthreads();
     if (tid < kb) lam[b0 + tid] = lamb[tid];

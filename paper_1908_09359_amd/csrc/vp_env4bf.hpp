@@ -68,6 +68,27 @@ __device__ inline v4f_e bf_tile(const __bf16* A, int PA, const __bf16* B, int PB
   return acc;
 }
 
+// One stage over MT x NT output tiles: a wave's tiles t = wave + 4 w are all
+// multiplied (tile(m0, n0) -> accumulator) before any is stored
+// (store(m0, n0, acc)); a store into LDS could alias the operands, so storing
+// each tile at once would hold back the next tile's reads.
+template <int MT, int NT, typename FT, typename FS>
+__device__ inline void bf_stage(FT tile, FS store) {
+  constexpr int NTW = (MT * NT + 3) / 4;
+  const int wave = threadIdx.x >> 6;
+  v4f_e c[NTW];
+#pragma unroll
+  for (int w = 0; w < NTW; ++w) {
+    const int t = min(wave + 4 * w, MT * NT - 1);  // a wave without a last tile repeats one, unstored
+    c[w] = tile((t / NT) * 16, (t % NT) * 16);
+  }
+#pragma unroll
+  for (int w = 0; w < NTW; ++w) {
+    const int t = wave + 4 * w;
+    if (t < MT * NT) store((t / NT) * 16, (t % NT) * 16, c[w]);
+  }
+}
+
 template <int D, int C, typename TS>
 __device__ void env4_bf16(TS* __restrict__ Lout_p, const TS* __restrict__ Lin_p, const TS* __restrict__ A_p, S3 sA,
                           const TS* __restrict__ t1_p, S4 s1, const TS* __restrict__ t2_p, S4 s2,
@@ -150,15 +171,12 @@ __device__ void env4_bf16(TS* __restrict__ Lout_p, const TS* __restrict__ Lin_p,
     for (int cs = 0; cs < C; ++cs) {
       const int pos = q * C + cs;
       // S1: X1[(l2,bb)][(l1,u)] = sum_a Ls[(l1,l2)][a] AT[(u, b0+bb)][a]; M = D^2, N = D BB
-      {
-        constexpr int MT = (D * D + 15) / 16, NT = (D * BB + 15) / 16;
-        for (int t = wave; t < MT * NT; t += 4) {
-          const int m0 = (t / NT) * 16, n0 = (t % NT) * 16;
-          // B rows j = (u, bb) -> AT row u C + b0 + bb: a strided row set, fetched row by row
-          v4f_e c4 = {0, 0, 0, 0};
-          {
-            // rows past M or N are clamped to the last one: their products land in
-            // output rows and columns that are never stored
+      bf_stage<(D * D + 15) / 16, (D * BB + 15) / 16>(
+          [&](int m0, int n0) {
+            // B rows j = (u, bb) -> AT row u C + b0 + bb: a strided row set, fetched
+            // row by row; rows past M or N are clamped to the last one (their
+            // products land in output rows and columns that are never stored)
+            v4f_e c4 = {0, 0, 0, 0};
             const int i = min(m0 + (lane & 15), D * D - 1), j = min(n0 + (lane & 15), D * BB - 1);
             const int kq = (lane >> 4) * 8, u = j / BB, bb = j - u * BB;
 #pragma unroll
@@ -167,58 +185,53 @@ __device__ void env4_bf16(TS* __restrict__ Lout_p, const TS* __restrict__ Lin_p,
               const v8bf_e b = ld8(AT + (u * C + b0 + bb) * S::P1, 32 * s + kq, S::K1);
               c4 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c4, 0, 0, 0);
             }
-          }
-          const int j = n0 + (lane & 15);
+            return c4;
+          },
+          [&](int m0, int n0, const v4f_e& c4) {
+            const int j = n0 + (lane & 15);
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int i = m0 + 4 * (lane >> 4) + r;  // (l1, l2)
-            if (i < D * D && j < D * BB) {
-              const int l1 = i / D, l2 = i - l1 * D, u = j / BB, bb = j - u * BB;
-              X1[(l2 * BB + bb) * S::P2 + l1 * D + u] = (__bf16)c4[r];
+            for (int r = 0; r < 4; ++r) {
+              const int i = m0 + 4 * (lane >> 4) + r;  // (l1, l2)
+              if (i < D * D && j < D * BB) {
+                const int l1 = i / D, l2 = i - l1 * D, u = j / BB, bb = j - u * BB;
+                X1[(l2 * BB + bb) * S::P2 + l1 * D + u] = (__bf16)c4[r];
+              }
             }
-          }
-        }
-      }
+          });
       __syncthreads();
       if (pos + 1 < NS) {  // Ls is free: the next slice goes in
         store();
         if (pos + 2 < NS) fetch((pos + 2) % C);
       }
       // S2: X2[(bb,r1)][(l2,m)] = sum_{(l1,u)} X1[(l2,bb)][(l1,u)] T1[(r1,m)][(l1,u)]; M = D BB, N = D^2
-      {
-        constexpr int MT = (D * BB + 15) / 16, NT = (D * D + 15) / 16;
-        for (int t = wave; t < MT * NT; t += 4) {
-          const int m0 = (t / NT) * 16, n0 = (t % NT) * 16;
-          const v4f_e c4 = bf_tile<S::K2>(X1, S::P2, T1, S::P2, m0, n0, D * BB, D * D);
-          const int j = n0 + (lane & 15);  // (r1, m)
+      bf_stage<(D * BB + 15) / 16, (D * D + 15) / 16>(
+          [&](int m0, int n0) { return bf_tile<S::K2>(X1, S::P2, T1, S::P2, m0, n0, D * BB, D * D); },
+          [&](int m0, int n0, const v4f_e& c4) {
+            const int j = n0 + (lane & 15);  // (r1, m)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int i = m0 + 4 * (lane >> 4) + r;  // (l2, bb)
-            if (i < D * BB && j < D * D) {
-              const int l2 = i / BB, bb = i - l2 * BB, r1 = j / D, m = j - r1 * D;
-              X2[(bb * D + r1) * S::P3 + l2 * D + m] = (__bf16)c4[r];
+            for (int r = 0; r < 4; ++r) {
+              const int i = m0 + 4 * (lane >> 4) + r;  // (l2, bb)
+              if (i < D * BB && j < D * D) {
+                const int l2 = i / BB, bb = i - l2 * BB, r1 = j / D, m = j - r1 * D;
+                X2[(bb * D + r1) * S::P3 + l2 * D + m] = (__bf16)c4[r];
+              }
             }
-          }
-        }
-      }
+          });
       __syncthreads();
       // S3: X3[(bb,r1,r2)][dd] = sum_{(l2,m)} X2[(bb,r1)][(l2,m)] T2[(r2,dd)][(l2,m)]; M = BB D, N = D^2
-      {
-        constexpr int MT = (BB * D + 15) / 16, NT = (D * D + 15) / 16;
-        for (int t = wave; t < MT * NT; t += 4) {
-          const int m0 = (t / NT) * 16, n0 = (t % NT) * 16;
-          const v4f_e c4 = bf_tile<S::K3>(X2, S::P3, T2, S::P3, m0, n0, BB * D, D * D);
-          const int j = n0 + (lane & 15);  // (r2, dd)
+      bf_stage<(BB * D + 15) / 16, (D * D + 15) / 16>(
+          [&](int m0, int n0) { return bf_tile<S::K3>(X2, S::P3, T2, S::P3, m0, n0, BB * D, D * D); },
+          [&](int m0, int n0, const v4f_e& c4) {
+            const int j = n0 + (lane & 15);  // (r2, dd)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int i = m0 + 4 * (lane >> 4) + r;  // (bb, r1)
-            if (i < BB * D && j < D * D) {
-              const int r2 = j / D, dd = j - r2 * D;
-              X3[(i * D + r2) * S::P4 + dd] = (__bf16)c4[r];
+            for (int r = 0; r < 4; ++r) {
+              const int i = m0 + 4 * (lane >> 4) + r;  // (bb, r1)
+              if (i < BB * D && j < D * D) {
+                const int r2 = j / D, dd = j - r2 * D;
+                X3[(i * D + r2) * S::P4 + dd] = (__bf16)c4[r];
+              }
             }
-          }
-        }
-      }
+          });
       __syncthreads();
       // S4: acc[e][(bb,r1,r2)] += sum_dd BT[(cs, e)][dd] X3[(bb,r1,r2)][dd]; M = C, N = BB D^2
 #pragma unroll
