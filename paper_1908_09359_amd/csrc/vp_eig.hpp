@@ -22,10 +22,10 @@ constexpr int EIG_PACK = EIG_NMAX * (EIG_NMAX + 1) / 2;
 // LDS the caller provides: a first block (the size of a packed matrix) that
 // holds the LU factors (3 x n x EIG_KMAX) and the kept vectors (n x EIG_KMAX).
 // Small work arrays follow the packed matrix: d, e, e^2, tau, p, w, v (7 n),
-// two spare rows (2 n), the multisection probes and counts (2 WG) and the batch
-// eigenvalues (EIG_KMAX).
+// two spare rows (2 n), a row of WG doubles (reduction partials, the iterates'
+// scales) and the batch eigenvalues (EIG_KMAX).
 constexpr size_t EIG_PACK_BYTES = sizeof(double) * EIG_PACK;
-constexpr size_t EIG_SMALL_BYTES = sizeof(double) * (9 * EIG_NMAX + WG + EIG_KMAX) + sizeof(int) * WG;
+constexpr size_t EIG_SMALL_BYTES = sizeof(double) * (9 * EIG_NMAX + WG + EIG_KMAX);
 constexpr size_t EIG_LDS_BYTES = EIG_PACK_BYTES + EIG_SMALL_BYTES;
 static_assert(3 * EIG_NMAX * EIG_KMAX * 8 + EIG_NMAX * EIG_KMAX * 8 <= EIG_PACK_BYTES, "eig LDS");
 
@@ -63,6 +63,34 @@ __device__ inline double dpp_f64(double x) {
   const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
   const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xf, 0xf, false);
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over the 16 lanes of a row, returned to all of them: quad_perm [1,0,3,2]
+// and [2,3,0,1] sum each quad, row_half_mirror pairs the quads of each half,
+// row_mirror the halves.
+__device__ inline double row16_sum(double x) {
+  x += dpp_f64<0xB1>(x);
+  x += dpp_f64<0x4E>(x);
+  x += dpp_f64<0x141>(x);
+  x += dpp_f64<0x140>(x);
+  return x;
+}
+
+// x + x of lane l ^ 32 and x + x of lane l ^ 16, by the gfx950 lane swaps
+// (v_permlane32_swap / v_permlane16_swap on each half of the double): VALU
+// moves, no LDS round trip.  With x as both operands, the swap leaves the
+// lane's own value in one result and its partner's in the other.
+__device__ inline double xor32_sum(double x) {
+  const long long b = __double_as_longlong(x);
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)b, (unsigned)b, false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+  return __longlong_as_double(((long long)hi[0] << 32) | lo[0]) + __longlong_as_double(((long long)hi[1] << 32) | lo[1]);
+}
+__device__ inline double xor16_sum(double x) {
+  const long long b = __double_as_longlong(x);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)b, (unsigned)b, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+  return __longlong_as_double(((long long)hi[0] << 32) | lo[0]) + __longlong_as_double(((long long)hi[1] << 32) | lo[1]);
 }
 
 // Householder tridiagonalisation Q^T A Q = T, Q = H_0 H_1 ... H_{n-3}.
@@ -177,8 +205,7 @@ __device__ __noinline__ void eig_tridiag(const gbl_f64* H, int n, lds_f64* dg, l
 #pragma unroll
       for (int q = 0; q < 8; ++q) part += pr[q] * vr[q];
       // v^T p: four block rows per wavefront, then across wavefronts
-      part += __shfl_xor(part, 16, 64);
-      part += __shfl_xor(part, 32, 64);
+      part = xor32_sum(xor16_sum(part));
       if (bc == 0) {
 #pragma unroll
         for (int q = 0; q < 8; ++q) pv[16 * q + br] = pr[q];
@@ -255,7 +282,6 @@ __device__ __forceinline__ void sym_topk_eig(const double* H, int n, int k, doub
   double* vv = wv + EIG_NMAX;
   double* probe_x = vv + 3 * EIG_NMAX;
   double* lamb = probe_x + WG;
-  int* probe_c = reinterpret_cast<int*>(lamb + EIG_KMAX);
   const int tid = threadIdx.x;
 
   // ---- tridiagonalisation (out of line: its register tile needs the whole register budget)
@@ -287,24 +313,22 @@ __device__ __forceinline__ void sym_topk_eig(const double* H, int n, int k, doub
     const int t = b0 + g;
     const int q = n - 1 - t;            // ascending index
     double a = lo, c = hi;
+    // A group's 16 lanes lie in one wavefront: the first probe with more than
+    // q eigenvalues below it is found by a ballot, and the new interval's ends
+    // are read from its lane and the lane before (no LDS, no barrier).
+    const int gl = (tid & 63) & ~15;  // lane 0 of this group within the wavefront
     for (int it = 0; it < 13; ++it) {  // 17^13 > 2^52
-      double x = a + (c - a) * (double)(lane + 1) / 17.0;
-      int cnt = (g < kb) ? sturm_count(dg, e2, n, x, pivmin) : 0;
-      probe_x[tid] = x;
-      probe_c[tid] = cnt;
-      __syncthreads();
+      const double x = a + (c - a) * (double)(lane + 1) / 17.0;
+      const int cnt = (g < kb) ? sturm_count(dg, e2, n, x, pivmin) : 0;
+      const unsigned long long above = __ballot(cnt > q);
+      const unsigned gm = (unsigned)(above >> gl) & 0xFFFFu;
+      const int s1 = gm ? __builtin_ctz(gm) : 16;  // probes 0 .. s1-1 have at most q below them
+      const double xl = __shfl(x, gl + max(s1 - 1, 0), 64);
+      const double xh = __shfl(x, gl + min(s1, 15), 64);
       if (g < kb) {
-        double na = a, nc = c;
-        for (int s = 0; s < 16; ++s) {
-          int cs = probe_c[(g << 4) + s];
-          double xs = probe_x[(g << 4) + s];
-          if (cs <= q) na = xs;
-          else { nc = xs; break; }
-        }
-        a = na;
-        c = nc;
+        if (s1 > 0) a = xl;
+        if (s1 < 16) c = xh;
       }
-      __syncthreads();
     }
     if (g < kb && lane == 0) lamb[g] = 0.5 * (a + c);
     // deterministic, eigenvector-dependent start vectors: entry j of vector t
@@ -472,8 +496,7 @@ __device__ __forceinline__ void sym_topk_eig(const double* H, int n, int k, doub
           double dp = 0.0;
           if (sv < col)
             for (int j = tid & 15; j < n; j += 16) dp += Vw[j * ld + sv] * Vw[j * ld + col];
-#pragma unroll
-          for (int o = 8; o > 0; o >>= 1) dp += __shfl_xor(dp, o, 16);
+          dp = row16_sum(dp);
           if ((tid & 15) == 0 && sv < col) pv[sv] = dp;
         }
         __syncthreads();
@@ -490,8 +513,7 @@ __device__ __forceinline__ void sym_topk_eig(const double* H, int n, int k, doub
       double nn = 0.0;
       if (col < k)
         for (int j = tid & 15; j < n; j += 16) nn += Vw[j * ld + col] * Vw[j * ld + col];
-#pragma unroll
-      for (int o = 8; o > 0; o >>= 1) nn += __shfl_xor(nn, o, 16);
+      nn = row16_sum(nn);
       if ((tid & 15) == 0 && col < k) pv[col] = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
     }
     __syncthreads();
@@ -537,8 +559,7 @@ __device__ __forceinline__ void sym_topk_eig(const double* H, int n, int k, doub
       double part = 0.0;
 #pragma unroll
       for (int q = 0; q < 8; ++q) part += vr[q] * x[q];
-      part += __shfl_xor(part, 16, 64);
-      part += __shfl_xor(part, 32, 64);
+      part = xor32_sum(xor16_sum(part));
       lds_f64* red = (i & 1) ? rs1 : rs0;
       if ((tid & 63) < 16) red[wave * 16 + col] = part;
       // stage reflector i - 1 (every reader of that row has passed the previous
@@ -575,8 +596,7 @@ __device__ __forceinline__ void sym_topk_eig(const double* H, int n, int k, doub
         double dp = 0.0;
         if (col < k)
           for (int r = i + 1 + (tid & 15); r < n; r += 16) dp += vv[r] * Vg[r * k + col];
-#pragma unroll
-        for (int o = 8; o > 0; o >>= 1) dp += __shfl_xor(dp, o, 16);
+        dp = row16_sum(dp);
         if ((tid & 15) == 0 && col < k) pv[col] = t * dp;
       }
       __syncthreads();
