@@ -173,6 +173,27 @@ vp_status vp_sample_batch(vp_ctx* ctx, int32_t n_lats, const int32_t* lats_host,
  * VP_SCHED_PHASES, VP_SCHED_PERSISTENT and VP_SCHED_GRAPH.  Waits. */
 vp_status vp_autotune(vp_ctx* ctx, int32_t lat, int32_t sweeps, double* ms_host, int32_t* schedule_out);
 
+/* Tile variants of the fused float32 / float64 2-row column step (App. C: the
+ * 4-line environment step, used by the vertical sweep, the right 2-row
+ * environments and the 2-row measurement) at D = 8, Dc = 16: the step
+ * contracts the upper-boundary index b in blocks of BB, VP_TILE_DEFAULT
+ * BB = Dc/4, VP_TILE_SMALL Dc/8, VP_TILE_LARGE Dc/2 (a larger block needs more
+ * LDS per work-group, a smaller one more barriers per step).  The blocking
+ * only partitions the output, so every variant gives bit-identical results;
+ * other shapes and the bf16 sampling steps have one variant, and the
+ * persistent schedule always takes the default.  vp_set_tile selects one for
+ * a lattice (VP_ERR_ARG for an unknown variant). */
+typedef enum { VP_TILE_DEFAULT = 0, VP_TILE_SMALL = 1, VP_TILE_LARGE = 2, VP_N_TILES = 3 } vp_tile;
+vp_status vp_set_tile(vp_ctx* ctx, int32_t lat, int32_t tile);
+
+/* The tile autotuner: times `sweeps` unmeasured sweeps of the lattice under
+ * each tile variant with its current schedule (after one warm-up sweep each;
+ * the chains advance by VP_N_TILES (sweeps + 1) sweeps, which count as
+ * burn-in), keeps the fastest and returns it in *tile_out; ms_host
+ * [VP_N_TILES] (may be NULL) receives the milliseconds per sweep of each.
+ * Waits. */
+vp_status vp_autotune_tiles(vp_ctx* ctx, int32_t lat, int32_t sweeps, double* ms_host, int32_t* tile_out);
+
 /* Record the sampler's decisions: while trace_dev is set (NULL clears it),
  * every sweep of vp_sample overwrites trace_dev[chain][b][0..1] with the ratio
  * rho = Psi(S')/Psi(S) that bond b's Metropolis test used (float64, after the

@@ -16,6 +16,7 @@ VP_ERR_ZERO_AMPLITUDE, VP_ERR_NONFINITE, VP_ERR_UNSUPPORTED = 5, 6, 7
 VP_FP64, VP_FP32, VP_BF16 = 0, 1, 2
 VP_SAMPLER_PAIR_SEQ, VP_SAMPLER_LEARNED_PLAQ = 0, 1
 VP_SCHED_PHASES, VP_SCHED_PERSISTENT, VP_SCHED_GRAPH = 0, 1, 2
+VP_TILE_DEFAULT, VP_TILE_SMALL, VP_TILE_LARGE, VP_N_TILES = 0, 1, 2, 3
 
 STATUS_NAMES = {0: "VP_OK", 1: "VP_ERR_ARG", 2: "VP_ERR_SHAPE", 3: "VP_ERR_OOM", 4: "VP_ERR_DEVICE",
                 5: "VP_ERR_ZERO_AMPLITUDE", 6: "VP_ERR_NONFINITE", 7: "VP_ERR_UNSUPPORTED"}
@@ -26,7 +27,8 @@ EXPORTED = ["vp_create", "vp_destroy", "vp_last_error", "vp_num_params", "vp_wor
             "vp_timing_enable", "vp_timing_read", "vp_stats_tau", "vp_trace_ratios", "vp_plaquette_ratios",
             "vp_proposal_num_params", "vp_proposal_set_weights", "vp_proposal_get_weights", "vp_proposal_forward",
             "vp_proposal_loss_grad", "vp_proposal_train", "vp_set_sampler", "vp_move_counts", "vp_set_schedule",
-            "vp_sample_batch", "vp_autotune", "vp_sample_split", "vp_optimize"]
+            "vp_sample_batch", "vp_autotune", "vp_sample_split", "vp_optimize", "vp_set_tile",
+            "vp_autotune_tiles"]
 
 PHASES = ["row3_envs", "hsweep", "row4_envs", "vsweep", "compress_up", "compress_down", "measure3",
           "measure4", "other"]
@@ -91,6 +93,8 @@ def _load():
         "vp_sample_split": ([P, I32, I32, I32, I32, P, P, P, P, P], I32),
         "vp_optimize": ([P, I32, I32, I32, I32, P, ctypes.c_uint64, P], I32),
         "vp_autotune": ([P, I32, I32, P, P], I32),
+        "vp_set_tile": ([P, I32, I32], I32),
+        "vp_autotune_tiles": ([P, I32, I32, P, P], I32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -234,6 +238,16 @@ class Context:
         ms = (ctypes.c_double * 3)()
         pick = ctypes.c_int32()
         self._check(LIB.vp_autotune(self.h, lat, sweeps, ms, ctypes.byref(pick)))
+        return pick.value, list(ms)
+
+    def vp_set_tile(self, lat, tile):
+        self._check(LIB.vp_set_tile(self.h, lat, tile))
+
+    def vp_autotune_tiles(self, lat, sweeps):
+        """Returns (chosen tile variant, [ms per sweep of VP_TILE_DEFAULT, VP_TILE_SMALL, VP_TILE_LARGE])."""
+        ms = (ctypes.c_double * VP_N_TILES)()
+        pick = ctypes.c_int32()
+        self._check(LIB.vp_autotune_tiles(self.h, lat, sweeps, ms, ctypes.byref(pick)))
         return pick.value, list(ms)
 
     def vp_move_counts(self, lat, counts):

@@ -767,6 +767,14 @@ vp_status vp_set_schedule(vp_ctx* ctx, int32_t lat, int32_t schedule) {
   return VP_OK;
 }
 
+vp_status vp_set_tile(vp_ctx* ctx, int32_t lat, int32_t tile) {
+  Lattice* L = get_lat(ctx, lat);
+  if (!L) return fail(ctx, VP_ERR_ARG, "bad lattice index");
+  if (tile < 0 || tile >= VP_N_TILES) return fail(ctx, VP_ERR_ARG, "unknown tile variant %d", tile);
+  L->dev.tile = tile;
+  return VP_OK;
+}
+
 vp_status vp_sample_batch(vp_ctx* ctx, int32_t n_lats, const int32_t* lats_host, int32_t n_burn, int32_t n_meas,
                           const vp_outputs* outs_host) {
   if (!ctx || n_lats < 1 || !lats_host) return fail(ctx, VP_ERR_ARG, "need at least one lattice");
@@ -852,6 +860,44 @@ vp_status vp_autotune(vp_ctx* ctx, int32_t lat, int32_t sweeps, double* ms_host,
   if (st != VP_OK) return st;
   L->schedule = pick;
   if (schedule_out) *schedule_out = pick;
+  return VP_OK;
+}
+
+vp_status vp_autotune_tiles(vp_ctx* ctx, int32_t lat, int32_t sweeps, double* ms_host, int32_t* tile_out) {
+  Lattice* L = get_lat(ctx, lat);
+  if (!L) return fail(ctx, VP_ERR_ARG, "bad lattice index");
+  if (sweeps < 1) return fail(ctx, VP_ERR_ARG, "sweeps must be >= 1");
+  if (!L->tensors_ready || !L->chains_ready)
+    return fail(ctx, VP_ERR_ARG, "tensors and chains must be initialised first");
+  hipStream_t s = ctx->stream;
+  hipEvent_t e0, e1;
+  HIP_TRY(ctx, hipEventCreate(&e0));
+  HIP_TRY(ctx, hipEventCreate(&e1));
+  double best = 1e300;
+  int32_t pick = VP_TILE_DEFAULT;
+  const bool timing = ctx->timing;
+  ctx->timing = false;
+  vp_status st = VP_OK;
+  for (int k = 0; k < VP_N_TILES && st == VP_OK; ++k) {
+    L->dev.tile = k;
+    st = vp_sample(ctx, lat, 1, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);  // warm-up
+    if (st != VP_OK) break;
+    hipEventRecord(e0, s);
+    st = vp_sample(ctx, lat, sweeps, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+    hipEventRecord(e1, s);
+    if (st != VP_OK) break;
+    if (hipEventSynchronize(e1) != hipSuccess) { st = fail(ctx, VP_ERR_DEVICE, "autotune timing failed"); break; }
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    if (ms_host) ms_host[k] = ms / sweeps;
+    if (ms < best) { best = ms; pick = k; }
+  }
+  ctx->timing = timing;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  L->dev.tile = pick;
+  if (st != VP_OK) return st;
+  if (tile_out) *tile_out = pick;
   return VP_OK;
 }
 

@@ -197,7 +197,10 @@ constexpr int env4_bb() {
   return (GRAM && sizeof(TB) == 8 && C % 8 == 0 && (D * D + 15) / 16 != 4) ? C / 8 : 0;
 }
 
-template <typename TC, typename TB, int D, int C, bool GRAM = false, bool BF16 = false>
+// BBX > 0 takes that b-block size (a tile variant; it must divide C) instead of
+// the default one.  The blocking partitions only the output columns, so every
+// output element is summed in the same order for every BBX.
+template <typename TC, typename TB, int D, int C, bool GRAM = false, bool BF16 = false, int BBX = 0>
 __device__ void env4_fused(TC* __restrict__ Lout_p, const TC* __restrict__ Lin_p, const TB* __restrict__ A_p, S3 sA,
                            const TB* __restrict__ t1_p, S4 s1, const TB* __restrict__ t2_p, S4 s2,
                            const TB* __restrict__ B_p, S3 sB, char* lds) {
@@ -207,7 +210,7 @@ __device__ void env4_fused(TC* __restrict__ Lout_p, const TC* __restrict__ Lin_p
   const auto* t1 = gmem(t1_p);
   const auto* t2 = gmem(t2_p);
   const auto* B = gmem(B_p);
-  using Sh = Env4Shape<D, C, env4_bb<TC, TB, D, C, GRAM>()>;
+  using Sh = Env4Shape<D, C, (BBX > 0 ? BBX : env4_bb<TC, TB, D, C, GRAM>())>;
   constexpr int BB = Sh::BB, NBLK = Sh::NBLK, N4 = Sh::N4, NT4 = Sh::NT4, T4W = Sh::T4W;
   constexpr bool REGT = Sh::template regt<GRAM, BF16>();
   constexpr int KS = (D * D + 3) / 4;

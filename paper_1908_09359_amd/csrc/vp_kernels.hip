@@ -138,9 +138,10 @@ constexpr size_t step3_lds() {
 }
 
 // LDS bytes a kernel provides for its 2-row column steps.
-template <typename TC, typename TB, int DD, int CC, bool GRAM = false>
+template <typename TC, typename TB, int DD, int CC, bool GRAM = false, int BBX = 0>
 constexpr size_t env4_lds() {
-  if constexpr (DD > 0) return Env4Shape<DD, CC, env4_bb<TC, TB, DD, CC, GRAM>()>::template lds_bytes<TC, TB, GRAM>();
+  if constexpr (DD > 0)
+    return Env4Shape<DD, CC, (BBX > 0 ? BBX : env4_bb<TC, TB, DD, CC, GRAM>())>::template lds_bytes<TC, TB, GRAM>();
   else return GEMM_TILE_BYTES;  // the generic step's GEMM tiles
 }
 
@@ -148,7 +149,7 @@ constexpr size_t env4_lds() {
 // DD > 0 selects the fused MFMA step (environment layout [c][a][l1][l2]);
 // DD == 0 the generic strided-GEMM step (layout [a][l1][l2][c]).  BF16: bf16
 // operands with f32 accumulation.
-template <typename T, int DD, int CC, bool BF16 = false>
+template <typename T, int DD, int CC, bool BF16 = false, int BBX = 0>
 __device__ inline int step4(const LatDev& L, const Chain<T>& C, T* out, const T* in, int y, int x,
                             int flip1, int flip2, const T* Ux, const T* Dx, bool right, char* lds) {
   int k1 = y * L.Lx + x, k2 = (y + 1) * L.Lx + x;
@@ -160,7 +161,7 @@ __device__ inline int step4(const LatDev& L, const Chain<T>& C, T* out, const T*
   if constexpr (DD > 0 && BF16) {
     env4_bf16<DD, CC, T>(out, in, Ux, sb, t1, s, t2, s, Dx, sb, lds);
   } else if constexpr (DD > 0) {
-    env4_fused<T, T, DD, CC>(out, in, Ux, sb, t1, s, t2, s, Dx, sb, lds);
+    env4_fused<T, T, DD, CC, false, false, BBX>(out, in, Ux, sb, t1, s, t2, s, Dx, sb, lds);
   } else {
     env4_step<T, T, BF16>(out, in, Ux, sb, t1, s, t2, s, Dx, sb, C.ws + L.oX0, C.ws + L.oX1, L.c, L.d, lds);
   }
@@ -329,7 +330,7 @@ __device__ __forceinline__ void ph_hsweep(const LatDev& L, int ch, int y, int la
 }
 
 // R4[x] for x = Lx-1 .. 1 of <D_{y+2}|M_{y+1} M_y|U_{y-1}>.
-template <typename T, int DD, int CC, bool BF16>
+template <typename T, int DD, int CC, bool BF16, int BBX = 0>
 __device__ __forceinline__ void ph_row4_right(const LatDev& L, int ch, int y, char* lds) {
   Chain<T> C = chain_of<T>(L, ch);
   if (chain_flagged(C.meta)) return;
@@ -339,7 +340,7 @@ __device__ __forceinline__ void ph_row4_right(const LatDev& L, int ch, int y, ch
   set_unit<T>(R + (int64_t)L.Lx * sz, sz);
   if (threadIdx.x == 0) eR[L.Lx] = 0;
   for (int x = L.Lx - 1; x >= 1; --x) {
-    int e = step4<T, DD, CC, BF16>(L, C, R + (int64_t)x * sz, R + (int64_t)(x + 1) * sz, y, x, 0, 0,
+    int e = step4<T, DD, CC, BF16, BBX>(L, C, R + (int64_t)x * sz, R + (int64_t)(x + 1) * sz, y, x, 0, 0,
                                    ub<T>(L, C, y, x), db<T>(L, C, y + 2, x), true, lds);
     if (threadIdx.x == 0) eR[x] = eR[x + 1] + e;
     __syncthreads();
@@ -371,7 +372,7 @@ constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
 // with probability pi = sigmoid(f_x(S)) (word 0 of Philox counter (chain,
 // sweep, y(Lx-1)+x, 6)), accepted with min[1, R pi(S')/pi(S)] (word 1); R from
 // the two-row network with columns x and x+1 exchanged in both rows.
-template <typename T, int DD, int CC, bool BF16, bool LEARN>
+template <typename T, int DD, int CC, bool BF16, bool LEARN, int BBX = 0>
 __device__ __forceinline__ void ph_vsweep(const LatDev& L, int ch, int y, char* lds) {
   Chain<T> C = chain_of<T>(L, ch);
   if (chain_flagged(C.meta)) return;
@@ -390,11 +391,11 @@ __device__ __forceinline__ void ph_vsweep(const LatDev& L, int ch, int y, char* 
     const int vb = y * (2 * L.Lx - 1) + (L.Lx - 1) + x;
     if (C.sp[y * L.Lx + x] == C.sp[(y + 1) * L.Lx + x]) trace_skip(L, C.id, vb);
     if (x == L.Lx - 1 && !(C.sp[y * L.Lx + x] != C.sp[(y + 1) * L.Lx + x])) break;
-    int enxt = ecur + step4<T, DD, CC, BF16>(L, C, nxt, cur, y, x, 0, 0, Ux, Dx, false, lds);
+    int enxt = ecur + step4<T, DD, CC, BF16, BBX>(L, C, nxt, cur, y, x, 0, 0, Ux, Dx, false, lds);
     const int k1 = y * L.Lx + x, k2 = (y + 1) * L.Lx + x;
     if (C.sp[k1] != C.sp[k2]) {
       T* f = tmp + slot[2] * sz;
-      int ef = ecur + step4<T, DD, CC, BF16>(L, C, f, cur, y, x, 1, 1, Ux, Dx, false, lds);
+      int ef = ecur + step4<T, DD, CC, BF16, BBX>(L, C, f, cur, y, x, 1, 1, Ux, Dx, false, lds);
       double num = wg_dot<T>(f, R + (int64_t)(x + 1) * sz, sz);
       double den = wg_dot<T>(nxt, R + (int64_t)(x + 1) * sz, sz);
       bool acc = metropolis(L, C.id, C.meta, num, den, ef - enxt, vb);
@@ -428,10 +429,10 @@ __device__ __forceinline__ void ph_vsweep(const LatDev& L, int ch, int y, char* 
           T* nxt = tmp + slot[1] * sz;
           T* f1 = tmp + slot[2] * sz;
           T* f2 = tmp + slot[3] * sz;
-          const int ef1 = ecur + step4<T, DD, CC, BF16>(L, C, f1, cur, y, x, 1, 1, Ux, Dx, false, lds);
-          const int ef2 = ef1 + step4<T, DD, CC, BF16>(L, C, f2, f1, y, x + 1, 1, 1, Ux1, Dx1, false, lds);
+          const int ef1 = ecur + step4<T, DD, CC, BF16, BBX>(L, C, f1, cur, y, x, 1, 1, Ux, Dx, false, lds);
+          const int ef2 = ef1 + step4<T, DD, CC, BF16, BBX>(L, C, f2, f1, y, x + 1, 1, 1, Ux1, Dx1, false, lds);
           // the current network through column x+1, into the slot of cur (no longer needed)
-          const int eden = enxt + step4<T, DD, CC, BF16>(L, C, cur, nxt, y, x + 1, 0, 0, Ux1, Dx1, false, lds);
+          const int eden = enxt + step4<T, DD, CC, BF16, BBX>(L, C, cur, nxt, y, x + 1, 0, 0, Ux1, Dx1, false, lds);
           const double num = wg_dot<T>(f2, R + (int64_t)(x + 2) * sz, sz);
           const double den = wg_dot<T>(cur, R + (int64_t)(x + 2) * sz, sz);
           const double pi_back = net_sigmoid(net_logit<T>(Wn, C.sp, L.Ly, L.Lx, y, x, 1, lds));
@@ -655,7 +656,7 @@ __device__ __forceinline__ void ph_measure3(const LatDev& L, int ch, int y, cons
 }
 
 // Vertical and diagonal pairs between rows y and y+1 (two-row network).
-template <typename T, int DD, int CC>
+template <typename T, int DD, int CC, int BBX = 0>
 __device__ __forceinline__ void ph_measure4(const LatDev& L, int ch, int y, const SampleOut& o, char* lds) {
   Chain<T> C = chain_of<T>(L, ch);
   if (chain_flagged(C.meta)) return;
@@ -670,14 +671,14 @@ __device__ __forceinline__ void ph_measure4(const LatDev& L, int ch, int y, cons
   if (threadIdx.x == 0) { eR[Lx] = 0; eL[0] = 0; }
   __syncthreads();
   for (int x = Lx - 1; x >= 1; --x) {
-    int e = step4<T, DD, CC>(L, C, R + (int64_t)x * sz, R + (int64_t)(x + 1) * sz, y, x, 0, 0, ub<T>(L, C, y, x),
+    int e = step4<T, DD, CC, false, BBX>(L, C, R + (int64_t)x * sz, R + (int64_t)(x + 1) * sz, y, x, 0, 0, ub<T>(L, C, y, x),
                      db<T>(L, C, y + 2, x), true, lds);
     if (threadIdx.x == 0) eR[x] = eR[x + 1] + e;
     __syncthreads();
   }
   // left environments Le[1..max(Lx-1,1)]; Le[Lx] of a wider row pair is never needed
   for (int x = 0; x < (Lx > 1 ? Lx - 1 : 1); ++x) {
-    int e = step4<T, DD, CC>(L, C, Le + (int64_t)(x + 1) * sz, Le + (int64_t)x * sz, y, x, 0, 0, ub<T>(L, C, y, x),
+    int e = step4<T, DD, CC, false, BBX>(L, C, Le + (int64_t)(x + 1) * sz, Le + (int64_t)x * sz, y, x, 0, 0, ub<T>(L, C, y, x),
                      db<T>(L, C, y + 2, x), false, lds);
     if (threadIdx.x == 0) eL[x + 1] = eL[x] + e;
     __syncthreads();
@@ -693,7 +694,7 @@ __device__ __forceinline__ void ph_measure4(const LatDev& L, int ch, int y, cons
     if (C.sp[k1] == C.sp[k2]) {
       eacc += 0.25 * L.J1;
     } else {
-      int e1 = eL[x] + step4<T, DD, CC>(L, C, tmp, Le + (int64_t)x * sz, y, x, 1, 1, ub<T>(L, C, y, x), db<T>(L, C, y + 2, x), false, lds);
+      int e1 = eL[x] + step4<T, DD, CC, false, BBX>(L, C, tmp, Le + (int64_t)x * sz, y, x, 1, 1, ub<T>(L, C, y, x), db<T>(L, C, y + 2, x), false, lds);
       double num = wg_dot<T>(tmp, R + (int64_t)(x + 1) * sz, sz);
       rho = ldexp(num / Nm, e1 + eR[x + 1] - eN);
       eacc += -0.25 * L.J1 + 0.5 * L.J1 * rho;
@@ -713,9 +714,9 @@ __device__ __forceinline__ void ph_measure4(const LatDev& L, int ch, int y, cons
         } else {
           // column x: flips (y,x) for which 0 and (y+1,x) for which 1; column x+1 the other site
           int f1a = which == 0 ? 1 : 0, f1b = which == 0 ? 0 : 1;
-          int e1 = eL[x] + step4<T, DD, CC>(L, C, tmp, Le + (int64_t)x * sz, y, x, f1a, f1b, ub<T>(L, C, y, x),
+          int e1 = eL[x] + step4<T, DD, CC, false, BBX>(L, C, tmp, Le + (int64_t)x * sz, y, x, f1a, f1b, ub<T>(L, C, y, x),
                                     db<T>(L, C, y + 2, x), false, lds);
-          int e2 = e1 + step4<T, DD, CC>(L, C, tmp + sz, tmp, y, x + 1, 1 - f1a, 1 - f1b, ub<T>(L, C, y, x + 1),
+          int e2 = e1 + step4<T, DD, CC, false, BBX>(L, C, tmp + sz, tmp, y, x + 1, 1 - f1a, 1 - f1b, ub<T>(L, C, y, x + 1),
                                  db<T>(L, C, y + 2, x + 1), false, lds);
           double num = wg_dot<T>(tmp + sz, R + (int64_t)(x + 2) * sz, sz);
           rho = ldexp(num / Nm, e2 + eR[x + 2] - eN);
@@ -732,9 +733,9 @@ __device__ __forceinline__ void ph_measure4(const LatDev& L, int ch, int y, cons
       const int k1 = y * Lx + x, k2 = k1 + Lx;
       double rho = 0.0;
       if (C.sp[k1] + C.sp[k1 + 1] + C.sp[k2] + C.sp[k2 + 1] == 2) {
-        int e1 = eL[x] + step4<T, DD, CC>(L, C, tmp, Le + (int64_t)x * sz, y, x, 1, 1, ub<T>(L, C, y, x),
+        int e1 = eL[x] + step4<T, DD, CC, false, BBX>(L, C, tmp, Le + (int64_t)x * sz, y, x, 1, 1, ub<T>(L, C, y, x),
                                           db<T>(L, C, y + 2, x), false, lds);
-        int e2 = e1 + step4<T, DD, CC>(L, C, tmp + sz, tmp, y, x + 1, 1, 1, ub<T>(L, C, y, x + 1),
+        int e2 = e1 + step4<T, DD, CC, false, BBX>(L, C, tmp + sz, tmp, y, x + 1, 1, 1, ub<T>(L, C, y, x + 1),
                                        db<T>(L, C, y + 2, x + 1), false, lds);
         double num = wg_dot<T>(tmp + sz, R + (int64_t)(x + 2) * sz, sz);
         rho = ldexp(num / Nm, e2 + eR[x + 2] - eN);
@@ -760,22 +761,23 @@ __global__ void __launch_bounds__(WG, 2) k_hsweep(LatDev L, int y, int last_row,
   ph_hsweep<T, DD, CC, BF16>(L, blockIdx.x, y, last_row, moves, lds);
 }
 // LDS of a 2-row step: the bf16 step stages compact bf16 operands.
-template <typename T, int DD, int CC, bool BF16>
+template <typename T, int DD, int CC, bool BF16, int BBX = 0>
 constexpr size_t step4_lds() {
   if constexpr (BF16 && DD > 0) return Env4Bf<DD, CC>::lds_bytes();
-  else return env4_lds<T, T, DD, CC>();
+  else return env4_lds<T, T, DD, CC, false, BBX>();
 }
 
-template <typename T, int DD, int CC, bool BF16>
+// BBX: b-block of the fused 2-row step (a tile variant, 0 = default).
+template <typename T, int DD, int CC, bool BF16, int BBX = 0>
 __global__ void __launch_bounds__(WG, 2) k_row4_right(LatDev L, int y) {
-  __shared__ __attribute__((aligned(16))) char lds[step4_lds<T, DD, CC, BF16>()];
-  ph_row4_right<T, DD, CC, BF16>(L, blockIdx.x, y, lds);
+  __shared__ __attribute__((aligned(16))) char lds[step4_lds<T, DD, CC, BF16, BBX>()];
+  ph_row4_right<T, DD, CC, BF16, BBX>(L, blockIdx.x, y, lds);
 }
-template <typename T, int DD, int CC, bool BF16, bool LEARN>
+template <typename T, int DD, int CC, bool BF16, bool LEARN, int BBX = 0>
 __global__ void __launch_bounds__(WG, 2) k_vsweep(LatDev L, int y) {
   __shared__ __attribute__((aligned(16)))
-  char lds[cmax(step4_lds<T, DD, CC, BF16>(), LEARN ? net_lds_bytes<T>() : 0)];
-  ph_vsweep<T, DD, CC, BF16, LEARN>(L, blockIdx.x, y, lds);
+  char lds[cmax(step4_lds<T, DD, CC, BF16, BBX>(), LEARN ? net_lds_bytes<T>() : 0)];
+  ph_vsweep<T, DD, CC, BF16, LEARN, BBX>(L, blockIdx.x, y, lds);
 }
 template <typename T, int DD, int CC>
 __global__ void __launch_bounds__(WG, 2) k_compress(LatDev L, int y, int upper) {
@@ -787,10 +789,10 @@ __global__ void __launch_bounds__(WG, 2) k_measure3(LatDev L, int y, SampleOut o
   __shared__ __attribute__((aligned(16))) char lds[step3_lds<T, DD, CC, false, true>()];
   ph_measure3<T, DD, CC>(L, blockIdx.x, y, o, lds);
 }
-template <typename T, int DD, int CC>
+template <typename T, int DD, int CC, int BBX = 0>
 __global__ void __launch_bounds__(WG, 2) k_measure4(LatDev L, int y, SampleOut o) {
-  __shared__ __attribute__((aligned(16))) char lds[env4_lds<T, T, DD, CC>()];
-  ph_measure4<T, DD, CC>(L, blockIdx.x, y, o, lds);
+  __shared__ __attribute__((aligned(16))) char lds[env4_lds<T, T, DD, CC, false, BBX>()];
+  ph_measure4<T, DD, CC, BBX>(L, blockIdx.x, y, o, lds);
 }
 
 __global__ void k_begin_sample(LatDev L) {
@@ -1078,11 +1080,22 @@ void launch_psi_fixed(const LatDev& L, hipStream_t s) {
   const int y = L.Ly - 1;
   VP_DISPATCH_DC_BF(k_hsweep, T, false, L, y, 1, 0);
 }
+// Tile variants of the fused float32 / float64 2-row step at D = 8, Dc = 16: the
+// b-block BB = Dc/4 (variant 0, the default), Dc/8 (1) or Dc/2 (2).
+constexpr int tile_bb(int tile) { return tile == 1 ? 2 : (tile == 2 ? 8 : 0); }
+
 // bf16 operands are taken from float64 storage (VP_BF16 works in float64).
 template <typename T>
 void launch_row4_right(const LatDev& L, int y, bool bf16, hipStream_t s) {
   if constexpr (sizeof(T) == 8) {
     if (bf16) { VP_DISPATCH_DC_BF(k_row4_right, T, true, L, y); return; }
+  }
+  if (L.d == 8 && L.c == 16) {
+    const dim3 g(L.n_chains), b(WG);
+    if (L.tile == 1) hipLaunchKernelGGL((k_row4_right<T, 8, 16, false, tile_bb(1)>), g, b, 0, s, L, y);
+    else if (L.tile == 2) hipLaunchKernelGGL((k_row4_right<T, 8, 16, false, tile_bb(2)>), g, b, 0, s, L, y);
+    else hipLaunchKernelGGL((k_row4_right<T, 8, 16, false, 0>), g, b, 0, s, L, y);
+    return;
   }
   VP_DISPATCH_DC_BF(k_row4_right, T, false, L, y);
 }
@@ -1106,6 +1119,19 @@ void launch_vsweep(const LatDev& L, int y, bool bf16, bool learned, hipStream_t 
       return;
     }
   }
+  if (L.d == 8 && L.c == 16) {
+    const dim3 g(L.n_chains), b(WG);
+    if (learned) {
+      if (L.tile == 1) hipLaunchKernelGGL((k_vsweep<T, 8, 16, false, true, tile_bb(1)>), g, b, 0, s, L, y);
+      else if (L.tile == 2) hipLaunchKernelGGL((k_vsweep<T, 8, 16, false, true, tile_bb(2)>), g, b, 0, s, L, y);
+      else hipLaunchKernelGGL((k_vsweep<T, 8, 16, false, true, 0>), g, b, 0, s, L, y);
+    } else {
+      if (L.tile == 1) hipLaunchKernelGGL((k_vsweep<T, 8, 16, false, false, tile_bb(1)>), g, b, 0, s, L, y);
+      else if (L.tile == 2) hipLaunchKernelGGL((k_vsweep<T, 8, 16, false, false, tile_bb(2)>), g, b, 0, s, L, y);
+      else hipLaunchKernelGGL((k_vsweep<T, 8, 16, false, false, 0>), g, b, 0, s, L, y);
+    }
+    return;
+  }
   if (learned) VP_DISPATCH_DC_VS(T, false, true);
   else VP_DISPATCH_DC_VS(T, false, false);
 }
@@ -1119,6 +1145,13 @@ void launch_measure3(const LatDev& L, int y, const SampleOut& o, hipStream_t s) 
 }
 template <typename T>
 void launch_measure4(const LatDev& L, int y, const SampleOut& o, hipStream_t s) {
+  if (L.d == 8 && L.c == 16) {
+    const dim3 g(L.n_chains), b(WG);
+    if (L.tile == 1) hipLaunchKernelGGL((k_measure4<T, 8, 16, tile_bb(1)>), g, b, 0, s, L, y, o);
+    else if (L.tile == 2) hipLaunchKernelGGL((k_measure4<T, 8, 16, tile_bb(2)>), g, b, 0, s, L, y, o);
+    else hipLaunchKernelGGL((k_measure4<T, 8, 16, 0>), g, b, 0, s, L, y, o);
+    return;
+  }
   VP_DISPATCH_DC(k_measure4, T, L, y, o);
 }
 // One persistent launch: `grid` work-groups drain the item queue.
