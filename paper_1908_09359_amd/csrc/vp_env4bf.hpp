@@ -19,6 +19,7 @@
 namespace vp {
 
 typedef __bf16 v8bf_e __attribute__((ext_vector_type(8)));
+typedef __bf16 v4bf_e __attribute__((ext_vector_type(4)));
 typedef float v4f_e __attribute__((ext_vector_type(4)));
 
 template <int D, int C>
@@ -29,7 +30,11 @@ struct Env4Bf {
   static constexpr int K1 = C, K2 = D * D, K3 = D * D, K4 = D;      // contraction lengths
   static constexpr int P1 = rup8(K1) + 8, P2 = rup8(K2) + 8, P3 = rup8(K3) + 8, P4 = rup8(K4) + 8;  // row strides
   // operand arrays (bf16 elements)
-  static constexpr int nAT = D * C * P1;          // [(u, b)][a]
+  // rows (u, b) of the boundary tensor, each block of C rows (one u) shifted by
+  // UP elements: the 16 rows an S1 tile reads span several u, whose blocks
+  // would otherwise start in the same banks
+  static constexpr int UP = 32;
+  static constexpr int nAT = D * (C * P1 + UP);   // [(u, b)][a]
   static constexpr int nLs = D * D * P1;          // [(l1, l2)][a]     (one lower-bond slice)
   static constexpr int nT1 = D * D * P2;          // [(r1, m)][(l1, u)]
   static constexpr int nT2 = D * D * P3;          // [(r2, dd)][(l2, m)]
@@ -115,8 +120,9 @@ __device__ void env4_bf16(TS* __restrict__ Lout_p, const TS* __restrict__ Lin_p,
   // stage the column tensors once, transposed to k-contiguous rows; zero the
   // padding of every array (the intermediates' padding is never written later)
   for (int e = tid; e < S::nAT; e += WG) {
-    const int row = e / S::P1, a = e - row * S::P1, u = row / C, b = row - u * C;
-    AT[e] = a < C ? (__bf16)(float)A[a * sA.s0 + u * sA.s1 + b * sA.s2] : zero;
+    const int u = e / (C * S::P1 + S::UP), rem = e - u * (C * S::P1 + S::UP);
+    const int b = rem / S::P1, a = rem - b * S::P1;
+    AT[e] = (b < C && a < C) ? (__bf16)(float)A[a * sA.s0 + u * sA.s1 + b * sA.s2] : zero;
   }
   for (int e = tid; e < S::nT1; e += WG) {
     const int row = e / S::P2, k = e - row * S::P2;  // row = (r1, m), k = (l1, u)
@@ -137,24 +143,41 @@ __device__ void env4_bf16(TS* __restrict__ Lout_p, const TS* __restrict__ Lin_p,
 
   // lower-bond slices of Lin ([a][(l1,l2)], contiguous) are read coalesced one
   // slice ahead into registers, so their global-memory latency overlaps the
-  // previous slice's products, and transposed into Ls when stored
+  // previous slice's products, and transposed into Ls when stored.  QUAD: a
+  // thread holds four consecutive a of one row (l1,l2) and stores them in one
+  // 8-byte write (single 2-byte writes of the transpose would put eight lanes
+  // on each bank); each of its four reads is still coalesced across the row.
   constexpr int SL = C * D * D;
-  constexpr int NPF = (SL + WG - 1) / WG;
+  constexpr bool QUAD = C % 4 == 0 && (C / 4) * D * D <= WG;
+  constexpr int NPF = QUAD ? 4 : (SL + WG - 1) / WG;
+  const int qrow = tid % (D * D), qa = 4 * (tid / (D * D));
+  const bool qok = tid < (C / 4) * D * D;
   float pre[NPF];
   auto fetch = [&](int cs) {
 #pragma unroll
     for (int u = 0; u < NPF; ++u) {
-      const int e = tid + u * WG;
-      pre[u] = e < SL ? (float)Lin[cs * SL + e] : 0.0f;
+      if constexpr (QUAD) {
+        pre[u] = qok ? (float)Lin[cs * SL + (qa + u) * (D * D) + qrow] : 0.0f;
+      } else {
+        const int e = tid + u * WG;
+        pre[u] = e < SL ? (float)Lin[cs * SL + e] : 0.0f;
+      }
     }
   };
   // slices in the order (block, slice); the next one is stored into Ls as soon
   // as S1 of the current one has read it, so a slice costs four barriers
   auto store = [&]() {
+    if constexpr (QUAD) {
+      if (qok) {
+        const v4bf_e v = {(__bf16)pre[0], (__bf16)pre[1], (__bf16)pre[2], (__bf16)pre[3]};
+        *reinterpret_cast<v4bf_e*>(Ls + qrow * S::P1 + qa) = v;  // 8-byte aligned: P1 % 8 == 0
+      }
+    } else {
 #pragma unroll
-    for (int u = 0; u < NPF; ++u) {
-      const int e = tid + u * WG, a = e / (D * D), row = e - a * (D * D);  // row = (l1, l2)
-      if (e < SL) Ls[row * S::P1 + a] = (__bf16)pre[u];
+      for (int u = 0; u < NPF; ++u) {
+        const int e = tid + u * WG, a = e / (D * D), row = e - a * (D * D);  // row = (l1, l2)
+        if (e < SL) Ls[row * S::P1 + a] = (__bf16)pre[u];
+      }
     }
   };
   constexpr int NS = S::NBLK * C;
@@ -182,7 +205,7 @@ __device__ void env4_bf16(TS* __restrict__ Lout_p, const TS* __restrict__ Lin_p,
 #pragma unroll
             for (int s = 0; s < (S::K1 + 31) / 32; ++s) {
               const v8bf_e a = ld8(Ls + i * S::P1, 32 * s + kq, S::K1);
-              const v8bf_e b = ld8(AT + (u * C + b0 + bb) * S::P1, 32 * s + kq, S::K1);
+              const v8bf_e b = ld8(AT + u * (C * S::P1 + S::UP) + (b0 + bb) * S::P1, 32 * s + kq, S::K1);
               c4 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c4, 0, 0, 0);
             }
             return c4;
