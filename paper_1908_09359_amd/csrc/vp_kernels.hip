@@ -835,51 +835,54 @@ constexpr size_t sweep_lds() {
 }
 
 // Out-of-line phases of the persistent kernel: each keeps its own register
-// allocation instead of the union of all phases.
+// allocation instead of the union of all phases.  Their LDS argument is typed
+// as LDS, so that the phases inlined into them address it with LDS
+// instructions (through a plain pointer they would be flat ones).
+typedef __attribute__((address_space(3))) char lds_char;
 template <typename T, int DD, int CC, bool BF16>
-__device__ __noinline__ void nl_row3_right(const LatDev& L, int ch, int y, char* lds) {
-  ph_row3_right<T, DD, CC, BF16>(L, ch, y, y, y + 1, lds);
+__device__ __noinline__ void nl_row3_right(const LatDev& L, int ch, int y, lds_char* lds) {
+  ph_row3_right<T, DD, CC, BF16>(L, ch, y, y, y + 1, (char*)lds);
 }
 template <typename T, int DD, int CC, bool BF16>
-__device__ __noinline__ void nl_hsweep(const LatDev& L, int ch, int y, char* lds) {
-  ph_hsweep<T, DD, CC, BF16>(L, ch, y, y == L.Ly - 1, 1, lds);
+__device__ __noinline__ void nl_hsweep(const LatDev& L, int ch, int y, lds_char* lds) {
+  ph_hsweep<T, DD, CC, BF16>(L, ch, y, y == L.Ly - 1, 1, (char*)lds);
 }
 template <typename T, int DD, int CC, bool BF16>
-__device__ __noinline__ void nl_row4_right(const LatDev& L, int ch, int y, char* lds) {
-  ph_row4_right<T, DD, CC, BF16>(L, ch, y, lds);
+__device__ __noinline__ void nl_row4_right(const LatDev& L, int ch, int y, lds_char* lds) {
+  ph_row4_right<T, DD, CC, BF16>(L, ch, y, (char*)lds);
 }
 template <typename T, int DD, int CC, bool BF16, bool LEARN>
-__device__ __noinline__ void nl_vsweep(const LatDev& L, int ch, int y, char* lds) {
-  ph_vsweep<T, DD, CC, BF16, LEARN>(L, ch, y, lds);
+__device__ __noinline__ void nl_vsweep(const LatDev& L, int ch, int y, lds_char* lds) {
+  ph_vsweep<T, DD, CC, BF16, LEARN>(L, ch, y, (char*)lds);
 }
 template <typename T, int DD, int CC>
-__device__ __noinline__ void nl_compress(const LatDev& L, int ch, int y, int upper, char* lds) {
-  ph_compress<T, DD, CC>(L, ch, y, upper, lds);
+__device__ __noinline__ void nl_compress(const LatDev& L, int ch, int y, int upper, lds_char* lds) {
+  ph_compress<T, DD, CC>(L, ch, y, upper, (char*)lds);
 }
 template <typename T, int DD, int CC>
-__device__ __noinline__ void nl_measure3(const LatDev& L, int ch, int y, const SampleOut& o, char* lds) {
-  ph_measure3<T, DD, CC>(L, ch, y, o, lds);
+__device__ __noinline__ void nl_measure3(const LatDev& L, int ch, int y, const SampleOut& o, lds_char* lds) {
+  ph_measure3<T, DD, CC>(L, ch, y, o, (char*)lds);
 }
 template <typename T, int DD, int CC>
-__device__ __noinline__ void nl_measure4(const LatDev& L, int ch, int y, const SampleOut& o, char* lds) {
-  ph_measure4<T, DD, CC>(L, ch, y, o, lds);
+__device__ __noinline__ void nl_measure4(const LatDev& L, int ch, int y, const SampleOut& o, lds_char* lds) {
+  ph_measure4<T, DD, CC>(L, ch, y, o, (char*)lds);
 }
 
 template <typename T, int DD, int CC, bool BF16>
 __device__ void chain_sweep(const LatDev& L, int ch, const SampleOut* o, char* lds) {
   const int Ly = L.Ly;
   for (int y = 0; y < Ly; ++y) {
-    nl_row3_right<T, DD, CC, BF16>(L, ch, y, lds);
+    nl_row3_right<T, DD, CC, BF16>(L, ch, y, (lds_char*)lds);
     __syncthreads();
-    nl_hsweep<T, DD, CC, BF16>(L, ch, y, lds);
+    nl_hsweep<T, DD, CC, BF16>(L, ch, y, (lds_char*)lds);
     __syncthreads();
     if (y < Ly - 1) {
-      nl_row4_right<T, DD, CC, BF16>(L, ch, y, lds);
+      nl_row4_right<T, DD, CC, BF16>(L, ch, y, (lds_char*)lds);
       __syncthreads();
-      if (L.learned) nl_vsweep<T, DD, CC, BF16, true>(L, ch, y, lds);
-      else nl_vsweep<T, DD, CC, BF16, false>(L, ch, y, lds);
+      if (L.learned) nl_vsweep<T, DD, CC, BF16, true>(L, ch, y, (lds_char*)lds);
+      else nl_vsweep<T, DD, CC, BF16, false>(L, ch, y, (lds_char*)lds);
       __syncthreads();
-      nl_compress<T, DD, CC>(L, ch, y, 1, lds);
+      nl_compress<T, DD, CC>(L, ch, y, 1, (lds_char*)lds);
       __syncthreads();
     }
   }
@@ -888,15 +891,15 @@ __device__ void chain_sweep(const LatDev& L, int ch, const SampleOut* o, char* l
   __syncthreads();
   for (int y = Ly - 1; y >= 0; --y) {
     if (o) {
-      nl_measure3<T, DD, CC>(L, ch, y, *o, lds);
+      nl_measure3<T, DD, CC>(L, ch, y, *o, (lds_char*)lds);
       __syncthreads();
       if (y < Ly - 1) {
-        nl_measure4<T, DD, CC>(L, ch, y, *o, lds);
+        nl_measure4<T, DD, CC>(L, ch, y, *o, (lds_char*)lds);
         __syncthreads();
       }
     }
     if (y >= 1) {
-      nl_compress<T, DD, CC>(L, ch, y, 0, lds);
+      nl_compress<T, DD, CC>(L, ch, y, 0, (lds_char*)lds);
       __syncthreads();
     }
   }
