@@ -23,6 +23,14 @@ __device__ inline __attribute__((address_space(1))) T* gmem(T* p) {
   return (__attribute__((address_space(1))) T*)p;
 }
 
+// LDS-typed pointer to a work-group's shared memory.  A helper the compiler
+// keeps out of line receives its LDS through such a parameter: converted to a
+// plain pointer inside, the accesses are still LDS instructions (through a
+// plain parameter they would be flat ones whenever the compiler cannot prove
+// that every caller passes LDS).
+typedef __attribute__((address_space(3))) char lds_char;
+__device__ inline lds_char* as_lds(char* p) { return (lds_char*)p; }
+
 // ---------------------------------------------------------------------------
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11), written from its
 // definition: ten rounds of two 64x64->128 products, word permutation and key
@@ -391,7 +399,8 @@ __device__ void env4_step(TC* Lout, const TC* Lin, const T* A, S3 sA, const T* t
 //   Out[l][u][r][dd] = sum Lp[a][l][c] A[a][u][b] Rn[b][r][e] B[c][dd][e].
 template <typename T>
 __device__ void defect3(T* Out, const T* Lp, const T* A, S3 sA, const T* Rn, const T* B, S3 sB,
-                        T* X0, T* X1, int c, int d, char* tiles) {
+                        T* X0, T* X1, int c, int d, lds_char* tiles_l) {
+  char* tiles = (char*)tiles_l;
   using TC = T;
   // X0[l][u][c'][b] = sum_a Lp[a][(l,c')] A[a][(u,b)]
   wg_gemm_t<TC>(tiles, X0, view(c, d * c * c, c, c, c * c, 1), Lp, view(c, c, 1, 1, d * c, 0),
@@ -407,7 +416,8 @@ __device__ void defect3(T* Out, const T* Lp, const T* A, S3 sA, const T* Rn, con
 // Compression helper: Y[a][l][dd][k] = sum_{u,b,r} A[a][u][b] t[l][u][r][dd] Tin[b][r][k].
 template <typename TC, typename T>
 __device__ void compress_y(TC* Y, const T* A, S3 sA, const T* t, S4 st, const TC* Tin, TC* X0,
-                           int c, int d, char* tiles) {
+                           int c, int d, lds_char* tiles_l) {
+  char* tiles = (char*)tiles_l;
   // X0[a][k][u][r] = sum_b A[(a,u)][b] Tin[b][(r,k)]
   wg_gemm_t<TC>(tiles, X0, view(d, c * d * d, d, c, 1, d * d), A, view(d, sA.s0, sA.s1, 1, sA.s2, 0),
              Tin, view(1, d * c, 0, c, c, 1), c * d, d * c, c);

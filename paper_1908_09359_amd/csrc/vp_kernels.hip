@@ -104,7 +104,8 @@ constexpr bool fused3() {
 }
 template <typename T, int DD, int CC, bool BF16 = false>
 __device__ inline int step3(const LatDev& L, const Chain<T>& C, T* out, const T* in, int y, int x,
-                            int flip, const T* Ux, const T* Dx, bool right, char* tiles) {
+                            int flip, const T* Ux, const T* Dx, bool right, lds_char* tiles_l) {
+  char* tiles = (char*)tiles_l;
   int k = y * L.Lx + x;
   const T* t = tw<T>(L, k, C.sp[k] ^ flip);
   S4 st = st_std(L.d);
@@ -151,7 +152,8 @@ constexpr size_t env4_lds() {
 // operands with f32 accumulation.
 template <typename T, int DD, int CC, bool BF16 = false, int BBX = 0>
 __device__ inline int step4(const LatDev& L, const Chain<T>& C, T* out, const T* in, int y, int x,
-                            int flip1, int flip2, const T* Ux, const T* Dx, bool right, char* lds) {
+                            int flip1, int flip2, const T* Ux, const T* Dx, bool right, lds_char* lds_l) {
+  char* lds = (char*)lds_l;
   int k1 = y * L.Lx + x, k2 = (y + 1) * L.Lx + x;
   const T* t1 = tw<T>(L, k1, C.sp[k1] ^ flip1);
   const T* t2 = tw<T>(L, k2, C.sp[k2] ^ flip2);
@@ -220,7 +222,7 @@ __device__ __forceinline__ void ph_row3_right(const LatDev& L, int ch, int y, in
   if (threadIdx.x == 0) eR[L.Lx] = 0;
   for (int x = L.Lx - 1; x >= 1; --x) {
     int e = step3<T, DD, CC, BF16>(L, C, R + (int64_t)x * sz, R + (int64_t)(x + 1) * sz, y, x, 0,
-                           ub<T>(L, C, ub_slot, x), db<T>(L, C, db_slot, x), true, tiles);
+                           ub<T>(L, C, ub_slot, x), db<T>(L, C, db_slot, x), true, as_lds(tiles));
     if (threadIdx.x == 0) eR[x] = eR[x + 1] + e;
     __syncthreads();
   }
@@ -277,16 +279,16 @@ __device__ __forceinline__ void ph_hsweep(const LatDev& L, int ch, int y, int la
     const T* Dx = db<T>(L, C, y + 1, x);
     T* cur = tmp + slot[0] * sz;
     T* nxt = tmp + slot[1] * sz;
-    int enxt = ecur + step3<T, DD, CC, BF16>(L, C, nxt, cur, y, x, 0, Ux, Dx, false, tiles);
+    int enxt = ecur + step3<T, DD, CC, BF16>(L, C, nxt, cur, y, x, 0, Ux, Dx, false, as_lds(tiles));
     const int k = y * L.Lx + x;
     bool acc = false;
     if (moves && C.sp[k] == C.sp[k + 1]) trace_skip(L, C.id, y * (2 * L.Lx - 1) + x);
     if (moves && C.sp[k] != C.sp[k + 1]) {
       T* f1 = tmp + slot[2] * sz;
       T* f2 = tmp + slot[3] * sz;
-      int ef1 = ecur + step3<T, DD, CC, BF16>(L, C, f1, cur, y, x, 1, Ux, Dx, false, tiles);
+      int ef1 = ecur + step3<T, DD, CC, BF16>(L, C, f1, cur, y, x, 1, Ux, Dx, false, as_lds(tiles));
       int ef2 = ef1 + step3<T, DD, CC, BF16>(L, C, f2, f1, y, x + 1, 1, ub<T>(L, C, y, x + 1),
-                                     db<T>(L, C, y + 1, x + 1), false, tiles);
+                                     db<T>(L, C, y + 1, x + 1), false, as_lds(tiles));
       double num = wg_dot<T>(f2, R + (int64_t)(x + 2) * sz, sz);
       double den = wg_dot<T>(nxt, R + (int64_t)(x + 1) * sz, sz);
       int bond = y * (2 * L.Lx - 1) + x;
@@ -314,7 +316,7 @@ __device__ __forceinline__ void ph_hsweep(const LatDev& L, int ch, int y, int la
     T* cur = tmp + slot[0] * sz;
     T* nxt = tmp + slot[1] * sz;
     int e = ecur + step3<T, DD, CC, BF16>(L, C, nxt, cur, y, x, 0, ub<T>(L, C, y, x), db<T>(L, C, y + 1, x), false,
-                                  tiles);
+                                  as_lds(tiles));
     double v = (double)nxt[0];
     if (threadIdx.x == 0) {
       if (v == 0.0) {
@@ -341,7 +343,7 @@ __device__ __forceinline__ void ph_row4_right(const LatDev& L, int ch, int y, ch
   if (threadIdx.x == 0) eR[L.Lx] = 0;
   for (int x = L.Lx - 1; x >= 1; --x) {
     int e = step4<T, DD, CC, BF16, BBX>(L, C, R + (int64_t)x * sz, R + (int64_t)(x + 1) * sz, y, x, 0, 0,
-                                   ub<T>(L, C, y, x), db<T>(L, C, y + 2, x), true, lds);
+                                   ub<T>(L, C, y, x), db<T>(L, C, y + 2, x), true, as_lds(lds));
     if (threadIdx.x == 0) eR[x] = eR[x + 1] + e;
     __syncthreads();
   }
@@ -391,11 +393,11 @@ __device__ __forceinline__ void ph_vsweep(const LatDev& L, int ch, int y, char* 
     const int vb = y * (2 * L.Lx - 1) + (L.Lx - 1) + x;
     if (C.sp[y * L.Lx + x] == C.sp[(y + 1) * L.Lx + x]) trace_skip(L, C.id, vb);
     if (x == L.Lx - 1 && !(C.sp[y * L.Lx + x] != C.sp[(y + 1) * L.Lx + x])) break;
-    int enxt = ecur + step4<T, DD, CC, BF16, BBX>(L, C, nxt, cur, y, x, 0, 0, Ux, Dx, false, lds);
+    int enxt = ecur + step4<T, DD, CC, BF16, BBX>(L, C, nxt, cur, y, x, 0, 0, Ux, Dx, false, as_lds(lds));
     const int k1 = y * L.Lx + x, k2 = (y + 1) * L.Lx + x;
     if (C.sp[k1] != C.sp[k2]) {
       T* f = tmp + slot[2] * sz;
-      int ef = ecur + step4<T, DD, CC, BF16, BBX>(L, C, f, cur, y, x, 1, 1, Ux, Dx, false, lds);
+      int ef = ecur + step4<T, DD, CC, BF16, BBX>(L, C, f, cur, y, x, 1, 1, Ux, Dx, false, as_lds(lds));
       double num = wg_dot<T>(f, R + (int64_t)(x + 1) * sz, sz);
       double den = wg_dot<T>(nxt, R + (int64_t)(x + 1) * sz, sz);
       bool acc = metropolis(L, C.id, C.meta, num, den, ef - enxt, vb);
@@ -429,10 +431,10 @@ __device__ __forceinline__ void ph_vsweep(const LatDev& L, int ch, int y, char* 
           T* nxt = tmp + slot[1] * sz;
           T* f1 = tmp + slot[2] * sz;
           T* f2 = tmp + slot[3] * sz;
-          const int ef1 = ecur + step4<T, DD, CC, BF16, BBX>(L, C, f1, cur, y, x, 1, 1, Ux, Dx, false, lds);
-          const int ef2 = ef1 + step4<T, DD, CC, BF16, BBX>(L, C, f2, f1, y, x + 1, 1, 1, Ux1, Dx1, false, lds);
+          const int ef1 = ecur + step4<T, DD, CC, BF16, BBX>(L, C, f1, cur, y, x, 1, 1, Ux, Dx, false, as_lds(lds));
+          const int ef2 = ef1 + step4<T, DD, CC, BF16, BBX>(L, C, f2, f1, y, x + 1, 1, 1, Ux1, Dx1, false, as_lds(lds));
           // the current network through column x+1, into the slot of cur (no longer needed)
-          const int eden = enxt + step4<T, DD, CC, BF16, BBX>(L, C, cur, nxt, y, x + 1, 0, 0, Ux1, Dx1, false, lds);
+          const int eden = enxt + step4<T, DD, CC, BF16, BBX>(L, C, cur, nxt, y, x + 1, 0, 0, Ux1, Dx1, false, as_lds(lds));
           const double num = wg_dot<T>(f2, R + (int64_t)(x + 2) * sz, sz);
           const double den = wg_dot<T>(cur, R + (int64_t)(x + 2) * sz, sz);
           const double pi_back = net_sigmoid(net_logit<T>(Wn, C.sp, L.Ly, L.Lx, y, x, 1, lds));
@@ -520,7 +522,7 @@ __device__ __forceinline__ void ph_compress(const LatDev& L, int ch, int y, int 
   for (int j = Lx - 1; j >= 1; --j) {
     const int k = y * Lx + j;
     const T* t = tw<T>(L, k, C.sp[k]);
-    compress_y<double, T>(Y, A_in(j), sA, t, st, Ta, X0, c, d, lds);
+    compress_y<double, T>(Y, A_in(j), sA, t, st, Ta, X0, c, d, as_lds(lds));
     // W = G_{j-1} Y, G viewed as ((a,l), (a',l')); stored [a'][a][l][l'] (fused) or [a][l][l'][a']
     const View gv = DD > 0 ? view(d, d * d, d, d, c * d * d, 1) : view(d, d * d * c, d * c, d, 1, c);
     wg_gemm_t<double>(lds, W, rowmajor(dc), G + (int64_t)j * gsz, gv, Y, rowmajor(dc), dc, dc, dc);
@@ -554,7 +556,7 @@ __device__ __forceinline__ void ph_compress(const LatDev& L, int ch, int y, int 
   {
     const int k = y * Lx;
     const T* t = tw<T>(L, k, C.sp[k]);
-    compress_y<double, T>(Y, A_in(0), sA, t, st, Ta, X0, c, d, lds);
+    compress_y<double, T>(Y, A_in(0), sA, t, st, Ta, X0, c, d, as_lds(lds));
     double nrm2 = 0.0;
     for (int i = threadIdx.x; i < dc; i += WG) nrm2 += Y[i] * Y[i];
     nrm2 = wg_sum(nrm2);
@@ -591,14 +593,14 @@ __device__ __forceinline__ void ph_measure3(const LatDev& L, int ch, int y, cons
   __syncthreads();
   for (int x = Lx - 1; x >= 1; --x) {
     int e = step3<T, DD, CC>(L, C, R + (int64_t)x * sz, R + (int64_t)(x + 1) * sz, y, x, 0, ub<T>(L, C, y, x),
-                     db<T>(L, C, y + 1, x), true, tiles);
+                     db<T>(L, C, y + 1, x), true, as_lds(tiles));
     if (threadIdx.x == 0) eR[x] = eR[x + 1] + e;
     __syncthreads();
   }
   // left environments Le[1..max(Lx-1,1)]; Le[Lx] of a wider row is never needed
   for (int x = 0; x < (Lx > 1 ? Lx - 1 : 1); ++x) {
     int e = step3<T, DD, CC>(L, C, Le + (int64_t)(x + 1) * sz, Le + (int64_t)x * sz, y, x, 0, ub<T>(L, C, y, x),
-                     db<T>(L, C, y + 1, x), false, tiles);
+                     db<T>(L, C, y + 1, x), false, as_lds(tiles));
     if (threadIdx.x == 0) eL[x + 1] = eL[x] + e;
     __syncthreads();
   }
@@ -619,7 +621,7 @@ __device__ __forceinline__ void ph_measure3(const LatDev& L, int ch, int y, cons
                                  R + (int64_t)(x + 1) * sz, db<T>(L, C, y + 1, x), sb_std(CC, DD), tiles);
       else
         defect3<T>(Dl, Le + (int64_t)x * sz, ub<T>(L, C, y, x), sb_std(L.c, d), R + (int64_t)(x + 1) * sz,
-                   db<T>(L, C, y + 1, x), sb_std(L.c, d), C.ws + L.oX0, C.ws + L.oX1, L.c, d, tiles);
+                   db<T>(L, C, y + 1, x), sb_std(L.c, d), C.ws + L.oX0, C.ws + L.oX1, L.c, d, as_lds(tiles));
       const double f = ldexp(1.0 / Nm, eL[x] + eR[x + 1] - eN);
       const int dl = L.dims[4 * k], du = L.dims[4 * k + 1], dr = L.dims[4 * k + 2], dd = L.dims[4 * k + 3];
       const int n = dl * du * dr * dd;
@@ -640,9 +642,9 @@ __device__ __forceinline__ void ph_measure3(const LatDev& L, int ch, int y, cons
       eacc += 0.25 * L.J1;
     } else {
       int e1 = eL[x] + step3<T, DD, CC>(L, C, tmp, Le + (int64_t)x * sz, y, x, 1, ub<T>(L, C, y, x), db<T>(L, C, y + 1, x),
-                                false, tiles);
+                                false, as_lds(tiles));
       int e2 = e1 + step3<T, DD, CC>(L, C, tmp + sz, tmp, y, x + 1, 1, ub<T>(L, C, y, x + 1), db<T>(L, C, y + 1, x + 1),
-                             false, tiles);
+                             false, as_lds(tiles));
       double num = wg_dot<T>(tmp + sz, R + (int64_t)(x + 2) * sz, sz);
       rho = ldexp(num / Nm, e2 + eR[x + 2] - eN);
       eacc += -0.25 * L.J1 + 0.5 * L.J1 * rho;
@@ -672,14 +674,14 @@ __device__ __forceinline__ void ph_measure4(const LatDev& L, int ch, int y, cons
   __syncthreads();
   for (int x = Lx - 1; x >= 1; --x) {
     int e = step4<T, DD, CC, false, BBX>(L, C, R + (int64_t)x * sz, R + (int64_t)(x + 1) * sz, y, x, 0, 0, ub<T>(L, C, y, x),
-                     db<T>(L, C, y + 2, x), true, lds);
+                     db<T>(L, C, y + 2, x), true, as_lds(lds));
     if (threadIdx.x == 0) eR[x] = eR[x + 1] + e;
     __syncthreads();
   }
   // left environments Le[1..max(Lx-1,1)]; Le[Lx] of a wider row pair is never needed
   for (int x = 0; x < (Lx > 1 ? Lx - 1 : 1); ++x) {
     int e = step4<T, DD, CC, false, BBX>(L, C, Le + (int64_t)(x + 1) * sz, Le + (int64_t)x * sz, y, x, 0, 0, ub<T>(L, C, y, x),
-                     db<T>(L, C, y + 2, x), false, lds);
+                     db<T>(L, C, y + 2, x), false, as_lds(lds));
     if (threadIdx.x == 0) eL[x + 1] = eL[x] + e;
     __syncthreads();
   }
@@ -694,7 +696,7 @@ __device__ __forceinline__ void ph_measure4(const LatDev& L, int ch, int y, cons
     if (C.sp[k1] == C.sp[k2]) {
       eacc += 0.25 * L.J1;
     } else {
-      int e1 = eL[x] + step4<T, DD, CC, false, BBX>(L, C, tmp, Le + (int64_t)x * sz, y, x, 1, 1, ub<T>(L, C, y, x), db<T>(L, C, y + 2, x), false, lds);
+      int e1 = eL[x] + step4<T, DD, CC, false, BBX>(L, C, tmp, Le + (int64_t)x * sz, y, x, 1, 1, ub<T>(L, C, y, x), db<T>(L, C, y + 2, x), false, as_lds(lds));
       double num = wg_dot<T>(tmp, R + (int64_t)(x + 1) * sz, sz);
       rho = ldexp(num / Nm, e1 + eR[x + 1] - eN);
       eacc += -0.25 * L.J1 + 0.5 * L.J1 * rho;
@@ -715,9 +717,9 @@ __device__ __forceinline__ void ph_measure4(const LatDev& L, int ch, int y, cons
           // column x: flips (y,x) for which 0 and (y+1,x) for which 1; column x+1 the other site
           int f1a = which == 0 ? 1 : 0, f1b = which == 0 ? 0 : 1;
           int e1 = eL[x] + step4<T, DD, CC, false, BBX>(L, C, tmp, Le + (int64_t)x * sz, y, x, f1a, f1b, ub<T>(L, C, y, x),
-                                    db<T>(L, C, y + 2, x), false, lds);
+                                    db<T>(L, C, y + 2, x), false, as_lds(lds));
           int e2 = e1 + step4<T, DD, CC, false, BBX>(L, C, tmp + sz, tmp, y, x + 1, 1 - f1a, 1 - f1b, ub<T>(L, C, y, x + 1),
-                                 db<T>(L, C, y + 2, x + 1), false, lds);
+                                 db<T>(L, C, y + 2, x + 1), false, as_lds(lds));
           double num = wg_dot<T>(tmp + sz, R + (int64_t)(x + 2) * sz, sz);
           rho = ldexp(num / Nm, e2 + eR[x + 2] - eN);
           eacc += -0.25 * L.J2 + 0.5 * L.J2 * rho;
@@ -734,9 +736,9 @@ __device__ __forceinline__ void ph_measure4(const LatDev& L, int ch, int y, cons
       double rho = 0.0;
       if (C.sp[k1] + C.sp[k1 + 1] + C.sp[k2] + C.sp[k2 + 1] == 2) {
         int e1 = eL[x] + step4<T, DD, CC, false, BBX>(L, C, tmp, Le + (int64_t)x * sz, y, x, 1, 1, ub<T>(L, C, y, x),
-                                          db<T>(L, C, y + 2, x), false, lds);
+                                          db<T>(L, C, y + 2, x), false, as_lds(lds));
         int e2 = e1 + step4<T, DD, CC, false, BBX>(L, C, tmp + sz, tmp, y, x + 1, 1, 1, ub<T>(L, C, y, x + 1),
-                                       db<T>(L, C, y + 2, x + 1), false, lds);
+                                       db<T>(L, C, y + 2, x + 1), false, as_lds(lds));
         double num = wg_dot<T>(tmp + sz, R + (int64_t)(x + 2) * sz, sz);
         rho = ldexp(num / Nm, e2 + eR[x + 2] - eN);
       }
@@ -838,7 +840,6 @@ constexpr size_t sweep_lds() {
 // allocation instead of the union of all phases.  Their LDS argument is typed
 // as LDS, so that the phases inlined into them address it with LDS
 // instructions (through a plain pointer they would be flat ones).
-typedef __attribute__((address_space(3))) char lds_char;
 template <typename T, int DD, int CC, bool BF16>
 __device__ __noinline__ void nl_row3_right(const LatDev& L, int ch, int y, lds_char* lds) {
   ph_row3_right<T, DD, CC, BF16>(L, ch, y, y, y + 1, (char*)lds);
