@@ -28,8 +28,13 @@ struct Env3Shape {
   static constexpr bool ok = D * D == 64 && D * C == 128;
   static constexpr int BB = C / 4, NBLK = 4;
   static constexpr int SA = C * D * C;   // one boundary-MPS site, staged in LDS
-  static constexpr int P0 = C * BB + 1;  // X0 rows (l,u), columns (c,bb)
-  static constexpr int P1 = BB * D + 1;  // X1 rows (c,dd), columns (bb,r)
+  // Row strides of the intermediates, chosen for the stores of the MFMA outputs:
+  // the 16 lanes of a tile row write X0 at u P0 + bb (u, bb < 4) and X1 at
+  // dd P1 + r (dd < 8, r < 2); P0 = 4 and P1 = 2 (mod 16) put them on distinct
+  // banks (in float32 the next 16 lanes, four output rows on, land on the other
+  // 16 banks).
+  static constexpr int P0 = C * BB + 4;  // X0 rows (l,u), columns (c,bb)
+  static constexpr int P1 = BB * D + 2;  // X1 rows (c,dd), columns (bb,r)
   static constexpr int SX = (D * D * P0 > C * D * P1) ? D * D * P0 : C * D * P1;
   static constexpr int SP = 2 * 256;     // split-K partial tiles of S3
   template <typename T>
