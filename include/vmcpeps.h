@@ -213,6 +213,23 @@ vp_status vp_eval(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev, int32_t n_c
                   double* log_abs_psi_dev, int8_t* sign_dev, double* e_loc_dev,
                   void* dlnpsi_dev, double* ratios_dev);
 
+/* Spin-inversion symmetrisation (Sec. III, symmetrised wave function
+ * Phi(S) = Psi(S) + Psi(Sbar), Sbar = S with every spin reversed; observables
+ * are taken with the weight |Phi(S)|^2).  For the configurations spins_dev
+ * [n_cfg][N] (1 <= n_cfg <= n_chains, S^z_tot = 0) evaluates S and Sbar as
+ * vp_eval does and writes, per configuration (device pointers, n_cfg entries
+ * each, caller-owned): log_abs_phi_dev log|Phi(S)|, sign_phi_dev its sign,
+ * e_loc_phi_dev E_Phi(S) = sum_S' <S|H|S'> Phi(S')/Phi(S)
+ * = (Psi(S) E_loc(S) + Psi(Sbar) E_loc(Sbar)) / Phi(S), and log_w_dev
+ * log(|Phi(S)|^2 / |Psi(S)|^2), the weight that turns samples of |Psi|^2 (from
+ * vp_sample) into samples of |Phi|^2: <O>_Phi = sum w O / sum w.  Where
+ * Psi(Sbar) = -Psi(S) exactly, log|Phi| and log w are -inf, the sign 0 and
+ * E_Phi 0.  Allocates and frees a workspace of n_cfg (N + 17) bytes; waits for
+ * the stream; same preconditions and errors as vp_eval; invalidates the
+ * sampler's state. */
+vp_status vp_eval_sis(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev, int32_t n_cfg,
+                      double* log_abs_phi_dev, int8_t* sign_phi_dev, double* e_loc_phi_dev, double* log_w_dev);
+
 /* Two truncation cutoffs (Sec. II.A, App. D): the chains of lattice
  * lat_sample move with its cutoff Dc1 (a ratio only meets a uniform number,
  * so a modest cutoff suffices), and after every sweep past the n_burn first

@@ -16,7 +16,8 @@ spin of S, and observables are taken with the weight |Phi(S)|^2.
                        Phi(S')/Phi(S) = (Psi(S) r + Psi(Sbar) rbar) / (Psi(S) + Psi(Sbar))
                        with r = Psi(S')/Psi(S), rbar = Psi(Sbar')/Psi(Sbar).
                        The Heisenberg elements are invariant under the reversal
-                       (<Sbar|H|Sbar'> = <S|H|S'>).
+                       (<Sbar|H|Sbar'> = <S|H|S'>).  Also returned: log|Psi(S)|
+                       and log|Psi(Sbar)|, which fix the conditioning of the sum.
 * ``reweighted_mean`` -- <O>_Phi = sum_i w_i O_i / sum_i w_i over samples drawn
                        from |Psi|^2.
 
@@ -63,7 +64,8 @@ def eval_config(T, lat, spins):
     e_phi = local_energy(lat, spins, phi_ratio)
     log_abs_phi = m + math.log(abs(phi))
     return dict(sign=1 if phi > 0 else -1, log_abs_phi=log_abs_phi, e_loc=e_phi,
-                log_w=2.0 * (log_abs_phi - a["log_abs_psi"]))
+                log_w=2.0 * (log_abs_phi - a["log_abs_psi"]),
+                log_abs_psi=a["log_abs_psi"], log_abs_psi_rev=b["log_abs_psi"])
 
 
 def reweighted_mean(values, log_w):

@@ -28,7 +28,7 @@ EXPORTED = ["vp_create", "vp_destroy", "vp_last_error", "vp_num_params", "vp_wor
             "vp_proposal_num_params", "vp_proposal_set_weights", "vp_proposal_get_weights", "vp_proposal_forward",
             "vp_proposal_loss_grad", "vp_proposal_train", "vp_set_sampler", "vp_move_counts", "vp_set_schedule",
             "vp_sample_batch", "vp_autotune", "vp_sample_split", "vp_optimize", "vp_set_tile",
-            "vp_autotune_tiles"]
+            "vp_autotune_tiles", "vp_eval_sis"]
 
 PHASES = ["row3_envs", "hsweep", "row4_envs", "vsweep", "compress_up", "compress_down", "measure3",
           "measure4", "other"]
@@ -71,6 +71,7 @@ def _load():
         "vp_init_chains": ([P, I32, P], I32),
         "vp_sample": ([P, I32, I32, I32, P, P, P, P, P, P], I32),
         "vp_eval": ([P, I32, P, I32, P, P, P, P, P], I32),
+        "vp_eval_sis": ([P, I32, P, I32, P, P, P, P], I32),
         "vp_gradient": ([P, I32, P, P, P, I64, P, P], I32),
         "vp_sr_update": ([P, I32, P, P, P, I64, D, D, P], I32),
         "vp_sign_sgd_update": ([P, I32, P, D, U64], I32),
@@ -268,6 +269,10 @@ class Context:
     def vp_eval(self, lat, spins, n_cfg, log_abs_psi, sign, e_loc, dlnpsi=None, ratios=None):
         self._check(LIB.vp_eval(self.h, lat, _ptr(spins), n_cfg, _ptr(log_abs_psi), _ptr(sign), _ptr(e_loc),
                                 _ptr(dlnpsi), _ptr(ratios)))
+
+    def vp_eval_sis(self, lat, spins, n_cfg, log_abs_phi, sign, e_loc, log_w):
+        self._check(LIB.vp_eval_sis(self.h, lat, _ptr(spins), n_cfg, _ptr(log_abs_phi), _ptr(sign), _ptr(e_loc),
+                                    _ptr(log_w)))
 
     def vp_gradient(self, lat, e_loc, dlnpsi, spins, n_samples, grad, e_mean):
         self._check(LIB.vp_gradient(self.h, lat, _ptr(e_loc), _ptr(dlnpsi), _ptr(spins), n_samples,

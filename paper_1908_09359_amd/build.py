@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libvmcpeps.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["vp_kernels.hip", "vp_sr.hip", "vp_net.hip", "vp_api.cpp"]
+SOURCES = ["vp_kernels.hip", "vp_sr.hip", "vp_net.hip", "vp_sis.hip", "vp_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("VP_OFFLOAD_ARCH", "gfx950")

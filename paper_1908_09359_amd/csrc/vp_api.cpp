@@ -922,6 +922,40 @@ vp_status vp_eval(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev, int32_t n_c
   return eval_configs(ctx, L, spins_dev, n_cfg, o);
 }
 
+vp_status vp_eval_sis(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev, int32_t n_cfg, double* log_abs_phi_dev,
+                      int8_t* sign_phi_dev, double* e_loc_phi_dev, double* log_w_dev) {
+  Lattice* L = get_lat(ctx, lat);
+  if (!L || !spins_dev) return fail(ctx, VP_ERR_ARG, "bad lattice index or null spins");
+  if (!log_abs_phi_dev || !sign_phi_dev || !e_loc_phi_dev || !log_w_dev)
+    return fail(ctx, VP_ERR_ARG, "null output pointer");
+  if (n_cfg < 1 || n_cfg > L->p.n_chains) return fail(ctx, VP_ERR_ARG, "need 1 <= n_cfg <= n_chains");
+  hipStream_t s = ctx->stream;
+  const size_t nb = (size_t)n_cfg * L->N;
+  // workspace: reversed configurations, then log|Psi(Sbar)|, E_loc(Sbar), sign(Sbar)
+  char* work = nullptr;
+  const size_t off_l = (nb + 255) / 256 * 256, off_e = off_l + sizeof(double) * n_cfg,
+               off_s = off_e + sizeof(double) * n_cfg;
+  if (hipMalloc((void**)&work, off_s + n_cfg) != hipSuccess) return fail(ctx, VP_ERR_OOM, "symmetrisation workspace");
+  int8_t* rev = (int8_t*)work;
+  double* lr = (double*)(work + off_l);
+  double* er = (double*)(work + off_e);
+  int8_t* sr = (int8_t*)(work + off_s);
+  // S into the caller's outputs, Sbar into the workspace, then combined in place
+  vp_status st = vp_eval(ctx, lat, spins_dev, n_cfg, log_abs_phi_dev, sign_phi_dev, e_loc_phi_dev, nullptr, nullptr);
+  if (st == VP_OK) {
+    launch_reverse_spins(spins_dev, rev, (int64_t)nb, s);
+    st = vp_eval(ctx, lat, rev, n_cfg, lr, sr, er, nullptr, nullptr);
+  }
+  if (st == VP_OK) {
+    launch_sis_combine(n_cfg, log_abs_phi_dev, sign_phi_dev, e_loc_phi_dev, lr, sr, er, log_w_dev, s);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+      st = fail(ctx, VP_ERR_DEVICE, "symmetrisation kernel failed");
+  }
+  hipStreamSynchronize(s);
+  hipFree(work);
+  return st;
+}
+
 vp_status vp_sample_split(vp_ctx* ctx, int32_t lat_sample, int32_t lat_measure, int32_t n_burn, int32_t n_meas,
                           double* log_abs_psi_dev, int8_t* sign_dev, double* e_loc_dev, void* dlnpsi_dev,
                           int8_t* spins_out_dev) {

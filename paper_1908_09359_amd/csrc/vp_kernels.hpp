@@ -137,4 +137,10 @@ void net_gather(const int8_t* spins, const double* ratios, const int32_t* idx, i
                 double* rb, hipStream_t s);
 void net_cast_f64(const float* src, double* dst, hipStream_t s);
 
+// Spin-inversion symmetrisation: t = reversed s (n bytes); the outputs of S
+// combined in place with those of Sbar into log|Phi|, sign, E_Phi and log w.
+void launch_reverse_spins(const int8_t* s, int8_t* t, int64_t n, hipStream_t st);
+void launch_sis_combine(int n, double* log_abs, int8_t* sign, double* e_loc, const double* log_abs_r,
+                        const int8_t* sign_r, const double* e_loc_r, double* log_w, hipStream_t st);
+
 }  // namespace vp
