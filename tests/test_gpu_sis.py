@@ -143,3 +143,71 @@ def test_sis_errors_are_reported():
     torch.cuda.synchronize()
     assert np.all(np.isfinite(lw[:2].cpu().numpy()))
     ctx.close()
+
+
+def test_sis_reweighted_samples_give_energy_of_phi():
+    """The whole workflow on an enumerable lattice (2x4, exact contraction): 8192 independent
+    chains of the GPU sampler (|Psi|^2, one sample each after 24 sweeps) and their log-weights
+    from vp_eval_sis.  Tensors: a reversal-symmetric PEPS (T_k[1] = T_k[0] with bond index 0 <-> 1
+    on every leg of dimension 2, so Psi(Sbar) = Psi(S)) plus 0.1 times a random one, a state near
+    a symmetric one, as after an optimisation.  Checked within 5 standard errors: the mean weight
+    against <Phi|Phi>/<Psi|Psi> and sum w E_Phi / sum w against <Phi|H|Phi>/<Phi|Phi>, both from
+    the dense Phi = Psi + P Psi."""
+    import torch
+    import bruteforce as bf
+    from paper_1908_09359_amd import binding as B
+    Ly, Lx, D, Dc, J2, n = 2, 4, 2, 8, 0.3, 8192
+    print(f"sis reweighted sampling {Ly}x{Lx} D={D} {n} chains", flush=True)
+    lat = Lattice(Ly, Lx, D, Dc, J2=J2)
+    T = W.random_tensors(Ly, Lx, D, seed=31)
+    for y in range(Ly):
+        for x in range(Lx):
+            dims = lat.dims(y, x)
+            m = int(np.prod(dims))
+            o = lat.offsets[lat.site(y, x)]
+            a = T[o:o + m].reshape(dims)
+            for ax, d in enumerate(dims):
+                if d == 2:
+                    a = np.flip(a, axis=ax)
+            T[o + m:o + 2 * m] = a.reshape(-1)
+    T = T + 0.1 * W.random_tensors(Ly, Lx, D, seed=32)
+    ctx = B.Context(B.lattice(Ly, Lx, D, Dc, 1.0, J2, B.VP_FP64, n), seed=77)
+    dev = torch.device("cuda")
+    ctx.vp_set_tensors(0, torch.tensor(T, dtype=torch.float64, device=dev))
+    ctx.vp_init_chains(0, None)
+    lp = torch.empty(n, dtype=torch.float64, device=dev)
+    sg = torch.empty(n, dtype=torch.int8, device=dev)
+    el = torch.empty(n, dtype=torch.float64, device=dev)
+    lw = torch.empty(n, dtype=torch.float64, device=dev)
+    so = torch.empty((n, Ly * Lx), dtype=torch.int8, device=dev)
+    ctx.vp_sample(0, 23, 1, lp, sg, el, None, so)
+    ctx.vp_eval_sis(0, so, n, lp, sg, el, lw)
+    ctx.vp_sync()
+    e_phi, w = el.cpu().numpy(), np.exp(lw.cpu().numpy())
+    ctx.close()
+    configs = bf.sz0_configs(Ly * Lx)
+    index = {c.tobytes(): i for i, c in enumerate(configs)}
+    psi = bf.amplitudes(T, Ly, Lx, D, configs)
+    phi = psi + psi[[index[(1 - c).astype(np.int8).tobytes()] for c in configs]]
+    Hm = np.zeros((len(configs), len(configs)))
+    for k, s in enumerate(configs):
+        for i, j, J in bf.bonds(Ly, Lx, 1.0, J2):
+            if s[i] == s[j]:
+                Hm[k, k] += 0.25 * J
+            else:
+                Hm[k, k] -= 0.25 * J
+                t = s.copy()
+                t[i], t[j] = s[j], s[i]
+                Hm[index[t.tobytes()], k] += 0.5 * J
+    norm_ratio = float(phi @ phi / (psi @ psi))
+    exact_phi = float(phi @ Hm @ phi / (phi @ phi))
+    exact_psi = float(psi @ Hm @ psi / (psi @ psi))
+    w_mean, w_err = float(np.mean(w)), float(np.std(w) / np.sqrt(n))
+    est = float(np.sum(w * e_phi) / np.sum(w))
+    sigma = float(np.sqrt(np.sum(w ** 2 * (e_phi - est) ** 2)) / np.sum(w))
+    ess = float(np.sum(w) ** 2 / np.sum(w ** 2))
+    print(f"mean weight {w_mean:.5f} +- {w_err:.5f} (exact {norm_ratio:.5f}); reweighted E {est:.5f} +- "
+          f"{sigma:.5f} (exact Phi {exact_phi:.5f}, Psi {exact_psi:.5f}); effective samples {ess:.0f}",
+          flush=True)
+    assert abs(w_mean - norm_ratio) <= 5.0 * w_err
+    assert abs(est - exact_phi) <= 5.0 * sigma
