@@ -18,6 +18,7 @@ namespace vp {
 
 constexpr int EIG_NMAX = 128;
 constexpr int EIG_KMAX = 16;   // eigenvectors per inverse-iteration batch (one thread each)
+constexpr int EIG_INV_ITERS = 2;  // inverse-iteration sweeps per eigenvector (shifts accurate to the last bits)
 constexpr int EIG_PACK = EIG_NMAX * (EIG_NMAX + 1) / 2;
 // LDS the caller provides: a first block (the size of a packed matrix) that
 // holds the LU factors (3 x n x EIG_KMAX) and the kept vectors (n x EIG_KMAX).
@@ -402,7 +403,7 @@ __device__ __forceinline__ void sym_topk_eig(const double* H, int n, int k, doub
       U0[IX(nm1)] = recip(fabs(aa) < tiny ? (aa < 0.0 ? -tiny : tiny) : aa);
       U1[IX(nm1)] = 0.0;  // the last row has no superdiagonal
       double s = 1.0;     // scale of the current iterate, applied as it is read
-      for (int it = 0; it < 3; ++it) {
+      for (int it = 0; it < EIG_INV_ITERS; ++it) {
         // forward elimination; the running entry j + 1 stays in a register
         double carry = Xs[IX(0)] * s;
         double nx[4], nm[4];  // Xs[j+1], ML[j] of the next block

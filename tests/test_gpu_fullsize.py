@@ -11,8 +11,8 @@ input of the oracle's own compressions by (1 + 2^-52 xi), xi ~ N(0, 1)
 (``tests/conditioning_probe.py``), moves this configuration's E_loc by 9e-11 per
 site, its ratios by 6e-8 (relative) and log|Psi| by 4e-9; the GPU takes the kept
 subspace from eigenvectors of Gram matrices, which square the singular values
-and can amplify that sensitivity further (measured deviation: 1.6e-9 per site,
-ratios 2.5e-7).  The float64 assertions are therefore |dE|/site <= 1e-8,
+and can amplify that sensitivity further (measured deviation: 1.9e-9 per site,
+ratios 2.0e-7).  The float64 assertions are therefore |dE|/site <= 1e-8,
 log|Psi| within 1e-10 relative, ratios and log-derivatives within 1e-6
 relative, and the deviations are printed.  float32: the same probe at 2^-24
 moves the oracle's E_loc by 5.3e-3 per site and its ratios by 83%, so no float32
