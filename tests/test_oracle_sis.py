@@ -129,3 +129,13 @@ def test_spin_independent_tensors_give_phi_twice_psi():
         assert abs(o["log_abs_phi"] - (a["log_abs_psi"] + math.log(2.0))) < 1e-12
         assert abs(o["e_loc"] - a["e_loc"]) < 1e-12 * Ly * Lx
         assert abs(o["log_w"] - math.log(4.0)) < 1e-12
+
+
+def test_reweighted_mean_closed_forms():
+    v = np.array([1.0, 2.0, 4.0, 8.0])
+    # equal weights give the plain mean, whatever their common scale
+    assert abs(sis.reweighted_mean(v, np.full(4, 700.0)) - 3.75) < 1e-15
+    # a weight of zero (log w = -inf) drops its sample
+    assert abs(sis.reweighted_mean(v, np.array([0.0, 0.0, 0.0, -np.inf])) - 7.0 / 3.0) < 1e-15
+    # w = (1, 2, 3, 4): sum w v / sum w = (1 + 4 + 12 + 32) / 10
+    assert abs(sis.reweighted_mean(v, np.log([1.0, 2.0, 3.0, 4.0])) - 4.9) < 1e-14
