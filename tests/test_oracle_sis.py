@@ -14,6 +14,7 @@
   for both terms would break it).
 * Spin-independent tensors (T_k[1] = T_k[0]): Psi(Sbar) = Psi(S), so Phi = 2 Psi,
   E_Phi = E_loc and w = 4.
+* ``reweighted_mean`` against closed forms (equal weights, a zero weight, integer weights).
 """
 import math
 
