@@ -9,6 +9,7 @@ next to this file.
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -16,7 +17,11 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libvmcpeps.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["vp_kernels.hip", "vp_sr.hip", "vp_net.hip", "vp_sis.hip", "vp_api.cpp"]
+# (source, object name, extra flags): the phase kernels compile once per working type
+SOURCES = [("vp_kernels.hip", "vp_kernels_f64", ["-DVP_KERNEL_UNIT=0"]),
+           ("vp_kernels.hip", "vp_kernels_f32", ["-DVP_KERNEL_UNIT=1"]),
+           ("vp_sr.hip", "vp_sr", []), ("vp_net.hip", "vp_net", []), ("vp_sis.hip", "vp_sis", []),
+           ("vp_api.cpp", "vp_api", [])]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("VP_OFFLOAD_ARCH", "gfx950")
@@ -39,14 +44,17 @@ def _run(cmd):
 
 def build(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
-    for src in SOURCES:
-        obj = os.path.join(BUILD, src.rsplit(".", 1)[0] + ".o")
-        cmd = [HIPCC, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj] + FLAGS
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        _run(cmd)
+    objs, cmds = [], []
+    for src, name, extra in SOURCES:
+        obj = os.path.join(BUILD, name + ".o")
+        cmds.append([HIPCC, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj] + FLAGS + extra)
         objs.append(obj)
+    if verbose:
+        for cmd in cmds:
+            print(" ".join(cmd), flush=True)
+    # the translation units are independent: compile them side by side
+    with ThreadPoolExecutor(max_workers=min(len(cmds), os.cpu_count() or 1)) as pool:
+        list(pool.map(_run, cmds))
     tmp = OUT + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs
     if verbose:

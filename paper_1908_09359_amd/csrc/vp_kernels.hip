@@ -14,6 +14,10 @@
 
 #include <type_traits>
 
+#ifndef VP_KERNEL_UNIT
+#define VP_KERNEL_UNIT 0
+#endif
+
 namespace vp {
 
 namespace {
@@ -1207,6 +1211,10 @@ int sweep_queue_occupancy(const LatDev& L, bool bf16) {
   return n;
 }
 
+// The library compiles this file once per working type (VP_KERNEL_UNIT 0:
+// float64 and the type-independent launchers, 1: float32) so that the two
+// halves build side by side.
+#if VP_KERNEL_UNIT == 0
 void launch_begin_sample(const LatDev& L, hipStream_t s) {
   hipLaunchKernelGGL(k_begin_sample, dim3((L.n_chains + WG - 1) / WG), dim3(WG), 0, s, L);
 }
@@ -1227,6 +1235,7 @@ void launch_init_chains(const LatDev& L, hipStream_t s) {
 void launch_copy_spins(const LatDev& L, const int8_t* src, int n_cfg, hipStream_t s) {
   hipLaunchKernelGGL(k_copy_spins, dim3(n_cfg), dim3(64), 0, s, L, src, n_cfg);
 }
+#endif
 template <typename T>
 void launch_gradient(const int64_t* offs, const int64_t* coff, const int32_t* sz, int N, int64_t Np,
                      const double* e, const T* dl, const int8_t* spins, int64_t ns, double* grad, double* emean,
@@ -1237,11 +1246,13 @@ void launch_gradient(const int64_t* offs, const int64_t* coff, const int32_t* sz
   hipLaunchKernelGGL(k_gradient<T>, dim3((unsigned)((nh + WG - 1) / WG)), dim3(WG), 0, s, offs, coff, sz, N, e, dl,
                      spins, ns, nh, (const double*)emean, grad);
 }
+#if VP_KERNEL_UNIT == 0
 void launch_sign_sgd(double* T, const double* g, int64_t Np, double step_len, uint64_t seed, int lat_id,
                      uint64_t step, hipStream_t s) {
   int blocks = (int)std::min<int64_t>((Np + WG - 1) / WG, 65536);
   hipLaunchKernelGGL(k_sign_sgd, dim3(blocks), dim3(WG), 0, s, T, g, Np, step_len, seed, lat_id, step);
 }
+#endif
 
 #define VP_INSTANTIATE(T)                                                                            \
   template void launch_prepare_tensors<T>(const LatDev&, const double*, T*, const int64_t*, hipStream_t); \
@@ -1261,7 +1272,10 @@ void launch_sign_sgd(double* T, const double* g, int64_t Np, double step_len, ui
                                    const double*, const T*, const int8_t*, int64_t, double*, double*, \
                                    double*, hipStream_t);
 
+#if VP_KERNEL_UNIT == 0
 VP_INSTANTIATE(double)
+#else
 VP_INSTANTIATE(float)
+#endif
 
 }  // namespace vp
