@@ -53,7 +53,11 @@
  * Memory: every pointer argument named *_dev is a device pointer owned by the
  *   caller (for example a torch tensor's data_ptr on the same device);
  *   pointers named *_host are host pointers.  The library owns only its
- *   internal workspace, allocated by vp_create and freed by vp_destroy.
+ *   internal workspace: what the sweeps and vp_eval_sis need is allocated by
+ *   vp_create; the workspaces of vp_sr_update, vp_optimize and the proposal
+ *   network calls depend on their arguments, are allocated by the first call
+ *   that needs them and kept for later calls (replaced by a larger one when a
+ *   call needs more).  vp_destroy frees all of it.
  * Streams: work is enqueued on the hipStream_t given to vp_create (NULL = the
  *   null stream).  Calls return once the work is enqueued unless stated
  *   otherwise; vp_sync waits and reports device-side error flags.
@@ -213,7 +217,7 @@ vp_status vp_eval(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev, int32_t n_c
                   double* log_abs_psi_dev, int8_t* sign_dev, double* e_loc_dev,
                   void* dlnpsi_dev, double* ratios_dev);
 
-/* Spin-inversion symmetrisation (Sec. III, symmetrised wave function
+/* Spin-inversion symmetrisation (Sec. II.B, symmetrised wave function
  * Phi(S) = Psi(S) + Psi(Sbar), Sbar = S with every spin reversed; observables
  * are taken with the weight |Phi(S)|^2).  For the configurations spins_dev
  * [n_cfg][N] (1 <= n_cfg <= n_chains, S^z_tot = 0) evaluates S and Sbar as
@@ -224,9 +228,9 @@ vp_status vp_eval(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev, int32_t n_c
  * log(|Phi(S)|^2 / |Psi(S)|^2), the weight that turns samples of |Psi|^2 (from
  * vp_sample) into samples of |Phi|^2: <O>_Phi = sum w O / sum w.  Where
  * Psi(Sbar) = -Psi(S) exactly, log|Phi| and log w are -inf, the sign 0 and
- * E_Phi 0.  Allocates and frees a workspace of n_cfg (N + 17) bytes; waits for
- * the stream; same preconditions and errors as vp_eval; invalidates the
- * sampler's state. */
+ * E_Phi 0.  Uses the n_chains (N + 17) bytes of scratch reserved by vp_create;
+ * waits for the stream; same preconditions and errors as vp_eval; invalidates
+ * the sampler's state. */
 vp_status vp_eval_sis(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev, int32_t n_cfg,
                       double* log_abs_phi_dev, int8_t* sign_phi_dev, double* e_loc_phi_dev, double* log_w_dev);
 
@@ -279,8 +283,8 @@ vp_status vp_proposal_loss_grad(vp_ctx* ctx, int32_t lat, const int8_t* spins_de
 /* Adam (beta1 0.9, beta2 0.999, eps 1e-8, step size lr) on that loss over
  * epochs passes of shuffled minibatches of `batch` configurations (whole
  * batches only; the shuffle is seeded by seed).  loss_dev [epochs] float64
- * (mean minibatch loss per epoch) may be NULL.  Allocates its workspace for
- * the call and waits. */
+ * (mean minibatch loss per epoch) may be NULL.  Keeps its workspace (sized by
+ * the batch) for later calls; waits. */
 vp_status vp_proposal_train(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev, const double* ratios_dev,
                             int64_t n, int32_t epochs, int32_t batch, double lr, uint64_t seed,
                             double* loss_dev);
@@ -308,8 +312,8 @@ vp_status vp_gradient(vp_ctx* ctx, int32_t lat, const double* e_loc_dev, const v
  * the full-layout log-derivatives and g the Eq. (5) gradient, solved in float64
  * by a blocked Cholesky factorisation on the device; then T <- T - lr * delta.
  * delta_dev [Np] may be NULL.  Needs Np <= 32768 and n_samples * Np < 2^31;
- * allocates (8 Np^2 + 8 n_samples Np) bytes of workspace for the call and
- * waits for completion.  VP_ERR_NONFINITE if S + shift I is not numerically
+ * needs (8 Np^2 + 8 n_samples Np) bytes of workspace, kept by the lattice for
+ * later calls, and waits for completion.  VP_ERR_NONFINITE if S + shift I is not numerically
  * positive definite. */
 vp_status vp_sr_update(vp_ctx* ctx, int32_t lat, const double* e_loc_dev, const void* dlnpsi_dev,
                        const int8_t* spins_dev, int64_t n_samples, double shift, double lr,
@@ -325,8 +329,11 @@ vp_status vp_sign_sgd_update(vp_ctx* ctx, int32_t lat, const double* grad_dev, d
  * step length delta_host[i] and random counter step0 + i (Sec. II.B uses
  * 0.005, 0.002, 0.001 and 0.0005 in successive stages).  e_mean_host
  * [n_steps] (may be NULL) receives each step's mean E_loc, measured before
- * its update.  Allocates the samples of one step for the call and waits for
- * completion. */
+ * its update.  Keeps the buffers of one step's samples for later calls and
+ * waits for completion.  Stops with VP_ERR_ZERO_AMPLITUDE or VP_ERR_NONFINITE,
+ * before that step's gradient and update, when a chain met a zero or
+ * non-finite amplitude (its rows were not measured); the tensors then hold the
+ * previous step's update. */
 vp_status vp_optimize(vp_ctx* ctx, int32_t lat, int32_t n_steps, int32_t n_burn, int32_t n_meas,
                       const double* delta_host, uint64_t step0, double* e_mean_host);
 

@@ -50,6 +50,18 @@ struct Lattice {
   int32_t sampler = VP_SAMPLER_PAIR_SEQ;
   int32_t schedule = VP_SCHED_PHASES;
   int64_t sweeps = 0;           // sweeps since vp_init_chains (every chain's counter)
+  // spin-inversion scratch, reserved at vp_create: reversed configurations
+  // [n_chains][N], then log|Psi(Sbar)|, E_loc(Sbar) [n_chains] and sign(Sbar)
+  char* d_sis = nullptr;
+  // workspaces whose size depends on call arguments (SR, optimisation loop,
+  // proposal network): allocated on first use, grown when a later call needs
+  // more, released by vp_destroy
+  struct Buf {
+    void* p = nullptr;
+    size_t cap = 0;
+  };
+  Buf sr_work, sr_flag, opt_lp, opt_el, opt_grad, opt_em, opt_sg, opt_so, opt_dl;
+  Buf nw_work, nw_part, nw_cnt, nw_scal, nw_grad, nw_sb, nw_rb, nw_idx;
   LatDev dev{};
   bool tensors_ready = false;
   bool chains_ready = false;
@@ -103,6 +115,29 @@ vp_status fail(vp_ctx* ctx, vp_status st, const char* fmt, ...) {
     hipError_t e_ = (expr);                                                                 \
     if (e_ != hipSuccess) return fail((ctx), VP_ERR_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
+
+// Makes b hold at least `bytes`; a larger buffer replaces it once the stream has
+// finished with the old one.
+bool grow(hipStream_t s, Lattice::Buf& b, size_t bytes) {
+  if (b.p && b.cap >= bytes) return true;
+  if (b.p) {
+    hipStreamSynchronize(s);
+    hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+  }
+  if (hipMalloc(&b.p, std::max<size_t>(bytes, 256)) != hipSuccess) {
+    b.p = nullptr;
+    return false;
+  }
+  b.cap = std::max<size_t>(bytes, 256);
+  return true;
+}
+
+size_t sis_bytes(const vp_lattice& p) {
+  const size_t nb = (size_t)p.n_chains * p.Ly * p.Lx;
+  return (nb + 255) / 256 * 256 + 2 * sizeof(double) * p.n_chains + p.n_chains;
+}
 
 void site_dims(const vp_lattice& p, int y, int x, int32_t out[4]) {
   out[0] = x > 0 ? p.D : 1;
@@ -484,7 +519,8 @@ vp_status eval_configs(vp_ctx* ctx, Lattice* L, const int8_t* spins_dev, int32_t
   return VP_OK;
 }
 
-// Workspace of one batched network call of n configurations.
+// Workspace of one batched network call of n configurations, in the lattice's
+// grow-only buffers.
 struct NetWork {
   float* work = nullptr;
   double* part = nullptr;
@@ -494,21 +530,17 @@ struct NetWork {
   int8_t* sb = nullptr;
   double* rb = nullptr;
   int32_t* idx = nullptr;
-  bool alloc(const Lattice& L, int n) {
+  bool alloc(Lattice& L, int n, hipStream_t s) {
     const int H = L.p.Ly, W = L.p.Lx;
-    return hipMalloc((void**)&work, sizeof(float) * net_work_floats(n, H, W)) == hipSuccess &&
-           hipMalloc((void**)&part, sizeof(double) * n) == hipSuccess &&
-           hipMalloc((void**)&cnt, sizeof(int) * n) == hipSuccess &&
-           hipMalloc((void**)&scal, sizeof(double) * 4) == hipSuccess &&
-           hipMalloc((void**)&grad, sizeof(float) * NET_NPARAM) == hipSuccess &&
-           hipMalloc((void**)&sb, (size_t)n * H * W) == hipSuccess &&
-           hipMalloc((void**)&rb, sizeof(double) * n * (H - 1) * (W - 1)) == hipSuccess &&
-           hipMalloc((void**)&idx, sizeof(int32_t) * n) == hipSuccess;
-  }
-  ~NetWork() {
-    void* p[] = {work, part, cnt, scal, grad, sb, rb, idx};
-    for (void* q : p)
-      if (q) hipFree(q);
+    if (!(grow(s, L.nw_work, sizeof(float) * net_work_floats(n, H, W)) && grow(s, L.nw_part, sizeof(double) * n) &&
+          grow(s, L.nw_cnt, sizeof(int) * n) && grow(s, L.nw_scal, sizeof(double) * 4) &&
+          grow(s, L.nw_grad, sizeof(float) * NET_NPARAM) && grow(s, L.nw_sb, (size_t)n * H * W) &&
+          grow(s, L.nw_rb, sizeof(double) * n * (H - 1) * (W - 1)) && grow(s, L.nw_idx, sizeof(int32_t) * n)))
+      return false;
+    work = (float*)L.nw_work.p; part = (double*)L.nw_part.p; cnt = (int*)L.nw_cnt.p;
+    scal = (double*)L.nw_scal.p; grad = (float*)L.nw_grad.p; sb = (int8_t*)L.nw_sb.p;
+    rb = (double*)L.nw_rb.p; idx = (int32_t*)L.nw_idx.p;
+    return true;
   }
 };
 
@@ -584,7 +616,8 @@ vp_status vp_create(const vp_lattice* lats, int32_t n_lats, uint64_t seed, void*
               alloc((void**)&L.d_scratch, 64 * sizeof(double)) &&
               alloc((void**)&L.d_net, sizeof(float) * NET_NPARAM) &&
               alloc((void**)&L.d_net64, sizeof(double) * NET_NPARAM) &&
-              alloc((void**)&L.d_adam, 2 * sizeof(float) * NET_NPARAM);
+              alloc((void**)&L.d_adam, 2 * sizeof(float) * NET_NPARAM) &&
+              alloc((void**)&L.d_sis, sis_bytes(p));
     if (!ok) {
       vp_destroy(ctx);
       return fail(nullptr, VP_ERR_OOM, "device allocation failed for lattice %d", i);
@@ -630,9 +663,15 @@ vp_status vp_destroy(vp_ctx* ctx) {
   for (hipEvent_t e : ctx->ev) hipEventDestroy(e);
   for (auto& L : ctx->lats) {
     void* ptrs[] = {L.T, L.Tw, L.ws, L.cws, L.iws, L.dws, L.meta, L.spins, L.d_kU, L.d_kD,
-                    L.d_dims, L.d_sizes, L.d_offs, L.d_coff, L.d_scratch, L.d_net, L.d_net64, L.d_adam};
+                    L.d_dims, L.d_sizes, L.d_offs, L.d_coff, L.d_scratch, L.d_net, L.d_net64, L.d_adam,
+                    L.d_sis};
     for (void* q : ptrs)
       if (q) hipFree(q);
+    Lattice::Buf* bufs[] = {&L.sr_work, &L.sr_flag, &L.opt_lp, &L.opt_el, &L.opt_grad, &L.opt_em, &L.opt_sg,
+                            &L.opt_so, &L.opt_dl, &L.nw_work, &L.nw_part, &L.nw_cnt, &L.nw_scal, &L.nw_grad,
+                            &L.nw_sb, &L.nw_rb, &L.nw_idx};
+    for (Lattice::Buf* b : bufs)
+      if (b->p) hipFree(b->p);
   }
   void* qp[] = {ctx->q_lats, ctx->q_outs, ctx->q_items, ctx->q_next};
   for (void* q : qp)
@@ -931,11 +970,11 @@ vp_status vp_eval_sis(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev, int32_t
   if (n_cfg < 1 || n_cfg > L->p.n_chains) return fail(ctx, VP_ERR_ARG, "need 1 <= n_cfg <= n_chains");
   hipStream_t s = ctx->stream;
   const size_t nb = (size_t)n_cfg * L->N;
-  // workspace: reversed configurations, then log|Psi(Sbar)|, E_loc(Sbar), sign(Sbar)
-  char* work = nullptr;
+  // the scratch reserved at vp_create (sized for n_chains configurations):
+  // reversed configurations, then log|Psi(Sbar)|, E_loc(Sbar), sign(Sbar)
+  char* work = L->d_sis;
   const size_t off_l = (nb + 255) / 256 * 256, off_e = off_l + sizeof(double) * n_cfg,
                off_s = off_e + sizeof(double) * n_cfg;
-  if (hipMalloc((void**)&work, off_s + n_cfg) != hipSuccess) return fail(ctx, VP_ERR_OOM, "symmetrisation workspace");
   int8_t* rev = (int8_t*)work;
   double* lr = (double*)(work + off_l);
   double* er = (double*)(work + off_e);
@@ -952,7 +991,6 @@ vp_status vp_eval_sis(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev, int32_t
       st = fail(ctx, VP_ERR_DEVICE, "symmetrisation kernel failed");
   }
   hipStreamSynchronize(s);
-  hipFree(work);
   return st;
 }
 
@@ -1065,7 +1103,7 @@ vp_status vp_proposal_forward(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev,
   if (!L->net_ready) return fail(ctx, VP_ERR_ARG, "the proposal network has no weights yet");
   if (n < 1) return fail(ctx, VP_ERR_ARG, "n must be >= 1");
   NetWork w;
-  if (!w.alloc(*L, n)) return fail(ctx, VP_ERR_OOM, "proposal workspace allocation failed");
+  if (!w.alloc(*L, n, ctx->stream)) return fail(ctx, VP_ERR_OOM, "proposal workspace allocation failed");
   net_forward(L->d_net, spins_dev, n, L->p.Ly, L->p.Lx, w.work, logits_dev, ctx->stream);
   HIP_TRY(ctx, hipGetLastError());
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
@@ -1081,7 +1119,7 @@ vp_status vp_proposal_loss_grad(vp_ctx* ctx, int32_t lat, const int8_t* spins_de
   if (n < 1) return fail(ctx, VP_ERR_ARG, "n must be >= 1");
   if (L->p.Ly < 2 || L->p.Lx < 2) return fail(ctx, VP_ERR_SHAPE, "plaquettes need Ly, Lx >= 2");
   NetWork w;
-  if (!w.alloc(*L, n)) return fail(ctx, VP_ERR_OOM, "proposal workspace allocation failed");
+  if (!w.alloc(*L, n, ctx->stream)) return fail(ctx, VP_ERR_OOM, "proposal workspace allocation failed");
   hipStream_t s = ctx->stream;
   net_loss_grad(L->d_net, spins_dev, ratios_dev, n, L->p.Ly, L->p.Lx, w.work, w.part, w.cnt, w.scal, grad_dev, s);
   HIP_TRY(ctx, hipMemcpyAsync(loss_dev, w.scal, sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -1101,7 +1139,7 @@ vp_status vp_proposal_train(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev, c
   if (L->p.Ly < 2 || L->p.Lx < 2) return fail(ctx, VP_ERR_SHAPE, "plaquettes need Ly, Lx >= 2");
   const int nb = (int)std::min<int64_t>(batch, n);
   NetWork w;
-  if (!w.alloc(*L, nb)) return fail(ctx, VP_ERR_OOM, "proposal workspace allocation failed");
+  if (!w.alloc(*L, nb, ctx->stream)) return fail(ctx, VP_ERR_OOM, "proposal workspace allocation failed");
   hipStream_t s = ctx->stream;
   const int H = L->p.Ly, W = L->p.Lx;
   std::vector<int32_t> perm(n);
@@ -1164,13 +1202,13 @@ vp_status vp_sr_update(vp_ctx* ctx, int32_t lat, const double* e_loc_dev, const 
   if (!(shift >= 0.0)) return fail(ctx, VP_ERR_ARG, "shift must be >= 0");
   if (L->Np > 32768) return fail(ctx, VP_ERR_SHAPE, "the dense S matrix needs Np <= 32768 (Np = %lld)", (long long)L->Np);
   if (n_samples * L->Np >= (int64_t)1 << 31) return fail(ctx, VP_ERR_SHAPE, "n_samples * Np must stay below 2^31");
-  // the factorisation workspace is allocated for the call and released afterwards
-  double* work = nullptr;
-  int* flag = nullptr;
+  // the factorisation workspace: kept by the lattice from the first call on
   const int64_t nd = sr_work_doubles(L->Np, n_samples);
-  if (hipMalloc((void**)&work, sizeof(double) * nd) != hipSuccess) return fail(ctx, VP_ERR_OOM, "SR workspace");
-  if (hipMalloc((void**)&flag, sizeof(int)) != hipSuccess) { hipFree(work); return fail(ctx, VP_ERR_OOM, "SR flag"); }
-  hipMemsetAsync(flag, 0, sizeof(int), ctx->stream);
+  if (!grow(ctx->stream, L->sr_work, sizeof(double) * nd) || !grow(ctx->stream, L->sr_flag, sizeof(int)))
+    return fail(ctx, VP_ERR_OOM, "SR workspace");
+  double* work = (double*)L->sr_work.p;
+  int* flag = (int*)L->sr_flag.p;
+  HIP_TRY(ctx, hipMemsetAsync(flag, 0, sizeof(int), ctx->stream));
   int rc = works_f64(L->p.prec)
                ? launch_sr<double>(L->d_offs, L->d_coff, L->d_sizes, L->N, L->Np, e_loc_dev, (const double*)dlnpsi_dev,
                                    spins_dev, n_samples, shift, lr, L->T, delta_dev, work, flag, ctx->stream)
@@ -1179,8 +1217,6 @@ vp_status vp_sr_update(vp_ctx* ctx, int32_t lat, const double* e_loc_dev, const 
   int hflag = 0;
   hipError_t e1 = hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream);
   hipError_t e2 = hipStreamSynchronize(ctx->stream);
-  hipFree(work);
-  hipFree(flag);
   if (rc != 0 || e1 != hipSuccess || e2 != hipSuccess) return fail(ctx, VP_ERR_DEVICE, "SR kernels failed");
   if (hflag) return fail(ctx, VP_ERR_NONFINITE, "S + shift I is not numerically positive definite");
   return stage_tensors(ctx, *L);
@@ -1202,37 +1238,35 @@ vp_status vp_optimize(vp_ctx* ctx, int32_t lat, int32_t n_steps, int32_t n_burn,
     return fail(ctx, VP_ERR_ARG, "need n_steps >= 0, n_burn >= 0, n_meas >= 1");
   const int64_t n = (int64_t)L->p.n_chains * n_meas;
   const size_t wsz = type_size(L->p.prec);
-  // the samples of one step, the gradient and the mean energy: allocated for the call
-  double *lp = nullptr, *el = nullptr, *grad = nullptr, *em = nullptr;
-  int8_t *sg = nullptr, *so = nullptr;
-  void* dl = nullptr;
-  auto release = [&]() {
-    void* ps[] = {lp, el, grad, em, sg, so, dl};
-    for (void* q : ps)
-      if (q) hipFree(q);
-  };
-  if (hipMalloc((void**)&lp, sizeof(double) * n) != hipSuccess ||
-      hipMalloc((void**)&el, sizeof(double) * n) != hipSuccess ||
-      hipMalloc((void**)&grad, sizeof(double) * L->Np) != hipSuccess ||
-      hipMalloc((void**)&em, sizeof(double)) != hipSuccess || hipMalloc((void**)&sg, n) != hipSuccess ||
-      hipMalloc((void**)&so, n * L->N) != hipSuccess || hipMalloc(&dl, wsz * n * (L->Np / 2)) != hipSuccess) {
-    release();
+  // the samples of one step, the gradient and the mean energy: kept by the lattice
+  hipStream_t s = ctx->stream;
+  if (!grow(s, L->opt_lp, sizeof(double) * n) || !grow(s, L->opt_el, sizeof(double) * n) ||
+      !grow(s, L->opt_grad, sizeof(double) * L->Np) || !grow(s, L->opt_em, sizeof(double)) ||
+      !grow(s, L->opt_sg, n) || !grow(s, L->opt_so, n * L->N) || !grow(s, L->opt_dl, wsz * n * (L->Np / 2)))
     return fail(ctx, VP_ERR_OOM, "optimisation buffers");
-  }
+  double* lp = (double*)L->opt_lp.p;
+  double* el = (double*)L->opt_el.p;
+  double* grad = (double*)L->opt_grad.p;
+  double* em = (double*)L->opt_em.p;
+  int8_t* sg = (int8_t*)L->opt_sg.p;
+  int8_t* so = (int8_t*)L->opt_so.p;
+  void* dl = L->opt_dl.p;
   vp_status st = VP_OK;
   for (int i = 0; i < n_steps && st == VP_OK; ++i) {
     // Algorithm 1: sample, Eq. (5) gradient, Eq. (10) update
     st = vp_sample(ctx, lat, n_burn, n_meas, lp, sg, el, dl, so, nullptr);
+    // a chain that met a zero or non-finite amplitude left its rows unmeasured:
+    // stop before they enter the gradient and the tensors
+    if (st == VP_OK) st = check_flags(ctx, *L);
     if (st == VP_OK) st = vp_gradient(ctx, lat, el, dl, so, n, grad, em);
     if (st == VP_OK && e_mean_host) {
-      if (hipMemcpyAsync(e_mean_host + i, em, sizeof(double), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
-          hipStreamSynchronize(ctx->stream) != hipSuccess)
+      if (hipMemcpyAsync(e_mean_host + i, em, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
         st = fail(ctx, VP_ERR_DEVICE, "reading the step energy failed");
     }
     if (st == VP_OK) st = vp_sign_sgd_update(ctx, lat, grad, delta_host[i], step0 + (uint64_t)i);
   }
-  hipStreamSynchronize(ctx->stream);
-  release();
+  hipStreamSynchronize(s);
   return st;
 }
 

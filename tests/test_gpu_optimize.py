@@ -73,3 +73,32 @@ def test_optimisation_lowers_the_energy():
     assert e[-10:].mean() < e[:3].mean() - 0.1
     # D=2 reaches about -0.556 here (3% above the exact -0.5743)
     assert e[-10:].mean() < -0.53
+
+
+def test_zero_amplitude_stops_before_the_update():
+    """A chain whose configuration has Psi = 0 is flagged by the sampler and left
+    unmeasured; vp_optimize must report it before its gradient or update can
+    touch the tensors."""
+    import torch
+    B = _B()
+    Ly, Lx, D, Dc = 4, 4, 2, 4
+    print("optimize with a zero-amplitude chain 4x4 D=2 Dc=4", flush=True)
+    T = W.random_tensors(Ly, Lx, D, seed=83)
+    n0 = 1 * 1 * D * D          # site (0, 0): dims (l, u, r, d) = (1, 1, D, D)
+    T[n0:2 * n0] = 0.0          # T_0[s = 1] = 0: every configuration with s_0 = 1 has Psi = 0
+    lat = olat.Lattice(Ly, Lx, D, Dc)
+    good = olat.neel(lat)       # s_0 = 0
+    bad = 1 - good              # s_0 = 1
+    assert good[0] == 0 and bad[0] == 1
+    ctx = B.Context(B.lattice(Ly, Lx, D, Dc, 1.0, 0.0, B.VP_FP64, 2), seed=7)
+    dev = torch.device("cuda")
+    ctx.vp_set_tensors(0, torch.tensor(T, dtype=torch.float64, device=dev))
+    ctx.vp_init_chains(0, torch.tensor(np.stack([good, bad]), dtype=torch.int8, device=dev))
+    with pytest.raises(B.VPError) as ei:
+        ctx.vp_optimize(0, [0.01, 0.01], 0, 2)
+    assert ei.value.status == B.VP_ERR_ZERO_AMPLITUDE
+    Tg = torch.empty(len(T), dtype=torch.float64, device=dev)
+    ctx.vp_get_tensors(0, Tg)
+    torch.cuda.synchronize()
+    assert np.array_equal(Tg.cpu().numpy(), T)
+    ctx.close()
