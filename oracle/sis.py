@@ -1,6 +1,6 @@
 """Spin-inversion symmetrised amplitude of the oracle (test infrastructure only).
 
-Sec. III (symmetrised wave function): after the optimisation the amplitude
+Sec. II.B (symmetrised wave function): after the optimisation the amplitude
 Psi(S) is replaced by Phi(S) = Psi(S) + Psi(Sbar), where Sbar reverses every
 spin of S, and observables are taken with the weight |Phi(S)|^2.
 

@@ -1,4 +1,4 @@
-// Spin-inversion symmetrised amplitude (Sec. III, symmetrised wave function):
+// Spin-inversion symmetrised amplitude (Sec. II.B, symmetrised wave function):
 // Phi(S) = Psi(S) + Psi(Sbar), Sbar = S with every spin reversed.
 //
 // The evaluation of S and of Sbar each give (sign, log|Psi|, E_loc).  Since the

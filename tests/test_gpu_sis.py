@@ -1,4 +1,4 @@
-"""GPU parity of the spin-inversion symmetrised evaluation (Sec. III,
+"""GPU parity of the spin-inversion symmetrised evaluation (Sec. II.B,
 Phi(S) = Psi(S) + Psi(Sbar)) through the C ABI (``vp_eval_sis``).
 
 * Against the oracle (``oracle.sis``, which forms every Phi(S')/Phi(S) from the

@@ -1,5 +1,5 @@
 """Pins of the oracle's spin-inversion symmetrised amplitude, Phi(S) = Psi(S) + Psi(Sbar)
-(Sec. III, symmetrised wave function; observables weighted by |Phi(S)|^2).
+(Sec. II.B, symmetrised wave function; observables weighted by |Phi(S)|^2).
 
 * Brute force: with exact contractions (Dc at the exact rank), E_Phi(S) equals
   sum_S' <S|H|S'> Phi(S')/Phi(S) written out with dense amplitudes of S' and of
