@@ -91,3 +91,40 @@ def test_neel_and_shuffle():
         seen.add(sh.tobytes())
         assert np.array_equal(sh, neel_shuffled(lat, 9359, 0, chain))
     assert len(seen) == 20
+
+
+def _arrangement_counts(lat, n_chains, seed=9359):
+    counts = {}
+    for chain in range(n_chains):
+        k = neel_shuffled(lat, seed, 0, chain).tobytes()
+        counts[k] = counts.get(k, 0) + 1
+    return counts
+
+
+def _chi2_uniform_pvalue(counts, n_cells, n):
+    from scipy import stats
+    obs = np.zeros(n_cells)
+    obs[:len(counts)] = list(counts.values())
+    return stats.chisquare(obs, np.full(n_cells, n / n_cells)).pvalue
+
+
+def test_neel_shuffle_is_uniform_over_the_sector():
+    """A uniform permutation of the Neel list gives every S^z = 0 arrangement with
+    probability 1 / C(N, N/2).  On a 2x3 lattice (20 arrangements) the shuffled
+    starts of 6000 chains pass a chi-square test of uniformity, while the same
+    shuffle with a planted Sattolo index range (j < i, which draws only N-cycles
+    and can never return the Neel arrangement itself) fails it."""
+    from math import comb
+    lat = Lattice(2, 3, 2, 4)
+    n, cells = 6000, comb(6, 3)
+    counts = _arrangement_counts(lat, n)
+    assert len(counts) == cells
+    assert _chi2_uniform_pvalue(counts, cells, n) > 1e-3
+    exact = philox.bounded_index
+    philox.bounded_index = lambda word, m: exact(word, m - 1)  # j in [0, i): Sattolo's algorithm
+    try:
+        planted = _arrangement_counts(lat, n)
+    finally:
+        philox.bounded_index = exact
+    assert neel(lat).tobytes() not in planted
+    assert _chi2_uniform_pvalue(planted, cells, n) < 1e-6
