@@ -4,8 +4,9 @@
 // Van Loan, Sec. 8.3.1) with the matrix in registers, eigenvalues of the
 // tridiagonal matrix by Sturm-count multisection (16 probes per eigenvalue and
 // step), eigenvectors of the tridiagonal matrix by inverse iteration with
-// partial-pivoting LU (Wilkinson), classical Gram-Schmidt (twice) among the
-// kept vectors, and back-transformation by the stored reflectors.
+// partial-pivoting LU (Wilkinson), classical Gram-Schmidt (twice, each vector
+// normalised as soon as it is orthogonalised) among the kept vectors, and
+// back-transformation by the stored reflectors.
 //
 // Global and LDS data are addressed through address-space-qualified pointers
 // wherever the compiler cannot infer the space: a generic (flat) access counts
@@ -487,11 +488,23 @@ __device__ __forceinline__ void sym_topk_eig(const double* H, int n, int k, doub
   const bool in_lds = k <= EIG_KMAX;
 
   // ---- classical Gram-Schmidt, twice, over the kept vectors in descending
-  // order, then unit norms; Vw is the LDS or the global copy of the vectors
+  // order; each vector is brought to unit norm as soon as it is orthogonalised,
+  // so that the projections of the later vectors onto it are exact projections
+  // (inverse iteration leaves the vectors scaled to max |x| = 1, not to unit
+  // norm).  Vw is the LDS or the global copy of the vectors.
   auto orthonormalise = [&](auto* Vw, int ld) {
+    auto unit = [&](int col) {
+      double nn = 0.0;
+      for (int j = tid; j < n; j += WG) nn += Vw[j * ld + col] * Vw[j * ld + col];
+      nn = wg_sum(nn);
+      const double f = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+      for (int j = tid; j < n; j += WG) Vw[j * ld + col] *= f;
+      __syncthreads();
+    };
+    unit(0);
     for (int col = 1; col < k; ++col) {
       for (int pass = 0; pass < 2; ++pass) {
-        // dots with every earlier vector: 16 lanes per earlier vector
+        // dots with every earlier (unit) vector: 16 lanes per earlier vector
         for (int s0 = 0; s0 < col; s0 += WG / 16) {
           const int sv = s0 + (tid >> 4);
           double dp = 0.0;
@@ -508,21 +521,8 @@ __device__ __forceinline__ void sym_topk_eig(const double* H, int n, int k, doub
         }
         __syncthreads();
       }
+      unit(col);
     }
-    for (int c0 = 0; c0 < k; c0 += WG / 16) {
-      const int col = c0 + (tid >> 4);
-      double nn = 0.0;
-      if (col < k)
-        for (int j = tid & 15; j < n; j += 16) nn += Vw[j * ld + col] * Vw[j * ld + col];
-      nn = row16_sum(nn);
-      if ((tid & 15) == 0 && col < k) pv[col] = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
-    }
-    __syncthreads();
-    for (int e = tid; e < n * k; e += WG) {
-      const int j = e / k, col = e - j * k;
-      Vw[j * ld + col] *= pv[col];
-    }
-    __syncthreads();
   };
   const gbl_f64* rf = (const gbl_f64*)refl;
   // entry tid of reflector i (zero outside rows i + 1 .. n - 1)
