@@ -273,6 +273,19 @@ vp_status vp_proposal_set_weights(vp_ctx* ctx, int32_t lat, const float* w_dev);
 vp_status vp_proposal_get_weights(vp_ctx* ctx, int32_t lat, float* w_dev);
 /* Logit maps of n configurations: logits_dev [n][Ly][Lx] float32.  Waits. */
 vp_status vp_proposal_forward(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev, int32_t n, float* logits_dev);
+/* vp_proposal_forward for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same kernels and the same logits, bit for bit, with the
+ * activations in a fixed 16 MiB array of device memory per GPU (looked up once
+ * per device by vp_create) instead of the lattice's workspace.  Calls no
+ * allocation routine and does not wait: the call only enqueues on the
+ * context's stream.  n * Ly * Lx * 97 floats must fit the 4 Mi floats of that
+ * array (n <= 168 at 16x16, n <= 42 at 32x32), otherwise VP_ERR_ARG and nothing
+ * is launched.  Nothing in the array needs clearing (every activation is
+ * written before it is read), but every call on one GPU shares it: calls that
+ * overlap on one GPU (other streams, other contexts, other threads) race. */
+vp_status vp_proposal_forward_noalloc(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev, int32_t n,
+                                      float* logits_dev);
 /* Training loss and its gradient on n configurations: the mean over all
  * movable plaquettes of the binary cross-entropy of pi against the acceptance
  * probability a = min(1, rho^2), rho from ratios_dev (as written by

@@ -579,6 +579,14 @@ vp_status vp_create(const vp_lattice* lats, int32_t n_lats, uint64_t seed, void*
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
     return fail(nullptr, VP_ERR_DEVICE, "no HIP device available");
+  {
+    // the allocation-free forward pass's scratch on this GPU: looked up once per device
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = net_scratch_setup(dev);
+    if (e != hipSuccess)
+      return fail(nullptr, VP_ERR_DEVICE, "static scratch lookup failed: %s", hipGetErrorString(e));
+  }
   vp_ctx* ctx = new vp_ctx;
   ctx->seed = seed;
   ctx->stream = (hipStream_t)stream;
@@ -1107,6 +1115,25 @@ vp_status vp_proposal_forward(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev,
   net_forward(L->d_net, spins_dev, n, L->p.Ly, L->p.Lx, w.work, logits_dev, ctx->stream);
   HIP_TRY(ctx, hipGetLastError());
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return VP_OK;
+}
+
+vp_status vp_proposal_forward_noalloc(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev, int32_t n,
+                                      float* logits_dev) {
+  Lattice* L = get_lat(ctx, lat);
+  if (!L || !spins_dev || !logits_dev) return fail(ctx, VP_ERR_ARG, "bad lattice index or null pointer");
+  if (!L->net_ready) return fail(ctx, VP_ERR_ARG, "the proposal network has no weights yet");
+  if (n < 1) return fail(ctx, VP_ERR_ARG, "n must be >= 1");
+  const size_t need = net_forward_floats(n, L->p.Ly, L->p.Lx);
+  if (need > NET_SCRATCH_FLOATS)
+    return fail(ctx, VP_ERR_ARG, "n = %d needs %zu floats of scratch; the static scratch holds %zu (n <= %zu here)",
+                n, need, NET_SCRATCH_FLOATS, NET_SCRATCH_FLOATS / net_forward_floats(1, L->p.Ly, L->p.Lx));
+  int dev = 0;
+  HIP_TRY(ctx, hipGetDevice(&dev));
+  float* scratch = net_scratch_ptr(dev);
+  if (!scratch) return fail(ctx, VP_ERR_DEVICE, "no static scratch on device %d (create the context there)", dev);
+  net_forward(L->d_net, spins_dev, n, L->p.Ly, L->p.Lx, scratch, logits_dev, ctx->stream);
+  HIP_TRY(ctx, hipGetLastError());
   return VP_OK;
 }
 

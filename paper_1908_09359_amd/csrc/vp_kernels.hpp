@@ -128,6 +128,14 @@ void launch_sign_sgd(double* T, const double* g, int64_t Np, double step_len, ui
 // Proposal network (batched, float32): work holds net_work_floats(n, H, W)
 // floats; part [n] doubles, cnt [n] ints, scal [2] doubles.
 size_t net_work_floats(int n, int H, int W);
+// Floats net_forward uses of its work buffer (a prefix of net_work_floats).
+size_t net_forward_floats(int n, int H, int W);
+// The static forward-pass scratch: NET_SCRATCH_FLOATS floats per GPU.
+// net_scratch_setup looks up the calling process's copy on `device` once (with
+// that device current); net_scratch_ptr returns it, or null before the setup.
+constexpr size_t NET_SCRATCH_FLOATS = size_t(4) << 20;  // 16 MiB
+hipError_t net_scratch_setup(int device);
+float* net_scratch_ptr(int device);
 void net_forward(const float* th, const int8_t* spins, int n, int H, int W, float* work, float* logits,
                  hipStream_t s);
 void net_loss_grad(const float* th, const int8_t* spins, const double* ratios, int n, int H, int W, float* work,

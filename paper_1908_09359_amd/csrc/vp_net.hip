@@ -10,8 +10,47 @@
 #include <math.h>
 
 #include <algorithm>
+#include <mutex>
 
 namespace vp {
+
+// Activation scratch of the allocation-free forward pass
+// (vp_proposal_forward_noalloc): a fixed array in device memory, one copy per
+// GPU, held until the process ends.  Host code never passes this name to a
+// kernel: on the host it is only a stand-in, and the device address of each
+// GPU's copy is looked up once (net_scratch_setup) and used from then on.
+static __device__ __align__(256) float scratch[NET_SCRATCH_FLOATS];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t net_scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  int cur = -1;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return e;
+  if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+  void* ptr = nullptr;
+  e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (cur != device) {
+    const hipError_t e2 = hipSetDevice(cur);
+    if (e == hipSuccess) e = e2;
+  }
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = static_cast<float*>(ptr);
+  return hipSuccess;
+}
+
+float* net_scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
 
 namespace {
 
@@ -193,6 +232,11 @@ __global__ void k_cast_params(const float* __restrict__ src, T* __restrict__ dst
 unsigned grid_for(int64_t total) { return (unsigned)std::min<int64_t>((total + WG - 1) / WG, 65536); }
 
 }  // namespace
+
+size_t net_forward_floats(int n, int H, int Wd) {
+  // x, a1, a2, a3: what net_forward reads and writes besides its output
+  return (size_t)n * H * Wd * (1 + 3 * NET_CH);
+}
 
 size_t net_work_floats(int n, int H, int Wd) {
   const size_t HW = (size_t)H * Wd;
