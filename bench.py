@@ -16,11 +16,16 @@ Two paths on the 16x16, D=8, Dc=16 Heisenberg workload:
     python bench.py [--steps K] [--warmup W] [--chains C] [--tau-sweeps S]
 
 Prints one JSON line whose value is the learned path's samples/s; the plain
-path is reported beside it.  With --tau-sweeps S > 0 both paths also run S
-measured sweeps to estimate tau_int of E_loc and the time each needs for the
-same standard error of E/site.  Inputs are synthetic (seeded Gaussian tensors
-of standard deviation 1/D^2, Philox-shuffled Neel starts) and resident in HBM
-before the timed region.
+path is reported beside it.  After each path's timed region (untimed): tau_int
+of its own E_loc/N and M_z^2 series, and the E/N bias of its measured
+configurations against a float64 evaluation of the same configurations; for
+the learned path also its bf16 sampling ratios and decisions against float64
+along the same sweep.  From these, the time ratio at fixed dE (dE^2 = stderr^2
++ bias^2).  With --tau-sweeps S > 0 both paths also run S further measured
+sweeps for a longer tau_int estimate.  Inputs are synthetic (seeded Gaussian
+tensors of standard deviation 1/D^2, Philox-shuffled Neel starts) and resident
+in HBM before the timed region.  The CPU baseline (the oracle, one process per
+host core) runs first, before this process touches the GPU.
 """
 import argparse
 import json
@@ -94,24 +99,40 @@ def phase_flops(Ly, Lx, D, Dc, nch, launches, anti_h=0, anti_v=0):
     return out
 
 
-def cpu_baseline(Ly, Lx, D, Dc, seed):
-    """The oracle, one chain, one sweep (sampling + measurement) of the same workload, one thread."""
+def _oracle_chain_sweep(args):
+    """One chain of the oracle: one sweep (sampling + measurement) of the workload, one thread; seconds."""
+    Ly, Lx, D, Dc, seed, chain = args
     from threadpoolctl import threadpool_limits
     from oracle import lattice as olat
     from oracle import vmc
     from paper_1908_09359_amd import workloads as W
     lat = olat.Lattice(Ly, Lx, D, Dc)
     T = W.random_tensors(Ly, Lx, D, seed=seed)
-    ch = vmc.Chain(lat, olat.neel_shuffled(lat, 9359, 0, 0), 9359, 0, 0)
+    ch = vmc.Chain(lat, olat.neel_shuffled(lat, 9359, 0, chain), 9359, 0, chain)
     with threadpool_limits(limits=1):
         Dl = vmc._lower_boundaries(T, lat, ch.spins)
         t0 = time.perf_counter()
         U, _ = vmc._top_down_pass(T, lat, ch, Dl)
         vmc._measure(T, lat, ch.spins, U)
-        dt = time.perf_counter() - t0
-    return {"value": 1.0 / dt, "unit": "samples/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 chain x 1 sweep (pair moves, sampling + measurement) of {Ly}x{Lx} D={D} Dc={Dc}, "
-                      f"float64 numpy on 1 thread, {dt:.1f} s"}
+        return time.perf_counter() - t0
+
+
+def cpu_baseline(Ly, Lx, D, Dc, seed, max_procs=16):
+    """The oracle on the host's cores: one single-threaded process per core, each
+    running one chain's sweep; samples/s = chains / the slowest chain's time."""
+    import multiprocessing as mp
+    procs = max(1, min(os.cpu_count() or 1, max_procs))
+    with mp.get_context("spawn").Pool(procs) as pool:
+        times = pool.map(_oracle_chain_sweep, [(Ly, Lx, D, Dc, seed, c) for c in range(procs)])
+    wall = max(times)
+    return {"value": procs / wall, "unit": "samples/s", "cores": procs, "kind": "oracle",
+            "per_core": 1.0 / (sum(times) / len(times)),
+            "sample": f"{procs} chains x 1 sweep (pair moves, sampling + measurement) of {Ly}x{Lx} D={D} Dc={Dc}, "
+                      f"float64 numpy, one single-threaded process per core; {wall:.1f} s for the slowest chain",
+            "paper": {"value_per_core": 0.044, "unit": "samples/s per core",
+                      "hardware": "Intel E5-2620 (500 cores), 32x32 D=8, Dc 16 sampling / 24 measurement, "
+                                  "derived from the optimisation wall time quoted in Sec. II.B (4 days, 170 steps "
+                                  "x 45000 sweeps)"}}
 
 
 class Path:
@@ -171,10 +192,11 @@ class Path:
         cnt0 = self.counts()
         # the configurations measured in each step (an output of the sweep)
         so = torch.empty((steps, self.nch, self.N), dtype=torch.int8, device=self.dev)
+        el = torch.empty((steps, self.nch), dtype=torch.float64, device=self.dev)
         self.ctx.vp_timing_enable(True)
         t0 = time.perf_counter()
         for s in range(steps):
-            self.ctx.vp_sample(0, 0, 1, self.lp, self.sg, self.el, self.dl, so[s])
+            self.ctx.vp_sample(0, 0, 1, self.lp, self.sg, el[s], self.dl, so[s])
         self.ctx.vp_sync()
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
@@ -184,12 +206,35 @@ class Path:
         g = so.view(steps, self.nch, self.Ly, self.Lx)
         anti_h = int((g[..., :, 1:] != g[..., :, :-1]).sum().item())
         anti_v = int((g[..., 1:, :] != g[..., :-1, :]).sum().item())
+        self.el.copy_(el[-1])
+        self.last_spins, self.el_series, self.spin_series = so[-1], el, so
         return {"samples_per_s": self.nch * steps / dt, "ms_per_step": dt / steps * 1e3, "ms": ms,
                 "launches": launches, "seconds": dt, "anti_h": anti_h, "anti_v": anti_v,
                 "pair_accept": float(cnt[0] / max(cnt[1], 1)),
                 "plaquette_accept": float(cnt[2] / cnt[3]) if cnt[3] else None,
                 "plaquette_proposed_per_sweep": float(cnt[3] / self.nch / steps),
-                "e_site_last_sweep": float(self.el.mean().item()) / self.N}
+                "e_site_last_sweep": float(el[-1].mean().item()) / self.N}
+
+    def series_stats(self):
+        """tau_int (Sokal window 5) and variance per sample of the timed sweeps' own series:
+        E_loc / N, and the squared staggered magnetisation M_z^2 (a function of the
+        configuration alone)."""
+        import numpy as np
+        torch = self.torch
+        x = self.el_series.t().contiguous().cpu().numpy() / self.N          # [chains][steps]
+        g = self.spin_series.view(-1, self.nch, self.Ly, self.Lx).to(torch.float64)
+        yy = torch.arange(self.Ly, device=self.dev).view(-1, 1)
+        xx = torch.arange(self.Lx, device=self.dev).view(1, -1)
+        stag = ((-1.0) ** (yy + xx)).to(torch.float64)
+        mz = ((0.5 - g) * stag).sum(dim=(2, 3)) / self.N                   # [steps][chains]
+        m2 = (mz * mz).t().contiguous().cpu().numpy()
+        out = {}
+        for name, v in (("e_site", x), ("mz2", m2)):
+            tau, mean, err = self.B.vp_stats_tau(v, 5.0)
+            out[name] = {"tau_int_mean": float(np.mean(tau)), "mean": mean, "stderr": err,
+                         "var_per_sample": float(np.mean(np.var(v, axis=1, ddof=1)))}
+        out["series_length"] = int(x.shape[1])
+        return out
 
     def tau_run(self, sweeps):
         """`sweeps` measured sweeps: tau_int of E_loc/N per chain and the tau-corrected error of E/N."""
@@ -249,6 +294,92 @@ def split_run(B, torch, Ly, Lx, D, Dc1, Dc2, nch, warmup, steps, seed=9359):
             "samples_per_s": nch * steps / dt, "ms_per_step": dt / steps * 1e3, "e_site_mean": e}
 
 
+def fp64_reference(B, torch, Ly, Lx, D, Dc, spins, e_loc, n):
+    """The first n of a path's measured configurations re-evaluated in float64 (vp_eval, untimed):
+    the bias of the path's E_loc / N against the float64 evaluation of the same configurations."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    ctx = B.Context(B.lattice(Ly, Lx, D, Dc, 1.0, 0.0, B.VP_FP64, n), seed=1)
+    ctx.vp_init_tensors(0, seed=1908, scale=0.0, perturb=0.0)  # the paths' tensors (same seed, lattice 0)
+    lp = torch.empty(n, dtype=torch.float64, device=dev)
+    sg = torch.empty(n, dtype=torch.int8, device=dev)
+    el = torch.empty(n, dtype=torch.float64, device=dev)
+    ctx.vp_eval(0, spins[:n].contiguous(), n, lp, sg, el)
+    ctx.vp_sync()
+    d = (e_loc[:n].cpu().numpy() - el.cpu().numpy()) / (Ly * Lx)
+    ctx.close()
+    return {"configs": n, "bias_e_site": float(d.mean()), "bias_stderr": float(d.std(ddof=1) / np.sqrt(n)),
+            "mean_abs_e_site": float(np.abs(d).mean()), "max_abs_e_site": float(np.abs(d).max())}
+
+
+def bf16_decisions(B, torch, Ly, Lx, D, Dc, starts, seed=4242):
+    """One traced pair sweep from the same starts in float64 and with bf16-operand sampling
+    steps, same seed: along each chain, until the first decision that differs (after which
+    the configurations differ), the bf16 ratio's relative error against the float64 ratio of
+    the same bond, and how often a decision differs."""
+    import numpy as np
+    dev = torch.device("cuda:0")
+    n = starts.shape[0]
+    nb = Ly * (Lx - 1) + (Ly - 1) * Lx
+    tr = {}
+    for prec in (B.VP_FP64, B.VP_BF16):
+        ctx = B.Context(B.lattice(Ly, Lx, D, Dc, 1.0, 0.0, prec, n), seed=seed)
+        ctx.vp_init_tensors(0, seed=1908, scale=0.0, perturb=0.0)
+        ctx.vp_init_chains(0, starts.contiguous())
+        t = torch.full((n, nb, 2), -1.0, dtype=torch.float64, device=dev)
+        ctx.vp_trace_ratios(0, t)
+        lp = torch.empty(n, dtype=torch.float64, device=dev)
+        sg = torch.empty(n, dtype=torch.int8, device=dev)
+        el = torch.empty(n, dtype=torch.float64, device=dev)
+        ctx.vp_sample(0, 0, 1, lp, sg, el)
+        ctx.vp_sync()
+        tr[prec] = t.cpu().numpy()
+        ctx.close()
+    a, b = tr[B.VP_FP64], tr[B.VP_BF16]
+    # bond k of row y: horizontal for k - y (2 Lx - 1) < Lx - 1, vertical otherwise
+    vertical = np.array([(k % (2 * Lx - 1)) >= Lx - 1 for k in range(nb)])
+    rel, vert, flips, agreed = [], [], 0, 0
+    for c in range(n):
+        for k in range(nb):
+            if a[c, k, 1] != b[c, k, 1]:
+                flips += 1
+                break
+            if a[c, k, 0] != 0.0:
+                agreed += 1
+                rel.append(abs(b[c, k, 0] - a[c, k, 0]) / abs(a[c, k, 0]))
+                vert.append(vertical[k])
+    rel, vert = np.array(rel), np.array(vert, dtype=bool)
+    rv = rel[vert] if vert.any() else rel
+    return {"chains": n, "bonds_compared": int(len(rel)), "rel_err_median": float(np.median(rel)),
+            "rel_err_p95": float(np.quantile(rel, 0.95)),
+            "vertical_bonds_compared": int(vert.sum()), "vertical_rel_err_median": float(np.median(rv)),
+            "vertical_rel_err_p95": float(np.quantile(rv, 0.95)),
+            "decisions_differing_per_proposal": flips / max(agreed + flips, 1)}
+
+
+def fixed_de(plain, learned):
+    """Time ratio plain / learned at the accuracy the plain path reached in its timed run.
+
+    Per path: stderr^2 = v 2 tau / (rate t) (v: E_loc/N variance per sample, tau: its
+    integrated autocorrelation time in sweeps), and dE^2 = stderr^2 + bias^2 with bias the
+    path's E/N bias against float64.  Target dE = the plain path's dE after its timed
+    seconds; the learned path needs t = v 2 tau / (rate (dE^2 - bias^2)) to reach it.
+    Also given: the same ratio without the bias terms, and with neither bias nor variance
+    (2 tau / rate only; both paths sample |Psi|^2 of the same tensors)."""
+    def parts(r):
+        st = r["stats"]["e_site"]
+        return st["var_per_sample"], st["tau_int_mean"], r["samples_per_s"], r["fp64_reference"]["bias_e_site"]
+    vp, tp, rp, bp = parts(plain)
+    vl, tl, rl, bl = parts(learned)
+    t_plain = plain["seconds"]
+    se2 = vp * 2 * tp / (rp * t_plain)
+    de2 = se2 + bp * bp
+    t_learned = vl * 2 * tl / (rl * (de2 - bl * bl)) if de2 > bl * bl else float("inf")
+    return {"target_dE_e_site": de2 ** 0.5, "plain_stderr": se2 ** 0.5, "plain_bias": bp, "learned_bias": bl,
+            "plain_seconds": t_plain, "learned_seconds": t_learned, "ratio": t_plain / t_learned,
+            "ratio_without_bias": (vp * tp / rp) / (vl * tl / rl), "ratio_tau_and_rate_only": (tp / rp) / (tl / rl)}
+
+
 def roofline(ms, launches, flops, fp64_phases, path):
     """The phase with the largest share of the timed sweeps among those with an algorithmic
     flop count: its flops over the timed region / its summed live launch time."""
@@ -288,6 +419,12 @@ def main():
               "(chains shard across GPUs with no communication inside a sweep)", file=sys.stderr)
         sys.exit(2)
 
+    # the oracle's processes start before anything in this process touches the GPU
+    cpu = None
+    if not args.no_cpu_baseline and not args.copy_probe:
+        cpu = cpu_baseline(args.L, args.L, args.D, args.Dc, seed=1908)
+        print(f"cpu baseline: {cpu['value']:.3f} samples/s on {cpu['cores']} cores", file=sys.stderr, flush=True)
+
     import torch
     if args.copy_probe:
         x = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")  # 1 GiB
@@ -308,6 +445,10 @@ def main():
         print(f"plain: {r['samples_per_s']:.1f} samples/s", file=sys.stderr, flush=True)
         fl = phase_flops(Ly, Lx, D, Dc, nch, r["launches"], r["anti_h"], r["anti_v"])
         r["roofline"] = roofline(r["ms"], r["launches"], fl, ("compress_up", "compress_down"), "plain")
+        r["stats"] = p.series_stats()
+        r["fp64_reference"] = fp64_reference(B, torch, Ly, Lx, D, Dc, p.last_spins, p.el, nch)
+        print(f"plain: E/N bias against float64 {r['fp64_reference']['bias_e_site']:.3e} "
+              f"(mean |dE|/N {r['fp64_reference']['mean_abs_e_site']:.3e})", file=sys.stderr, flush=True)
         if args.tau_sweeps:
             r["tau"] = p.tau_run(args.tau_sweeps)
         p.close()
@@ -324,6 +465,11 @@ def main():
         fl = phase_flops(Ly, Lx, D, Dc, nch, r["launches"], r["anti_h"], r["anti_v"])
         r["roofline"] = roofline(r["ms"], r["launches"], fl, ("compress_up", "compress_down", "measure3", "measure4"),
                                  "learned")
+        r["stats"] = p.series_stats()
+        r["fp64_reference"] = fp64_reference(B, torch, Ly, Lx, D, Dc, p.last_spins, p.el, nch)
+        r["bf16_sampling"] = bf16_decisions(B, torch, Ly, Lx, D, Dc, p.last_spins[:min(64, nch)])
+        print(f"learned: bf16 ratios rel err median {r['bf16_sampling']['vertical_rel_err_median']:.3e}, decisions differing "
+              f"{r['bf16_sampling']['decisions_differing_per_proposal']:.4f}", file=sys.stderr, flush=True)
         if args.tau_sweeps:
             r["tau"] = p.tau_run(args.tau_sweeps)
         p.close()
@@ -349,8 +495,15 @@ def main():
         out[name] = {k: v for k, v in r.items() if k not in ("ms", "launches", "roofline", "anti_h", "anti_v")}
         out[name]["phase_ms_per_step"] = {k: v / args.steps for k, v in r["ms"].items()}
         out[name]["dominant_kernel"] = r["roofline"]
+    if "plain" in res:
+        out["plain_bias_e_site"] = res["plain"]["fp64_reference"]["bias_e_site"]
+    if "learned" in res:
+        # median relative error of the bf16-operand ratios (the 2-row steps: vertical bonds)
+        out["bf16_ratio_err"] = res["learned"]["bf16_sampling"]["vertical_rel_err_median"]
     if "plain" in res and "learned" in res:
         out["learned_over_plain_raw"] = res["learned"]["samples_per_s"] / res["plain"]["samples_per_s"]
+        out["fixed_dE"] = fixed_de(res["plain"], res["learned"])
+        out["learned_over_plain_at_fixed_dE"] = out["fixed_dE"]["ratio"]
         if args.tau_sweeps:
             # time to a fixed standard error dE of E/site ~ var * 2 tau / (dE^2 * rate).  Both paths
             # sample |Psi|^2 of the same tensors, so var is the same in expectation; its sample
@@ -358,11 +511,11 @@ def main():
             # the ratio, which keeps tau_int and the rate only.
             def cost(t):
                 return 2.0 * t["tau_int_mean"] / t["samples_per_s"]
-            out["learned_over_plain_at_fixed_dE"] = cost(res["plain"]["tau"]) / cost(res["learned"]["tau"])
+            out["learned_over_plain_at_fixed_dE_long_run"] = cost(res["plain"]["tau"]) / cost(res["learned"]["tau"])
     if args.split_dc2:
         out["split_cutoffs"] = split_run(B, torch, Ly, Lx, D, Dc, args.split_dc2, nch, args.warmup, args.steps)
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(Ly, Lx, D, Dc, seed=1908)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

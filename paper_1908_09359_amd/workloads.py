@@ -55,3 +55,16 @@ def random_proposal_weights(seed, n=19105, scale=0.05, bias=-1.0):
     w = (np.random.default_rng(seed).standard_normal(n) * scale).astype(np.float32)
     w[-1] = bias
     return w
+
+
+def random_sr_inputs(Ly, Lx, D, n_samples, seed):
+    """Seeded stand-ins for one stochastic-reconfiguration step's inputs: E_loc
+    ~ N(-10, 3^2), compact log-derivatives ~ N(0, 1) rounded to float32 (the
+    float32 path stores them so) and returned as float64 [n_samples][Np/2], and
+    uniform S^z = 0 configurations."""
+    rng = np.random.default_rng(seed)
+    nh = num_params(Ly, Lx, D) // 2
+    e = rng.standard_normal(n_samples) * 3.0 - 10.0
+    dl = rng.standard_normal((n_samples, nh), dtype=np.float32).astype(np.float64)
+    spins = random_configs(Ly, Lx, n_samples, seed=seed + 1)
+    return e, dl, spins
