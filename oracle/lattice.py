@@ -22,11 +22,16 @@ from . import philox
 class Lattice:
     """An Ly x Lx open-boundary square lattice carrying a PEPS of bond dimension D."""
 
-    def __init__(self, Ly, Lx, D, Dc, J1=1.0, J2=0.0):
+    def __init__(self, Ly, Lx, D, Dc, J1=1.0, J2=0.0, compress_mode="canonical", fit_sweeps=2):
+        """compress_mode: the boundary truncation, "canonical" (SVD compression)
+        or "variational" (the fit of App. B with fit_sweeps sweeps)."""
         if Ly < 1 or Lx < 1 or D < 1 or Dc < 1:
             raise ValueError("lattice sizes, D and Dc must be >= 1")
+        if compress_mode not in ("canonical", "variational") or fit_sweeps < 0:
+            raise ValueError("compress_mode is canonical or variational, fit_sweeps >= 0")
         self.Ly, self.Lx, self.D, self.Dc = int(Ly), int(Lx), int(D), int(Dc)
         self.J1, self.J2 = float(J1), float(J2)
+        self.compress_mode, self.fit_sweeps = compress_mode, int(fit_sweeps)
         self.N = self.Ly * self.Lx
         self.offsets = []
         off = 0

@@ -117,6 +117,119 @@ def compress(B, Dc):
     return B, math.log(nu)
 
 
+def variational_bond_dims(B, Dc):
+    """Bond dimensions k_0..k_n of the fitted MPS: those of the canonical
+    compression of B (left-to-right rank bounds, then k_j = min(Dc, bound_j,
+    p_j k_{j+1}) from the right), so that both modes produce the same shapes."""
+    n = len(B)
+    bound = [1] * (n + 1)
+    for j in range(n):
+        a, p, b = B[j].shape
+        bound[j + 1] = min(bound[j] * p, b)
+    k = [1] * (n + 1)
+    for j in range(n - 1, 0, -1):
+        k[j] = min(Dc, bound[j], B[j].shape[1] * k[j + 1])
+    return k
+
+
+def _qr_q(M):
+    """Q of the thin Householder QR of a tall matrix (LAPACK through numpy)."""
+    return np.linalg.qr(M, mode='reduced')[0]
+
+
+def _fit_env_left(L, Bj, Uj):
+    """L_{j+1}[k', b] = sum L_j[k, a] U_j[k, p, k'] B_j[a, p, b]."""
+    return np.einsum('ka,kpl,apb->lb', L, Uj, Bj, optimize=True)
+
+
+def _fit_env_right(R, Bj, Uj):
+    """R_j[k, a] = sum U_j[k, p, k'] B_j[a, p, b] R_{j+1}[k', b]."""
+    return np.einsum('kpl,apb,lb->ka', Uj, Bj, R, optimize=True)
+
+
+def _fit_center(L, Bj, R):
+    """The site tensor that maximises the overlap with B given orthonormal
+    neighbours: M[k, p, k'] = sum L[k, a] B_j[a, p, b] R[k', b]."""
+    return np.einsum('ka,apb,lb->kpl', L, Bj, R, optimize=True)
+
+
+def compress_variational(B, Dc, sweeps, qr=_qr_q):
+    """Variational boundary-MPS fit (App. B): minimise ||B - U||^2 over MPS U of
+    bond dimension Dc by alternating single-site updates (the iterative
+    compression sweep the paper cites).  The paper fixes neither the start nor
+    the number of sweeps; here they are:
+
+    * start: the MPS of the leading k_j x k_{j+1} blocks of the sites of B
+      (their first combined bond indices; k from ``variational_bond_dims``),
+      brought to right-orthonormal form without changing its state: from the
+      right, each site j >= 1 becomes the orthonormal rows Q of its LQ
+      factorisation and the factor L = M Q^T moves into site j - 1;
+    * right environments R_j = <U_j..U_{n-1}|B_j..B_{n-1}> of that start;
+    * each sweep: left to right, j = 0..n-2, the optimal site given orthonormal
+      neighbours, M = L_j B_j R_{j+1}, replaced by the Q of its QR
+      ((k_j p) x k_{j+1}) and L_{j+1} updated; then right to left, j = n-1..1,
+      the same M replaced by the orthonormal rows of its LQ (k_j x (p k_{j+1}))
+      and R_j updated;
+    * finally the optimal site 0, M_0 = B_0 R_1, carries the norm nu:
+      U_0 = M_0 / nu.
+
+    With orthonormal neighbours the fitted state is M_j in the basis they span,
+    so the result does not depend on the sign or gauge conventions of the QR
+    (``qr`` may be any thin QR).  Returns (sites (k_j, p_j, k_{j+1}), log nu);
+    raises ZeroAmplitude if the fitted state is zero.  Parity: pinned by
+    exactness at full rank, a monotonically decreasing distance over sweeps,
+    the Eckart-Young optimum on two sites, and independence of the QR gauge
+    (tests/test_oracle_variational.py); a rank-deficient centre (whose Q is
+    completed arbitrarily) is parity unpinned.
+    """
+    B = [np.asarray(b, dtype=np.float64) for b in B]
+    n = len(B)
+    k = variational_bond_dims(B, Dc)
+    U = [B[j][:k[j], :, :k[j + 1]].copy() for j in range(n)]
+
+    def lq_rows(M):
+        kj, p, kr = M.shape
+        return qr(M.reshape(kj, p * kr).T).T.reshape(kj, p, kr)
+
+    # right-orthonormal form of the start, state unchanged: U_j = L Q with Q's
+    # rows orthonormal; L moves into site j - 1
+    for j in range(n - 1, 0, -1):
+        kj, p, kr = U[j].shape
+        M = U[j].reshape(kj, p * kr)
+        Q = lq_rows(U[j]).reshape(kj, p * kr)
+        U[j] = Q.reshape(kj, p, kr)
+        U[j - 1] = np.tensordot(U[j - 1], M @ Q.T, axes=(2, 0))
+    R = [None] * (n + 1)
+    R[n] = np.ones((1, 1))
+    for j in range(n - 1, 0, -1):
+        R[j] = _fit_env_right(R[j + 1], B[j], U[j])
+    L = [None] * (n + 1)
+    L[0] = np.ones((1, 1))
+    for _ in range(sweeps):
+        for j in range(n - 1):
+            M = _fit_center(L[j], B[j], R[j + 1])
+            kj, p, kr = M.shape
+            U[j] = qr(M.reshape(kj * p, kr)).reshape(kj, p, kr)
+            L[j + 1] = _fit_env_left(L[j], B[j], U[j])
+        for j in range(n - 1, 0, -1):
+            U[j] = lq_rows(_fit_center(L[j], B[j], R[j + 1]))
+            R[j] = _fit_env_right(R[j + 1], B[j], U[j])
+    M0 = _fit_center(L[0], B[0], R[1])
+    nu = float(np.linalg.norm(M0))
+    if nu == 0.0:
+        raise ZeroAmplitude("boundary MPS fitted to the zero state")
+    U[0] = M0 / nu
+    return U, math.log(nu)
+
+
+def compress_boundary(B, lat):
+    """The lattice's truncation: the canonical SVD compression (default) or the
+    variational fit with ``lat.fit_sweeps`` sweeps (``lat.compress_mode``)."""
+    if getattr(lat, "compress_mode", "canonical") == "variational":
+        return compress_variational(B, lat.Dc, lat.fit_sweeps)
+    return compress(B, lat.Dc)
+
+
 def upper_boundaries(T, lat, spins, upto=None):
     """U_{-1}, U_0, ..., U_{upto} (default Ly-2) and their cumulative log-scales.
 
@@ -127,7 +240,7 @@ def upper_boundaries(T, lat, spins, upto=None):
     U = [trivial_mps(lat.Lx)]
     lam = [0.0]
     for y in range(upto + 1):
-        Uy, lognu = compress(absorb_down(U[-1], row_tensors(T, lat, spins, y)), lat.Dc)
+        Uy, lognu = compress_boundary(absorb_down(U[-1], row_tensors(T, lat, spins, y)), lat)
         U.append(Uy)
         lam.append(lam[-1] + lognu)
     return U, lam
@@ -135,7 +248,7 @@ def upper_boundaries(T, lat, spins, upto=None):
 
 def lower_boundary(Dn, T, lat, spins, y):
     """D_y = C(<D_{y+1}|M_y) and its log-scale."""
-    return compress(absorb_up(Dn, row_tensors(T, lat, spins, y)), lat.Dc)
+    return compress_boundary(absorb_up(Dn, row_tensors(T, lat, spins, y)), lat)
 
 
 # --------------------------------------------------------------------------

@@ -27,7 +27,7 @@ import numpy as np
 
 from . import philox
 from .lattice import bonds, bond_elements, compact_offsets, compact_size, site_tensor
-from .peps import (ZeroAmplitude, absorb_down, compress, defect3, env3_left, env4_left,
+from .peps import (ZeroAmplitude, absorb_down, compress, compress_boundary, defect3, env3_left, env4_left,
                    lower_boundary, row3_envs, row4_envs, row_tensors, trivial_mps,
                    upper_boundaries, row3_value)
 
@@ -243,7 +243,7 @@ def _top_down_pass(T, lat, ch, Dl, proposal=None):
             L4 = env4_left(L4, Uy1[x], r1[x], r2[x], D2[x])
             bond += 1
         # Row y is final for this sweep: form U_y.
-        Uy, lognu = compress(absorb_down(Uy1, row_tensors(T, lat, ch.spins, y)), lat.Dc)
+        Uy, lognu = compress_boundary(absorb_down(Uy1, row_tensors(T, lat, ch.spins, y)), lat)
         U.append(Uy)
         lam.append(lam[-1] + lognu)
     if last == 0.0:
