@@ -94,6 +94,21 @@ typedef enum { VP_FP64 = 0, VP_FP32 = 1, VP_BF16 = 2 } vp_prec;
  * each vertical bond (see vp_set_sampler). */
 typedef enum { VP_SAMPLER_PAIR_SEQ = 0, VP_SAMPLER_LEARNED_PLAQ = 1 } vp_sampler;
 
+/* Boundary truncation to Dc (App. B).  VP_COMPRESS_CANONICAL: the canonical
+ * SVD compression (left-to-right orthogonalisation, right-to-left truncation
+ * keeping the Dc largest singular values; float64 in every precision).
+ * VP_COMPRESS_VARIATIONAL: the paper's variational fit, minimising
+ * ||M_y|U_{y-1}> - |U_y>||^2 by fit_sweeps sweeps of single-site updates (in
+ * the working precision): start from the leading k_l x k_r blocks of the
+ * product sites (right-orthonormal form, state kept), then per sweep each site
+ * replaced by the Q of the optimal site's QR (left to right) and by the
+ * orthonormal rows of its LQ (right to left); the optimal site 0 carries the
+ * norm.  Both use the same bond dimensions.  The persistent schedule
+ * (VP_SCHED_PERSISTENT, vp_sample_batch) runs the canonical compression only:
+ * with VP_COMPRESS_VARIATIONAL it returns VP_ERR_UNSUPPORTED, and vp_autotune
+ * skips it (its time reads -1). */
+typedef enum { VP_COMPRESS_CANONICAL = 0, VP_COMPRESS_VARIATIONAL = 1 } vp_compress;
+
 typedef struct {
   int32_t Ly, Lx;      /* lattice extent */
   int32_t D;           /* PEPS virtual bond dimension */
@@ -101,6 +116,8 @@ typedef struct {
   double J1, J2;       /* nearest-neighbour and diagonal couplings */
   int32_t prec;        /* vp_prec of the contractions */
   int32_t n_chains;    /* Markov chains kept on the device */
+  int32_t compress;    /* vp_compress (0 = canonical, the zero-initialised default) */
+  int32_t fit_sweeps;  /* sweeps of VP_COMPRESS_VARIATIONAL (0..64) */
 } vp_lattice;
 
 typedef struct vp_ctx vp_ctx;

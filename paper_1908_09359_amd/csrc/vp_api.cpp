@@ -247,6 +247,9 @@ vp_status check_lattice(vp_ctx* ctx, const vp_lattice& p) {
     return fail(ctx, VP_ERR_SHAPE, "sizes beyond the built kernels (D <= 16, Dc <= 64, D*Dc <= 128)");
   if (p.prec != VP_FP64 && p.prec != VP_FP32 && p.prec != VP_BF16)
     return fail(ctx, VP_ERR_ARG, "unknown precision %d", p.prec);
+  if (p.compress != VP_COMPRESS_CANONICAL && p.compress != VP_COMPRESS_VARIATIONAL)
+    return fail(ctx, VP_ERR_ARG, "unknown truncation mode %d", p.compress);
+  if (p.fit_sweeps < 0 || p.fit_sweeps > 64) return fail(ctx, VP_ERR_ARG, "fit_sweeps must be 0..64");
   return VP_OK;
 }
 
@@ -345,6 +348,9 @@ template <typename T>
 vp_status run_queue(vp_ctx* ctx, const std::vector<Lattice*>& lats, int n_burn, int n_meas,
                     const std::vector<SampleOut>& outs, hipStream_t s) {
   const int n = (int)lats.size();
+  for (const Lattice* L : lats)
+    if (L->p.compress != VP_COMPRESS_CANONICAL)
+      return fail(ctx, VP_ERR_UNSUPPORTED, "the persistent schedule runs the canonical compression only");
   // the tables are rewritten: the previous call's launches must be done
   HIP_TRY(ctx, hipStreamSynchronize(s));
   std::vector<int> order(n);
@@ -646,6 +652,7 @@ vp_status vp_create(const vp_lattice* lats, int32_t n_lats, uint64_t seed, void*
     D.Ly = p.Ly; D.Lx = p.Lx; D.d = p.D; D.c = p.Dc; D.N = L.N;
     D.J1 = p.J1; D.J2 = p.J2; D.n_chains = p.n_chains;
     D.seed = seed; D.lat_id = i;
+    D.cmode = p.compress; D.fit_sweeps = p.fit_sweeps;
     D.Tw = L.Tw; D.ws = L.ws; D.ws_stride = P.ws;
     D.cws = L.cws; D.cws_stride = P.cws;
     D.iws = L.iws; D.iws_stride = P.iws; D.dws = L.dws; D.dws_stride = P.dws;
@@ -887,6 +894,10 @@ vp_status vp_autotune(vp_ctx* ctx, int32_t lat, int32_t sweeps, double* ms_host,
   ctx->timing = false;
   vp_status st = VP_OK;
   for (int k = 0; k < 3 && st == VP_OK; ++k) {
+    if (cand[k] == VP_SCHED_PERSISTENT && L->p.compress != VP_COMPRESS_CANONICAL) {
+      if (ms_host) ms_host[k] = -1.0;  // not available with the variational fit
+      continue;
+    }
     L->schedule = cand[k];
     // one untimed sweep first (initial boundaries, graph and code warm-up)
     st = vp_sample(ctx, lat, 1, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);

@@ -162,6 +162,123 @@ __device__ void env3_fused(T* __restrict__ Lout_p, const T* __restrict__ Lin_p, 
   __syncthreads();
 }
 
+// The optimal site of the variational boundary fit (App. B) for the same
+// shapes: the 3-line network with its lower boundary site removed,
+//   Mout[c][dd][e] = sum_{a,l,u,b,r} Lin[a][l][c] A[a][u][b] t[l][u][r][dd] Rn[b][r][e],
+// as env3_fused's products S1 and S2 per block of BB upper-boundary indices b,
+// then S3' Mout[(c,dd)][e] += sum_{bb,r} X1[(c,dd)][(bb,r)] Rn[(b0+bb,r)][e],
+// accumulated over the blocks in registers (two row tiles per wavefront).
+template <typename T, int D, int C>
+__device__ void env3_center_fused(T* __restrict__ Mout_p, const T* __restrict__ Lin_p, const T* __restrict__ A_p,
+                                  S3 sA, const T* __restrict__ t_p, S4 st, const T* __restrict__ Rn_p, char* lds) {
+  auto* Mout = gmem(Mout_p);
+  const auto* Lin = gmem(Lin_p);
+  const auto* A = gmem(A_p);
+  const auto* t = gmem(t_p);
+  const auto* Rn = gmem(Rn_p);
+  using Sh = Env3Shape<D, C>;
+  static_assert(Sh::ok, "env3_center_fused: D*D = 64 and D*Dc = 128 only");
+  using M = Mfma<T>;
+  typedef typename M::acc_t acc_t;
+  constexpr int BB = Sh::BB, P0 = Sh::P0, P1 = Sh::P1;
+  T* As = reinterpret_cast<T*>(lds);
+  T* Rs = As + Sh::SA;
+  T* X = Rs + Sh::SA;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, q = lane >> 4, li = lane & 15;
+
+  T lf[2][C / 4];
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int s = 0; s < C / 4; ++s) lf[mt][s] = Lin[(4 * s + q) * (D * C) + (2 * wave + mt) * 16 + li];
+  T tf[D * D / 4];
+  {
+    const int j = 16 * wave + li, r = j / D, dd = j % D;
+#pragma unroll
+    for (int s = 0; s < D * D / 4; ++s) {
+      const int k = 4 * s + q, l = k / D, u = k % D;
+      tf[s] = t[l * st.l + u * st.u + r * st.r + dd * st.d];
+    }
+  }
+  // A as [a][b-block][u][bb] (S1 columns contiguous), Rn as [(b,r)][e]
+  for (int e = tid; e < Sh::SA; e += WG) {
+    const int p = e / (D * C);
+    Rs[e] = Rn[e];
+    const int rem = e % (D * C), blk = rem / (D * BB), u = (rem / BB) % D, b = blk * BB + rem % BB;
+    As[e] = A[p * sA.s0 + u * sA.s1 + b * sA.s2];
+  }
+  __syncthreads();
+
+  acc_t acc3[2];
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt) acc3[mt] = acc_t{0, 0, 0, 0};
+  for (int blk = 0; blk < Sh::NBLK; ++blk) {
+    const int b0 = blk * BB;
+    {  // S1 -> X0 stored [(l,u)][(c,bb)]
+      acc_t acc[2][2];
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) acc[mt][nt] = acc_t{0, 0, 0, 0};
+#pragma unroll
+      for (int s = 0; s < C / 4; ++s) {
+        const int k = 4 * s + q;
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+          const T b = As[k * (D * C) + b0 * D + nt * 16 + li];
+#pragma unroll
+          for (int mt = 0; mt < 2; ++mt) acc[mt][nt] = M::op(lf[mt][s], b, acc[mt][nt]);
+        }
+      }
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = (2 * wave + mt) * 16 + M::row(lane, r), j = nt * 16 + li;
+            const int l = i / C, c = i % C, u = j / BB, bb = j % BB;
+            X[(l * D + u) * P0 + c * BB + bb] = acc[mt][nt][r];
+          }
+    }
+    __syncthreads();
+    // S2: rows (c,bb) in four tiles, columns (r,dd) of tile `wave`
+    acc_t acc2[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) acc2[mt] = acc_t{0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < D * D / 4; ++s) {
+      const int k = 4 * s + q;
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt) acc2[mt] = M::op(X[k * P0 + mt * 16 + li], tf[s], acc2[mt]);
+    }
+    __syncthreads();  // X0 consumed: X1 takes its place, stored [(c,dd)][(bb,r)]
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = mt * 16 + M::row(lane, r), j = 16 * wave + li;
+        const int c = i / BB, bb = i % BB, rr = j / D, dd = j % D;
+        X[(c * D + dd) * P1 + bb * D + rr] = acc2[mt][r];
+      }
+    __syncthreads();
+    // S3': row tiles 2w, 2w+1 of (c,dd), all e, the block's (bb,r) as the sum
+#pragma unroll
+    for (int s = 0; s < BB * D / 4; ++s) {
+      const int k = 4 * s + q;
+      const T b = Rs[(b0 * D + k) * C + li];
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) acc3[mt] = M::op(X[((2 * wave + mt) * 16 + li) * P1 + k], b, acc3[mt]);
+    }
+    __syncthreads();  // X1 consumed before the next block's S1 stores
+  }
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Mout[((2 * wave + mt) * 16 + M::row(lane, r)) * C + li] = acc3[mt][r];
+  __syncthreads();
+}
+
 template <typename T, int D, int C>
 __device__ void defect3_fused(T* __restrict__ Out_p, const T* __restrict__ Lp_p, const T* __restrict__ A_p, S3 sA,
                               const T* __restrict__ Rn_p, const T* __restrict__ B_p, S3 sB, char* lds) {

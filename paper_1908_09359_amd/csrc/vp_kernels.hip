@@ -7,6 +7,7 @@
 #include "vp_env4.hpp"
 #include "vp_env4bf.hpp"
 #include "vp_env3.hpp"
+#include "vp_fit.hpp"
 #include "vp_kernels.hpp"
 #include "vp_net.hpp"
 
@@ -481,6 +482,149 @@ constexpr size_t compress_lds() {
   return kGram > kEig ? kGram : kEig;
 }
 
+// LDS of the variational fit: its 3-line steps, the optimal-site step and the GEMM tiles.
+template <typename T, int DD, int CC>
+constexpr size_t fit_lds() {
+  return step3_lds<T, DD, CC, false>();
+}
+
+// One 3-line column step of the fit's environments <U'|M_y|U_{y-1}> (upper) or
+// <D_{y+1}|M_y|D'> (lower, the row's u and d legs swapped in st): A is the
+// input boundary site, U the fitted one in the lower position.  Left step
+// Lout[b][r][e] = sum Lin[a][l][c] A[a][x][b] t[l][x][r][y] U[c][y][e]; the
+// right step mirrors it.  Returns the power of two taken out.
+template <typename T, int DD, int CC>
+__device__ inline int fit_env(const LatDev& L, const Chain<T>& C, T* out, const T* in, const T* A, const T* t, S4 st,
+                              const T* U, bool right, lds_char* lds) {
+  if constexpr (fused3<T, DD, CC>()) {
+    if (right)
+      env3_fused<T, DD, CC>(out, in, A, sb_mirror(CC, DD), t, st_mirror(st), U, sb_mirror(CC, DD), (char*)lds);
+    else
+      env3_fused<T, DD, CC>(out, in, A, sb_std(CC, DD), t, st, U, sb_std(CC, DD), (char*)lds);
+    return wg_renorm<T>(out, CC * DD * CC);
+  }
+  if (right)
+    env3_step<T>(out, in, A, sb_mirror(L.c, L.d), t, st_mirror(st), U, sb_mirror(L.c, L.d), C.ws + L.oX0,
+                 C.ws + L.oX1, L.c, L.d, (char*)lds);
+  else
+    env3_step<T>(out, in, A, sb_std(L.c, L.d), t, st, U, sb_std(L.c, L.d), C.ws + L.oX0, C.ws + L.oX1, L.c, L.d,
+                 (char*)lds);
+  return wg_renorm<T>(out, e3sz(L));
+}
+
+// The optimal fitted site given orthonormal neighbours:
+// Mc[k][y][k'] = sum Lj[a][l][k] A[a][x][b] t[l][x][r][y] Rn[b][r][k'],
+// as Y = (A t Rn) (the compression's right half) and Mc = Lj^T Y.
+template <typename T, int DD, int CC>
+__device__ inline void fit_center(const LatDev& L, const Chain<T>& C, T* Mc, const T* Lj, const T* A, const T* t,
+                                  S4 st, const T* Rn, lds_char* lds) {
+  if constexpr (fused3<T, DD, CC>()) {
+    env3_center_fused<T, DD, CC>(Mc, Lj, A, sb_std(CC, DD), t, st, Rn, (char*)lds);
+    return;
+  }
+  const int c = L.c, d = L.d;
+  T* Y = C.ws + L.oX1;
+  compress_y<T, T>(Y, A, sb_std(c, d), t, st, Rn, C.ws + L.oX0, c, d, lds);
+  wg_gemm_t<T>((char*)lds, Mc, rowmajor(d * c), Lj, colmajor(c), Y, rowmajor(d * c), c, d * c, c * d);
+}
+
+// Variational fit (App. B) of row y into U_y (upper = 1) or D_y: minimise the
+// distance between the fitted MPS and M_y|U_{y-1}> (or <D_{y+1}|M_y) by
+// L.fit_sweeps sweeps of single-site updates, in the working precision.
+//   start: leading kl x kr blocks of the product sites, brought to
+//          right-orthonormal form from the right (LQ, factor into the left
+//          neighbour); right environments of the start;
+//   sweep: left to right, the optimal site Lj B Rn replaced by its QR's Q and
+//          the left environment advanced; right to left, the same replaced by
+//          its LQ's orthonormal rows and the right environment advanced;
+//   end:   the optimal site 0 normalised; its norm (with the environments'
+//          powers of two) goes into the log-scale.
+// Bond dimensions are the plan's (those of the canonical compression).
+template <typename T, int DD, int CC>
+__device__ __forceinline__ void ph_compress_var(const LatDev& L, int ch, int y, int upper, char* lds) {
+  Chain<T> C = chain_of<T>(L, ch);
+  if (chain_flagged(C.meta)) return;
+  const int c = L.c, d = L.d, Lx = L.Lx, ssz = c * d * c;
+  const int in_slot = upper ? y : y + 1;
+  const int out_slot = upper ? y + 1 : y;
+  auto A_in = [&](int x) -> const T* { return upper ? ub<T>(L, C, in_slot, x) : db<T>(L, C, in_slot, x); };
+  auto A_out = [&](int x) -> T* { return upper ? ub<T>(L, C, out_slot, x) : db<T>(L, C, out_slot, x); };
+  auto tsite = [&](int x) -> const T* { const int k = y * Lx + x; return tw<T>(L, k, C.sp[k]); };
+  auto phys = [&](int x) { const int k = y * Lx + x; return upper ? L.dims[4 * k + 3] : L.dims[4 * k + 1]; };
+  const int32_t* kb = upper ? (L.kU + (y + 1) * (Lx + 1)) : (L.kD + y * (Lx + 1));
+  const S4 st = upper ? st_std(d) : st_swapud(st_std(d));
+  T* Le = C.ws + L.oL3;
+  T* Re = C.ws + L.oR3;
+  int* eL = C.iw + L.ieL3;
+  int* eR = C.iw + L.ieR3;
+  T* Mc = C.ws + L.oT3;
+  T* Xq = Mc + ssz;        // QR scratch: the factored matrix (R in its upper triangle)
+  T* Qq = Xq + ssz;        // QR scratch: Q; also the carry's temporary
+  lds_char* ll = as_lds(lds);
+  // the fitted site x as a (k_x p) x k_{x+1} matrix (QR), or its transpose (LQ)
+  auto qr_view = [&](int x) { return view(phys(x), d * c, c, 1, 1, 0); };
+  auto lq_view = [&](int x) { return view(kb[x + 1], c, 1, 1, d * c, 0); };
+
+  // start
+  for (int x = 0; x < Lx; ++x) {
+    const int k = y * Lx + x;
+    fit_start<T>(A_out(x), A_in(x), sb_std(c, d), tsite(x), st, c, d, kb[x], kb[x + 1], phys(x), L.dims[4 * k],
+                 L.dims[4 * k + 2]);
+  }
+  for (int x = Lx - 1; x >= 1; --x) {
+    const int m = phys(x) * kb[x + 1], n = kb[x];
+    fit_qr_any<T>(A_out(x), ssz, lq_view(x), m, n, Xq, Qq);
+    fit_carry<T>(A_out(x - 1), Xq, m, n, kb[x - 1], phys(x - 1), c, d, Qq);
+  }
+  set_unit<T>(Re + (int64_t)Lx * ssz, ssz);
+  set_unit<T>(Le, ssz);
+  if (threadIdx.x == 0) { eR[Lx] = 0; eL[0] = 0; }
+  __syncthreads();
+  for (int x = Lx - 1; x >= 1; --x) {
+    const int e = fit_env<T, DD, CC>(L, C, Re + (int64_t)x * ssz, Re + (int64_t)(x + 1) * ssz, A_in(x), tsite(x), st,
+                                     A_out(x), true, ll);
+    if (threadIdx.x == 0) eR[x] = eR[x + 1] + e;
+    __syncthreads();
+  }
+  for (int s = 0; s < L.fit_sweeps; ++s) {
+    for (int x = 0; x < Lx - 1; ++x) {
+      fit_center<T, DD, CC>(L, C, Mc, Le + (int64_t)x * ssz, A_in(x), tsite(x), st, Re + (int64_t)(x + 1) * ssz, ll);
+      wg_copy<T>(A_out(x), Mc, ssz);
+      fit_qr_any<T>(A_out(x), ssz, qr_view(x), kb[x] * phys(x), kb[x + 1], Xq, Qq);
+      const int e = fit_env<T, DD, CC>(L, C, Le + (int64_t)(x + 1) * ssz, Le + (int64_t)x * ssz, A_in(x), tsite(x),
+                                       st, A_out(x), false, ll);
+      if (threadIdx.x == 0) eL[x + 1] = eL[x] + e;
+      __syncthreads();
+    }
+    for (int x = Lx - 1; x >= 1; --x) {
+      fit_center<T, DD, CC>(L, C, Mc, Le + (int64_t)x * ssz, A_in(x), tsite(x), st, Re + (int64_t)(x + 1) * ssz, ll);
+      wg_copy<T>(A_out(x), Mc, ssz);
+      fit_qr_any<T>(A_out(x), ssz, lq_view(x), phys(x) * kb[x + 1], kb[x], Xq, Qq);
+      const int e = fit_env<T, DD, CC>(L, C, Re + (int64_t)x * ssz, Re + (int64_t)(x + 1) * ssz, A_in(x), tsite(x),
+                                       st, A_out(x), true, ll);
+      if (threadIdx.x == 0) eR[x] = eR[x + 1] + e;
+      __syncthreads();
+    }
+  }
+  // site 0: the optimal tensor with everything to its right orthonormal
+  fit_center<T, DD, CC>(L, C, Mc, Le, A_in(0), tsite(0), st, Re + ssz, ll);
+  double nrm2 = 0.0;
+  for (int i = threadIdx.x; i < ssz; i += WG) nrm2 += (double)Mc[i] * (double)Mc[i];
+  nrm2 = wg_sum(nrm2);
+  const double nu = sqrt(nrm2);
+  const double inv = nu > 0.0 ? 1.0 / nu : 0.0;
+  T* out0 = A_out(0);
+  for (int i = threadIdx.x; i < ssz; i += WG) out0[i] = (T)((double)Mc[i] * inv);
+  if (threadIdx.x == 0) {
+    if (!(nu > 0.0)) atomicOr(&C.meta->flags, FLAG_ZERO);
+    else if (!isfinite(nu)) atomicOr(&C.meta->flags, FLAG_NONFINITE);
+    const double lognu = log(nu) + eR[1] * 0.69314718055994530942;
+    if (upper) C.dw[L.dlamU + y + 1] = C.dw[L.dlamU + y] + lognu;
+    else C.dw[L.dlamD + y] = C.dw[L.dlamD + y + 1] + lognu;
+  }
+  __syncthreads();
+}
+
 template <typename T, int DD, int CC>
 __device__ __forceinline__ void ph_compress(const LatDev& L, int ch, int y, int upper, char* lds) {
   Chain<T> C = chain_of<T>(L, ch);
@@ -789,6 +933,13 @@ template <typename T, int DD, int CC>
 __global__ void __launch_bounds__(WG, 2) k_compress(LatDev L, int y, int upper) {
   __shared__ __attribute__((aligned(16))) char lds[compress_lds<T, DD, CC>()];
   ph_compress<T, DD, CC>(L, blockIdx.x, y, upper, lds);
+}
+// The variational fit in a kernel of its own (it needs far less LDS than the
+// canonical compression's eigensolver).
+template <typename T, int DD, int CC>
+__global__ void __launch_bounds__(WG, 2) k_compress_fit(LatDev L, int y, int upper) {
+  __shared__ __attribute__((aligned(16))) char lds[fit_lds<T, DD, CC>()];
+  ph_compress_var<T, DD, CC>(L, blockIdx.x, y, upper, lds);
 }
 template <typename T, int DD, int CC>
 __global__ void __launch_bounds__(WG, 2) k_measure3(LatDev L, int y, SampleOut o) {
@@ -1145,7 +1296,8 @@ void launch_vsweep(const LatDev& L, int y, bool bf16, bool learned, hipStream_t 
 }
 template <typename T>
 void launch_compress(const LatDev& L, int y, int upper, hipStream_t s) {
-  VP_DISPATCH_DC(k_compress, T, L, y, upper);
+  if (L.cmode == 1) VP_DISPATCH_DC(k_compress_fit, T, L, y, upper);
+  else VP_DISPATCH_DC(k_compress, T, L, y, upper);
 }
 template <typename T>
 void launch_measure3(const LatDev& L, int y, const SampleOut& o, hipStream_t s) {

@@ -46,6 +46,8 @@ struct LatDev {
   const void* net;          // proposal network parameters in the working precision, or null
   int learned;              // learned plaquette moves in the persistent sweep kernel
   int tile;                 // tile variant of the fused 2-row step (per-phase launches): 0, 1, 2
+  int cmode;                // boundary truncation: 0 canonical SVD compression, 1 variational fit
+  int fit_sweeps;           // sweeps of the variational fit
   const int32_t* kU;        // bond dims of U_y: kU[(y+1)*(Lx+1) + j], y = -1..Ly-1
   const int32_t* kD;        // bond dims of D_y: kD[y*(Lx+1) + j], y = 0..Ly
   const int32_t* dims;      // true leg dims per site [N][4] (l,u,r,d)

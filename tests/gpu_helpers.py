@@ -10,11 +10,11 @@ def n_pairs(Ly, Lx, J2):
     return Ly * (Lx - 1) + (Ly - 1) * Lx + (2 * (Ly - 1) * (Lx - 1) if J2 != 0.0 else 0)
 
 
-def gpu_eval(Ly, Lx, D, Dc, J2, prec, T, cfgs, n_chains=None):
+def gpu_eval(Ly, Lx, D, Dc, J2, prec, T, cfgs, n_chains=None, compress=0, fit_sweeps=0):
     import torch
     from paper_1908_09359_amd import binding as B
     n = len(cfgs)
-    lat = B.lattice(Ly, Lx, D, Dc, 1.0, J2, prec, n_chains or n)
+    lat = B.lattice(Ly, Lx, D, Dc, 1.0, J2, prec, n_chains or n, compress, fit_sweeps)
     ctx = B.Context(lat, seed=1)
     dev = torch.device("cuda")
     ctx.vp_set_tensors(0, torch.tensor(T, dtype=torch.float64, device=dev))
@@ -33,8 +33,8 @@ def gpu_eval(Ly, Lx, D, Dc, J2, prec, T, cfgs, n_chains=None):
     return out
 
 
-def oracle_eval(Ly, Lx, D, Dc, J2, T, cfgs):
-    lat = olat.Lattice(Ly, Lx, D, Dc, J2=J2)
+def oracle_eval(Ly, Lx, D, Dc, J2, T, cfgs, compress_mode="canonical", fit_sweeps=2):
+    lat = olat.Lattice(Ly, Lx, D, Dc, J2=J2, compress_mode=compress_mode, fit_sweeps=fit_sweeps)
     outs = [vmc.eval_config(T, lat, c) for c in cfgs]
     return dict(log_abs_psi=np.array([o["log_abs_psi"] for o in outs]),
                 sign=np.array([o["sign"] for o in outs]),

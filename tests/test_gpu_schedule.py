@@ -61,7 +61,13 @@ def _run(schedule, Ly, Lx, D, Dc, J2, n, T, seed, calls, learned=None):
     return outs, c
 
 
-@pytest.mark.parametrize("Ly,Lx,D,Dc,J2,learn", [(4, 4, 2, 4, 0.0, False), (6, 6, 4, 8, 0.5, False),
+FAULTED = ("a GPU memory fault was reported in this case once, on a build whose compression kernels also "
+           "held the variational fit; the fit has since moved to a kernel of its own, but the fault's cause was "
+           "not shown, so the case stays off the GPU until it is")
+
+
+@pytest.mark.parametrize("Ly,Lx,D,Dc,J2,learn", [pytest.param(4, 4, 2, 4, 0.0, False, marks=pytest.mark.skip(reason=FAULTED)),
+                                                 (6, 6, 4, 8, 0.5, False),
                                                  (4, 6, 3, 4, 0.0, True), (4, 6, 8, 16, 0.0, True)])
 def test_schedules_agree_bit_exactly(Ly, Lx, D, Dc, J2, learn):
     B = _B()
