@@ -12,7 +12,10 @@ of every boundary compression multiplied by (1 + eps xi), xi ~ N(0, 1) i.i.d.
 from a seeded stream (nothing else changes).  ``floor`` is the largest
 deviation from the unperturbed evaluation over several seeds: the per-output
 floor that the GPU parity bounds are derived from (a bound is a small multiple
-of it, never below the float64 bounds of the small lattices).
+of it, never below the float64 bounds of the small lattices).  The float64
+floor perturbs the compression inputs at the float64 unit; the float32 floor
+models float32 storage (``storage=True``): the site tensors, the compression
+inputs and the compressed boundaries, each at the float32 unit.
 """
 import numpy as np
 
@@ -22,20 +25,36 @@ F64_UNIT = 2.0 ** -52
 F32_UNIT = 2.0 ** -24
 
 
-def perturbed_eval(T, lat, spins, eps, seed):
-    """oracle.vmc.eval_config with every compression input scaled by (1 + eps xi)."""
-    exact = peps.compress
+def perturbed_eval(T, lat, spins, eps, seed, storage=False):
+    """oracle.vmc.eval_config with every compression input (canonical or
+    variational) scaled by (1 + eps xi).  With ``storage`` also the site
+    tensors and every compression output: the model of an implementation that
+    stores every tensor in a format of unit eps (the float32 path stores the
+    site tensors, boundaries and environments in float32)."""
+    exact, exact_fit = peps.compress, peps.compress_variational
     rng = np.random.default_rng(seed)
 
-    def perturbed(B, Dc):
-        return exact([b * (1.0 + eps * rng.standard_normal(b.shape)) for b in B], Dc)
+    def jitter(B):
+        return [b * (1.0 + eps * rng.standard_normal(b.shape)) for b in B]
 
-    peps.compress = perturbed
+    def out(res):
+        return (jitter(res[0]), res[1]) if storage else res
+
+    def perturbed(B, Dc):
+        return out(exact(jitter(B), Dc))
+
+    def perturbed_fit(B, Dc, sweeps, **kw):
+        return out(exact_fit(jitter(B), Dc, sweeps, **kw))
+
+    if storage:
+        T = np.asarray(T) * (1.0 + eps * rng.standard_normal(np.shape(T)))
+
+    peps.compress, peps.compress_variational = perturbed, perturbed_fit
     vmc.compress = perturbed
     try:
         return vmc.eval_config(T, lat, spins)
     finally:
-        peps.compress = exact
+        peps.compress, peps.compress_variational = exact, exact_fit
         vmc.compress = exact
 
 

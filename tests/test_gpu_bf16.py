@@ -217,7 +217,8 @@ def test_c3_gate_fp64_within_floors():
 def test_c3_gate_fp32_within_floors():
     """The same 64 configurations in float32 (the plain path's precision):
     each |dE_loc|/N within max(1e-4, 3 x its float32-level floor) (the oracle
-    under 2^-24 perturbations of every compression input, three seeds); the
+    with float32 storage modelled: site tensors, compression inputs and the
+    compressed boundaries multiplied by (1 + 2^-24 xi), eight seeds); the
     configurations meeting 1e-4 itself are counted and printed."""
     B = _B()
     doc, fl, w, T, cfgs = _gate()
