@@ -68,3 +68,25 @@ def random_sr_inputs(Ly, Lx, D, n_samples, seed):
     dl = rng.standard_normal((n_samples, nh), dtype=np.float32).astype(np.float64)
     spins = random_configs(Ly, Lx, n_samples, seed=seed + 1)
     return e, dl, spins
+
+
+def pad_tensors(T_small, Ly, Lx, D_small, D_big, noise=0.0, seed=0):
+    """The flat parameters of a bond-D_small PEPS written into the layout of
+    bond D_big (entries with a virtual index >= D_small are zero, so the state
+    is the same), plus noise * N(0, 1) on every entry of the D_big layout."""
+    def dims(D, y, x):
+        return ((D if x > 0 else 1), (D if y > 0 else 1), (D if x < Lx - 1 else 1), (D if y < Ly - 1 else 1))
+    out = []
+    o = 0
+    for y in range(Ly):
+        for x in range(Lx):
+            ds, db = dims(D_small, y, x), dims(D_big, y, x)
+            n = int(np.prod(ds))
+            blk = np.zeros((2,) + db)
+            blk[:, :ds[0], :ds[1], :ds[2], :ds[3]] = np.asarray(T_small[o:o + 2 * n]).reshape((2,) + ds)
+            o += 2 * n
+            out.append(blk.ravel())
+    T = np.concatenate(out)
+    if noise:
+        T = T + noise * np.random.default_rng(seed).standard_normal(T.shape)
+    return T

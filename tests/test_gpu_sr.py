@@ -63,3 +63,31 @@ def test_sr_ragged_blocks(prec):
     delta, Tn = _run_sr(Ly, Lx, D, prec, e, dl, spins, 1e-3, 0.1, T)
     assert np.max(np.abs(delta - ref)) <= 1e-9 * np.max(np.abs(ref))
     assert np.allclose(Tn, T - 0.1 * ref, rtol=0, atol=1e-9 * np.max(np.abs(ref)))
+
+
+def test_sr_at_the_8x8_D4_size():
+    """One SR step at the 8x8, D=4 workload's size (Np = 21632, Ns = 20480 = 1024
+    chains x 20 sweeps) on seeded float32 log-derivatives, against the oracle's
+    float64 Cholesky solve stored by tests/golden/make_sr_c2.py (512 sampled
+    entries of delta and of the gradient).  S is rank-deficient (Ns < Np), so
+    the shift 1e-4 bounds its smallest eigenvalue and kappa(S + shift I) ~ 4e4:
+    the bound is 1e-9 max|delta| (~ kappa eps sqrt(Np) = 6.5e-10)."""
+    import json
+    import os
+    from paper_1908_09359_amd import binding as B
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sr_c2_8x8_D4.json")) as f:
+        doc = json.load(f)
+    w = doc["workload"]
+    print(f"sr fp32 8x8 D=4 Np={w['Np']} Ns={w['n_samples']}", flush=True)
+    e, dl, spins = W.random_sr_inputs(w["Ly"], w["Lx"], w["D"], w["n_samples"], w["seed"])
+    T = W.random_tensors(w["Ly"], w["Lx"], w["D"], seed=36)
+    delta, Tn = _run_sr(w["Ly"], w["Lx"], w["D"], B.VP_FP32, e, dl.astype(np.float32), spins, w["shift"], 0.05, T)
+    idx = np.asarray(doc["index"])
+    ref = np.asarray(doc["delta"])
+    err = np.max(np.abs(delta[idx] - ref)) / doc["delta_max_abs"]
+    print(f"sr at the 8x8 D=4 size: max |d delta| / max |delta| = {err:.3e}, "
+          f"max |delta| {np.max(np.abs(delta)):.6f} vs {doc['delta_max_abs']:.6f}", flush=True)
+    assert err <= 1e-9
+    assert abs(np.max(np.abs(delta)) - doc["delta_max_abs"]) <= 1e-9 * doc["delta_max_abs"]
+    assert abs(np.linalg.norm(delta) - doc["delta_norm"]) <= 1e-9 * doc["delta_norm"]
+    assert np.max(np.abs(Tn[idx] - (T[idx] - 0.05 * delta[idx]))) <= 1e-12
