@@ -67,7 +67,7 @@ def kernel_source_digest():
     return h.hexdigest()[:16]
 
 
-def phase_flops(Ly, Lx, D, Dc, nch, launches, anti_h=0, anti_v=0):
+def phase_flops(Ly, Lx, D, Dc, nch, launches, anti_h=0, anti_v=0, fit_sweeps=None):
     """Algorithmic flops of each phase over the timed region (all chains, all launches).
 
     Column-step costs (multiply-adds, bulk dimensions):
@@ -82,6 +82,11 @@ def phase_flops(Ly, Lx, D, Dc, nch, launches, anti_h=0, anti_v=0):
     network per antiparallel pair: two 3-line steps for a horizontal pair, one
     2-row step for a vertical pair.  anti_h / anti_v are the numbers of
     antiparallel horizontal / vertical pairs in the configurations measured.
+    With fit_sweeps (the variational fit instead of the canonical compression),
+    a row's compression is (Lx-1)(1 + 2 S) 3-line environment steps, 2 S (Lx-1)
+    + 1 optimal-site contractions (D^4 Dc^2 + 2 D^2 Dc^3 each) and Lx - 1 + 2 S
+    (Lx - 1) Householder QRs of (D Dc) x Dc blocks (4 m n^2 - 4/3 n^3 flops,
+    factorisation and Q).
     """
     c, d = Dc, D
     env3 = d ** 4 * c ** 2 + 2 * d ** 2 * c ** 3
@@ -90,6 +95,10 @@ def phase_flops(Ly, Lx, D, Dc, nch, launches, anti_h=0, anti_v=0):
     n = d * c
     comp_mac = (Lx - 1) * env4 + Lx * (d ** 2 * c ** 3 + d ** 4 * c ** 2) + (Lx - 1) * (2 * n ** 3 + d ** 2 * c ** 3)
     comp = 2 * comp_mac + (Lx - 1) * (4.0 / 3.0 * n ** 3 + 4 * n ** 2 * c)
+    if fit_sweeps is not None:
+        S = fit_sweeps
+        qr = 4.0 * n * c * c - 4.0 / 3.0 * c ** 3
+        comp = 2.0 * ((Lx - 1) * (1 + 2 * S) * env3 + (2 * S * (Lx - 1) + 1) * env3) + (Lx - 1) * (1 + 2 * S) * qr
     per_launch = {"row3_envs": 2 * (Lx - 1) * env3, "row4_envs": 2 * (Lx - 1) * env4,
                   "compress_up": comp, "compress_down": comp}
     out = {k: v * nch * launches.get(k, 0) for k, v in per_launch.items()}
@@ -135,16 +144,52 @@ def cpu_baseline(Ly, Lx, D, Dc, seed, max_procs=16):
                                   "x 45000 sweeps)"}}
 
 
+def set_tensors(ctx, T=None):
+    """The workload's tensors: given ones (a device tensor), or the seeded N(0,1)/D^2 draw."""
+    if T is None:
+        ctx.vp_init_tensors(0, seed=1908, scale=0.0, perturb=0.0)
+    else:
+        ctx.vp_set_tensors(0, T)
+
+
+def correlated_tensors(B, torch, L, D, seed=7, steps=60):
+    """A correlated stand-in for the paper's optimised states: an L x L PEPS of bond
+    dimension 2 brought down by Algorithm 1 (vp_optimize: 256 chains, 2 + 4 sweeps
+    per step, step lengths 0.05, 0.02, 0.01 for a third of the steps each), written
+    into the bond-D layout (the same state) plus noise of 1e-3 times its rms entry."""
+    import numpy as np
+    from paper_1908_09359_amd import workloads as W
+    t0 = time.perf_counter()
+    dev = torch.device("cuda:0")
+    ctx = B.Context(B.lattice(L, L, 2, 4, 1.0, 0.0, B.VP_FP64, 256), seed=seed)
+    ctx.vp_init_tensors(0, seed=seed, scale=0.0, perturb=0.0)
+    ctx.vp_init_chains(0, None)
+    third = steps // 3
+    deltas = [0.05] * third + [0.02] * third + [0.01] * (steps - 2 * third)
+    e = np.array(ctx.vp_optimize(0, deltas, 2, 4)) / (L * L)
+    T2 = torch.empty(ctx.num_params(), dtype=torch.float64, device=dev)
+    ctx.vp_get_tensors(0, T2)
+    ctx.vp_sync()
+    T2 = T2.cpu().numpy()
+    ctx.close()
+    rms = float(np.sqrt(np.mean(T2 ** 2)))
+    T = W.pad_tensors(T2, L, L, 2, D, noise=1e-3 * rms, seed=seed)
+    info = {"recipe": f"{L}x{L} D=2 PEPS after {steps} steps of vp_optimize (256 chains, 2+4 sweeps per step), "
+                      f"zero-padded to D={D}, plus 1e-3 x rms noise", "d2_e_site_first_step": float(e[0]),
+            "d2_e_site_last_steps": float(e[-5:].mean()), "seconds": time.perf_counter() - t0}
+    return torch.tensor(T, dtype=torch.float64, device=dev), info
+
+
 class Path:
     """One lattice context, its output buffers and the sweep loop of one path."""
 
-    def __init__(self, B, torch, Ly, Lx, D, Dc, prec, nch, seed=9359):
+    def __init__(self, B, torch, Ly, Lx, D, Dc, prec, nch, seed=9359, compress=0, fit_sweeps=0, T=None):
         self.B, self.torch = B, torch
         self.Ly, self.Lx, self.N = Ly, Lx, Ly * Lx
         self.prec, self.nch = prec, nch
         self.dev = torch.device("cuda:0")
-        self.ctx = B.Context(B.lattice(Ly, Lx, D, Dc, 1.0, 0.0, prec, nch), seed=seed)
-        self.ctx.vp_init_tensors(0, seed=1908, scale=0.0, perturb=0.0)
+        self.ctx = B.Context(B.lattice(Ly, Lx, D, Dc, 1.0, 0.0, prec, nch, compress, fit_sweeps), seed=seed)
+        set_tensors(self.ctx, T)
         self.ctx.vp_init_chains(0, None)
         dt = torch.float32 if prec == B.VP_FP32 else torch.float64
         self.lp = torch.empty(nch, dtype=torch.float64, device=self.dev)
@@ -294,13 +339,14 @@ def split_run(B, torch, Ly, Lx, D, Dc1, Dc2, nch, warmup, steps, seed=9359):
             "samples_per_s": nch * steps / dt, "ms_per_step": dt / steps * 1e3, "e_site_mean": e}
 
 
-def fp64_reference(B, torch, Ly, Lx, D, Dc, spins, e_loc, n):
-    """The first n of a path's measured configurations re-evaluated in float64 (vp_eval, untimed):
-    the bias of the path's E_loc / N against the float64 evaluation of the same configurations."""
+def fp64_reference(B, torch, Ly, Lx, D, Dc, spins, e_loc, n, compress=0, fit_sweeps=0, T=None):
+    """The first n of a path's measured configurations re-evaluated in float64 (vp_eval, untimed,
+    same truncation): the bias of the path's E_loc / N against the float64 evaluation of the same
+    configurations."""
     import numpy as np
     dev = torch.device("cuda:0")
-    ctx = B.Context(B.lattice(Ly, Lx, D, Dc, 1.0, 0.0, B.VP_FP64, n), seed=1)
-    ctx.vp_init_tensors(0, seed=1908, scale=0.0, perturb=0.0)  # the paths' tensors (same seed, lattice 0)
+    ctx = B.Context(B.lattice(Ly, Lx, D, Dc, 1.0, 0.0, B.VP_FP64, n, compress, fit_sweeps), seed=1)
+    set_tensors(ctx, T)  # the paths' tensors
     lp = torch.empty(n, dtype=torch.float64, device=dev)
     sg = torch.empty(n, dtype=torch.int8, device=dev)
     el = torch.empty(n, dtype=torch.float64, device=dev)
@@ -312,7 +358,7 @@ def fp64_reference(B, torch, Ly, Lx, D, Dc, spins, e_loc, n):
             "mean_abs_e_site": float(np.abs(d).mean()), "max_abs_e_site": float(np.abs(d).max())}
 
 
-def bf16_decisions(B, torch, Ly, Lx, D, Dc, starts, seed=4242):
+def bf16_decisions(B, torch, Ly, Lx, D, Dc, starts, seed=4242, compress=0, fit_sweeps=0, T=None):
     """One traced pair sweep from the same starts in float64 and with bf16-operand sampling
     steps, same seed: along each chain, until the first decision that differs (after which
     the configurations differ), the bf16 ratio's relative error against the float64 ratio of
@@ -323,8 +369,8 @@ def bf16_decisions(B, torch, Ly, Lx, D, Dc, starts, seed=4242):
     nb = Ly * (Lx - 1) + (Ly - 1) * Lx
     tr = {}
     for prec in (B.VP_FP64, B.VP_BF16):
-        ctx = B.Context(B.lattice(Ly, Lx, D, Dc, 1.0, 0.0, prec, n), seed=seed)
-        ctx.vp_init_tensors(0, seed=1908, scale=0.0, perturb=0.0)
+        ctx = B.Context(B.lattice(Ly, Lx, D, Dc, 1.0, 0.0, prec, n, compress, fit_sweeps), seed=seed)
+        set_tensors(ctx, T)
         ctx.vp_init_chains(0, starts.contiguous())
         t = torch.full((n, nb, 2), -1.0, dtype=torch.float64, device=dev)
         ctx.vp_trace_ratios(0, t)
@@ -361,14 +407,17 @@ def fixed_de(plain, learned):
     """Time ratio plain / learned at the accuracy the plain path reached in its timed run.
 
     Per path: stderr^2 = v 2 tau / (rate t) (v: E_loc/N variance per sample, tau: its
-    integrated autocorrelation time in sweeps), and dE^2 = stderr^2 + bias^2 with bias the
-    path's E/N bias against float64.  Target dE = the plain path's dE after its timed
+    integrated autocorrelation time in sweeps), and dE^2 = stderr^2 + bias^2 with bias^2 the
+    squared E/N bias against float64 less the variance of that estimate (floored at 0).  Target dE = the plain path's dE after its timed
     seconds; the learned path needs t = v 2 tau / (rate (dE^2 - bias^2)) to reach it.
     Also given: the same ratio without the bias terms, and with neither bias nor variance
     (2 tau / rate only; both paths sample |Psi|^2 of the same tensors)."""
     def parts(r):
-        st = r["stats"]["e_site"]
-        return st["var_per_sample"], st["tau_int_mean"], r["samples_per_s"], r["fp64_reference"]["bias_e_site"]
+        # the squared bias less the variance of its estimate (floored at 0): the mean of a few
+        # hundred heavy-tailed differences carries its own noise
+        st, ref = r["stats"]["e_site"], r["fp64_reference"]
+        b2 = max(ref["bias_e_site"] ** 2 - ref["bias_stderr"] ** 2, 0.0)
+        return st["var_per_sample"], st["tau_int_mean"], r["samples_per_s"], b2 ** 0.5
     vp, tp, rp, bp = parts(plain)
     vl, tl, rl, bl = parts(learned)
     t_plain = plain["seconds"]
@@ -410,6 +459,16 @@ def main():
     ap.add_argument("--split-dc2", type=int, default=0,
                     help="also time two-cutoff sampling (Dc1 = --Dc, Dc2 = this) on the --L, --D lattice")
     ap.add_argument("--only", choices=["both", "plain", "learned"], default="both")
+    ap.add_argument("--compress", choices=["canonical", "variational"], default="canonical",
+                    help="boundary truncation: canonical SVD compression or the variational fit (App. B)")
+    ap.add_argument("--fit-sweeps", type=int, default=2, help="sweeps of the variational fit")
+    ap.add_argument("--corr-chains", type=int, default=512,
+                    help="chains of the correlated stand-in workload (0: skip it)")
+    ap.add_argument("--corr-burn", type=int, default=20,
+                    help="untimed sweeps from the chain starts before the correlated workload's timed region")
+    ap.add_argument("--also-fit", type=int, default=2,
+                    help="with the canonical compression, also time both paths with the variational fit of "
+                         "this many sweeps for min(steps, 5) steps (0: skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 1 GiB device to device three times (calibrates HBM byte counters)")
@@ -438,15 +497,21 @@ def main():
 
     Ly = Lx = args.L
     D, Dc, nch = args.D, args.Dc, args.chains
+    cm = B.VP_COMPRESS_VARIATIONAL if args.compress == "variational" else B.VP_COMPRESS_CANONICAL
+    fs = args.fit_sweeps if args.compress == "variational" else 0
+    trunc = dict(compress=cm, fit_sweeps=fs)
     res = {}
     if args.only in ("both", "plain"):
-        p = Path(B, torch, Ly, Lx, D, Dc, B.VP_FP32, nch)
+        p = Path(B, torch, Ly, Lx, D, Dc, B.VP_FP32, nch, **trunc)
         r = p.timed(args.warmup, args.steps)
         print(f"plain: {r['samples_per_s']:.1f} samples/s", file=sys.stderr, flush=True)
-        fl = phase_flops(Ly, Lx, D, Dc, nch, r["launches"], r["anti_h"], r["anti_v"])
-        r["roofline"] = roofline(r["ms"], r["launches"], fl, ("compress_up", "compress_down"), "plain")
+        fl = phase_flops(Ly, Lx, D, Dc, nch, r["launches"], r["anti_h"], r["anti_v"],
+                         fs if cm == B.VP_COMPRESS_VARIATIONAL else None)
+        # the canonical compression runs in float64 in every precision, the fit in the working one
+        r["roofline"] = roofline(r["ms"], r["launches"], fl,
+                                 ("compress_up", "compress_down") if cm == B.VP_COMPRESS_CANONICAL else (), "plain")
         r["stats"] = p.series_stats()
-        r["fp64_reference"] = fp64_reference(B, torch, Ly, Lx, D, Dc, p.last_spins, p.el, nch)
+        r["fp64_reference"] = fp64_reference(B, torch, Ly, Lx, D, Dc, p.last_spins, p.el, nch, **trunc)
         print(f"plain: E/N bias against float64 {r['fp64_reference']['bias_e_site']:.3e} "
               f"(mean |dE|/N {r['fp64_reference']['mean_abs_e_site']:.3e})", file=sys.stderr, flush=True)
         if args.tau_sweeps:
@@ -456,18 +521,19 @@ def main():
         torch.cuda.empty_cache()
         res["plain"] = r
     if args.only in ("both", "learned"):
-        p = Path(B, torch, Ly, Lx, D, Dc, B.VP_BF16, nch)
+        p = Path(B, torch, Ly, Lx, D, Dc, B.VP_BF16, nch, **trunc)
         tr = p.train_proposal(args.train_sweeps, args.train_epochs, 256, 3e-3)
         print(f"learned: trained in {tr['seconds']:.1f} s", file=sys.stderr, flush=True)
         r = p.timed(args.warmup, args.steps)
         print(f"learned: {r['samples_per_s']:.1f} samples/s", file=sys.stderr, flush=True)
         r["training"] = tr
-        fl = phase_flops(Ly, Lx, D, Dc, nch, r["launches"], r["anti_h"], r["anti_v"])
+        fl = phase_flops(Ly, Lx, D, Dc, nch, r["launches"], r["anti_h"], r["anti_v"],
+                         fs if cm == B.VP_COMPRESS_VARIATIONAL else None)
         r["roofline"] = roofline(r["ms"], r["launches"], fl, ("compress_up", "compress_down", "measure3", "measure4"),
                                  "learned")
         r["stats"] = p.series_stats()
-        r["fp64_reference"] = fp64_reference(B, torch, Ly, Lx, D, Dc, p.last_spins, p.el, nch)
-        r["bf16_sampling"] = bf16_decisions(B, torch, Ly, Lx, D, Dc, p.last_spins[:min(64, nch)])
+        r["fp64_reference"] = fp64_reference(B, torch, Ly, Lx, D, Dc, p.last_spins, p.el, nch, **trunc)
+        r["bf16_sampling"] = bf16_decisions(B, torch, Ly, Lx, D, Dc, p.last_spins[:min(64, nch)], **trunc)
         print(f"learned: bf16 ratios rel err median {r['bf16_sampling']['vertical_rel_err_median']:.3e}, decisions differing "
               f"{r['bf16_sampling']['decisions_differing_per_proposal']:.4f}", file=sys.stderr, flush=True)
         if args.tau_sweeps:
@@ -485,8 +551,9 @@ def main():
                                + ("learned plaquette moves + pair sweeps, bf16-operand 2-row steps in the "
                                   "sampling pass, "
                                   "fp64 measurement" if is_learned else "plain pair sweeps, fp32 contractions")
-                               + " / fp64 compression",
-                   "Ly": Ly, "Lx": Lx, "D": D, "Dc": Dc, "chains": nch, "J2": 0.0,
+                               + (" / fp64 canonical compression" if cm == B.VP_COMPRESS_CANONICAL else
+                                  f" / variational boundary fit, {fs} sweeps"),
+                   "Ly": Ly, "Lx": Lx, "D": D, "Dc": Dc, "chains": nch, "J2": 0.0, "compress": args.compress,
                    "parallelism": "chains (1 GPU)"},
         "roofline": head["roofline"],
         "phase_ms_per_step": {k: v / args.steps for k, v in head["ms"].items()},
@@ -512,6 +579,59 @@ def main():
             def cost(t):
                 return 2.0 * t["tau_int_mean"] / t["samples_per_s"]
             out["learned_over_plain_at_fixed_dE_long_run"] = cost(res["plain"]["tau"]) / cost(res["learned"]["tau"])
+    if args.corr_chains and args.compress == "canonical" and args.only == "both":
+        Tc, info = correlated_tensors(B, torch, Ly, D)
+        print(f"correlated workload: D=2 optimisation {info['d2_e_site_first_step']:.4f} -> "
+              f"{info['d2_e_site_last_steps']:.4f} per site in {info['seconds']:.1f} s", file=sys.stderr, flush=True)
+        cres = {}
+        nc = args.corr_chains
+        for name, prec in (("plain", B.VP_FP32), ("learned", B.VP_BF16)):
+            p = Path(B, torch, Ly, Lx, D, Dc, prec, nc, T=Tc)
+            # equilibrate from the random starts before anything is trained or timed
+            for _ in range(args.corr_burn):
+                p.sweep()
+            if name == "learned":
+                p.train_proposal(args.train_sweeps, args.train_epochs, 256, 3e-3)
+            r = p.timed(args.warmup, args.steps)
+            r["stats"] = p.series_stats()
+            r["fp64_reference"] = fp64_reference(B, torch, Ly, Lx, D, Dc, p.last_spins, p.el, nc, T=Tc)
+            print(f"correlated {name}: {r['samples_per_s']:.1f} samples/s, tau_int(E) "
+                  f"{r['stats']['e_site']['tau_int_mean']:.3f}, tau_int(Mz^2) {r['stats']['mz2']['tau_int_mean']:.3f}, "
+                  f"E/N {r['stats']['e_site']['mean']:.5f} +- {r['stats']['e_site']['stderr']:.5f}",
+                  file=sys.stderr, flush=True)
+            cres[name] = {k: r[k] for k in ("samples_per_s", "ms_per_step", "seconds", "pair_accept",
+                                             "plaquette_accept", "plaquette_proposed_per_sweep", "stats",
+                                             "fp64_reference")}
+            p.close()
+            del p
+            torch.cuda.empty_cache()
+        fd = fixed_de(cres["plain"], cres["learned"])
+        ep, el_ = cres["plain"]["stats"]["e_site"], cres["learned"]["stats"]["e_site"]
+        out["correlated"] = {"workload": info, "chains": nc, **cres, "fixed_dE": fd,
+                             "learned_over_plain_at_fixed_dE": fd["ratio"],
+                             "energies_agree_sigma": abs(ep["mean"] - el_["mean"]) /
+                             max((ep["stderr"] ** 2 + el_["stderr"] ** 2) ** 0.5, 1e-300)}
+        del Tc
+        torch.cuda.empty_cache()
+    if args.also_fit and args.compress == "canonical":
+        fit = {}
+        ft = dict(compress=B.VP_COMPRESS_VARIATIONAL, fit_sweeps=args.also_fit)
+        fsteps = min(args.steps, 5)
+        for name, prec in (("plain", B.VP_FP32), ("learned", B.VP_BF16)):
+            if args.only not in ("both", name):
+                continue
+            p = Path(B, torch, Ly, Lx, D, Dc, prec, nch, **ft)
+            if name == "learned":
+                p.train_proposal(args.train_sweeps, args.train_epochs, 256, 3e-3)
+            r = p.timed(min(args.warmup, 2), fsteps)
+            fit[name] = {"samples_per_s": r["samples_per_s"], "ms_per_step": r["ms_per_step"], "steps": fsteps,
+                         "phase_ms_per_step": {k: v / fsteps for k, v in r["ms"].items()}}
+            print(f"{name} with the variational fit ({args.also_fit} sweeps): {r['samples_per_s']:.1f} samples/s",
+                  file=sys.stderr, flush=True)
+            p.close()
+            del p
+            torch.cuda.empty_cache()
+        out["variational_fit"] = dict(fit_sweeps=args.also_fit, **fit)
     if args.split_dc2:
         out["split_cutoffs"] = split_run(B, torch, Ly, Lx, D, Dc, args.split_dc2, nch, args.warmup, args.steps)
     if cpu is not None:
