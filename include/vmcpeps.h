@@ -103,7 +103,10 @@ typedef enum { VP_SAMPLER_PAIR_SEQ = 0, VP_SAMPLER_LEARNED_PLAQ = 1 } vp_sampler
  * product sites (right-orthonormal form, state kept), then per sweep each site
  * replaced by the Q of the optimal site's QR (left to right) and by the
  * orthonormal rows of its LQ (right to left); the optimal site 0 carries the
- * norm.  Both use the same bond dimensions.  The persistent schedule
+ * norm.  Both use the same bond dimensions.  Sizes: D <= 16 and Dc <= 64;
+ * D*Dc <= 128 for the canonical compression (its eigenproblems), D*Dc <= 192
+ * for the fit (Dc = 3D at D = 8, the measuring cutoff of Sec. II.A and App. D).
+ * The persistent schedule
  * (VP_SCHED_PERSISTENT, vp_sample_batch) runs the canonical compression only:
  * with VP_COMPRESS_VARIATIONAL it returns VP_ERR_UNSUPPORTED, and vp_autotune
  * skips it (its time reads -1). */

@@ -243,12 +243,17 @@ vp_status check_lattice(vp_ctx* ctx, const vp_lattice& p) {
   if ((p.Ly * p.Lx) % 2)
     return fail(ctx, VP_ERR_SHAPE, "the S^z_tot = 0 sector needs an even number of sites");
   if (p.Ly * p.Lx > 4096) return fail(ctx, VP_ERR_SHAPE, "at most 4096 sites");
-  if (p.D > 16 || p.Dc > 64 || p.D * p.Dc > 128)
-    return fail(ctx, VP_ERR_SHAPE, "sizes beyond the built kernels (D <= 16, Dc <= 64, D*Dc <= 128)");
   if (p.prec != VP_FP64 && p.prec != VP_FP32 && p.prec != VP_BF16)
     return fail(ctx, VP_ERR_ARG, "unknown precision %d", p.prec);
   if (p.compress != VP_COMPRESS_CANONICAL && p.compress != VP_COMPRESS_VARIATIONAL)
     return fail(ctx, VP_ERR_ARG, "unknown truncation mode %d", p.compress);
+  // the canonical compression's eigenproblems have order up to D*Dc (at most
+  // 128 in registers); the fit has none, and its QRs take up to 64 columns
+  if (p.D > 16 || p.Dc > 64) return fail(ctx, VP_ERR_SHAPE, "sizes beyond the built kernels (D <= 16, Dc <= 64)");
+  if (p.compress == VP_COMPRESS_CANONICAL && p.D * p.Dc > 128)
+    return fail(ctx, VP_ERR_SHAPE, "the canonical compression needs D*Dc <= 128");
+  if (p.compress == VP_COMPRESS_VARIATIONAL && p.D * p.Dc > 192)
+    return fail(ctx, VP_ERR_SHAPE, "the variational fit needs D*Dc <= 192");
   if (p.fit_sweeps < 0 || p.fit_sweeps > 64) return fail(ctx, VP_ERR_ARG, "fit_sweeps must be 0..64");
   return VP_OK;
 }

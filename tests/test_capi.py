@@ -57,6 +57,19 @@ def test_create_rejects_bad_shapes_before_touching_the_device(bad):
     assert ei.value.status == (binding.VP_ERR_ARG if "prec" in bad else binding.VP_ERR_SHAPE)
 
 
+@pytest.mark.parametrize("D,Dc,compress,sweeps,status", [
+    (8, 24, 0, 0, "VP_ERR_SHAPE"),   # the canonical compression's eigenproblems stop at D*Dc = 128
+    (8, 32, 1, 2, "VP_ERR_SHAPE"),   # the fit stops at D*Dc = 192
+    (8, 16, 2, 0, "VP_ERR_ARG"),     # unknown truncation mode
+    (8, 16, 1, 65, "VP_ERR_ARG"),    # fit sweeps beyond 64
+])
+def test_create_checks_truncation_limits(D, Dc, compress, sweeps, status):
+    from paper_1908_09359_amd import binding
+    with pytest.raises(binding.VPError) as ei:
+        binding.Context(binding.vp_lattice(4, 4, D, Dc, 1.0, 0.0, binding.VP_FP64, 1, compress, sweeps))
+    assert ei.value.status == getattr(binding, status)
+
+
 def test_workload_inputs_are_seeded():
     import numpy as np
     from paper_1908_09359_amd import workloads

@@ -4,7 +4,9 @@ their states measured at Dc2.
 The oracle side composes two pinned oracle functions: its chain at Dc1 (the
 decisions, hence the configurations, are the sampler's) and its fixed-
 configuration evaluation at Dc2.  float64: configurations bit-exact, E_loc,
-log|Psi| and dlnPsi to rounding.
+log|Psi| and dlnPsi to rounding.  The paper's production shape (D=8,
+Dc1 = 2D = 16, Dc2 = 3D = 24) is measured with the variational fit (App. B),
+the compression the paper itself uses; the canonical one stops at D*Dc = 128.
 """
 import numpy as np
 import pytest
@@ -21,16 +23,19 @@ def _B():
     return B
 
 
-@pytest.mark.parametrize("Ly,Lx,D,Dc1,Dc2,J2", [(4, 4, 3, 4, 9, 0.0), (4, 6, 4, 8, 12, 0.5)])
-def test_split_cutoffs_match_oracle(Ly, Lx, D, Dc1, Dc2, J2):
+@pytest.mark.parametrize("Ly,Lx,D,Dc1,Dc2,J2,fit2", [(4, 4, 3, 4, 9, 0.0, 0), (4, 6, 4, 8, 12, 0.5, 0),
+                                                     (4, 6, 8, 16, 24, 0.5, 2)])
+def test_split_cutoffs_match_oracle(Ly, Lx, D, Dc1, Dc2, J2, fit2):
     import torch
     B = _B()
-    print(f"split {Ly}x{Lx} D={D} Dc1={Dc1} Dc2={Dc2} J2={J2}", flush=True)
+    print(f"split {Ly}x{Lx} D={D} Dc1={Dc1} Dc2={Dc2} J2={J2} "
+          f"{'fit ' + str(fit2) + ' sweeps' if fit2 else 'canonical'} at Dc2", flush=True)
     n, nb, nm, seed = 3, 1, 2, 31
     N = Ly * Lx
     T = W.random_tensors(Ly, Lx, D, seed=70 + D)
     ctx = B.Context([B.lattice(Ly, Lx, D, Dc1, 1.0, J2, B.VP_FP64, n),
-                     B.lattice(Ly, Lx, D, Dc2, 1.0, J2, B.VP_FP64, n)], seed=seed)
+                     B.lattice(Ly, Lx, D, Dc2, 1.0, J2, B.VP_FP64, n,
+                               B.VP_COMPRESS_VARIATIONAL if fit2 else B.VP_COMPRESS_CANONICAL, fit2)], seed=seed)
     dev = torch.device("cuda")
     tt = torch.tensor(T, dtype=torch.float64, device=dev)
     ctx.vp_set_tensors(0, tt)
@@ -48,7 +53,8 @@ def test_split_cutoffs_match_oracle(Ly, Lx, D, Dc1, Dc2, J2):
              so=so.cpu().numpy().reshape(n, nm, N))
     ctx.close()
     lat1 = olat.Lattice(Ly, Lx, D, Dc1, J2=J2)
-    lat2 = olat.Lattice(Ly, Lx, D, Dc2, J2=J2)
+    lat2 = (olat.Lattice(Ly, Lx, D, Dc2, J2=J2, compress_mode="variational", fit_sweeps=fit2) if fit2
+            else olat.Lattice(Ly, Lx, D, Dc2, J2=J2))
     differs = 0.0
     for c in range(n):
         ch = vmc.Chain(lat1, olat.neel_shuffled(lat1, seed, 0, c), seed, 0, c)

@@ -46,6 +46,7 @@ def _compare(g, o, N, tol_e, tol_lp, tol_rel):
     (6, 6, 4, 8, 0.5, 2),     # fused 3-line steps, D=4 Dc=8
     (6, 6, 8, 16, 0.0, 2),    # fused 3-line steps, D=8 Dc=16, truncated rows
     (4, 6, 6, 12, 0.5, 3),
+    (4, 6, 8, 24, 0.5, 2),    # Dc = 3D at D=8: generic steps, the work-group QR (up to 192 x 24)
 ])
 def test_fit_fp64_parity(Ly, Lx, D, Dc, J2, sweeps):
     B = _B()
@@ -69,7 +70,7 @@ def test_fit_at_full_rank_equals_canonical():
     assert np.max(np.abs(g["log_abs_psi"] - c["log_abs_psi"])) <= 1e-12
 
 
-@pytest.mark.parametrize("Ly,Lx,D,Dc", [(6, 6, 4, 8), (4, 6, 8, 16)])
+@pytest.mark.parametrize("Ly,Lx,D,Dc", [(6, 6, 4, 8), (4, 6, 8, 16), (4, 6, 8, 24)])
 def test_fit_fp32_parity(Ly, Lx, D, Dc):
     B = _B()
     print(f"fit fp32 {Ly}x{Lx} D={D} Dc={Dc}", flush=True)
