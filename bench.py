@@ -46,12 +46,14 @@ PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15, "hbm": 8.0e12}
 # what the same counter reads for a device-to-device copy of known size.  They
 # describe the kernel sources whose digest is `src`; for any other sources the
 # benchmark reports no traffic.
-TRAFFIC = {"src": "659b82e251e111ff",
+TRAFFIC = {"src": "ac0e3a765e9b6d32",
            "bytes_per_launch": {
-               # k_compress<double, 8, 16> (both directions): 1.88e+07 KiB fetched x 2.0, 1.819e+07 KiB written
-               "learned": {"compress_up": 5.7142e+10, "compress_down": 5.7142e+10, "measure4": 4.8126e+10},
-               # k_compress<float, 8, 16>: 1.841e+07 KiB fetched x 2.0, 1.799e+07 KiB written
-               "plain": {"compress_up": 5.6121e+10, "compress_down": 5.6121e+10, "measure4": 1.8341e+10}}}
+               # k_compress<double, 8, 16> (both directions): 1.882e+07 KiB fetched x 2.0, 1.817e+07 KiB written
+               "learned": {"compress_up": 5.716e+10, "compress_down": 5.716e+10, "measure4": 4.625e+10,
+                           "vsweep": 4.832e+10},
+               # k_compress<float, 8, 16>: 1.851e+07 KiB fetched x 2.0, 1.797e+07 KiB written
+               "plain": {"compress_up": 5.631e+10, "compress_down": 5.631e+10, "measure4": 1.834e+10,
+                         "vsweep": 1.251e+10}}}
 
 
 def kernel_source_digest():
@@ -273,12 +275,13 @@ class Path:
         stag = ((-1.0) ** (yy + xx)).to(torch.float64)
         mz = ((0.5 - g) * stag).sum(dim=(2, 3)) / self.N                   # [steps][chains]
         m2 = (mz * mz).t().contiguous().cpu().numpy()
-        out = {}
+        out = {"series_length": int(x.shape[1])}
+        if x.shape[1] < 2:  # one timed sweep: no series to analyse
+            return None
         for name, v in (("e_site", x), ("mz2", m2)):
             tau, mean, err = self.B.vp_stats_tau(v, 5.0)
             out[name] = {"tau_int_mean": float(np.mean(tau)), "mean": mean, "stderr": err,
                          "var_per_sample": float(np.mean(np.var(v, axis=1, ddof=1)))}
-        out["series_length"] = int(x.shape[1])
         return out
 
     def tau_run(self, sweeps):
@@ -412,6 +415,10 @@ def fixed_de(plain, learned):
     seconds; the learned path needs t = v 2 tau / (rate (dE^2 - bias^2)) to reach it.
     Also given: the same ratio without the bias terms, and with neither bias nor variance
     (2 tau / rate only; both paths sample |Psi|^2 of the same tensors)."""
+    if plain["stats"] is None or learned["stats"] is None:
+        return {"ratio": None, "ratio_without_bias": None, "ratio_tau_and_rate_only": None,
+                "reason": "one timed sweep per chain: no series"}
+
     def parts(r):
         # the squared bias less the variance of its estimate (floored at 0): the mean of a few
         # hundred heavy-tailed differences carries its own noise
@@ -420,6 +427,11 @@ def fixed_de(plain, learned):
         return st["var_per_sample"], st["tau_int_mean"], r["samples_per_s"], b2 ** 0.5
     vp, tp, rp, bp = parts(plain)
     vl, tl, rl, bl = parts(learned)
+    if min(vp, tp, vl, tl) <= 0.0:
+        # a few sweeps per chain: the windowed tau_int estimate can come out at or below zero
+        return {"ratio": None, "ratio_without_bias": None, "ratio_tau_and_rate_only": None,
+                "reason": f"tau_int or variance not positive (tau {tp:.3g} / {tl:.3g}, var {vp:.3g} / {vl:.3g}): "
+                          "too few timed sweeps per chain"}
     t_plain = plain["seconds"]
     se2 = vp * 2 * tp / (rp * t_plain)
     de2 = se2 + bp * bp
@@ -579,7 +591,7 @@ def main():
             def cost(t):
                 return 2.0 * t["tau_int_mean"] / t["samples_per_s"]
             out["learned_over_plain_at_fixed_dE_long_run"] = cost(res["plain"]["tau"]) / cost(res["learned"]["tau"])
-    if args.corr_chains and args.compress == "canonical" and args.only == "both":
+    if args.corr_chains and args.compress == "canonical" and args.only == "both" and args.steps >= 2:
         Tc, info = correlated_tensors(B, torch, Ly, D)
         print(f"correlated workload: D=2 optimisation {info['d2_e_site_first_step']:.4f} -> "
               f"{info['d2_e_site_last_steps']:.4f} per site in {info['seconds']:.1f} s", file=sys.stderr, flush=True)
