@@ -1,0 +1,219 @@
+"""Simple-update imaginary-time evolution (App. A), nearest-neighbour terms:
+test infrastructure only (tests/, never the product path).
+
+The PEPS is held as site tensors B_k (same layout as the parameter vector:
+B_k[s][l, u, r, d]) and a diagonal matrix lambda on every link between
+nearest neighbours (App. A: the environment of a tensor approximated by these
+diagonal matrices).  A step applies exp(-dt J S_i.S_j) once to every
+nearest-neighbour link; each application (App. A, Fig. 7 (b)-(h), here with
+two sites instead of three):
+
+1. the lambdas of the outer links are contracted into both site tensors;
+2. QR of the first (outer legs x (s, bond)) and of the second tensor gives
+   Q_A R_A and Q_B R_B (the reduced tensors R carry the physical and bond legs);
+3. Theta = R_A lambda_bond R_B^T with the gate applied to the two physical legs;
+4. SVD of Theta (rows (a, s_A), columns (s_B, b)), truncated to the link's
+   dimension: the kept singular values, normalised, are the new lambda;
+5. the new tensors are Q_A U and Q_B V with the outer lambdas divided out.
+
+Readings (the paper is silent on these): the gate is the exact exponential of
+the bond term; a step visits the links in four classes - horizontal links with
+x even, horizontal with x odd, vertical with y even, vertical with y odd - and
+links of one class share no site, so their updates commute exactly; the new
+lambda is normalised to unit 2-norm; singular values below 1e-6 times the
+largest are dropped (lambda 0, their vectors 0), and dividing by a lambda
+means multiplying by 1/lambda where lambda > 0 and by 0 elsewhere; the start
+is the given tensors with every lambda 1; the result absorbs lambda^(1/2)
+into each of the two tensors of every link (App. A's last step).  The
+convergence measure is App. A's: the mean over links of
+||lambda(t+dt) - lambda(t)|| / ||lambda(t)|| over one step.
+
+Pinned (tests/test_oracle_simple_update.py): the QR-reduced update equals the
+update written out on the full two-site tensor (step 2 left out); without
+truncation on open chains the result is the dense Trotter product of the same
+gates applied to the start; one link converges to the singlet (-3/4); the gate
+is the matrix exponential of the bond term.
+"""
+import numpy as np
+
+DROP = 1e-6  # relative singular-value floor of step 4
+
+
+def heisenberg_gate(dt, J):
+    """exp(-dt J S_A.S_B) as G[t_A, t_B, s_A, s_B] (s = 0 is S^z = +1/2).
+
+    S_A.S_B is 1/4 on the triplet and -3/4 on the singlet (ud - du)/sqrt(2)."""
+    a = np.exp(-0.25 * dt * J)
+    b = np.exp(0.75 * dt * J)
+    G = np.zeros((2, 2, 2, 2))
+    G[0, 0, 0, 0] = G[1, 1, 1, 1] = a
+    G[0, 1, 0, 1] = G[1, 0, 1, 0] = 0.5 * (a + b)
+    G[0, 1, 1, 0] = G[1, 0, 0, 1] = 0.5 * (a - b)
+    return G
+
+
+def link_index(lat, y, x, horizontal):
+    """Horizontal links (y,x)-(y,x+1) first, row-major; then vertical (y,x)-(y+1,x)."""
+    if horizontal:
+        return y * (lat.Lx - 1) + x
+    return lat.Ly * (lat.Lx - 1) + y * lat.Lx + x
+
+
+def n_links(lat):
+    return lat.Ly * (lat.Lx - 1) + (lat.Ly - 1) * lat.Lx
+
+
+def leg_links(lat, y, x):
+    """Link index of legs (l, u, r, d) of site (y, x); None on the open boundary."""
+    return (link_index(lat, y, x - 1, True) if x > 0 else None,
+            link_index(lat, y - 1, x, False) if y > 0 else None,
+            link_index(lat, y, x, True) if x < lat.Lx - 1 else None,
+            link_index(lat, y, x, False) if y < lat.Ly - 1 else None)
+
+
+def link_classes(lat):
+    """The four classes of links, each a list of ((y, x), (y2, x2), leg of A, leg of B)."""
+    out = [[], [], [], []]
+    for y in range(lat.Ly):
+        for x in range(lat.Lx - 1):
+            out[x % 2].append(((y, x), (y, x + 1), 2, 0))
+    for y in range(lat.Ly - 1):
+        for x in range(lat.Lx):
+            out[2 + y % 2].append(((y, x), (y + 1, x), 3, 1))
+    return out
+
+
+def su_init(T, lat):
+    """Site tensors (arrays (2, l, u, r, d)) of the flat parameter vector T and unit lambdas."""
+    B = []
+    for y in range(lat.Ly):
+        for x in range(lat.Lx):
+            dims = lat.dims(y, x)
+            o = lat.offsets[lat.site(y, x)]
+            B.append(np.array(T[o:o + 2 * int(np.prod(dims))], dtype=np.float64).reshape((2,) + dims))
+    lam = [np.ones(lat.D) for _ in range(n_links(lat))]
+    return B, lam
+
+
+def _pinv(v):
+    out = np.zeros_like(v)
+    nz = v > 0.0
+    out[nz] = 1.0 / v[nz]
+    return out
+
+
+def _scale_legs(A, vecs):
+    """A[s, l, u, r, d] times vecs[q] on leg q (None: leave the leg)."""
+    A = A.copy()
+    for q, v in enumerate(vecs):
+        if v is not None:
+            shape = [1] * 5
+            shape[1 + q] = v.shape[0]
+            A = A * v.reshape(shape)
+    return A
+
+
+def _outer_lambdas(lat, lam, y, x, bond_leg, inverse=False):
+    links = leg_links(lat, y, x)
+    return [None if (q == bond_leg or links[q] is None) else (_pinv(lam[links[q]]) if inverse else lam[links[q]])
+            for q in range(4)]
+
+
+def _to_matrix(M, bond_leg):
+    """(outer legs in (l, u, r, d) order) x (s, bond) of M[s, l, u, r, d]."""
+    others = [q for q in range(4) if q != bond_leg]
+    P = np.transpose(M, [1 + q for q in others] + [0, 1 + bond_leg])
+    return P.reshape(-1, 2 * M.shape[1 + bond_leg]), P.shape[:3]
+
+
+def _from_matrix(X, outer_shape, bond_leg, kdim):
+    """Inverse of _to_matrix for X[(outer), (s, k)] with a bond leg of kdim."""
+    others = [q for q in range(4) if q != bond_leg]
+    P = X.reshape(tuple(outer_shape) + (2, kdim))
+    order = [0] * 5
+    # axes of P: others[0], others[1], others[2], s, bond -> target (s, l, u, r, d)
+    src = {1 + others[0]: 0, 1 + others[1]: 1, 1 + others[2]: 2, 0: 3, 1 + bond_leg: 4}
+    for t in range(5):
+        order[t] = src[t]
+    return np.transpose(P, order)
+
+
+def _truncated_svd(Theta, kdim):
+    U, S, Vt = np.linalg.svd(Theta, full_matrices=False)
+    k = int(min(kdim, np.sum(S > DROP * S[0]))) if S[0] > 0 else 0
+    lam_new = np.zeros(kdim)
+    lam_new[:k] = S[:k] / np.linalg.norm(S[:k]) if k else 0.0
+    Uk = np.zeros((U.shape[0], kdim))
+    Vk = np.zeros((kdim, Vt.shape[1]))
+    Uk[:, :k] = U[:, :k]
+    Vk[:k] = Vt[:k]
+    return Uk, lam_new, Vk
+
+
+def su_bond(B, lam, lat, a, b, leg_a, leg_b, G, reduced=True):
+    """Apply the gate G to the link between sites a and b (App. A, Fig. 7), in place.
+
+    reduced=False writes the same update out on the full two-site tensor (no QR),
+    the plain definition the reduced one is checked against."""
+    (ya, xa), (yb, xb) = a, b
+    ka, kb = lat.site(ya, xa), lat.site(yb, xb)
+    link = leg_links(lat, ya, xa)[leg_a]
+    kdim = lam[link].shape[0]
+    MA = _scale_legs(B[ka], _outer_lambdas(lat, lam, ya, xa, leg_a))
+    MB = _scale_legs(B[kb], _outer_lambdas(lat, lam, yb, xb, leg_b))
+    XA, shape_a = _to_matrix(MA, leg_a)
+    XB, shape_b = _to_matrix(MB, leg_b)
+    if reduced:
+        QA, RA = np.linalg.qr(XA, mode='reduced')
+        QB, RB = np.linalg.qr(XB, mode='reduced')
+    else:
+        QA, RA = np.eye(XA.shape[0]), XA
+        QB, RB = np.eye(XB.shape[0]), XB
+    ra, rb = RA.shape[0], RB.shape[0]
+    RA3 = RA.reshape(ra, 2, kdim)
+    RB3 = RB.reshape(rb, 2, kdim)
+    theta = np.einsum('ask,k,btk->asbt', RA3, lam[link], RB3)          # [a, s_A, b, s_B]
+    theta = np.einsum('uvst,asbt->aubv', G, theta)                     # gate on (s_A, s_B)
+    Theta = np.transpose(theta, (0, 1, 3, 2)).reshape(2 * ra, 2 * rb)   # rows (a, t_A), cols (t_B, b)
+    U, lam_new, Vt = _truncated_svd(Theta, kdim)
+    XA_new = (QA @ U.reshape(ra, 2 * kdim)).reshape(-1, 2 * kdim)       # [(outer), (t_A, i)]
+    Vb = np.transpose(Vt.reshape(kdim, 2, rb), (2, 1, 0)).reshape(rb, 2 * kdim)
+    XB_new = QB @ Vb                                                   # [(outer), (t_B, i)]
+    A_new = _from_matrix(XA_new, shape_a, leg_a, kdim)
+    B_new = _from_matrix(XB_new, shape_b, leg_b, kdim)
+    B[ka] = _scale_legs(A_new, _outer_lambdas(lat, lam, ya, xa, leg_a, inverse=True))
+    B[kb] = _scale_legs(B_new, _outer_lambdas(lat, lam, yb, xb, leg_b, inverse=True))
+    lam[link] = lam_new
+
+
+def su_step(B, lam, lat, dt, reduced=True):
+    """One step over every nearest-neighbour link, class by class; returns the
+    mean relative change of the lambdas (App. A's convergence measure)."""
+    if lat.J2 != 0.0:
+        raise ValueError("the simple update here covers nearest-neighbour terms only (J2 = 0)")
+    G = heisenberg_gate(dt, lat.J1)
+    old = [l.copy() for l in lam]
+    for cls in link_classes(lat):
+        for a, b, la, lb in cls:
+            su_bond(B, lam, lat, a, b, la, lb, G, reduced)
+    if not lam:
+        return 0.0
+    return float(np.mean([np.linalg.norm(n - o) / np.linalg.norm(o) for n, o in zip(lam, old)]))
+
+
+def su_absorb(B, lam, lat):
+    """The flat parameter vector with lambda^(1/2) absorbed into both tensors of every link."""
+    out = []
+    for y in range(lat.Ly):
+        for x in range(lat.Lx):
+            links = leg_links(lat, y, x)
+            vecs = [None if l is None else np.sqrt(lam[l]) for l in links]
+            out.append(_scale_legs(B[lat.site(y, x)], vecs).ravel())
+    return np.concatenate(out)
+
+
+def simple_update(T, lat, dt, steps):
+    """`steps` steps from T (unit lambdas); returns (absorbed T, per-step changes, B, lambdas)."""
+    B, lam = su_init(T, lat)
+    changes = [su_step(B, lam, lat, dt) for _ in range(steps)]
+    return su_absorb(B, lam, lat), changes, B, lam

@@ -1,0 +1,142 @@
+"""Pins of the oracle's simple update (App. A; oracle/simple_update.py), CPU only.
+
+* The gate is the matrix exponential of J S_A.S_B (scipy's expm of the
+  Pauli-matrix form).
+* The QR-reduced bond update equals the same update written out on the full
+  two-site tensor (no QR), in the lambdas and in every amplitude of the
+  absorbed state (the bond gauges of the two may differ).
+* Without truncation on open chains (1 x 4 and 4 x 1, D = 4: every cut has rank
+  at most 4) a step is exact: the absorbed state is the dense product of the
+  same gates, in the same order, applied to the start, up to normalisation.
+* On one link the evolution converges to the singlet, E = -3/4.
+* On a 2 x 4 lattice (D = 2, truncated): the energy of the absorbed state falls
+  well below the start's and stays above the exact ground energy (variational),
+  and the convergence measure decreases.
+"""
+import itertools
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import bruteforce as bf
+from oracle import lattice as olat
+from oracle import simple_update as su
+from paper_1908_09359_amd import workloads as W
+
+
+def _bond_hamiltonian():
+    sx = np.array([[0.0, 1.0], [1.0, 0.0]]) / 2
+    sy = np.array([[0.0, -1.0j], [1.0j, 0.0]]) / 2
+    sz = np.array([[1.0, 0.0], [0.0, -1.0]]) / 2
+    return np.real(np.kron(sx, sx) + np.kron(sy, sy) + np.kron(sz, sz))
+
+
+def _dense_state(T, Ly, Lx, D):
+    """All 2^N amplitudes, configuration index = sum s_k 2^(N-1-k)."""
+    N = Ly * Lx
+    cfgs = np.array(list(itertools.product([0, 1], repeat=N)), dtype=np.int8)
+    return bf.amplitudes(T, Ly, Lx, D, cfgs)
+
+
+def _apply_gate(psi, N, i, j, G4):
+    """The 4 x 4 gate on sites i < j of the dense state."""
+    t = psi.reshape([2] * N)
+    t = np.moveaxis(t, [i, j], [0, 1])
+    shp = t.shape
+    t = (G4 @ t.reshape(4, -1)).reshape(shp)
+    return np.moveaxis(t, [0, 1], [i, j]).ravel()
+
+
+def _hpsi(psi, Ly, Lx):
+    """H psi for the nearest-neighbour Heisenberg lattice (J = 1)."""
+    N = Ly * Lx
+    h = _bond_hamiltonian()
+    out = np.zeros_like(psi)
+    for y in range(Ly):
+        for x in range(Lx):
+            k = y * Lx + x
+            if x < Lx - 1:
+                out += _apply_gate(psi, N, k, k + 1, h)
+            if y < Ly - 1:
+                out += _apply_gate(psi, N, k, k + Lx, h)
+    return out
+
+
+def _energy(psi, Ly, Lx):
+    return float(psi @ _hpsi(psi, Ly, Lx) / (psi @ psi))
+
+
+@pytest.mark.parametrize("dt,J", [(0.01, 1.0), (0.3, 1.0), (0.2, 0.5)])
+def test_gate_is_the_exponential_of_the_bond_term(dt, J):
+    G = su.heisenberg_gate(dt, J).reshape(4, 4)
+    assert np.allclose(G, scipy.linalg.expm(-dt * J * _bond_hamiltonian()), atol=1e-15, rtol=1e-14)
+
+
+def test_reduced_update_equals_full_two_site_update():
+    Ly, Lx, D = 3, 4, 3
+    lat = olat.Lattice(Ly, Lx, D, 16)
+    T = W.random_tensors(Ly, Lx, D, seed=91)
+    Br, lr = su.su_init(T, lat)
+    Bf, lf = su.su_init(T, lat)
+    for _ in range(3):
+        cr = su.su_step(Br, lr, lat, 0.05, reduced=True)
+        cf = su.su_step(Bf, lf, lat, 0.05, reduced=False)
+        assert abs(cr - cf) <= 1e-10 * max(1.0, abs(cf))
+    for a, b in zip(lr, lf):
+        assert np.allclose(a, b, atol=1e-11)
+    cfgs = np.array(bf.sz0_configs(Ly * Lx))
+    pr = bf.amplitudes(su.su_absorb(Br, lr, lat), Ly, Lx, D, cfgs)
+    pf = bf.amplitudes(su.su_absorb(Bf, lf, lat), Ly, Lx, D, cfgs)
+    assert np.max(np.abs(pr - pf)) <= 1e-10 * np.max(np.abs(pf))
+
+
+@pytest.mark.parametrize("Ly,Lx", [(1, 4), (4, 1)])
+def test_untruncated_chain_is_the_dense_trotter_product(Ly, Lx):
+    D, dt, steps = 4, 0.1, 2
+    N = Ly * Lx
+    lat = olat.Lattice(Ly, Lx, D, 16)
+    T = W.random_tensors(Ly, Lx, D, seed=17)
+    psi = _dense_state(T, Ly, Lx, D)
+    G4 = su.heisenberg_gate(dt, 1.0).reshape(4, 4)
+    for _ in range(steps):
+        for cls in su.link_classes(lat):
+            for (ya, xa), (yb, xb), _, _ in cls:
+                psi = _apply_gate(psi, N, ya * Lx + xa, yb * Lx + xb, G4)
+    Tsu, changes, _, _ = su.simple_update(T, lat, dt, steps)
+    phi = _dense_state(Tsu, Ly, Lx, D)
+    cos = abs(phi @ psi) / (np.linalg.norm(phi) * np.linalg.norm(psi))
+    assert cos >= 1.0 - 1e-12
+    assert len(changes) == steps and all(c > 0 for c in changes)
+
+
+def test_one_link_converges_to_the_singlet():
+    lat = olat.Lattice(1, 2, 2, 4)
+    T = W.random_tensors(1, 2, 2, seed=3)
+    Tsu, changes, _, lam = su.simple_update(T, lat, 0.2, 120)
+    psi = _dense_state(Tsu, 1, 2, 2)
+    assert abs(_energy(psi, 1, 2) + 0.75) <= 1e-9
+    # the singlet has Schmidt rank 2 with equal weights
+    assert np.allclose(lam[0], [np.sqrt(0.5), np.sqrt(0.5)], atol=1e-9)
+    assert changes[-1] <= 1e-9
+
+
+def test_truncated_evolution_lowers_the_energy_variationally():
+    Ly, Lx, D = 2, 4, 2
+    lat = olat.Lattice(Ly, Lx, D, 16)
+    T = W.random_tensors(Ly, Lx, D, seed=23)
+    e0 = _energy(_dense_state(T, Ly, Lx, D), Ly, Lx)
+    Tsu, changes, _, _ = su.simple_update(T, lat, 0.1, 40)
+    e1 = _energy(_dense_state(Tsu, Ly, Lx, D), Ly, Lx)
+    # exact ground energy of the 2 x 4 open Heisenberg lattice by dense diagonalisation
+    N = Ly * Lx
+    H = np.zeros((2 ** N, 2 ** N))
+    for k in range(2 ** N):
+        e = np.zeros(2 ** N)
+        e[k] = 1.0
+        H[:, k] = _hpsi(e, Ly, Lx)
+    e_exact = np.linalg.eigvalsh(H)[0]
+    assert e1 >= e_exact - 1e-12
+    assert e1 < e0 - 1.0 and e1 < 0.9 * e_exact
+    assert changes[-1] < 0.1 * changes[0]
+
