@@ -54,8 +54,8 @@
  *   caller (for example a torch tensor's data_ptr on the same device);
  *   pointers named *_host are host pointers.  The library owns only its
  *   internal workspace: what the sweeps and vp_eval_sis need is allocated by
- *   vp_create; the workspaces of vp_sr_update, vp_optimize and the proposal
- *   network calls depend on their arguments, are allocated by the first call
+ *   vp_create; the workspaces of vp_sr_update, vp_optimize, vp_simple_update
+ *   and the proposal network calls depend on their arguments, are allocated by the first call
  *   that needs them and kept for later calls (replaced by a larger one when a
  *   call needs more).  vp_destroy frees all of it.
  * Streams: work is enqueued on the hipStream_t given to vp_create (NULL = the
@@ -369,6 +369,35 @@ vp_status vp_sign_sgd_update(vp_ctx* ctx, int32_t lat, const double* grad_dev, d
  * previous step's update. */
 vp_status vp_optimize(vp_ctx* ctx, int32_t lat, int32_t n_steps, int32_t n_burn, int32_t n_meas,
                       const double* delta_host, uint64_t step0, double* e_mean_host);
+
+/* Simple-update imaginary-time evolution (App. A), the initialisation the
+ * paper runs before Algorithm 1, for the nearest-neighbour terms (the lattice
+ * must have J2 = 0, else VP_ERR_UNSUPPORTED).  The PEPS is held as site
+ * tensors and a diagonal lambda (D numbers) on every link; a step applies
+ * exp(-dt J1 S_i.S_j) once to every link, in four classes of links that share
+ * no site (horizontal links with x even, x odd, vertical links with y even,
+ * y odd).  Per link: the outer links' lambdas multiply both tensors, each is
+ * reduced by a thin Householder QR, the gate acts on the reduced two-site
+ * tensor (lambda of the link between), its truncated SVD gives the new
+ * lambda (the leading D singular values above 1e-6 of the largest,
+ * normalised to unit 2-norm) and the new tensors, from which the outer
+ * lambdas are divided out again (App. A, Fig. 7).  The first call on the
+ * current tensors starts from them with every lambda 1; a later call
+ * continues the same evolution (for example with a smaller dt) until
+ * vp_set_tensors, vp_init_tensors, an update or an optimisation changes the
+ * tensors.  On return the lattice's tensors are the evolved PEPS with
+ * lambda^(1/2) absorbed into both tensors of every link, and the sampler's
+ * boundaries are invalidated as by vp_set_tensors.  change_dev [n_steps]
+ * (float64, device, may be NULL) receives App. A's convergence measure per
+ * step: the mean over links of ||lambda(t+dt) - lambda(t)|| / ||lambda(t)||.
+ * Workspace: the tensors and lambdas of the evolution and up to 512 links'
+ * scratch (about 350 KB per link at D = 8), allocated by the first call. */
+vp_status vp_simple_update(vp_ctx* ctx, int32_t lat, double dt, int32_t n_steps, double* change_dev);
+
+/* The lambdas of the simple update of the current tensors, lam_dev
+ * [n_links][D] float64 (device): horizontal links (y,x)-(y,x+1) row-major,
+ * then vertical links (y,x)-(y+1,x) row-major; VP_ERR_ARG when there is none. */
+vp_status vp_simple_update_lambdas(vp_ctx* ctx, int32_t lat, double* lam_dev);
 
 /* Integrated autocorrelation time of each chain's measurement series with
  * Sokal's automatic window (Madras & Sokal, J. Stat. Phys. 50, 1988): rho(t)

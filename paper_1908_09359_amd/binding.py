@@ -29,7 +29,7 @@ EXPORTED = ["vp_create", "vp_destroy", "vp_last_error", "vp_num_params", "vp_wor
             "vp_proposal_num_params", "vp_proposal_set_weights", "vp_proposal_get_weights", "vp_proposal_forward",
             "vp_proposal_forward_noalloc", "vp_proposal_loss_grad", "vp_proposal_train", "vp_set_sampler", "vp_move_counts", "vp_set_schedule",
             "vp_sample_batch", "vp_autotune", "vp_sample_split", "vp_optimize", "vp_set_tile",
-            "vp_autotune_tiles", "vp_eval_sis"]
+            "vp_autotune_tiles", "vp_eval_sis", "vp_simple_update", "vp_simple_update_lambdas"]
 
 PHASES = ["row3_envs", "hsweep", "row4_envs", "vsweep", "compress_up", "compress_down", "measure3",
           "measure4", "other"]
@@ -95,6 +95,8 @@ def _load():
         "vp_sample_batch": ([P, I32, P, I32, I32, P], I32),
         "vp_sample_split": ([P, I32, I32, I32, I32, P, P, P, P, P], I32),
         "vp_optimize": ([P, I32, I32, I32, I32, P, ctypes.c_uint64, P], I32),
+        "vp_simple_update": ([P, I32, D, I32, P], I32),
+        "vp_simple_update_lambdas": ([P, I32, P], I32),
         "vp_autotune": ([P, I32, I32, P, P], I32),
         "vp_set_tile": ([P, I32, I32], I32),
         "vp_autotune_tiles": ([P, I32, I32, P, P], I32),
@@ -271,6 +273,12 @@ class Context:
         e = (ctypes.c_double * len(deltas))()
         self._check(LIB.vp_optimize(self.h, lat, len(deltas), n_burn, n_meas, d, ctypes.c_uint64(step0), e))
         return list(e)
+
+    def vp_simple_update(self, lat, dt, n_steps, change=None):
+        self._check(LIB.vp_simple_update(self.h, lat, float(dt), int(n_steps), _ptr(change)))
+
+    def vp_simple_update_lambdas(self, lat, lam):
+        self._check(LIB.vp_simple_update_lambdas(self.h, lat, _ptr(lam)))
 
     def vp_eval(self, lat, spins, n_cfg, log_abs_psi, sign, e_loc, dlnpsi=None, ratios=None):
         self._check(LIB.vp_eval(self.h, lat, _ptr(spins), n_cfg, _ptr(log_abs_psi), _ptr(sign), _ptr(e_loc),

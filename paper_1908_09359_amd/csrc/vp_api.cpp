@@ -62,6 +62,9 @@ struct Lattice {
   };
   Buf sr_work, sr_flag, opt_lp, opt_el, opt_grad, opt_em, opt_sg, opt_so, opt_dl;
   Buf nw_work, nw_part, nw_cnt, nw_scal, nw_grad, nw_sb, nw_rb, nw_idx;
+  // simple update: site tensors, link lambdas, per-link changes, per-work-group scratch
+  Buf su_B, su_lam, su_change, su_scr;
+  bool su_valid = false;        // su_B / su_lam hold the evolution of the current tensors
   LatDev dev{};
   bool tensors_ready = false;
   bool chains_ready = false;
@@ -689,7 +692,7 @@ vp_status vp_destroy(vp_ctx* ctx) {
       if (q) hipFree(q);
     Lattice::Buf* bufs[] = {&L.sr_work, &L.sr_flag, &L.opt_lp, &L.opt_el, &L.opt_grad, &L.opt_em, &L.opt_sg,
                             &L.opt_so, &L.opt_dl, &L.nw_work, &L.nw_part, &L.nw_cnt, &L.nw_scal, &L.nw_grad,
-                            &L.nw_sb, &L.nw_rb, &L.nw_idx};
+                            &L.nw_sb, &L.nw_rb, &L.nw_idx, &L.su_B, &L.su_lam, &L.su_change, &L.su_scr};
     for (Lattice::Buf* b : bufs)
       if (b->p) hipFree(b->p);
   }
@@ -710,6 +713,7 @@ static vp_status stage_tensors(vp_ctx* ctx, Lattice& L) {
   HIP_TRY(ctx, hipGetLastError());
   L.tensors_ready = true;
   L.lower_valid = false;
+  L.su_valid = false;
   return VP_OK;
 }
 
@@ -718,6 +722,59 @@ vp_status vp_set_tensors(vp_ctx* ctx, int32_t lat, const double* T_dev) {
   if (!L || !T_dev) return fail(ctx, VP_ERR_ARG, "bad lattice index or null tensor pointer");
   HIP_TRY(ctx, hipMemcpyAsync(L->T, T_dev, sizeof(double) * L->Np, hipMemcpyDeviceToDevice, ctx->stream));
   return stage_tensors(ctx, *L);
+}
+
+vp_status vp_simple_update(vp_ctx* ctx, int32_t lat, double dt, int32_t n_steps, double* change_dev) {
+  Lattice* L = get_lat(ctx, lat);
+  if (!L) return fail(ctx, VP_ERR_ARG, "bad lattice index");
+  if (!std::isfinite(dt) || n_steps < 0) return fail(ctx, VP_ERR_ARG, "dt must be finite and n_steps >= 0");
+  if (L->p.J2 != 0.0)
+    return fail(ctx, VP_ERR_UNSUPPORTED, "the simple update covers nearest-neighbour terms only (J2 = 0)");
+  if (!L->tensors_ready) return fail(ctx, VP_ERR_ARG, "tensors must be set first");
+  hipStream_t s = ctx->stream;
+  const int Ly = L->p.Ly, Lx = L->p.Lx, D = L->p.D;
+  const int nl = Ly * (Lx - 1) + (Ly - 1) * Lx;
+  int most = 1;
+  for (int c = 0; c < 4; ++c) most = std::max(most, su_class_links(Ly, Lx, c));
+  const int chunk = std::min(most, 512);  // work-groups (links) per launch
+  if (!(grow(s, L->su_B, sizeof(double) * L->Np) && grow(s, L->su_lam, sizeof(double) * std::max(nl, 1) * D) &&
+        grow(s, L->su_change, sizeof(double) * std::max(nl, 1)) &&
+        grow(s, L->su_scr, sizeof(double) * (size_t)chunk * su_scratch_doubles(D))))
+    return fail(ctx, VP_ERR_OOM, "simple-update workspace");
+  double* B = (double*)L->su_B.p;
+  double* lam = (double*)L->su_lam.p;
+  double* chg = (double*)L->su_change.p;
+  if (!L->su_valid) {  // start: the current tensors, every lambda 1
+    HIP_TRY(ctx, hipMemcpyAsync(B, L->T, sizeof(double) * L->Np, hipMemcpyDeviceToDevice, s));
+    if (nl > 0) launch_su_init(lam, (int64_t)nl * D, s);
+  }
+  for (int step = 0; step < n_steps; ++step) {
+    for (int c = 0; c < 4; ++c) {
+      const int count = su_class_links(Ly, Lx, c);
+      for (int first = 0; first < count; first += chunk)
+        launch_su_class(B, lam, L->d_offs, L->d_dims, Ly, Lx, D, c, first, std::min(chunk, count - first), dt,
+                        L->p.J1, (double*)L->su_scr.p, chg, s);
+    }
+    if (change_dev) launch_su_mean(chg, nl, change_dev + step, s);
+    HIP_TRY(ctx, hipGetLastError());
+  }
+  launch_su_absorb(B, lam, L->d_offs, L->d_dims, Ly, Lx, D, L->T, s);
+  HIP_TRY(ctx, hipGetLastError());
+  vp_status st = stage_tensors(ctx, *L);
+  if (st != VP_OK) return st;
+  L->su_valid = true;  // a later call continues from B and the lambdas
+  return VP_OK;
+}
+
+vp_status vp_simple_update_lambdas(vp_ctx* ctx, int32_t lat, double* lam_dev) {
+  Lattice* L = get_lat(ctx, lat);
+  if (!L || !lam_dev) return fail(ctx, VP_ERR_ARG, "bad lattice index or null pointer");
+  if (!L->su_valid) return fail(ctx, VP_ERR_ARG, "no simple update of the current tensors");
+  const int nl = L->p.Ly * (L->p.Lx - 1) + (L->p.Ly - 1) * L->p.Lx;
+  if (nl > 0)
+    HIP_TRY(ctx, hipMemcpyAsync(lam_dev, L->su_lam.p, sizeof(double) * nl * L->p.D, hipMemcpyDeviceToDevice,
+                                ctx->stream));
+  return VP_OK;
 }
 
 vp_status vp_get_tensors(vp_ctx* ctx, int32_t lat, double* T_dev) {

@@ -147,6 +147,19 @@ void net_gather(const int8_t* spins, const double* ratios, const int32_t* idx, i
                 double* rb, hipStream_t s);
 void net_cast_f64(const float* src, double* dst, hipStream_t s);
 
+// Simple update (vp_su.hip): links per class (0: horizontal x even, 1: x odd,
+// 2: vertical y even, 3: y odd), per-work-group scratch (doubles), lambda <- 1,
+// one launch over links first .. first+count-1 of a class, the mean of the
+// per-link changes, and the absorption of lambda^(1/2) into T.
+int su_class_links(int Ly, int Lx, int cls);
+int64_t su_scratch_doubles(int D);
+void launch_su_init(double* lam, int64_t n, hipStream_t s);
+void launch_su_class(double* B, double* lam, const int64_t* offs, const int32_t* dims, int Ly, int Lx, int D, int cls,
+                     int first, int count, double dt, double J, double* scr, double* change, hipStream_t s);
+void launch_su_mean(const double* change, int n, double* out, hipStream_t s);
+void launch_su_absorb(const double* B, const double* lam, const int64_t* offs, const int32_t* dims, int Ly, int Lx,
+                      int D, double* T, hipStream_t s);
+
 // Spin-inversion symmetrisation: t = reversed s (n bytes); the outputs of S
 // combined in place with those of Sbar into log|Phi|, sign, E_Phi and log w.
 void launch_reverse_spins(const int8_t* s, int8_t* t, int64_t n, hipStream_t st);

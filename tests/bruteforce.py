@@ -93,3 +93,28 @@ def local_energies(T, Ly, Lx, D, J1, J2, configs):
             pf = amplitudes(T, Ly, Lx, D, flipped[anti])
             e[anti] += 0.5 * J * pf / psi[anti]
     return e, psi
+
+
+def sector_energy(psi, configs, Ly, Lx, J1=1.0):
+    """<psi|H|psi> / <psi|psi> for amplitudes psi of every S^z = 0 configuration
+    (rows of ``configs``), H the nearest-neighbour Heisenberg lattice: parallel
+    pairs give J1/4, antiparallel pairs -J1/4 plus J1/2 times the amplitude of
+    the exchanged configuration (found by its bit code)."""
+    configs = np.asarray(configs)
+    N = Ly * Lx
+    codes = (configs.astype(np.int64) << np.arange(N, dtype=np.int64)[::-1]).sum(axis=1)
+    order = np.argsort(codes)
+    sorted_codes = codes[order]
+    num = 0.0
+    for y in range(Ly):
+        for x in range(Lx):
+            k = y * Lx + x
+            for k2 in ([k + 1] if x < Lx - 1 else []) + ([k + Lx] if y < Ly - 1 else []):
+                par = configs[:, k] == configs[:, k2]
+                num += J1 * np.sum(np.where(par, 0.25, -0.25) * psi * psi)
+                anti = ~par
+                partner = codes[anti] ^ ((1 << (N - 1 - k)) | (1 << (N - 1 - k2)))
+                j = order[np.searchsorted(sorted_codes, partner)]
+                num += 0.5 * J1 * np.sum(psi[anti] * psi[j])
+    return float(num / (psi @ psi))
+

@@ -140,3 +140,15 @@ def test_truncated_evolution_lowers_the_energy_variationally():
     assert e1 < e0 - 1.0 and e1 < 0.9 * e_exact
     assert changes[-1] < 0.1 * changes[0]
 
+
+def test_sector_energy_of_the_brute_force_helper():
+    """bruteforce.sector_energy (used by the GPU tests) against the dense energy of
+    the same state projected onto S^z = 0 (H conserves S^z)."""
+    Ly, Lx, D = 2, 4, 2
+    T = W.random_tensors(Ly, Lx, D, seed=29)
+    psi = _dense_state(T, Ly, Lx, D)
+    cfgs = np.array(list(itertools.product([0, 1], repeat=Ly * Lx)), dtype=np.int8)
+    keep = cfgs.sum(axis=1) == Ly * Lx // 2
+    psi0 = np.where(keep, psi, 0.0)
+    assert abs(bf.sector_energy(psi[keep], cfgs[keep], Ly, Lx) - _energy(psi0, Ly, Lx)) <= 1e-12
+
