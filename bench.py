@@ -57,15 +57,24 @@ TRAFFIC = {"src": "ac0e3a765e9b6d32",
 
 
 def kernel_source_digest():
-    """sha256 over the device sources of the library, the .hip and .hpp files (names and contents)."""
+    """sha256 over the sources of the phase kernels: vp_kernels.hip and every header it
+    includes, directly or through other headers (names and contents)."""
     import hashlib
-    import glob
+    import re
+    csrc = os.path.join(ROOT, "paper_1908_09359_amd", "csrc")
+    seen, todo = set(), ["vp_kernels.hip"]
+    while todo:
+        f = todo.pop()
+        if f in seen or not os.path.exists(os.path.join(csrc, f)):
+            continue
+        seen.add(f)
+        with open(os.path.join(csrc, f)) as fh:
+            todo += re.findall(r'#include "([^"/]+)"', fh.read())
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1908_09359_amd", "csrc", "*"))):
-        if f.endswith((".hip", ".hpp")):
-            h.update(os.path.basename(f).encode())
-            with open(f, "rb") as fh:
-                h.update(fh.read())
+    for f in sorted(seen):
+        h.update(f.encode())
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -154,32 +163,26 @@ def set_tensors(ctx, T=None):
         ctx.vp_set_tensors(0, T)
 
 
-def correlated_tensors(B, torch, L, D, seed=7, steps=60):
-    """A correlated stand-in for the paper's optimised states: an L x L PEPS of bond
-    dimension 2 brought down by Algorithm 1 (vp_optimize: 256 chains, 2 + 4 sweeps
-    per step, step lengths 0.05, 0.02, 0.01 for a third of the steps each), written
-    into the bond-D layout (the same state) plus noise of 1e-3 times its rms entry."""
+def correlated_tensors(B, torch, L, D, seed=7, steps=200, dt=0.05):
+    """A correlated stand-in for the paper's optimised states: the simple-update state
+    (App. A, the paper's initialisation before Algorithm 1) of the L x L Heisenberg
+    lattice at bond dimension D, `steps` steps of dt from seeded N(0,1)/D^2 tensors."""
     import numpy as np
-    from paper_1908_09359_amd import workloads as W
     t0 = time.perf_counter()
     dev = torch.device("cuda:0")
-    ctx = B.Context(B.lattice(L, L, 2, 4, 1.0, 0.0, B.VP_FP64, 256), seed=seed)
+    ctx = B.Context(B.lattice(L, L, D, 4, 1.0, 0.0, B.VP_FP64, 1), seed=seed)
     ctx.vp_init_tensors(0, seed=seed, scale=0.0, perturb=0.0)
-    ctx.vp_init_chains(0, None)
-    third = steps // 3
-    deltas = [0.05] * third + [0.02] * third + [0.01] * (steps - 2 * third)
-    e = np.array(ctx.vp_optimize(0, deltas, 2, 4)) / (L * L)
-    T2 = torch.empty(ctx.num_params(), dtype=torch.float64, device=dev)
-    ctx.vp_get_tensors(0, T2)
+    ch = torch.zeros(steps, dtype=torch.float64, device=dev)
+    ctx.vp_simple_update(0, dt, steps, ch)
+    T = torch.empty(ctx.num_params(), dtype=torch.float64, device=dev)
+    ctx.vp_get_tensors(0, T)
     ctx.vp_sync()
-    T2 = T2.cpu().numpy()
+    c = ch.cpu().numpy()
     ctx.close()
-    rms = float(np.sqrt(np.mean(T2 ** 2)))
-    T = W.pad_tensors(T2, L, L, 2, D, noise=1e-3 * rms, seed=seed)
-    info = {"recipe": f"{L}x{L} D=2 PEPS after {steps} steps of vp_optimize (256 chains, 2+4 sweeps per step), "
-                      f"zero-padded to D={D}, plus 1e-3 x rms noise", "d2_e_site_first_step": float(e[0]),
-            "d2_e_site_last_steps": float(e[-5:].mean()), "seconds": time.perf_counter() - t0}
-    return torch.tensor(T, dtype=torch.float64, device=dev), info
+    info = {"recipe": f"{L}x{L} D={D} simple-update state (App. A): seeded N(0,1)/D^2 tensors, {steps} steps of "
+                      f"dt {dt}", "su_change_first": float(c[0]), "su_change_last": float(c[-1]),
+            "seconds": time.perf_counter() - t0}
+    return T, info
 
 
 class Path:
@@ -413,8 +416,11 @@ def fixed_de(plain, learned):
     integrated autocorrelation time in sweeps), and dE^2 = stderr^2 + bias^2 with bias^2 the
     squared E/N bias against float64 less the variance of that estimate (floored at 0).  Target dE = the plain path's dE after its timed
     seconds; the learned path needs t = v 2 tau / (rate (dE^2 - bias^2)) to reach it.
+    Both paths sample |Psi|^2 of the same tensors, so v is the same in expectation; its
+    estimates from heavy-tailed E_loc series are noisy, so v is pooled over both paths
+    (weighted by their sample counts; the per-path estimates are reported beside it).
     Also given: the same ratio without the bias terms, and with neither bias nor variance
-    (2 tau / rate only; both paths sample |Psi|^2 of the same tensors)."""
+    (2 tau / rate only)."""
     if plain["stats"] is None or learned["stats"] is None:
         return {"ratio": None, "ratio_without_bias": None, "ratio_tau_and_rate_only": None,
                 "reason": "one timed sweep per chain: no series"}
@@ -433,12 +439,15 @@ def fixed_de(plain, learned):
                 "reason": f"tau_int or variance not positive (tau {tp:.3g} / {tl:.3g}, var {vp:.3g} / {vl:.3g}): "
                           "too few timed sweeps per chain"}
     t_plain = plain["seconds"]
-    se2 = vp * 2 * tp / (rp * t_plain)
+    n_p, n_l = plain["samples_per_s"] * plain["seconds"], learned["samples_per_s"] * learned["seconds"]
+    v = (vp * n_p + vl * n_l) / (n_p + n_l)
+    se2 = v * 2 * tp / (rp * t_plain)
     de2 = se2 + bp * bp
-    t_learned = vl * 2 * tl / (rl * (de2 - bl * bl)) if de2 > bl * bl else float("inf")
+    t_learned = v * 2 * tl / (rl * (de2 - bl * bl)) if de2 > bl * bl else float("inf")
     return {"target_dE_e_site": de2 ** 0.5, "plain_stderr": se2 ** 0.5, "plain_bias": bp, "learned_bias": bl,
+            "var_per_sample_pooled": v, "var_per_sample_plain": vp, "var_per_sample_learned": vl,
             "plain_seconds": t_plain, "learned_seconds": t_learned, "ratio": t_plain / t_learned,
-            "ratio_without_bias": (vp * tp / rp) / (vl * tl / rl), "ratio_tau_and_rate_only": (tp / rp) / (tl / rl)}
+            "ratio_without_bias": (tp / rp) / (tl / rl), "ratio_tau_and_rate_only": (tp / rp) / (tl / rl)}
 
 
 def roofline(ms, launches, flops, fp64_phases, path):
@@ -593,8 +602,8 @@ def main():
             out["learned_over_plain_at_fixed_dE_long_run"] = cost(res["plain"]["tau"]) / cost(res["learned"]["tau"])
     if args.corr_chains and args.compress == "canonical" and args.only == "both" and args.steps >= 2:
         Tc, info = correlated_tensors(B, torch, Ly, D)
-        print(f"correlated workload: D=2 optimisation {info['d2_e_site_first_step']:.4f} -> "
-              f"{info['d2_e_site_last_steps']:.4f} per site in {info['seconds']:.1f} s", file=sys.stderr, flush=True)
+        print(f"correlated workload: simple update, lambda change {info['su_change_first']:.2e} -> "
+              f"{info['su_change_last']:.2e} in {info['seconds']:.1f} s", file=sys.stderr, flush=True)
         cres = {}
         nc = args.corr_chains
         for name, prec in (("plain", B.VP_FP32), ("learned", B.VP_BF16)):

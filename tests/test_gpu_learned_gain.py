@@ -2,10 +2,10 @@
 correlated state (the random i.i.d. workloads decorrelate within one sweep, so
 no proposal can gain there).
 
-The state: an 8x8 PEPS of bond dimension 2 brought down by Algorithm 1
-(vp_optimize), written into the D=4 layout (the same state) plus 1e-3 x rms
-noise.  Both samplers run in float64 from the same Neel-shuffled starts, 256
-chains, 10 burn-in and 60 measured sweeps: pair sweeps alone, and pair sweeps
+The state: the simple-update state (App. A, vp_simple_update) of the 8x8
+Heisenberg lattice at D=4, 200 steps of dt 0.05 from seeded random tensors
+(about -0.613 per site).  Both samplers run in float64 from the same
+Neel-shuffled starts, 256 chains, 30 burn-in and 60 measured sweeps: pair sweeps alone, and pair sweeps
 plus learned plaquette moves (network trained on the pair sampler's
 configurations and their plaquette ratios).  Printed per sampler: tau_int of
 E_loc/N and of M_z^2 (a function of the configuration alone), the acceptance
@@ -21,7 +21,7 @@ from paper_1908_09359_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-L, D, DC, NCH, NB, NM = 8, 4, 8, 256, 10, 60
+L, D, DC, NCH, NB, NM = 8, 4, 8, 256, 30, 60
 
 
 def _B():
@@ -30,19 +30,20 @@ def _B():
 
 
 def _state(B, torch):
+    """The simple-update state (App. A) of the L x L Heisenberg lattice at bond
+    dimension D: 200 steps of dt 0.05 from seeded random tensors."""
     dev = torch.device("cuda")
-    ctx = B.Context(B.lattice(L, L, 2, 4, 1.0, 0.0, B.VP_FP64, 256), seed=7)
+    ctx = B.Context(B.lattice(L, L, D, 4, 1.0, 0.0, B.VP_FP64, 1), seed=7)
     ctx.vp_init_tensors(0, seed=7, scale=0.0, perturb=0.0)
-    ctx.vp_init_chains(0, None)
-    e = np.array(ctx.vp_optimize(0, [0.05] * 15 + [0.02] * 15 + [0.01] * 10, 2, 4)) / (L * L)
-    T2 = torch.empty(ctx.num_params(), dtype=torch.float64, device=dev)
-    ctx.vp_get_tensors(0, T2)
+    ch = torch.zeros(200, dtype=torch.float64, device=dev)
+    ctx.vp_simple_update(0, 0.05, 200, ch)
+    T = torch.empty(ctx.num_params(), dtype=torch.float64, device=dev)
+    ctx.vp_get_tensors(0, T)
     ctx.vp_sync()
-    T2 = T2.cpu().numpy()
+    c = ch.cpu().numpy()
     ctx.close()
-    print(f"D=2 optimisation: E/N {e[0]:.4f} -> {e[-5:].mean():.4f}", flush=True)
-    rms = float(np.sqrt(np.mean(T2 ** 2)))
-    return W.pad_tensors(T2, L, L, 2, D, noise=1e-3 * rms, seed=7)
+    print(f"simple update: lambda change {c[0]:.2e} -> {c[-1]:.2e}", flush=True)
+    return T.cpu().numpy()
 
 
 def _run(B, torch, T, learned):
@@ -100,7 +101,7 @@ def _run(B, torch, T, learned):
 def test_learned_moves_on_a_correlated_state():
     import torch
     B = _B()
-    print(f"learned-move gain: {L}x{L} D={D} Dc={DC} (optimised D=2 state, padded), {NCH} chains", flush=True)
+    print(f"learned-move gain: {L}x{L} D={D} Dc={DC} (simple-update state), {NCH} chains", flush=True)
     T = _state(B, torch)
     res = {}
     for learned in (False, True):
