@@ -1,5 +1,6 @@
-"""Simple-update imaginary-time evolution (App. A), nearest-neighbour terms:
-test infrastructure only (tests/, never the product path).
+"""Simple-update imaginary-time evolution (App. A), nearest- and
+next-nearest-neighbour terms: test infrastructure only (tests/, never the
+product path).
 
 The PEPS is held as site tensors B_k (same layout as the parameter vector:
 B_k[s][l, u, r, d]) and a diagonal matrix lambda on every link between
@@ -27,6 +28,19 @@ is the given tensors with every lambda 1; the result absorbs lambda^(1/2)
 into each of the two tensors of every link (App. A's last step).  The
 convergence measure is App. A's: the mean over links of
 ||lambda(t+dt) - lambda(t)|| / ||lambda(t)|| over one step.
+
+Next-nearest-neighbour terms (J2, both diagonals of every plaquette) follow
+Fig. 7: the pair (B_1, B_3) is joined through a corner site B_2 (reading: the
+diagonal (y,x)-(y+1,x+1) through (y,x+1), the anti-diagonal (y,x+1)-(y+1,x)
+through (y,x)); B_1 and B_3 with their outer lambdas are QR-reduced to R_1
+and R_3; the gate acts on the physical legs of B_1 and B_3 of
+T_a = R_1 lambda_4 B_2 lambda_7 R_3^T (B_2 with its outer lambdas); a
+truncated SVD splits T_a into R~_1, lambda~_4 and T_b; a second one splits
+lambda~_4 T_b into T_c, lambda~_7 and R~_3; the new B_1 = Q_1 R~_1,
+B_2 = T_c / lambda~_4 and B_3 = Q_3 R~_3, each with its outer lambdas divided
+out.  A step visits the nearest-neighbour classes, then the plaquettes in four
+classes (y mod 2, x mod 2), each class's diagonals and then its
+anti-diagonals; plaquettes of one class share no site.
 
 Pinned (tests/test_oracle_simple_update.py): the QR-reduced update equals the
 update written out on the full two-site tensor (step 2 left out); without
@@ -186,16 +200,94 @@ def su_bond(B, lam, lat, a, b, leg_a, leg_b, G, reduced=True):
     lam[link] = lam_new
 
 
+def nnn_paths(lat, y, x, anti):
+    """(B_1, B_2, B_3) sites and the legs joining them for a diagonal of plaquette (y, x):
+    ((y1, x1), leg of B_1 to B_2, (y2, x2), leg of B_2 to B_1, leg of B_2 to B_3, (y3, x3), leg of B_3 to B_2)."""
+    if not anti:   # (y, x) - (y+1, x+1) through (y, x+1)
+        return (y, x), 2, (y, x + 1), 0, 3, (y + 1, x + 1), 1
+    return (y, x + 1), 0, (y, x), 2, 3, (y + 1, x), 1   # (y, x+1) - (y+1, x) through (y, x)
+
+
+def plaquette_classes(lat):
+    """Plaquettes (y, x) in four classes by (y mod 2, x mod 2); a class's plaquettes share no site."""
+    out = [[], [], [], []]
+    for y in range(lat.Ly - 1):
+        for x in range(lat.Lx - 1):
+            out[2 * (y % 2) + x % 2].append((y, x))
+    return out
+
+
+def su_nnn(B, lam, lat, y, x, anti, G, reduced=True):
+    """Apply the gate G to the next-nearest-neighbour pair of plaquette (y, x) (App. A, Fig. 7), in place.
+
+    reduced=False leaves out the QR reductions of B_1 and B_3 (the plain definition)."""
+    (y1, x1), l1, (y2, x2), l21, l23, (y3, x3), l3 = nnn_paths(lat, y, x, anti)
+    k1, k2, k3 = lat.site(y1, x1), lat.site(y2, x2), lat.site(y3, x3)
+    link4 = leg_links(lat, y1, x1)[l1]
+    link7 = leg_links(lat, y3, x3)[l3]
+    D4, D7 = lam[link4].shape[0], lam[link7].shape[0]
+    # (b) B_1, B_3 with their outer lambdas, QR-reduced
+    X1, shape1 = _to_matrix(_scale_legs(B[k1], _outer_lambdas(lat, lam, y1, x1, l1)), l1)
+    X3, shape3 = _to_matrix(_scale_legs(B[k3], _outer_lambdas(lat, lam, y3, x3, l3)), l3)
+    if reduced:
+        Q1, R1 = np.linalg.qr(X1, mode='reduced')
+        Q3, R3 = np.linalg.qr(X3, mode='reduced')
+    else:
+        Q1, R1 = np.eye(X1.shape[0]), X1
+        Q3, R3 = np.eye(X3.shape[0]), X3
+    r1, r3 = R1.shape[0], R3.shape[0]
+    R1 = R1.reshape(r1, 2, D4)
+    R3 = R3.reshape(r3, 2, D7)
+    # B_2 with its two outer lambdas as M2[k4, k7, o2, s2]
+    links2 = leg_links(lat, y2, x2)
+    outer2 = [q for q in range(4) if q not in (l21, l23)]
+    M2 = _scale_legs(B[k2], [None if (q in (l21, l23) or links2[q] is None) else lam[links2[q]] for q in range(4)])
+    M2 = np.transpose(M2, [1 + l21, 1 + l23] + [1 + q for q in outer2] + [0])
+    o2_shape = M2.shape[2:4]
+    M2 = M2.reshape(D4, D7, -1, 2)
+    # (c) T_a[a1, s1, s2, o2, s3, a3] with lambda_4, lambda_7 and the gate on (s1, s3)
+    Ta = np.einsum('aip,p,pqos,q,cjq->aisojc', R1, lam[link4], M2, lam[link7], R3, optimize=True)
+    Ta = np.einsum('uvij,aisojc->ausovc', G, Ta, optimize=True)   # [a1, t1, s2, o2, t3, a3]
+    n2 = Ta.shape[3]
+    # (d) SVD rows (a1, t1): R~_1, lambda~_4, T_b
+    U1, lam4, Tb = _truncated_svd(Ta.reshape(2 * r1, 2 * n2 * 2 * r3), D4)
+    # (e) lambda~_4 T_b, rows (i4, s2, o2), columns (t3, a3): T_c, lambda~_7, R~_3
+    Tb = (lam4[:, None] * Tb).reshape(D4 * 2 * n2, 2 * r3)
+    Tc, lam7, V3 = _truncated_svd(Tb, D7)
+    # (f) B~_1 = Q_1 R~_1 with the outer lambdas divided out
+    X1n = (Q1 @ U1.reshape(r1, 2 * D4)).reshape(-1, 2 * D4)
+    B[k1] = _scale_legs(_from_matrix(X1n, shape1, l1, D4), _outer_lambdas(lat, lam, y1, x1, l1, inverse=True))
+    # (g) B~_2 = T_c / lambda~_4 with its outer lambdas divided out
+    C = (Tc.reshape(D4, 2, n2, D7) * _pinv(lam4)[:, None, None, None])        # [i4, s2, o2, i7]
+    C = C.reshape((D4, 2) + tuple(o2_shape) + (D7,))
+    order = [0] * 5
+    src = {1 + l21: 0, 0: 1, 1 + outer2[0]: 2, 1 + outer2[1]: 3, 1 + l23: 4}
+    for t in range(5):
+        order[t] = src[t]
+    inv2 = [None if (q in (l21, l23) or links2[q] is None) else _pinv(lam[links2[q]]) for q in range(4)]
+    B[k2] = _scale_legs(np.transpose(C, order), inv2)
+    # (h) B~_3 = Q_3 R~_3 with the outer lambdas divided out
+    Vb = np.transpose(V3.reshape(D7, 2, r3), (2, 1, 0)).reshape(r3, 2 * D7)
+    B[k3] = _scale_legs(_from_matrix(Q3 @ Vb, shape3, l3, D7), _outer_lambdas(lat, lam, y3, x3, l3, inverse=True))
+    lam[link4] = lam4
+    lam[link7] = lam7
+
+
 def su_step(B, lam, lat, dt, reduced=True):
-    """One step over every nearest-neighbour link, class by class; returns the
-    mean relative change of the lambdas (App. A's convergence measure)."""
-    if lat.J2 != 0.0:
-        raise ValueError("the simple update here covers nearest-neighbour terms only (J2 = 0)")
+    """One step over every nearest-neighbour link, class by class, then (J2 != 0) every
+    next-nearest-neighbour pair, plaquette class by class; returns the mean relative
+    change of the lambdas (App. A's convergence measure)."""
     G = heisenberg_gate(dt, lat.J1)
     old = [l.copy() for l in lam]
     for cls in link_classes(lat):
         for a, b, la, lb in cls:
             su_bond(B, lam, lat, a, b, la, lb, G, reduced)
+    if lat.J2 != 0.0:
+        G2 = heisenberg_gate(dt, lat.J2)
+        for cls in plaquette_classes(lat):
+            for anti in (False, True):
+                for (y, x) in cls:
+                    su_nnn(B, lam, lat, y, x, anti, G2, reduced)
     if not lam:
         return 0.0
     return float(np.mean([np.linalg.norm(n - o) / np.linalg.norm(o) for n, o in zip(lam, old)]))

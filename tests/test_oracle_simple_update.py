@@ -11,7 +11,12 @@
 * On one link the evolution converges to the singlet, E = -3/4.
 * On a 2 x 4 lattice (D = 2, truncated): the energy of the absorbed state falls
   well below the start's and stays above the exact ground energy (variational),
-  and the convergence measure decreases.
+  and the convergence measure decreases; the same with J2 = 0.5.
+* Next-nearest-neighbour terms (Fig. 7's three-site update): the QR-reduced
+  update equals the full one; from a product state where no truncation
+  occurs, a step is the dense product of the same gates in the same order;
+  with J1 = 0 the two diagonals of a 2 x 2 plaquette decouple and the
+  evolution converges to two singlets, E = -3/2.
 """
 import itertools
 
@@ -48,23 +53,26 @@ def _apply_gate(psi, N, i, j, G4):
     return np.moveaxis(t, [0, 1], [i, j]).ravel()
 
 
-def _hpsi(psi, Ly, Lx):
-    """H psi for the nearest-neighbour Heisenberg lattice (J = 1)."""
+def _hpsi(psi, Ly, Lx, J2=0.0, J1=1.0):
+    """H psi: J1 on nearest-neighbour pairs, J2 on both diagonals of every plaquette."""
     N = Ly * Lx
     h = _bond_hamiltonian()
     out = np.zeros_like(psi)
     for y in range(Ly):
         for x in range(Lx):
             k = y * Lx + x
-            if x < Lx - 1:
-                out += _apply_gate(psi, N, k, k + 1, h)
-            if y < Ly - 1:
-                out += _apply_gate(psi, N, k, k + Lx, h)
+            if x < Lx - 1 and J1:
+                out += J1 * _apply_gate(psi, N, k, k + 1, h)
+            if y < Ly - 1 and J1:
+                out += J1 * _apply_gate(psi, N, k, k + Lx, h)
+            if J2 and x < Lx - 1 and y < Ly - 1:
+                out += J2 * _apply_gate(psi, N, k, k + Lx + 1, h)
+                out += J2 * _apply_gate(psi, N, k + 1, k + Lx, h)
     return out
 
 
-def _energy(psi, Ly, Lx):
-    return float(psi @ _hpsi(psi, Ly, Lx) / (psi @ psi))
+def _energy(psi, Ly, Lx, J2=0.0, J1=1.0):
+    return float(psi @ _hpsi(psi, Ly, Lx, J2, J1) / (psi @ psi))
 
 
 @pytest.mark.parametrize("dt,J", [(0.01, 1.0), (0.3, 1.0), (0.2, 0.5)])
@@ -73,9 +81,10 @@ def test_gate_is_the_exponential_of_the_bond_term(dt, J):
     assert np.allclose(G, scipy.linalg.expm(-dt * J * _bond_hamiltonian()), atol=1e-15, rtol=1e-14)
 
 
-def test_reduced_update_equals_full_two_site_update():
+@pytest.mark.parametrize("J2", [0.0, 0.5])
+def test_reduced_update_equals_full_two_site_update(J2):
     Ly, Lx, D = 3, 4, 3
-    lat = olat.Lattice(Ly, Lx, D, 16)
+    lat = olat.Lattice(Ly, Lx, D, 16, J2=J2)
     T = W.random_tensors(Ly, Lx, D, seed=91)
     Br, lr = su.su_init(T, lat)
     Bf, lf = su.su_init(T, lat)
@@ -121,20 +130,21 @@ def test_one_link_converges_to_the_singlet():
     assert changes[-1] <= 1e-9
 
 
-def test_truncated_evolution_lowers_the_energy_variationally():
+@pytest.mark.parametrize("J2", [0.0, 0.5])
+def test_truncated_evolution_lowers_the_energy_variationally(J2):
     Ly, Lx, D = 2, 4, 2
-    lat = olat.Lattice(Ly, Lx, D, 16)
+    lat = olat.Lattice(Ly, Lx, D, 16, J2=J2)
     T = W.random_tensors(Ly, Lx, D, seed=23)
-    e0 = _energy(_dense_state(T, Ly, Lx, D), Ly, Lx)
+    e0 = _energy(_dense_state(T, Ly, Lx, D), Ly, Lx, J2)
     Tsu, changes, _, _ = su.simple_update(T, lat, 0.1, 40)
-    e1 = _energy(_dense_state(Tsu, Ly, Lx, D), Ly, Lx)
-    # exact ground energy of the 2 x 4 open Heisenberg lattice by dense diagonalisation
+    e1 = _energy(_dense_state(Tsu, Ly, Lx, D), Ly, Lx, J2)
+    # exact ground energy of the 2 x 4 open lattice by dense diagonalisation
     N = Ly * Lx
     H = np.zeros((2 ** N, 2 ** N))
     for k in range(2 ** N):
         e = np.zeros(2 ** N)
         e[k] = 1.0
-        H[:, k] = _hpsi(e, Ly, Lx)
+        H[:, k] = _hpsi(e, Ly, Lx, J2)
     e_exact = np.linalg.eigvalsh(H)[0]
     assert e1 >= e_exact - 1e-12
     assert e1 < e0 - 1.0 and e1 < 0.9 * e_exact
@@ -151,4 +161,51 @@ def test_sector_energy_of_the_brute_force_helper():
     keep = cfgs.sum(axis=1) == Ly * Lx // 2
     psi0 = np.where(keep, psi, 0.0)
     assert abs(bf.sector_energy(psi[keep], cfgs[keep], Ly, Lx) - _energy(psi0, Ly, Lx)) <= 1e-12
+
+
+def _product_state(lat, seed):
+    """A random product state written into the bond-D layout (every virtual index 0)."""
+    rng = np.random.default_rng(seed)
+    T = np.zeros(lat.Np)
+    for y in range(lat.Ly):
+        for x in range(lat.Lx):
+            o = lat.offsets[lat.site(y, x)]
+            n = int(np.prod(lat.dims(y, x)))
+            T[o], T[o + n] = rng.normal(size=2)
+    return T
+
+
+@pytest.mark.parametrize("Ly,Lx,D,J1,J2,tol", [(2, 2, 4, 0.0, 1.0, 1e-13), (2, 3, 8, 1.0, 0.5, 1e-10)])
+def test_untruncated_nnn_step_is_the_dense_gate_product(Ly, Lx, D, J1, J2, tol):
+    """From a product state the ranks stay within D for one step (the residue at
+    2x3 is the 1e-6 singular-value floor): the state is the dense product of the
+    step's gates, nearest-neighbour classes first, then the plaquette classes'
+    diagonals and anti-diagonals."""
+    N = Ly * Lx
+    dt = 0.1
+    lat = olat.Lattice(Ly, Lx, D, 16, J1=J1, J2=J2)
+    T = _product_state(lat, 3)
+    psi = _dense_state(T, Ly, Lx, D)
+    G1 = su.heisenberg_gate(dt, J1).reshape(4, 4)
+    G2 = su.heisenberg_gate(dt, J2).reshape(4, 4)
+    for cls in su.link_classes(lat):
+        for (ya, xa), (yb, xb), _, _ in cls:
+            psi = _apply_gate(psi, N, ya * Lx + xa, yb * Lx + xb, G1)
+    for cls in su.plaquette_classes(lat):
+        for anti in (False, True):
+            for (y, x) in cls:
+                (y1, x1), _, _, _, _, (y3, x3), _ = su.nnn_paths(lat, y, x, anti)
+                i, j = sorted((y1 * Lx + x1, y3 * Lx + x3))
+                psi = _apply_gate(psi, N, i, j, G2)
+    Tsu, _, _, _ = su.simple_update(T, lat, dt, 1)
+    phi = _dense_state(Tsu, Ly, Lx, D)
+    assert abs(phi @ psi) / (np.linalg.norm(phi) * np.linalg.norm(psi)) >= 1.0 - tol
+
+
+def test_decoupled_diagonals_converge_to_two_singlets():
+    lat = olat.Lattice(2, 2, 4, 16, J1=0.0, J2=1.0)
+    T = W.random_tensors(2, 2, 4, seed=8)
+    Tsu, changes, _, _ = su.simple_update(T, lat, 0.2, 150)
+    assert abs(_energy(_dense_state(Tsu, 2, 2, 4), 2, 2, J2=1.0, J1=0.0) + 1.5) <= 1e-10
+    assert changes[-1] <= 1e-9
 
