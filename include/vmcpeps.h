@@ -371,17 +371,22 @@ vp_status vp_optimize(vp_ctx* ctx, int32_t lat, int32_t n_steps, int32_t n_burn,
                       const double* delta_host, uint64_t step0, double* e_mean_host);
 
 /* Simple-update imaginary-time evolution (App. A), the initialisation the
- * paper runs before Algorithm 1, for the nearest-neighbour terms (the lattice
- * must have J2 = 0, else VP_ERR_UNSUPPORTED).  The PEPS is held as site
- * tensors and a diagonal lambda (D numbers) on every link; a step applies
- * exp(-dt J1 S_i.S_j) once to every link, in four classes of links that share
- * no site (horizontal links with x even, x odd, vertical links with y even,
- * y odd).  Per link: the outer links' lambdas multiply both tensors, each is
- * reduced by a thin Householder QR, the gate acts on the reduced two-site
- * tensor (lambda of the link between), its truncated SVD gives the new
- * lambda (the leading D singular values above 1e-6 of the largest,
- * normalised to unit 2-norm) and the new tensors, from which the outer
- * lambdas are divided out again (App. A, Fig. 7).  The first call on the
+ * paper runs before Algorithm 1.  The PEPS is held as site tensors and a
+ * diagonal lambda (D numbers) on every link; a step applies exp(-dt J1
+ * S_i.S_j) once to every link, in four classes of links that share no site
+ * (horizontal links with x even, x odd, vertical links with y even, y odd),
+ * then, when J2 != 0, exp(-dt J2 S_i.S_j) to both diagonals of every
+ * plaquette, in four classes of plaquettes (y mod 2, x mod 2), diagonals
+ * before anti-diagonals.  Per link: the outer links' lambdas multiply both
+ * tensors, each is reduced by a thin Householder QR, the gate acts on the
+ * reduced two-site tensor (lambda of the link between), its truncated SVD
+ * gives the new lambda (the leading D singular values above 1e-6 of the
+ * largest, normalised to unit 2-norm) and the new tensors, from which the
+ * outer lambdas are divided out again.  Per diagonal (Fig. 7): the pair is
+ * joined through a corner site ((y,x)-(y+1,x+1) through (y,x+1),
+ * (y,x+1)-(y+1,x) through (y,x)); the end tensors are QR-reduced, the gate
+ * acts on the reduced three-site tensor, and two truncated SVDs give both
+ * links' lambdas and the three new tensors.  The first call on the
  * current tensors starts from them with every lambda 1; a later call
  * continues the same evolution (for example with a smaller dt) until
  * vp_set_tensors, vp_init_tensors, an update or an optimisation changes the
@@ -390,8 +395,9 @@ vp_status vp_optimize(vp_ctx* ctx, int32_t lat, int32_t n_steps, int32_t n_burn,
  * boundaries are invalidated as by vp_set_tensors.  change_dev [n_steps]
  * (float64, device, may be NULL) receives App. A's convergence measure per
  * step: the mean over links of ||lambda(t+dt) - lambda(t)|| / ||lambda(t)||.
- * Workspace: the tensors and lambdas of the evolution and up to 512 links'
- * scratch (about 350 KB per link at D = 8), allocated by the first call. */
+ * Workspace: the tensors and lambdas of the evolution and the scratch of up
+ * to 512 links or diagonals per launch (about 350 KB per link and 2 MB per
+ * diagonal at D = 8; at most about 1 GiB), allocated by the first call. */
 vp_status vp_simple_update(vp_ctx* ctx, int32_t lat, double dt, int32_t n_steps, double* change_dev);
 
 /* The lambdas of the simple update of the current tensors, lam_dev

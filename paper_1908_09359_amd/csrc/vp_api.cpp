@@ -728,34 +728,49 @@ vp_status vp_simple_update(vp_ctx* ctx, int32_t lat, double dt, int32_t n_steps,
   Lattice* L = get_lat(ctx, lat);
   if (!L) return fail(ctx, VP_ERR_ARG, "bad lattice index");
   if (!std::isfinite(dt) || n_steps < 0) return fail(ctx, VP_ERR_ARG, "dt must be finite and n_steps >= 0");
-  if (L->p.J2 != 0.0)
-    return fail(ctx, VP_ERR_UNSUPPORTED, "the simple update covers nearest-neighbour terms only (J2 = 0)");
   if (!L->tensors_ready) return fail(ctx, VP_ERR_ARG, "tensors must be set first");
   hipStream_t s = ctx->stream;
   const int Ly = L->p.Ly, Lx = L->p.Lx, D = L->p.D;
+  const bool nnn = L->p.J2 != 0.0;
   const int nl = Ly * (Lx - 1) + (Ly - 1) * Lx;
   int most = 1;
-  for (int c = 0; c < 4; ++c) most = std::max(most, su_class_links(Ly, Lx, c));
-  const int chunk = std::min(most, 512);  // work-groups (links) per launch
+  for (int c = 0; c < 4; ++c) {
+    most = std::max(most, su_class_links(Ly, Lx, c));
+    if (nnn) most = std::max(most, su_class_plaquettes(Ly, Lx, c));
+  }
+  const int64_t stride = su_scratch_doubles(D, nnn);
+  // work-groups per launch: every link or plaquette of a class, within about 1 GiB of scratch
+  const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)most, 512, ((int64_t)1 << 27) / stride}));
   if (!(grow(s, L->su_B, sizeof(double) * L->Np) && grow(s, L->su_lam, sizeof(double) * std::max(nl, 1) * D) &&
-        grow(s, L->su_change, sizeof(double) * std::max(nl, 1)) &&
-        grow(s, L->su_scr, sizeof(double) * (size_t)chunk * su_scratch_doubles(D))))
+        grow(s, L->su_change, sizeof(double) * std::max(nl, 1) * D) &&
+        grow(s, L->su_scr, sizeof(double) * (size_t)chunk * stride)))
     return fail(ctx, VP_ERR_OOM, "simple-update workspace");
   double* B = (double*)L->su_B.p;
   double* lam = (double*)L->su_lam.p;
-  double* chg = (double*)L->su_change.p;
+  double* prev = (double*)L->su_change.p;  // the lambdas at the start of a step
+  double* scr = (double*)L->su_scr.p;
   if (!L->su_valid) {  // start: the current tensors, every lambda 1
     HIP_TRY(ctx, hipMemcpyAsync(B, L->T, sizeof(double) * L->Np, hipMemcpyDeviceToDevice, s));
     if (nl > 0) launch_su_init(lam, (int64_t)nl * D, s);
   }
   for (int step = 0; step < n_steps; ++step) {
+    if (change_dev && nl > 0)
+      HIP_TRY(ctx, hipMemcpyAsync(prev, lam, sizeof(double) * nl * D, hipMemcpyDeviceToDevice, s));
     for (int c = 0; c < 4; ++c) {
       const int count = su_class_links(Ly, Lx, c);
       for (int first = 0; first < count; first += chunk)
         launch_su_class(B, lam, L->d_offs, L->d_dims, Ly, Lx, D, c, first, std::min(chunk, count - first), dt,
-                        L->p.J1, (double*)L->su_scr.p, chg, s);
+                        L->p.J1, scr, stride, s);
     }
-    if (change_dev) launch_su_mean(chg, nl, change_dev + step, s);
+    if (nnn)
+      for (int c = 0; c < 4; ++c)
+        for (int anti = 0; anti < 2; ++anti) {
+          const int count = su_class_plaquettes(Ly, Lx, c);
+          for (int first = 0; first < count; first += chunk)
+            launch_su_nnn(B, lam, L->d_offs, L->d_dims, Ly, Lx, D, c, anti, first, std::min(chunk, count - first),
+                          dt, L->p.J2, scr, stride, s);
+        }
+    if (change_dev) launch_su_mean(lam, prev, nl, D, change_dev + step, s);
     HIP_TRY(ctx, hipGetLastError());
   }
   launch_su_absorb(B, lam, L->d_offs, L->d_dims, Ly, Lx, D, L->T, s);

@@ -148,15 +148,21 @@ void net_gather(const int8_t* spins, const double* ratios, const int32_t* idx, i
 void net_cast_f64(const float* src, double* dst, hipStream_t s);
 
 // Simple update (vp_su.hip): links per class (0: horizontal x even, 1: x odd,
-// 2: vertical y even, 3: y odd), per-work-group scratch (doubles), lambda <- 1,
-// one launch over links first .. first+count-1 of a class, the mean of the
-// per-link changes, and the absorption of lambda^(1/2) into T.
+// 2: vertical y even, 3: y odd), plaquettes per class (y mod 2, x mod 2) =
+// (cls >> 1, cls & 1), per-work-group scratch (doubles; nnn: large enough for
+// the three-site update too), lambda <- 1, one launch over links (or
+// plaquettes' diagonals) first .. first+count-1 of a class, the mean relative
+// change of the lambdas against those at the start of the step, and the
+// absorption of lambda^(1/2) into T.
 int su_class_links(int Ly, int Lx, int cls);
-int64_t su_scratch_doubles(int D);
+int su_class_plaquettes(int Ly, int Lx, int cls);
+int64_t su_scratch_doubles(int D, bool nnn);
 void launch_su_init(double* lam, int64_t n, hipStream_t s);
 void launch_su_class(double* B, double* lam, const int64_t* offs, const int32_t* dims, int Ly, int Lx, int D, int cls,
-                     int first, int count, double dt, double J, double* scr, double* change, hipStream_t s);
-void launch_su_mean(const double* change, int n, double* out, hipStream_t s);
+                     int first, int count, double dt, double J, double* scr, int64_t stride, hipStream_t s);
+void launch_su_nnn(double* B, double* lam, const int64_t* offs, const int32_t* dims, int Ly, int Lx, int D, int cls,
+                   int anti, int first, int count, double dt, double J, double* scr, int64_t stride, hipStream_t s);
+void launch_su_mean(const double* lam, const double* prev, int n, int D, double* out, hipStream_t s);
 void launch_su_absorb(const double* B, const double* lam, const int64_t* offs, const int32_t* dims, int Ly, int Lx,
                       int D, double* T, hipStream_t s);
 

@@ -11,10 +11,14 @@ amplitudes and 1e-10 relative on the changes (measured: 5e-15 and 2e-14; a few
 steps from random tensors, so no nearly degenerate truncation decides the
 result, and the Gram route's squared conditioning stays far below them).
 
+The J1-J2 cases add the next-nearest-neighbour (three-site) update of Fig. 7.
+
 Also: two calls of 2 and 3 steps give the 5-step call bit for bit; zero steps
-leave the tensors unchanged; the J1-J2 lattice is rejected; and on the 4x4
-Heisenberg lattice at D = 4, 100 steps of dt = 0.05 bring the energy of the
-absorbed state within 5% of the exact ground energy and not below it.
+leave the tensors unchanged; a negative step count is rejected; with J1 = 0
+the two diagonals of a 2x2 plaquette converge to two singlets (E = -3/2); and
+on the 4x4 Heisenberg lattice at D = 4, 100 steps of dt = 0.05 bring the
+energy of the absorbed state within 5% of the exact ground energy and not
+below it.
 """
 import numpy as np
 import pytest
@@ -58,18 +62,21 @@ def _gpu_su(Ly, Lx, D, T, calls, J2=0.0):
     return out
 
 
-@pytest.mark.parametrize("Ly,Lx,D,dt,steps", [
-    (1, 4, 4, 0.1, 2),     # open chain, no truncation (exact Trotter product on the oracle side)
-    (4, 1, 4, 0.1, 2),     # the same along the vertical links
-    (3, 4, 3, 0.05, 3),    # truncated, ragged rows of links
-    (4, 4, 2, 0.1, 4),
-    (2, 6, 4, 0.05, 3),    # QR-reduced sites (outer extent 16 > 2D = 8)
+@pytest.mark.parametrize("Ly,Lx,D,J2,dt,steps", [
+    (1, 4, 4, 0.0, 0.1, 2),     # open chain, no truncation (exact Trotter product on the oracle side)
+    (4, 1, 4, 0.0, 0.1, 2),     # the same along the vertical links
+    (3, 4, 3, 0.0, 0.05, 3),    # truncated, ragged rows of links
+    (4, 4, 2, 0.0, 0.1, 4),
+    (2, 6, 4, 0.0, 0.05, 3),    # QR-reduced sites (outer extent 16 > 2D = 8)
+    (3, 4, 3, 0.5, 0.05, 3),    # J1-J2: three-site updates, every plaquette class
+    (4, 4, 2, 0.5, 0.1, 3),
+    (3, 4, 4, 0.3, 0.05, 2),    # QR-reduced end sites of the diagonals (interior sites: 64 > 2D rows)
 ])
-def test_simple_update_matches_oracle(Ly, Lx, D, dt, steps):
-    print(f"simple update {Ly}x{Lx} D={D} dt={dt} steps={steps}", flush=True)
-    lat = olat.Lattice(Ly, Lx, D, 4)
+def test_simple_update_matches_oracle(Ly, Lx, D, J2, dt, steps):
+    print(f"simple update {Ly}x{Lx} D={D} J2={J2} dt={dt} steps={steps}", flush=True)
+    lat = olat.Lattice(Ly, Lx, D, 4, J2=J2)
     T = W.random_tensors(Ly, Lx, D, seed=400 + Ly * Lx + D)
-    Tg, lam_g, ch_g = _gpu_su(Ly, Lx, D, T, [(dt, steps)])
+    Tg, lam_g, ch_g = _gpu_su(Ly, Lx, D, T, [(dt, steps)], J2=J2)
     To, ch_o, _, lam_o = su.simple_update(T, lat, dt, steps)
     assert np.max(np.abs(lam_g - np.array(lam_o))) <= 1e-12
     assert np.max(np.abs(ch_g - np.array(ch_o)) / np.maximum(np.abs(ch_o), 1e-300)) <= 1e-10
@@ -95,13 +102,11 @@ def test_state_rules():
     import torch
     B = _B()
     dev = torch.device("cuda")
-    ctx = B.Context(B.lattice(4, 4, 2, 4, 1.0, 0.5, B.VP_FP64, 1), seed=1)
+    ctx = B.Context(B.lattice(4, 4, 2, 4, 1.0, 0.0, B.VP_FP64, 1), seed=1)
     ctx.vp_init_tensors(0, seed=3, scale=0.0, perturb=0.0)
     with pytest.raises(B.VPError) as ei:
-        ctx.vp_simple_update(0, 0.05, 1)
-    assert ei.value.status == B.VP_ERR_UNSUPPORTED
-    ctx.close()
-    ctx = B.Context(B.lattice(4, 4, 2, 4, 1.0, 0.0, B.VP_FP64, 1), seed=1)
+        ctx.vp_simple_update(0, 0.05, -1)
+    assert ei.value.status == B.VP_ERR_ARG
     ctx.vp_init_tensors(0, seed=3, scale=0.0, perturb=0.0)
     ctx.vp_simple_update(0, 0.05, 2)
     lam = torch.empty((_n_links(4, 4), 2), dtype=torch.float64, device=dev)
@@ -111,6 +116,38 @@ def test_state_rules():
         ctx.vp_simple_update_lambdas(0, lam)
     assert ei.value.status == B.VP_ERR_ARG
     ctx.close()
+
+
+def test_decoupled_diagonals_converge_to_two_singlets():
+    """J1 = 0, J2 = 1 on 2x2: the diagonals are independent pairs; the evolution
+    (three-site updates only) reaches the product of their singlets, E = -3/2."""
+    import itertools
+    T = W.random_tensors(2, 2, 4, seed=8)
+    B = _B()
+    import torch
+    dev = torch.device("cuda")
+    ctx = B.Context(B.lattice(2, 2, 4, 4, 0.0, 1.0, B.VP_FP64, 1), seed=1)
+    ctx.vp_set_tensors(0, torch.tensor(T, dtype=torch.float64, device=dev))
+    ch = torch.zeros(150, dtype=torch.float64, device=dev)
+    ctx.vp_simple_update(0, 0.2, 150, ch)
+    Tg = torch.empty(ctx.num_params(), dtype=torch.float64, device=dev)
+    ctx.vp_get_tensors(0, Tg)
+    torch.cuda.synchronize()
+    Tg = Tg.cpu().numpy()
+    ctx.close()
+    cfgs = np.array(list(itertools.product([0, 1], repeat=4)), dtype=np.int8)
+    psi = bf.amplitudes(Tg, 2, 2, 4, cfgs)
+    sz = np.array([[0.5, 0.0], [0.0, -0.5]])
+    sp = np.array([[0.0, 1.0], [0.0, 0.0]])
+    h = np.kron(sz, sz) + 0.5 * (np.kron(sp, sp.T) + np.kron(sp.T, sp))
+
+    def apply(v, i, j):
+        t = np.moveaxis(v.reshape([2] * 4), [i, j], [0, 1])
+        sh = t.shape
+        return np.moveaxis((h @ t.reshape(4, -1)).reshape(sh), [0, 1], [i, j]).ravel()
+    e = psi @ (apply(psi, 0, 3) + apply(psi, 1, 2)) / (psi @ psi)
+    print(f"decoupled diagonals: E {e:.12f}, last change {ch[-1].item():.2e}", flush=True)
+    assert abs(e + 1.5) <= 1e-10
 
 
 def _exact_ground_energy_4x4():
