@@ -6,7 +6,11 @@ Eq. (10) sign-gradient update, step after step.
 * a short optimisation of the 4x4 Heisenberg antiferromagnet at D=2 from
   random tensors lowers the energy towards the exact ground state
   (-0.5743/site by exact diagonalisation in the S^z = 0 sector), with staged
-  step lengths as the paper uses.
+  step lengths as the paper uses;
+* the paper's order (Sec. II.B): the simple-update state (App. A) as the
+  start of Algorithm 1.  At 4x4, D=4 (exact contraction, Dc=16) the same 40
+  optimisation steps started from the simple-update state reach the exact
+  energy to about 1e-4 per site, from random tensors 0.017 above it.
 """
 import numpy as np
 import pytest
@@ -73,6 +77,31 @@ def test_optimisation_lowers_the_energy():
     assert e[-10:].mean() < e[:3].mean() - 0.1
     # D=2 reaches about -0.556 here (3% above the exact -0.5743)
     assert e[-10:].mean() < -0.53
+
+
+def test_simple_update_start_then_optimisation():
+    import torch
+    B = _B()
+    Ly, Lx, D, Dc, n = 4, 4, 4, 16, 128
+    print("simple update + optimize 4x4 D=4 Dc=16 Heisenberg, 128 chains", flush=True)
+    deltas = [0.005] * 20 + [0.002] * 20
+    out = {}
+    for start in ("random", "simple update"):
+        ctx = B.Context(B.lattice(Ly, Lx, D, Dc, 1.0, 0.0, B.VP_FP64, n), seed=5)
+        ctx.vp_init_tensors(0, seed=6, scale=0.0, perturb=0.0)
+        if start == "simple update":
+            ctx.vp_simple_update(0, 0.05, 100)
+        ctx.vp_init_chains(0, None)
+        e = np.array(ctx.vp_optimize(0, deltas, 4, 8)) / (Ly * Lx)
+        ctx.close()
+        assert np.all(np.isfinite(e))
+        out[start] = e
+        print(f"{start}: E/site first {e[:3]}, last 10 {e[-10:].mean():.5f}", flush=True)
+    su, rnd = out["simple update"], out["random"]
+    # the simple-update state alone is at -0.5627 per site; measured after 40 steps:
+    # -0.57426 from it against -0.5578 from random tensors (exact -0.57433)
+    assert su[-10:].mean() < rnd[-10:].mean() - 0.005
+    assert su[-10:].mean() < -0.570
 
 
 def test_zero_amplitude_stops_before_the_update():
