@@ -20,8 +20,16 @@ by Metropolis-Hastings.  Nothing here is in the paper; the readings are:
 Flat parameter layout: W1[32][1][3][3], b1[32], W2[32][32][3][3], b2[32],
 W3[32][32][3][3], b3[32], W4[1][32][3][3], b4[1].
 
+Inference in bfloat16 (``forward_bf16``, the sampler's evaluation in its bf16
+mode): every weight rounded to bf16, the input (+-1) exact, each layer's
+output accumulated in float64 from those, the bias (float32) added, and the
+ReLU output rounded to bf16 before the next layer reads it; the last layer's
+output is not rounded.  bf16 rounding: the value rounded to float32, then to
+the nearest bf16 (8 significant bits), ties to even.
+
 Parity: the convolution is pinned against scipy's correlate in the tests, the
-gradient against finite differences of ``loss``.
+gradient against finite differences of ``loss``, the bf16 rounding against
+torch's float32 -> bfloat16 conversion.
 """
 import math
 
@@ -83,6 +91,24 @@ def forward(theta, spins, Ly, Lx):
         pre.append(zpre)
         acts.append(np.maximum(zpre, 0.0) if i < len(layers) - 1 else zpre)
     return acts[-1][0], (acts, pre)
+
+
+def bf16(x):
+    """x rounded to float32, then to bfloat16 (round to nearest, ties to even), as float64."""
+    f = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def forward_bf16(theta, spins, Ly, Lx):
+    """Logit map z [Ly][Lx] of the bf16 inference described above."""
+    layers = unpack(theta)
+    a = spins_input(spins, Ly, Lx)
+    for i, (W, b) in enumerate(layers):
+        z = conv3(a, bf16(W), np.asarray(b, dtype=np.float32).astype(np.float64))
+        a = bf16(np.maximum(z, 0.0)) if i < len(layers) - 1 else z
+    return a[0]
 
 
 def movable(spins, Ly, Lx):

@@ -196,3 +196,30 @@ def test_propensity_correction_is_what_keeps_psi2_stationary():
     good, bad = kernel(True), kernel(False)
     assert np.max(np.abs(p @ good - p)) < 1e-13
     assert np.max(np.abs(p @ bad - p)) > 1e-6
+
+
+def test_bf16_rounding_matches_torch():
+    """bf16(): float32 then round to nearest bf16, ties to even; against torch's conversion,
+    on random values over many binades and on exact ties."""
+    import torch
+    rng = np.random.default_rng(5)
+    x = rng.normal(size=4000) * np.exp2(rng.integers(-30, 30, size=4000))
+    # exact ties: float32 values whose low 16 bits are 0x8000, on both parities of bit 16
+    # mantissa bits 17..22 random, exponent of 1.0 .. 2^7 (finite values)
+    t = (rng.integers(0, 2 ** 6, size=200, dtype=np.uint64) << 17) | (rng.integers(127, 135, size=200, dtype=np.uint64) << 23)
+    ties = np.concatenate([((t | 0x8000)), ((t | 0x18000))]).astype(np.uint32).view(np.float32).astype(np.float64)
+    for v in (x, ties, -ties):
+        ref = torch.tensor(v, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+        assert np.array_equal(P.bf16(v), ref)
+
+
+def test_bf16_inference_is_close_to_float64_and_not_equal():
+    rng = np.random.default_rng(8)
+    theta = rng.normal(scale=0.2, size=P.n_params()).astype(np.float32).astype(np.float64)
+    Ly, Lx = 6, 8
+    s = W.random_configs(Ly, Lx, 1, seed=3)[0]
+    z, _ = P.forward(theta, s, Ly, Lx)
+    zb = P.forward_bf16(theta, s, Ly, Lx)
+    d = np.abs(zb - z)
+    assert d.max() > 0.0                       # the rounding is there
+    assert d.max() <= 0.05 * np.abs(z).max()   # and only at the bf16 level
