@@ -293,6 +293,17 @@ vp_status vp_proposal_set_weights(vp_ctx* ctx, int32_t lat, const float* w_dev);
 vp_status vp_proposal_get_weights(vp_ctx* ctx, int32_t lat, float* w_dev);
 /* Logit maps of n configurations: logits_dev [n][Ly][Lx] float32.  Waits. */
 vp_status vp_proposal_forward(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev, int32_t n, float* logits_dev);
+/* The logits of every plaquette (y, x) of n configurations as the learned
+ * sweep evaluates them inside the sampler: logits_dev [n][(Ly-1)(Lx-1)]
+ * float64, plaquette index y (Lx-1) + x (all plaquettes, movable or not),
+ * from the local 9x9 window of each; with flip = 1 the plaquette's four spins
+ * are flipped first (the reverse proposal).  VP_FP64 and VP_FP32 evaluate in
+ * the working precision; VP_BF16 in bf16 inference: weights and ReLU outputs
+ * rounded to bf16 (nearest, ties to even), float32 accumulation on the bf16
+ * MFMA, biases in float32.  Asynchronous; VP_ERR_SHAPE for a lattice of one
+ * row or column. */
+vp_status vp_proposal_logits_sweep(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev, int32_t n, int32_t flip,
+                                   double* logits_dev);
 /* vp_proposal_forward for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * allocation): the same kernels and the same logits, bit for bit, with the

@@ -29,7 +29,8 @@ EXPORTED = ["vp_create", "vp_destroy", "vp_last_error", "vp_num_params", "vp_wor
             "vp_proposal_num_params", "vp_proposal_set_weights", "vp_proposal_get_weights", "vp_proposal_forward",
             "vp_proposal_forward_noalloc", "vp_proposal_loss_grad", "vp_proposal_train", "vp_set_sampler", "vp_move_counts", "vp_set_schedule",
             "vp_sample_batch", "vp_autotune", "vp_sample_split", "vp_optimize", "vp_set_tile",
-            "vp_autotune_tiles", "vp_eval_sis", "vp_simple_update", "vp_simple_update_lambdas"]
+            "vp_autotune_tiles", "vp_eval_sis", "vp_simple_update", "vp_simple_update_lambdas",
+            "vp_proposal_logits_sweep"]
 
 PHASES = ["row3_envs", "hsweep", "row4_envs", "vsweep", "compress_up", "compress_down", "measure3",
           "measure4", "other"]
@@ -87,6 +88,7 @@ def _load():
         "vp_proposal_get_weights": ([P, I32, P], I32),
         "vp_proposal_forward": ([P, I32, P, I32, P], I32),
         "vp_proposal_forward_noalloc": ([P, I32, P, I32, P], I32),
+        "vp_proposal_logits_sweep": ([P, I32, P, I32, I32, P], I32),
         "vp_proposal_loss_grad": ([P, I32, P, P, I32, P, P], I32),
         "vp_proposal_train": ([P, I32, P, P, I64, I32, I32, D, U64, P], I32),
         "vp_set_sampler": ([P, I32, I32], I32),
@@ -213,6 +215,9 @@ class Context:
 
     def vp_proposal_forward(self, lat, spins, n, logits):
         self._check(LIB.vp_proposal_forward(self.h, lat, _ptr(spins), n, _ptr(logits)))
+
+    def vp_proposal_logits_sweep(self, lat, spins, n, flip, logits):
+        self._check(LIB.vp_proposal_logits_sweep(self.h, lat, _ptr(spins), int(n), int(flip), _ptr(logits)))
 
     def vp_proposal_forward_noalloc(self, lat, spins, n, logits):
         self._check(LIB.vp_proposal_forward_noalloc(self.h, lat, _ptr(spins), n, _ptr(logits)))

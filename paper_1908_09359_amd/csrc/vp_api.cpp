@@ -44,6 +44,7 @@ struct Lattice {
   // proposal network: float32 master, working-precision copy, Adam moments
   float* d_net = nullptr;
   double* d_net64 = nullptr;
+  char* d_netbf = nullptr;      // packed bf16 copy (bf16 inference in the bf16 sampling mode)
   float* d_adam = nullptr;      // [2][NET_NPARAM]: m, v
   int64_t adam_t = 0;
   bool net_ready = false;
@@ -638,6 +639,7 @@ vp_status vp_create(const vp_lattice* lats, int32_t n_lats, uint64_t seed, void*
               alloc((void**)&L.d_scratch, 64 * sizeof(double)) &&
               alloc((void**)&L.d_net, sizeof(float) * NET_NPARAM) &&
               alloc((void**)&L.d_net64, sizeof(double) * NET_NPARAM) &&
+              alloc((void**)&L.d_netbf, NET_BF_BYTES) &&
               alloc((void**)&L.d_adam, 2 * sizeof(float) * NET_NPARAM) &&
               alloc((void**)&L.d_sis, sis_bytes(p));
     if (!ok) {
@@ -667,6 +669,7 @@ vp_status vp_create(const vp_lattice* lats, int32_t n_lats, uint64_t seed, void*
     D.meta = L.meta; D.spins = L.spins;
     D.trace = nullptr;
     D.net = works_f64(p.prec) ? (const void*)L.d_net64 : (const void*)L.d_net;
+    D.net_bf = (const void*)L.d_netbf;
     D.n_bonds = p.Ly * (p.Lx - 1) + (p.Ly - 1) * p.Lx;
     D.kU = L.d_kU; D.kD = L.d_kD; D.dims = L.d_dims; D.coff = L.d_coff;
     if (works_f64(p.prec)) launch_init_trivial<double>(D, ctx->stream);
@@ -687,7 +690,7 @@ vp_status vp_destroy(vp_ctx* ctx) {
   for (auto& L : ctx->lats) {
     void* ptrs[] = {L.T, L.Tw, L.ws, L.cws, L.iws, L.dws, L.meta, L.spins, L.d_kU, L.d_kD,
                     L.d_dims, L.d_sizes, L.d_offs, L.d_coff, L.d_scratch, L.d_net, L.d_net64, L.d_adam,
-                    L.d_sis};
+                    L.d_sis, L.d_netbf};
     for (void* q : ptrs)
       if (q) hipFree(q);
     Lattice::Buf* bufs[] = {&L.sr_work, &L.sr_flag, &L.opt_lp, &L.opt_el, &L.opt_grad, &L.opt_em, &L.opt_sg,
@@ -1152,6 +1155,7 @@ vp_status vp_proposal_set_weights(vp_ctx* ctx, int32_t lat, const float* w_dev) 
   hipStream_t s = ctx->stream;
   HIP_TRY(ctx, hipMemcpyAsync(L->d_net, w_dev, sizeof(float) * NET_NPARAM, hipMemcpyDeviceToDevice, s));
   net_cast_f64(L->d_net, L->d_net64, s);
+  net_pack_bf16(L->d_net, L->d_netbf, s);
   HIP_TRY(ctx, hipMemsetAsync(L->d_adam, 0, 2 * sizeof(float) * NET_NPARAM, s));
   HIP_TRY(ctx, hipGetLastError());
   L->adam_t = 0;
@@ -1203,6 +1207,20 @@ vp_status vp_proposal_forward(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev,
   net_forward(L->d_net, spins_dev, n, L->p.Ly, L->p.Lx, w.work, logits_dev, ctx->stream);
   HIP_TRY(ctx, hipGetLastError());
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  return VP_OK;
+}
+
+vp_status vp_proposal_logits_sweep(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev, int32_t n, int32_t flip,
+                                   double* logits_dev) {
+  Lattice* L = get_lat(ctx, lat);
+  if (!L || !spins_dev || !logits_dev) return fail(ctx, VP_ERR_ARG, "bad lattice index or null pointer");
+  if (!L->net_ready) return fail(ctx, VP_ERR_ARG, "the proposal network has no weights yet");
+  if (n < 1 || (flip != 0 && flip != 1)) return fail(ctx, VP_ERR_ARG, "n must be >= 1 and flip 0 or 1");
+  if (L->p.Ly < 2 || L->p.Lx < 2) return fail(ctx, VP_ERR_SHAPE, "the lattice has no plaquettes");
+  const int kind = L->p.prec == VP_BF16 ? 2 : (works_f64(L->p.prec) ? 1 : 0);
+  net_local_logits(kind, L->d_net, L->d_net64, L->d_netbf, spins_dev, n, L->p.Ly, L->p.Lx, flip, logits_dev,
+                   ctx->stream);
+  HIP_TRY(ctx, hipGetLastError());
   return VP_OK;
 }
 
@@ -1286,6 +1304,7 @@ vp_status vp_proposal_train(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev, c
     eloss[ep] = nbatch ? m / nbatch : 0.0;
   }
   net_cast_f64(L->d_net, L->d_net64, s);
+  net_pack_bf16(L->d_net, L->d_netbf, s);
   HIP_TRY(ctx, hipGetLastError());
   if (loss_dev)
     HIP_TRY(ctx, hipMemcpyAsync(loss_dev, eloss.data(), sizeof(double) * epochs, hipMemcpyHostToDevice, s));

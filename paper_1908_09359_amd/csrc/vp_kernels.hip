@@ -427,8 +427,12 @@ __device__ __forceinline__ void ph_vsweep(const LatDev& L, int ch, int y, char* 
         const int q = y * (L.Lx - 1) + x;
         U64x4 w = philox4x64_10((uint64_t)C.id, (uint64_t)C.meta->sweep, (uint64_t)q, TAG_PLAQ, L.seed,
                                 (uint64_t)L.lat_id);
-        const T* Wn = static_cast<const T*>(L.net);
-        const double pi_fwd = net_sigmoid(net_logit<T>(Wn, C.sp, L.Ly, L.Lx, y, x, 0, lds));
+        // bf16 inference with the bf16 sampling steps, the working precision otherwise
+        auto logit = [&](int flip) -> double {
+          if constexpr (BF16) return net_logit_bf16(static_cast<const char*>(L.net_bf), C.sp, L.Ly, L.Lx, y, x, flip, lds);
+          else return net_logit<T>(static_cast<const T*>(L.net), C.sp, L.Ly, L.Lx, y, x, flip, lds);
+        };
+        const double pi_fwd = net_sigmoid(logit(0));
         if (uniform53(w.v[0]) < pi_fwd) {
           const T* Ux1 = ub<T>(L, C, y, x + 1);
           const T* Dx1 = db<T>(L, C, y + 2, x + 1);
@@ -442,7 +446,7 @@ __device__ __forceinline__ void ph_vsweep(const LatDev& L, int ch, int y, char* 
           const int eden = enxt + step4<T, DD, CC, BF16, BBX>(L, C, cur, nxt, y, x + 1, 0, 0, Ux1, Dx1, false, as_lds(lds));
           const double num = wg_dot<T>(f2, R + (int64_t)(x + 2) * sz, sz);
           const double den = wg_dot<T>(cur, R + (int64_t)(x + 2) * sz, sz);
-          const double pi_back = net_sigmoid(net_logit<T>(Wn, C.sp, L.Ly, L.Lx, y, x, 1, lds));
+          const double pi_back = net_sigmoid(logit(1));
           const bool acc = plaquette_accept(C.meta, num, den, ef2 - eden, pi_fwd, pi_back, uniform53(w.v[1]));
           if (threadIdx.x == 0) {
             C.meta->p_proposed += 1;
@@ -926,7 +930,7 @@ __global__ void __launch_bounds__(WG, 2) k_row4_right(LatDev L, int y) {
 template <typename T, int DD, int CC, bool BF16, bool LEARN, int BBX = 0>
 __global__ void __launch_bounds__(WG, 2) k_vsweep(LatDev L, int y) {
   __shared__ __attribute__((aligned(16)))
-  char lds[cmax(step4_lds<T, DD, CC, BF16, BBX>(), LEARN ? net_lds_bytes<T>() : 0)];
+  char lds[cmax(step4_lds<T, DD, CC, BF16, BBX>(), LEARN ? (BF16 ? net_bf_lds_bytes() : net_lds_bytes<T>()) : 0)];
   ph_vsweep<T, DD, CC, BF16, LEARN, BBX>(L, blockIdx.x, y, lds);
 }
 template <typename T, int DD, int CC>

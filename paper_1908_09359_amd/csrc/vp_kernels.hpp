@@ -44,6 +44,7 @@ struct LatDev {
   double* trace;            // [n_chains][n_bonds][2] (rho, accepted) of the last sweep, or null
   int n_bonds;              // Ly(Lx-1) + (Ly-1)Lx
   const void* net;          // proposal network parameters in the working precision, or null
+  const void* net_bf;       // their packed bf16 copy (bf16 inference in the bf16 sampling mode)
   int learned;              // learned plaquette moves in the persistent sweep kernel
   int tile;                 // tile variant of the fused 2-row step (per-phase launches): 0, 1, 2
   int cmode;                // boundary truncation: 0 canonical SVD compression, 1 variational fit
@@ -146,6 +147,12 @@ void net_adam(float* th, const float* g, float* m, float* v, float lr, int t, hi
 void net_gather(const int8_t* spins, const double* ratios, const int32_t* idx, int nb, int H, int W, int8_t* sb,
                 double* rb, hipStream_t s);
 void net_cast_f64(const float* src, double* dst, hipStream_t s);
+// The packed bf16 copy of the parameters (NET_BF_BYTES bytes) for bf16 inference.
+void net_pack_bf16(const float* src, void* dst, hipStream_t s);
+// Logits of every plaquette of n configurations [n][(H-1)(W-1)] float64, as the
+// learned sweep evaluates them: kind 0 float32 weights, 1 float64, 2 bf16 inference.
+void net_local_logits(int kind, const float* w32, const double* w64, const void* wbf, const int8_t* spins, int n,
+                      int H, int Wd, int flip, double* out, hipStream_t s);
 
 // Simple update (vp_su.hip): links per class (0: horizontal x even, 1: x odd,
 // 2: vertical y even, 3: y odd), plaquettes per class (y mod 2, x mod 2) =

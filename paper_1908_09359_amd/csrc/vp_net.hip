@@ -231,6 +231,52 @@ __global__ void k_cast_params(const float* __restrict__ src, T* __restrict__ dst
 
 unsigned grid_for(int64_t total) { return (unsigned)std::min<int64_t>((total + WG - 1) / WG, 65536); }
 
+// The packed bf16 copy (layout in vp_net.hpp): element i of the bf16 region,
+// then the biases.
+__global__ void k_pack_bf16(const float* __restrict__ th, char* __restrict__ out) {
+  __bf16* w = reinterpret_cast<__bf16*>(out + sizeof(float) * NBF_FLOATS);
+  float* b = reinterpret_cast<float*>(out);
+  for (int i = blockIdx.x * WG + threadIdx.x; i < NBF_N; i += gridDim.x * WG) {
+    float v;
+    if (i < NBF_W2) {  // W1[co][tap]
+      v = th[NET_OFF_W1 + i];
+    } else if (i < NBF_W4) {  // W2 / W3 [tap][co][ci] <- W[co][ci][tap]
+      const int j = i < NBF_W3 ? i - NBF_W2 : i - NBF_W3;
+      const int t = j / (NET_CH * NET_CH), co = (j / NET_CH) % NET_CH, ci = j % NET_CH;
+      v = th[(i < NBF_W3 ? NET_OFF_W2 : NET_OFF_W3) + (co * NET_CH + ci) * 9 + t];
+    } else {  // W4[tap][ci] <- W4[0][ci][tap]
+      const int j = i - NBF_W4, t = j / NET_CH, ci = j % NET_CH;
+      v = th[NET_OFF_W4 + ci * 9 + t];
+    }
+    w[i] = (__bf16)v;
+  }
+  for (int i = blockIdx.x * WG + threadIdx.x; i < NBF_FLOATS; i += gridDim.x * WG)
+    b[i] = i < NET_CH ? th[NET_OFF_B1 + i]
+           : i < 2 * NET_CH ? th[NET_OFF_B2 + i - NET_CH]
+           : i < 3 * NET_CH ? th[NET_OFF_B3 + i - 2 * NET_CH]
+           : i == 3 * NET_CH ? th[NET_OFF_B4] : 0.0f;
+}
+
+// The logits of every plaquette of n configurations as the learned sweep
+// evaluates them (one work-group per configuration): bf16 inference from the
+// packed copy, or the working-precision evaluation from W.
+template <typename T, bool BF16>
+__global__ void __launch_bounds__(WG) k_net_local(const T* __restrict__ W, const char* __restrict__ Pb,
+                                                  const int8_t* __restrict__ spins, int H, int Wd, int flip,
+                                                  double* __restrict__ out) {
+  __shared__ __attribute__((aligned(16))) char lds[BF16 ? net_bf_lds_bytes() : net_lds_bytes<T>()];
+  const int n = blockIdx.x, P = (H - 1) * (Wd - 1);
+  const int8_t* sp = spins + (int64_t)n * H * Wd;
+  for (int q = 0; q < P; ++q) {
+    const int y = q / (Wd - 1), x = q % (Wd - 1);
+    double z;
+    if constexpr (BF16) z = net_logit_bf16(Pb, sp, H, Wd, y, x, flip, lds);
+    else z = net_logit<T>(W, sp, H, Wd, y, x, flip, lds);
+    if (threadIdx.x == 0) out[(int64_t)n * P + q] = z;
+    __syncthreads();
+  }
+}
+
 }  // namespace
 
 size_t net_forward_floats(int n, int H, int Wd) {
@@ -311,6 +357,23 @@ void net_gather(const int8_t* spins, const double* ratios, const int32_t* idx, i
 
 void net_cast_f64(const float* src, double* dst, hipStream_t s) {
   hipLaunchKernelGGL(k_cast_params<double>, dim3(grid_for(NET_NPARAM)), dim3(WG), 0, s, src, dst, NET_NPARAM);
+}
+
+void net_pack_bf16(const float* src, void* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_bf16, dim3(grid_for(NBF_N)), dim3(WG), 0, s, src, (char*)dst);
+}
+
+void net_local_logits(int kind, const float* w32, const double* w64, const void* wbf, const int8_t* spins, int n,
+                      int H, int Wd, int flip, double* out, hipStream_t s) {
+  if (kind == 2)
+    hipLaunchKernelGGL((k_net_local<float, true>), dim3(n), dim3(WG), 0, s, w32, (const char*)wbf, spins, H, Wd,
+                       flip, out);
+  else if (kind == 1)
+    hipLaunchKernelGGL((k_net_local<double, false>), dim3(n), dim3(WG), 0, s, w64, (const char*)wbf, spins, H,
+                       Wd, flip, out);
+  else
+    hipLaunchKernelGGL((k_net_local<float, false>), dim3(n), dim3(WG), 0, s, w32, (const char*)wbf, spins, H, Wd,
+                       flip, out);
 }
 
 }  // namespace vp

@@ -299,3 +299,45 @@ def test_bf16_chains_energy_matches_fp32():
     (m1, s1), (m2, s2) = means[B.VP_FP32], means[B.VP_BF16]
     print(f"E/N fp32 {m1:.5f} +- {s1:.5f}   bf16 {m2:.5f} +- {s2:.5f}", flush=True)
     assert abs(m1 - m2) <= 4 * np.hypot(s1, s2)
+
+
+def test_bf16_learned_chains_energy_matches_fp32_pairs():
+    """Learned plaquette moves with bf16 inference of the network keep |Psi|^2
+    stationary: their chains' energy agrees with float32 pair sweeps within 4
+    combined standard errors (6x6, D=4, Dc=8, 256 chains, 4 + 12 sweeps; network
+    with random weights and output bias 0.5, so moves are proposed often)."""
+    import torch
+    B = _B()
+    Ly = Lx = 6
+    T = W.random_tensors(Ly, Lx, 4, seed=606)
+    th = W.random_proposal_weights(seed=61, scale=0.2, bias=0.5)
+    means, prop = {}, 0
+    for prec, learned in ((B.VP_FP32, False), (B.VP_BF16, True)):
+        print(f"chains prec={prec} learned={learned} 6x6 D=4 Dc=8 256 x (4+12)", flush=True)
+        n, nm = 256, 12
+        ctx = B.Context(B.lattice(Ly, Lx, 4, 8, 1.0, 0.0, prec, n), seed=4343)
+        dev = torch.device("cuda")
+        ctx.vp_set_tensors(0, torch.tensor(T, dtype=torch.float64, device=dev))
+        ctx.vp_init_chains(0, None)
+        if learned:
+            ctx.vp_proposal_set_weights(0, torch.tensor(th, device=dev))
+            ctx.vp_set_sampler(0, B.VP_SAMPLER_LEARNED_PLAQ)
+        lp = torch.empty(n * nm, dtype=torch.float64, device=dev)
+        sg = torch.empty(n * nm, dtype=torch.int8, device=dev)
+        el = torch.empty(n * nm, dtype=torch.float64, device=dev)
+        ctx.vp_sample(0, 4, nm, lp, sg, el)
+        ctx.vp_sync()
+        if learned:
+            cnt = torch.empty((n, 4), dtype=torch.int64, device=dev)
+            ctx.vp_move_counts(0, cnt)
+            c = cnt.cpu().numpy().sum(axis=0)
+            prop, acc = c[3], c[2]
+        cm = el.cpu().numpy().reshape(n, nm).mean(axis=1) / (Ly * Lx)
+        means[learned] = (cm.mean(), cm.std(ddof=1) / np.sqrt(n))
+        ctx.close()
+    (m1, s1), (m2, s2) = means[False], means[True]
+    print(f"E/N fp32 pairs {m1:.5f} +- {s1:.5f}   bf16 learned {m2:.5f} +- {s2:.5f}; plaquette moves "
+          f"{acc} of {prop}", flush=True)
+    assert prop > 0 and acc > 0
+    assert abs(m1 - m2) <= 4 * np.hypot(s1, s2)
+

@@ -219,3 +219,61 @@ def test_training_lowers_the_loss():
     ctx.close()
     assert np.all(np.isfinite(ls))
     assert l1.item() < l0.item() and ls[-1] < ls[0]
+
+
+@pytest.mark.parametrize("prec", ["VP_FP64", "VP_FP32", "VP_BF16"])
+def test_sweep_logits_match_oracle(prec):
+    """The network as the learned sweep evaluates it (vp_proposal_logits_sweep: the
+    local 9x9 window of every plaquette, both directions of the move) against the
+    oracle's full-lattice forward pass at the plaquette's top-left site.  float64:
+    1e-12; float32: 1e-5 relative to the largest |logit|; bf16 inference against
+    the oracle's bf16 inference (forward_bf16): median 1e-5 and at most 2e-2 of the
+    largest |logit| (an activation that sits at a bf16 rounding boundary can round
+    the other way under a different float32 summation order), and measurably away
+    from the float64 network (the rounding is really there)."""
+    import torch
+    from oracle import proposal as Pn
+    B = _B()
+    Ly, Lx, n = 6, 8, 6
+    print(f"sweep logits {prec} {Ly}x{Lx}, {n} configurations", flush=True)
+    th = np.random.default_rng(12).normal(scale=0.2, size=Pn.n_params()).astype(np.float32)
+    cfgs = W.random_configs(Ly, Lx, n, seed=13)
+    dev = torch.device("cuda")
+    ctx = B.Context(B.lattice(Ly, Lx, 2, 4, 1.0, 0.0, getattr(B, prec), 1), seed=1)
+    ctx.vp_proposal_set_weights(0, torch.tensor(th, device=dev))
+    sp = torch.tensor(cfgs, dtype=torch.int8, device=dev)
+    P = (Ly - 1) * (Lx - 1)
+    got = {}
+    for flip in (0, 1):
+        out = torch.empty((n, P), dtype=torch.float64, device=dev)
+        ctx.vp_proposal_logits_sweep(0, sp, n, flip, out)
+        torch.cuda.synchronize()
+        got[flip] = out.cpu().numpy()
+    ctx.close()
+    theta = th.astype(np.float64)
+    ref = {0: np.zeros((n, P)), 1: np.zeros((n, P))}
+    ref64 = {0: np.zeros((n, P)), 1: np.zeros((n, P))}
+    fwd = Pn.forward_bf16 if prec == "VP_BF16" else (lambda t, s, a, b: Pn.forward(t, s, a, b)[0])
+    for i in range(n):
+        for q in range(P):
+            y, x = divmod(q, Lx - 1)
+            for flip in (0, 1):
+                s = cfgs[i].reshape(Ly, Lx).copy()
+                if flip:
+                    s[y:y + 2, x:x + 2] ^= 1
+                ref[flip][i, q] = fwd(theta, s.ravel(), Ly, Lx)[y, x]
+                ref64[flip][i, q] = Pn.forward(theta, s.ravel(), Ly, Lx)[0][y, x]
+    scale = max(np.abs(ref[0]).max(), np.abs(ref[1]).max())
+    d = np.concatenate([np.abs(got[f] - ref[f]).ravel() for f in (0, 1)])
+    print(f"{prec}: max |dz| {d.max():.2e}, median {np.median(d):.2e}, largest |z| {scale:.2f}", flush=True)
+    if prec == "VP_FP64":
+        assert d.max() <= 1e-12 * max(1.0, scale)
+    elif prec == "VP_FP32":
+        assert d.max() <= 1e-5 * max(1.0, scale)
+    else:
+        d64 = np.concatenate([np.abs(got[f] - ref64[f]).ravel() for f in (0, 1)])
+        print(f"bf16 against the float64 network: median {np.median(d64):.2e}", flush=True)
+        assert np.median(d) <= 1e-5 * max(1.0, scale)
+        assert d.max() <= 2e-2 * max(1.0, scale)
+        assert np.median(d64) >= 20 * max(np.median(d), 1e-7)
+

@@ -33,10 +33,10 @@ def _bufs(n, m, N, npar, dt):
                 spins_out=torch.empty((n * m, N), dtype=torch.int8, device=dev))
 
 
-def _run(schedule, Ly, Lx, D, Dc, J2, n, T, seed, calls, learned=None):
+def _run(schedule, Ly, Lx, D, Dc, J2, n, T, seed, calls, learned=None, prec=None):
     import torch
     B = _B()
-    ctx = B.Context(B.lattice(Ly, Lx, D, Dc, 1.0, J2, B.VP_FP64, n), seed=seed)
+    ctx = B.Context(B.lattice(Ly, Lx, D, Dc, 1.0, J2, B.VP_FP64 if prec is None else prec, n), seed=seed)
     dev = torch.device("cuda")
     ctx.vp_set_tensors(0, torch.tensor(T, dtype=torch.float64, device=dev))
     ctx.vp_init_chains(0, None)
@@ -84,6 +84,25 @@ def test_schedules_agree_bit_exactly(Ly, Lx, D, Dc, J2, learn):
         assert np.array_equal(rc, gc), sch
     if learn:
         assert rc[:, 3].sum() > 0
+
+
+def test_schedules_agree_bit_exactly_bf16_learned():
+    """The bf16 sampling mode with learned moves (bf16 2-row steps, bf16 inference of
+    the proposal network): phases, persistent queue and graph replay agree bit for bit."""
+    B = _B()
+    Ly, Lx, D, Dc = 4, 6, 8, 16
+    print(f"schedules bf16 learned {Ly}x{Lx} D={D} Dc={Dc}", flush=True)
+    T = W.random_tensors(Ly, Lx, D, seed=98)
+    th = W.random_proposal_weights(seed=91, scale=0.3, bias=0.5)
+    calls = [(1, 3), (0, 2), (2, 2)]
+    ref, rc = _run(B.VP_SCHED_PHASES, Ly, Lx, D, Dc, 0.0, 5, T, 17, calls, th, B.VP_BF16)
+    for sch in (B.VP_SCHED_PERSISTENT, B.VP_SCHED_GRAPH):
+        got, gc = _run(sch, Ly, Lx, D, Dc, 0.0, 5, T, 17, calls, th, B.VP_BF16)
+        for a, b in zip(ref, got):
+            for k in a:
+                assert np.array_equal(a[k], b[k]), (sch, k)
+        assert np.array_equal(rc, gc), sch
+    assert rc[:, 3].sum() > 0 and rc[:, 2].sum() > 0
 
 
 def test_uneven_batch_matches_oracle():
