@@ -216,11 +216,17 @@ class Path:
         for s in range(sweeps):
             self.sweep(spins=True)
             cfgs[s * self.nch:(s + 1) * self.nch].copy_(self.so)
+            if sweeps > 200 and (s + 1) % 500 == 0:
+                self.ctx.vp_sync()
+                print(f"training data: {(s + 1) * self.nch} configurations", file=sys.stderr, flush=True)
         last = self.so.clone()
         rho = torch.empty((sweeps * self.nch, npl), dtype=torch.float64, device=self.dev)
         for s in range(sweeps):
             self.ctx.vp_plaquette_ratios(0, cfgs[s * self.nch:(s + 1) * self.nch], self.nch,
                                          rho[s * self.nch:(s + 1) * self.nch])
+            if sweeps > 200 and (s + 1) % 500 == 0:
+                self.ctx.vp_sync()
+                print(f"training targets: {(s + 1) * self.nch} configurations", file=sys.stderr, flush=True)
         w = torch.tensor(random_proposal_weights(seed=4), device=self.dev)
         self.ctx.vp_proposal_set_weights(0, w)
         loss = torch.empty(epochs, dtype=torch.float64, device=self.dev)
@@ -485,6 +491,13 @@ def main():
     ap.add_argument("--fit-sweeps", type=int, default=2, help="sweeps of the variational fit")
     ap.add_argument("--corr-chains", type=int, default=512,
                     help="chains of the correlated stand-in workload (0: skip it)")
+    ap.add_argument("--corr-L", type=int, default=0, help="lattice of the correlated workload (0: --L)")
+    ap.add_argument("--corr-D", type=int, default=0, help="its bond dimension (0: --D)")
+    ap.add_argument("--corr-Dc", type=int, default=0, help="its cutoff (0: --Dc)")
+    ap.add_argument("--corr-steps", type=int, default=0, help="its timed sweeps (0: --steps)")
+    ap.add_argument("--corr-train-sweeps", type=int, default=0,
+                    help="its training data: pair sweeps of every chain (0: --train-sweeps)")
+    ap.add_argument("--corr-train-epochs", type=int, default=0, help="its training epochs (0: --train-epochs)")
     ap.add_argument("--corr-burn", type=int, default=20,
                     help="untimed sweeps from the chain starts before the correlated workload's timed region")
     ap.add_argument("--also-fit", type=int, default=2,
@@ -600,29 +613,38 @@ def main():
             def cost(t):
                 return 2.0 * t["tau_int_mean"] / t["samples_per_s"]
             out["learned_over_plain_at_fixed_dE_long_run"] = cost(res["plain"]["tau"]) / cost(res["learned"]["tau"])
-    if args.corr_chains and args.compress == "canonical" and args.only == "both" and args.steps >= 2:
-        Tc, info = correlated_tensors(B, torch, Ly, D)
+    cL, cD, cDc = args.corr_L or Ly, args.corr_D or D, args.corr_Dc or Dc
+    c_steps = args.corr_steps or args.steps
+    c_tsw, c_tep = args.corr_train_sweeps or args.train_sweeps, args.corr_train_epochs or args.train_epochs
+    if args.corr_chains and args.compress == "canonical" and args.only == "both" and c_steps >= 2:
+        Tc, info = correlated_tensors(B, torch, cL, cD)
+        info.update({"L": cL, "D": cD, "Dc": cDc, "timed_sweeps": c_steps})
         print(f"correlated workload: simple update, lambda change {info['su_change_first']:.2e} -> "
               f"{info['su_change_last']:.2e} in {info['seconds']:.1f} s", file=sys.stderr, flush=True)
         cres = {}
         nc = args.corr_chains
         for name, prec in (("plain", B.VP_FP32), ("learned", B.VP_BF16)):
-            p = Path(B, torch, Ly, Lx, D, Dc, prec, nc, T=Tc)
+            p = Path(B, torch, cL, cL, cD, cDc, prec, nc, T=Tc)
             # equilibrate from the random starts before anything is trained or timed
             for _ in range(args.corr_burn):
                 p.sweep()
+            tr = None
             if name == "learned":
-                p.train_proposal(args.train_sweeps, args.train_epochs, 256, 3e-3)
-            r = p.timed(args.warmup, args.steps)
+                tr = p.train_proposal(c_tsw, c_tep, 256, 3e-3)
+                print(f"correlated learned: trained on {tr['configs']} configurations, loss {tr['loss_first_epoch']:.4f}"
+                      f" -> {tr['loss_last_epoch']:.4f} in {tr['seconds']:.1f} s", file=sys.stderr, flush=True)
+            r = p.timed(args.warmup, c_steps)
             r["stats"] = p.series_stats()
-            r["fp64_reference"] = fp64_reference(B, torch, Ly, Lx, D, Dc, p.last_spins, p.el, nc, T=Tc)
+            r["fp64_reference"] = fp64_reference(B, torch, cL, cL, cD, cDc, p.last_spins, p.el, nc, T=Tc)
+            if tr is not None:
+                r["training"] = tr
             print(f"correlated {name}: {r['samples_per_s']:.1f} samples/s, tau_int(E) "
                   f"{r['stats']['e_site']['tau_int_mean']:.3f}, tau_int(Mz^2) {r['stats']['mz2']['tau_int_mean']:.3f}, "
                   f"E/N {r['stats']['e_site']['mean']:.5f} +- {r['stats']['e_site']['stderr']:.5f}",
                   file=sys.stderr, flush=True)
             cres[name] = {k: r[k] for k in ("samples_per_s", "ms_per_step", "seconds", "pair_accept",
                                              "plaquette_accept", "plaquette_proposed_per_sweep", "stats",
-                                             "fp64_reference")}
+                                             "fp64_reference", "training") if k in r}
             p.close()
             del p
             torch.cuda.empty_cache()
