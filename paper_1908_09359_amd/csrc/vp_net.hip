@@ -59,32 +59,62 @@ __global__ void k_net_input(const int8_t* __restrict__ spins, int64_t total, flo
     x[i] = spins[i] ? -1.0f : 1.0f;
 }
 
-// out[b][co][y][x] = b[co] + sum W[co][ci][ky][kx] in[b][ci][y+ky-1][x+kx-1] (zero outside), ReLU if relu.
-__global__ void k_conv_fwd(const float* __restrict__ in, int Ci, const float* __restrict__ W,
-                           const float* __restrict__ bias, int Co, float* __restrict__ out, int n, int H, int Wd,
-                           int relu) {
-  const int64_t total = (int64_t)n * Co * H * Wd;
-  for (int64_t i = blockIdx.x * (int64_t)WG + threadIdx.x; i < total; i += (int64_t)gridDim.x * WG) {
-    const int x = (int)(i % Wd), y = (int)((i / Wd) % H);
-    const int co = (int)((i / ((int64_t)H * Wd)) % Co);
-    const int64_t b = i / ((int64_t)Co * H * Wd);
-    float acc = bias[co];
-    const float* w = W + (int64_t)co * Ci * 9;
-    const float* src = in + b * Ci * H * Wd;
-    for (int ci = 0; ci < Ci; ++ci) {
+// The 3x3 convolutions of training and of the batched forward pass as
+// implicit GEMMs on the fp32 MFMA (16x16x4, float32 accumulation).  A
+// work-group takes 64 rows of the batch's positions (b, y, x); wave w owns rows
+// 16 w .. 16 w + 15 against every 16-column tile.  The contraction index k
+// runs over (tap, channel), tap = 3 ky + kx, padded to a multiple of 4; the
+// weight matrix is staged in LDS with rows of KP + 1 floats (the 16 columns a
+// step reads then fall in distinct banks).  Positions outside the lattice read
+// zero (the zero padding of every layer).
+constexpr int CONV_ROWS = 64;
+
+template <int CI, int CO>
+struct ConvShape {
+  static constexpr int K = 9 * CI, KP = (K + 3) / 4 * 4, NT = (CO + 15) / 16, LD = KP + 1;
+};
+
+// out[b][co][y][x] = bias[co] + sum W[co][ci][ky][kx] in[b][ci][y+ky-1][x+kx-1], ReLU if RELU.
+template <int CI, int CO, bool RELU>
+__global__ void __launch_bounds__(WG) k_conv_fwd(const float* __restrict__ in, const float* __restrict__ W,
+                                                 const float* __restrict__ bias, float* __restrict__ out, int n, int H,
+                                                 int Wd) {
+  using S = ConvShape<CI, CO>;
+  __shared__ float Wl[S::NT * 16 * S::LD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int e = tid; e < S::NT * 16 * S::KP; e += WG) {
+    const int co = e / S::KP, k = e % S::KP, tap = k / CI, ci = k % CI;
+    Wl[co * S::LD + k] = (co < CO && k < S::K) ? W[(co * CI + ci) * 9 + tap] : 0.0f;
+  }
+  __syncthreads();
+  const int HW = H * Wd;
+  const int64_t rows = (int64_t)n * HW;
+  const int64_t r = (int64_t)blockIdx.x * CONV_ROWS + 16 * wave + (lane & 15);
+  const bool valid = r < rows;
+  const int64_t b = valid ? r / HW : 0;
+  const int p = valid ? (int)(r % HW) : 0, y = p / Wd, x = p % Wd;
+  v4f_g acc[S::NT];
 #pragma unroll
-      for (int ky = 0; ky < 3; ++ky) {
-        const int yy = y + ky - 1;
-        if (yy < 0 || yy >= H) continue;
+  for (int t = 0; t < S::NT; ++t) acc[t] = v4f_g{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int k0 = 0; k0 < S::KP; k0 += 4) {
+    const int k = k0 + (lane >> 4), tap = k / CI, ci = k % CI;
+    const int yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
+    const float a = (valid && k < S::K && yy >= 0 && yy < H && xx >= 0 && xx < Wd)
+                        ? in[(b * CI + ci) * HW + yy * Wd + xx] : 0.0f;
 #pragma unroll
-        for (int kx = 0; kx < 3; ++kx) {
-          const int xx = x + kx - 1;
-          if (xx < 0 || xx >= Wd) continue;
-          acc += w[ci * 9 + ky * 3 + kx] * src[((int64_t)ci * H + yy) * Wd + xx];
-        }
+    for (int t = 0; t < S::NT; ++t) acc[t] = mfma4(a, Wl[(16 * t + (lane & 15)) * S::LD + k], acc[t]);
+  }
+#pragma unroll
+  for (int t = 0; t < S::NT; ++t) {
+    const int co = 16 * t + (lane & 15);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t rr = (int64_t)blockIdx.x * CONV_ROWS + 16 * wave + mfma4_row(0.0f, lane, q);
+      if (co < CO && rr < rows) {
+        const float v = acc[t][q] + bias[co];
+        out[((rr / HW) * CO + co) * HW + rr % HW] = RELU ? fmaxf(v, 0.0f) : v;
       }
     }
-    out[i] = relu ? fmaxf(acc, 0.0f) : acc;
   }
 }
 
@@ -141,63 +171,119 @@ __global__ void k_scale(float* __restrict__ v, int64_t n, const double* __restri
   for (int64_t i = blockIdx.x * (int64_t)WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * WG) v[i] *= f;
 }
 
-// din[b][ci][y][x] = [act(b,ci,y,x) > 0] sum_{co,ky,kx} W[co][ci][ky][kx] dout[b][co][y-ky+1][x-kx+1]
-__global__ void k_conv_bwd_data(const float* __restrict__ dout, int Co, const float* __restrict__ W, int Ci,
-                                const float* __restrict__ act, float* __restrict__ din, int n, int H, int Wd) {
-  const int64_t total = (int64_t)n * Ci * H * Wd;
-  for (int64_t i = blockIdx.x * (int64_t)WG + threadIdx.x; i < total; i += (int64_t)gridDim.x * WG) {
-    if (!(act[i] > 0.0f)) {
-      din[i] = 0.0f;
-      continue;
-    }
-    const int x = (int)(i % Wd), y = (int)((i / Wd) % H);
-    const int ci = (int)((i / ((int64_t)H * Wd)) % Ci);
-    const int64_t b = i / ((int64_t)Ci * H * Wd);
-    const float* g = dout + b * Co * H * Wd;
-    float acc = 0.0f;
-    for (int co = 0; co < Co; ++co) {
-      const float* w = W + ((int64_t)co * Ci + ci) * 9;
+// din[b][ci][y][x] = [act(b,ci,y,x) > 0] sum_{co,ky,kx} W[co][ci][ky][kx] dout[b][co][y-ky+1][x-kx+1],
+// the same implicit GEMM with k over (tap, co) and the transposed weights in LDS.
+template <int CO, int CI>
+__global__ void __launch_bounds__(WG) k_conv_bwd_data(const float* __restrict__ dout, const float* __restrict__ W,
+                                                      const float* __restrict__ act, float* __restrict__ din, int n,
+                                                      int H, int Wd) {
+  using S = ConvShape<CO, CI>;  // contraction over (tap, co), columns ci
+  __shared__ float Wl[S::NT * 16 * S::LD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int e = tid; e < S::NT * 16 * S::KP; e += WG) {
+    const int ci = e / S::KP, k = e % S::KP, tap = k / CO, co = k % CO;
+    Wl[ci * S::LD + k] = (ci < CI && k < S::K) ? W[(co * CI + ci) * 9 + tap] : 0.0f;
+  }
+  __syncthreads();
+  const int HW = H * Wd;
+  const int64_t rows = (int64_t)n * HW;
+  const int64_t r = (int64_t)blockIdx.x * CONV_ROWS + 16 * wave + (lane & 15);
+  const bool valid = r < rows;
+  const int64_t b = valid ? r / HW : 0;
+  const int p = valid ? (int)(r % HW) : 0, y = p / Wd, x = p % Wd;
+  v4f_g acc[S::NT];
 #pragma unroll
-      for (int ky = 0; ky < 3; ++ky) {
-        const int yy = y - ky + 1;
-        if (yy < 0 || yy >= H) continue;
+  for (int t = 0; t < S::NT; ++t) acc[t] = v4f_g{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int k0 = 0; k0 < S::KP; k0 += 4) {
+    const int k = k0 + (lane >> 4), tap = k / CO, co = k % CO;
+    const int yy = y - tap / 3 + 1, xx = x - tap % 3 + 1;
+    const float a = (valid && k < S::K && yy >= 0 && yy < H && xx >= 0 && xx < Wd)
+                        ? dout[(b * CO + co) * HW + yy * Wd + xx] : 0.0f;
 #pragma unroll
-        for (int kx = 0; kx < 3; ++kx) {
-          const int xx = x - kx + 1;
-          if (xx < 0 || xx >= Wd) continue;
-          acc += w[ky * 3 + kx] * g[((int64_t)co * H + yy) * Wd + xx];
-        }
+    for (int t = 0; t < S::NT; ++t) acc[t] = mfma4(a, Wl[(16 * t + (lane & 15)) * S::LD + k], acc[t]);
+  }
+#pragma unroll
+  for (int t = 0; t < S::NT; ++t) {
+    const int ci = 16 * t + (lane & 15);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t rr = (int64_t)blockIdx.x * CONV_ROWS + 16 * wave + mfma4_row(0.0f, lane, q);
+      if (ci < CI && rr < rows) {
+        const int64_t o = ((rr / HW) * CI + ci) * HW + rr % HW;
+        din[o] = act[o] > 0.0f ? acc[t][q] : 0.0f;
       }
     }
-    din[i] = acc;
   }
 }
 
-// One work-group per weight (co, ci, ky, kx) and per bias co:
-//   gW = sum_{b,y,x} dout[b][co][y][x] in[b][ci][y+ky-1][x+kx-1],  gb = sum dout[b][co][y][x].
-__global__ void k_conv_bwd_weight(const float* __restrict__ dout, int Co, const float* __restrict__ in, int Ci,
-                                  float* __restrict__ gW, float* __restrict__ gb, int n, int H, int Wd) {
-  const int nw = Co * Ci * 9;
-  const int j = blockIdx.x;
+// Weight gradient gW[co][(ci, tap)] = sum over positions of dout[b][co][p] in[b][ci][p + tap offset]:
+// an implicit GEMM (rows co, columns (ci, tap)) whose contraction runs over the
+// batch's positions, split into chunks of CONV_WCHUNK positions, one
+// work-group per chunk writing its partial product; wave w owns tiles
+// w, w + 4, ... of the (CO / 16) x (9 CI / 16) output tiles.
+constexpr int CONV_WCHUNK = 256;
+
+template <int CO, int CI>
+__global__ void __launch_bounds__(WG) k_conv_wgrad_part(const float* __restrict__ dout, const float* __restrict__ in,
+                                                        float* __restrict__ part, int n, int H, int Wd) {
+  constexpr int MT = (CO + 15) / 16, NC = 9 * CI, NTN = (NC + 15) / 16, NTILE = MT * NTN;
+  constexpr int TW = (NTILE + 3) / 4;  // tiles per wave
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int HW = H * Wd;
+  const int64_t rows = (int64_t)n * HW, r0 = (int64_t)blockIdx.x * CONV_WCHUNK;
+  v4f_g acc[TW];
+#pragma unroll
+  for (int j = 0; j < TW; ++j) acc[j] = v4f_g{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int k0 = 0; k0 < CONV_WCHUNK; k0 += 4) {
+    const int64_t r = r0 + k0 + (lane >> 4);
+    const bool valid = r < rows;
+    const int64_t b = valid ? r / HW : 0;
+    const int p = valid ? (int)(r % HW) : 0, y = p / Wd, x = p % Wd;
+#pragma unroll
+    for (int j = 0; j < TW; ++j) {
+      const int tile = wave + 4 * j;
+      if (tile < NTILE) {  // uniform over the wavefront
+        const int mt = tile / NTN, nt = tile % NTN;
+        const int co = 16 * mt + (lane & 15), col = 16 * nt + (lane & 15);
+        const float a = (valid && co < CO) ? dout[(b * CO + co) * HW + p] : 0.0f;
+        const int ci = col / 9, tap = col % 9, yy = y + tap / 3 - 1, xx = x + tap % 3 - 1;
+        const float bv = (valid && col < NC && yy >= 0 && yy < H && xx >= 0 && xx < Wd)
+                             ? in[(b * CI + ci) * HW + yy * Wd + xx] : 0.0f;
+        acc[j] = mfma4(a, bv, acc[j]);
+      }
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < TW; ++j) {
+    const int tile = wave + 4 * j;
+    if (tile < NTILE) {
+      const int mt = tile / NTN, nt = tile % NTN, col = 16 * nt + (lane & 15);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int co = 16 * mt + mfma4_row(0.0f, lane, q);
+        if (co < CO && col < NC) part[((int64_t)blockIdx.x * CO + co) * NC + col] = acc[j][q];
+      }
+    }
+  }
+}
+
+// gW[j] = sum over the chunks of part[c][j] (float64, chunk order); gb[co] =
+// sum over positions of dout[b][co][p] (float64, fixed order; one work-group per co).
+__global__ void k_conv_wgrad_sum(const float* __restrict__ part, int nchunk, int nw, float* __restrict__ gW) {
+  for (int j = blockIdx.x * WG + threadIdx.x; j < nw; j += gridDim.x * WG) {
+    double acc = 0.0;
+    for (int c = 0; c < nchunk; ++c) acc += (double)part[(int64_t)c * nw + j];
+    gW[j] = (float)acc;
+  }
+}
+
+__global__ void k_conv_bgrad(const float* __restrict__ dout, int Co, float* __restrict__ gb, int n, int H, int Wd) {
+  const int co = blockIdx.x;
   const int64_t HW = (int64_t)H * Wd, total = (int64_t)n * HW;
   double acc = 0.0;
-  if (j < nw) {
-    const int co = j / (Ci * 9), ci = (j / 9) % Ci, ky = (j % 9) / 3, kx = j % 3;
-    for (int64_t i = threadIdx.x; i < total; i += WG) {
-      const int64_t b = i / HW;
-      const int p = (int)(i % HW), y = p / Wd + ky - 1, x = p % Wd + kx - 1;
-      if (y < 0 || y >= H || x < 0 || x >= Wd) continue;
-      acc += (double)dout[(b * Co + co) * HW + p] * (double)in[(b * Ci + ci) * HW + (int64_t)y * Wd + x];
-    }
-  } else {
-    const int co = j - nw;
-    for (int64_t i = threadIdx.x; i < total; i += WG) acc += (double)dout[((i / HW) * Co + co) * HW + i % HW];
-  }
+  for (int64_t i = threadIdx.x; i < total; i += WG) acc += (double)dout[((i / HW) * Co + co) * HW + i % HW];
   acc = wg_sum(acc);
-  if (threadIdx.x == 0) {
-    if (j < nw) gW[j] = (float)acc;
-    else gb[j - nw] = (float)acc;
-  }
+  if (threadIdx.x == 0) gb[co] = (float)acc;
 }
 
 // Adam (Kingma & Ba, 2015) with bias correction; t is the 1-based step.
@@ -284,10 +370,25 @@ size_t net_forward_floats(int n, int H, int Wd) {
   return (size_t)n * H * Wd * (1 + 3 * NET_CH);
 }
 
+static size_t wgrad_chunks(int n, int H, int Wd) { return ((size_t)n * H * Wd + CONV_WCHUNK - 1) / CONV_WCHUNK; }
+
 size_t net_work_floats(int n, int H, int Wd) {
   const size_t HW = (size_t)H * Wd;
-  // x, a1, a2, a3, z, d3, d2, d1 (dz shares z's shape)
-  return (size_t)n * HW * (1 + 3 * NET_CH + 1 + 1 + 3 * NET_CH);
+  // x, a1, a2, a3, z, d3, d2, d1 (dz shares z's shape), then the weight-gradient partials
+  return (size_t)n * HW * (1 + 3 * NET_CH + 1 + 1 + 3 * NET_CH) + wgrad_chunks(n, H, Wd) * NET_CH * NET_CH * 9;
+}
+
+template <int CO, int CI>
+static void wgrad(const float* dout, const float* in, float* part, float* gW, float* gb, int n, int H, int Wd,
+                  hipStream_t s) {
+  const int nchunk = (int)wgrad_chunks(n, H, Wd), nw = CO * CI * 9;
+  hipLaunchKernelGGL((k_conv_wgrad_part<CO, CI>), dim3(nchunk), dim3(WG), 0, s, dout, in, part, n, H, Wd);
+  hipLaunchKernelGGL(k_conv_wgrad_sum, dim3(grid_for(nw)), dim3(WG), 0, s, part, nchunk, nw, gW);
+  hipLaunchKernelGGL(k_conv_bgrad, dim3(CO), dim3(WG), 0, s, dout, CO, gb, n, H, Wd);
+}
+
+static unsigned conv_grid(int n, int H, int Wd) {
+  return (unsigned)(((int64_t)n * H * Wd + CONV_ROWS - 1) / CONV_ROWS);
 }
 
 void net_forward(const float* th, const int8_t* spins, int n, int H, int Wd, float* work, float* logits,
@@ -297,15 +398,16 @@ void net_forward(const float* th, const int8_t* spins, int n, int H, int Wd, flo
   float* a1 = x + n * HW;
   float* a2 = a1 + n * NET_CH * HW;
   float* a3 = a2 + n * NET_CH * HW;
+  const unsigned g = conv_grid(n, H, Wd);
   hipLaunchKernelGGL(k_net_input, dim3(grid_for(n * HW)), dim3(WG), 0, s, spins, n * HW, x);
-  hipLaunchKernelGGL(k_conv_fwd, dim3(grid_for(n * NET_CH * HW)), dim3(WG), 0, s, x, 1, th + NET_OFF_W1,
-                     th + NET_OFF_B1, NET_CH, a1, n, H, Wd, 1);
-  hipLaunchKernelGGL(k_conv_fwd, dim3(grid_for(n * NET_CH * HW)), dim3(WG), 0, s, a1, NET_CH, th + NET_OFF_W2,
-                     th + NET_OFF_B2, NET_CH, a2, n, H, Wd, 1);
-  hipLaunchKernelGGL(k_conv_fwd, dim3(grid_for(n * NET_CH * HW)), dim3(WG), 0, s, a2, NET_CH, th + NET_OFF_W3,
-                     th + NET_OFF_B3, NET_CH, a3, n, H, Wd, 1);
-  hipLaunchKernelGGL(k_conv_fwd, dim3(grid_for(n * HW)), dim3(WG), 0, s, a3, NET_CH, th + NET_OFF_W4,
-                     th + NET_OFF_B4, 1, logits, n, H, Wd, 0);
+  hipLaunchKernelGGL((k_conv_fwd<1, NET_CH, true>), dim3(g), dim3(WG), 0, s, x, th + NET_OFF_W1, th + NET_OFF_B1, a1,
+                     n, H, Wd);
+  hipLaunchKernelGGL((k_conv_fwd<NET_CH, NET_CH, true>), dim3(g), dim3(WG), 0, s, a1, th + NET_OFF_W2,
+                     th + NET_OFF_B2, a2, n, H, Wd);
+  hipLaunchKernelGGL((k_conv_fwd<NET_CH, NET_CH, true>), dim3(g), dim3(WG), 0, s, a2, th + NET_OFF_W3,
+                     th + NET_OFF_B3, a3, n, H, Wd);
+  hipLaunchKernelGGL((k_conv_fwd<NET_CH, 1, false>), dim3(g), dim3(WG), 0, s, a3, th + NET_OFF_W4, th + NET_OFF_B4,
+                     logits, n, H, Wd);
 }
 
 void net_loss_grad(const float* th, const int8_t* spins, const double* ratios, int n, int H, int Wd, float* work,
@@ -324,24 +426,21 @@ void net_loss_grad(const float* th, const int8_t* spins, const double* ratios, i
   hipLaunchKernelGGL(k_plaq_loss, dim3(n), dim3(WG), 0, s, z, spins, ratios, H, Wd, dz, part, cnt);
   hipLaunchKernelGGL(k_loss_total, dim3(1), dim3(WG), 0, s, part, cnt, n, scal);
   hipLaunchKernelGGL(k_scale, dim3(grid_for(n * HW)), dim3(WG), 0, s, dz, n * HW, (const double*)scal);
+  float* wpart = d1 + n * NET_CH * HW;
+  const unsigned g = conv_grid(n, H, Wd);
   // layer 4
-  hipLaunchKernelGGL(k_conv_bwd_weight, dim3(NET_CH * 9 + 1), dim3(WG), 0, s, dz, 1, a3, NET_CH,
-                     grad + NET_OFF_W4, grad + NET_OFF_B4, n, H, Wd);
-  hipLaunchKernelGGL(k_conv_bwd_data, dim3(grid_for(n * NET_CH * HW)), dim3(WG), 0, s, dz, 1, th + NET_OFF_W4,
-                     NET_CH, a3, d3, n, H, Wd);
+  wgrad<1, NET_CH>(dz, a3, wpart, grad + NET_OFF_W4, grad + NET_OFF_B4, n, H, Wd, s);
+  hipLaunchKernelGGL((k_conv_bwd_data<1, NET_CH>), dim3(g), dim3(WG), 0, s, dz, th + NET_OFF_W4, a3, d3, n, H, Wd);
   // layer 3
-  hipLaunchKernelGGL(k_conv_bwd_weight, dim3(NET_CH * NET_CH * 9 + NET_CH), dim3(WG), 0, s, d3, NET_CH, a2, NET_CH,
-                     grad + NET_OFF_W3, grad + NET_OFF_B3, n, H, Wd);
-  hipLaunchKernelGGL(k_conv_bwd_data, dim3(grid_for(n * NET_CH * HW)), dim3(WG), 0, s, d3, NET_CH,
-                     th + NET_OFF_W3, NET_CH, a2, d2, n, H, Wd);
+  wgrad<NET_CH, NET_CH>(d3, a2, wpart, grad + NET_OFF_W3, grad + NET_OFF_B3, n, H, Wd, s);
+  hipLaunchKernelGGL((k_conv_bwd_data<NET_CH, NET_CH>), dim3(g), dim3(WG), 0, s, d3, th + NET_OFF_W3, a2, d2, n, H,
+                     Wd);
   // layer 2
-  hipLaunchKernelGGL(k_conv_bwd_weight, dim3(NET_CH * NET_CH * 9 + NET_CH), dim3(WG), 0, s, d2, NET_CH, a1, NET_CH,
-                     grad + NET_OFF_W2, grad + NET_OFF_B2, n, H, Wd);
-  hipLaunchKernelGGL(k_conv_bwd_data, dim3(grid_for(n * NET_CH * HW)), dim3(WG), 0, s, d2, NET_CH,
-                     th + NET_OFF_W2, NET_CH, a1, d1, n, H, Wd);
+  wgrad<NET_CH, NET_CH>(d2, a1, wpart, grad + NET_OFF_W2, grad + NET_OFF_B2, n, H, Wd, s);
+  hipLaunchKernelGGL((k_conv_bwd_data<NET_CH, NET_CH>), dim3(g), dim3(WG), 0, s, d2, th + NET_OFF_W2, a1, d1, n, H,
+                     Wd);
   // layer 1 (its input is the spin map: no further backward)
-  hipLaunchKernelGGL(k_conv_bwd_weight, dim3(NET_CH * 9 + NET_CH), dim3(WG), 0, s, d1, NET_CH, x, 1,
-                     grad + NET_OFF_W1, grad + NET_OFF_B1, n, H, Wd);
+  wgrad<NET_CH, 1>(d1, x, wpart, grad + NET_OFF_W1, grad + NET_OFF_B1, n, H, Wd, s);
 }
 
 void net_adam(float* th, const float* g, float* m, float* v, float lr, int t, hipStream_t s) {
