@@ -23,9 +23,15 @@
  *   of the occupied slot s_k (the other slot is zero by construction).
  * Hamiltonian (Sec. II.A Eq. (3), App. C Eq. (Elocal)):
  *   H = J1 sum_NN S_i.S_j + J2 sum_diag S_i.S_j, S = sigma/2.
+ *   VP_GEOM_TRIANGULAR (Sec. III.B, Fig. 7(a): the triangular lattice drawn
+ *   on the square grid): the diagonal (y,x)-(y+1,x+1) of every plaquette is a
+ *   nearest-neighbour bond (coupling J1) and the other diagonal is uncoupled;
+ *   the triangular J2 bonds (the other diagonal and the (2,1), (1,2) vectors)
+ *   are not built, so J2 must be 0 there.
  * Pair order (the "ratios" outputs): horizontal bonds row by row, then
  *   vertical bonds row by row, then for every plaquette (y, x) the two
- *   diagonals (y,x)-(y+1,x+1) and (y,x+1)-(y+1,x) when J2 != 0.
+ *   diagonals (y,x)-(y+1,x+1) and (y,x+1)-(y+1,x) when a diagonal is coupled
+ *   (J2 != 0, or the triangular geometry); an uncoupled diagonal's ratio is 0.
  * Contraction (App. B, App. C): boundary MPS truncated to Dc by the canonical
  *   SVD compression (left-to-right orthogonalisation, right-to-left truncation
  *   keeping the Dc largest singular values); 3-line row networks for
@@ -112,6 +118,10 @@ typedef enum { VP_SAMPLER_PAIR_SEQ = 0, VP_SAMPLER_LEARNED_PLAQ = 1 } vp_sampler
  * skips it (its time reads -1). */
 typedef enum { VP_COMPRESS_CANONICAL = 0, VP_COMPRESS_VARIATIONAL = 1 } vp_compress;
 
+/* Lattice geometry of the Hamiltonian (see "Hamiltonian" above); the PEPS is
+ * the square-lattice one in both. */
+typedef enum { VP_GEOM_SQUARE = 0, VP_GEOM_TRIANGULAR = 1 } vp_geometry;
+
 typedef struct {
   int32_t Ly, Lx;      /* lattice extent */
   int32_t D;           /* PEPS virtual bond dimension */
@@ -121,6 +131,7 @@ typedef struct {
   int32_t n_chains;    /* Markov chains kept on the device */
   int32_t compress;    /* vp_compress (0 = canonical, the zero-initialised default) */
   int32_t fit_sweeps;  /* sweeps of VP_COMPRESS_VARIATIONAL (0..64) */
+  int32_t geometry;    /* vp_geometry (0 = square, the zero-initialised default) */
 } vp_lattice;
 
 typedef struct vp_ctx vp_ctx;
@@ -232,7 +243,8 @@ vp_status vp_trace_ratios(vp_ctx* ctx, int32_t lat, double* trace_dev);
 /* Evaluate fixed configurations spins_dev [n_cfg][N] (n_cfg <= n_chains):
  * the same outputs as one measured sweep without Metropolis moves, plus every
  * pair ratio (ratios_dev [n_cfg][n_pairs], 0 for parallel pairs; may be NULL).
- * n_pairs = Ly(Lx-1) + (Ly-1)Lx (+ 2(Ly-1)(Lx-1) when J2 != 0). */
+ * n_pairs = Ly(Lx-1) + (Ly-1)Lx (+ 2(Ly-1)(Lx-1) when a diagonal is coupled:
+ * J2 != 0 or VP_GEOM_TRIANGULAR). */
 vp_status vp_eval(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev, int32_t n_cfg,
                   double* log_abs_psi_dev, int8_t* sign_dev, double* e_loc_dev,
                   void* dlnpsi_dev, double* ratios_dev);
@@ -393,7 +405,7 @@ vp_status vp_optimize(vp_ctx* ctx, int32_t lat, int32_t n_steps, int32_t n_burn,
  * reduced two-site tensor (lambda of the link between), its truncated SVD
  * gives the new lambda (the leading D singular values above 1e-6 of the
  * largest, normalised to unit 2-norm) and the new tensors, from which the
- * outer lambdas are divided out again.  Per diagonal (Fig. 7): the pair is
+ * outer lambdas are divided out again.  Per diagonal (Fig. 8): the pair is
  * joined through a corner site ((y,x)-(y+1,x+1) through (y,x+1),
  * (y,x+1)-(y+1,x) through (y,x)); the end tensors are QR-reduced, the gate
  * acts on the reduced three-site tensor, and two truncated SVDs give both

@@ -13,6 +13,12 @@ Conventions (the paper leaves these open; readings are listed in the design note
 * H = J1 sum_NN S_i.S_j + J2 sum_diag S_i.S_j with S = sigma/2 and open
   boundaries (Sec. III.A; the Hamiltonian elements of App. C Eq. (Elocal)).
   Pinned by reproducing exact-diagonalisation energies printed in Table III.
+* The triangular lattice on the square grid (Sec. III.B, Fig. 7(a)): one
+  diagonal of every plaquette, here (y,x)-(y+1,x+1), is a nearest-neighbour
+  bond of coupling J1; the other diagonal is uncoupled.  Its J2 bonds (the
+  other diagonal and the (2,1), (1,2) vectors) are not covered, so J2 must be
+  0 there; on the open 4x4 lattice the choice of diagonal does not change the
+  spectrum (a mirror image).
 """
 import numpy as np
 
@@ -22,15 +28,27 @@ from . import philox
 class Lattice:
     """An Ly x Lx open-boundary square lattice carrying a PEPS of bond dimension D."""
 
-    def __init__(self, Ly, Lx, D, Dc, J1=1.0, J2=0.0, compress_mode="canonical", fit_sweeps=2):
+    def __init__(self, Ly, Lx, D, Dc, J1=1.0, J2=0.0, compress_mode="canonical", fit_sweeps=2,
+                 geometry="square"):
         """compress_mode: the boundary truncation, "canonical" (SVD compression)
-        or "variational" (the fit of App. B with fit_sweeps sweeps)."""
+        or "variational" (the fit of App. B with fit_sweeps sweeps).  geometry:
+        "square" (J2 on both diagonals) or "triangular" (J1 on the diagonal
+        (y,x)-(y+1,x+1), J2 = 0)."""
         if Ly < 1 or Lx < 1 or D < 1 or Dc < 1:
             raise ValueError("lattice sizes, D and Dc must be >= 1")
         if compress_mode not in ("canonical", "variational") or fit_sweeps < 0:
             raise ValueError("compress_mode is canonical or variational, fit_sweeps >= 0")
+        if geometry not in ("square", "triangular"):
+            raise ValueError("geometry is square or triangular")
+        if geometry == "triangular" and J2 != 0.0:
+            raise ValueError("triangular lattice: its J2 bonds are not covered, J2 must be 0")
         self.Ly, self.Lx, self.D, self.Dc = int(Ly), int(Lx), int(D), int(Dc)
         self.J1, self.J2 = float(J1), float(J2)
+        self.geometry = geometry
+        # couplings of the diagonal (y,x)-(y+1,x+1) and anti-diagonal (y,x+1)-(y+1,x) of a plaquette
+        self.Jd = self.J1 if geometry == "triangular" else self.J2
+        self.Ja = 0.0 if geometry == "triangular" else self.J2
+        self.diagonals = self.Jd != 0.0 or self.Ja != 0.0
         self.compress_mode, self.fit_sweeps = compress_mode, int(fit_sweeps)
         self.N = self.Ly * self.Lx
         self.offsets = []
@@ -78,7 +96,8 @@ def compact_offsets(lat):
 # --------------------------------------------------------------------------
 
 def bonds(lat):
-    """All interacting pairs ((y1,x1), (y2,x2), J): NN horizontal, NN vertical, both diagonals."""
+    """All interacting pairs ((y1,x1), (y2,x2), J): NN horizontal, NN vertical, and
+    when a diagonal is coupled both diagonals of every plaquette (an uncoupled one with J = 0)."""
     out = []
     for y in range(lat.Ly):
         for x in range(lat.Lx - 1):
@@ -86,11 +105,11 @@ def bonds(lat):
     for y in range(lat.Ly - 1):
         for x in range(lat.Lx):
             out.append(((y, x), (y + 1, x), lat.J1))
-    if lat.J2 != 0.0:
+    if lat.diagonals:
         for y in range(lat.Ly - 1):
             for x in range(lat.Lx - 1):
-                out.append(((y, x), (y + 1, x + 1), lat.J2))
-                out.append(((y, x + 1), (y + 1, x), lat.J2))
+                out.append(((y, x), (y + 1, x + 1), lat.Jd))
+                out.append(((y, x + 1), (y + 1, x), lat.Ja))
     return out
 
 

@@ -6,7 +6,7 @@ The PEPS is held as site tensors B_k (same layout as the parameter vector:
 B_k[s][l, u, r, d]) and a diagonal matrix lambda on every link between
 nearest neighbours (App. A: the environment of a tensor approximated by these
 diagonal matrices).  A step applies exp(-dt J S_i.S_j) once to every
-nearest-neighbour link; each application (App. A, Fig. 7 (b)-(h), here with
+nearest-neighbour link; each application (App. A, Fig. 8 (b)-(h), here with
 two sites instead of three):
 
 1. the lambdas of the outer links are contracted into both site tensors;
@@ -29,8 +29,8 @@ into each of the two tensors of every link (App. A's last step).  The
 convergence measure is App. A's: the mean over links of
 ||lambda(t+dt) - lambda(t)|| / ||lambda(t)|| over one step.
 
-Next-nearest-neighbour terms (J2, both diagonals of every plaquette) follow
-Fig. 7: the pair (B_1, B_3) is joined through a corner site B_2 (reading: the
+Diagonal terms (J2 on both diagonals of every plaquette; on the triangular
+lattice J1 on the diagonal (y,x)-(y+1,x+1) alone) follow Fig. 8: the pair (B_1, B_3) is joined through a corner site B_2 (reading: the
 diagonal (y,x)-(y+1,x+1) through (y,x+1), the anti-diagonal (y,x+1)-(y+1,x)
 through (y,x)); B_1 and B_3 with their outer lambdas are QR-reduced to R_1
 and R_3; the gate acts on the physical legs of B_1 and B_3 of
@@ -165,7 +165,7 @@ def _truncated_svd(Theta, kdim):
 
 
 def su_bond(B, lam, lat, a, b, leg_a, leg_b, G, reduced=True):
-    """Apply the gate G to the link between sites a and b (App. A, Fig. 7), in place.
+    """Apply the gate G to the link between sites a and b (App. A, Fig. 8), in place.
 
     reduced=False writes the same update out on the full two-site tensor (no QR),
     the plain definition the reduced one is checked against."""
@@ -218,7 +218,7 @@ def plaquette_classes(lat):
 
 
 def su_nnn(B, lam, lat, y, x, anti, G, reduced=True):
-    """Apply the gate G to the next-nearest-neighbour pair of plaquette (y, x) (App. A, Fig. 7), in place.
+    """Apply the gate G to the next-nearest-neighbour pair of plaquette (y, x) (App. A, Fig. 8), in place.
 
     reduced=False leaves out the QR reductions of B_1 and B_3 (the plain definition)."""
     (y1, x1), l1, (y2, x2), l21, l23, (y3, x3), l3 = nnn_paths(lat, y, x, anti)
@@ -274,20 +274,24 @@ def su_nnn(B, lam, lat, y, x, anti, G, reduced=True):
 
 
 def su_step(B, lam, lat, dt, reduced=True):
-    """One step over every nearest-neighbour link, class by class, then (J2 != 0) every
-    next-nearest-neighbour pair, plaquette class by class; returns the mean relative
+    """One step over every nearest-neighbour link, class by class, then every coupled
+    diagonal pair, plaquette class by class (a class's diagonals, then its
+    anti-diagonals; an uncoupled diagonal is skipped); returns the mean relative
     change of the lambdas (App. A's convergence measure)."""
     G = heisenberg_gate(dt, lat.J1)
     old = [l.copy() for l in lam]
     for cls in link_classes(lat):
         for a, b, la, lb in cls:
             su_bond(B, lam, lat, a, b, la, lb, G, reduced)
-    if lat.J2 != 0.0:
-        G2 = heisenberg_gate(dt, lat.J2)
+    if lat.diagonals:
+        gates = {False: heisenberg_gate(dt, lat.Jd), True: heisenberg_gate(dt, lat.Ja)}
+        coupled = {False: lat.Jd != 0.0, True: lat.Ja != 0.0}
         for cls in plaquette_classes(lat):
             for anti in (False, True):
+                if not coupled[anti]:
+                    continue
                 for (y, x) in cls:
-                    su_nnn(B, lam, lat, y, x, anti, G2, reduced)
+                    su_nnn(B, lam, lat, y, x, anti, gates[anti], reduced)
     if not lam:
         return 0.0
     return float(np.mean([np.linalg.norm(n - o) / np.linalg.norm(o) for n, o in zip(lam, old)]))

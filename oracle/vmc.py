@@ -87,7 +87,7 @@ def _measure(T, lat, spins, U, collect_ratios=True):
                     f2 = row_tensors(T, lat, spins, y + 1, flips=((y + 1, x),))
                     Lm = env4_left(L4[x], U[y][x], f1[x], f2[x], D2[x])
                     ratio[((y, x), (y + 1, x))] = _dot(Lm, R4[x + 1]) / N4
-            if lat.J2 != 0.0:
+            if lat.diagonals:
                 for x in range(lat.Lx - 1):
                     for p, q in (((y, x), (y + 1, x + 1)), ((y, x + 1), (y + 1, x))):
                         if s[p] != s[q]:

@@ -259,8 +259,17 @@ vp_status check_lattice(vp_ctx* ctx, const vp_lattice& p) {
   if (p.compress == VP_COMPRESS_VARIATIONAL && p.D * p.Dc > 192)
     return fail(ctx, VP_ERR_SHAPE, "the variational fit needs D*Dc <= 192");
   if (p.fit_sweeps < 0 || p.fit_sweeps > 64) return fail(ctx, VP_ERR_ARG, "fit_sweeps must be 0..64");
+  if (p.geometry != VP_GEOM_SQUARE && p.geometry != VP_GEOM_TRIANGULAR)
+    return fail(ctx, VP_ERR_ARG, "unknown geometry %d", p.geometry);
+  if (p.geometry == VP_GEOM_TRIANGULAR && p.J2 != 0.0)
+    return fail(ctx, VP_ERR_UNSUPPORTED, "triangular lattice: its J2 bonds are not built, J2 must be 0");
   return VP_OK;
 }
+
+// Couplings of the diagonal (y,x)-(y+1,x+1) and the anti-diagonal (y,x+1)-(y+1,x).
+double diag_coupling(const vp_lattice& p) { return p.geometry == VP_GEOM_TRIANGULAR ? p.J1 : p.J2; }
+double anti_coupling(const vp_lattice& p) { return p.geometry == VP_GEOM_TRIANGULAR ? 0.0 : p.J2; }
+bool has_diagonals(const vp_lattice& p) { return diag_coupling(p) != 0.0 || anti_coupling(p) != 0.0; }
 
 Lattice* get_lat(vp_ctx* ctx, int32_t lat) {
   if (!ctx || lat < 0 || lat >= (int32_t)ctx->lats.size()) return nullptr;
@@ -519,7 +528,7 @@ vp_status eval_configs(vp_ctx* ctx, Lattice* L, const int8_t* spins_dev, int32_t
   o.n_meas = n_meas;
   o.m = row;
   o.np_half = L->Np / 2;
-  o.n_pairs = p.Ly * (p.Lx - 1) + (p.Ly - 1) * p.Lx + (p.J2 != 0.0 ? 2 * (p.Ly - 1) * (p.Lx - 1) : 0);
+  o.n_pairs = p.Ly * (p.Lx - 1) + (p.Ly - 1) * p.Lx + (has_diagonals(p) ? 2 * (p.Ly - 1) * (p.Lx - 1) : 0);
   if (works_f64(p.prec)) run_eval<double>(D, o, n_cfg, s); else run_eval<float>(D, o, n_cfg, s);
   HIP_TRY(ctx, hipGetLastError());
   L->chains_ready = false;
@@ -660,7 +669,7 @@ vp_status vp_create(const vp_lattice* lats, int32_t n_lats, uint64_t seed, void*
     hipMemset(L.spins, 0, (size_t)p.n_chains * L.N);
     LatDev& D = L.dev;
     D.Ly = p.Ly; D.Lx = p.Lx; D.d = p.D; D.c = p.Dc; D.N = L.N;
-    D.J1 = p.J1; D.J2 = p.J2; D.n_chains = p.n_chains;
+    D.J1 = p.J1; D.Jd = diag_coupling(p); D.Ja = anti_coupling(p); D.n_chains = p.n_chains;
     D.seed = seed; D.lat_id = i;
     D.cmode = p.compress; D.fit_sweeps = p.fit_sweeps;
     D.Tw = L.Tw; D.ws = L.ws; D.ws_stride = P.ws;
@@ -734,7 +743,8 @@ vp_status vp_simple_update(vp_ctx* ctx, int32_t lat, double dt, int32_t n_steps,
   if (!L->tensors_ready) return fail(ctx, VP_ERR_ARG, "tensors must be set first");
   hipStream_t s = ctx->stream;
   const int Ly = L->p.Ly, Lx = L->p.Lx, D = L->p.D;
-  const bool nnn = L->p.J2 != 0.0;
+  const bool nnn = has_diagonals(L->p);
+  const double Jdiag[2] = {diag_coupling(L->p), anti_coupling(L->p)};
   const int nl = Ly * (Lx - 1) + (Ly - 1) * Lx;
   int most = 1;
   for (int c = 0; c < 4; ++c) {
@@ -768,10 +778,11 @@ vp_status vp_simple_update(vp_ctx* ctx, int32_t lat, double dt, int32_t n_steps,
     if (nnn)
       for (int c = 0; c < 4; ++c)
         for (int anti = 0; anti < 2; ++anti) {
+          if (Jdiag[anti] == 0.0) continue;  // an uncoupled diagonal (triangular lattice)
           const int count = su_class_plaquettes(Ly, Lx, c);
           for (int first = 0; first < count; first += chunk)
             launch_su_nnn(B, lam, L->d_offs, L->d_dims, Ly, Lx, D, c, anti, first, std::min(chunk, count - first),
-                          dt, L->p.J2, scr, stride, s);
+                          dt, Jdiag[anti], scr, stride, s);
         }
     if (change_dev) launch_su_mean(lam, prev, nl, D, change_dev + step, s);
     HIP_TRY(ctx, hipGetLastError());
@@ -1102,7 +1113,8 @@ vp_status vp_sample_split(vp_ctx* ctx, int32_t lat_sample, int32_t lat_measure, 
   if (n_burn < 0 || n_meas < 0) return fail(ctx, VP_ERR_ARG, "negative sweep count");
   const vp_lattice& pa = A->p;
   const vp_lattice& pm = M->p;
-  if (pa.Ly != pm.Ly || pa.Lx != pm.Lx || pa.D != pm.D || pa.J1 != pm.J1 || pa.J2 != pm.J2 || pa.prec != pm.prec)
+  if (pa.Ly != pm.Ly || pa.Lx != pm.Lx || pa.D != pm.D || pa.J1 != pm.J1 || pa.J2 != pm.J2 || pa.prec != pm.prec ||
+      pa.geometry != pm.geometry)
     return fail(ctx, VP_ERR_SHAPE, "the sampling and measuring lattices may differ only in Dc and chain count");
   if (pm.n_chains < pa.n_chains)
     return fail(ctx, VP_ERR_SHAPE, "the measuring lattice needs at least as many chains as the sampling one");

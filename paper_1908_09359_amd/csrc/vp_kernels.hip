@@ -855,16 +855,19 @@ __device__ __forceinline__ void ph_measure4(const LatDev& L, int ch, int y, cons
     }
     if (o.ratios && threadIdx.x == 0) o.ratios[(int64_t)ch * o.n_pairs + base_v + y * Lx + x] = rho;
   }
-  if (L.J2 != 0.0) {
+  if (L.Jd != 0.0 || L.Ja != 0.0) {
     const int base_d = base_v + (L.Ly - 1) * Lx;
     for (int x = 0; x < Lx - 1; ++x) {
       for (int which = 0; which < 2; ++which) {
         // which 0: (y,x)-(y+1,x+1); which 1: (y,x+1)-(y+1,x)
         const int kp = which == 0 ? y * Lx + x : y * Lx + x + 1;
         const int kq = which == 0 ? (y + 1) * Lx + x + 1 : (y + 1) * Lx + x;
+        const double Jw = which == 0 ? L.Jd : L.Ja;
         double rho = 0.0;
-        if (C.sp[kp] == C.sp[kq]) {
-          eacc += 0.25 * L.J2;
+        if (Jw == 0.0) {
+          // an uncoupled diagonal (triangular lattice): no term, ratio slot 0
+        } else if (C.sp[kp] == C.sp[kq]) {
+          eacc += 0.25 * Jw;
         } else {
           // column x: flips (y,x) for which 0 and (y+1,x) for which 1; column x+1 the other site
           int f1a = which == 0 ? 1 : 0, f1b = which == 0 ? 0 : 1;
@@ -874,7 +877,7 @@ __device__ __forceinline__ void ph_measure4(const LatDev& L, int ch, int y, cons
                                  db<T>(L, C, y + 2, x + 1), false, as_lds(lds));
           double num = wg_dot<T>(tmp + sz, R + (int64_t)(x + 2) * sz, sz);
           rho = ldexp(num / Nm, e2 + eR[x + 2] - eN);
-          eacc += -0.25 * L.J2 + 0.5 * L.J2 * rho;
+          eacc += -0.25 * Jw + 0.5 * Jw * rho;
         }
         if (o.ratios && threadIdx.x == 0)
           o.ratios[(int64_t)ch * o.n_pairs + base_d + 2 * (y * (Lx - 1) + x) + which] = rho;

@@ -26,7 +26,8 @@ enum : int32_t { FLAG_ZERO = 1, FLAG_NONFINITE = 2 };
 // (smaller) dimensions are realised by zero entries.
 struct LatDev {
   int Ly, Lx, d, c, N;
-  double J1, J2;
+  double J1;
+  double Jd, Ja;  // couplings of the diagonal (y,x)-(y+1,x+1) and the anti-diagonal (y,x+1)-(y+1,x)
   int n_chains;
   uint64_t seed;
   int lat_id;

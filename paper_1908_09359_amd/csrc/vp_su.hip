@@ -7,7 +7,7 @@
 // four classes: horizontal links with x even, with x odd, vertical links with
 // y even, with y odd.  Links of one class share no site, so one work-group per
 // link updates a class in any order with the same result.  Per link (App. A,
-// Fig. 7 (b)-(h), two sites):
+// Fig. 8 (b)-(h), two sites):
 //   1. the lambdas of the outer links multiply both site tensors, written as
 //      matrices X = (outer legs) x (s, bond);
 //   2. thin Householder QR of each (when it has more rows than columns):
@@ -21,7 +21,7 @@
 //   5. the new tensors Q_A U and Q_B V with the outer lambdas divided out
 //      (1/lambda where lambda > 0, else 0).
 // Next-nearest-neighbour terms (both diagonals of every plaquette) follow
-// Fig. 7: the pair (B_1, B_3) is joined through a corner site B_2 (the
+// Fig. 8: the pair (B_1, B_3) is joined through a corner site B_2 (the
 // diagonal (y,x)-(y+1,x+1) through (y,x+1), the anti-diagonal (y,x+1)-(y+1,x)
 // through (y,x)); B_1 and B_3 are QR-reduced, the gate acts on the reduced
 // three-site tensor T_a = R_1 lambda_4 B_2 lambda_7 R_3^T, a truncated SVD

@@ -61,8 +61,11 @@ def sz0_configs(N):
     return np.array(out)
 
 
-def bonds(Ly, Lx, J1, J2):
-    """Bond list in the same order as the method's: horizontal, vertical, two diagonals per plaquette."""
+def bonds(Ly, Lx, J1, J2, triangular=False):
+    """Bond list in the same order as the method's: horizontal, vertical, two diagonals per plaquette.
+    triangular: J1 on the diagonal (y,x)-(y+1,x+1) and the anti-diagonal uncoupled (J2 must be 0)."""
+    if triangular:
+        assert J2 == 0.0
     out = []
     for y in range(Ly):
         for x in range(Lx - 1):
@@ -70,20 +73,22 @@ def bonds(Ly, Lx, J1, J2):
     for y in range(Ly - 1):
         for x in range(Lx):
             out.append((y * Lx + x, (y + 1) * Lx + x, J1))
-    if J2 != 0.0:
+    if J2 != 0.0 or triangular:
         for y in range(Ly - 1):
             for x in range(Lx - 1):
-                out.append((y * Lx + x, (y + 1) * Lx + x + 1, J2))
-                out.append((y * Lx + x + 1, (y + 1) * Lx + x, J2))
+                out.append((y * Lx + x, (y + 1) * Lx + x + 1, J1 if triangular else J2))
+                out.append((y * Lx + x + 1, (y + 1) * Lx + x, 0.0 if triangular else J2))
     return out
 
 
-def local_energies(T, Ly, Lx, D, J1, J2, configs):
+def local_energies(T, Ly, Lx, D, J1, J2, configs, triangular=False):
     """E_loc(S) = sum_S' <S'|H|S> Psi(S')/Psi(S), with H = sum J S_i.S_j written out directly."""
     configs = np.asarray(configs)
     psi = amplitudes(T, Ly, Lx, D, configs)
     e = np.zeros(len(configs))
-    for i, j, J in bonds(Ly, Lx, J1, J2):
+    for i, j, J in bonds(Ly, Lx, J1, J2, triangular):
+        if J == 0.0:
+            continue
         par = configs[:, i] == configs[:, j]
         e += np.where(par, 0.25 * J, -0.25 * J)
         flipped = configs.copy()
@@ -95,11 +100,12 @@ def local_energies(T, Ly, Lx, D, J1, J2, configs):
     return e, psi
 
 
-def sector_energy(psi, configs, Ly, Lx, J1=1.0):
+def sector_energy(psi, configs, Ly, Lx, J1=1.0, triangular=False):
     """<psi|H|psi> / <psi|psi> for amplitudes psi of every S^z = 0 configuration
-    (rows of ``configs``), H the nearest-neighbour Heisenberg lattice: parallel
-    pairs give J1/4, antiparallel pairs -J1/4 plus J1/2 times the amplitude of
-    the exchanged configuration (found by its bit code)."""
+    (rows of ``configs``), H the nearest-neighbour Heisenberg lattice (triangular:
+    with the diagonal (y,x)-(y+1,x+1) as a further nearest-neighbour bond):
+    parallel pairs give J1/4, antiparallel pairs -J1/4 plus J1/2 times the
+    amplitude of the exchanged configuration (found by its bit code)."""
     configs = np.asarray(configs)
     N = Ly * Lx
     codes = (configs.astype(np.int64) << np.arange(N, dtype=np.int64)[::-1]).sum(axis=1)
@@ -109,7 +115,10 @@ def sector_energy(psi, configs, Ly, Lx, J1=1.0):
     for y in range(Ly):
         for x in range(Lx):
             k = y * Lx + x
-            for k2 in ([k + 1] if x < Lx - 1 else []) + ([k + Lx] if y < Ly - 1 else []):
+            nb = ([k + 1] if x < Lx - 1 else []) + ([k + Lx] if y < Ly - 1 else [])
+            if triangular and x < Lx - 1 and y < Ly - 1:
+                nb.append(k + Lx + 1)
+            for k2 in nb:
                 par = configs[:, k] == configs[:, k2]
                 num += J1 * np.sum(np.where(par, 0.25, -0.25) * psi * psi)
                 anti = ~par

@@ -6,15 +6,16 @@ from oracle import lattice as olat
 from oracle import vmc
 
 
-def n_pairs(Ly, Lx, J2):
-    return Ly * (Lx - 1) + (Ly - 1) * Lx + (2 * (Ly - 1) * (Lx - 1) if J2 != 0.0 else 0)
+def n_pairs(Ly, Lx, J2, geometry=0):
+    diag = J2 != 0.0 or geometry == 1
+    return Ly * (Lx - 1) + (Ly - 1) * Lx + (2 * (Ly - 1) * (Lx - 1) if diag else 0)
 
 
-def gpu_eval(Ly, Lx, D, Dc, J2, prec, T, cfgs, n_chains=None, compress=0, fit_sweeps=0):
+def gpu_eval(Ly, Lx, D, Dc, J2, prec, T, cfgs, n_chains=None, compress=0, fit_sweeps=0, geometry=0):
     import torch
     from paper_1908_09359_amd import binding as B
     n = len(cfgs)
-    lat = B.lattice(Ly, Lx, D, Dc, 1.0, J2, prec, n_chains or n, compress, fit_sweeps)
+    lat = B.lattice(Ly, Lx, D, Dc, 1.0, J2, prec, n_chains or n, compress, fit_sweeps, geometry)
     ctx = B.Context(lat, seed=1)
     dev = torch.device("cuda")
     ctx.vp_set_tensors(0, torch.tensor(T, dtype=torch.float64, device=dev))
@@ -24,7 +25,7 @@ def gpu_eval(Ly, Lx, D, Dc, J2, prec, T, cfgs, n_chains=None, compress=0, fit_sw
     el = torch.empty(n, dtype=torch.float64, device=dev)
     dt = torch.float32 if prec == B.VP_FP32 else torch.float64
     dl = torch.empty((n, ctx.num_params() // 2), dtype=dt, device=dev)
-    ra = torch.empty((n, n_pairs(Ly, Lx, J2)), dtype=torch.float64, device=dev)
+    ra = torch.empty((n, n_pairs(Ly, Lx, J2, geometry)), dtype=torch.float64, device=dev)
     ctx.vp_eval(0, sp, n, lp, sg, el, dl, ra)
     torch.cuda.synchronize()
     out = dict(log_abs_psi=lp.cpu().numpy(), sign=sg.cpu().numpy(), e_loc=el.cpu().numpy(),
@@ -33,8 +34,9 @@ def gpu_eval(Ly, Lx, D, Dc, J2, prec, T, cfgs, n_chains=None, compress=0, fit_sw
     return out
 
 
-def oracle_eval(Ly, Lx, D, Dc, J2, T, cfgs, compress_mode="canonical", fit_sweeps=2):
-    lat = olat.Lattice(Ly, Lx, D, Dc, J2=J2, compress_mode=compress_mode, fit_sweeps=fit_sweeps)
+def oracle_eval(Ly, Lx, D, Dc, J2, T, cfgs, compress_mode="canonical", fit_sweeps=2, geometry=0):
+    lat = olat.Lattice(Ly, Lx, D, Dc, J2=J2, compress_mode=compress_mode, fit_sweeps=fit_sweeps,
+                       geometry=("square", "triangular")[geometry])
     outs = [vmc.eval_config(T, lat, c) for c in cfgs]
     return dict(log_abs_psi=np.array([o["log_abs_psi"] for o in outs]),
                 sign=np.array([o["sign"] for o in outs]),

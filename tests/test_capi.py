@@ -70,6 +70,17 @@ def test_create_checks_truncation_limits(D, Dc, compress, sweeps, status):
     assert ei.value.status == getattr(binding, status)
 
 
+@pytest.mark.parametrize("J2,geometry,status", [
+    (0.1, 1, "VP_ERR_UNSUPPORTED"),  # the triangular lattice's J2 bonds are not built
+    (0.0, 2, "VP_ERR_ARG"),          # unknown geometry
+])
+def test_create_checks_the_geometry(J2, geometry, status):
+    from paper_1908_09359_amd import binding
+    with pytest.raises(binding.VPError) as ei:
+        binding.Context(binding.lattice(4, 4, 2, 4, 1.0, J2, binding.VP_FP64, 1, geometry=geometry))
+    assert ei.value.status == getattr(binding, status)
+
+
 def test_workload_inputs_are_seeded():
     import numpy as np
     from paper_1908_09359_amd import workloads

@@ -11,7 +11,7 @@ amplitudes and 1e-10 relative on the changes (measured: 5e-15 and 2e-14; a few
 steps from random tensors, so no nearly degenerate truncation decides the
 result, and the Gram route's squared conditioning stays far below them).
 
-The J1-J2 cases add the next-nearest-neighbour (three-site) update of Fig. 7.
+The J1-J2 cases add the next-nearest-neighbour (three-site) update of Fig. 8.
 
 Also: two calls of 2 and 3 steps give the 5-step call bit for bit; zero steps
 leave the tensors unchanged; a negative step count is rejected; with J1 = 0

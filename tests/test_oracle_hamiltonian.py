@@ -98,6 +98,15 @@ def test_table3_triangular_ed(j2, e_paper):
     assert abs(e - e_paper) < 6e-8, (e, e_paper)
 
 
+def test_table3_triangular_ed_from_the_oracle_lattice():
+    """The oracle's own bond set of the triangular geometry (Lattice(...,
+    geometry="triangular")) gives Table III's J2 = 0 energy."""
+    lat = Lattice(4, 4, 1, 1, geometry="triangular")
+    bl = [(lat.site(*p), lat.site(*q), J) for p, q, J in bonds(lat) if J != 0.0]
+    e_paper = [e for j2, e in _golden() if j2 == 0.0][0]
+    assert abs(_ground_energy(16, bl) / 16 - e_paper) < 6e-8
+
+
 def test_triangular_ed_orientation_independent():
     e1 = _ground_energy(16, _triangular_bonds(4, 0.0, diag=(1, 1)))
     e2 = _ground_energy(16, _triangular_bonds(4, 0.0, diag=(1, -1)))

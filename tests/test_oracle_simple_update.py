@@ -12,7 +12,7 @@
 * On a 2 x 4 lattice (D = 2, truncated): the energy of the absorbed state falls
   well below the start's and stays above the exact ground energy (variational),
   and the convergence measure decreases; the same with J2 = 0.5.
-* Next-nearest-neighbour terms (Fig. 7's three-site update): the QR-reduced
+* Next-nearest-neighbour terms (Fig. 8's three-site update): the QR-reduced
   update equals the full one; from a product state where no truncation
   occurs, a step is the dense product of the same gates in the same order;
   with J1 = 0 the two diagonals of a 2 x 2 plaquette decouple and the
@@ -53,8 +53,9 @@ def _apply_gate(psi, N, i, j, G4):
     return np.moveaxis(t, [0, 1], [i, j]).ravel()
 
 
-def _hpsi(psi, Ly, Lx, J2=0.0, J1=1.0):
-    """H psi: J1 on nearest-neighbour pairs, J2 on both diagonals of every plaquette."""
+def _hpsi(psi, Ly, Lx, J2=0.0, J1=1.0, tri=False):
+    """H psi: J1 on nearest-neighbour pairs, J2 on both diagonals of every plaquette
+    (tri: the triangular lattice, J1 on the diagonal (y,x)-(y+1,x+1) alone)."""
     N = Ly * Lx
     h = _bond_hamiltonian()
     out = np.zeros_like(psi)
@@ -65,14 +66,16 @@ def _hpsi(psi, Ly, Lx, J2=0.0, J1=1.0):
                 out += J1 * _apply_gate(psi, N, k, k + 1, h)
             if y < Ly - 1 and J1:
                 out += J1 * _apply_gate(psi, N, k, k + Lx, h)
+            if tri and x < Lx - 1 and y < Ly - 1:
+                out += J1 * _apply_gate(psi, N, k, k + Lx + 1, h)
             if J2 and x < Lx - 1 and y < Ly - 1:
                 out += J2 * _apply_gate(psi, N, k, k + Lx + 1, h)
                 out += J2 * _apply_gate(psi, N, k + 1, k + Lx, h)
     return out
 
 
-def _energy(psi, Ly, Lx, J2=0.0, J1=1.0):
-    return float(psi @ _hpsi(psi, Ly, Lx, J2, J1) / (psi @ psi))
+def _energy(psi, Ly, Lx, J2=0.0, J1=1.0, tri=False):
+    return float(psi @ _hpsi(psi, Ly, Lx, J2, J1, tri) / (psi @ psi))
 
 
 @pytest.mark.parametrize("dt,J", [(0.01, 1.0), (0.3, 1.0), (0.2, 0.5)])
@@ -209,3 +212,47 @@ def test_decoupled_diagonals_converge_to_two_singlets():
     assert abs(_energy(_dense_state(Tsu, 2, 2, 4), 2, 2, J2=1.0, J1=0.0) + 1.5) <= 1e-10
     assert changes[-1] <= 1e-9
 
+
+
+def test_triangular_untruncated_step_is_the_dense_gate_product():
+    """The triangular lattice (J1 on the diagonal (y,x)-(y+1,x+1), Sec. III.B):
+    from a product state on 2 x 2 at D = 8 (no truncation; the residue is the
+    1e-6 singular-value floor) a step is the dense product of the
+    nearest-neighbour gates and then the diagonal's gate (three-site update
+    through the corner (y,x+1)); the anti-diagonal is not touched."""
+    Ly = Lx = 2
+    N, D, dt = 4, 8, 0.1
+    lat = olat.Lattice(Ly, Lx, D, 16, geometry="triangular")
+    T = _product_state(lat, 5)
+    psi = _dense_state(T, Ly, Lx, D)
+    G1 = su.heisenberg_gate(dt, 1.0).reshape(4, 4)
+    for cls in su.link_classes(lat):
+        for (ya, xa), (yb, xb), _, _ in cls:
+            psi = _apply_gate(psi, N, ya * Lx + xa, yb * Lx + xb, G1)
+    psi = _apply_gate(psi, N, 0, 3, G1)
+    Tsu, _, _, _ = su.simple_update(T, lat, dt, 1)
+    phi = _dense_state(Tsu, Ly, Lx, D)
+    assert abs(phi @ psi) / (np.linalg.norm(phi) * np.linalg.norm(psi)) >= 1.0 - 1e-10
+
+
+def test_triangular_evolution_is_variational():
+    """2 x 4 triangular lattice, D = 2 (truncated): the absorbed state's energy
+    falls well below the start's (to within 15% of the ground energy; the
+    frustrated lattice is further from a D = 2 state than the square one) and
+    stays above the exact ground energy."""
+    Ly, Lx, D = 2, 4, 2
+    lat = olat.Lattice(Ly, Lx, D, 16, geometry="triangular")
+    T = W.random_tensors(Ly, Lx, D, seed=31)
+    e0 = _energy(_dense_state(T, Ly, Lx, D), Ly, Lx, tri=True)
+    Tsu, changes, _, _ = su.simple_update(T, lat, 0.1, 40)
+    e1 = _energy(_dense_state(Tsu, Ly, Lx, D), Ly, Lx, tri=True)
+    N = Ly * Lx
+    H = np.zeros((2 ** N, 2 ** N))
+    for k in range(2 ** N):
+        e = np.zeros(2 ** N)
+        e[k] = 1.0
+        H[:, k] = _hpsi(e, Ly, Lx, tri=True)
+    e_exact = np.linalg.eigvalsh(H)[0]
+    assert e1 >= e_exact - 1e-12
+    assert e1 < e0 - 1.0 and e1 < 0.85 * e_exact
+    assert changes[-1] < 0.1 * changes[0]
