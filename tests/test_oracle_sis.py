@@ -140,3 +140,66 @@ def test_reweighted_mean_closed_forms():
     assert abs(sis.reweighted_mean(v, np.array([0.0, 0.0, 0.0, -np.inf])) - 7.0 / 3.0) < 1e-15
     # w = (1, 2, 3, 4): sum w v / sum w = (1 + 4 + 12 + 32) / 10
     assert abs(sis.reweighted_mean(v, np.log([1.0, 2.0, 3.0, 4.0])) - 4.9) < 1e-14
+
+
+def _phi2_distribution(T, lat, configs):
+    """|Phi(S)|^2 / Z over the S^z = 0 sector from dense amplitudes of S and its reversal."""
+    psi = bf.amplitudes(T, lat.Ly, lat.Lx, lat.D, configs)
+    psi_rev = bf.amplitudes(T, lat.Ly, lat.Lx, lat.D, 1 - np.asarray(configs))
+    phi2 = (psi + psi_rev) ** 2
+    return phi2 / phi2.sum()
+
+
+def _chi2_pvalue(counts, p):
+    import scipy.stats
+    n = counts.sum()
+    keep = p * n >= 5
+    obs = np.append(counts[keep], counts[~keep].sum())
+    exp = np.append(p[keep] * n, p[~keep].sum() * n)
+    if exp[-1] == 0:
+        obs, exp = obs[:-1], exp[:-1]
+    return scipy.stats.chisquare(obs, exp)[1]
+
+
+def test_pair_chains_sample_phi_squared():
+    """Chains of the pair (S, Sbar) visit the S^z = 0 configurations of a 2x3
+    lattice with the frequencies |Phi|^2 / Z of the dense amplitudes (chi-square;
+    consecutive sweeps are correlated, so the p-value is a coarse gate), while
+    the plain chain on the same tensors does not (its weight is |Psi|^2): the
+    check would catch an acceptance that left out the reversed chain."""
+    from oracle.lattice import neel_shuffled
+    lat = Lattice(2, 3, 2, 8)
+    T = np.random.default_rng(3).standard_normal(lat.Np) / lat.D ** 2
+    configs = bf.sz0_configs(6)
+    p_phi = _phi2_distribution(T, lat, configs)
+    index = _dense_index(configs)
+    counts = np.zeros(len(configs))
+    counts_plain = np.zeros(len(configs))
+    for chain in range(4):
+        start = neel_shuffled(lat, 9359, 0, chain)
+        ch = vmc.Chain(lat, start, 1234, 0, chain)
+        for smp in sis.run_pair_chain(T, lat, ch, 10, 600):
+            counts[index[smp["spins"].tobytes()]] += 1
+        ch = vmc.Chain(lat, start, 1234, 0, chain)
+        for smp in vmc.run_chain(T, lat, ch, 10, 600):
+            counts_plain[index[smp["spins"].tobytes()]] += 1
+    assert _chi2_pvalue(counts, p_phi) > 1e-4
+    assert _chi2_pvalue(counts_plain, p_phi) < 1e-8
+
+
+def test_pair_chain_measurements_equal_the_fixed_configuration_evaluation():
+    """Every measured sample of the pair chain (truncated 4x4, D=3, Dc=3, J2 = 0.5)
+    equals ``eval_config`` of its configuration: sign, log|Phi| and E_Phi."""
+    lat = Lattice(4, 4, 3, 3, J2=0.5)
+    T = W.random_tensors(4, 4, 3, seed=41)
+    from oracle.lattice import neel_shuffled
+    ch = vmc.Chain(lat, neel_shuffled(lat, 5, 0, 1), 77, 0, 1)
+    samples = sis.run_pair_chain(T, lat, ch, 1, 3)
+    moved = False
+    for smp in samples:
+        ref = sis.eval_config(T, lat, smp["spins"])
+        assert smp["sign"] == ref["sign"]
+        assert abs(smp["log_abs_phi"] - ref["log_abs_phi"]) <= 1e-10
+        assert abs(smp["e_loc"] - ref["e_loc"]) <= 1e-10 * max(1.0, abs(ref["e_loc"]))
+        moved |= not np.array_equal(smp["spins"], neel_shuffled(lat, 5, 0, 1))
+    assert moved and ch.accepted > 0
