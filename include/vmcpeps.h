@@ -97,8 +97,10 @@ typedef enum { VP_FP64 = 0, VP_FP32 = 1, VP_BF16 = 2 } vp_prec;
 /* Samplers (vp_set_sampler).  VP_SAMPLER_PAIR_SEQ: the sequential
  * nearest-neighbour exchange sweep of Sec. II.A Eq. (9).
  * VP_SAMPLER_LEARNED_PLAQ: the same sweep with a learned plaquette move after
- * each vertical bond (see vp_set_sampler). */
-typedef enum { VP_SAMPLER_PAIR_SEQ = 0, VP_SAMPLER_LEARNED_PLAQ = 1 } vp_sampler;
+ * each vertical bond (see vp_set_sampler).  VP_SAMPLER_SIS_PAIR: chains of the
+ * weight |Phi(S)|^2 of the spin-inversion symmetrised amplitude (Sec. II.B;
+ * see vp_set_sampler). */
+typedef enum { VP_SAMPLER_PAIR_SEQ = 0, VP_SAMPLER_LEARNED_PLAQ = 1, VP_SAMPLER_SIS_PAIR = 2 } vp_sampler;
 
 /* Boundary truncation to Dc (App. B).  VP_COMPRESS_CANONICAL: the canonical
  * SVD compression (left-to-right orthogonalisation, right-to-left truncation
@@ -352,7 +354,25 @@ vp_status vp_proposal_train(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev, c
  * and its flip accepted iff u < rho^2 pi(S')/pi(S), u = word 1 of the same
  * counter: Metropolis-Hastings for a propose-or-stay move, so |Psi|^2 stays
  * the stationary distribution whatever the weights.  The network runs in the
- * working precision. */
+ * working precision.
+ * VP_SAMPLER_SIS_PAIR (n_chains even, the per-phase schedule): Markov chains
+ * of |Phi(S)|^2, Phi(S) = Psi(S) + Psi(Sbar), Sbar = S with every spin
+ * reversed (Sec. II.B).  Chain c < n_chains/2 carries S and chain
+ * c + n_chains/2 its reversal; every vp_sample call first sets the second half
+ * to the reversal of the first, rebuilds the lower boundaries and contracts
+ * both amplitudes top-down.  The pair visits the bonds in the Eq. (9) order;
+ * each chain's ratio r = Psi(S')/Psi(S), rbar = Psi(Sbar')/Psi(Sbar) comes
+ * from its own environments, and the exchange of the same pair in both is
+ * accepted iff u < q^2, q = (Psi(S) r + Psi(Sbar) rbar) / (Psi(S) + Psi(Sbar)),
+ * u from chain c's Philox counter (c, sweep, bond, 4); Psi(S) and Psi(Sbar)
+ * are the last top-down contractions times the ratios of the moves accepted
+ * since.  vp_sample then writes n_chains/2 samples per measured sweep, indexed
+ * [c][m]: log|Phi|, sign(Phi), E_Phi(S) = (Psi(S) E_loc(S) + Psi(Sbar)
+ * E_loc(Sbar)) / (Psi(S) + Psi(Sbar)) (the Heisenberg elements are invariant
+ * under the reversal), and S; dlnpsi_dev must be NULL (not produced) and
+ * accept_dev covers the first n_chains/2 chains.  An exactly zero Psi(S) or
+ * Psi(Sbar) in a visited network flags the pair (VP_ERR_ZERO_AMPLITUDE).
+ * vp_sample_batch and vp_sample_split return VP_ERR_UNSUPPORTED for it. */
 vp_status vp_set_sampler(vp_ctx* ctx, int32_t lat, int32_t sampler);
 /* Move counters since vp_init_chains: counts_dev [n_chains][4] int64 =
  * (pair accepted, pair proposed, plaquette accepted, plaquette proposed). */

@@ -16,7 +16,7 @@ VP_ERR_ZERO_AMPLITUDE, VP_ERR_NONFINITE, VP_ERR_UNSUPPORTED = 5, 6, 7
 VP_COMPRESS_CANONICAL, VP_COMPRESS_VARIATIONAL = 0, 1
 VP_GEOM_SQUARE, VP_GEOM_TRIANGULAR = 0, 1
 VP_FP64, VP_FP32, VP_BF16 = 0, 1, 2
-VP_SAMPLER_PAIR_SEQ, VP_SAMPLER_LEARNED_PLAQ = 0, 1
+VP_SAMPLER_PAIR_SEQ, VP_SAMPLER_LEARNED_PLAQ, VP_SAMPLER_SIS_PAIR = 0, 1, 2
 VP_SCHED_PHASES, VP_SCHED_PERSISTENT, VP_SCHED_GRAPH = 0, 1, 2
 VP_TILE_DEFAULT, VP_TILE_SMALL, VP_TILE_LARGE, VP_N_TILES = 0, 1, 2, 3
 

@@ -476,6 +476,69 @@ void run_eval(const LatDev& D, const SampleOut& o, int n_cfg, hipStream_t s) {
   launch_finish_sample(D, o, n_cfg, s);
 }
 
+// Chains of |Phi|^2 (VP_SAMPLER_SIS_PAIR): chain c and c + n/2 carry S and its
+// reversal.  Per call: the second half set to the reversal of the first, the
+// lower boundaries and both top-down amplitudes contracted; then every sweep
+// runs the plain phases over all chains and the decision phases over the pairs,
+// and a measured sweep combines the two chains' measurements (taken into the
+// scratch reserved at vp_create) into row m of the caller's outputs.
+template <typename T>
+vp_status run_pair_sample(vp_ctx* ctx, Lattice& L, int n_burn, int n_meas, double* log_abs_phi, int8_t* sign_phi,
+                          double* e_loc_phi, int8_t* spins_out) {
+  hipStream_t s = ctx->stream;
+  const int Ly = L.p.Ly, n = L.p.n_chains, h = n / 2, N = L.N;
+  const bool bf = L.p.prec == VP_BF16;
+  launch_reverse_spins(L.spins, L.spins + (size_t)h * N, (int64_t)h * N, s);
+  run_lower_pass<T>(ctx, L, s);
+  L.lower_valid = true;
+  for (int y = 0; y < Ly - 1; ++y) launch_compress<T>(L.dev, y, 1, s);
+  launch_psi_fixed<T>(L.dev, s);
+  HIP_TRY(ctx, hipGetLastError());
+  // per-chain measurements of one sweep: log|Psi| [n], E_loc [n], sign [n]
+  char* work = L.d_sis;
+  const size_t nb = (size_t)n * N;
+  const size_t off_l = (nb + 255) / 256 * 256, off_e = off_l + sizeof(double) * n, off_s = off_e + sizeof(double) * n;
+  SampleOut o{};
+  o.log_abs_psi = (double*)(work + off_l);
+  o.e_loc = (double*)(work + off_e);
+  o.sign = (int8_t*)(work + off_s);
+  o.n_meas = 1;
+  o.m = 0;
+  o.dyn_m = 0;
+  o.np_half = L.Np / 2;
+  o.psi_meas = bf;
+  Rec r(ctx);
+  for (int i = 0; i < n_burn + n_meas; ++i) {
+    const bool meas = i >= n_burn;
+    for (int y = 0; y < Ly; ++y) {
+      TIMED(r, VP_PH_ROW3_ENVS, launch_row3_right<T>(L.dev, y, y, y + 1, bf, s));
+      TIMED(r, VP_PH_HSWEEP, launch_hsweep_pair<T>(L.dev, y, y == Ly - 1, bf, s));
+      if (y < Ly - 1) {
+        TIMED(r, VP_PH_ROW4_ENVS, launch_row4_right<T>(L.dev, y, bf, s));
+        TIMED(r, VP_PH_VSWEEP, launch_vsweep_pair<T>(L.dev, y, bf, s));
+        TIMED(r, VP_PH_COMPRESS_UP, launch_compress<T>(L.dev, y, 1, s));
+      }
+    }
+    if (meas) TIMED(r, VP_PH_OTHER, launch_begin_sample(L.dev, s));
+    for (int y = Ly - 1; y >= 0; --y) {
+      if (meas) {
+        TIMED(r, VP_PH_MEASURE3, launch_measure3<T>(L.dev, y, o, s));
+        if (y < Ly - 1) TIMED(r, VP_PH_MEASURE4, launch_measure4<T>(L.dev, y, o, s));
+      }
+      if (y >= 1) TIMED(r, VP_PH_COMPRESS_DOWN, launch_compress<T>(L.dev, y, 0, s));
+    }
+    if (meas) {
+      TIMED(r, VP_PH_OTHER, launch_finish_sample(L.dev, o, n, s));
+      TIMED(r, VP_PH_OTHER, launch_pair_combine(h, n_meas, i - n_burn, o.log_abs_psi, o.sign, o.e_loc, L.spins, N,
+                                                log_abs_phi, sign_phi, e_loc_phi, spins_out, s));
+    }
+    TIMED(r, VP_PH_OTHER, launch_next_sweep(L.dev, s));
+    HIP_TRY(ctx, hipGetLastError());
+    if (ctx->ev_used >= 8192) fold_timing(ctx);
+  }
+  return VP_OK;
+}
+
 vp_status check_flags(vp_ctx* ctx, Lattice& L) {
   std::vector<ChainMeta> m(L.p.n_chains);
   HIP_TRY(ctx, hipMemcpyAsync(m.data(), L.meta, sizeof(ChainMeta) * m.size(), hipMemcpyDeviceToHost, ctx->stream));
@@ -862,6 +925,22 @@ vp_status vp_sample(vp_ctx* ctx, int32_t lat, int32_t n_burn, int32_t n_meas, do
     return fail(ctx, VP_ERR_ARG, "log_abs_psi, sign and e_loc outputs are required");
   hipStream_t s = ctx->stream;
   const bool f64 = works_f64(L->p.prec);
+  if (L->sampler == VP_SAMPLER_SIS_PAIR) {
+    if (L->schedule != VP_SCHED_PHASES)
+      return fail(ctx, VP_ERR_UNSUPPORTED, "the |Phi|^2 sampler runs the per-phase schedule only");
+    if (dlnpsi_dev) return fail(ctx, VP_ERR_UNSUPPORTED, "the |Phi|^2 sampler produces no log-derivatives");
+    vp_status st = f64 ? run_pair_sample<double>(ctx, *L, n_burn, n_meas, log_abs_psi_dev, sign_dev, e_loc_dev,
+                                                  spins_out_dev)
+                       : run_pair_sample<float>(ctx, *L, n_burn, n_meas, log_abs_psi_dev, sign_dev, e_loc_dev,
+                                                spins_out_dev);
+    if (st != VP_OK) return st;
+    L->sweeps += n_burn + n_meas;
+    if (accept_dev)
+      HIP_TRY(ctx, hipMemcpy2DAsync(accept_dev, 2 * sizeof(int64_t), (const char*)L->meta + sizeof(int64_t),
+                                    sizeof(ChainMeta), 2 * sizeof(int64_t), L->p.n_chains / 2,
+                                    hipMemcpyDeviceToDevice, s));
+    return VP_OK;
+  }
   if (!L->lower_valid) {
     if (f64) run_lower_pass<double>(ctx, *L, s); else run_lower_pass<float>(ctx, *L, s);
     L->lower_valid = true;
@@ -934,6 +1013,8 @@ vp_status vp_sample_batch(vp_ctx* ctx, int32_t n_lats, const int32_t* lats_host,
       if (q == L) return fail(ctx, VP_ERR_ARG, "lattice %d listed twice", lats_host[i]);
     if (!L->tensors_ready || !L->chains_ready)
       return fail(ctx, VP_ERR_ARG, "lattice %d: tensors and chains must be initialised first", lats_host[i]);
+    if (L->sampler == VP_SAMPLER_SIS_PAIR)
+      return fail(ctx, VP_ERR_UNSUPPORTED, "lattice %d: the |Phi|^2 sampler runs through vp_sample only", lats_host[i]);
     if (!ls.empty() && (L->p.D != ls[0]->p.D || L->p.Dc != ls[0]->p.Dc || L->p.prec != ls[0]->p.prec))
       return fail(ctx, VP_ERR_SHAPE, "one batch needs equal D, Dc and precision");
     SampleOut o{};
@@ -1120,6 +1201,8 @@ vp_status vp_sample_split(vp_ctx* ctx, int32_t lat_sample, int32_t lat_measure, 
     return fail(ctx, VP_ERR_SHAPE, "the measuring lattice needs at least as many chains as the sampling one");
   if (!A->tensors_ready || !A->chains_ready || !M->tensors_ready)
     return fail(ctx, VP_ERR_ARG, "tensors of both lattices and the sampling chains must be set first");
+  if (A->sampler == VP_SAMPLER_SIS_PAIR)
+    return fail(ctx, VP_ERR_UNSUPPORTED, "the |Phi|^2 sampler runs through vp_sample only");
   if (n_meas > 0 && (!log_abs_psi_dev || !sign_dev || !e_loc_dev))
     return fail(ctx, VP_ERR_ARG, "log_abs_psi, sign and e_loc outputs are required");
   hipStream_t s = ctx->stream;
@@ -1186,8 +1269,10 @@ vp_status vp_proposal_get_weights(vp_ctx* ctx, int32_t lat, float* w_dev) {
 vp_status vp_set_sampler(vp_ctx* ctx, int32_t lat, int32_t sampler) {
   Lattice* L = get_lat(ctx, lat);
   if (!L) return fail(ctx, VP_ERR_ARG, "bad lattice index");
-  if (sampler != VP_SAMPLER_PAIR_SEQ && sampler != VP_SAMPLER_LEARNED_PLAQ)
+  if (sampler != VP_SAMPLER_PAIR_SEQ && sampler != VP_SAMPLER_LEARNED_PLAQ && sampler != VP_SAMPLER_SIS_PAIR)
     return fail(ctx, VP_ERR_ARG, "unknown sampler %d", sampler);
+  if (sampler == VP_SAMPLER_SIS_PAIR && L->p.n_chains % 2)
+    return fail(ctx, VP_ERR_SHAPE, "the |Phi|^2 sampler pairs the chains: n_chains must be even");
   if (sampler == VP_SAMPLER_LEARNED_PLAQ && !L->net_ready)
     return fail(ctx, VP_ERR_ARG, "the learned sampler needs proposal weights (vp_proposal_set_weights)");
   if (sampler == VP_SAMPLER_LEARNED_PLAQ && (L->p.Ly < 2 || L->p.Lx < 2))

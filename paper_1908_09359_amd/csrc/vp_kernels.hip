@@ -468,6 +468,239 @@ __device__ __forceinline__ void ph_vsweep(const LatDev& L, int ch, int y, char* 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Chains of |Phi|^2, Phi(S) = Psi(S) + Psi(Sbar) (Sec. II.B): chain ch < n/2
+// carries S and chain ch + n/2 its reversal Sbar.  One work-group visits the
+// bonds of both in the plain sampler's order; each chain's ratio comes from
+// its own environments, and one decision (the S chain's Philox stream) moves
+// the same pair in both.  Acceptance |Phi(S')/Phi(S)|^2 with
+//   Phi(S')/Phi(S) = (Psi(S) r + Psi(Sbar) rbar) / (Psi(S) + Psi(Sbar)),
+// r, rbar the two chains' ratios; Psi(S), Psi(Sbar) are the amplitudes of the
+// last top-down contractions (ChainMeta logpsi, sign) multiplied by the ratios
+// of every move accepted since, held in registers within a kernel.
+// ---------------------------------------------------------------------------
+struct PairAmp {
+  double la[2];  // log|Psi| of S and Sbar
+  double sg[2];  // their signs
+};
+
+__device__ inline PairAmp load_pair_amp(const ChainMeta* m0, const ChainMeta* m1) {
+  PairAmp A;
+  A.la[0] = m0->logpsi;
+  A.la[1] = m1->logpsi;
+  A.sg[0] = m0->sign < 0 ? -1.0 : 1.0;
+  A.sg[1] = m1->sign < 0 ? -1.0 : 1.0;
+  return A;
+}
+
+// Every thread of the work-group reads the metas before any thread writes them.
+__device__ inline void store_pair_amp(ChainMeta* m0, ChainMeta* m1, const PairAmp& A) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    m0->logpsi = A.la[0];
+    m1->logpsi = A.la[1];
+    m0->sign = A.sg[0] < 0.0 ? -1 : 1;
+    m1->sign = A.sg[1] < 0.0 ? -1 : 1;
+  }
+}
+
+__device__ inline void raise_pair(ChainMeta* m0, ChainMeta* m1, int f) {
+  raise_flag(m0, f);
+  raise_flag(m1, f);
+}
+
+__device__ inline bool pair_metropolis(const LatDev& L, int ch, ChainMeta* m0, ChainMeta* m1, PairAmp& A,
+                                       const double* num, const double* den, const int* esum, int bond) {
+  double r[2];
+  for (int c = 0; c < 2; ++c) {
+    if (den[c] == 0.0) {
+      raise_pair(m0, m1, FLAG_ZERO);
+      return false;
+    }
+    r[c] = scaled(num[c] / den[c], esum[c]);
+    if (!isfinite(r[c])) {
+      raise_pair(m0, m1, FLAG_NONFINITE);
+      return false;
+    }
+  }
+  // amplitudes relative to exp(max log|Psi|): no exponential overflows
+  const double mx = fmax(A.la[0], A.la[1]);
+  const double pa = A.sg[0] * exp(A.la[0] - mx);
+  const double pb = A.sg[1] * exp(A.la[1] - mx);
+  const double phi = pa + pb;
+  if (phi == 0.0) {
+    raise_pair(m0, m1, FLAG_ZERO);
+    return false;
+  }
+  const double q = (pa * r[0] + pb * r[1]) / phi;
+  const double R = q * q;
+  if (!isfinite(R)) {
+    raise_pair(m0, m1, FLAG_NONFINITE);
+    return false;
+  }
+  U64x4 w = philox4x64_10((uint64_t)ch, (uint64_t)m0->sweep, (uint64_t)bond, TAG_METRO, L.seed, (uint64_t)L.lat_id);
+  const bool acc = uniform53(w.v[0]) < R;
+  if (L.trace && threadIdx.x == 0) {
+    double* t = L.trace + 2 * ((int64_t)ch * L.n_bonds + bond);
+    t[0] = q;
+    t[1] = acc ? 1.0 : 0.0;
+  }
+  if (acc)
+    for (int c = 0; c < 2; ++c)
+      if (r[c] != 0.0) {
+        A.sg[c] = r[c] < 0.0 ? -A.sg[c] : A.sg[c];
+        A.la[c] += log(fabs(r[c]));
+      } else {
+        A.la[c] = -INFINITY;
+      }
+  return acc;
+}
+
+// Thread 0 counts the proposal in both chains and, if accepted, exchanges the
+// pair (k1, k2) in both; the work-group then sees the new spins.
+__device__ inline void pair_apply(ChainMeta* m0, ChainMeta* m1, int8_t* sp0, int8_t* sp1, int k1, int k2, bool acc) {
+  if (threadIdx.x == 0) {
+    m0->proposed += 1;
+    m1->proposed += 1;
+    if (acc) {
+      int8_t a = sp0[k1]; sp0[k1] = sp0[k2]; sp0[k2] = a;
+      a = sp1[k1]; sp1[k1] = sp1[k2]; sp1[k2] = a;
+      m0->accepted += 1;
+      m1->accepted += 1;
+    }
+  }
+  __syncthreads();
+}
+
+// Horizontal bonds of row y for the pair (ch, ch + n/2); the last row also
+// gives both amplitudes afresh.
+template <typename T, int DD, int CC, bool BF16>
+__device__ __forceinline__ void ph_hsweep_pair(const LatDev& L, int ch, int y, int last_row, char* tiles) {
+  Chain<T> C[2] = {chain_of<T>(L, ch), chain_of<T>(L, ch + L.n_chains / 2)};
+  if (chain_flagged(C[0].meta) || chain_flagged(C[1].meta)) return;
+  PairAmp A = load_pair_amp(C[0].meta, C[1].meta);
+  const int sz = e3sz(L);
+  int slot[2][4] = {{0, 1, 2, 3}, {0, 1, 2, 3}};  // cur, nxt, f1, f2 per chain
+  int ecur[2] = {0, 0};
+  for (int c = 0; c < 2; ++c) set_unit<T>(C[c].ws + L.oT3 + slot[c][0] * sz, sz);
+  for (int x = 0; x < L.Lx - 1; ++x) {
+    const int k = y * L.Lx + x;
+    const int bond = y * (2 * L.Lx - 1) + x;
+    const bool anti = C[0].sp[k] != C[0].sp[k + 1];  // the same pair of Sbar is antiparallel too
+    if (!anti) trace_skip(L, C[0].id, bond);
+    int enxt[2], ef1[2], esum[2];
+    double num[2], den[2];
+    for (int c = 0; c < 2; ++c) {
+      T* tmp = C[c].ws + L.oT3;
+      const T* R = C[c].ws + L.oR3;
+      const int* eR = C[c].iw + L.ieR3;
+      const T* Ux = ub<T>(L, C[c], y, x);
+      const T* Dx = db<T>(L, C[c], y + 1, x);
+      T* cur = tmp + slot[c][0] * sz;
+      T* nxt = tmp + slot[c][1] * sz;
+      enxt[c] = ecur[c] + step3<T, DD, CC, BF16>(L, C[c], nxt, cur, y, x, 0, Ux, Dx, false, as_lds(tiles));
+      if (anti) {
+        T* f1 = tmp + slot[c][2] * sz;
+        T* f2 = tmp + slot[c][3] * sz;
+        ef1[c] = ecur[c] + step3<T, DD, CC, BF16>(L, C[c], f1, cur, y, x, 1, Ux, Dx, false, as_lds(tiles));
+        const int ef2 = ef1[c] + step3<T, DD, CC, BF16>(L, C[c], f2, f1, y, x + 1, 1, ub<T>(L, C[c], y, x + 1),
+                                                       db<T>(L, C[c], y + 1, x + 1), false, as_lds(tiles));
+        num[c] = wg_dot<T>(f2, R + (int64_t)(x + 2) * sz, sz);
+        den[c] = wg_dot<T>(nxt, R + (int64_t)(x + 1) * sz, sz);
+        esum[c] = ef2 + eR[x + 2] - enxt[c] - eR[x + 1];
+      }
+    }
+    if (anti) {
+      const bool acc = pair_metropolis(L, C[0].id, C[0].meta, C[1].meta, A, num, den, esum, bond);
+      pair_apply(C[0].meta, C[1].meta, C[0].sp, C[1].sp, k, k + 1, acc);
+      if (acc)  // column x now carries the exchanged tensor: f1 becomes current
+        for (int c = 0; c < 2; ++c) {
+          int t = slot[c][1]; slot[c][1] = slot[c][2]; slot[c][2] = t;
+          enxt[c] = ef1[c];
+        }
+    }
+    for (int c = 0; c < 2; ++c) {
+      int t = slot[c][0]; slot[c][0] = slot[c][1]; slot[c][1] = t;
+      ecur[c] = enxt[c];
+    }
+  }
+  if (!last_row) {
+    store_pair_amp(C[0].meta, C[1].meta, A);
+    return;
+  }
+  const int x = L.Lx - 1;
+  for (int c = 0; c < 2; ++c) {
+    T* tmp = C[c].ws + L.oT3;
+    T* cur = tmp + slot[c][0] * sz;
+    T* nxt = tmp + slot[c][1] * sz;
+    const int e = ecur[c] + step3<T, DD, CC, BF16>(L, C[c], nxt, cur, y, x, 0, ub<T>(L, C[c], y, x),
+                                                  db<T>(L, C[c], y + 1, x), false, as_lds(tiles));
+    const double v = (double)nxt[0];
+    __syncthreads();  // every thread has read the metas and nxt[0]
+    if (threadIdx.x == 0) {
+      if (v == 0.0) {
+        atomicOr(&C[c].meta->flags, FLAG_ZERO);
+      } else if (!isfinite(v)) {
+        atomicOr(&C[c].meta->flags, FLAG_NONFINITE);
+      } else {
+        C[c].meta->logpsi = C[c].dw[L.dlamU + y] + log(fabs(v)) + e * 0.69314718055994530942;
+        C[c].meta->sign = v > 0 ? 1 : -1;
+      }
+    }
+  }
+}
+
+// Vertical bonds between rows y and y+1 for the pair (ch, ch + n/2).
+template <typename T, int DD, int CC, bool BF16>
+__device__ __forceinline__ void ph_vsweep_pair(const LatDev& L, int ch, int y, char* lds) {
+  Chain<T> C[2] = {chain_of<T>(L, ch), chain_of<T>(L, ch + L.n_chains / 2)};
+  if (chain_flagged(C[0].meta) || chain_flagged(C[1].meta)) return;
+  PairAmp A = load_pair_amp(C[0].meta, C[1].meta);
+  const int sz = e4sz(L);
+  int slot[2][3] = {{0, 1, 2}, {0, 1, 2}};  // cur, nxt, f per chain
+  int ecur[2] = {0, 0};
+  for (int c = 0; c < 2; ++c) set_unit<T>(C[c].ws + L.oT4 + slot[c][0] * sz, sz);
+  for (int x = 0; x < L.Lx; ++x) {
+    const int k1 = y * L.Lx + x, k2 = (y + 1) * L.Lx + x;
+    const int vb = y * (2 * L.Lx - 1) + (L.Lx - 1) + x;
+    const bool anti = C[0].sp[k1] != C[0].sp[k2];
+    if (!anti) trace_skip(L, C[0].id, vb);
+    if (x == L.Lx - 1 && !anti) break;
+    int enxt[2], ef[2], esum[2];
+    double num[2], den[2];
+    for (int c = 0; c < 2; ++c) {
+      T* tmp = C[c].ws + L.oT4;
+      const T* R = C[c].ws + L.oR4;
+      const T* Ux = ub<T>(L, C[c], y, x);
+      const T* Dx = db<T>(L, C[c], y + 2, x);
+      T* cur = tmp + slot[c][0] * sz;
+      T* nxt = tmp + slot[c][1] * sz;
+      enxt[c] = ecur[c] + step4<T, DD, CC, BF16>(L, C[c], nxt, cur, y, x, 0, 0, Ux, Dx, false, as_lds(lds));
+      if (anti) {
+        T* f = tmp + slot[c][2] * sz;
+        ef[c] = ecur[c] + step4<T, DD, CC, BF16>(L, C[c], f, cur, y, x, 1, 1, Ux, Dx, false, as_lds(lds));
+        num[c] = wg_dot<T>(f, R + (int64_t)(x + 1) * sz, sz);
+        den[c] = wg_dot<T>(nxt, R + (int64_t)(x + 1) * sz, sz);
+        esum[c] = ef[c] - enxt[c];
+      }
+    }
+    if (anti) {
+      const bool acc = pair_metropolis(L, C[0].id, C[0].meta, C[1].meta, A, num, den, esum, vb);
+      pair_apply(C[0].meta, C[1].meta, C[0].sp, C[1].sp, k1, k2, acc);
+      if (acc)
+        for (int c = 0; c < 2; ++c) {
+          int t = slot[c][1]; slot[c][1] = slot[c][2]; slot[c][2] = t;
+          enxt[c] = ef[c];
+        }
+    }
+    for (int c = 0; c < 2; ++c) {
+      int t = slot[c][0]; slot[c][0] = slot[c][1]; slot[c][1] = t;
+      ecur[c] = enxt[c];
+    }
+  }
+  store_pair_amp(C[0].meta, C[1].meta, A);
+}
+
 // Boundary compression (App. B) of row y into U_y (upper = 1) or D_y.
 //
 // The canonical SVD compression is computed through Gram matrices: the
@@ -924,6 +1157,12 @@ constexpr size_t step4_lds() {
   else return env4_lds<T, T, DD, CC, false, BBX>();
 }
 
+// The pair sampler's decision phases: one work-group per pair (n/2 of them).
+template <typename T, int DD, int CC, bool BF16>
+__global__ void __launch_bounds__(WG, 2) k_hsweep_pair(LatDev L, int y, int last_row) {
+  __shared__ __attribute__((aligned(16))) char lds[step3_lds<T, DD, CC, BF16>()];
+  ph_hsweep_pair<T, DD, CC, BF16>(L, blockIdx.x, y, last_row, lds);
+}
 // BBX: b-block of the fused 2-row step (a tile variant, 0 = default).
 template <typename T, int DD, int CC, bool BF16, int BBX = 0>
 __global__ void __launch_bounds__(WG, 2) k_row4_right(LatDev L, int y) {
@@ -935,6 +1174,11 @@ __global__ void __launch_bounds__(WG, 2) k_vsweep(LatDev L, int y) {
   __shared__ __attribute__((aligned(16)))
   char lds[cmax(step4_lds<T, DD, CC, BF16, BBX>(), LEARN ? (BF16 ? net_bf_lds_bytes() : net_lds_bytes<T>()) : 0)];
   ph_vsweep<T, DD, CC, BF16, LEARN, BBX>(L, blockIdx.x, y, lds);
+}
+template <typename T, int DD, int CC, bool BF16>
+__global__ void __launch_bounds__(WG, 2) k_vsweep_pair(LatDev L, int y) {
+  __shared__ __attribute__((aligned(16))) char lds[step4_lds<T, DD, CC, BF16>()];
+  ph_vsweep_pair<T, DD, CC, BF16>(L, blockIdx.x, y, lds);
 }
 template <typename T, int DD, int CC>
 __global__ void __launch_bounds__(WG, 2) k_compress(LatDev L, int y, int upper) {
@@ -1301,6 +1545,32 @@ void launch_vsweep(const LatDev& L, int y, bool bf16, bool learned, hipStream_t 
   if (learned) VP_DISPATCH_DC_VS(T, false, true);
   else VP_DISPATCH_DC_VS(T, false, false);
 }
+
+// Pair sampler launches: one work-group per chain pair (grid n_chains / 2).
+#define VP_DISPATCH_PAIR(KERNEL, T, BF, ...)                                                           \
+  do {                                                                                                 \
+    const dim3 g(L.n_chains / 2), b(WG);                                                               \
+    if (L.d == 8 && L.c == 16) hipLaunchKernelGGL((KERNEL<T, 8, 16, BF>), g, b, 0, s, __VA_ARGS__);    \
+    else if (L.d == 6 && L.c == 12) hipLaunchKernelGGL((KERNEL<T, 6, 12, BF>), g, b, 0, s, __VA_ARGS__); \
+    else if (L.d == 4 && L.c == 8) hipLaunchKernelGGL((KERNEL<T, 4, 8, BF>), g, b, 0, s, __VA_ARGS__);  \
+    else hipLaunchKernelGGL((KERNEL<T, 0, 0, BF>), g, b, 0, s, __VA_ARGS__);                           \
+  } while (0)
+template <typename T>
+void launch_hsweep_pair(const LatDev& L, int y, int last_row, bool bf16, hipStream_t s) {
+  if (L.n_chains < 2) return;
+  if constexpr (sizeof(T) == 8) {
+    if (bf16) { VP_DISPATCH_PAIR(k_hsweep_pair, T, true, L, y, last_row); return; }
+  }
+  VP_DISPATCH_PAIR(k_hsweep_pair, T, false, L, y, last_row);
+}
+template <typename T>
+void launch_vsweep_pair(const LatDev& L, int y, bool bf16, hipStream_t s) {
+  if (L.n_chains < 2) return;
+  if constexpr (sizeof(T) == 8) {
+    if (bf16) { VP_DISPATCH_PAIR(k_vsweep_pair, T, true, L, y); return; }
+  }
+  VP_DISPATCH_PAIR(k_vsweep_pair, T, false, L, y);
+}
 template <typename T>
 void launch_compress(const LatDev& L, int y, int upper, hipStream_t s) {
   if (L.cmode == 1) VP_DISPATCH_DC(k_compress_fit, T, L, y, upper);
@@ -1421,6 +1691,8 @@ void launch_sign_sgd(double* T, const double* g, int64_t Np, double step_len, ui
   template void launch_psi_fixed<T>(const LatDev&, hipStream_t);                                    \
   template void launch_row4_right<T>(const LatDev&, int, bool, hipStream_t);                              \
   template void launch_vsweep<T>(const LatDev&, int, bool, bool, hipStream_t);                                \
+  template void launch_hsweep_pair<T>(const LatDev&, int, int, bool, hipStream_t);                            \
+  template void launch_vsweep_pair<T>(const LatDev&, int, bool, hipStream_t);                                 \
   template void launch_sweep_queue<T>(const LatDev&, const LatDev*, const SampleOut*, int, const int2*, int, int*, \
                                       bool, int, hipStream_t);                                              \
   template int sweep_queue_occupancy<T>(const LatDev&, bool);                                \

@@ -100,6 +100,9 @@ template <typename T> void launch_row3_right(const LatDev& L, int y, int ub_slot
 template <typename T> void launch_hsweep(const LatDev& L, int y, int last_row, bool bf16, hipStream_t s);
 template <typename T> void launch_row4_right(const LatDev& L, int y, bool bf16, hipStream_t s);
 template <typename T> void launch_vsweep(const LatDev& L, int y, bool bf16, bool learned, hipStream_t s);
+// Chains of |Phi|^2: the decision phases over the pairs (ch, ch + n_chains/2), grid n_chains/2.
+template <typename T> void launch_hsweep_pair(const LatDev& L, int y, int last_row, bool bf16, hipStream_t s);
+template <typename T> void launch_vsweep_pair(const LatDev& L, int y, bool bf16, hipStream_t s);
 // Persistent whole-sweep launch over (lattice, chain) items; lats/outs/items/next are device arrays,
 // L0 a host copy of any of the lattices (they share d, c and the working type).
 template <typename T> void launch_sweep_queue(const LatDev& L0, const LatDev* lats, const SampleOut* outs,
@@ -179,5 +182,11 @@ void launch_su_absorb(const double* B, const double* lam, const int64_t* offs, c
 void launch_reverse_spins(const int8_t* s, int8_t* t, int64_t n, hipStream_t st);
 void launch_sis_combine(int n, double* log_abs, int8_t* sign, double* e_loc, const double* log_abs_r,
                         const int8_t* sign_r, const double* e_loc_r, double* log_w, hipStream_t st);
+// The pair sampler's measurement: pair c's S values at index c and Sbar values
+// at c + h of (log_abs, sign, e_loc) combined into row m of the [h][n_meas]
+// outputs, and the S configuration (spins [2h][N]) into spins_out (may be null).
+void launch_pair_combine(int h, int n_meas, int m, const double* log_abs, const int8_t* sign, const double* e_loc,
+                         const int8_t* spins, int N, double* out_log_abs, int8_t* out_sign, double* out_e_loc,
+                         int8_t* out_spins, hipStream_t st);
 
 }  // namespace vp

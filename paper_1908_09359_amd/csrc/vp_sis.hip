@@ -53,7 +53,52 @@ __global__ void __launch_bounds__(SIS_WG) k_sis_combine(int n, double* __restric
   log_w[i] = 2.0 * (lphi - la);
 }
 
+// Pair c of the |Phi|^2 chains: S at c, Sbar at c + h; outputs [h][n_meas], row m.
+__global__ void __launch_bounds__(SIS_WG) k_pair_combine(int h, int n_meas, int m, const double* __restrict__ log_abs,
+                                                         const int8_t* __restrict__ sign,
+                                                         const double* __restrict__ e_loc, double* __restrict__ out_la,
+                                                         int8_t* __restrict__ out_sg, double* __restrict__ out_e) {
+  const int c = blockIdx.x * SIS_WG + threadIdx.x;
+  if (c >= h) return;
+  const int64_t o = (int64_t)c * n_meas + m;
+  const double la = log_abs[c], lb = log_abs[c + h];
+  const double mx = fmax(la, lb);
+  const double pa = (double)sign[c] * exp(la - mx);
+  const double pb = (double)sign[c + h] * exp(lb - mx);
+  const double phi = pa + pb;
+  if (phi == 0.0) {  // no weight under |Phi|^2 (only a start can be here)
+    out_la[o] = -INFINITY;
+    out_sg[o] = 0;
+    out_e[o] = 0.0;
+    return;
+  }
+  out_la[o] = mx + log(fabs(phi));
+  out_sg[o] = phi > 0.0 ? 1 : -1;
+  out_e[o] = (pa * e_loc[c] + pb * e_loc[c + h]) / phi;
+}
+
+__global__ void __launch_bounds__(SIS_WG) k_pair_spins(int h, int n_meas, int m, int N, const int8_t* __restrict__ spins,
+                                                       int8_t* __restrict__ out) {
+  const int64_t n = (int64_t)h * N;
+  for (int64_t i = blockIdx.x * (int64_t)SIS_WG + threadIdx.x; i < n; i += (int64_t)gridDim.x * SIS_WG) {
+    const int64_t c = i / N, k = i - c * N;
+    out[(c * n_meas + m) * N + k] = spins[i];
+  }
+}
+
 }  // namespace
+
+void launch_pair_combine(int h, int n_meas, int m, const double* log_abs, const int8_t* sign, const double* e_loc,
+                         const int8_t* spins, int N, double* out_log_abs, int8_t* out_sign, double* out_e_loc,
+                         int8_t* out_spins, hipStream_t st) {
+  if (h <= 0) return;
+  k_pair_combine<<<(h + SIS_WG - 1) / SIS_WG, SIS_WG, 0, st>>>(h, n_meas, m, log_abs, sign, e_loc, out_log_abs,
+                                                               out_sign, out_e_loc);
+  if (out_spins) {
+    const int64_t blocks = ((int64_t)h * N + SIS_WG - 1) / SIS_WG;
+    k_pair_spins<<<(unsigned)(blocks < 4096 ? blocks : 4096), SIS_WG, 0, st>>>(h, n_meas, m, N, spins, out_spins);
+  }
+}
 
 void launch_reverse_spins(const int8_t* s, int8_t* t, int64_t n, hipStream_t st) {
   if (n <= 0) return;
