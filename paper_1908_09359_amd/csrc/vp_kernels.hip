@@ -390,6 +390,10 @@ __device__ __forceinline__ void ph_vsweep(const LatDev& L, int ch, int y, char* 
   int slot[4] = {0, 1, 2, 3};  // cur, nxt, f (and a fourth temp for plaquette moves)
   set_unit<T>(tmp + slot[0] * sz, sz);
   int ecur = 0;
+  // a learned move at (y, x-1) has already contracted the network through
+  // column x for the spins it left: that is this column's nxt (exponent epre)
+  bool have_nxt = false;
+  int epre = 0;
   for (int x = 0; x < L.Lx; ++x) {
     const T* Ux = ub<T>(L, C, y, x);
     const T* Dx = db<T>(L, C, y + 2, x);
@@ -398,7 +402,9 @@ __device__ __forceinline__ void ph_vsweep(const LatDev& L, int ch, int y, char* 
     const int vb = y * (2 * L.Lx - 1) + (L.Lx - 1) + x;
     if (C.sp[y * L.Lx + x] == C.sp[(y + 1) * L.Lx + x]) trace_skip(L, C.id, vb);
     if (x == L.Lx - 1 && !(C.sp[y * L.Lx + x] != C.sp[(y + 1) * L.Lx + x])) break;
-    int enxt = ecur + step4<T, DD, CC, BF16, BBX>(L, C, nxt, cur, y, x, 0, 0, Ux, Dx, false, as_lds(lds));
+    int enxt = have_nxt ? epre : ecur + step4<T, DD, CC, BF16, BBX>(L, C, nxt, cur, y, x, 0, 0, Ux, Dx, false,
+                                                                       as_lds(lds));
+    have_nxt = false;
     const int k1 = y * L.Lx + x, k2 = (y + 1) * L.Lx + x;
     if (C.sp[k1] != C.sp[k2]) {
       T* f = tmp + slot[2] * sz;
@@ -460,6 +466,11 @@ __device__ __forceinline__ void ph_vsweep(const LatDev& L, int ch, int y, char* 
             int t = slot[1]; slot[1] = slot[2]; slot[2] = t;
             enxt = ef1;
           }
+          // the next column's nxt: f2 (accepted) or the current network through x+1
+          // (rejected, in the slot of cur, which becomes the nxt slot below)
+          have_nxt = true;
+          epre = acc ? ef2 : eden;
+          if (acc) { int t = slot[0]; slot[0] = slot[3]; slot[3] = t; }
         }
       }
     }
