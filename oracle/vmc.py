@@ -183,12 +183,14 @@ class Chain:
         self.plaq_proposed = 0
 
 
-def _top_down_pass(T, lat, ch, Dl, proposal=None):
+def _top_down_pass(T, lat, ch, Dl, proposal=None, vertical=True):
     """Visit every bond once in the pinned order, accepting with r < |Psi(S_b)/Psi(S_a)|^2.
 
     With ``proposal`` (flat network parameters, see ``oracle.proposal``) the
     row-pair step also visits plaquette (y, x) right after the vertical bond
-    (y, x)-(y+1, x), for x = 0..Lx-2 (``_plaquette_step``).
+    (y, x)-(y+1, x), for x = 0..Lx-2 (``_plaquette_step``).  With
+    ``vertical=False`` only the horizontal bonds are visited (each keeps its
+    bond index y(2Lx-1)+x); the vertical ones are left to another pass.
 
     Returns the upper boundaries of the final configuration and (sign, log|Psi|).
     """
@@ -218,6 +220,12 @@ def _top_down_pass(T, lat, ch, Dl, proposal=None):
             row = row_tensors(T, lat, ch.spins, y)
             last = row3_value(Uy1, row, Dn)
             break
+        if not vertical:
+            bond += lat.Lx
+            Uy, lognu = compress_boundary(absorb_down(Uy1, row_tensors(T, lat, ch.spins, y)), lat)
+            U.append(Uy)
+            lam.append(lam[-1] + lognu)
+            continue
         # Vertical bonds between rows y and y+1.
         D2 = Dl[y + 2]
         r1 = row_tensors(T, lat, ch.spins, y)
