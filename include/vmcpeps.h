@@ -124,6 +124,26 @@ typedef enum { VP_COMPRESS_CANONICAL = 0, VP_COMPRESS_VARIATIONAL = 1 } vp_compr
  * the square-lattice one in both. */
 typedef enum { VP_GEOM_SQUARE = 0, VP_GEOM_TRIANGULAR = 1 } vp_geometry;
 
+/* How the vertical bonds' ratios are contracted (App. C: the horizontal terms
+ * of row k from 3-line networks between its row boundaries, the other terms
+ * "similarly computed").  VP_VERT_ROWPAIR: the 2-row network of rows y, y+1
+ * between U_{y-1} and D_{y+2}.  VP_VERT_COLUMN: column-wise boundaries - the
+ * vertical bond (y,x)-(y+1,x) is the horizontal bond (x,y)-(x,y+1) of the
+ * transposed lattice (site (y,x) -> (x,y), legs (l,u,r,d) -> (u,l,d,r); the
+ * same state), whose 3-line networks run between column boundary MPS.  The
+ * context keeps that transposed lattice beside the user's (its workspace is
+ * counted by vp_workspace_bytes) and refreshes its tensors whenever the
+ * tensors change.  A sweep of vp_sample then visits the horizontal bonds row
+ * by row (row boundaries, bond indices as in VP_VERT_ROWPAIR), then the
+ * vertical bonds column by column: the transposed lattice's horizontal pass,
+ * after a lower-boundary pass of its own, with Philox key word 1 = lattice
+ * index + 65536 and bond index x(2Ly-1)+y for the bond (y,x)-(y+1,x).  A
+ * measured sweep evaluates the final configuration (Psi and G from the row
+ * networks, E_loc from both).  Nearest-neighbour square lattices only
+ * (J2 = 0), the pair sampler and the per-phase schedule
+ * (VP_ERR_UNSUPPORTED otherwise). */
+typedef enum { VP_VERT_ROWPAIR = 0, VP_VERT_COLUMN = 1 } vp_vertical;
+
 typedef struct {
   int32_t Ly, Lx;      /* lattice extent */
   int32_t D;           /* PEPS virtual bond dimension */
@@ -134,6 +154,7 @@ typedef struct {
   int32_t compress;    /* vp_compress (0 = canonical, the zero-initialised default) */
   int32_t fit_sweeps;  /* sweeps of VP_COMPRESS_VARIATIONAL (0..64) */
   int32_t geometry;    /* vp_geometry (0 = square, the zero-initialised default) */
+  int32_t vertical;    /* vp_vertical (0 = 2-row networks, the default) */
 } vp_lattice;
 
 typedef struct vp_ctx vp_ctx;

@@ -15,6 +15,7 @@ VP_OK, VP_ERR_ARG, VP_ERR_SHAPE, VP_ERR_OOM, VP_ERR_DEVICE = 0, 1, 2, 3, 4
 VP_ERR_ZERO_AMPLITUDE, VP_ERR_NONFINITE, VP_ERR_UNSUPPORTED = 5, 6, 7
 VP_COMPRESS_CANONICAL, VP_COMPRESS_VARIATIONAL = 0, 1
 VP_GEOM_SQUARE, VP_GEOM_TRIANGULAR = 0, 1
+VP_VERT_ROWPAIR, VP_VERT_COLUMN = 0, 1
 VP_FP64, VP_FP32, VP_BF16 = 0, 1, 2
 VP_SAMPLER_PAIR_SEQ, VP_SAMPLER_LEARNED_PLAQ, VP_SAMPLER_SIS_PAIR = 0, 1, 2
 VP_SCHED_PHASES, VP_SCHED_PERSISTENT, VP_SCHED_GRAPH = 0, 1, 2
@@ -46,7 +47,7 @@ class vp_lattice(ctypes.Structure):
     _fields_ = [("Ly", ctypes.c_int32), ("Lx", ctypes.c_int32), ("D", ctypes.c_int32), ("Dc", ctypes.c_int32),
                 ("J1", ctypes.c_double), ("J2", ctypes.c_double), ("prec", ctypes.c_int32),
                 ("n_chains", ctypes.c_int32), ("compress", ctypes.c_int32), ("fit_sweeps", ctypes.c_int32),
-                ("geometry", ctypes.c_int32)]
+                ("geometry", ctypes.c_int32), ("vertical", ctypes.c_int32)]
 
 
 class VPError(RuntimeError):
@@ -124,10 +125,11 @@ def _ptr(t):
 
 
 def lattice(Ly, Lx, D, Dc, J1=1.0, J2=0.0, prec=VP_FP64, n_chains=1, compress=0, fit_sweeps=0,
-            geometry=0):
+            geometry=0, vertical=0):
     """A vp_lattice; compress = VP_COMPRESS_CANONICAL (0) or VP_COMPRESS_VARIATIONAL (1);
-    geometry = VP_GEOM_SQUARE (0) or VP_GEOM_TRIANGULAR (1)."""
-    return vp_lattice(Ly, Lx, D, Dc, J1, J2, prec, n_chains, compress, fit_sweeps, geometry)
+    geometry = VP_GEOM_SQUARE (0) or VP_GEOM_TRIANGULAR (1); vertical = VP_VERT_ROWPAIR (0)
+    or VP_VERT_COLUMN (1)."""
+    return vp_lattice(Ly, Lx, D, Dc, J1, J2, prec, n_chains, compress, fit_sweeps, geometry, vertical)
 
 
 def vp_num_params(lat):

@@ -20,7 +20,7 @@ BUILD = os.path.join(ROOT, "_build")
 # (source, object name, extra flags): the phase kernels compile once per working type
 SOURCES = [("vp_kernels.hip", "vp_kernels_f64", ["-DVP_KERNEL_UNIT=0"]),
            ("vp_kernels.hip", "vp_kernels_f32", ["-DVP_KERNEL_UNIT=1"]),
-           ("vp_sr.hip", "vp_sr", []), ("vp_net.hip", "vp_net", []), ("vp_sis.hip", "vp_sis", []), ("vp_su.hip", "vp_su", []),
+           ("vp_sr.hip", "vp_sr", []), ("vp_net.hip", "vp_net", []), ("vp_sis.hip", "vp_sis", []), ("vp_su.hip", "vp_su", []), ("vp_cols.hip", "vp_cols", []),
            ("vp_api.cpp", "vp_api", [])]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

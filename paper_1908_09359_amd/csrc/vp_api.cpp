@@ -65,17 +65,21 @@ struct Lattice {
   Buf nw_work, nw_part, nw_cnt, nw_scal, nw_grad, nw_sb, nw_rb, nw_idx;
   // simple update: site tensors, link lambdas, per-link changes, per-work-group scratch
   Buf su_B, su_lam, su_change, su_scr;
+  // VP_VERT_COLUMN evaluation: the transposed lattice's pair ratios
+  Buf col_ratios;
   bool su_valid = false;        // su_B / su_lam hold the evolution of the current tensors
   LatDev dev{};
   bool tensors_ready = false;
   bool chains_ready = false;
   bool lower_valid = false;     // D boundaries match the current spins
+  int col = -1;                 // VP_VERT_COLUMN: index of the transposed lattice in vp_ctx::lats, else -1
 };
 
 }  // namespace
 
 struct vp_ctx {
-  std::vector<Lattice> lats;
+  std::vector<Lattice> lats;         // the caller's lattices, then the transposed ones of VP_VERT_COLUMN
+  int32_t n_user = 0;                // lattices the caller indexes
   uint64_t seed = 0;
   hipStream_t stream = nullptr;
   std::string err;
@@ -263,7 +267,20 @@ vp_status check_lattice(vp_ctx* ctx, const vp_lattice& p) {
     return fail(ctx, VP_ERR_ARG, "unknown geometry %d", p.geometry);
   if (p.geometry == VP_GEOM_TRIANGULAR && p.J2 != 0.0)
     return fail(ctx, VP_ERR_UNSUPPORTED, "triangular lattice: its J2 bonds are not built, J2 must be 0");
+  if (p.vertical != VP_VERT_ROWPAIR && p.vertical != VP_VERT_COLUMN)
+    return fail(ctx, VP_ERR_ARG, "unknown vertical-bond mode %d", p.vertical);
+  if (p.vertical == VP_VERT_COLUMN && (p.J2 != 0.0 || p.geometry != VP_GEOM_SQUARE))
+    return fail(ctx, VP_ERR_UNSUPPORTED, "column-wise vertical bonds: nearest-neighbour square lattices only");
   return VP_OK;
+}
+
+// The transposed lattice of a VP_VERT_COLUMN lattice: Lx x Ly, everything else equal.
+vp_lattice transposed_params(const vp_lattice& p) {
+  vp_lattice t = p;
+  t.Ly = p.Lx;
+  t.Lx = p.Ly;
+  t.vertical = VP_VERT_ROWPAIR;
+  return t;
 }
 
 // Couplings of the diagonal (y,x)-(y+1,x+1) and the anti-diagonal (y,x+1)-(y+1,x).
@@ -272,7 +289,7 @@ double anti_coupling(const vp_lattice& p) { return p.geometry == VP_GEOM_TRIANGU
 bool has_diagonals(const vp_lattice& p) { return diag_coupling(p) != 0.0 || anti_coupling(p) != 0.0; }
 
 Lattice* get_lat(vp_ctx* ctx, int32_t lat) {
-  if (!ctx || lat < 0 || lat >= (int32_t)ctx->lats.size()) return nullptr;
+  if (!ctx || lat < 0 || lat >= ctx->n_user) return nullptr;
   return &ctx->lats[lat];
 }
 
@@ -463,17 +480,93 @@ vp_status run_graph(vp_ctx* ctx, Lattice& L, int n_burn, int n_meas, const Sampl
 }
 
 template <typename T>
-void run_eval(const LatDev& D, const SampleOut& o, int n_cfg, hipStream_t s) {
+void run_eval(const LatDev& D, const SampleOut& o, int n_cfg, hipStream_t s, bool rowpair = true) {
   const int Ly = D.Ly;
   for (int y = 0; y < Ly - 1; ++y) launch_compress<T>(D, y, 1, s);
   launch_psi_fixed<T>(D, s);
   launch_begin_sample(D, s);
   for (int y = Ly - 1; y >= 0; --y) {
     launch_measure3<T>(D, y, o, s);
-    if (y < Ly - 1) launch_measure4<T>(D, y, o, s);
+    if (y < Ly - 1 && rowpair) launch_measure4<T>(D, y, o, s);
     if (y >= 1) launch_compress<T>(D, y, 0, s);
   }
   launch_finish_sample(D, o, n_cfg, s);
+}
+
+// Per-chain scratch of one measurement (log|Psi|, E_loc, sign), in the region
+// reserved at vp_create after the spin-inversion configurations.
+SampleOut scratch_out(Lattice& L) {
+  const size_t nb = (size_t)L.p.n_chains * L.N;
+  const size_t off_l = (nb + 255) / 256 * 256, off_e = off_l + sizeof(double) * L.p.n_chains,
+               off_s = off_e + sizeof(double) * L.p.n_chains;
+  SampleOut o{};
+  o.log_abs_psi = (double*)(L.d_sis + off_l);
+  o.e_loc = (double*)(L.d_sis + off_e);
+  o.sign = (int8_t*)(L.d_sis + off_s);
+  o.n_meas = 1;
+  o.m = 0;
+  o.dyn_m = 0;
+  o.np_half = L.Np / 2;
+  return o;
+}
+
+// VP_VERT_COLUMN sampling: every sweep visits the horizontal bonds with the row
+// boundaries, then the vertical bonds as the horizontal bonds of the transposed
+// lattice C (after its own lower-boundary pass); a measured sweep evaluates the
+// final configuration: the rows' upper boundaries afresh and their measurement
+// pass (Psi, horizontal terms, G), then C's measurement pass (its upper
+// boundaries are those of its pass), whose energies are added to the rows'.
+template <typename T>
+vp_status run_col_sample(vp_ctx* ctx, Lattice& L, Lattice& C, int n_burn, int n_meas, SampleOut o) {
+  hipStream_t s = ctx->stream;
+  const int Ly = L.p.Ly, Lx = L.p.Lx, n = L.p.n_chains;
+  const bool bf = L.p.prec == VP_BF16;
+  if (!L.lower_valid) {
+    run_lower_pass<T>(ctx, L, s);
+    L.lower_valid = true;
+  }
+  o.psi_meas = 1;  // Psi of the final configuration, from the rows' measurement pass
+  SampleOut oc = scratch_out(C);
+  oc.psi_meas = 0;
+  Rec r(ctx);
+  for (int i = 0; i < n_burn + n_meas; ++i) {
+    for (int y = 0; y < Ly; ++y) {
+      TIMED(r, VP_PH_ROW3_ENVS, launch_row3_right<T>(L.dev, y, y, y + 1, bf, s));
+      TIMED(r, VP_PH_HSWEEP, launch_hsweep<T>(L.dev, y, y == Ly - 1, bf, s));
+      if (y < Ly - 1) TIMED(r, VP_PH_COMPRESS_UP, launch_compress<T>(L.dev, y, 1, s));
+    }
+    launch_transpose_spins(L.spins, C.spins, n, Ly, Lx, true, s);
+    run_lower_pass<T>(ctx, C, s);
+    for (int y = 0; y < Lx; ++y) {
+      TIMED(r, VP_PH_ROW3_ENVS, launch_row3_right<T>(C.dev, y, y, y + 1, bf, s));
+      TIMED(r, VP_PH_HSWEEP, launch_hsweep<T>(C.dev, y, y == Lx - 1, bf, s));
+      if (y < Lx - 1) TIMED(r, VP_PH_COMPRESS_UP, launch_compress<T>(C.dev, y, 1, s));
+    }
+    launch_transpose_spins(C.spins, L.spins, n, Ly, Lx, false, s);
+    if (i >= n_burn) {
+      for (int y = 0; y < Ly - 1; ++y) TIMED(r, VP_PH_COMPRESS_UP, launch_compress<T>(L.dev, y, 1, s));
+      TIMED(r, VP_PH_OTHER, launch_begin_sample(L.dev, s));
+      for (int y = Ly - 1; y >= 0; --y) {
+        TIMED(r, VP_PH_MEASURE3, launch_measure3<T>(L.dev, y, o, s));
+        if (y >= 1) TIMED(r, VP_PH_COMPRESS_DOWN, launch_compress<T>(L.dev, y, 0, s));
+      }
+      TIMED(r, VP_PH_OTHER, launch_finish_sample(L.dev, o, n, s));
+      TIMED(r, VP_PH_OTHER, launch_begin_sample(C.dev, s));
+      for (int y = Lx - 1; y >= 0; --y) {
+        TIMED(r, VP_PH_MEASURE3, launch_measure3<T>(C.dev, y, oc, s));
+        if (y >= 1) TIMED(r, VP_PH_COMPRESS_DOWN, launch_compress<T>(C.dev, y, 0, s));
+      }
+      TIMED(r, VP_PH_OTHER, launch_finish_sample(C.dev, oc, n, s));
+      launch_add_energy(o.e_loc, n_meas, i - n_burn, oc.e_loc, n, s);
+    } else {
+      for (int y = Ly - 1; y >= 1; --y) TIMED(r, VP_PH_COMPRESS_DOWN, launch_compress<T>(L.dev, y, 0, s));
+    }
+    TIMED(r, VP_PH_OTHER, launch_next_sweep(L.dev, s));
+    TIMED(r, VP_PH_OTHER, launch_next_sweep(C.dev, s));
+    HIP_TRY(ctx, hipGetLastError());
+    if (ctx->ev_used >= 8192) fold_timing(ctx);
+  }
+  return VP_OK;
 }
 
 // Chains of |Phi|^2 (VP_SAMPLER_SIS_PAIR): chain c and c + n/2 carry S and its
@@ -540,9 +633,15 @@ vp_status run_pair_sample(vp_ctx* ctx, Lattice& L, int n_burn, int n_meas, doubl
 }
 
 vp_status check_flags(vp_ctx* ctx, Lattice& L) {
-  std::vector<ChainMeta> m(L.p.n_chains);
+  std::vector<ChainMeta> m(L.p.n_chains), mc;
   HIP_TRY(ctx, hipMemcpyAsync(m.data(), L.meta, sizeof(ChainMeta) * m.size(), hipMemcpyDeviceToHost, ctx->stream));
+  if (L.col >= 0) {  // the transposed lattice's chains of VP_VERT_COLUMN
+    mc.resize(m.size());
+    HIP_TRY(ctx, hipMemcpyAsync(mc.data(), ctx->lats[L.col].meta, sizeof(ChainMeta) * mc.size(),
+                                hipMemcpyDeviceToHost, ctx->stream));
+  }
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+  for (size_t i = 0; i < mc.size(); ++i) m[i].flags |= mc[i].flags;
   int zero = 0, nonfin = 0;
   for (auto& x : m) {
     zero += (x.flags & FLAG_ZERO) != 0;
@@ -592,13 +691,38 @@ vp_status eval_configs(vp_ctx* ctx, Lattice* L, const int8_t* spins_dev, int32_t
   o.m = row;
   o.np_half = L->Np / 2;
   o.n_pairs = p.Ly * (p.Lx - 1) + (p.Ly - 1) * p.Lx + (has_diagonals(p) ? 2 * (p.Ly - 1) * (p.Lx - 1) : 0);
-  if (works_f64(p.prec)) run_eval<double>(D, o, n_cfg, s); else run_eval<float>(D, o, n_cfg, s);
+  const bool cols = L->col >= 0;
+  if (works_f64(p.prec)) run_eval<double>(D, o, n_cfg, s, !cols); else run_eval<float>(D, o, n_cfg, s, !cols);
   HIP_TRY(ctx, hipGetLastError());
   L->chains_ready = false;
   L->lower_valid = false;
-  std::vector<ChainMeta> m(n_cfg);
+  std::vector<ChainMeta> m(n_cfg), mc;
+  if (cols) {
+    // VP_VERT_COLUMN: the vertical terms from the transposed lattice's horizontal ones
+    Lattice& C = ctx->lats[L->col];
+    // the transposed configurations through the scratch (the copy clears their flags)
+    launch_transpose_spins(L->spins, (int8_t*)C.d_sis, n_cfg, p.Ly, p.Lx, true, s);
+    launch_copy_spins(C.dev, (const int8_t*)C.d_sis, n_cfg, s);
+    LatDev Dt = C.dev;
+    Dt.n_chains = n_cfg;
+    SampleOut oc = scratch_out(C);
+    const int npt = C.p.Ly * (C.p.Lx - 1) + (C.p.Ly - 1) * C.p.Lx;
+    oc.n_pairs = npt;
+    if (o.ratios) {
+      if (!grow(s, C.col_ratios, sizeof(double) * (size_t)n_cfg * npt))
+        return fail(ctx, VP_ERR_OOM, "column-wise ratio workspace");
+      oc.ratios = (double*)C.col_ratios.p;
+    }
+    if (works_f64(p.prec)) run_eval<double>(Dt, oc, n_cfg, s, false); else run_eval<float>(Dt, oc, n_cfg, s, false);
+    launch_add_energy(o.e_loc, n_meas, row, oc.e_loc, n_cfg, s);
+    if (o.ratios) launch_column_ratios(oc.ratios, npt, o.ratios, o.n_pairs, n_cfg, p.Ly, p.Lx, s);
+    HIP_TRY(ctx, hipGetLastError());
+    mc.resize(n_cfg);
+    HIP_TRY(ctx, hipMemcpyAsync(mc.data(), C.meta, sizeof(ChainMeta) * n_cfg, hipMemcpyDeviceToHost, s));
+  }
   HIP_TRY(ctx, hipMemcpyAsync(m.data(), L->meta, sizeof(ChainMeta) * n_cfg, hipMemcpyDeviceToHost, s));
   HIP_TRY(ctx, hipStreamSynchronize(s));
+  for (size_t i = 0; i < mc.size(); ++i) m[i].flags |= mc[i].flags;
   for (int i = 0; i < n_cfg; ++i) {
     if (m[i].flags & FLAG_NONFINITE) return fail(ctx, VP_ERR_NONFINITE, "configuration %d: non-finite value", i);
     if (m[i].flags & FLAG_ZERO) return fail(ctx, VP_ERR_ZERO_AMPLITUDE, "configuration %d: zero amplitude", i);
@@ -650,8 +774,15 @@ int64_t vp_num_params(const vp_lattice* p) {
 int64_t vp_workspace_bytes(const vp_lattice* p) {
   if (!p) return -1;
   Plan P = plan_workspace(*p, nullptr);
-  return (int64_t)p->n_chains * (P.ws * (int64_t)type_size(p->prec) + P.cws * 8 + P.iws * 4 + P.dws * 8 +
-                                 p->Ly * p->Lx + (int64_t)sizeof(ChainMeta));
+  int64_t b = (int64_t)p->n_chains * (P.ws * (int64_t)type_size(p->prec) + P.cws * 8 + P.iws * 4 + P.dws * 8 +
+                                      p->Ly * p->Lx + (int64_t)sizeof(ChainMeta));
+  if (p->vertical == VP_VERT_COLUMN) {  // the transposed lattice's chains
+    const vp_lattice t = transposed_params(*p);
+    Plan Q = plan_workspace(t, nullptr);
+    b += (int64_t)t.n_chains * (Q.ws * (int64_t)type_size(t.prec) + Q.cws * 8 + Q.iws * 4 + Q.dws * 8 +
+                                t.Ly * t.Lx + (int64_t)sizeof(ChainMeta));
+  }
+  return b;
 }
 
 const char* vp_last_error(const vp_ctx* ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
@@ -677,10 +808,23 @@ vp_status vp_create(const vp_lattice* lats, int32_t n_lats, uint64_t seed, void*
   vp_ctx* ctx = new vp_ctx;
   ctx->seed = seed;
   ctx->stream = (hipStream_t)stream;
-  ctx->lats.resize(n_lats);
-  for (int i = 0; i < n_lats; ++i) {
+  // the caller's lattices, then the transposed lattice of each VP_VERT_COLUMN
+  // one (Philox key word 1: its lattice index + 65536)
+  std::vector<vp_lattice> all(lats, lats + n_lats);
+  std::vector<int> key(n_lats);
+  for (int i = 0; i < n_lats; ++i) key[i] = i;
+  for (int i = 0; i < n_lats; ++i)
+    if (lats[i].vertical == VP_VERT_COLUMN) {
+      all.push_back(transposed_params(lats[i]));
+      key.push_back(i + 65536);
+    }
+  ctx->n_user = n_lats;
+  ctx->lats.resize(all.size());
+  for (int i = 0, t = n_lats; i < n_lats; ++i)
+    if (lats[i].vertical == VP_VERT_COLUMN) ctx->lats[i].col = t++;
+  for (int i = 0; i < (int)all.size(); ++i) {
     Lattice& L = ctx->lats[i];
-    L.p = lats[i];
+    L.p = all[i];
     const vp_lattice& p = L.p;
     L.N = p.Ly * p.Lx;
     L.tsize = type_size(p.prec);
@@ -733,7 +877,7 @@ vp_status vp_create(const vp_lattice* lats, int32_t n_lats, uint64_t seed, void*
     LatDev& D = L.dev;
     D.Ly = p.Ly; D.Lx = p.Lx; D.d = p.D; D.c = p.Dc; D.N = L.N;
     D.J1 = p.J1; D.Jd = diag_coupling(p); D.Ja = anti_coupling(p); D.n_chains = p.n_chains;
-    D.seed = seed; D.lat_id = i;
+    D.seed = seed; D.lat_id = key[i];
     D.cmode = p.compress; D.fit_sweeps = p.fit_sweeps;
     D.Tw = L.Tw; D.ws = L.ws; D.ws_stride = P.ws;
     D.cws = L.cws; D.cws_stride = P.cws;
@@ -767,7 +911,8 @@ vp_status vp_destroy(vp_ctx* ctx) {
       if (q) hipFree(q);
     Lattice::Buf* bufs[] = {&L.sr_work, &L.sr_flag, &L.opt_lp, &L.opt_el, &L.opt_grad, &L.opt_em, &L.opt_sg,
                             &L.opt_so, &L.opt_dl, &L.nw_work, &L.nw_part, &L.nw_cnt, &L.nw_scal, &L.nw_grad,
-                            &L.nw_sb, &L.nw_rb, &L.nw_idx, &L.su_B, &L.su_lam, &L.su_change, &L.su_scr};
+                            &L.nw_sb, &L.nw_rb, &L.nw_idx, &L.su_B, &L.su_lam, &L.su_change, &L.su_scr,
+                            &L.col_ratios};
     for (Lattice::Buf* b : bufs)
       if (b->p) hipFree(b->p);
   }
@@ -789,6 +934,12 @@ static vp_status stage_tensors(vp_ctx* ctx, Lattice& L) {
   L.tensors_ready = true;
   L.lower_valid = false;
   L.su_valid = false;
+  if (L.col >= 0) {  // VP_VERT_COLUMN: the transposed lattice carries the same state
+    Lattice& C = ctx->lats[L.col];
+    launch_transpose_tensors(L.T, C.T, L.d_offs, C.d_offs, L.d_dims, L.p.Ly, L.p.Lx, ctx->stream);
+    HIP_TRY(ctx, hipGetLastError());
+    return stage_tensors(ctx, C);
+  }
   return VP_OK;
 }
 
@@ -910,6 +1061,8 @@ vp_status vp_init_chains(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev) {
   L->chains_ready = true;
   L->sweeps = 0;
   L->lower_valid = false;
+  if (L->col >= 0)  // the transposed lattice's sweep and move counters follow the chains
+    HIP_TRY(ctx, hipMemsetAsync(ctx->lats[L->col].meta, 0, sizeof(ChainMeta) * L->p.n_chains, ctx->stream));
   return VP_OK;
 }
 
@@ -939,6 +1092,29 @@ vp_status vp_sample(vp_ctx* ctx, int32_t lat, int32_t n_burn, int32_t n_meas, do
       HIP_TRY(ctx, hipMemcpy2DAsync(accept_dev, 2 * sizeof(int64_t), (const char*)L->meta + sizeof(int64_t),
                                     sizeof(ChainMeta), 2 * sizeof(int64_t), L->p.n_chains / 2,
                                     hipMemcpyDeviceToDevice, s));
+    return VP_OK;
+  }
+  if (L->col >= 0) {
+    if (L->schedule != VP_SCHED_PHASES)
+      return fail(ctx, VP_ERR_UNSUPPORTED, "column-wise vertical bonds run the per-phase schedule only");
+    Lattice& C = ctx->lats[L->col];
+    SampleOut o{};
+    o.log_abs_psi = log_abs_psi_dev;
+    o.sign = sign_dev;
+    o.e_loc = e_loc_dev;
+    o.dlnpsi = dlnpsi_dev;
+    o.spins = spins_out_dev;
+    o.n_meas = n_meas;
+    o.m = 0;
+    o.dyn_m = 1;  // row = sweep counter - (counter at the first measured sweep)
+    o.sweep0 = L->sweeps + n_burn;
+    o.np_half = L->Np / 2;
+    vp_status st = f64 ? run_col_sample<double>(ctx, *L, C, n_burn, n_meas, o)
+                       : run_col_sample<float>(ctx, *L, C, n_burn, n_meas, o);
+    if (st != VP_OK) return st;
+    L->sweeps += n_burn + n_meas;
+    if (accept_dev) launch_sum_counts(L->meta, C.meta, accept_dev, L->p.n_chains, s);
+    HIP_TRY(ctx, hipGetLastError());
     return VP_OK;
   }
   if (!L->lower_valid) {
@@ -1015,6 +1191,9 @@ vp_status vp_sample_batch(vp_ctx* ctx, int32_t n_lats, const int32_t* lats_host,
       return fail(ctx, VP_ERR_ARG, "lattice %d: tensors and chains must be initialised first", lats_host[i]);
     if (L->sampler == VP_SAMPLER_SIS_PAIR)
       return fail(ctx, VP_ERR_UNSUPPORTED, "lattice %d: the |Phi|^2 sampler runs through vp_sample only", lats_host[i]);
+    if (L->col >= 0)
+      return fail(ctx, VP_ERR_UNSUPPORTED, "lattice %d: column-wise vertical bonds run through vp_sample only",
+                  lats_host[i]);
     if (!ls.empty() && (L->p.D != ls[0]->p.D || L->p.Dc != ls[0]->p.Dc || L->p.prec != ls[0]->p.prec))
       return fail(ctx, VP_ERR_SHAPE, "one batch needs equal D, Dc and precision");
     SampleOut o{};
@@ -1134,6 +1313,7 @@ vp_status vp_autotune_tiles(vp_ctx* ctx, int32_t lat, int32_t sweeps, double* ms
 vp_status vp_trace_ratios(vp_ctx* ctx, int32_t lat, double* trace_dev) {
   Lattice* L = get_lat(ctx, lat);
   if (!L) return fail(ctx, VP_ERR_ARG, "bad lattice index");
+  if (L->col >= 0) return fail(ctx, VP_ERR_UNSUPPORTED, "no ratio trace with column-wise vertical bonds");
   L->dev.trace = trace_dev;
   return VP_OK;
 }
@@ -1203,6 +1383,8 @@ vp_status vp_sample_split(vp_ctx* ctx, int32_t lat_sample, int32_t lat_measure, 
     return fail(ctx, VP_ERR_ARG, "tensors of both lattices and the sampling chains must be set first");
   if (A->sampler == VP_SAMPLER_SIS_PAIR)
     return fail(ctx, VP_ERR_UNSUPPORTED, "the |Phi|^2 sampler runs through vp_sample only");
+  if (A->col >= 0 || M->col >= 0)
+    return fail(ctx, VP_ERR_UNSUPPORTED, "column-wise vertical bonds run through vp_sample and vp_eval only");
   if (n_meas > 0 && (!log_abs_psi_dev || !sign_dev || !e_loc_dev))
     return fail(ctx, VP_ERR_ARG, "log_abs_psi, sign and e_loc outputs are required");
   hipStream_t s = ctx->stream;
@@ -1273,6 +1455,8 @@ vp_status vp_set_sampler(vp_ctx* ctx, int32_t lat, int32_t sampler) {
     return fail(ctx, VP_ERR_ARG, "unknown sampler %d", sampler);
   if (sampler == VP_SAMPLER_SIS_PAIR && L->p.n_chains % 2)
     return fail(ctx, VP_ERR_SHAPE, "the |Phi|^2 sampler pairs the chains: n_chains must be even");
+  if (sampler != VP_SAMPLER_PAIR_SEQ && L->col >= 0)
+    return fail(ctx, VP_ERR_UNSUPPORTED, "column-wise vertical bonds run the pair sampler only");
   if (sampler == VP_SAMPLER_LEARNED_PLAQ && !L->net_ready)
     return fail(ctx, VP_ERR_ARG, "the learned sampler needs proposal weights (vp_proposal_set_weights)");
   if (sampler == VP_SAMPLER_LEARNED_PLAQ && (L->p.Ly < 2 || L->p.Lx < 2))
@@ -1552,7 +1736,8 @@ vp_status vp_timing_read(vp_ctx* ctx, double* ms_host, int64_t* launches_host) {
 vp_status vp_sync(vp_ctx* ctx) {
   if (!ctx) return fail(nullptr, VP_ERR_ARG, "null context");
   HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
-  for (auto& L : ctx->lats) {
+  for (int i = 0; i < ctx->n_user; ++i) {  // a transposed lattice is checked with its own
+    Lattice& L = ctx->lats[i];
     if (!L.chains_ready) continue;
     vp_status st = check_flags(ctx, L);
     if (st != VP_OK) return st;

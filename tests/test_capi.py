@@ -81,6 +81,27 @@ def test_create_checks_the_geometry(J2, geometry, status):
     assert ei.value.status == getattr(binding, status)
 
 
+@pytest.mark.parametrize("J2,geometry,vertical,status", [
+    (0.5, 0, 1, "VP_ERR_UNSUPPORTED"),  # column-wise vertical bonds: no diagonal terms
+    (0.0, 1, 1, "VP_ERR_UNSUPPORTED"),  # nor the triangular geometry
+    (0.0, 0, 2, "VP_ERR_ARG"),          # unknown vertical-bond mode
+])
+def test_create_checks_the_vertical_mode(J2, geometry, vertical, status):
+    from paper_1908_09359_amd import binding
+    with pytest.raises(binding.VPError) as ei:
+        binding.Context(binding.lattice(4, 4, 2, 4, 1.0, J2, binding.VP_FP64, 1, geometry=geometry,
+                                        vertical=vertical))
+    assert ei.value.status == getattr(binding, status)
+
+
+def test_column_mode_workspace_counts_the_transposed_lattice():
+    from paper_1908_09359_amd import binding
+    a = binding.vp_workspace_bytes(binding.lattice(4, 6, 4, 8, n_chains=8))
+    b = binding.vp_workspace_bytes(binding.lattice(4, 6, 4, 8, n_chains=8, vertical=1))
+    t = binding.vp_workspace_bytes(binding.lattice(6, 4, 4, 8, n_chains=8))
+    assert b == a + t
+
+
 def test_workload_inputs_are_seeded():
     import numpy as np
     from paper_1908_09359_amd import workloads
