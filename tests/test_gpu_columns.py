@@ -178,3 +178,23 @@ def test_column_mode_rules():
         ctx.vp_init_chains(2, None)
     assert ei.value.status == B.VP_ERR_ARG
     ctx.close()
+
+
+def test_column_sampler_bf16_measures_in_float64():
+    """VP_BF16 with column-wise vertical bonds: bf16-operand ratios decide the moves
+    of both passes, the measurement runs in float64 and equals the oracle's
+    column-wise evaluation of every visited configuration."""
+    B = _B()
+    Ly, Lx, D, Dc = 6, 6, 4, 8
+    print("column-wise sampler bf16 6x6 D=4 Dc=8 3 chains 1+2", flush=True)
+    T = W.random_tensors(Ly, Lx, D, seed=29)
+    g = _gpu_sample(Ly, Lx, D, Dc, B.VP_BF16, T, 3, 1, 2, seed=31)
+    lat = olat.Lattice(Ly, Lx, D, Dc)
+    cfgs = g["spins"].reshape(-1, Ly * Lx)
+    assert np.all(cfgs.sum(1) == Ly * Lx // 2)
+    for c, e, lp, s in zip(cfgs, g["e_loc"].reshape(-1), g["log_abs_psi"].reshape(-1), g["sign"].reshape(-1)):
+        o = cols.eval_config(T, lat, c)
+        assert s == o["sign"]
+        assert abs(lp - o["log_abs_psi"]) <= 1e-9
+        assert abs(e - o["e_loc"]) / (Ly * Lx) <= 1e-9
+    assert g["accept"][:, 0].sum() > 0

@@ -166,3 +166,23 @@ def test_pair_sampler_rules():
     ctx.vp_sync()
     assert np.all(np.isfinite(el.cpu().numpy()))
     ctx.close()
+
+
+def test_pair_chains_bf16_sampling_measure_in_float64():
+    """VP_BF16: the pair decisions use bf16-operand ratios, the measurement runs in
+    float64, so every measured sample equals the oracle's evaluation of its
+    configuration at the float64 bounds."""
+    B = _B()
+    Ly, Lx, D, Dc = 6, 6, 4, 8
+    print("|Phi|^2 pair chains bf16 6x6 D=4 Dc=8 3 pairs 1+2", flush=True)
+    T = W.random_tensors(Ly, Lx, D, seed=13)
+    g = _gpu_pair_sample(Ly, Lx, D, Dc, 0.0, B.VP_BF16, T, 3, 1, 2, seed=17)
+    lat = olat.Lattice(Ly, Lx, D, Dc)
+    cfgs = g["spins"].reshape(-1, Ly * Lx)
+    assert np.all(cfgs.sum(1) == Ly * Lx // 2)
+    for c, e, la, s in zip(cfgs, g["e_loc"].reshape(-1), g["log_abs_phi"].reshape(-1), g["sign"].reshape(-1)):
+        ref = sis.eval_config(T, lat, c)
+        assert s == ref["sign"]
+        assert abs(la - ref["log_abs_phi"]) <= 1e-9
+        assert abs(e - ref["e_loc"]) / (Ly * Lx) <= 1e-9
+    assert g["accept"][:, 0].sum() > 0
