@@ -1113,7 +1113,12 @@ vp_status vp_sample(vp_ctx* ctx, int32_t lat, int32_t n_burn, int32_t n_meas, do
                        : run_col_sample<float>(ctx, *L, C, n_burn, n_meas, o);
     if (st != VP_OK) return st;
     L->sweeps += n_burn + n_meas;
-    if (accept_dev) launch_sum_counts(L->meta, C.meta, accept_dev, L->p.n_chains, s);
+    if (accept_dev) {  // the row pass's counts plus the column pass's
+      HIP_TRY(ctx, hipMemcpy2DAsync(accept_dev, 2 * sizeof(int64_t), (const char*)L->meta + sizeof(int64_t),
+                                    sizeof(ChainMeta), 2 * sizeof(int64_t), L->p.n_chains, hipMemcpyDeviceToDevice,
+                                    s));
+      launch_add_counts(C.meta, accept_dev, 2, L->p.n_chains, s);
+    }
     HIP_TRY(ctx, hipGetLastError());
     return VP_OK;
   }
@@ -1475,6 +1480,8 @@ vp_status vp_move_counts(vp_ctx* ctx, int32_t lat, int64_t* counts_dev) {
   HIP_TRY(ctx, hipMemcpy2DAsync(counts_dev + 2, 4 * sizeof(int64_t),
                                 (const char*)L->meta + offsetof(ChainMeta, p_accepted), sizeof(ChainMeta),
                                 2 * sizeof(int64_t), n, hipMemcpyDeviceToDevice, s));
+  if (L->col >= 0) launch_add_counts(ctx->lats[L->col].meta, counts_dev, 4, n, s);  // the vertical moves
+  HIP_TRY(ctx, hipGetLastError());
   return VP_OK;
 }
 

@@ -81,12 +81,13 @@ __global__ void __launch_bounds__(CW) k_add_energy(double* __restrict__ e, int n
   if (c < n) e[(int64_t)c * n_meas + m] += et[c];
 }
 
-__global__ void __launch_bounds__(CW) k_sum_counts(const ChainMeta* __restrict__ a, const ChainMeta* __restrict__ b,
-                                                   int64_t* __restrict__ out, int n) {
+// out[c][0..1] (row stride `stride`) += the transposed lattice's (accepted, proposed)
+__global__ void __launch_bounds__(CW) k_add_counts(const ChainMeta* __restrict__ b, int64_t* __restrict__ out,
+                                                   int stride, int n) {
   const int c = blockIdx.x * CW + threadIdx.x;
   if (c < n) {
-    out[2 * c] = a[c].accepted + b[c].accepted;
-    out[2 * c + 1] = a[c].proposed + b[c].proposed;
+    out[(int64_t)stride * c] += b[c].accepted;
+    out[(int64_t)stride * c + 1] += b[c].proposed;
   }
 }
 
@@ -119,9 +120,9 @@ void launch_add_energy(double* e, int n_meas, int m, const double* et, int n, hi
   k_add_energy<<<(n + CW - 1) / CW, CW, 0, s>>>(e, n_meas, m, et, n);
 }
 
-void launch_sum_counts(const ChainMeta* a, const ChainMeta* b, int64_t* out, int n, hipStream_t s) {
+void launch_add_counts(const ChainMeta* b, int64_t* out, int stride, int n, hipStream_t s) {
   if (n <= 0) return;
-  k_sum_counts<<<(n + CW - 1) / CW, CW, 0, s>>>(a, b, out, n);
+  k_add_counts<<<(n + CW - 1) / CW, CW, 0, s>>>(b, out, stride, n);
 }
 
 }  // namespace vp

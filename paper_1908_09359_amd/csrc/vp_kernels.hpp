@@ -194,13 +194,14 @@ void launch_pair_combine(int h, int n_meas, int m, const double* log_abs, const 
 // lattice's leg dimensions) and configurations ([n_chains][N], to or from the
 // transposed site order), its horizontal ratios placed as the row lattice's
 // vertical ones (rt [n][npt] -> r [n][np]), its energies added into row m of
-// the [n][n_meas] outputs, and the two lattices' move counts summed [n][2].
+// the [n][n_meas] outputs, and its move counts added to (accepted, proposed)
+// at the start of every stride-long row of out [n][stride].
 void launch_transpose_tensors(const double* T, double* Tt, const int64_t* offs, const int64_t* offs_t,
                               const int32_t* dims, int Ly, int Lx, hipStream_t s);
 void launch_transpose_spins(const int8_t* src, int8_t* dst, int n_chains, int Ly, int Lx, bool to_columns,
                             hipStream_t s);
 void launch_column_ratios(const double* rt, int npt, double* r, int np, int n, int Ly, int Lx, hipStream_t s);
 void launch_add_energy(double* e, int n_meas, int m, const double* et, int n, hipStream_t s);
-void launch_sum_counts(const ChainMeta* a, const ChainMeta* b, int64_t* out, int n, hipStream_t s);
+void launch_add_counts(const ChainMeta* b, int64_t* out, int stride, int n, hipStream_t s);
 
 }  // namespace vp

@@ -95,8 +95,10 @@ def _gpu_sample(Ly, Lx, D, Dc, prec, T, n_chains, n_burn, n_meas, seed):
     so = torch.empty((n, N), dtype=torch.int8, device=dev)
     acc = torch.zeros((n_chains, 2), dtype=torch.int64, device=dev)
     ctx.vp_sample(0, n_burn, n_meas, lp, sg, el, dl, so, acc)
+    mc = torch.zeros((n_chains, 4), dtype=torch.int64, device=dev)
+    ctx.vp_move_counts(0, mc)
     ctx.vp_sync()
-    out = dict(log_abs_psi=lp.cpu().numpy().reshape(n_chains, n_meas), sign=sg.cpu().numpy().reshape(n_chains, n_meas),
+    out = dict(moves=mc.cpu().numpy(), log_abs_psi=lp.cpu().numpy().reshape(n_chains, n_meas), sign=sg.cpu().numpy().reshape(n_chains, n_meas),
                e_loc=el.cpu().numpy().reshape(n_chains, n_meas), dlnpsi=dl.double().cpu().numpy().reshape(n_chains, n_meas, -1),
                spins=so.cpu().numpy().reshape(n_chains, n_meas, N), accept=acc.cpu().numpy())
     ctx.close()
@@ -117,6 +119,7 @@ def test_column_sampler_fp64_matches_oracle(Ly, Lx, D, Dc, chains, burn, meas):
         o = cols.run_chain(T, lat, ch, burn, meas)
         assert np.array_equal(g["spins"][c], np.stack([x["spins"] for x in o])), c
         assert tuple(g["accept"][c]) == (ch.accepted, ch.proposed)
+        assert tuple(g["moves"][c]) == (ch.accepted, ch.proposed, 0, 0)
         assert np.array_equal(g["sign"][c], np.array([x["sign"] for x in o]))
         assert np.max(np.abs(g["log_abs_psi"][c] - np.array([x["log_abs_psi"] for x in o]))) <= 1e-10
         assert np.max(np.abs(g["e_loc"][c] - np.array([x["e_loc"] for x in o]))) / N <= 1e-10
