@@ -22,9 +22,8 @@ whose 3-line networks run between column boundary MPS.
 Only the nearest-neighbour model (J2 = 0) on the square geometry is covered:
 the diagonal terms need the 2-row networks.
 """
-import numpy as np
-
-from .lattice import Lattice, bonds, local_energy, site_tensor
+from . import lattice as L
+from .lattice import bonds, local_energy
 from . import vmc
 
 COLUMN_KEY = 1 << 16  # Philox key word 1 of the column pass: lattice id + COLUMN_KEY
@@ -38,33 +37,16 @@ def _check(lat):
 def transposed(lat):
     """The Lx x Ly lattice of the transposed PEPS (same D, Dc, couplings and truncation)."""
     _check(lat)
-    return Lattice(lat.Lx, lat.Ly, lat.D, lat.Dc, J1=lat.J1, compress_mode=lat.compress_mode,
-                   fit_sweeps=lat.fit_sweeps)
+    return L.transpose_lattice(lat)
 
 
 def transpose_tensors(T, lat):
-    """T' with T'_(x,y)[s][u][l][d][r] = T_(y,x)[s][l][u][r][d], in the transposed lattice's layout."""
-    lt = transposed(lat)
-    out = np.zeros(lt.Np)
-    for y in range(lat.Ly):
-        for x in range(lat.Lx):
-            for s in (0, 1):
-                t = np.transpose(site_tensor(T, lat, y, x, s), (1, 0, 3, 2))
-                dims = lt.dims(x, y)
-                assert t.shape == dims
-                n = int(np.prod(dims))
-                o = lt.offsets[lt.site(x, y)] + s * n
-                out[o:o + n] = t.ravel()
-    return out
+    _check(lat)
+    return L.transpose_tensors(T, lat)
 
 
-def transpose_spins(spins, lat):
-    """s'(x, y) = s(y, x), in the transposed lattice's site order."""
-    return np.asarray(spins, dtype=np.int8).reshape(lat.Ly, lat.Lx).T.ravel().copy()
-
-
-def untranspose_spins(spins_t, lat):
-    return np.asarray(spins_t, dtype=np.int8).reshape(lat.Lx, lat.Ly).T.ravel().copy()
+transpose_spins = L.transpose_spins
+untranspose_spins = L.untranspose_spins
 
 
 def eval_config(T, lat, spins):

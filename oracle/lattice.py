@@ -15,10 +15,10 @@ Conventions (the paper leaves these open; readings are listed in the design note
   Pinned by reproducing exact-diagonalisation energies printed in Table III.
 * The triangular lattice on the square grid (Sec. III.B, Fig. 7(a)): one
   diagonal of every plaquette, here (y,x)-(y+1,x+1), is a nearest-neighbour
-  bond of coupling J1; the other diagonal is uncoupled.  Its J2 bonds (the
-  other diagonal and the (2,1), (1,2) vectors) are not covered, so J2 must be
-  0 there; on the open 4x4 lattice the choice of diagonal does not change the
-  spectrum (a mirror image).
+  bond of coupling J1.  Its next-nearest neighbours (distance sqrt(3), coupling
+  J2) are the other diagonal (y,x+1)-(y+1,x) and the two knight bonds
+  (y,x)-(y+1,x+2) and (y,x)-(y+2,x+1).  On the open 4x4 lattice the choice of
+  diagonal does not change the spectrum (a mirror image).
 """
 import numpy as np
 
@@ -33,22 +33,23 @@ class Lattice:
         """compress_mode: the boundary truncation, "canonical" (SVD compression)
         or "variational" (the fit of App. B with fit_sweeps sweeps).  geometry:
         "square" (J2 on both diagonals) or "triangular" (J1 on the diagonal
-        (y,x)-(y+1,x+1), J2 = 0)."""
+        (y,x)-(y+1,x+1), J2 on the other diagonal and the knight bonds)."""
         if Ly < 1 or Lx < 1 or D < 1 or Dc < 1:
             raise ValueError("lattice sizes, D and Dc must be >= 1")
         if compress_mode not in ("canonical", "variational") or fit_sweeps < 0:
             raise ValueError("compress_mode is canonical or variational, fit_sweeps >= 0")
         if geometry not in ("square", "triangular"):
             raise ValueError("geometry is square or triangular")
-        if geometry == "triangular" and J2 != 0.0:
-            raise ValueError("triangular lattice: its J2 bonds are not covered, J2 must be 0")
         self.Ly, self.Lx, self.D, self.Dc = int(Ly), int(Lx), int(D), int(Dc)
         self.J1, self.J2 = float(J1), float(J2)
         self.geometry = geometry
         # couplings of the diagonal (y,x)-(y+1,x+1) and anti-diagonal (y,x+1)-(y+1,x) of a plaquette
         self.Jd = self.J1 if geometry == "triangular" else self.J2
-        self.Ja = 0.0 if geometry == "triangular" else self.J2
+        self.Ja = self.J2
         self.diagonals = self.Jd != 0.0 or self.Ja != 0.0
+        # knight bonds (y,x)-(y+1,x+2) and (y,x)-(y+2,x+1) of the triangular lattice
+        self.Jk = self.J2 if geometry == "triangular" else 0.0
+        self.knights = self.Jk != 0.0
         self.compress_mode, self.fit_sweeps = compress_mode, int(fit_sweeps)
         self.N = self.Ly * self.Lx
         self.offsets = []
@@ -96,8 +97,10 @@ def compact_offsets(lat):
 # --------------------------------------------------------------------------
 
 def bonds(lat):
-    """All interacting pairs ((y1,x1), (y2,x2), J): NN horizontal, NN vertical, and
-    when a diagonal is coupled both diagonals of every plaquette (an uncoupled one with J = 0)."""
+    """All interacting pairs ((y1,x1), (y2,x2), J): NN horizontal, NN vertical, when a
+    diagonal is coupled both diagonals of every plaquette (an uncoupled one with J = 0),
+    and on the triangular lattice with J2 != 0 the knight bonds (y,x)-(y+1,x+2), then
+    (y,x)-(y+2,x+1)."""
     out = []
     for y in range(lat.Ly):
         for x in range(lat.Lx - 1):
@@ -110,6 +113,13 @@ def bonds(lat):
             for x in range(lat.Lx - 1):
                 out.append(((y, x), (y + 1, x + 1), lat.Jd))
                 out.append(((y, x + 1), (y + 1, x), lat.Ja))
+    if lat.knights:
+        for y in range(lat.Ly - 1):
+            for x in range(lat.Lx - 2):
+                out.append(((y, x), (y + 1, x + 2), lat.Jk))
+        for y in range(lat.Ly - 2):
+            for x in range(lat.Lx - 1):
+                out.append(((y, x), (y + 2, x + 1), lat.Jk))
     return out
 
 
@@ -180,3 +190,39 @@ def neel_shuffled(lat, seed, lattice_id, chain):
         j = philox.bounded_index(w[0], i + 1)
         s[i], s[j] = s[j], s[i]
     return s
+
+
+# --------------------------------------------------------------------------
+# The transposed lattice: site (y, x) -> (x, y), legs (l, u, r, d) -> (u, l, d, r)
+# --------------------------------------------------------------------------
+
+def transpose_lattice(lat):
+    """The Lx x Ly lattice of the transposed PEPS (same D, Dc, couplings, geometry and truncation;
+    the diagonal (y,x)-(y+1,x+1) maps onto itself)."""
+    return Lattice(lat.Lx, lat.Ly, lat.D, lat.Dc, J1=lat.J1, J2=lat.J2, compress_mode=lat.compress_mode,
+                   fit_sweeps=lat.fit_sweeps, geometry=lat.geometry)
+
+
+def transpose_tensors(T, lat):
+    """T' with T'_(x,y)[s][u][l][d][r] = T_(y,x)[s][l][u][r][d], in the transposed lattice's layout."""
+    lt = transpose_lattice(lat)
+    out = np.zeros(lt.Np)
+    for y in range(lat.Ly):
+        for x in range(lat.Lx):
+            for s in (0, 1):
+                t = np.transpose(site_tensor(T, lat, y, x, s), (1, 0, 3, 2))
+                dims = lt.dims(x, y)
+                assert t.shape == dims
+                n = int(np.prod(dims))
+                o = lt.offsets[lt.site(x, y)] + s * n
+                out[o:o + n] = t.ravel()
+    return out
+
+
+def transpose_spins(spins, lat):
+    """s'(x, y) = s(y, x), in the transposed lattice's site order."""
+    return np.asarray(spins, dtype=np.int8).reshape(lat.Ly, lat.Lx).T.ravel().copy()
+
+
+def untranspose_spins(spins_t, lat):
+    return np.asarray(spins_t, dtype=np.int8).reshape(lat.Lx, lat.Ly).T.ravel().copy()

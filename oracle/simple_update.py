@@ -30,7 +30,8 @@ convergence measure is App. A's: the mean over links of
 ||lambda(t+dt) - lambda(t)|| / ||lambda(t)|| over one step.
 
 Diagonal terms (J2 on both diagonals of every plaquette; on the triangular
-lattice J1 on the diagonal (y,x)-(y+1,x+1) alone) follow Fig. 8: the pair (B_1, B_3) is joined through a corner site B_2 (reading: the
+lattice J1 on the diagonal (y,x)-(y+1,x+1) and J2 on the other; its knight
+bonds are left to the optimisation that follows) follow Fig. 8: the pair (B_1, B_3) is joined through a corner site B_2 (reading: the
 diagonal (y,x)-(y+1,x+1) through (y,x+1), the anti-diagonal (y,x+1)-(y+1,x)
 through (y,x)); B_1 and B_3 with their outer lambdas are QR-reduced to R_1
 and R_3; the gate acts on the physical legs of B_1 and B_3 of

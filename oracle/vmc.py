@@ -26,7 +26,8 @@ import math
 import numpy as np
 
 from . import philox
-from .lattice import bonds, bond_elements, compact_offsets, compact_size, site_tensor
+from .lattice import (bonds, bond_elements, compact_offsets, compact_size, site_tensor, transpose_lattice,
+                      transpose_spins, transpose_tensors)
 from .peps import (ZeroAmplitude, absorb_down, compress, compress_boundary, defect3, env3_left, env4_left,
                    lower_boundary, row3_envs, row4_envs, row_tensors, trivial_mps,
                    upper_boundaries, row3_value)
@@ -96,8 +97,12 @@ def _measure(T, lat, spins, U, collect_ratios=True):
                             Lm = env4_left(L4[x], U[y][x], f1[x], f2[x], D2[x])
                             Lm = env4_left(Lm, U[y][x + 1], f1[x + 1], f2[x + 1], D2[x + 1])
                             ratio[(p, q)] = _dot(Lm, R4[x + 2]) / N4
+            if lat.knights:
+                ratio.update(_knight_ratios(T, lat, spins, y, U[y], row, row2, D2, L4, R4, N4))
         if y >= 1:
             Dl[y], _ = lower_boundary(Dn, T, lat, spins, y)
+    if lat.knights and lat.Ly > 2:
+        ratio.update(_long_knight_ratios(T, lat, spins))
     e_loc = 0.0
     ratio_vec = np.zeros(len(bonds(lat)))
     for i, (p, q, J) in enumerate(bonds(lat)):
@@ -107,6 +112,44 @@ def _measure(T, lat, spins, U, collect_ratios=True):
             e_loc += off * ratio[(p, q)]
             ratio_vec[i] = ratio[(p, q)]
     return e_loc, G, ratio_vec, Dl
+
+
+def _knight_ratios(T, lat, spins, y, Uy, row, row2, D2, L4, R4, N4):
+    """Ratios of the knight bonds (y,x)-(y+1,x+2) of row pair y: the 2-row network
+    with site (y,x) flipped in column x, column x+1 unchanged and site (y+1,x+2)
+    flipped in column x+2, divided by the same network with the current tensors."""
+    s = np.asarray(spins).reshape(lat.Ly, lat.Lx)
+    out = {}
+    for x in range(lat.Lx - 2):
+        p, q = (y, x), (y + 1, x + 2)
+        if s[p] != s[q]:
+            f1 = row_tensors(T, lat, spins, y, flips=(p,))
+            f2 = row_tensors(T, lat, spins, y + 1, flips=(q,))
+            Lm = L4[x]
+            for c in (x, x + 1, x + 2):
+                Lm = env4_left(Lm, Uy[c], f1[c], f2[c], D2[c])
+            out[(p, q)] = _dot(Lm, R4[x + 3]) / N4
+    return out
+
+
+def _long_knight_ratios(T, lat, spins):
+    """Ratios of the knight bonds (y,x)-(y+2,x+1), which span three rows: each is the
+    knight bond (x,y)-(x+1,y+2) of the transposed lattice (the same state), taken
+    there by ``_knight_ratios`` with that lattice's boundaries for its configuration."""
+    lt, Tt, st = transpose_lattice(lat), transpose_tensors(T, lat), transpose_spins(spins, lat)
+    U, _ = upper_boundaries(Tt, lt, st)
+    Dl = _lower_boundaries(Tt, lt, st)
+    out = {}
+    for yt in range(lt.Ly - 1):
+        r1, r2, D2 = row_tensors(Tt, lt, st, yt), row_tensors(Tt, lt, st, yt + 1), Dl[yt + 2]
+        L4, R4 = row4_envs(U[yt], r1, r2, D2)
+        N4 = _dot(L4[1], R4[1])
+        if N4 == 0.0:
+            raise ZeroAmplitude("row-pair network value is zero")
+        for (p, q), rho in _knight_ratios(Tt, lt, st, yt, U[yt], r1, r2, D2, L4, R4, N4).items():
+            # (x, y)-(x+1, y+2) of the transposed lattice is (y, x)-(y+2, x+1)
+            out[((p[1], p[0]), (q[1], q[0]))] = rho
+    return out
 
 
 def plaquette_ratios(T, lat, spins):

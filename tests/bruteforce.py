@@ -63,9 +63,8 @@ def sz0_configs(N):
 
 def bonds(Ly, Lx, J1, J2, triangular=False):
     """Bond list in the same order as the method's: horizontal, vertical, two diagonals per plaquette.
-    triangular: J1 on the diagonal (y,x)-(y+1,x+1) and the anti-diagonal uncoupled (J2 must be 0)."""
-    if triangular:
-        assert J2 == 0.0
+    triangular: J1 on the diagonal (y,x)-(y+1,x+1), J2 on the anti-diagonal, then (J2 != 0) the knight
+    bonds (y,x)-(y+1,x+2) and (y,x)-(y+2,x+1)."""
     out = []
     for y in range(Ly):
         for x in range(Lx - 1):
@@ -77,7 +76,14 @@ def bonds(Ly, Lx, J1, J2, triangular=False):
         for y in range(Ly - 1):
             for x in range(Lx - 1):
                 out.append((y * Lx + x, (y + 1) * Lx + x + 1, J1 if triangular else J2))
-                out.append((y * Lx + x + 1, (y + 1) * Lx + x, 0.0 if triangular else J2))
+                out.append((y * Lx + x + 1, (y + 1) * Lx + x, J2))
+    if triangular and J2 != 0.0:
+        for y in range(Ly - 1):
+            for x in range(Lx - 2):
+                out.append((y * Lx + x, (y + 1) * Lx + x + 2, J2))
+        for y in range(Ly - 2):
+            for x in range(Lx - 1):
+                out.append((y * Lx + x, (y + 2) * Lx + x + 1, J2))
     return out
 
 
@@ -98,6 +104,26 @@ def local_energies(T, Ly, Lx, D, J1, J2, configs, triangular=False):
             pf = amplitudes(T, Ly, Lx, D, flipped[anti])
             e[anti] += 0.5 * J * pf / psi[anti]
     return e, psi
+
+
+def sector_energy_bonds(psi, configs, N, bond_list):
+    """<psi|H|psi> / <psi|psi> over the S^z = 0 amplitudes psi (rows of ``configs``) for
+    H = sum over (i, j, J) of J S_i.S_j (the configurations' exchanged partners found by bit code)."""
+    configs = np.asarray(configs)
+    codes = (configs.astype(np.int64) << np.arange(N, dtype=np.int64)[::-1]).sum(axis=1)
+    order = np.argsort(codes)
+    sorted_codes = codes[order]
+    num = 0.0
+    for k, k2, J in bond_list:
+        if J == 0.0:
+            continue
+        par = configs[:, k] == configs[:, k2]
+        num += J * np.sum(np.where(par, 0.25, -0.25) * psi * psi)
+        anti = ~par
+        partner = codes[anti] ^ ((1 << (N - 1 - k)) | (1 << (N - 1 - k2)))
+        j = order[np.searchsorted(sorted_codes, partner)]
+        num += 0.5 * J * np.sum(psi[anti] * psi[j])
+    return float(num / (psi @ psi))
 
 
 def sector_energy(psi, configs, Ly, Lx, J1=1.0, triangular=False):

@@ -94,9 +94,30 @@ def test_eval_exact_eloc_ratios_triangular(shape):
                 assert out['ratios'][b] == 0.0
 
 
-def test_triangular_needs_zero_j2():
-    with pytest.raises(ValueError):
-        Lattice(4, 4, 2, 4, J2=0.1, geometry="triangular")
+@pytest.mark.parametrize("shape", [(4, 4), (3, 4), (4, 3)])
+def test_eval_exact_triangular_j2(shape):
+    """The triangular lattice with J2 (the other diagonal and the knight bonds; the
+    three-row ones through the transposed lattice): E_loc and every ratio against
+    brute force in the exact regime."""
+    Ly, Lx = shape
+    J2 = 0.3
+    lat = Lattice(Ly, Lx, 2, 16, J2=J2, geometry="triangular")
+    T = _rand_T(lat, 9)
+    cf = _configs(lat, 10, 8)
+    e_ref, psi = bf.local_energies(T, Ly, Lx, 2, 1.0, J2, cf, triangular=True)
+    bl = bf.bonds(Ly, Lx, 1.0, J2, triangular=True)
+    assert [(p[0] * Lx + p[1], q[0] * Lx + q[1], J) for p, q, J in bonds(lat)] == bl
+    for c, er, pr in zip(cf, e_ref, psi):
+        out = vmc.eval_config(T, lat, c)
+        assert abs(out['e_loc'] - er) < 1e-10 * max(1.0, abs(er))
+        for b, (i, j, J) in enumerate(bl):
+            if c[i] != c[j] and J != 0.0:
+                f = c.copy()
+                f[i], f[j] = c[j], c[i]
+                rho = bf.amplitudes(T, Ly, Lx, 2, f[None])[0] / pr
+                assert abs(out['ratios'][b] - rho) < 1e-9 * max(1.0, abs(rho))
+            else:
+                assert out['ratios'][b] == 0.0
 
 
 def test_dlnpsi_exact_linearity():

@@ -137,3 +137,15 @@ def test_parameter_count_sec2b():
     assert Lattice(4, 4, 2, 4).Np == 288
     assert Lattice(8, 8, 4, 8).Np == 21632
     assert Lattice(16, 16, 8, 16).Np == 1663488
+
+
+@pytest.mark.parametrize("j2", [0.02, 0.14])
+def test_table3_triangular_j2_from_the_oracle_lattice(j2):
+    """With J2 the oracle's triangular bond set (the other diagonal and the knight
+    bonds (y,x)-(y+1,x+2), (y,x)-(y+2,x+1)) gives Table III's energies."""
+    lat = Lattice(4, 4, 1, 1, J2=j2, geometry="triangular")
+    bl = [(lat.site(*p), lat.site(*q), J) for p, q, J in bonds(lat) if J != 0.0]
+    assert sorted((min(i, j), max(i, j), J) for i, j, J in bl) == \
+        sorted((min(i, j), max(i, j), J) for i, j, J in _triangular_bonds(4, j2))
+    e_paper = [e for jj, e in _golden() if jj == j2][0]
+    assert abs(_ground_energy(16, bl) / 16 - e_paper) < 6e-8
