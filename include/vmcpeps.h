@@ -25,13 +25,21 @@
  *   H = J1 sum_NN S_i.S_j + J2 sum_diag S_i.S_j, S = sigma/2.
  *   VP_GEOM_TRIANGULAR (Sec. III.B, Fig. 7(a): the triangular lattice drawn
  *   on the square grid): the diagonal (y,x)-(y+1,x+1) of every plaquette is a
- *   nearest-neighbour bond (coupling J1) and the other diagonal is uncoupled;
- *   the triangular J2 bonds (the other diagonal and the (2,1), (1,2) vectors)
- *   are not built, so J2 must be 0 there.
+ *   nearest-neighbour bond (coupling J1); the next-nearest neighbours
+ *   (coupling J2) are the other diagonal (y,x+1)-(y+1,x) and the knight bonds
+ *   (y,x)-(y+1,x+2) (a 2-row network over three columns) and (y,x)-(y+2,x+1)
+ *   (the same bond of the transposed lattice, site (y,x) -> (x,y): the
+ *   context keeps that lattice beside the caller's, counted by
+ *   vp_workspace_bytes, and evaluates it for every measured configuration).
+ *   With J2 != 0 the triangular lattice is measured with the per-phase
+ *   schedule and the pair or learned samplers (VP_ERR_UNSUPPORTED otherwise),
+ *   and the simple update evolves its diagonals but not its knight bonds.
  * Pair order (the "ratios" outputs): horizontal bonds row by row, then
  *   vertical bonds row by row, then for every plaquette (y, x) the two
  *   diagonals (y,x)-(y+1,x+1) and (y,x+1)-(y+1,x) when a diagonal is coupled
- *   (J2 != 0, or the triangular geometry); an uncoupled diagonal's ratio is 0.
+ *   (J2 != 0, or the triangular geometry), then (triangular, J2 != 0) the
+ *   bonds (y,x)-(y+1,x+2) for y < Ly-1, x < Lx-2 and (y,x)-(y+2,x+1) for
+ *   y < Ly-2, x < Lx-1, row-major; an uncoupled bond's ratio is 0.
  * Contraction (App. B, App. C): boundary MPS truncated to Dc by the canonical
  *   SVD compression (left-to-right orthogonalisation, right-to-left truncation
  *   keeping the Dc largest singular values); 3-line row networks for
@@ -267,7 +275,8 @@ vp_status vp_trace_ratios(vp_ctx* ctx, int32_t lat, double* trace_dev);
  * the same outputs as one measured sweep without Metropolis moves, plus every
  * pair ratio (ratios_dev [n_cfg][n_pairs], 0 for parallel pairs; may be NULL).
  * n_pairs = Ly(Lx-1) + (Ly-1)Lx (+ 2(Ly-1)(Lx-1) when a diagonal is coupled:
- * J2 != 0 or VP_GEOM_TRIANGULAR). */
+ * J2 != 0 or VP_GEOM_TRIANGULAR; + (Ly-1)(Lx-2) + (Ly-2)(Lx-1) for the knight
+ * bonds of VP_GEOM_TRIANGULAR with J2 != 0). */
 vp_status vp_eval(vp_ctx* ctx, int32_t lat, const int8_t* spins_dev, int32_t n_cfg,
                   double* log_abs_psi_dev, int8_t* sign_dev, double* e_loc_dev,
                   void* dlnpsi_dev, double* ratios_dev);

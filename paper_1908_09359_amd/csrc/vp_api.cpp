@@ -19,6 +19,12 @@ using namespace vp;
 
 namespace {
 
+// A transposed lattice kept beside a caller's lattice (site (y,x) -> (x,y), the
+// same state): TWIN_COLUMNS carries the vertical bonds of VP_VERT_COLUMN as its
+// horizontal ones; TWIN_KNIGHTS evaluates the triangular lattice's knight bonds
+// (y,x)-(y+2,x+1) as its own (x,y)-(x+1,y+2) ones.
+enum { TWIN_NONE = 0, TWIN_COLUMNS = 1, TWIN_KNIGHTS = 2 };
+
 struct Lattice {
   vp_lattice p{};
   int N = 0;
@@ -72,7 +78,8 @@ struct Lattice {
   bool tensors_ready = false;
   bool chains_ready = false;
   bool lower_valid = false;     // D boundaries match the current spins
-  int col = -1;                 // VP_VERT_COLUMN: index of the transposed lattice in vp_ctx::lats, else -1
+  int col = -1;                 // index of the transposed lattice in vp_ctx::lats, else -1
+  int role = 0;                 // what that lattice does: TWIN_COLUMNS or TWIN_KNIGHTS
 };
 
 }  // namespace
@@ -265,8 +272,6 @@ vp_status check_lattice(vp_ctx* ctx, const vp_lattice& p) {
   if (p.fit_sweeps < 0 || p.fit_sweeps > 64) return fail(ctx, VP_ERR_ARG, "fit_sweeps must be 0..64");
   if (p.geometry != VP_GEOM_SQUARE && p.geometry != VP_GEOM_TRIANGULAR)
     return fail(ctx, VP_ERR_ARG, "unknown geometry %d", p.geometry);
-  if (p.geometry == VP_GEOM_TRIANGULAR && p.J2 != 0.0)
-    return fail(ctx, VP_ERR_UNSUPPORTED, "triangular lattice: its J2 bonds are not built, J2 must be 0");
   if (p.vertical != VP_VERT_ROWPAIR && p.vertical != VP_VERT_COLUMN)
     return fail(ctx, VP_ERR_ARG, "unknown vertical-bond mode %d", p.vertical);
   if (p.vertical == VP_VERT_COLUMN && (p.J2 != 0.0 || p.geometry != VP_GEOM_SQUARE))
@@ -285,8 +290,17 @@ vp_lattice transposed_params(const vp_lattice& p) {
 
 // Couplings of the diagonal (y,x)-(y+1,x+1) and the anti-diagonal (y,x+1)-(y+1,x).
 double diag_coupling(const vp_lattice& p) { return p.geometry == VP_GEOM_TRIANGULAR ? p.J1 : p.J2; }
-double anti_coupling(const vp_lattice& p) { return p.geometry == VP_GEOM_TRIANGULAR ? 0.0 : p.J2; }
+double anti_coupling(const vp_lattice& p) { return p.J2; }
 bool has_diagonals(const vp_lattice& p) { return diag_coupling(p) != 0.0 || anti_coupling(p) != 0.0; }
+// The triangular lattice's knight bonds (y,x)-(y+1,x+2) and (y,x)-(y+2,x+1), coupling J2.
+bool has_knights(const vp_lattice& p) { return p.geometry == VP_GEOM_TRIANGULAR && p.J2 != 0.0; }
+// Pairs of the ratio outputs: horizontal, vertical, two diagonals per plaquette, knight bonds.
+int n_pairs_of(const vp_lattice& p) {
+  int n = p.Ly * (p.Lx - 1) + (p.Ly - 1) * p.Lx;
+  if (has_diagonals(p)) n += 2 * (p.Ly - 1) * (p.Lx - 1);
+  if (has_knights(p)) n += (p.Ly - 1) * std::max(p.Lx - 2, 0) + std::max(p.Ly - 2, 0) * (p.Lx - 1);
+  return n;
+}
 
 Lattice* get_lat(vp_ctx* ctx, int32_t lat) {
   if (!ctx || lat < 0 || lat >= ctx->n_user) return nullptr;
@@ -480,13 +494,13 @@ vp_status run_graph(vp_ctx* ctx, Lattice& L, int n_burn, int n_meas, const Sampl
 }
 
 template <typename T>
-void run_eval(const LatDev& D, const SampleOut& o, int n_cfg, hipStream_t s, bool rowpair = true) {
+void run_eval(const LatDev& D, const SampleOut& o, int n_cfg, hipStream_t s, bool rowpair = true, bool rows = true) {
   const int Ly = D.Ly;
   for (int y = 0; y < Ly - 1; ++y) launch_compress<T>(D, y, 1, s);
   launch_psi_fixed<T>(D, s);
   launch_begin_sample(D, s);
   for (int y = Ly - 1; y >= 0; --y) {
-    launch_measure3<T>(D, y, o, s);
+    if (rows) launch_measure3<T>(D, y, o, s);
     if (y < Ly - 1 && rowpair) launch_measure4<T>(D, y, o, s);
     if (y >= 1) launch_compress<T>(D, y, 0, s);
   }
@@ -508,6 +522,37 @@ SampleOut scratch_out(Lattice& L) {
   o.dyn_m = 0;
   o.np_half = L.Np / 2;
   return o;
+}
+
+// TWIN_KNIGHTS: the knight bonds (y,x)-(y+2,x+1) of the n configurations in L's
+// chain slots, evaluated as the transposed lattice's (x,y)-(x+1,y+2) bonds (its
+// 2-row measurement with every other term switched off); their energies are
+// added into row m of e ([n][n_meas]) and, when r is given, their ratios placed
+// in r ([n][np]) after the pairs the 2-row measurement writes.
+template <typename T>
+bool eval_knights(vp_ctx* ctx, Lattice& L, int n, double* e, int n_meas, int m, double* r, int np, hipStream_t s) {
+  Lattice& C = ctx->lats[L.col];
+  const vp_lattice& p = L.p;
+  launch_transpose_spins(L.spins, (int8_t*)C.d_sis, n, p.Ly, p.Lx, true, s);
+  launch_copy_spins(C.dev, (const int8_t*)C.d_sis, n, s);  // clears the transposed chains' flags
+  LatDev Dt = C.dev;
+  Dt.n_chains = n;
+  SampleOut oc = scratch_out(C);
+  // the transposed lattice's ratio layout: its nearest-neighbour pairs, then its knight bonds
+  const int base_t = C.p.Ly * (C.p.Lx - 1) + (C.p.Ly - 1) * C.p.Lx;
+  const int npt = base_t + (C.p.Ly - 1) * std::max(C.p.Lx - 2, 0);
+  oc.n_pairs = npt;
+  if (r) {
+    if (!grow(s, C.col_ratios, sizeof(double) * (size_t)n * npt)) return false;
+    oc.ratios = (double*)C.col_ratios.p;
+  }
+  run_eval<T>(Dt, oc, n, s, true, false);
+  launch_add_energy(e, n_meas, m, oc.e_loc, n, s);
+  if (r) {
+    const int base_r = np - std::max(p.Ly - 2, 0) * (p.Lx - 1);
+    launch_knight_ratios(oc.ratios, npt, base_t, r, np, base_r, n, p.Ly, p.Lx, s);
+  }
+  return true;
 }
 
 // VP_VERT_COLUMN sampling: every sweep visits the horizontal bonds with the row
@@ -635,7 +680,7 @@ vp_status run_pair_sample(vp_ctx* ctx, Lattice& L, int n_burn, int n_meas, doubl
 vp_status check_flags(vp_ctx* ctx, Lattice& L) {
   std::vector<ChainMeta> m(L.p.n_chains), mc;
   HIP_TRY(ctx, hipMemcpyAsync(m.data(), L.meta, sizeof(ChainMeta) * m.size(), hipMemcpyDeviceToHost, ctx->stream));
-  if (L.col >= 0) {  // the transposed lattice's chains of VP_VERT_COLUMN
+  if (L.col >= 0) {  // the transposed lattice's chains
     mc.resize(m.size());
     HIP_TRY(ctx, hipMemcpyAsync(mc.data(), ctx->lats[L.col].meta, sizeof(ChainMeta) * mc.size(),
                                 hipMemcpyDeviceToHost, ctx->stream));
@@ -690,8 +735,8 @@ vp_status eval_configs(vp_ctx* ctx, Lattice* L, const int8_t* spins_dev, int32_t
   o.n_meas = n_meas;
   o.m = row;
   o.np_half = L->Np / 2;
-  o.n_pairs = p.Ly * (p.Lx - 1) + (p.Ly - 1) * p.Lx + (has_diagonals(p) ? 2 * (p.Ly - 1) * (p.Lx - 1) : 0);
-  const bool cols = L->col >= 0;
+  o.n_pairs = n_pairs_of(p);
+  const bool cols = L->role == TWIN_COLUMNS;
   if (works_f64(p.prec)) run_eval<double>(D, o, n_cfg, s, !cols); else run_eval<float>(D, o, n_cfg, s, !cols);
   HIP_TRY(ctx, hipGetLastError());
   L->chains_ready = false;
@@ -719,6 +764,14 @@ vp_status eval_configs(vp_ctx* ctx, Lattice* L, const int8_t* spins_dev, int32_t
     HIP_TRY(ctx, hipGetLastError());
     mc.resize(n_cfg);
     HIP_TRY(ctx, hipMemcpyAsync(mc.data(), C.meta, sizeof(ChainMeta) * n_cfg, hipMemcpyDeviceToHost, s));
+  } else if (L->role == TWIN_KNIGHTS) {
+    const bool ok = works_f64(p.prec) ? eval_knights<double>(ctx, *L, n_cfg, o.e_loc, n_meas, row, o.ratios, o.n_pairs, s)
+                                      : eval_knights<float>(ctx, *L, n_cfg, o.e_loc, n_meas, row, o.ratios, o.n_pairs, s);
+    if (!ok) return fail(ctx, VP_ERR_OOM, "knight-bond ratio workspace");
+    HIP_TRY(ctx, hipGetLastError());
+    mc.resize(n_cfg);
+    HIP_TRY(ctx, hipMemcpyAsync(mc.data(), ctx->lats[L->col].meta, sizeof(ChainMeta) * n_cfg, hipMemcpyDeviceToHost,
+                                s));
   }
   HIP_TRY(ctx, hipMemcpyAsync(m.data(), L->meta, sizeof(ChainMeta) * n_cfg, hipMemcpyDeviceToHost, s));
   HIP_TRY(ctx, hipStreamSynchronize(s));
@@ -776,7 +829,7 @@ int64_t vp_workspace_bytes(const vp_lattice* p) {
   Plan P = plan_workspace(*p, nullptr);
   int64_t b = (int64_t)p->n_chains * (P.ws * (int64_t)type_size(p->prec) + P.cws * 8 + P.iws * 4 + P.dws * 8 +
                                       p->Ly * p->Lx + (int64_t)sizeof(ChainMeta));
-  if (p->vertical == VP_VERT_COLUMN) {  // the transposed lattice's chains
+  if (p->vertical == VP_VERT_COLUMN || has_knights(*p)) {  // the transposed lattice's chains
     const vp_lattice t = transposed_params(*p);
     Plan Q = plan_workspace(t, nullptr);
     b += (int64_t)t.n_chains * (Q.ws * (int64_t)type_size(t.prec) + Q.cws * 8 + Q.iws * 4 + Q.dws * 8 +
@@ -811,17 +864,23 @@ vp_status vp_create(const vp_lattice* lats, int32_t n_lats, uint64_t seed, void*
   // the caller's lattices, then the transposed lattice of each VP_VERT_COLUMN
   // one (Philox key word 1: its lattice index + 65536)
   std::vector<vp_lattice> all(lats, lats + n_lats);
-  std::vector<int> key(n_lats);
+  std::vector<int> key(n_lats), twin_role(n_lats, TWIN_NONE);
   for (int i = 0; i < n_lats; ++i) key[i] = i;
-  for (int i = 0; i < n_lats; ++i)
-    if (lats[i].vertical == VP_VERT_COLUMN) {
-      all.push_back(transposed_params(lats[i]));
-      key.push_back(i + 65536);
-    }
   ctx->n_user = n_lats;
+  std::vector<std::pair<int, int>> twins;  // (lattice, role)
+  for (int i = 0; i < n_lats; ++i) {
+    const int role = lats[i].vertical == VP_VERT_COLUMN ? TWIN_COLUMNS : (has_knights(lats[i]) ? TWIN_KNIGHTS : 0);
+    if (role == TWIN_NONE) continue;
+    twins.push_back({i, role});
+    all.push_back(transposed_params(lats[i]));
+    key.push_back(i + 65536);
+    twin_role.push_back(role);
+  }
   ctx->lats.resize(all.size());
-  for (int i = 0, t = n_lats; i < n_lats; ++i)
-    if (lats[i].vertical == VP_VERT_COLUMN) ctx->lats[i].col = t++;
+  for (size_t t = 0; t < twins.size(); ++t) {
+    ctx->lats[twins[t].first].col = n_lats + (int)t;
+    ctx->lats[twins[t].first].role = twins[t].second;
+  }
   for (int i = 0; i < (int)all.size(); ++i) {
     Lattice& L = ctx->lats[i];
     L.p = all[i];
@@ -877,6 +936,10 @@ vp_status vp_create(const vp_lattice* lats, int32_t n_lats, uint64_t seed, void*
     LatDev& D = L.dev;
     D.Ly = p.Ly; D.Lx = p.Lx; D.d = p.D; D.c = p.Dc; D.N = L.N;
     D.J1 = p.J1; D.Jd = diag_coupling(p); D.Ja = anti_coupling(p); D.n_chains = p.n_chains;
+    D.Jk = has_knights(p) ? p.J2 : 0.0;
+    if (twin_role[i] == TWIN_KNIGHTS) {  // evaluates the knight bonds (y,x)-(y+1,x+2) alone
+      D.J1 = 0.0; D.Jd = 0.0; D.Ja = 0.0;
+    }
     D.seed = seed; D.lat_id = key[i];
     D.cmode = p.compress; D.fit_sweeps = p.fit_sweeps;
     D.Tw = L.Tw; D.ws = L.ws; D.ws_stride = P.ws;
@@ -934,7 +997,7 @@ static vp_status stage_tensors(vp_ctx* ctx, Lattice& L) {
   L.tensors_ready = true;
   L.lower_valid = false;
   L.su_valid = false;
-  if (L.col >= 0) {  // VP_VERT_COLUMN: the transposed lattice carries the same state
+  if (L.col >= 0) {  // the transposed lattice carries the same state
     Lattice& C = ctx->lats[L.col];
     launch_transpose_tensors(L.T, C.T, L.d_offs, C.d_offs, L.d_dims, L.p.Ly, L.p.Lx, ctx->stream);
     HIP_TRY(ctx, hipGetLastError());
@@ -1094,7 +1157,9 @@ vp_status vp_sample(vp_ctx* ctx, int32_t lat, int32_t n_burn, int32_t n_meas, do
                                     hipMemcpyDeviceToDevice, s));
     return VP_OK;
   }
-  if (L->col >= 0) {
+  if (L->role == TWIN_KNIGHTS && L->schedule != VP_SCHED_PHASES)
+    return fail(ctx, VP_ERR_UNSUPPORTED, "the triangular knight bonds are measured with the per-phase schedule only");
+  if (L->role == TWIN_COLUMNS) {
     if (L->schedule != VP_SCHED_PHASES)
       return fail(ctx, VP_ERR_UNSUPPORTED, "column-wise vertical bonds run the per-phase schedule only");
     Lattice& C = ctx->lats[L->col];
@@ -1150,6 +1215,11 @@ vp_status vp_sample(vp_ctx* ctx, int32_t lat, int32_t n_burn, int32_t n_meas, do
     for (int i = 0; i < n_burn + n_meas; ++i) {
       const SampleOut* op = i >= n_burn ? &o : nullptr;
       if (f64) run_sweep<double>(ctx, *L, op, s); else run_sweep<float>(ctx, *L, op, s);
+      if (op && L->role == TWIN_KNIGHTS) {  // the knight bonds (y,x)-(y+2,x+1) of the final configurations
+        const bool ok = f64 ? eval_knights<double>(ctx, *L, L->p.n_chains, e_loc_dev, n_meas, i - n_burn, nullptr, 0, s)
+                            : eval_knights<float>(ctx, *L, L->p.n_chains, e_loc_dev, n_meas, i - n_burn, nullptr, 0, s);
+        if (!ok) return fail(ctx, VP_ERR_OOM, "knight-bond workspace");
+      }
       HIP_TRY(ctx, hipGetLastError());
     }
   }
@@ -1197,7 +1267,8 @@ vp_status vp_sample_batch(vp_ctx* ctx, int32_t n_lats, const int32_t* lats_host,
     if (L->sampler == VP_SAMPLER_SIS_PAIR)
       return fail(ctx, VP_ERR_UNSUPPORTED, "lattice %d: the |Phi|^2 sampler runs through vp_sample only", lats_host[i]);
     if (L->col >= 0)
-      return fail(ctx, VP_ERR_UNSUPPORTED, "lattice %d: column-wise vertical bonds run through vp_sample only",
+      return fail(ctx, VP_ERR_UNSUPPORTED,
+                  "lattice %d: column-wise vertical bonds and the triangular knight bonds run through vp_sample only",
                   lats_host[i]);
     if (!ls.empty() && (L->p.D != ls[0]->p.D || L->p.Dc != ls[0]->p.Dc || L->p.prec != ls[0]->p.prec))
       return fail(ctx, VP_ERR_SHAPE, "one batch needs equal D, Dc and precision");
@@ -1318,7 +1389,7 @@ vp_status vp_autotune_tiles(vp_ctx* ctx, int32_t lat, int32_t sweeps, double* ms
 vp_status vp_trace_ratios(vp_ctx* ctx, int32_t lat, double* trace_dev) {
   Lattice* L = get_lat(ctx, lat);
   if (!L) return fail(ctx, VP_ERR_ARG, "bad lattice index");
-  if (L->col >= 0) return fail(ctx, VP_ERR_UNSUPPORTED, "no ratio trace with column-wise vertical bonds");
+  if (L->role == TWIN_COLUMNS) return fail(ctx, VP_ERR_UNSUPPORTED, "no ratio trace with column-wise vertical bonds");
   L->dev.trace = trace_dev;
   return VP_OK;
 }
@@ -1389,7 +1460,8 @@ vp_status vp_sample_split(vp_ctx* ctx, int32_t lat_sample, int32_t lat_measure, 
   if (A->sampler == VP_SAMPLER_SIS_PAIR)
     return fail(ctx, VP_ERR_UNSUPPORTED, "the |Phi|^2 sampler runs through vp_sample only");
   if (A->col >= 0 || M->col >= 0)
-    return fail(ctx, VP_ERR_UNSUPPORTED, "column-wise vertical bonds run through vp_sample and vp_eval only");
+    return fail(ctx, VP_ERR_UNSUPPORTED,
+                "column-wise vertical bonds and the triangular knight bonds run through vp_sample and vp_eval only");
   if (n_meas > 0 && (!log_abs_psi_dev || !sign_dev || !e_loc_dev))
     return fail(ctx, VP_ERR_ARG, "log_abs_psi, sign and e_loc outputs are required");
   hipStream_t s = ctx->stream;
@@ -1460,8 +1532,10 @@ vp_status vp_set_sampler(vp_ctx* ctx, int32_t lat, int32_t sampler) {
     return fail(ctx, VP_ERR_ARG, "unknown sampler %d", sampler);
   if (sampler == VP_SAMPLER_SIS_PAIR && L->p.n_chains % 2)
     return fail(ctx, VP_ERR_SHAPE, "the |Phi|^2 sampler pairs the chains: n_chains must be even");
-  if (sampler != VP_SAMPLER_PAIR_SEQ && L->col >= 0)
+  if (sampler != VP_SAMPLER_PAIR_SEQ && L->role == TWIN_COLUMNS)
     return fail(ctx, VP_ERR_UNSUPPORTED, "column-wise vertical bonds run the pair sampler only");
+  if (sampler == VP_SAMPLER_SIS_PAIR && L->role == TWIN_KNIGHTS)
+    return fail(ctx, VP_ERR_UNSUPPORTED, "the |Phi|^2 chains do not measure the triangular knight bonds");
   if (sampler == VP_SAMPLER_LEARNED_PLAQ && !L->net_ready)
     return fail(ctx, VP_ERR_ARG, "the learned sampler needs proposal weights (vp_proposal_set_weights)");
   if (sampler == VP_SAMPLER_LEARNED_PLAQ && (L->p.Ly < 2 || L->p.Lx < 2))
@@ -1480,7 +1554,7 @@ vp_status vp_move_counts(vp_ctx* ctx, int32_t lat, int64_t* counts_dev) {
   HIP_TRY(ctx, hipMemcpy2DAsync(counts_dev + 2, 4 * sizeof(int64_t),
                                 (const char*)L->meta + offsetof(ChainMeta, p_accepted), sizeof(ChainMeta),
                                 2 * sizeof(int64_t), n, hipMemcpyDeviceToDevice, s));
-  if (L->col >= 0) launch_add_counts(ctx->lats[L->col].meta, counts_dev, 4, n, s);  // the vertical moves
+  if (L->role == TWIN_COLUMNS) launch_add_counts(ctx->lats[L->col].meta, counts_dev, 4, n, s);  // the vertical moves
   HIP_TRY(ctx, hipGetLastError());
   return VP_OK;
 }

@@ -75,6 +75,21 @@ __global__ void __launch_bounds__(CW) k_column_ratios(const double* __restrict__
   }
 }
 
+// Knight bonds (y,x)-(y+2,x+1), y < Ly-2, x < Lx-1, of the row lattice's pair
+// order (from base_r, row-major) from the transposed lattice's (x,y)-(x+1,y+2)
+// bonds (from base_t, index x (Ly-2) + y).
+__global__ void __launch_bounds__(CW) k_knight_ratios(const double* __restrict__ rt, int npt, int base_t,
+                                                      double* __restrict__ r, int np, int base_r, int n, int Ly,
+                                                      int Lx) {
+  const int nk = (Ly - 2) * (Lx - 1);
+  const int64_t total = (int64_t)n * nk;
+  for (int64_t i = blockIdx.x * (int64_t)CW + threadIdx.x; i < total; i += (int64_t)gridDim.x * CW) {
+    const int64_t c = i / nk;
+    const int v = (int)(i - c * nk), y = v / (Lx - 1), x = v - y * (Lx - 1);
+    r[c * np + base_r + v] = rt[c * npt + base_t + x * (Ly - 2) + y];
+  }
+}
+
 __global__ void __launch_bounds__(CW) k_add_energy(double* __restrict__ e, int n_meas, int m,
                                                    const double* __restrict__ et, int n) {
   const int c = blockIdx.x * CW + threadIdx.x;
@@ -113,6 +128,12 @@ void launch_transpose_spins(const int8_t* src, int8_t* dst, int n_chains, int Ly
 void launch_column_ratios(const double* rt, int npt, double* r, int np, int n, int Ly, int Lx, hipStream_t s) {
   if (n <= 0 || Ly < 2) return;
   k_column_ratios<<<grid_of((int64_t)n * (Ly - 1) * Lx), CW, 0, s>>>(rt, npt, r, np, n, Ly, Lx);
+}
+
+void launch_knight_ratios(const double* rt, int npt, int base_t, double* r, int np, int base_r, int n, int Ly, int Lx,
+                          hipStream_t s) {
+  if (n <= 0 || Ly < 3 || Lx < 2) return;
+  k_knight_ratios<<<grid_of((int64_t)n * (Ly - 2) * (Lx - 1)), CW, 0, s>>>(rt, npt, base_t, r, np, base_r, n, Ly, Lx);
 }
 
 void launch_add_energy(double* e, int n_meas, int m, const double* et, int n, hipStream_t s) {

@@ -1089,7 +1089,9 @@ __device__ __forceinline__ void ph_measure4(const LatDev& L, int ch, int y, cons
   for (int x = 0; x < Lx; ++x) {
     const int k1 = y * Lx + x, k2 = (y + 1) * Lx + x;
     double rho = 0.0;
-    if (C.sp[k1] == C.sp[k2]) {
+    if (L.J1 == 0.0) {
+      // no nearest-neighbour terms (the knight-bond evaluation of a transposed lattice)
+    } else if (C.sp[k1] == C.sp[k2]) {
       eacc += 0.25 * L.J1;
     } else {
       int e1 = eL[x] + step4<T, DD, CC, false, BBX>(L, C, tmp, Le + (int64_t)x * sz, y, x, 1, 1, ub<T>(L, C, y, x), db<T>(L, C, y + 2, x), false, as_lds(lds));
@@ -1126,6 +1128,29 @@ __device__ __forceinline__ void ph_measure4(const LatDev& L, int ch, int y, cons
         if (o.ratios && threadIdx.x == 0)
           o.ratios[(int64_t)ch * o.n_pairs + base_d + 2 * (y * (Lx - 1) + x) + which] = rho;
       }
+    }
+  }
+  if (L.Jk != 0.0) {
+    // knight bonds (y,x)-(y+1,x+2) of the triangular lattice: the 2-row network with
+    // site (y,x) flipped in column x, column x+1 unchanged and (y+1,x+2) flipped in column x+2
+    const int base_k = base_v + (L.Ly - 1) * Lx + ((L.Jd != 0.0 || L.Ja != 0.0) ? 2 * (L.Ly - 1) * (Lx - 1) : 0);
+    for (int x = 0; x + 2 < Lx; ++x) {
+      const int kp = y * Lx + x, kq = (y + 1) * Lx + x + 2;
+      double rho = 0.0;
+      if (C.sp[kp] == C.sp[kq]) {
+        eacc += 0.25 * L.Jk;
+      } else {
+        int e = eL[x] + step4<T, DD, CC, false, BBX>(L, C, tmp, Le + (int64_t)x * sz, y, x, 1, 0, ub<T>(L, C, y, x),
+                                                     db<T>(L, C, y + 2, x), false, as_lds(lds));
+        e += step4<T, DD, CC, false, BBX>(L, C, tmp + sz, tmp, y, x + 1, 0, 0, ub<T>(L, C, y, x + 1),
+                                         db<T>(L, C, y + 2, x + 1), false, as_lds(lds));
+        e += step4<T, DD, CC, false, BBX>(L, C, tmp + 2 * sz, tmp + sz, y, x + 2, 0, 1, ub<T>(L, C, y, x + 2),
+                                         db<T>(L, C, y + 2, x + 2), false, as_lds(lds));
+        const double num = wg_dot<T>(tmp + 2 * sz, R + (int64_t)(x + 3) * sz, sz);
+        rho = ldexp(num / Nm, e + eR[x + 3] - eN);
+        eacc += -0.25 * L.Jk + 0.5 * L.Jk * rho;
+      }
+      if (o.ratios && threadIdx.x == 0) o.ratios[(int64_t)ch * o.n_pairs + base_k + y * (Lx - 2) + x] = rho;
     }
   }
   if (o.plaq) {

@@ -28,6 +28,7 @@ struct LatDev {
   int Ly, Lx, d, c, N;
   double J1;
   double Jd, Ja;  // couplings of the diagonal (y,x)-(y+1,x+1) and the anti-diagonal (y,x+1)-(y+1,x)
+  double Jk;      // coupling of the knight bonds (y,x)-(y+1,x+2) (triangular lattice), 0 otherwise
   int n_chains;
   uint64_t seed;
   int lat_id;
@@ -202,6 +203,10 @@ void launch_transpose_spins(const int8_t* src, int8_t* dst, int n_chains, int Ly
                             hipStream_t s);
 void launch_column_ratios(const double* rt, int npt, double* r, int np, int n, int Ly, int Lx, hipStream_t s);
 void launch_add_energy(double* e, int n_meas, int m, const double* et, int n, hipStream_t s);
+// The triangular lattice's knight bonds (y,x)-(y+2,x+1) (row-major from base_r of r
+// [n][np]) from the transposed lattice's (x,y)-(x+1,y+2) bonds (from base_t of rt [n][npt]).
+void launch_knight_ratios(const double* rt, int npt, int base_t, double* r, int np, int base_r, int n, int Ly, int Lx,
+                          hipStream_t s);
 void launch_add_counts(const ChainMeta* b, int64_t* out, int stride, int n, hipStream_t s);
 
 }  // namespace vp

@@ -8,7 +8,10 @@ from oracle import vmc
 
 def n_pairs(Ly, Lx, J2, geometry=0):
     diag = J2 != 0.0 or geometry == 1
-    return Ly * (Lx - 1) + (Ly - 1) * Lx + (2 * (Ly - 1) * (Lx - 1) if diag else 0)
+    n = Ly * (Lx - 1) + (Ly - 1) * Lx + (2 * (Ly - 1) * (Lx - 1) if diag else 0)
+    if geometry == 1 and J2 != 0.0:
+        n += (Ly - 1) * max(Lx - 2, 0) + max(Ly - 2, 0) * (Lx - 1)
+    return n
 
 
 def gpu_eval(Ly, Lx, D, Dc, J2, prec, T, cfgs, n_chains=None, compress=0, fit_sweeps=0, geometry=0):

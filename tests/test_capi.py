@@ -71,7 +71,6 @@ def test_create_checks_truncation_limits(D, Dc, compress, sweeps, status):
 
 
 @pytest.mark.parametrize("J2,geometry,status", [
-    (0.1, 1, "VP_ERR_UNSUPPORTED"),  # the triangular lattice's J2 bonds are not built
     (0.0, 2, "VP_ERR_ARG"),          # unknown geometry
 ])
 def test_create_checks_the_geometry(J2, geometry, status):
@@ -92,6 +91,14 @@ def test_create_checks_the_vertical_mode(J2, geometry, vertical, status):
         binding.Context(binding.lattice(4, 4, 2, 4, 1.0, J2, binding.VP_FP64, 1, geometry=geometry,
                                         vertical=vertical))
     assert ei.value.status == getattr(binding, status)
+
+
+def test_triangular_j2_workspace_counts_the_transposed_lattice():
+    from paper_1908_09359_amd import binding
+    a = binding.vp_workspace_bytes(binding.lattice(4, 6, 2, 4, 1.0, 0.0, n_chains=8, geometry=1))
+    b = binding.vp_workspace_bytes(binding.lattice(4, 6, 2, 4, 1.0, 0.2, n_chains=8, geometry=1))
+    t = binding.vp_workspace_bytes(binding.lattice(6, 4, 2, 4, 1.0, 0.0, n_chains=8, geometry=1))
+    assert b == a + t
 
 
 def test_column_mode_workspace_counts_the_transposed_lattice():

@@ -2,16 +2,20 @@
 
 The square-lattice PEPS carries the triangular Heisenberg model when one
 diagonal of every plaquette, here (y,x)-(y+1,x+1), is a nearest-neighbour bond
-(VP_GEOM_TRIANGULAR; the J2 = 0 column of Table III).
+(VP_GEOM_TRIANGULAR); the next-nearest neighbours (J2) are the other diagonal
+and the knight bonds (y,x)-(y+1,x+2) and (y,x)-(y+2,x+1), the latter taken on
+the transposed lattice.
 
 * float64 evaluation (Psi, E_loc, every ratio, dlnPsi) against the oracle on the
   same inputs, at the bounds of the square-lattice parity tests (the same
   2-row diagonal networks with one diagonal coupled and the other's ratio slot 0);
 * the simple update with the diagonal's three-site update against the oracle
   (lambdas to 1e-12, amplitudes of the absorbed state to 1e-11 relative);
-* end to end on the 4x4 lattice at D = 4, Dc = 16 (exact contraction): the
-  simple update, then 100 steps of Algorithm 1 by sampling (512 chains); the
-  energy of each state is the
+* J2 != 0: float64 evaluation (every knight bond's ratio) and the sampler's
+  chains against the oracle;
+* end to end on the 4x4 lattice at D = 4, Dc = 16 (exact contraction), J2 = 0
+  and 0.14: the simple update (its knight bonds left out), then 100 steps of
+  Algorithm 1 by sampling (512 chains); the energy of each state is the
   exact sum over the 12870 S^z = 0 configurations of |Psi|^2 E_loc, both from the
   GPU's vp_eval (and checked against a brute-force sum from the amplitudes
   alone), and is compared with Table III's exact-diagonalisation value.
@@ -38,14 +42,14 @@ def _B():
     return binding
 
 
-def _ed_per_site():
+def _ed_per_site(J2):
     with open(GOLDEN) as f:
         for line in f:
             if line.strip() and not line.startswith("#"):
                 j2, e = line.split()
-                if float(j2) == 0.0:
+                if float(j2) == J2:
                     return float(e)
-    raise AssertionError("no J2 = 0 row")
+    raise AssertionError(f"no J2 = {J2} row")
 
 
 @pytest.mark.parametrize("Ly,Lx,D,Dc,ncfg", [
@@ -73,6 +77,77 @@ def test_eval_fp64_parity_triangular(Ly, Lx, D, Dc, ncfg):
     assert np.all(g["ratios"][:, base_d + 1::2] == 0.0)
     for gd, od in zip(g["dlnpsi"], o["dlnpsi"]):
         assert np.max(np.abs(gd - od)) <= 1e-9 * max(1.0, np.max(np.abs(od)))
+
+
+@pytest.mark.parametrize("Ly,Lx,D,Dc,ncfg", [
+    (4, 4, 2, 4, 6),     # exact contraction
+    (4, 4, 3, 3, 4),     # truncated
+    (3, 4, 2, 4, 4),     # one row of three-row knight bonds
+    (5, 4, 2, 4, 3),     # transposed lattice 4x5
+    (6, 6, 4, 8, 2),     # fused MFMA 2-row steps, D=4 Dc=8
+    (4, 4, 8, 16, 2),    # fused MFMA 2-row steps, D=8 Dc=16
+])
+def test_eval_fp64_parity_triangular_j2(Ly, Lx, D, Dc, ncfg):
+    B = _B()
+    J2 = 0.3
+    print(f"triangular J2={J2} eval fp64 {Ly}x{Lx} D={D} Dc={Dc}", flush=True)
+    T = W.random_tensors(Ly, Lx, D, seed=650 + Ly * Lx + D)
+    cfgs = W.random_configs(Ly, Lx, ncfg, seed=23)
+    g = H.gpu_eval(Ly, Lx, D, Dc, J2, B.VP_FP64, T, cfgs, geometry=TRI)
+    o = H.oracle_eval(Ly, Lx, D, Dc, J2, T, cfgs, geometry=TRI)
+    N = Ly * Lx
+    assert np.array_equal(g["sign"], o["sign"])
+    assert np.max(np.abs(g["log_abs_psi"] - o["log_abs_psi"])) <= 1e-10
+    assert np.max(np.abs(g["e_loc"] - o["e_loc"])) / N <= 1e-10
+    scale = np.maximum(1.0, np.abs(o["ratios"]))
+    assert np.max(np.abs(g["ratios"] - o["ratios"]) / scale) <= 1e-9
+    for gd, od in zip(g["dlnpsi"], o["dlnpsi"]):
+        assert np.max(np.abs(gd - od)) <= 1e-9 * max(1.0, np.max(np.abs(od)))
+
+
+def test_sampler_fp64_triangular_j2_matches_oracle():
+    import torch
+    from oracle import vmc
+    B = _B()
+    Ly, Lx, D, Dc, J2 = 4, 4, 2, 4, 0.3
+    chains, burn, meas, seed = 2, 2, 3, 41
+    print(f"triangular J2={J2} sampler fp64 {Ly}x{Lx} D={D} Dc={Dc} {chains} chains {burn}+{meas}", flush=True)
+    T = W.random_tensors(Ly, Lx, D, seed=77)
+    ctx = B.Context(B.lattice(Ly, Lx, D, Dc, 1.0, J2, B.VP_FP64, chains, geometry=TRI), seed=seed)
+    dev = torch.device("cuda")
+    ctx.vp_set_tensors(0, torch.tensor(T, dtype=torch.float64, device=dev))
+    ctx.vp_init_chains(0, None)
+    n, N = chains * meas, Ly * Lx
+    lp = torch.empty(n, dtype=torch.float64, device=dev)
+    sg = torch.empty(n, dtype=torch.int8, device=dev)
+    el = torch.empty(n, dtype=torch.float64, device=dev)
+    so = torch.empty((n, N), dtype=torch.int8, device=dev)
+    ctx.vp_sample(0, burn, meas, lp, sg, el, None, so)
+    ctx.vp_sync()
+    el = el.cpu().numpy().reshape(chains, meas)
+    so = so.cpu().numpy().reshape(chains, meas, N)
+    ctx.close()
+    lat = olat.Lattice(Ly, Lx, D, Dc, J2=J2, geometry="triangular")
+    for c in range(chains):
+        ch = vmc.Chain(lat, olat.neel_shuffled(lat, seed, 0, c), seed, 0, c)
+        o = vmc.run_chain(T, lat, ch, burn, meas)
+        assert np.array_equal(so[c], np.stack([x["spins"] for x in o]))
+        assert np.max(np.abs(el[c] - np.array([x["e_loc"] for x in o]))) / N <= 1e-10
+
+
+def test_triangular_j2_rules():
+    B = _B()
+    ctx = B.Context(B.lattice(4, 4, 2, 4, 1.0, 0.2, B.VP_FP64, 2, geometry=TRI), seed=1)
+    with pytest.raises(B.VPError) as ei:
+        ctx.vp_set_sampler(0, B.VP_SAMPLER_SIS_PAIR)
+    assert ei.value.status == B.VP_ERR_UNSUPPORTED
+    ctx.vp_init_tensors(0, seed=2)
+    ctx.vp_init_chains(0, None)
+    ctx.vp_set_schedule(0, B.VP_SCHED_GRAPH)
+    with pytest.raises(B.VPError) as ei:
+        ctx.vp_sample(0, 1, 0, None, None, None)
+    assert ei.value.status == B.VP_ERR_UNSUPPORTED
+    ctx.close()
 
 
 def _n_links(Ly, Lx):
@@ -129,20 +204,22 @@ def _exact_energy(ctx, cfgs_dev, n):
     return float(np.sum(w * el) / np.sum(w)), sg * np.exp(lp - lp.max())
 
 
-def test_triangular_4x4_end_to_end_against_table3_ed():
+@pytest.mark.parametrize("J2", [0.0, 0.14])
+def test_triangular_4x4_end_to_end_against_table3_ed(J2):
     import torch
     B = _B()
     Ly = Lx = 4
     N, D, Dc = 16, 4, 16
     n_chains = 512
-    print("triangular 4x4 D=4 Dc=16: simple update, then 100 steps of Algorithm 1 (512 chains)", flush=True)
-    e_ed = _ed_per_site()
+    print(f"triangular 4x4 J2={J2} D=4 Dc=16: simple update, then 100 steps of Algorithm 1 (512 chains)", flush=True)
+    e_ed = _ed_per_site(J2)
     cfgs = np.array(bf.sz0_configs(N))
     dev = torch.device("cuda")
     cfg_dev = torch.tensor(cfgs, dtype=torch.int8, device=dev)
     # the GPU evaluation of every configuration needs a lattice with that many chains
-    ev = B.Context(B.lattice(Ly, Lx, D, Dc, 1.0, 0.0, B.VP_FP64, EVAL_BATCH, geometry=TRI), seed=3)
-    ctx = B.Context(B.lattice(Ly, Lx, D, Dc, 1.0, 0.0, B.VP_FP64, n_chains, geometry=TRI), seed=5)
+    ev = B.Context(B.lattice(Ly, Lx, D, Dc, 1.0, J2, B.VP_FP64, EVAL_BATCH, geometry=TRI), seed=3)
+    ctx = B.Context(B.lattice(Ly, Lx, D, Dc, 1.0, J2, B.VP_FP64, n_chains, geometry=TRI), seed=5)
+    bond_list = bf.bonds(Ly, Lx, 1.0, J2, triangular=True)
     ctx.vp_init_tensors(0, seed=6, scale=0.0, perturb=0.0)
     Tg = torch.empty(ctx.num_params(), dtype=torch.float64, device=dev)
 
@@ -151,7 +228,7 @@ def test_triangular_4x4_end_to_end_against_table3_ed():
         ev.vp_set_tensors(0, Tg)
         e, psi = _exact_energy(ev, cfg_dev, len(cfgs))
         # the same sum from the amplitudes alone (brute-force Hamiltonian action)
-        e_bf = bf.sector_energy(psi, cfgs, Ly, Lx, triangular=True)
+        e_bf = bf.sector_energy_bonds(psi, cfgs, N, bond_list)
         assert abs(e - e_bf) <= 1e-10 * abs(e_bf)
         return e / N
 
