@@ -474,7 +474,7 @@ def roofline(ms, launches, flops, fp64_phases, path):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=8)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--chains", type=int, default=1024)
     ap.add_argument("--L", type=int, default=16)
