@@ -58,6 +58,7 @@ def _gpu_pair_sample(Ly, Lx, D, Dc, J2, prec, T, n_pairs, n_burn, n_meas, seed):
     (4, 4, 2, 4, 0.0, 2, 3, 5),    # exact contraction
     (4, 4, 3, 3, 0.5, 3, 2, 3),    # truncated, J1-J2 (diagonal terms in E_Phi)
     (4, 4, 4, 8, 0.0, 1, 1, 2),    # fused MFMA steps, D=4 Dc=8
+    (4, 4, 8, 16, 0.5, 1, 1, 1),   # fused MFMA steps, D=8 Dc=16, J1-J2
 ])
 def test_pair_chains_match_oracle_fp64(Ly, Lx, D, Dc, J2, pairs, burn, meas):
     B = _B()
