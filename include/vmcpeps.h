@@ -236,7 +236,10 @@ vp_status vp_sample_batch(vp_ctx* ctx, int32_t n_lats, const int32_t* lats_host,
  * one warm-up sweep each; the chains advance by 3 (sweeps + 1) sweeps, which
  * count as burn-in), keeps the fastest and returns it in *schedule_out;
  * ms_host [3] (may be NULL) receives the milliseconds per sweep of
- * VP_SCHED_PHASES, VP_SCHED_PERSISTENT and VP_SCHED_GRAPH.  Waits. */
+ * VP_SCHED_PHASES, VP_SCHED_PERSISTENT and VP_SCHED_GRAPH, -1 for a schedule
+ * the lattice cannot run (the persistent one with the variational fit; both
+ * others with VP_VERT_COLUMN, the triangular knight bonds or the |Phi|^2
+ * chains).  Waits. */
 vp_status vp_autotune(vp_ctx* ctx, int32_t lat, int32_t sweeps, double* ms_host, int32_t* schedule_out);
 
 /* Tile variants of the fused float32 / float64 2-row column step (App. C: the

@@ -1325,6 +1325,10 @@ vp_status vp_autotune(vp_ctx* ctx, int32_t lat, int32_t sweeps, double* ms_host,
       if (ms_host) ms_host[k] = -1.0;  // not available with the variational fit
       continue;
     }
+    if (cand[k] != VP_SCHED_PHASES && (L->col >= 0 || L->sampler == VP_SAMPLER_SIS_PAIR)) {
+      if (ms_host) ms_host[k] = -1.0;  // the per-phase schedule only
+      continue;
+    }
     L->schedule = cand[k];
     // one untimed sweep first (initial boundaries, graph and code warm-up)
     st = vp_sample(ctx, lat, 1, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);

@@ -201,3 +201,15 @@ def test_column_sampler_bf16_measures_in_float64():
         assert abs(lp - o["log_abs_psi"]) <= 1e-9
         assert abs(e - o["e_loc"]) / (Ly * Lx) <= 1e-9
     assert g["accept"][:, 0].sum() > 0
+
+
+def test_autotune_keeps_the_per_phase_schedule():
+    import torch
+    B = _B()
+    dev = torch.device("cuda")
+    ctx = B.Context(B.lattice(4, 4, 2, 4, 1.0, 0.0, B.VP_FP64, 4, vertical=COL), seed=3)
+    ctx.vp_set_tensors(0, torch.tensor(W.random_tensors(4, 4, 2, seed=5), dtype=torch.float64, device=dev))
+    ctx.vp_init_chains(0, None)
+    sched, ms = ctx.vp_autotune(0, 2)
+    assert sched == B.VP_SCHED_PHASES and ms[0] > 0 and ms[1] == -1.0 and ms[2] == -1.0
+    ctx.close()

@@ -166,6 +166,8 @@ def test_pair_sampler_rules():
     ctx.vp_sample(0, 1, 1, lp, sg, el)  # the per-phase schedule without log-derivatives runs
     ctx.vp_sync()
     assert np.all(np.isfinite(el.cpu().numpy()))
+    sched, ms = ctx.vp_autotune(0, 1)  # times the per-phase schedule alone
+    assert sched == B.VP_SCHED_PHASES and ms[0] > 0 and ms[1] == -1.0 and ms[2] == -1.0
     ctx.close()
 
 

@@ -147,6 +147,8 @@ def test_triangular_j2_rules():
     with pytest.raises(B.VPError) as ei:
         ctx.vp_sample(0, 1, 0, None, None, None)
     assert ei.value.status == B.VP_ERR_UNSUPPORTED
+    sched, ms = ctx.vp_autotune(0, 1)  # times the per-phase schedule alone
+    assert sched == B.VP_SCHED_PHASES and ms[0] > 0 and ms[1] == -1.0 and ms[2] == -1.0
     ctx.close()
 
 
