@@ -7,12 +7,17 @@
 // upper-boundary indices and per lower-boundary index c, the last one
 // accumulated across c in MFMA registers), but every operand lives in LDS as
 // bf16 in the layout its MFMA consumes: k contiguous, rows of the contraction
-// length rounded up to 8 (zero padded) plus 8 elements of bank spread, so that
-// each lane fetches its 8 k-values of a 16x16x32 MFMA in one 16-byte read;
-// k-groups past the contraction length are zero without a read.
+// length rounded up to 8 (zero padded), so that each lane fetches its 8
+// k-values of a 16x16x32 MFMA in one 16-byte read; k-groups past the
+// contraction length are zero without a read.
 // Products accumulate in f32; stage outputs are rounded to bf16 when stored
-// for the next stage.  Lin/Lout and the column tensors are in TS (float64 or
-// float32) storage.
+// for the next stage.  The first three products put the operand whose index
+// runs fastest in the next stage's contraction (u, m, dd) on the MFMA's row
+// side: a lane's four accumulator rows are then four consecutive elements of
+// one destination row and go out in one 8-byte store (for D a multiple of 4).
+// Row strides (16-byte multiples, 8 elements of spread where it pays) keep the
+// 16-byte operand reads and the 8-byte stores of a pass on distinct banks.
+// Lin/Lout and the column tensors are in TS (float64 or float32) storage.
 #pragma once
 #include "vp_device.hpp"
 
@@ -28,25 +33,29 @@ struct Env4Bf {
   static constexpr int NBLK = C / BB;
   static constexpr int rup8(int x) { return (x + 7) / 8 * 8; }
   static constexpr int K1 = C, K2 = D * D, K3 = D * D, K4 = D;      // contraction lengths
-  static constexpr int P1 = rup8(K1) + 8, P2 = rup8(K2) + 8, P3 = rup8(K3) + 8, P4 = rup8(K4) + 8;  // row strides
-  // operand arrays (bf16 elements)
-  // rows (u, b) of the boundary tensor, each block of C rows (one u) shifted by
-  // UP elements: the 16 rows an S1 tile reads span several u, whose blocks
-  // would otherwise start in the same banks
-  static constexpr int UP = 32;
-  static constexpr int nAT = D * (C * P1 + UP);   // [(u, b)][a]
+  static constexpr int P1 = rup8(K1) + 8, P2 = rup8(K2) + 8, P3 = rup8(K3) + 8, P4 = rup8(K4);  // row strides
+  static constexpr int PA = rup8(K1);             // boundary tensor rows: unpadded (LDS budget, below)
+  static constexpr int BS = D * P4 + 8;           // X3: stride of a block of D rows (bb, r1, .)
+  static constexpr bool VEC = D % 4 == 0;         // four accumulator rows = four consecutive destination elements
+  // X1 (read by S2 only) and X3 (written by S3) can share their buffer when no
+  // zero padding is read (D a multiple of 8): at D = 8, C = 16 this keeps the
+  // step under 40 KB of LDS, four work-groups per CU
+  static constexpr bool ALIAS = D % 8 == 0;
+  // operand arrays (bf16 elements); every array is a multiple of 8 elements long
+  static constexpr int nAT = C * D * PA;          // [(b, u)][a]
   static constexpr int nLs = D * D * P1;          // [(l1, l2)][a]     (one lower-bond slice)
   static constexpr int nT1 = D * D * P2;          // [(r1, m)][(l1, u)]
   static constexpr int nT2 = D * D * P3;          // [(r2, dd)][(l2, m)]
   static constexpr int nBT = C * C * P4;          // [(c, e)][dd]
-  static constexpr int nX1 = D * BB * P2;         // [(l2, bb)][(l1, u)]
+  static constexpr int nX1 = BB * D * P2;         // [(bb, l2)][(l1, u)]
   static constexpr int nX2 = BB * D * P3;         // [(bb, r1)][(l2, m)]
-  static constexpr int nX3 = BB * D * D * P4;     // [(bb, r1, r2)][dd]
+  static constexpr int nX3 = BB * D * BS;         // [(bb, r1)] blocks of [r2][dd]
+  static constexpr int nX = ALIAS ? (nX1 > nX3 ? nX1 : nX3) + nX2 : nX1 + nX2 + nX3;  // the intermediates
   static constexpr int N4 = BB * D * D;           // output columns per block
   static constexpr int NT4 = (N4 + 15) / 16;
   static constexpr int T4W = (NT4 + 3) / 4;
   static constexpr size_t lds_bytes() {
-    return 2 * (size_t)(nAT + nLs + nT1 + nT2 + nBT + nX1 + nX2 + nX3);
+    return 2 * (size_t)(nAT + nLs + nT1 + nT2 + nBT + nX);
   }
 };
 
@@ -111,18 +120,17 @@ __device__ void env4_bf16(TS* __restrict__ Lout_p, const TS* __restrict__ Lin_p,
   __bf16* T1 = Ls + S::nLs;
   __bf16* T2 = T1 + S::nT1;
   __bf16* BT = T2 + S::nT2;
-  __bf16* X1 = BT + S::nBT;
-  __bf16* X2 = X1 + S::nX1;
-  __bf16* X3 = X2 + S::nX2;
+  __bf16* X2 = BT + S::nBT;
+  __bf16* X1 = X2 + S::nX2;
+  __bf16* X3 = S::ALIAS ? X1 : X1 + S::nX1;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const __bf16 zero = (__bf16)0.0f;
 
   // stage the column tensors once, transposed to k-contiguous rows; zero the
   // padding of every array (the intermediates' padding is never written later)
   for (int e = tid; e < S::nAT; e += WG) {
-    const int u = e / (C * S::P1 + S::UP), rem = e - u * (C * S::P1 + S::UP);
-    const int b = rem / S::P1, a = rem - b * S::P1;
-    AT[e] = (b < C && a < C) ? (__bf16)(float)A[a * sA.s0 + u * sA.s1 + b * sA.s2] : zero;
+    const int row = e / S::PA, a = e - row * S::PA, b = row / D, u = row - b * D;  // row = (b, u)
+    AT[e] = a < C ? (__bf16)(float)A[a * sA.s0 + u * sA.s1 + b * sA.s2] : zero;
   }
   for (int e = tid; e < S::nT1; e += WG) {
     const int row = e / S::P2, k = e - row * S::P2;  // row = (r1, m), k = (l1, u)
@@ -138,7 +146,7 @@ __device__ void env4_bf16(TS* __restrict__ Lout_p, const TS* __restrict__ Lin_p,
     const int row = e / S::P4, dd = e - row * S::P4, c = row / C, ee = row - c * C;
     BT[e] = dd < D ? (__bf16)(float)B[c * sB.s0 + dd * sB.s1 + ee * sB.s2] : zero;
   }
-  for (int e = tid; e < S::nX1 + S::nX2 + S::nX3; e += WG) X1[e] = zero;
+  for (int e = tid; e < S::nX; e += WG) X2[e] = zero;
   for (int e = tid; e < S::nLs; e += WG) Ls[e] = zero;
 
   // lower-bond slices of Lin ([a][(l1,l2)], contiguous) are read coalesced one
@@ -193,31 +201,24 @@ __device__ void env4_bf16(TS* __restrict__ Lout_p, const TS* __restrict__ Lin_p,
     for (int w = 0; w < S::T4W; ++w) acc[w] = {0, 0, 0, 0};
     for (int cs = 0; cs < C; ++cs) {
       const int pos = q * C + cs;
-      // S1: X1[(l2,bb)][(l1,u)] = sum_a Ls[(l1,l2)][a] AT[(u, b0+bb)][a]; M = D^2, N = D BB
-      bf_stage<(D * D + 15) / 16, (D * BB + 15) / 16>(
-          [&](int m0, int n0) {
-            // B rows j = (u, bb) -> AT row u C + b0 + bb: a strided row set, fetched
-            // row by row; rows past M or N are clamped to the last one (their
-            // products land in output rows and columns that are never stored)
-            v4f_e c4 = {0, 0, 0, 0};
-            const int i = min(m0 + (lane & 15), D * D - 1), j = min(n0 + (lane & 15), D * BB - 1);
-            const int kq = (lane >> 4) * 8, u = j / BB, bb = j - u * BB;
-#pragma unroll
-            for (int s = 0; s < (S::K1 + 31) / 32; ++s) {
-              const v8bf_e a = ld8(Ls + i * S::P1, 32 * s + kq, S::K1);
-              const v8bf_e b = ld8(AT + u * (C * S::P1 + S::UP) + (b0 + bb) * S::P1, 32 * s + kq, S::K1);
-              c4 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c4, 0, 0, 0);
-            }
-            return c4;
-          },
+      // S1: X1[(bb,l2)][(l1,u)] = sum_a AT[(b0+bb, u)][a] Ls[(l1,l2)][a]; M = BB D (rows (bb,u)), N = D^2
+      bf_stage<(BB * D + 15) / 16, (D * D + 15) / 16>(
+          [&](int m0, int n0) { return bf_tile<S::K1>(AT + b0 * D * S::PA, S::PA, Ls, S::P1, m0, n0, BB * D, D * D); },
           [&](int m0, int n0, const v4f_e& c4) {
-            const int j = n0 + (lane & 15);
+            const int i = n0 + (lane & 15), j0 = m0 + 4 * (lane >> 4);  // column (l1, l2), rows (bb, u0 + r)
+            if (i >= D * D) return;
+            const int l1 = i / D, l2 = i - l1 * D;
+            if constexpr (S::VEC) {
+              if (j0 < BB * D) {
+                const int bb = j0 / D, u0 = j0 - bb * D;
+                const v4bf_e v = {(__bf16)c4[0], (__bf16)c4[1], (__bf16)c4[2], (__bf16)c4[3]};
+                *reinterpret_cast<v4bf_e*>(X1 + (bb * D + l2) * S::P2 + l1 * D + u0) = v;
+              }
+            } else {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int i = m0 + 4 * (lane >> 4) + r;  // (l1, l2)
-              if (i < D * D && j < D * BB) {
-                const int l1 = i / D, l2 = i - l1 * D, u = j / BB, bb = j - u * BB;
-                X1[(l2 * BB + bb) * S::P2 + l1 * D + u] = (__bf16)c4[r];
+              for (int r = 0; r < 4; ++r) {
+                const int j = j0 + r, bb = j / D, u = j - bb * D;
+                if (j < BB * D) X1[(bb * D + l2) * S::P2 + l1 * D + u] = (__bf16)c4[r];
               }
             }
           });
@@ -226,47 +227,60 @@ __device__ void env4_bf16(TS* __restrict__ Lout_p, const TS* __restrict__ Lin_p,
         store();
         if (pos + 2 < NS) fetch((pos + 2) % C);
       }
-      // S2: X2[(bb,r1)][(l2,m)] = sum_{(l1,u)} X1[(l2,bb)][(l1,u)] T1[(r1,m)][(l1,u)]; M = D BB, N = D^2
-      bf_stage<(D * BB + 15) / 16, (D * D + 15) / 16>(
-          [&](int m0, int n0) { return bf_tile<S::K2>(X1, S::P2, T1, S::P2, m0, n0, D * BB, D * D); },
+      // S2: X2[(bb,r1)][(l2,m)] = sum_{(l1,u)} T1[(r1,m)][(l1,u)] X1[(bb,l2)][(l1,u)]; M = D^2 (rows (r1,m)), N = BB D
+      bf_stage<(D * D + 15) / 16, (BB * D + 15) / 16>(
+          [&](int m0, int n0) { return bf_tile<S::K2>(T1, S::P2, X1, S::P2, m0, n0, D * D, BB * D); },
           [&](int m0, int n0, const v4f_e& c4) {
-            const int j = n0 + (lane & 15);  // (r1, m)
+            const int n = n0 + (lane & 15), j0 = m0 + 4 * (lane >> 4);  // column (bb, l2), rows (r1, m0 + r)
+            if (n >= BB * D) return;
+            const int bb = n / D, l2 = n - bb * D;
+            if constexpr (S::VEC) {
+              if (j0 < D * D) {
+                const int r1 = j0 / D, m = j0 - r1 * D;
+                const v4bf_e v = {(__bf16)c4[0], (__bf16)c4[1], (__bf16)c4[2], (__bf16)c4[3]};
+                *reinterpret_cast<v4bf_e*>(X2 + (bb * D + r1) * S::P3 + l2 * D + m) = v;
+              }
+            } else {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int i = m0 + 4 * (lane >> 4) + r;  // (l2, bb)
-              if (i < D * BB && j < D * D) {
-                const int l2 = i / BB, bb = i - l2 * BB, r1 = j / D, m = j - r1 * D;
-                X2[(bb * D + r1) * S::P3 + l2 * D + m] = (__bf16)c4[r];
+              for (int r = 0; r < 4; ++r) {
+                const int j = j0 + r, r1 = j / D, m = j - r1 * D;
+                if (j < D * D) X2[(bb * D + r1) * S::P3 + l2 * D + m] = (__bf16)c4[r];
               }
             }
           });
       __syncthreads();
-      // S3: X3[(bb,r1,r2)][dd] = sum_{(l2,m)} X2[(bb,r1)][(l2,m)] T2[(r2,dd)][(l2,m)]; M = BB D, N = D^2
-      bf_stage<(BB * D + 15) / 16, (D * D + 15) / 16>(
-          [&](int m0, int n0) { return bf_tile<S::K3>(X2, S::P3, T2, S::P3, m0, n0, BB * D, D * D); },
+      // S3: X3[(bb,r1)][r2][dd] = sum_{(l2,m)} T2[(r2,dd)][(l2,m)] X2[(bb,r1)][(l2,m)]; M = D^2 (rows (r2,dd)), N = BB D
+      bf_stage<(D * D + 15) / 16, (BB * D + 15) / 16>(
+          [&](int m0, int n0) { return bf_tile<S::K3>(T2, S::P3, X2, S::P3, m0, n0, D * D, BB * D); },
           [&](int m0, int n0, const v4f_e& c4) {
-            const int j = n0 + (lane & 15);  // (r2, dd)
+            const int n = n0 + (lane & 15), j0 = m0 + 4 * (lane >> 4);  // column (bb, r1), rows (r2, dd0 + r)
+            if (n >= BB * D) return;
+            if constexpr (S::VEC) {
+              if (j0 < D * D) {
+                const int r2 = j0 / D, dd = j0 - r2 * D;
+                const v4bf_e v = {(__bf16)c4[0], (__bf16)c4[1], (__bf16)c4[2], (__bf16)c4[3]};
+                *reinterpret_cast<v4bf_e*>(X3 + n * S::BS + r2 * S::P4 + dd) = v;
+              }
+            } else {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int i = m0 + 4 * (lane >> 4) + r;  // (bb, r1)
-              if (i < BB * D && j < D * D) {
-                const int r2 = j / D, dd = j - r2 * D;
-                X3[(i * D + r2) * S::P4 + dd] = (__bf16)c4[r];
+              for (int r = 0; r < 4; ++r) {
+                const int j = j0 + r, r2 = j / D, dd = j - r2 * D;
+                if (j < D * D) X3[n * S::BS + r2 * S::P4 + dd] = (__bf16)c4[r];
               }
             }
           });
       __syncthreads();
-      // S4: acc[e][(bb,r1,r2)] += sum_dd BT[(cs, e)][dd] X3[(bb,r1,r2)][dd]; M = C, N = BB D^2
+      // S4: acc[e][(bb,r1,r2)] += sum_dd BT[(cs, e)][dd] X3[(bb,r1)][r2][dd]; M = C, N = BB D^2
 #pragma unroll
       for (int w = 0; w < S::T4W; ++w) {
         const int t = wave + 4 * w;
         if (t < S::NT4) {
           const int i = min(lane & 15, C - 1), j = min(t * 16 + (lane & 15), S::N4 - 1);
-          const int kq = (lane >> 4) * 8;
+          const int kq = (lane >> 4) * 8, jb = j / D, r2 = j - jb * D;
 #pragma unroll
           for (int s = 0; s < (S::K4 + 31) / 32; ++s) {
             const v8bf_e a = ld8(BT + (cs * C + i) * S::P4, 32 * s + kq, S::K4);
-            const v8bf_e b = ld8(X3 + j * S::P4, 32 * s + kq, S::K4);
+            const v8bf_e b = ld8(X3 + jb * S::BS + r2 * S::P4, 32 * s + kq, S::K4);
             acc[w] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[w], 0, 0, 0);
           }
         }
