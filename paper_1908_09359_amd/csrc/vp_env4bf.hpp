@@ -15,8 +15,10 @@
 // runs fastest in the next stage's contraction (u, m, dd) on the MFMA's row
 // side: a lane's four accumulator rows are then four consecutive elements of
 // one destination row and go out in one 8-byte store (for D a multiple of 4).
-// Row strides (16-byte multiples, 8 elements of spread where it pays) keep the
-// 16-byte operand reads and the 8-byte stores of a pass on distinct banks.
+// Row strides are 16-byte multiples chosen from measured LDS bank conflicts
+// (64 banks of 4 bytes): a 16x16 operand tile's 16-byte reads are
+// conflict-free over rows of 32 bytes (contraction length 16) and of 160
+// bytes (length 64), and cost four cycles over 144-byte rows.
 // Lin/Lout and the column tensors are in TS (float64 or float32) storage.
 #pragma once
 #include "vp_device.hpp"
@@ -33,8 +35,10 @@ struct Env4Bf {
   static constexpr int NBLK = C / BB;
   static constexpr int rup8(int x) { return (x + 7) / 8 * 8; }
   static constexpr int K1 = C, K2 = D * D, K3 = D * D, K4 = D;      // contraction lengths
-  static constexpr int P1 = rup8(K1) + 8, P2 = rup8(K2) + 8, P3 = rup8(K3) + 8, P4 = rup8(K4);  // row strides
-  static constexpr int PA = rup8(K1);             // boundary tensor rows: unpadded (LDS budget, below)
+  // row strides: Ls and AT unpadded, T1, T2 and X1 at 160 bytes for D = 8; X2
+  // keeps 144-byte rows so that the step fits 40 KB (its reads pay the conflicts)
+  static constexpr int P1 = rup8(K1), P2 = rup8(K2) + 16, P3 = rup8(K3) + 8, P4 = rup8(K4);
+  static constexpr int PA = P1;                   // boundary tensor rows
   static constexpr int BS = D * P4 + 8;           // X3: stride of a block of D rows (bb, r1, .)
   static constexpr bool VEC = D % 4 == 0;         // four accumulator rows = four consecutive destination elements
   // X1 (read by S2 only) and X3 (written by S3) can share their buffer when no
@@ -45,7 +49,7 @@ struct Env4Bf {
   static constexpr int nAT = C * D * PA;          // [(b, u)][a]
   static constexpr int nLs = D * D * P1;          // [(l1, l2)][a]     (one lower-bond slice)
   static constexpr int nT1 = D * D * P2;          // [(r1, m)][(l1, u)]
-  static constexpr int nT2 = D * D * P3;          // [(r2, dd)][(l2, m)]
+  static constexpr int nT2 = D * D * P2;          // [(r2, dd)][(l2, m)]
   static constexpr int nBT = C * C * P4;          // [(c, e)][dd]
   static constexpr int nX1 = BB * D * P2;         // [(bb, l2)][(l1, u)]
   static constexpr int nX2 = BB * D * P3;         // [(bb, r1)][(l2, m)]
@@ -138,7 +142,7 @@ __device__ void env4_bf16(TS* __restrict__ Lout_p, const TS* __restrict__ Lin_p,
     T1[e] = k < D * D ? (__bf16)(float)t1[l * s1.l + u * s1.u + r * s1.r + m * s1.d] : zero;
   }
   for (int e = tid; e < S::nT2; e += WG) {
-    const int row = e / S::P3, k = e - row * S::P3;  // row = (r2, dd), k = (l2, m)
+    const int row = e / S::P2, k = e - row * S::P2;  // row = (r2, dd), k = (l2, m)
     const int r = row / D, dd = row - r * D, l = k / D, m = k - l * D;
     T2[e] = k < D * D ? (__bf16)(float)t2[l * s2.l + m * s2.u + r * s2.r + dd * s2.d] : zero;
   }
@@ -251,7 +255,7 @@ __device__ void env4_bf16(TS* __restrict__ Lout_p, const TS* __restrict__ Lin_p,
       __syncthreads();
       // S3: X3[(bb,r1)][r2][dd] = sum_{(l2,m)} T2[(r2,dd)][(l2,m)] X2[(bb,r1)][(l2,m)]; M = D^2 (rows (r2,dd)), N = BB D
       bf_stage<(D * D + 15) / 16, (BB * D + 15) / 16>(
-          [&](int m0, int n0) { return bf_tile<S::K3>(T2, S::P3, X2, S::P3, m0, n0, D * D, BB * D); },
+          [&](int m0, int n0) { return bf_tile<S::K3>(T2, S::P2, X2, S::P3, m0, n0, D * D, BB * D); },
           [&](int m0, int n0, const v4f_e& c4) {
             const int n = n0 + (lane & 15), j0 = m0 + 4 * (lane >> 4);  // column (bb, r1), rows (r2, dd0 + r)
             if (n >= BB * D) return;
